@@ -1,0 +1,640 @@
+"""Plain FP64 CPU oracle for the EGFEM Newton hot path -- TEST INFRASTRUCTURE.
+
+Only the test-suite, the smoke check and the CPU-baseline leg of the benchmark
+may import this module.  The product path (the HIP library and its Python
+binding) never calls it, and it shares no code with that path: the only thing
+both sides consume is the seeded input module `workloads`.
+
+What is computed, in the paper's notation (Tolle & Marheineke, "Extended Group
+Finite Element Method", arXiv 2005.06193):
+
+* Sec. 2.1 / eq. (discrete_problem): P1 Lagrange trial space V_h on a simplicial
+  mesh, Dirichlet nodes fixed (here u_D = 0), one equation per free node.
+* Sec. 3.3 / eq. (egfem_terms): with b(u) = u the trilinear form
+  K_a : (u (x) a) uses the third-order tensor
+      (K_a)_ijk = int eta_k grad phi_j . grad phi_i          (stiffness form)
+  and, for the semilinear example of Sec. 5.3 decomposition (a),
+      (M_c)_ijk = int eta_k phi_j phi_i                      (mass form).
+  The nonlinearity is interpolated onto W_h = V_h = P1 (Case 2 of Sec. 3.1,
+  the original group FEM choice), so eta_k = phi_k and the interpolation
+  operator Pi_u of Sec. 3.2 is the identity.
+* Sec. 4 / eq. (EGFEM_root) reduced to u: F(u) = [K u] + T:(u (x) a(u)) - d
+  with a(u) = a0 + u*u evaluated pointwise at the nodes (eq. egfem_coeffs).
+* Sec. 4, Newton iteration: u <- u - DF(u)^{-1} F(u).  The Jacobian needs no
+  integration: DF = [K] + T . a + (T ._2 u) diag(a'(u)), the contractions of
+  the Notation in Sec. 3.3.  The lifted iteration on z = (u, a) with the block
+  Jacobian printed in Sec. 4 is implemented as well (dense, tiny meshes).
+* Sec. 2.1 eq. (nonlinear_terms) and eq. (SGA_root): the standard Galerkin
+  approach, re-integrating the nonlinear term by quadrature every iteration.
+* Sec. 3.1 Case 1 / Example exact_egfem: W_h = P2 makes the reformulation
+  exact (EGFEM(P2) == SGA for the u^2 nonlinearity).
+
+Integrals use numerical quadrature on the reference simplex (collapsed Gauss-
+Legendre product rules generated here), assembled element by element.  Linear
+systems are solved directly (SuperLU through scipy) -- the plain definition of
+"solve J delta = -F".  Everything is float64.
+
+Readings of points the paper leaves open are listed in the project's design
+notes; the ones that change numbers are: load d = M f for a nodal source f;
+Newton stops on ||F||_2 <= tol ||F(u0)||_2 over the free rows; damping halves
+the step up to 10 times while ||F(u + alpha delta)|| > (1 - 1e-4 alpha) ||F(u)||;
+assembled tensor entries below 1e-13 of their row's largest magnitude (zero
+in exact arithmetic) are dropped.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+FORM_STIFF = 0
+FORM_MASS = 1
+
+
+# ----------------------------------------------------------------------------
+# quadrature on the reference simplex {x_m >= 0, sum x_m <= 1}
+# ----------------------------------------------------------------------------
+def gauss_legendre_01(m: int):
+    """m-point Gauss-Legendre rule on [0,1] (exact for degree 2m-1)."""
+    x, w = np.polynomial.legendre.leggauss(m)
+    return 0.5 * (x + 1.0), 0.5 * w
+
+
+def simplex_quadrature(dim: int, degree: int):
+    """Collapsed (Duffy) Gauss-Legendre product rule on the reference simplex,
+    exact for polynomials of total degree <= `degree`.  Returns points [Q, dim]
+    and weights [Q] summing to the reference volume 1/dim!.
+
+    Map from the unit cube: x1 = s1, x2 = s2 (1 - s1), x3 = s3 (1 - s1)(1 - s2),
+    Jacobian (1-s1)^(dim-1) (1-s2)^(dim-2).  A degree-q polynomial becomes a
+    polynomial of degree <= q + dim - 1 in each cube variable, so each axis
+    takes ceil((q + dim) / 2) Gauss points.
+    """
+    m = max(1, math.ceil((degree + dim) / 2))
+    s, w = gauss_legendre_01(m)
+    if dim == 1:
+        return s[:, None].copy(), w.copy()
+    grids = np.meshgrid(*([s] * dim), indexing="ij")
+    wgrids = np.meshgrid(*([w] * dim), indexing="ij")
+    S = np.stack([g.ravel() for g in grids], axis=1)
+    W = np.prod(np.stack([g.ravel() for g in wgrids], axis=1), axis=1)
+    X = np.zeros_like(S)
+    scale = np.ones(S.shape[0])
+    for ax in range(dim):
+        X[:, ax] = S[:, ax] * scale
+        scale = scale * (1.0 - S[:, ax])
+    jac = np.ones(S.shape[0])
+    for ax in range(dim - 1):
+        jac = jac * (1.0 - S[:, ax]) ** (dim - 1 - ax)
+    return X, W * jac
+
+
+def barycentric(points: np.ndarray) -> np.ndarray:
+    """Barycentric coordinates [Q, dim+1] of reference points: lambda_0 = 1 - sum x,
+    lambda_m = x_m.  These are the P1 nodal basis functions on the element."""
+    return np.concatenate([1.0 - points.sum(axis=1, keepdims=True), points], axis=1)
+
+
+# ----------------------------------------------------------------------------
+# element geometry
+# ----------------------------------------------------------------------------
+def element_geometry(coords: np.ndarray, cells: np.ndarray):
+    """B_e = [x1-x0, ..., xd-x0], |det B_e| and the (constant) gradients of the
+    barycentric basis functions G[e, a, :] = grad lambda_a."""
+    X = coords[cells]                       # [E, d+1, d]
+    dim = X.shape[2]
+    B = np.transpose(X[:, 1:, :] - X[:, :1, :], (0, 2, 1))   # columns x_m - x_0
+    if dim == 1:
+        det = B[:, 0, 0].copy()
+        Binv = 1.0 / B
+    else:
+        det = np.linalg.det(B)
+        Binv = np.linalg.inv(B)
+    if np.any(det == 0.0):
+        raise ValueError("degenerate element")
+    # lambda_m (m>=1) = row m-1 of B^{-1} applied to (x - x0)
+    G = np.empty((X.shape[0], dim + 1, dim))
+    G[:, 1:, :] = Binv
+    G[:, 0, :] = -Binv.sum(axis=1)
+    return np.abs(det), G
+
+
+# ----------------------------------------------------------------------------
+# sparse third-order tensor in coordinate form
+# ----------------------------------------------------------------------------
+@dataclass
+class Tensor3:
+    n: int
+    i: np.ndarray
+    j: np.ndarray
+    k: np.ndarray
+    v: np.ndarray
+    structural_nnz: int = 0
+
+    @property
+    def nnz(self) -> int:
+        return int(self.v.size)
+
+    def dense(self) -> np.ndarray:
+        D = np.zeros((self.n, self.n, self.n))
+        np.add.at(D, (self.i, self.j, self.k), self.v)
+        return D
+
+
+DROP_REL = 1e-13
+
+
+def _merge_coo3(n, I, J, K, V, drop_rel=DROP_REL) -> Tensor3:
+    """Sum duplicate (i,j,k) entries in element order, then drop the entries that
+    vanish in exact arithmetic: |T_ijk| <= drop_rel * max_{j',k'} |T_ij'k'| (row-
+    relative; with drop_rel = 0 only exact 0.0 is dropped).  On right-isosceles
+    triangles and Kuhn tetrahedra grad phi_i . grad phi_j = 0 for some vertex
+    pairs; rounding turns these into a few ulps when h is not a power of two."""
+    key = (I.astype(np.int64) * n + J) * n + K
+    order = np.argsort(key, kind="stable")
+    key = key[order]
+    V = V[order]
+    starts = np.flatnonzero(np.concatenate([[True], key[1:] != key[:-1]]))
+    vals = np.add.reduceat(V, starts) if V.size else V
+    ukey = key[starts]
+    structural = int(ukey.size)
+    i = ukey // (n * n)
+    rowmax = np.zeros(n)
+    np.maximum.at(rowmax, i, np.abs(vals))
+    keep = np.abs(vals) > drop_rel * rowmax[i]
+    keep &= vals != 0.0
+    ukey = ukey[keep]
+    vals = vals[keep]
+    i = ukey // (n * n)
+    j = (ukey // n) % n
+    k = ukey % n
+    return Tensor3(n, i, j, k, vals, structural)
+
+
+def _degree_for(form: int, dim: int) -> int:
+    # stiffness integrand eta_k grad.grad is linear; mass integrand is cubic
+    return 1 if form == FORM_STIFF else 3
+
+
+def assemble_tensor(coords, cells, form: int, degree: Optional[int] = None,
+                    drop_rel: float = DROP_REL) -> Tensor3:
+    """T_ijk = sum_e sum_q w_q |det B_e| psi_k(x_q) grad phi_j . grad phi_i   (stiffness)
+    or T_ijk = sum_e sum_q w_q |det B_e| psi_k phi_j phi_i (x_q)              (mass),
+    with psi = phi = P1 nodal basis (eq. egfem_terms, Case 2 with W_h = V_h)."""
+    n = coords.shape[0]
+    dim = coords.shape[1]
+    if degree is None:
+        degree = _degree_for(form, dim)
+    det, G = element_geometry(coords, cells)
+    pts, wts = simplex_quadrature(dim, degree)
+    lam = barycentric(pts)                                   # [Q, d+1]
+    if form == FORM_STIFF:
+        GG = np.einsum("ead,ebd->eab", G, G)                 # grad phi_a . grad phi_b
+        psi = np.einsum("q,qc->c", wts, lam)                 # int over reference of psi_c
+        Te = det[:, None, None, None] * GG[:, :, :, None] * psi[None, None, None, :]
+    elif form == FORM_MASS:
+        trip = np.einsum("q,qa,qb,qc->abc", wts, lam, lam, lam)
+        Te = det[:, None, None, None] * trip[None]
+    else:
+        raise ValueError("unknown form")
+    nl = dim + 1
+    a_idx, b_idx, c_idx = np.meshgrid(np.arange(nl), np.arange(nl), np.arange(nl), indexing="ij")
+    I = cells[:, a_idx.ravel()].ravel().astype(np.int64)
+    J = cells[:, b_idx.ravel()].ravel().astype(np.int64)
+    K = cells[:, c_idx.ravel()].ravel().astype(np.int64)
+    return _merge_coo3(n, I, J, K, Te.reshape(-1), drop_rel)
+
+
+def assemble_stiffness(coords, cells) -> sp.csr_matrix:
+    """K_ij = int grad phi_j . grad phi_i."""
+    n = coords.shape[0]
+    det, G = element_geometry(coords, cells)
+    dim = coords.shape[1]
+    vol = det / math.factorial(dim)
+    Ke = vol[:, None, None] * np.einsum("ead,ebd->eab", G, G)
+    return _scatter_matrix(n, cells, Ke)
+
+
+def assemble_mass(coords, cells) -> sp.csr_matrix:
+    """M_ij = int phi_j phi_i, by quadrature of degree 2."""
+    n = coords.shape[0]
+    dim = coords.shape[1]
+    det, _ = element_geometry(coords, cells)
+    pts, wts = simplex_quadrature(dim, 2)
+    lam = barycentric(pts)
+    Me = det[:, None, None] * np.einsum("q,qa,qb->ab", wts, lam, lam)[None]
+    return _scatter_matrix(n, cells, Me)
+
+
+def _scatter_matrix(n, cells, Ae) -> sp.csr_matrix:
+    nl = cells.shape[1]
+    rows = np.repeat(cells, nl, axis=1).ravel()
+    cols = np.tile(cells, (1, nl)).ravel()
+    A = sp.coo_matrix((Ae.reshape(-1), (rows, cols)), shape=(n, n)).tocsr()
+    A.sum_duplicates()
+    return A
+
+
+# ----------------------------------------------------------------------------
+# tensor contractions (Notation, Sec. 3.3)
+# ----------------------------------------------------------------------------
+def contract_uv(T: Tensor3, u: np.ndarray, a: np.ndarray) -> np.ndarray:
+    """(T : (u (x) a))_i = sum_jk T_ijk u_j a_k."""
+    return np.bincount(T.i, weights=T.v * u[T.j] * a[T.k], minlength=T.n)
+
+
+def contract_first(T: Tensor3, a: np.ndarray) -> sp.csr_matrix:
+    """(T . a)_ij = sum_k T_ijk a_k."""
+    return sp.coo_matrix((T.v * a[T.k], (T.i, T.j)), shape=(T.n, T.n)).tocsr()
+
+
+def contract_mode2(T: Tensor3, u: np.ndarray) -> sp.csr_matrix:
+    """(T ._2 u)_ik = sum_j T_ijk u_j."""
+    return sp.coo_matrix((T.v * u[T.j], (T.i, T.k)), shape=(T.n, T.n)).tocsr()
+
+
+def contract_mode3(T: Tensor3, lam: np.ndarray, u: np.ndarray) -> np.ndarray:
+    """x_k = sum_ij lam_i T_ijk u_j (adjoint of the a-dependence)."""
+    return np.bincount(T.k, weights=T.v * lam[T.i] * u[T.j], minlength=T.n)
+
+
+# ----------------------------------------------------------------------------
+# problem definition and the reduced EGFEM Newton iteration
+# ----------------------------------------------------------------------------
+@dataclass
+class Problem:
+    T: Tensor3
+    d: np.ndarray                  # load vector (the paper's d), d = M f
+    dirichlet: np.ndarray          # bool [N]
+    a0: np.ndarray                 # [N]
+    K: Optional[sp.csr_matrix] = None   # added linear stiffness (semilinear form)
+    M: Optional[sp.csr_matrix] = None
+    coords: Optional[np.ndarray] = None
+    cells: Optional[np.ndarray] = None
+    form: int = FORM_STIFF
+
+    @property
+    def n(self) -> int:
+        return self.T.n
+
+    @property
+    def free(self) -> np.ndarray:
+        return ~self.dirichlet
+
+
+def build_problem(workload, degree: Optional[int] = None, drop_rel: float = DROP_REL) -> Problem:
+    """Offline phase: tensor, matrices and load for a workload from `workloads`."""
+    mesh = workload.mesh
+    T = assemble_tensor(mesh.coords, mesh.cells, workload.form, degree, drop_rel)
+    M = assemble_mass(mesh.coords, mesh.cells)
+    K = assemble_stiffness(mesh.coords, mesh.cells) if workload.add_stiffness else None
+    a0 = (np.asarray(workload.a0, dtype=np.float64).copy() if workload.a0 is not None
+          else np.full(mesh.n_nodes, float(workload.a0_const)))
+    d = M @ workload.f
+    return Problem(T, d, mesh.dirichlet.astype(bool), a0, K, M, mesh.coords, mesh.cells,
+                   workload.form)
+
+
+def nodal_a(p: Problem, u: np.ndarray) -> np.ndarray:
+    """a = a0 + u*u at the W-dofs (eq. egfem_coeffs with Pi_u = identity)."""
+    return p.a0 + u * u
+
+
+def nodal_da(p: Problem, u: np.ndarray) -> np.ndarray:
+    """pointwise derivative a'(u) = 2u."""
+    return 2.0 * u
+
+
+def residual(p: Problem, u: np.ndarray) -> np.ndarray:
+    """F(u) = [K u] + T:(u (x) a(u)) - d, Dirichlet rows set to zero."""
+    F = contract_uv(p.T, u, nodal_a(p, u)) - p.d
+    if p.K is not None:
+        F = F + p.K @ u
+    F[p.dirichlet] = 0.0
+    return F
+
+
+def _apply_dirichlet(p: Problem, J: sp.csr_matrix) -> sp.csr_matrix:
+    free = sp.diags(p.free.astype(np.float64))
+    dirm = sp.diags(p.dirichlet.astype(np.float64))
+    return (free @ J @ free + dirm).tocsr()
+
+
+def jacobian(p: Problem, u: np.ndarray) -> sp.csr_matrix:
+    """DF(u) = [K] + T . a(u) + (T ._2 u) diag(a'(u)); Dirichlet rows -> identity,
+    Dirichlet columns -> 0 (the reduced form of the block Jacobian of Sec. 4)."""
+    J = contract_first(p.T, nodal_a(p, u)) + contract_mode2(p.T, u) @ sp.diags(nodal_da(p, u))
+    if p.K is not None:
+        J = J + p.K
+    return _apply_dirichlet(p, J)
+
+
+@dataclass
+class NewtonStats:
+    iterations: int = 0
+    residual_norms: list = field(default_factory=list)
+    status: str = "not_converged"
+    backtracks: int = 0
+
+
+def newton(p: Problem, u0: Optional[np.ndarray] = None, tol: float = 1e-10,
+           max_iter: int = 50, residual_fn=None, jacobian_fn=None):
+    """Damped Newton on F(u) = 0.  Stops when ||F|| <= tol ||F(u0)||.  A step is
+    accepted when ||F(u + alpha delta)|| <= (1 - 1e-4 alpha) ||F(u)||, halving
+    alpha up to 10 times; when no trial passes, the iteration stops with status
+    'stagnated' (the residual has reached its rounding floor or the direction
+    is no descent direction)."""
+    residual_fn = residual_fn or (lambda v: residual(p, v))
+    jacobian_fn = jacobian_fn or (lambda v: jacobian(p, v))
+    u = np.zeros(p.n) if u0 is None else np.array(u0, dtype=np.float64)
+    u[p.dirichlet] = 0.0
+    F = residual_fn(u)
+    nF = float(np.linalg.norm(F))
+    nF0 = nF
+    st = NewtonStats(residual_norms=[nF])
+    if nF0 == 0.0:
+        st.status = "converged"
+        return u, st
+    for it in range(max_iter):
+        if nF <= tol * nF0:
+            st.status = "converged"
+            return u, st
+        J = jacobian_fn(u)
+        delta = spla.spsolve(J.tocsc(), -F)
+        alpha = 1.0
+        accepted = False
+        for _ in range(11):
+            ut = u + alpha * delta
+            Ft = residual_fn(ut)
+            nFt = float(np.linalg.norm(Ft))
+            if np.isfinite(nFt) and nFt <= (1.0 - 1e-4 * alpha) * nF:
+                accepted = True
+                break
+            alpha *= 0.5
+            st.backtracks += 1
+        if not accepted:
+            st.status = "stagnated"
+            return u, st
+        u, F, nF = ut, Ft, nFt
+        st.iterations = it + 1
+        st.residual_norms.append(nF)
+    st.status = "converged" if nF <= tol * nF0 else "not_converged"
+    return u, st
+
+
+# ----------------------------------------------------------------------------
+# lifted EGFEM Newton on z = (u, a) exactly as in Sec. 4 (dense; tiny meshes)
+# ----------------------------------------------------------------------------
+def newton_lifted(p: Problem, tol: float = 1e-13, max_iter: int = 50):
+    """z = (u, a);  F~(z) = [ [K u] + T:(u (x) a) - d ;  a - (a0 + u*u) ],
+    D F~ = [[ [K] + T . a , T ._2 u ], [ -diag(2u), I ]] with the u-block's
+    Dirichlet rows replaced by identity rows.  Full Newton steps."""
+    n = p.n
+    D = p.T.dense()
+    Kd = p.K.toarray() if p.K is not None else np.zeros((n, n))
+    u = np.zeros(n)
+    a = p.a0 + u * u
+    free = p.free
+
+    def Ft(u, a):
+        r1 = np.einsum("ijk,j,k->i", D, u, a) + Kd @ u - p.d
+        r1[~free] = u[~free]
+        r2 = a - (p.a0 + u * u)
+        return np.concatenate([r1, r2])
+
+    F = Ft(u, a)
+    nF0 = np.linalg.norm(F)
+    hist = [nF0]
+    for _ in range(max_iter):
+        if np.linalg.norm(F) <= tol * nF0:
+            break
+        Juu = np.einsum("ijk,k->ij", D, a) + Kd
+        Jua = np.einsum("ijk,j->ik", D, u)
+        Juu[~free, :] = 0.0
+        Jua[~free, :] = 0.0
+        Juu[~free, ~free] = 1.0
+        Jau = -np.diag(2.0 * u)
+        Jaa = np.eye(n)
+        Jz = np.block([[Juu, Jua], [Jau, Jaa]])
+        dz = np.linalg.solve(Jz, -F)
+        u = u + dz[:n]
+        a = a + dz[n:]
+        F = Ft(u, a)
+        hist.append(np.linalg.norm(F))
+    return u, a, hist
+
+
+# ----------------------------------------------------------------------------
+# standard Galerkin approach (eq. nonlinear_terms / SGA_root), re-assembled
+# by quadrature at every Newton iteration
+# ----------------------------------------------------------------------------
+def _sga_degree(form: int, dim: int) -> int:
+    if dim == 1:
+        return 5          # 3-point Gauss-Legendre
+    return 2 if form == FORM_STIFF else 4
+
+
+def sga_residual(p: Problem, u: np.ndarray, degree: Optional[int] = None) -> np.ndarray:
+    """F_i = int (a0_h + u_h^2) grad u_h . grad phi_i - d_i           (stiffness)
+       F_i = [K u]_i + int (a0_h + u_h^2) u_h phi_i - d_i            (mass form),
+    with u_h, a0_h the P1 interpolants; exact-degree quadrature per element."""
+    coords, cells = p.coords, p.cells
+    dim = coords.shape[1]
+    degree = degree or _sga_degree(p.form, dim)
+    det, G = element_geometry(coords, cells)
+    pts, wts = simplex_quadrature(dim, degree)
+    lam = barycentric(pts)
+    ue = u[cells]
+    uq = ue @ lam.T                                  # [E, Q]
+    aq = p.a0[cells] @ lam.T
+    wq = det[:, None] * wts[None, :]
+    if p.form == FORM_STIFF:
+        gu = np.einsum("ea,ead->ed", ue, G)
+        c = np.sum(wq * (aq + uq * uq), axis=1)
+        Re = c[:, None] * np.einsum("ead,ed->ea", G, gu)
+    else:
+        Re = np.einsum("eq,qa->ea", wq * (aq + uq * uq) * uq, lam)
+    F = np.bincount(cells.ravel(), weights=Re.ravel(), minlength=p.n) - p.d
+    if p.K is not None:
+        F = F + p.K @ u
+    F[p.dirichlet] = 0.0
+    return F
+
+
+def sga_jacobian(p: Problem, u: np.ndarray, degree: Optional[int] = None) -> sp.csr_matrix:
+    """D_u F re-assembled by quadrature (Sec. 4, Newton for the SGA)."""
+    coords, cells = p.coords, p.cells
+    dim = coords.shape[1]
+    degree = degree or _sga_degree(p.form, dim)
+    det, G = element_geometry(coords, cells)
+    pts, wts = simplex_quadrature(dim, degree)
+    lam = barycentric(pts)
+    ue = u[cells]
+    uq = ue @ lam.T
+    aq = p.a0[cells] @ lam.T
+    wq = det[:, None] * wts[None, :]
+    if p.form == FORM_STIFF:
+        gu = np.einsum("ea,ead->ed", ue, G)
+        GG = np.einsum("ead,ebd->eab", G, G)
+        c = np.sum(wq * (aq + uq * uq), axis=1)
+        Gg = np.einsum("ead,ed->ea", G, gu)          # grad phi_a . grad u_h
+        cross = np.einsum("eq,qb->eb", wq * 2.0 * uq, lam)   # int 2 u_h phi_b
+        Je = c[:, None, None] * GG + Gg[:, :, None] * cross[:, None, :]
+    else:
+        Je = np.einsum("eq,qa,qb->eab", wq * (aq + 3.0 * uq * uq), lam, lam)
+    J = _scatter_matrix(p.n, cells, Je)
+    if p.K is not None:
+        J = J + p.K
+    return _apply_dirichlet(p, J)
+
+
+def sga_newton(p: Problem, u0=None, tol: float = 1e-10, max_iter: int = 50):
+    return newton(p, u0, tol, max_iter, residual_fn=lambda v: sga_residual(p, v),
+                  jacobian_fn=lambda v: sga_jacobian(p, v))
+
+
+# ----------------------------------------------------------------------------
+# EGFEM with W_h = P2 (Case 1, exact reformulation of u^2), any dimension
+# ----------------------------------------------------------------------------
+@dataclass
+class P2Space:
+    n_u: int
+    n_w: int
+    edges: np.ndarray          # [n_edges, 2] global vertex pairs
+    cell_dofs: np.ndarray      # [E, nl + n_local_edges] W-dof ids per element
+    local_edges: list          # list of (a, b) local vertex pairs
+    Pi: sp.csr_matrix          # interpolation Pi_u: V_h -> W_h dofs (Sec. 3.2)
+
+
+def p2_space(coords, cells) -> P2Space:
+    """P2 Lagrange dofs = vertices + edge midpoints; (Pi_u)_kj = phi_j(x_k)."""
+    n = coords.shape[0]
+    nl = cells.shape[1]
+    local_edges = [(a, b) for a in range(nl) for b in range(a + 1, nl)]
+    pairs = np.stack([np.sort(cells[:, [a, b]], axis=1) for (a, b) in local_edges], axis=1)
+    flat = pairs.reshape(-1, 2).astype(np.int64)
+    keys = flat[:, 0] * n + flat[:, 1]
+    ukeys, inv = np.unique(keys, return_inverse=True)
+    edges = np.stack([ukeys // n, ukeys % n], axis=1)
+    edge_dof = n + inv.reshape(cells.shape[0], len(local_edges))
+    cell_dofs = np.concatenate([cells.astype(np.int64), edge_dof], axis=1)
+    ne = edges.shape[0]
+    rows = np.concatenate([np.arange(n), n + np.arange(ne), n + np.arange(ne)])
+    cols = np.concatenate([np.arange(n), edges[:, 0], edges[:, 1]])
+    vals = np.concatenate([np.ones(n), 0.5 * np.ones(ne), 0.5 * np.ones(ne)])
+    Pi = sp.coo_matrix((vals, (rows, cols)), shape=(n + ne, n)).tocsr()
+    return P2Space(n, n + ne, edges, cell_dofs, local_edges, Pi)
+
+
+def _p2_basis(lam: np.ndarray, local_edges) -> np.ndarray:
+    """P2 nodal basis at points: vertex a -> lambda_a (2 lambda_a - 1),
+    edge (a,b) -> 4 lambda_a lambda_b.  Returns [Q, nl + n_edges]."""
+    vert = lam * (2.0 * lam - 1.0)
+    edge = np.stack([4.0 * lam[:, a] * lam[:, b] for (a, b) in local_edges], axis=1)
+    return np.concatenate([vert, edge], axis=1)
+
+
+def assemble_tensor_p2(coords, cells, W: P2Space, form: int):
+    """T_ijk = int eta_k grad phi_j . grad phi_i (or eta_k phi_j phi_i) with eta the
+    P2 basis of W_h; returned as COO arrays with k over W-dofs."""
+    dim = coords.shape[1]
+    det, G = element_geometry(coords, cells)
+    pts, wts = simplex_quadrature(dim, 2 if form == FORM_STIFF else 4)
+    lam = barycentric(pts)
+    eta = _p2_basis(lam, W.local_edges)
+    nl = dim + 1
+    nw = eta.shape[1]
+    if form == FORM_STIFF:
+        GG = np.einsum("ead,ebd->eab", G, G)
+        psi = np.einsum("q,qc->c", wts, eta)
+        Te = det[:, None, None, None] * GG[:, :, :, None] * psi[None, None, None, :]
+    else:
+        trip = np.einsum("q,qa,qb,qc->abc", wts, lam, lam, eta)
+        Te = det[:, None, None, None] * trip[None]
+    ai, bi, ci = np.meshgrid(np.arange(nl), np.arange(nl), np.arange(nw), indexing="ij")
+    I = cells[:, ai.ravel()].ravel().astype(np.int64)
+    J = cells[:, bi.ravel()].ravel().astype(np.int64)
+    K = W.cell_dofs[:, ci.ravel()].ravel()
+    return I, J, K, Te.reshape(-1)
+
+
+@dataclass
+class ProblemP2:
+    base: Problem
+    W: P2Space
+    I: np.ndarray
+    J: np.ndarray
+    K: np.ndarray
+    V: np.ndarray
+
+
+def build_problem_p2(p: Problem) -> ProblemP2:
+    W = p2_space(p.coords, p.cells)
+    I, J, K, V = assemble_tensor_p2(p.coords, p.cells, W, p.form)
+    return ProblemP2(p, W, I, J, K, V)
+
+
+def residual_p2(q: ProblemP2, u: np.ndarray) -> np.ndarray:
+    """F = [K u] + T^{P2}:(u (x) a_W) - d with a_W = Pi a0 + (Pi u)^2 at the P2 dofs."""
+    p = q.base
+    Pu = q.W.Pi @ u
+    aW = q.W.Pi @ p.a0 + Pu * Pu
+    F = np.bincount(q.I, weights=q.V * u[q.J] * aW[q.K], minlength=p.n) - p.d
+    if p.K is not None:
+        F = F + p.K @ u
+    F[p.dirichlet] = 0.0
+    return F
+
+
+def jacobian_p2(q: ProblemP2, u: np.ndarray) -> sp.csr_matrix:
+    p = q.base
+    Pu = q.W.Pi @ u
+    aW = q.W.Pi @ p.a0 + Pu * Pu
+    n, nw = p.n, q.W.n_w
+    A = sp.coo_matrix((q.V * aW[q.K], (q.I, q.J)), shape=(n, n)).tocsr()
+    B = sp.coo_matrix((q.V * u[q.J], (q.I, q.K)), shape=(n, nw)).tocsr()
+    J = A + B @ sp.diags(2.0 * Pu) @ q.W.Pi
+    if p.K is not None:
+        J = J + p.K
+    return _apply_dirichlet(p, J.tocsr())
+
+
+def newton_p2(q: ProblemP2, tol=1e-13, max_iter=50):
+    return newton(q.base, None, tol, max_iter, residual_fn=lambda v: residual_p2(q, v),
+                  jacobian_fn=lambda v: jacobian_p2(q, v))
+
+
+# ----------------------------------------------------------------------------
+# adjoint of the converged solve (implicit function theorem)
+# ----------------------------------------------------------------------------
+def adjoint_gradients(p: Problem, u_star: np.ndarray, ubar: np.ndarray):
+    """For an objective with dJ/du = ubar at the solution u* of F(u; d(f), a0) = 0:
+       J(u*)^T lam = ubar (free rows; lam_D = 0),
+       dJ/df   = M lam               (F depends on f through -d = -M f),
+       dJ/da0  = -(T ._2 u*)^T lam,  i.e. -sum_ij lam_i T_ijk u*_j.
+    Returns (lam, grad_f, grad_a0)."""
+    J = jacobian(p, u_star)
+    rhs = np.array(ubar, dtype=np.float64)
+    rhs[p.dirichlet] = 0.0
+    lam = spla.spsolve(J.T.tocsc(), rhs)
+    grad_f = p.M @ lam
+    grad_a0 = -contract_mode3(p.T, lam, u_star)
+    return lam, grad_f, grad_a0
+
+
+def tracking_objective(u: np.ndarray, u_d: np.ndarray) -> float:
+    """J = 0.5 sum_i (u_i - u_d,i)^2 (nodal Euclidean)."""
+    r = u - u_d
+    return 0.5 * float(r @ r)
+
+
+# ----------------------------------------------------------------------------
+# the stream sizes of the stored tensor, for byte accounting
+# ----------------------------------------------------------------------------
+def slot_count(T: Tensor3) -> int:
+    """Number of distinct (i, j) pairs carrying at least one stored T_ijk."""
+    return int(np.unique(T.i * T.n + T.j).size)

@@ -1,0 +1,452 @@
+"""Pins of the CPU oracle against facts fixed by the mathematics or printed in
+the paper (not against the oracle itself).  CPU only."""
+import math
+import itertools
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as W
+from oracle import egfem_oracle as O
+
+
+# ----------------------------------------------------------------------------
+# exact rational helpers (brute force, independent of the oracle's numpy code)
+# ----------------------------------------------------------------------------
+def _frac_inv(B):
+    n = len(B)
+    A = [[Fraction(B[r][c]) for c in range(n)] + [Fraction(int(r == c)) for c in range(n)]
+         for r in range(n)]
+    for c in range(n):
+        p = next(r for r in range(c, n) if A[r][c] != 0)
+        A[c], A[p] = A[p], A[c]
+        piv = A[c][c]
+        A[c] = [x / piv for x in A[c]]
+        for r in range(n):
+            if r != c and A[r][c] != 0:
+                f = A[r][c]
+                A[r] = [x - f * y for x, y in zip(A[r], A[c])]
+    return [row[n:] for row in A]
+
+
+def _frac_det(B):
+    n = len(B)
+    if n == 1:
+        return Fraction(B[0][0])
+    return sum((-1) ** c * Fraction(B[0][c]) *
+               _frac_det([row[:c] + row[c + 1:] for row in B[1:]]) for c in range(n))
+
+
+def _exact_element(verts):
+    """grad lambda_a (exact rationals) and |e| for one simplex."""
+    d = len(verts) - 1
+    x0 = verts[0]
+    B = [[Fraction(verts[m + 1][r]) - Fraction(x0[r]) for m in range(d)] for r in range(d)]
+    Binv = _frac_inv(B)
+    vol = abs(_frac_det(B)) / math.factorial(d)
+    grads = [[-sum(Binv[m][r] for m in range(d)) for r in range(d)]] + [Binv[m] for m in range(d)]
+    return grads, vol
+
+
+def _int_monomial(alpha, vol, d):
+    """int_e prod lambda_a^alpha_a = d! prod(alpha_a!) |e| / (d + |alpha|)!"""
+    return Fraction(math.factorial(d) * math.prod(math.factorial(a) for a in alpha),
+                    math.factorial(d + sum(alpha))) * vol
+
+
+def _exact_tensor(coords, cells, form):
+    n, d = coords.shape
+    T = {}
+    for cell in cells:
+        verts = [[Fraction(float(x)) for x in coords[v]] for v in cell]
+        grads, vol = _exact_element(verts)
+        for a, b, c in itertools.product(range(d + 1), repeat=3):
+            if form == O.FORM_STIFF:
+                gg = sum(grads[a][r] * grads[b][r] for r in range(d))
+                al = [0] * (d + 1)
+                al[c] += 1
+                val = gg * _int_monomial(al, vol, d)
+            else:
+                al = [0] * (d + 1)
+                for x in (a, b, c):
+                    al[x] += 1
+                val = _int_monomial(al, vol, d)
+            key = (int(cell[a]), int(cell[b]), int(cell[c]))
+            T[key] = T.get(key, Fraction(0)) + val
+    return {k: v for k, v in T.items() if v != 0}
+
+
+def _as_dict(T: O.Tensor3):
+    return {(int(i), int(j), int(k)): float(v) for i, j, k, v in zip(T.i, T.j, T.k, T.v)}
+
+
+IRREGULAR = {
+    1: (np.array([[0.0], [0.375], [1.0]]), np.array([[0, 1], [1, 2]], dtype=np.int32)),
+    2: (np.array([[0.0, 0.0], [0.75, 0.125], [0.25, 0.625], [1.0, 0.875]]),
+        np.array([[0, 1, 2], [1, 3, 2]], dtype=np.int32)),
+    3: (np.array([[0.0, 0.0, 0.0], [0.75, 0.125, 0.0], [0.25, 0.625, 0.125],
+                  [0.125, 0.25, 0.5], [0.875, 0.75, 0.625]]),
+        np.array([[0, 1, 2, 3], [1, 2, 3, 4]], dtype=np.int32)),
+}
+
+
+# ----------------------------------------------------------------------------
+# quadrature
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_quadrature_exact_for_monomials(dim):
+    for deg in range(0, 7):
+        X, Wt = O.simplex_quadrature(dim, deg)
+        lam = O.barycentric(X)
+        assert abs(Wt.sum() - 1.0 / math.factorial(dim)) < 1e-15
+        for alpha in itertools.product(range(deg + 1), repeat=dim + 1):
+            if sum(alpha) > deg:
+                continue
+            num = np.sum(Wt * np.prod(lam ** np.array(alpha), axis=1))
+            ex = float(_int_monomial(alpha, Fraction(1, math.factorial(dim)), dim))
+            assert abs(num - ex) < 1e-15
+
+
+# ----------------------------------------------------------------------------
+# meshes and the sizes printed in the paper
+# ----------------------------------------------------------------------------
+def test_mesh_counts_and_volume():
+    for dim, n, nodes, cells in [(1, 256, 257, 256), (2, 256, 66049, 131072),
+                                 (2, 512, 263169, 524288), (3, 16, 17 ** 3, 6 * 16 ** 3)]:
+        m = W.structured_mesh(dim, n)
+        assert m.n_nodes == nodes and m.n_cells == cells
+        det, _ = O.element_geometry(m.coords, m.cells)
+        assert abs(det.sum() / math.factorial(dim) - 1.0) < 1e-12
+
+
+def test_table1_system_sizes():
+    """Sizes of Table tbl:superconductivity (Sec. 5.3) on the 64x64 triangle mesh."""
+    rows = {}
+    with open(__file__.replace("test_oracle_pins.py", "golden/table1_sizes.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                name, size = line.split()
+                rows[name] = int(size)
+    m = W.mesh_2d(64)
+    p2 = O.p2_space(m.coords, m.cells)
+    n_u, n_el = m.n_nodes, m.n_cells
+    n_edges = p2.edges.shape[0]
+    assert rows["SGA"] == n_u                              # u only
+    assert rows["GFEM"] == 2 * n_u                         # u + c on V_h
+    assert rows["EGFEM_P2"] == n_u + p2.n_w                # u + c on P2
+    assert rows["EGFEM_P3"] == n_u + n_u + 2 * n_edges + n_el   # P3: vertices, 2/edge, 1/cell
+    assert rows["EGFEM_I4"] == n_u + 6 * n_el              # 6-point degree-4 rule per triangle
+
+
+# ----------------------------------------------------------------------------
+# matrices
+# ----------------------------------------------------------------------------
+def test_stiffness_is_finite_difference_stencil():
+    n = 8
+    h = 1.0 / n
+    K1 = O.assemble_stiffness(*(lambda m: (m.coords, m.cells))(W.mesh_1d(n))).toarray()
+    assert np.allclose(K1[3, 2:5], [-1 / h, 2 / h, -1 / h], atol=1e-12)
+    m = W.mesh_2d(n)
+    K2 = O.assemble_stiffness(m.coords, m.cells).toarray()
+    i = 3 * (n + 1) + 4
+    row = K2[i]
+    assert abs(row[i] - 4.0) < 1e-13
+    for o in (1, -1, n + 1, -(n + 1)):
+        assert abs(row[i + o] + 1.0) < 1e-13
+    assert np.sum(np.abs(row) > 1e-13) == 5
+    m = W.mesh_3d(4)
+    K3 = O.assemble_stiffness(m.coords, m.cells).toarray()
+    s = 5
+    i = (2 * s + 2) * s + 2
+    row = K3[i]
+    h = 0.25
+    assert abs(row[i] - 6 * h) < 1e-13
+    for o in (1, -1, s, -s, s * s, -s * s):
+        assert abs(row[i + o] + h) < 1e-13
+    assert np.sum(np.abs(row) > 1e-13) == 7
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_mass_matrix(dim):
+    m = W.structured_mesh(dim, 4)
+    M = O.assemble_mass(m.coords, m.cells)
+    assert abs(M.sum() - 1.0) < 1e-13
+    # consistent mass: M_aa = 2|e|/((d+1)(d+2)), M_ab = |e|/((d+1)(d+2)) per element
+    coords, cells = IRREGULAR[dim]
+    Mi = O.assemble_mass(coords, cells).toarray()
+    ex = np.zeros_like(Mi)
+    for cell in cells:
+        _, vol = _exact_element([[Fraction(float(x)) for x in coords[v]] for v in cell])
+        for a in cell:
+            for b in cell:
+                ex[a, b] += float(vol * (2 if a == b else 1) / ((dim + 1) * (dim + 2)))
+    assert np.abs(Mi - ex).max() < 1e-15
+
+
+# ----------------------------------------------------------------------------
+# third-order tensors
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("dim", [1, 2, 3])
+@pytest.mark.parametrize("form", [O.FORM_STIFF, O.FORM_MASS])
+def test_tensor_matches_exact_rational_integrals(dim, form):
+    coords, cells = IRREGULAR[dim]
+    T = _as_dict(O.assemble_tensor(coords, cells, form, drop_rel=0.0))
+    ex = _exact_tensor(coords, cells, form)
+    assert set(T) == set(ex)
+    scale = max(abs(float(v)) for v in ex.values())
+    for key, v in ex.items():
+        assert abs(T[key] - float(v)) <= 1e-14 * scale
+
+
+def test_stiffness_tensor_identities():
+    for dim, n in [(1, 8), (2, 6), (3, 3)]:
+        m = W.structured_mesh(dim, n)
+        T = O.assemble_tensor(m.coords, m.cells, O.FORM_STIFF)
+        K = O.assemble_stiffness(m.coords, m.cells)
+        # T . 1 = K  (sum over k of int psi_k grad.grad, partition of unity of psi)
+        assert abs(O.contract_first(T, np.ones(T.n)) - K).max() < 1e-13
+        D = T.dense()
+        assert np.abs(D - D.transpose(1, 0, 2)).max() < 1e-14      # T_ijk = T_jik
+        assert np.abs(D.sum(axis=1)).max() < 1e-13                   # sum_j grad phi_j = 0
+        # per element T^e_ijk = K^e_ij / (d+1): with psi = 1 summed, equals K
+        assert np.abs(D.sum(axis=2) - K.toarray()).max() < 1e-13
+
+
+def test_mass_tensor_identities():
+    for dim, n in [(1, 8), (2, 5), (3, 2)]:
+        m = W.structured_mesh(dim, n)
+        T = O.assemble_tensor(m.coords, m.cells, O.FORM_MASS)
+        M = O.assemble_mass(m.coords, m.cells).toarray()
+        D = T.dense()
+        for perm in itertools.permutations(range(3)):
+            assert np.abs(D - D.transpose(perm)).max() < 1e-16
+        assert np.abs(D.sum(axis=2) - M).max() < 1e-15
+
+
+def test_tensor_nnz_closed_forms():
+    for n in (2, 3, 5, 8, 12):
+        m = W.mesh_2d(n)
+        T = O.assemble_tensor(m.coords, m.cells, O.FORM_STIFF)
+        assert T.nnz == 23 * n * n + 14 * n + 1
+        assert T.structural_nnz == 31 * n * n + 14 * n + 1
+        assert O.slot_count(T) == 5 * n * n + 6 * n + 1
+        TM = O.assemble_tensor(m.coords, m.cells, O.FORM_MASS)
+        assert TM.nnz == 31 * n * n + 14 * n + 1
+        assert O.slot_count(TM) == 7 * n * n + 6 * n + 1
+    for n in (2, 3, 4):
+        m = W.mesh_3d(n)
+        T = O.assemble_tensor(m.coords, m.cells, O.FORM_STIFF)
+        assert T.nnz == 63 * n ** 3 + 69 * n ** 2 + 21 * n + 1
+        assert T.structural_nnz == 115 * n ** 3 + 93 * n ** 2 + 21 * n + 1
+
+
+# ----------------------------------------------------------------------------
+# residual and Jacobian
+# ----------------------------------------------------------------------------
+def _small_problem(dim, n, form=O.FORM_STIFF, seed=5):
+    rng = np.random.default_rng(seed)
+    m = W.structured_mesh(dim, n)
+    if form == O.FORM_STIFF:
+        wl = W.Workload("t", m, rng.uniform(0, 10, m.n_nodes), form,
+                        rng.uniform(0.5, 2.0, m.n_nodes) if dim == 3 else None, 1.0, False, 1e-12, seed)
+    else:
+        wl = W.Workload("t", m, rng.uniform(-50, 50, m.n_nodes), form, None, 0.0, True, 1e-12, seed)
+    return O.build_problem(wl)
+
+
+def test_residual_special_cases():
+    p = _small_problem(2, 6)
+    rng = np.random.default_rng(1)
+    u = rng.uniform(-1, 1, p.n)
+    K = O.assemble_stiffness(p.coords, p.cells)
+    # constant a: T:(u (x) c 1) = c K u
+    assert np.abs(O.contract_uv(p.T, u, np.full(p.n, 2.5)) - 2.5 * (K @ u)).max() < 1e-12
+    # constant u: T:(c 1 (x) a) = 0 (sum_j grad phi_j = 0)
+    assert np.abs(O.contract_uv(p.T, np.full(p.n, 1.7), rng.uniform(1, 2, p.n))).max() < 1e-12
+
+
+@pytest.mark.parametrize("dim,n,form", [(1, 9, O.FORM_STIFF), (2, 5, O.FORM_STIFF),
+                                        (3, 2, O.FORM_STIFF), (2, 5, O.FORM_MASS)])
+def test_jacobian_taylor_and_fd(dim, n, form):
+    p = _small_problem(dim, n, form)
+    rng = np.random.default_rng(2)
+    u = rng.uniform(-1, 1, p.n)
+    u[p.dirichlet] = 0
+    v = rng.uniform(-1, 1, p.n)
+    v[p.dirichlet] = 0
+    J = O.jacobian(p, u)
+    F0 = O.residual(p, u)
+    errs = []
+    for eps in (1e-2, 5e-3, 2.5e-3):
+        errs.append(np.linalg.norm(O.residual(p, u + eps * v) - F0 - eps * (J @ v)))
+    assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5       # O(eps^2)
+    # full central-difference columns on the free nodes
+    Jd = J.toarray()
+    h = 1e-6
+    for c in np.flatnonzero(~p.dirichlet)[:6]:
+        e = np.zeros(p.n)
+        e[c] = h
+        col = (O.residual(p, u + e) - O.residual(p, u - e)) / (2 * h)
+        col[p.dirichlet] = 0
+        Jc = Jd[:, c].copy()
+        Jc[p.dirichlet] = 0
+        assert np.abs(col - Jc).max() < 1e-6 * max(1.0, np.abs(Jc).max())
+
+
+@pytest.mark.parametrize("dim,n,form", [(1, 8, O.FORM_STIFF), (2, 4, O.FORM_STIFF),
+                                        (3, 2, O.FORM_STIFF), (2, 4, O.FORM_MASS)])
+def test_lifted_newton_matches_reduced(dim, n, form):
+    p = _small_problem(dim, n, form)
+    u_red, st = O.newton(p, tol=1e-14, max_iter=40)
+    u_lift, a_lift, hist = O.newton_lifted(p, tol=1e-14)
+    assert np.linalg.norm(u_red - u_lift) <= 1e-12 * np.linalg.norm(u_red)
+    assert np.abs(a_lift - (p.a0 + u_lift ** 2)).max() < 1e-12
+
+
+# ----------------------------------------------------------------------------
+# closed-form solutions
+# ----------------------------------------------------------------------------
+def _cardano(p_, q_):
+    """Real root of t^3 + p t + q = 0 for p > 0."""
+    disc = math.sqrt(q_ * q_ / 4 + p_ ** 3 / 27)
+    return math.copysign(abs(-q_ / 2 + disc) ** (1 / 3), -q_ / 2 + disc) + \
+        math.copysign(abs(-q_ / 2 - disc) ** (1 / 3), -q_ / 2 - disc)
+
+
+def test_single_interior_node_1d():
+    """n = 2, h = 1/2: F_1 = u (sum_k T_11k a_k) - d_1 = 4u + 2u^3 - d_1."""
+    m = W.mesh_1d(2)
+    for fval in (0.3, 7.0, -12.0):
+        wl = W.Workload("t", m, np.full(3, fval), O.FORM_STIFF, None, 1.0, False, 1e-14, 0)
+        p = O.build_problem(wl)
+        u, st = O.newton(p, tol=1e-15, max_iter=60)
+        d1 = p.d[1]
+        ex = _cardano(2.0, -d1 / 2.0)          # u^3 + 2u - d1/2 = 0
+        assert abs(u[1] - ex) <= 1e-14 * max(1.0, abs(ex))
+
+
+def _thomas(a, b, c, r):
+    n = len(b)
+    cp = np.zeros(n)
+    dp = np.zeros(n)
+    cp[0] = c[0] / b[0]
+    dp[0] = r[0] / b[0]
+    for i in range(1, n):
+        den = b[i] - a[i] * cp[i - 1]
+        cp[i] = c[i] / den if i < n - 1 else 0.0
+        dp[i] = (r[i] - a[i] * dp[i - 1]) / den
+    x = np.zeros(n)
+    x[-1] = dp[-1]
+    for i in range(n - 2, -1, -1):
+        x[i] = dp[i] - cp[i] * x[i + 1]
+    return x
+
+
+def test_sga_1d_kirchhoff_closed_form():
+    """With exact quadrature the 1D SGA residual is K V(u) - d, V(u) = u + u^3/3
+    (grad phi_i is constant on each cell), so u_i solves u + u^3/3 = V_i with
+    V = K^{-1} d on the free nodes."""
+    n = 32
+    wl = W.nonlinear_diffusion_1d(n)
+    p = O.build_problem(wl)
+    u, st = O.sga_newton(p, tol=1e-15, max_iter=60)
+    h = 1.0 / n
+    nf = n - 1
+    V = _thomas(np.full(nf, -1 / h), np.full(nf, 2 / h), np.full(nf, -1 / h), p.d[1:-1])
+    ex = np.array([_cardano(3.0, -3.0 * v) for v in V])
+    assert np.abs(u[1:-1] - ex).max() <= 1e-13 * np.abs(ex).max()
+
+
+def test_egfem_p2_equals_sga():
+    """Case 1: W_h = P2 describes u_h^2 exactly, so EGFEM(P2) == SGA."""
+    for dim, n, form in [(1, 16, O.FORM_STIFF), (2, 6, O.FORM_STIFF), (2, 6, O.FORM_MASS)]:
+        p = _small_problem(dim, n, form)
+        rng = np.random.default_rng(3)
+        u = rng.uniform(-1, 1, p.n)
+        u[p.dirichlet] = 0
+        q = O.build_problem_p2(p)
+        Fs = O.sga_residual(p, u)
+        assert np.abs(O.residual_p2(q, u) - Fs).max() <= 1e-13 * np.abs(Fs).max()
+        Js = O.sga_jacobian(p, u)
+        assert abs(O.jacobian_p2(q, u) - Js).max() <= 1e-13 * abs(Js).max()
+        u1, _ = O.newton_p2(q, tol=1e-14)
+        u2, _ = O.sga_newton(p, tol=1e-14)
+        assert np.linalg.norm(u1 - u2) <= 1e-13 * np.linalg.norm(u2)
+
+
+def test_egfem_p1_vs_sga_second_order():
+    """Case 2 (P1) is an O(h^2) perturbation of SGA."""
+    diffs = []
+    for n in (16, 32, 64, 128):
+        m = W.mesh_1d(n)
+        x = m.coords[:, 0]
+        wl = W.Workload("t", m, 20 * np.sin(np.pi * x) + 5, O.FORM_STIFF, None, 1.0, False, 1e-14, 0)
+        p = O.build_problem(wl)
+        u1, _ = O.newton(p, tol=1e-14)
+        u2, _ = O.sga_newton(p, tol=1e-14)
+        diffs.append(np.abs(u1 - u2).max())
+    ratios = [diffs[i] / diffs[i + 1] for i in range(3)]
+    assert 3.7 < ratios[-1] < 4.3 and ratios[0] < ratios[1] < ratios[2], ratios
+
+
+def test_manufactured_solution_second_order():
+    """u* = sin(pi x) sin(pi y) vanishes on the boundary.  For
+    -div((1+u^2) grad u) = f:  f = 2 pi^2 u (1+u^2) - 2 u |grad u|^2;
+    for -Laplace u + u^3 = f:  f = 2 pi^2 u + u^3.  Nodal errors decay as h^2."""
+    for form in (O.FORM_STIFF, O.FORM_MASS):
+        errs = []
+        for n in (8, 16, 32):
+            m = W.mesh_2d(n)
+            x, y = m.coords[:, 0], m.coords[:, 1]
+            us = np.sin(np.pi * x) * np.sin(np.pi * y)
+            g2 = np.pi ** 2 * (np.cos(np.pi * x) ** 2 * np.sin(np.pi * y) ** 2 +
+                               np.sin(np.pi * x) ** 2 * np.cos(np.pi * y) ** 2)
+            if form == O.FORM_STIFF:
+                f = 2 * np.pi ** 2 * us * (1 + us ** 2) - 2 * us * g2
+                wl = W.Workload("t", m, f, form, None, 1.0, False, 1e-13, 0)
+            else:
+                f = 2 * np.pi ** 2 * us + us ** 3
+                wl = W.Workload("t", m, f, form, None, 0.0, True, 1e-13, 0)
+            p = O.build_problem(wl)
+            u, st = O.newton(p, tol=1e-13)
+            errs.append(np.abs(u - us).max())
+        assert 3.3 < errs[0] / errs[1] < 4.7 and 3.3 < errs[1] / errs[2] < 4.7, errs
+
+
+# ----------------------------------------------------------------------------
+# adjoint
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("dim,n", [(2, 5), (3, 2)])
+def test_adjoint_against_finite_differences(dim, n):
+    rng = np.random.default_rng(7)
+    m = W.structured_mesh(dim, n)
+    kappa = rng.uniform(0.5, 2.0, m.n_nodes)
+    f = rng.uniform(0, 10, m.n_nodes)
+    u_d = rng.uniform(0, 0.2, m.n_nodes)
+
+    def solve(fv, kv):
+        wl = W.Workload("t", m, fv, O.FORM_STIFF, kv, 0.0, False, 1e-15, 0)
+        p = O.build_problem(wl)
+        u, _ = O.newton(p, tol=1e-15, max_iter=60)
+        return p, u
+
+    p, u = solve(f, kappa)
+    lam, gf, gk = O.adjoint_gradients(p, u, u - u_d)
+    # dot-product test of the transpose solve: <J v, lam> = <v, J^T lam>
+    J = O.jacobian(p, u)
+    v = rng.uniform(-1, 1, p.n)
+    rhs = (u - u_d).copy()
+    rhs[p.dirichlet] = 0
+    assert abs((J @ v) @ lam - v @ rhs) < 1e-12 * max(1.0, abs(v @ rhs))
+    h = 1e-6
+    for vec, grad, which in ((v, gf, "f"), (rng.uniform(-1, 1, p.n), gk, "k")):
+        if which == "f":
+            jp = O.tracking_objective(solve(f + h * vec, kappa)[1], u_d)
+            jm = O.tracking_objective(solve(f - h * vec, kappa)[1], u_d)
+        else:
+            jp = O.tracking_objective(solve(f, kappa + h * vec)[1], u_d)
+            jm = O.tracking_objective(solve(f, kappa - h * vec)[1], u_d)
+        fd = (jp - jm) / (2 * h)
+        assert abs(fd - grad @ vec) <= 1e-6 * max(abs(fd), 1e-8), (which, fd, grad @ vec)
