@@ -1,0 +1,253 @@
+/*
+ * egfem.h -- C ABI of libegfem, the MI355X (gfx950) EGFEM Newton hot path.
+ *
+ * Method: Tolle & Marheineke, "Extended Group Finite Element Method"
+ * (arXiv 2005.06193).  A nonlinear coefficient a(u) is interpolated onto its
+ * own space W_h (here W_h = V_h = P1, Case 2 of Sec. 3.1, i.e. the group FEM
+ * choice), so the nonlinear form becomes the trilinear form of eq.
+ * (egfem_terms):
+ *
+ *     (K_a : (u (x) a))_i = sum_jk T_ijk u_j a_k,
+ *     T_ijk = int phi_k grad phi_j . grad phi_i      (EGFEM_FORM_STIFF)
+ *     T_ijk = int phi_k phi_j phi_i                  (EGFEM_FORM_MASS, the
+ *             trilinear mass form of Sec. 5.3, decomposition (a)).
+ *
+ * The discrete problem solved is the u-reduced form of eq. (EGFEM_root):
+ *
+ *     F(u) = [K u] + T:(u (x) a(u)) - d = 0   on the free nodes,
+ *     a(u) = a0 + u*u (pointwise at the nodes, eq. egfem_coeffs, Pi_u = I),
+ *     u = 0 on the Dirichlet nodes,
+ *
+ * by Newton's method (Sec. 4).  Its Jacobian needs no integration, only the
+ * contractions of the Notation in Sec. 3.3:
+ *
+ *     DF = [K] + T . a + (T ._2 u) diag(a'(u)),   a'(u) = 2u,
+ *
+ * emitted into the fixed CSR pattern of the P1 node adjacency (diagonal
+ * included) and solved with Jacobi-preconditioned BiCGStab.
+ *
+ * Conventions for every entry point below
+ *  - Vectors are float64 and contiguous.  Pointers documented as "device" are
+ *    HIP device pointers owned by the caller (e.g. torch tensor storage); the
+ *    library never frees them.  "host" pointers are ordinary CPU memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    kernels of a call are enqueued on it.  Calls that return numbers to the
+ *    host (norms, statistics) synchronise that stream; the others do not.
+ *  - Return value: 0 = EGFEM_OK; > 0 = numerical outcome (outputs and
+ *    statistics are valid); < 0 = error, nothing was written, and
+ *    egfem_last_error() returns a message (thread-local).
+ *  - A handle owns the device buffers it allocates (tensor streams, pattern,
+ *    matrices, solver workspace).  Calls that use the solver workspace of a
+ *    handle (newton, solve) must not run concurrently on the same handle.
+ *  - Results are deterministic for a fixed launch configuration: no floating
+ *    point atomics; reductions use a fixed order.
+ */
+#ifndef EGFEM_H
+#define EGFEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct egfem_tensor_s* egfem_tensor_t;
+
+enum egfem_status {
+  EGFEM_OK = 0,
+  EGFEM_NOT_CONVERGED = 1,   /* iteration cap reached */
+  EGFEM_BREAKDOWN = 2,       /* BiCGStab breakdown (rho or omega ~ 0) after one restart */
+  EGFEM_NONFINITE = 3,       /* NaN/Inf met in a residual or Krylov scalar */
+  EGFEM_STAGNATED = 4,       /* no damped step decreases ||F|| (rounding floor reached) */
+  EGFEM_ERR_ARG = -1,        /* null pointer, bad enum, bad option value */
+  EGFEM_ERR_SHAPE = -2,      /* sizes inconsistent or beyond a documented limit */
+  EGFEM_ERR_OOM = -3,        /* device or host allocation failed */
+  EGFEM_ERR_HIP = -4,        /* a HIP runtime call failed */
+  EGFEM_ERR_MESH = -5        /* cell index out of range or degenerate simplex */
+};
+
+enum egfem_form {
+  EGFEM_FORM_STIFF = 0,      /* T_ijk = int phi_k grad phi_j . grad phi_i */
+  EGFEM_FORM_MASS = 1        /* T_ijk = int phi_k phi_j phi_i (fully symmetric) */
+};
+
+/* ------------------------------------------------------------------------
+ * Offline phase (Sec. 3.3 eq. egfem_terms; the paper excludes it from the
+ * online times, Sec. 5 preamble).
+ *
+ * egfem_build_tensor: assemble T, the P1 stiffness matrix K_ij = int grad
+ * phi_j . grad phi_i and the consistent mass matrix M_ij = int phi_j phi_i on
+ * a conforming P1 simplex mesh, by exact integration of the element
+ * polynomials, and upload them as device streams.
+ *   dim      1, 2 or 3
+ *   coords   host [n_nodes * dim], node-major (x0,y0,x1,y1,...)
+ *   cells    host [n_cells * (dim+1)], 0-based node ids of each simplex
+ *   form     EGFEM_FORM_STIFF or EGFEM_FORM_MASS
+ *   drop_rel after summing element contributions, an entry is dropped when
+ *            |T_ijk| <= drop_rel * max_{j',k'} |T_ij'k'| (0: only exact zeros).
+ *            1e-13 removes the entries that vanish in exact arithmetic.
+ *   out      receives the handle.
+ * Limits: n_nodes < 2^31, stored entries < 2^31, and every node row must fit
+ * one row block (<= 1024 tensor entries and <= 512 adjacency slots per row),
+ * else EGFEM_ERR_SHAPE.  A zero-volume cell or an index outside [0, n_nodes)
+ * gives EGFEM_ERR_MESH.  Synchronous (host arrays may be reused on return).
+ * ---------------------------------------------------------------------- */
+int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords,
+                       int64_t n_cells, const int32_t* cells, int form,
+                       double drop_rel, egfem_tensor_t* out);
+
+void egfem_tensor_destroy(egfem_tensor_t T);
+
+/* Sizes and read-only device views of the pattern (for callers that build
+ * their own matrices in the same CSR pattern). */
+typedef struct {
+  int dim;
+  int form;
+  int symmetric;             /* 1: T fully symmetric (mass), B-stream aliases A */
+  int64_t n_nodes;
+  int64_t n_cells;
+  int64_t nnz;               /* stored entries of T (A-stream length) */
+  int64_t nnz_b;             /* B-stream length (== nnz) */
+  int64_t structural_nnz;    /* entries before the drop rule */
+  int64_t slots;             /* CSR entries of the P1 adjacency incl. diagonal */
+  int64_t row_blocks;        /* row blocks of the tensor-action kernels */
+  int64_t device_bytes;      /* bytes of device memory owned by the handle */
+  const int32_t* rowptr;     /* device [n_nodes+1] */
+  const int32_t* col;        /* device [slots], ascending within a row */
+  const double* kval;        /* device [slots] stiffness matrix values */
+  const double* mval;        /* device [slots] mass matrix values */
+} egfem_info;
+
+int egfem_tensor_info(egfem_tensor_t T, egfem_info* info);
+
+/* Copy the stored tensor to host COO arrays, ordered by (i, j, k), each of
+ * length info.nnz (caller-allocated host memory).  Synchronous. */
+int egfem_tensor_export(egfem_tensor_t T, int32_t* i, int32_t* j, int32_t* k, double* v);
+
+/* Copy the CSR pattern to host arrays rowptr [n_nodes+1] and col [slots]
+ * (caller-allocated).  Synchronous. */
+int egfem_tensor_pattern(egfem_tensor_t T, int32_t* rowptr, int32_t* col);
+
+/* ------------------------------------------------------------------------
+ * Online tensor actions (Notation of Sec. 3.3).
+ * ---------------------------------------------------------------------- */
+
+/* egfem_residual: raw trilinear action r_i = sum_jk T_ijk u_j a_k
+ * (second contraction T:(u (x) a), eq. egfem_terms).  No boundary rows, no
+ * load.  u, a, r: device [n_nodes]; r must not alias u or a. */
+int egfem_residual(egfem_tensor_t T, const double* u, const double* a, double* r,
+                   void* stream);
+
+/* egfem_jacobian: emit J in the CSR pattern of T (Sec. 4, block Jacobian
+ * reduced to u; no integration):
+ *   J_ij = [K_ij] + sum_k T_ijk a_k + dadu_j * sum_j' T_ij'j u_j'
+ * u, a: device [n_nodes]; dadu: device [n_nodes] or NULL (term omitted);
+ * add_stiffness: nonzero adds K; dirichlet: device uint8 [n_nodes] or NULL --
+ * rows with dirichlet[i] != 0 become identity rows and columns of such nodes
+ * become zero in the other rows; jval: device [slots].  dinv: device
+ * [n_nodes] or NULL, receives 1 / J_ii (Jacobi preconditioner). */
+int egfem_jacobian(egfem_tensor_t T, const double* u, const double* a, const double* dadu,
+                   int add_stiffness, const uint8_t* dirichlet, double* jval, double* dinv,
+                   void* stream);
+
+/* egfem_mode3: out_k = sum_ij w_i T_ijk u_j (adjoint of the a-dependence of
+ * the residual, i.e. ((T ._2 u)^T w)_k).  w, u, out: device [n_nodes]. */
+int egfem_mode3(egfem_tensor_t T, const double* w, const double* u, double* out, void* stream);
+
+/* egfem_matvec: y = A x for a matrix in T's CSR pattern.
+ * which: 0 = jval (caller values, device [slots]), 1 = stiffness K, 2 = mass M.
+ * transpose: nonzero computes A^T x (through the slot transpose permutation;
+ * deterministic, no atomics).  x, y: device [n_nodes], no aliasing. */
+int egfem_matvec(egfem_tensor_t T, int which, const double* jval, int transpose,
+                 const double* x, double* y, void* stream);
+
+/* ------------------------------------------------------------------------
+ * The nonlinear problem and Newton's method (Sec. 4).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  const double* a0;          /* device [n_nodes] or NULL: then a0_const everywhere */
+  double a0_const;
+  const double* load;        /* device [n_nodes]: the load vector d (e.g. M f) */
+  const uint8_t* dirichlet;  /* device [n_nodes], nonzero = Dirichlet node (u = 0); NULL = none */
+  int add_stiffness;         /* nonzero: F gets + K u (semilinear form) */
+} egfem_problem;
+
+/* F = [K u] + T:(u (x) (a0 + u*u)) - d, Dirichlet rows 0.  u, F: device.
+ * If norm != NULL it receives ||F||_2 on the host (synchronises the stream). */
+int egfem_problem_residual(egfem_tensor_t T, const egfem_problem* p, const double* u,
+                           double* F, double* norm, void* stream);
+
+/* DF(u) = [K] + T . a + (T ._2 u) diag(2u) with Dirichlet identity rows and
+ * zero Dirichlet columns, into jval (device [slots]); dinv optional as above. */
+int egfem_problem_jacobian(egfem_tensor_t T, const egfem_problem* p, const double* u,
+                           double* jval, double* dinv, void* stream);
+
+typedef struct {
+  double tol;                /* stop when ||F||_2 <= tol * ||F(u0)||_2 (default 1e-10) */
+  int max_newton;            /* default 50 */
+  int max_krylov;            /* BiCGStab iterations per linear solve (default 20000) */
+  double krylov_rtol;        /* inner relative tolerance when forcing == 0 (default 1e-12) */
+  int forcing;               /* 0: fixed krylov_rtol; 1: Eisenstat-Walker choice 2 */
+  double eta_max;            /* EW cap (default 0.1) */
+  int max_backtracks;        /* damping halvings (default 10) */
+  int krylov_blocks;         /* persistent Krylov grid size, 0 = automatic */
+} egfem_newton_opts;
+
+#define EGFEM_HIST 64
+
+typedef struct {
+  int status;                /* egfem_status of the solve */
+  int newton_iters;
+  int krylov_iters;          /* total over all Newton steps */
+  int backtracks;
+  double res0;               /* ||F(u0)||_2 */
+  double res;                /* final ||F||_2 */
+  double res_hist[EGFEM_HIST];    /* ||F|| after step k (k < EGFEM_HIST) */
+  int krylov_hist[EGFEM_HIST];    /* Krylov iterations of step k */
+} egfem_newton_stats;
+
+/* Fill opts with the defaults above. */
+void egfem_newton_opts_default(egfem_newton_opts* o);
+
+/* egfem_newton: damped Newton from the guess in u (device [n_nodes]; Dirichlet
+ * entries are set to 0) to the solution, written back into u.  A step
+ * u + alpha delta is accepted when ||F|| <= (1 - 1e-4 alpha) ||F(u)||, halving
+ * alpha up to max_backtracks times; if none passes, status EGFEM_STAGNATED and
+ * u is the last accepted iterate.  Per step: fused residual + norm, Jacobian
+ * emission, one persistent BiCGStab launch; the host reads back two scalars per
+ * step.  s may be NULL.  Synchronises the stream. */
+int egfem_newton(egfem_tensor_t T, const egfem_problem* p, double* u,
+                 const egfem_newton_opts* o, egfem_newton_stats* s, void* stream);
+
+/* egfem_solve: Jacobi-preconditioned BiCGStab for A x = rhs, A = J (jval in
+ * T's pattern) or J^T (transpose != 0).  x: device, initial guess on input.
+ * Stops when ||rhs - A x||_2 <= rtol ||rhs||_2 (recursive residual) or after
+ * max_iter iterations.  iters / relres (host, nullable) receive the outcome.
+ * Returns EGFEM_OK, EGFEM_NOT_CONVERGED, EGFEM_BREAKDOWN or EGFEM_NONFINITE.
+ * Synchronises the stream. */
+int egfem_solve(egfem_tensor_t T, const double* jval, int transpose, const double* rhs,
+                double* x, double rtol, int max_iter, int* iters, double* relres, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batched form: `count` independent problems (each its own handle, sizes may
+ * differ) solved by ONE persistent launch; each instance is owned by a team of
+ * workgroups sized by its tensor size, with device-side Newton control and
+ * team-local barriers.  us[m]: device [n_nodes of m], guess in / solution out.
+ * stats: host array [count] or NULL.  Same options for all instances;
+ * forcing and backtracking as egfem_newton.  Synchronises the stream.
+ * ---------------------------------------------------------------------- */
+int egfem_newton_batched(int count, const egfem_tensor_t* Ts, const egfem_problem* ps,
+                         double* const* us, const egfem_newton_opts* o,
+                         egfem_newton_stats* stats, void* stream);
+
+/* Thread-local message of the last error. */
+const char* egfem_last_error(void);
+
+/* Library version string. */
+const char* egfem_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EGFEM_H */

@@ -318,6 +318,56 @@ def residual(p: Problem, u: np.ndarray) -> np.ndarray:
     return F
 
 
+def residual_elementwise(p: Problem, u: np.ndarray, rows: Optional[np.ndarray] = None) -> np.ndarray:
+    """The same F(u) evaluated without the global tensor: per element,
+    (T:(u (x) a))_i = int a_h grad u_h . grad phi_i  (stiffness form) or
+    int a_h u_h phi_i (mass form) with a_h the P1 interpolant of a = a0 + u^2
+    (the group-FEM product approximation of Sec. 2.2), by quadrature.
+    With `rows`, only the cells touching those nodes are visited and only
+    F[rows] is meaningful."""
+    coords, cells = p.coords, p.cells
+    if rows is not None:
+        touch = np.zeros(p.n, dtype=bool)
+        touch[rows] = True
+        cells = cells[touch[cells].any(axis=1)]
+    dim = coords.shape[1]
+    det, G = element_geometry(coords, cells)
+    a = nodal_a(p, u)
+    ae = a[cells]
+    ue = u[cells]
+    if p.form == FORM_STIFF:
+        pts, wts = simplex_quadrature(dim, 1)
+        lam = barycentric(pts)
+        c = det * ((ae @ lam.T) @ wts)                       # int a_h over the element
+        gu = np.einsum("ea,ead->ed", ue, G)
+        Re = c[:, None] * np.einsum("ead,ed->ea", G, gu)
+    else:
+        pts, wts = simplex_quadrature(dim, 3)
+        lam = barycentric(pts)
+        wq = det[:, None] * wts[None, :]
+        Re = np.einsum("eq,qa->ea", wq * (ae @ lam.T) * (ue @ lam.T), lam)
+    F = np.bincount(cells.ravel(), weights=Re.ravel(), minlength=p.n) - p.d
+    if p.K is not None:
+        F = F + p.K @ u
+    F[p.dirichlet] = 0.0
+    return F
+
+
+def tensor_rows(p_or_mesh_coords, cells, form: int, rows: np.ndarray,
+                drop_rel: float = DROP_REL) -> Tensor3:
+    """The stored entries T_ijk for i in `rows` only, assembled from the cells
+    that touch those nodes (every contribution to row i comes from a cell
+    containing node i), for spot checks at full size."""
+    coords = p_or_mesh_coords
+    n = coords.shape[0]
+    touch = np.zeros(n, dtype=bool)
+    touch[rows] = True
+    sub = cells[touch[cells].any(axis=1)]
+    T = assemble_tensor(coords, sub, form, drop_rel=drop_rel)
+    keep = touch[T.i]
+    return Tensor3(n, T.i[keep], T.j[keep], T.k[keep], T.v[keep])
+
+
 def _apply_dirichlet(p: Problem, J: sp.csr_matrix) -> sp.csr_matrix:
     free = sp.diags(p.free.astype(np.float64))
     dirm = sp.diags(p.dirichlet.astype(np.float64))

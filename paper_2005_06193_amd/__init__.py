@@ -1,0 +1,6 @@
+"""MI355X (gfx950) EGFEM Newton hot path: HIP kernels behind a C ABI
+(include/egfem.h) with a thin ctypes binding.  See binding.py."""
+from .binding import (  # noqa: F401
+    EgfemError, FORM_MASS, FORM_STIFF, Info, NewtonOptions, NewtonStats, Problem, Tensor,
+    load_library, newton_batched, version, EXPORTS, LIB_PATH,
+)

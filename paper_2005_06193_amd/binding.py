@@ -1,0 +1,385 @@
+"""ctypes binding of libegfem (include/egfem.h).
+
+Argument marshalling only: torch tensors supply device memory and the current
+HIP stream; every step of the computation runs in the library's HIP kernels.
+There is no CPU fallback: without the built library (or without a HIP device)
+every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import warnings
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libegfem.so")
+
+EGFEM_OK = 0
+EGFEM_NOT_CONVERGED = 1
+EGFEM_BREAKDOWN = 2
+EGFEM_NONFINITE = 3
+EGFEM_STAGNATED = 4
+EGFEM_ERR_ARG = -1
+EGFEM_ERR_SHAPE = -2
+EGFEM_ERR_OOM = -3
+EGFEM_ERR_HIP = -4
+EGFEM_ERR_MESH = -5
+STATUS_NAMES = {0: "ok", 1: "not_converged", 2: "breakdown", 3: "nonfinite", 4: "stagnated",
+                -1: "err_arg", -2: "err_shape", -3: "err_oom", -4: "err_hip", -5: "err_mesh"}
+
+FORM_STIFF = 0
+FORM_MASS = 1
+HIST = 64
+
+
+class EgfemError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"egfem error {code} ({STATUS_NAMES.get(code, '?')}): {msg}")
+        self.code = code
+
+
+class _Info(C.Structure):
+    _fields_ = [("dim", C.c_int), ("form", C.c_int), ("symmetric", C.c_int),
+                ("n_nodes", C.c_int64), ("n_cells", C.c_int64), ("nnz", C.c_int64),
+                ("nnz_b", C.c_int64), ("structural_nnz", C.c_int64), ("slots", C.c_int64),
+                ("row_blocks", C.c_int64), ("device_bytes", C.c_int64),
+                ("rowptr", C.c_void_p), ("col", C.c_void_p), ("kval", C.c_void_p),
+                ("mval", C.c_void_p)]
+
+
+class _Problem(C.Structure):
+    _fields_ = [("a0", C.c_void_p), ("a0_const", C.c_double), ("load", C.c_void_p),
+                ("dirichlet", C.c_void_p), ("add_stiffness", C.c_int)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_newton", C.c_int), ("max_krylov", C.c_int),
+                ("krylov_rtol", C.c_double), ("forcing", C.c_int), ("eta_max", C.c_double),
+                ("max_backtracks", C.c_int), ("krylov_blocks", C.c_int)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("status", C.c_int), ("newton_iters", C.c_int), ("krylov_iters", C.c_int),
+                ("backtracks", C.c_int), ("res0", C.c_double), ("res", C.c_double),
+                ("res_hist", C.c_double * HIST), ("krylov_hist", C.c_int * HIST)]
+
+
+_lib = None
+
+EXPORTS = {
+    "egfem_build_tensor": (C.c_int, [C.c_int, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
+                                     C.c_int, C.c_double, C.POINTER(C.c_void_p)]),
+    "egfem_tensor_destroy": (None, [C.c_void_p]),
+    "egfem_tensor_info": (C.c_int, [C.c_void_p, C.POINTER(_Info)]),
+    "egfem_tensor_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "egfem_tensor_pattern": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "egfem_residual": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "egfem_jacobian": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
+                                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "egfem_mode3": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "egfem_matvec": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
+                               C.c_void_p]),
+    "egfem_problem_residual": (C.c_int, [C.c_void_p, C.POINTER(_Problem), C.c_void_p, C.c_void_p,
+                                         C.POINTER(C.c_double), C.c_void_p]),
+    "egfem_problem_jacobian": (C.c_int, [C.c_void_p, C.POINTER(_Problem), C.c_void_p, C.c_void_p,
+                                         C.c_void_p, C.c_void_p]),
+    "egfem_newton_opts_default": (None, [C.POINTER(_Opts)]),
+    "egfem_newton": (C.c_int, [C.c_void_p, C.POINTER(_Problem), C.c_void_p, C.POINTER(_Opts),
+                               C.POINTER(_Stats), C.c_void_p]),
+    "egfem_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double,
+                              C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double), C.c_void_p]),
+    "egfem_newton_batched": (C.c_int, [C.c_int, C.POINTER(C.c_void_p), C.POINTER(_Problem),
+                                       C.POINTER(C.c_void_p), C.POINTER(_Opts), C.POINTER(_Stats),
+                                       C.c_void_p]),
+    "egfem_last_error": (C.c_char_p, []),
+    "egfem_version": (C.c_char_p, []),
+}
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    """Load libegfem.so (torch is imported first so that its HIP runtime is the
+    one the library binds to)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise EgfemError(EGFEM_ERR_HIP, f"{path} is not built; run __graft_entry__.build()")
+    lib = C.CDLL(path)
+    for name, (res, args) in EXPORTS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, allow_positive: bool = False) -> int:
+    if rc < 0 or (rc > 0 and not allow_positive):
+        msg = load_library().egfem_last_error().decode(errors="replace")
+        raise EgfemError(rc, msg)
+    return rc
+
+
+def _require_device():
+    if not torch.cuda.is_available():
+        raise EgfemError(EGFEM_ERR_HIP, "no HIP device visible to torch")
+
+
+def _dptr(t: Optional[torch.Tensor], dtype=torch.float64, n: Optional[int] = None) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise EgfemError(EGFEM_ERR_ARG, "tensor must live on the HIP device")
+    if t.dtype != dtype:
+        raise EgfemError(EGFEM_ERR_ARG, f"expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise EgfemError(EGFEM_ERR_ARG, "tensor must be contiguous")
+    if n is not None and t.numel() != n:
+        raise EgfemError(EGFEM_ERR_SHAPE, f"expected {n} entries, got {t.numel()}")
+    return t.data_ptr()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+@dataclass
+class Info:
+    dim: int
+    form: int
+    symmetric: int
+    n_nodes: int
+    n_cells: int
+    nnz: int
+    nnz_b: int
+    structural_nnz: int
+    slots: int
+    row_blocks: int
+    device_bytes: int
+
+
+@dataclass
+class NewtonOptions:
+    tol: float = 1e-10
+    max_newton: int = 50
+    max_krylov: int = 20000
+    krylov_rtol: float = 1e-12
+    forcing: int = 0
+    eta_max: float = 0.1
+    max_backtracks: int = 10
+    krylov_blocks: int = 0
+
+    def c(self) -> _Opts:
+        return _Opts(self.tol, self.max_newton, self.max_krylov, self.krylov_rtol, self.forcing,
+                     self.eta_max, self.max_backtracks, self.krylov_blocks)
+
+
+@dataclass
+class NewtonStats:
+    status: int
+    newton_iters: int
+    krylov_iters: int
+    backtracks: int
+    res0: float
+    res: float
+    res_hist: List[float]
+    krylov_hist: List[int]
+
+    @property
+    def status_name(self) -> str:
+        return STATUS_NAMES.get(self.status, "?")
+
+    @classmethod
+    def from_c(cls, s: _Stats) -> "NewtonStats":
+        k = min(s.newton_iters, HIST)
+        return cls(s.status, s.newton_iters, s.krylov_iters, s.backtracks, s.res0, s.res,
+                   list(s.res_hist[:k]), list(s.krylov_hist[:k]))
+
+
+class Problem:
+    """Device-resident data of F(u) = [K u] + T:(u (x) (a0 + u^2)) - load = 0."""
+
+    def __init__(self, n: int, load: torch.Tensor, dirichlet: Optional[torch.Tensor] = None,
+                 a0: Optional[torch.Tensor] = None, a0_const: float = 1.0,
+                 add_stiffness: bool = False):
+        self.n = n
+        self.load = load
+        self.dirichlet = dirichlet
+        self.a0 = a0
+        self.a0_const = float(a0_const)
+        self.add_stiffness = bool(add_stiffness)
+
+    def c(self) -> _Problem:
+        return _Problem(_dptr(self.a0, n=self.n), self.a0_const, _dptr(self.load, n=self.n),
+                        _dptr(self.dirichlet, torch.uint8, self.n), int(self.add_stiffness))
+
+
+class Tensor:
+    """Handle of a built EGFEM tensor with its CSR pattern and matrices."""
+
+    def __init__(self, handle: int):
+        self._h = C.c_void_p(handle)
+        inf = _Info()
+        _check(load_library().egfem_tensor_info(self._h, C.byref(inf)))
+        self.info = Info(inf.dim, inf.form, inf.symmetric, inf.n_nodes, inf.n_cells, inf.nnz,
+                         inf.nnz_b, inf.structural_nnz, inf.slots, inf.row_blocks, inf.device_bytes)
+
+    # -- construction ----------------------------------------------------
+    @classmethod
+    def build(cls, coords: np.ndarray, cells: np.ndarray, form: int = FORM_STIFF,
+              drop_rel: float = 1e-13) -> "Tensor":
+        _require_device()
+        lib = load_library()
+        coords = np.ascontiguousarray(coords, dtype=np.float64)
+        cells = np.ascontiguousarray(cells, dtype=np.int32)
+        if coords.ndim != 2 or cells.ndim != 2 or cells.shape[1] != coords.shape[1] + 1:
+            raise EgfemError(EGFEM_ERR_SHAPE, "coords [N, d] and cells [E, d+1] expected")
+        out = C.c_void_p()
+        _check(lib.egfem_build_tensor(coords.shape[1], coords.shape[0], coords.ctypes.data,
+                                      cells.shape[0], cells.ctypes.data, int(form),
+                                      float(drop_rel), C.byref(out)))
+        return cls(out.value)
+
+    @classmethod
+    def from_mesh(cls, mesh, form: int = FORM_STIFF, drop_rel: float = 1e-13) -> "Tensor":
+        return cls.build(mesh.coords, mesh.cells, form, drop_rel)
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            load_library().egfem_tensor_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self) -> C.c_void_p:
+        if self._h is None:
+            raise EgfemError(EGFEM_ERR_ARG, "tensor handle already closed")
+        return self._h
+
+    @property
+    def n(self) -> int:
+        return self.info.n_nodes
+
+    # -- pattern ------------------------------------------------------------
+    def pattern(self):
+        """(rowptr, col) of the CSR pattern as host int32 arrays."""
+        rp = np.empty(self.n + 1, np.int32)
+        cl = np.empty(self.info.slots, np.int32)
+        _check(load_library().egfem_tensor_pattern(self.handle, rp.ctypes.data, cl.ctypes.data))
+        return rp, cl
+
+    def export(self):
+        """Host COO (i, j, k, v) of the stored tensor."""
+        nnz = self.info.nnz
+        i = np.empty(nnz, np.int32)
+        j = np.empty(nnz, np.int32)
+        k = np.empty(nnz, np.int32)
+        v = np.empty(nnz, np.float64)
+        _check(load_library().egfem_tensor_export(self.handle, i.ctypes.data, j.ctypes.data,
+                                                  k.ctypes.data, v.ctypes.data))
+        return i, j, k, v
+
+    # -- online actions -----------------------------------------------------
+    def residual(self, u: torch.Tensor, a: torch.Tensor, out: Optional[torch.Tensor] = None):
+        """r_i = sum_jk T_ijk u_j a_k."""
+        out = torch.empty_like(u) if out is None else out
+        _check(load_library().egfem_residual(self.handle, _dptr(u, n=self.n), _dptr(a, n=self.n),
+                                             _dptr(out, n=self.n), _stream()))
+        return out
+
+    def jacobian(self, u, a, dadu=None, add_stiffness=False, dirichlet=None, out=None,
+                 dinv=None):
+        out = torch.empty(self.info.slots, dtype=torch.float64, device="cuda") if out is None else out
+        _check(load_library().egfem_jacobian(self.handle, _dptr(u, n=self.n), _dptr(a, n=self.n),
+                                             _dptr(dadu, n=self.n), int(add_stiffness),
+                                             _dptr(dirichlet, torch.uint8, self.n),
+                                             _dptr(out, n=self.info.slots), _dptr(dinv, n=self.n),
+                                             _stream()))
+        return out
+
+    def mode3(self, w, u, out=None):
+        """out_k = sum_ij w_i T_ijk u_j."""
+        out = torch.empty_like(u) if out is None else out
+        _check(load_library().egfem_mode3(self.handle, _dptr(w, n=self.n), _dptr(u, n=self.n),
+                                          _dptr(out, n=self.n), _stream()))
+        return out
+
+    def matvec(self, x, which: str = "J", jval=None, transpose=False, out=None):
+        sel = {"J": 0, "K": 1, "M": 2}[which]
+        out = torch.empty_like(x) if out is None else out
+        _check(load_library().egfem_matvec(self.handle, sel, _dptr(jval, n=self.info.slots),
+                                           int(transpose), _dptr(x, n=self.n),
+                                           _dptr(out, n=self.n), _stream()))
+        return out
+
+    def problem_residual(self, p: Problem, u, out=None, with_norm=False):
+        out = torch.empty_like(u) if out is None else out
+        pc = p.c()
+        nrm = C.c_double(0.0)
+        _check(load_library().egfem_problem_residual(self.handle, C.byref(pc), _dptr(u, n=self.n),
+                                                     _dptr(out, n=self.n),
+                                                     C.byref(nrm) if with_norm else None,
+                                                     _stream()))
+        return (out, nrm.value) if with_norm else out
+
+    def problem_jacobian(self, p: Problem, u, out=None, dinv=None):
+        out = torch.empty(self.info.slots, dtype=torch.float64, device="cuda") if out is None else out
+        pc = p.c()
+        _check(load_library().egfem_problem_jacobian(self.handle, C.byref(pc), _dptr(u, n=self.n),
+                                                     _dptr(out, n=self.info.slots),
+                                                     _dptr(dinv, n=self.n), _stream()))
+        return out
+
+    def newton(self, p: Problem, u: torch.Tensor, opts: Optional[NewtonOptions] = None,
+               warn: bool = True) -> NewtonStats:
+        """Damped Newton in place on u; returns the statistics."""
+        o = (opts or NewtonOptions()).c()
+        pc = p.c()
+        st = _Stats()
+        rc = load_library().egfem_newton(self.handle, C.byref(pc), _dptr(u, n=self.n), C.byref(o),
+                                         C.byref(st), _stream())
+        _check(rc, allow_positive=True)
+        stats = NewtonStats.from_c(st)
+        if rc not in (EGFEM_OK, EGFEM_STAGNATED) and warn:
+            warnings.warn(f"egfem_newton ended with status {stats.status_name}")
+        return stats
+
+    def solve(self, jval, rhs, x=None, transpose=False, rtol=1e-12, max_iter=20000):
+        x = torch.zeros_like(rhs) if x is None else x
+        it = C.c_int(0)
+        rr = C.c_double(0.0)
+        rc = load_library().egfem_solve(self.handle, _dptr(jval, n=self.info.slots), int(transpose),
+                                        _dptr(rhs, n=self.n), _dptr(x, n=self.n), float(rtol),
+                                        int(max_iter), C.byref(it), C.byref(rr), _stream())
+        _check(rc, allow_positive=True)
+        return x, rc, it.value, rr.value
+
+
+def newton_batched(tensors: Sequence[Tensor], problems: Sequence[Problem],
+                   us: Sequence[torch.Tensor], opts: Optional[NewtonOptions] = None):
+    """All instances in one persistent launch; returns a list of NewtonStats."""
+    m = len(tensors)
+    if not (m == len(problems) == len(us)) or m == 0:
+        raise EgfemError(EGFEM_ERR_SHAPE, "tensors/problems/us must have equal nonzero length")
+    hs = (C.c_void_p * m)(*[t.handle.value for t in tensors])
+    ps = (_Problem * m)(*[p.c() for p in problems])
+    up = (C.c_void_p * m)(*[_dptr(u, n=t.n) for u, t in zip(us, tensors)])
+    st = (_Stats * m)()
+    o = (opts or NewtonOptions()).c()
+    rc = load_library().egfem_newton_batched(m, hs, ps, up, C.byref(o), st, _stream())
+    _check(rc, allow_positive=True)
+    return [NewtonStats.from_c(st[i]) for i in range(m)], rc
+
+
+def version() -> str:
+    return load_library().egfem_version().decode()

@@ -1,0 +1,361 @@
+// C entry points of libegfem: handle lifecycle, tensor actions, the Newton
+// driver (Sec. 4) and the Jacobi-BiCGStab solve.  Argument checks happen here;
+// the device work is in egfem_kernels.hip and egfem_krylov.hip.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "egfem_internal.h"
+
+namespace egfem {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+template <typename T>
+static int dalloc(T** p, size_t count) {
+  hipError_t e = hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T));
+  if (e != hipSuccess) return fail(EGFEM_ERR_OOM, "hipMalloc of solver workspace failed");
+  return EGFEM_OK;
+}
+
+int ensure_workspace(egfem_tensor_s* T) {
+  Workspace& W = T->ws;
+  if (W.ready) return EGFEM_OK;
+  const size_t N = (size_t)T->n, S = (size_t)T->slots;
+  int rc = EGFEM_OK;
+  double** nvecs[] = {&W.F, &W.delta, &W.utry, &W.dinv, &W.rhs, &W.r, &W.rhat,
+                      &W.p, &W.v, &W.s, &W.t, &W.phat, &W.shat};
+  for (double** v : nvecs)
+    if (rc == EGFEM_OK) rc = dalloc(v, N);
+  if (rc == EGFEM_OK) rc = dalloc(&W.jval, S);
+  if (rc == EGFEM_OK) rc = dalloc(&W.jvalT, S);
+  if (rc == EGFEM_OK) rc = dalloc(&W.qslot, S);
+  if (rc == EGFEM_OK) rc = dalloc(&W.partial, (size_t)T->row_blocks);
+  if (rc == EGFEM_OK) rc = dalloc(&W.red, (size_t)kRedSlots * 4 * kMaxKrylovBlocks);
+  if (rc == EGFEM_OK) rc = dalloc(&W.ctrl, 4);
+  if (rc == EGFEM_OK) rc = dalloc(&W.krow, (size_t)kMaxKrylovBlocks + 1);
+  if (rc == EGFEM_OK) rc = dalloc(&W.kout, 4);
+  if (rc == EGFEM_OK &&
+      hipHostMalloc((void**)&W.host_partial, std::max<size_t>(T->row_blocks, 1) * sizeof(double), 0) != hipSuccess)
+    rc = fail(EGFEM_ERR_OOM, "hipHostMalloc failed");
+  if (rc == EGFEM_OK && hipHostMalloc((void**)&W.host_kout, 4 * sizeof(double), 0) != hipSuccess)
+    rc = fail(EGFEM_ERR_OOM, "hipHostMalloc failed");
+  if (rc != EGFEM_OK) return rc;
+  T->device_bytes += (int64_t)((13 * N + 3 * S + T->row_blocks + (size_t)kRedSlots * 4 * kMaxKrylovBlocks + 4) *
+                                   sizeof(double) + (kMaxKrylovBlocks + 1) * 4 + 16);
+  W.krow_blocks = 0;
+  W.ready = true;
+  return EGFEM_OK;
+}
+
+static void free_workspace(Workspace& W) {
+  double* vecs[] = {W.F, W.delta, W.utry, W.jval, W.jvalT, W.dinv, W.rhs, W.r, W.rhat, W.p, W.v,
+                    W.s, W.t, W.phat, W.shat, W.partial, W.red, W.qslot, W.kout};
+  for (double* v : vecs)
+    if (v) hipFree(v);
+  if (W.ctrl) hipFree(W.ctrl);
+  if (W.krow) hipFree(W.krow);
+  if (W.host_partial) hipHostFree(W.host_partial);
+  if (W.host_kout) hipHostFree(W.host_kout);
+  W = Workspace();
+}
+
+__global__ void k_diag_inv(int64_t n, const int32_t* __restrict__ diag, const double* __restrict__ jval,
+                           double* __restrict__ dinv) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dinv[i] = 1.0 / jval[diag[i]];
+}
+
+// ||F||_2 from the per-block partial sums written by the fused residual kernel,
+// added on the host in block order (deterministic).
+static int read_norm(egfem_tensor_s* T, hipStream_t st, double* norm) {
+  Workspace& W = T->ws;
+  EGFEM_HIP_CHECK(hipMemcpyAsync(W.host_partial, W.partial, T->row_blocks * sizeof(double),
+                                 hipMemcpyDeviceToHost, st));
+  EGFEM_HIP_CHECK(hipStreamSynchronize(st));
+  double s = 0.0;
+  for (int64_t b = 0; b < T->row_blocks; ++b) s += W.host_partial[b];
+  *norm = std::sqrt(s);
+  return EGFEM_OK;
+}
+
+static ProblemView view(const egfem_problem* p) {
+  ProblemView v;
+  v.a0 = p->a0;
+  v.a0c = p->a0_const;
+  v.load = p->load;
+  v.dir = p->dirichlet;
+  v.addK = p->add_stiffness;
+  return v;
+}
+
+}  // namespace egfem
+
+using namespace egfem;
+
+extern "C" {
+
+const char* egfem_last_error(void) { return g_last_error.c_str(); }
+
+const char* egfem_version(void) { return "egfem-gfx950 0.1"; }
+
+void egfem_tensor_destroy(egfem_tensor_t T) {
+  if (!T) return;
+  free_workspace(T->ws);
+  void* ptrs[] = {T->rowptr, T->col, T->diag, T->tperm, T->kptrA, T->kA, T->vA,
+                  T->kval,   T->mval, T->blk_row};
+  for (void* p : ptrs)
+    if (p) hipFree(p);
+  if (!T->symmetric) {
+    if (T->jptrB) hipFree(T->jptrB);
+    if (T->jB) hipFree(T->jB);
+    if (T->vB) hipFree(T->vB);
+  }
+  delete T;
+}
+
+int egfem_tensor_info(egfem_tensor_t T, egfem_info* info) {
+  if (!T || !info) return fail(EGFEM_ERR_ARG, "null argument");
+  info->dim = T->dim;
+  info->form = T->form;
+  info->symmetric = T->symmetric;
+  info->n_nodes = T->n;
+  info->n_cells = T->n_cells;
+  info->nnz = T->nnz;
+  info->nnz_b = T->nnz_b;
+  info->structural_nnz = T->structural;
+  info->slots = T->slots;
+  info->row_blocks = T->row_blocks;
+  info->device_bytes = T->device_bytes;
+  info->rowptr = T->rowptr;
+  info->col = T->col;
+  info->kval = T->kval;
+  info->mval = T->mval;
+  return EGFEM_OK;
+}
+
+int egfem_tensor_export(egfem_tensor_t T, int32_t* i, int32_t* j, int32_t* k, double* v) {
+  if (!T || !i || !j || !k || !v) return fail(EGFEM_ERR_ARG, "null argument");
+  std::vector<int32_t> kptr(T->slots + 1), col(T->slots);
+  EGFEM_HIP_CHECK(hipMemcpy(kptr.data(), T->kptrA, kptr.size() * 4, hipMemcpyDeviceToHost));
+  EGFEM_HIP_CHECK(hipMemcpy(col.data(), T->col, col.size() * 4, hipMemcpyDeviceToHost));
+  EGFEM_HIP_CHECK(hipMemcpy(k, T->kA, T->nnz * 4, hipMemcpyDeviceToHost));
+  EGFEM_HIP_CHECK(hipMemcpy(v, T->vA, T->nnz * 8, hipMemcpyDeviceToHost));
+  for (int64_t r = 0; r < T->n; ++r)
+    for (int32_t s = T->h_rowptr[r]; s < T->h_rowptr[r + 1]; ++s)
+      for (int32_t p = kptr[s]; p < kptr[s + 1]; ++p) {
+        i[p] = (int32_t)r;
+        j[p] = col[s];
+      }
+  return EGFEM_OK;
+}
+
+int egfem_tensor_pattern(egfem_tensor_t T, int32_t* rowptr, int32_t* col) {
+  if (!T || !rowptr || !col) return fail(EGFEM_ERR_ARG, "null argument");
+  std::memcpy(rowptr, T->h_rowptr.data(), (T->n + 1) * sizeof(int32_t));
+  EGFEM_HIP_CHECK(hipMemcpy(col, T->col, T->slots * sizeof(int32_t), hipMemcpyDeviceToHost));
+  return EGFEM_OK;
+}
+
+int egfem_residual(egfem_tensor_t T, const double* u, const double* a, double* r, void* stream) {
+  if (!T || !u || !a || !r) return fail(EGFEM_ERR_ARG, "null argument");
+  if (r == u || r == a) return fail(EGFEM_ERR_ARG, "r must not alias u or a");
+  EGFEM_HIP_CHECK(launch_action_raw(T, u, a, r, (hipStream_t)stream));
+  return EGFEM_OK;
+}
+
+int egfem_jacobian(egfem_tensor_t T, const double* u, const double* a, const double* dadu,
+                   int add_stiffness, const uint8_t* dirichlet, double* jval, double* dinv,
+                   void* stream) {
+  if (!T || !u || !a || !jval) return fail(EGFEM_ERR_ARG, "null argument");
+  EGFEM_HIP_CHECK(launch_jacobian(T, u, a, nullptr, 0.0, 0, dadu, 0, add_stiffness, dirichlet, jval,
+                                  dinv, (hipStream_t)stream));
+  return EGFEM_OK;
+}
+
+int egfem_mode3(egfem_tensor_t T, const double* w, const double* u, double* out, void* stream) {
+  if (!T || !w || !u || !out) return fail(EGFEM_ERR_ARG, "null argument");
+  if (out == w || out == u) return fail(EGFEM_ERR_ARG, "out must not alias w or u");
+  int rc = ensure_workspace(T);
+  if (rc != EGFEM_OK) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  EGFEM_HIP_CHECK(launch_slot_mode2(T, u, T->ws.qslot, st));
+  EGFEM_HIP_CHECK(launch_csr_matvec_perm(T, T->ws.qslot, w, out, st));
+  return EGFEM_OK;
+}
+
+int egfem_matvec(egfem_tensor_t T, int which, const double* jval, int transpose, const double* x,
+                 double* y, void* stream) {
+  if (!T || !x || !y) return fail(EGFEM_ERR_ARG, "null argument");
+  if (x == y) return fail(EGFEM_ERR_ARG, "x and y must not alias");
+  const double* vals = which == 0 ? jval : (which == 1 ? T->kval : (which == 2 ? T->mval : nullptr));
+  if (!vals) return fail(EGFEM_ERR_ARG, "bad matrix selector or null jval");
+  hipStream_t st = (hipStream_t)stream;
+  if (transpose && which == 0)
+    EGFEM_HIP_CHECK(launch_csr_matvec_perm(T, vals, x, y, st));
+  else
+    EGFEM_HIP_CHECK(launch_csr_matvec(T, vals, x, y, st));
+  return EGFEM_OK;
+}
+
+int egfem_problem_residual(egfem_tensor_t T, const egfem_problem* p, const double* u, double* F,
+                           double* norm, void* stream) {
+  if (!T || !p || !u || !F) return fail(EGFEM_ERR_ARG, "null argument");
+  if (F == u) return fail(EGFEM_ERR_ARG, "F must not alias u");
+  int rc = ensure_workspace(T);
+  if (rc != EGFEM_OK) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  EGFEM_HIP_CHECK(launch_action_problem(T, view(p), u, nullptr, 0.0, nullptr, F, T->ws.partial, st));
+  if (norm) return read_norm(T, st, norm);
+  return EGFEM_OK;
+}
+
+int egfem_problem_jacobian(egfem_tensor_t T, const egfem_problem* p, const double* u, double* jval,
+                           double* dinv, void* stream) {
+  if (!T || !p || !u || !jval) return fail(EGFEM_ERR_ARG, "null argument");
+  EGFEM_HIP_CHECK(launch_jacobian(T, u, nullptr, p->a0, p->a0_const, 1, nullptr, 1,
+                                  p->add_stiffness, p->dirichlet, jval, dinv, (hipStream_t)stream));
+  return EGFEM_OK;
+}
+
+void egfem_newton_opts_default(egfem_newton_opts* o) {
+  if (!o) return;
+  o->tol = 1e-10;
+  o->max_newton = 50;
+  o->max_krylov = 20000;
+  o->krylov_rtol = 1e-12;
+  o->forcing = 0;
+  o->eta_max = 0.1;
+  o->max_backtracks = 10;
+  o->krylov_blocks = 0;
+}
+
+static int check_opts(const egfem_newton_opts& o) {
+  if (!(o.tol >= 0.0) || o.max_newton < 0 || o.max_krylov < 1 || !(o.krylov_rtol > 0.0) ||
+      !(o.eta_max > 0.0 && o.eta_max < 1.0) || o.max_backtracks < 0 || o.krylov_blocks < 0 ||
+      (o.forcing != 0 && o.forcing != 1))
+    return fail(EGFEM_ERR_ARG, "invalid Newton options");
+  return EGFEM_OK;
+}
+
+// Eisenstat-Walker forcing term, choice 2 (gamma = 0.9, exponent 2) with the
+// usual safeguards: keep eta from dropping faster than the previous term
+// predicts, cap at eta_max, and do not oversolve past the outer tolerance.
+static double ew_forcing(int k, double nF, double nF_prev, double eta_prev, double eta_max,
+                         double tol_abs) {
+  double eta;
+  if (k == 0) {
+    eta = eta_max;
+  } else {
+    eta = 0.9 * (nF / nF_prev) * (nF / nF_prev);
+    const double guard = 0.9 * eta_prev * eta_prev;
+    if (guard > 0.1) eta = std::max(eta, guard);
+    eta = std::min(eta, eta_max);
+  }
+  eta = std::max(eta, 0.5 * tol_abs / nF);
+  return std::min(eta, eta_max);
+}
+
+int egfem_newton(egfem_tensor_t T, const egfem_problem* p, double* u, const egfem_newton_opts* o,
+                 egfem_newton_stats* s, void* stream) {
+  if (!T || !p || !u) return fail(EGFEM_ERR_ARG, "null argument");
+  egfem_newton_opts opts;
+  egfem_newton_opts_default(&opts);
+  if (o) opts = *o;
+  int rc = check_opts(opts);
+  if (rc != EGFEM_OK) return rc;
+  rc = ensure_workspace(T);
+  if (rc != EGFEM_OK) return rc;
+  Workspace& W = T->ws;
+  hipStream_t st = (hipStream_t)stream;
+  const ProblemView pv = view(p);
+  egfem_newton_stats stats;
+  std::memset(&stats, 0, sizeof(stats));
+
+  EGFEM_HIP_CHECK(launch_mask_zero(u, p->dirichlet, T->n, st));
+  EGFEM_HIP_CHECK(launch_action_problem(T, pv, u, nullptr, 0.0, nullptr, W.F, W.partial, st));
+  double nF0 = 0.0;
+  if ((rc = read_norm(T, st, &nF0)) != EGFEM_OK) return rc;
+  stats.res0 = nF0;
+  stats.res = nF0;
+  int status = EGFEM_NOT_CONVERGED;
+  if (!std::isfinite(nF0)) status = EGFEM_NONFINITE;
+  else if (nF0 == 0.0) status = EGFEM_OK;
+  double nF = nF0, nF_prev = nF0, eta = opts.eta_max;
+  int k = 0;
+  while (status == EGFEM_NOT_CONVERGED) {
+    if (nF <= opts.tol * nF0) { status = EGFEM_OK; break; }
+    if (k >= opts.max_newton) break;
+    // Jacobian emission DF(u) and Jacobi diagonal
+    EGFEM_HIP_CHECK(launch_jacobian(T, u, nullptr, p->a0, p->a0_const, 1, nullptr, 1,
+                                    p->add_stiffness, p->dirichlet, W.jval, W.dinv, st));
+    const double rtol = opts.forcing ? ew_forcing(k, nF, nF_prev, eta, opts.eta_max, opts.tol * nF0)
+                                     : opts.krylov_rtol;
+    eta = rtol;
+    KrylovResult kr;
+    rc = krylov_bicgstab(T, W.jval, W.dinv, W.F, -1.0, W.delta, true, rtol, opts.max_krylov,
+                         opts.krylov_blocks, &kr, st, nullptr);
+    if (rc != EGFEM_OK) return rc;
+    stats.krylov_iters += kr.iters;
+    if (k < EGFEM_HIST) stats.krylov_hist[k] = kr.iters;
+    if (kr.status == EGFEM_NONFINITE) { status = EGFEM_NONFINITE; break; }
+    // damped update u + alpha delta, residual fused with the trial iterate
+    double alpha = 1.0, nFt = 0.0;
+    bool accepted = false;
+    for (int bt = 0; bt <= opts.max_backtracks; ++bt) {
+      EGFEM_HIP_CHECK(launch_action_problem(T, pv, u, W.delta, alpha, W.utry, W.F, W.partial, st));
+      if ((rc = read_norm(T, st, &nFt)) != EGFEM_OK) return rc;
+      if (std::isfinite(nFt) && nFt <= (1.0 - 1e-4 * alpha) * nF) { accepted = true; break; }
+      alpha *= 0.5;
+      ++stats.backtracks;
+    }
+    if (!accepted) {
+      status = EGFEM_STAGNATED;
+      // restore F at the last accepted iterate
+      EGFEM_HIP_CHECK(launch_action_problem(T, pv, u, nullptr, 0.0, nullptr, W.F, W.partial, st));
+      break;
+    }
+    EGFEM_HIP_CHECK(launch_copy(u, W.utry, T->n, st));
+    nF_prev = nF;
+    nF = nFt;
+    if (k < EGFEM_HIST) stats.res_hist[k] = nF;
+    ++k;
+  }
+  if (status == EGFEM_NOT_CONVERGED && nF <= opts.tol * nF0) status = EGFEM_OK;
+  EGFEM_HIP_CHECK(hipStreamSynchronize(st));
+  stats.status = status;
+  stats.newton_iters = k;
+  stats.res = nF;
+  if (s) *s = stats;
+  return status;
+}
+
+int egfem_solve(egfem_tensor_t T, const double* jval, int transpose, const double* rhs, double* x,
+                double rtol, int max_iter, int* iters, double* relres, void* stream) {
+  if (!T || !jval || !rhs || !x) return fail(EGFEM_ERR_ARG, "null argument");
+  if (!(rtol > 0.0) || max_iter < 1) return fail(EGFEM_ERR_ARG, "rtol > 0 and max_iter >= 1 required");
+  if (x == rhs) return fail(EGFEM_ERR_ARG, "x must not alias rhs");
+  int rc = ensure_workspace(T);
+  if (rc != EGFEM_OK) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_diag_inv, dim3((unsigned)((T->n + 255) / 256)), dim3(256), 0, st, T->n, T->diag,
+                     jval, T->ws.dinv);
+  EGFEM_HIP_CHECK(hipGetLastError());
+  KrylovResult kr;
+  rc = krylov_bicgstab(T, jval, T->ws.dinv, rhs, 1.0, x, false, rtol, max_iter, 0, &kr, st,
+                       transpose ? T->tperm : nullptr);
+  if (rc != EGFEM_OK) return rc;
+  if (iters) *iters = kr.iters;
+  if (relres) *relres = kr.relres;
+  return kr.status;
+}
+
+}  // extern "C"

@@ -1,0 +1,323 @@
+// Offline phase: assemble the EGFEM tensor, the stiffness and the mass matrix
+// of a P1 simplex mesh and lay them out as slot-aligned fiber streams.
+//
+// Tensor (eq. egfem_terms with W_h = V_h = P1):
+//   stiffness form  T_ijk = sum_e int_e phi_k grad phi_j . grad phi_i
+//                         = sum_e K^e_ij / (d+1)       (grad phi constant, int_e phi_k = |e|/(d+1))
+//   mass form       T_ijk = sum_e int_e phi_i phi_j phi_k
+//                         = sum_e d! |e| alpha! / (d+3)!  (exact simplex monomial integral)
+// K_ij = sum_e |e| grad phi_j . grad phi_i,  M_ij = sum_e |e| (1 + delta_ij) / ((d+1)(d+2)).
+//
+// Layout (all indices int32, values float64):
+//   CSR pattern of the P1 adjacency including the diagonal: rowptr, col.
+//   A-stream: for slot s = (i,j) the fiber kptrA[s]..kptrA[s+1] of (k, T_ijk), k ascending.
+//   B-stream: for slot s = (i,k) the fiber jptrB[s]..jptrB[s+1] of (j, T_ijk), j ascending.
+//   For the fully symmetric mass tensor B == A and is not stored twice.
+//   tperm[s] = slot of (j,i); diag[i] = slot of (i,i).
+//   Row blocks: runs of rows that fit the LDS capacities of the tensor kernels.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "egfem_internal.h"
+
+namespace {
+
+struct Geom {
+  double vol;          // |e|
+  double G[4][3];      // grad lambda_a
+};
+
+bool cell_geometry(int dim, const double* X, const int32_t* c, Geom& g) {
+  double B[3][3] = {{0}};   // B[r][m] = x_{m+1}[r] - x_0[r]
+  for (int m = 0; m < dim; ++m)
+    for (int r = 0; r < dim; ++r) B[r][m] = X[(int64_t)c[m + 1] * dim + r] - X[(int64_t)c[0] * dim + r];
+  double inv[3][3] = {{0}};
+  double det;
+  if (dim == 1) {
+    det = B[0][0];
+    inv[0][0] = 1.0 / det;
+  } else if (dim == 2) {
+    det = B[0][0] * B[1][1] - B[0][1] * B[1][0];
+    inv[0][0] = B[1][1] / det;
+    inv[0][1] = -B[0][1] / det;
+    inv[1][0] = -B[1][0] / det;
+    inv[1][1] = B[0][0] / det;
+  } else {
+    const double c00 = B[1][1] * B[2][2] - B[1][2] * B[2][1];
+    const double c01 = B[1][2] * B[2][0] - B[1][0] * B[2][2];
+    const double c02 = B[1][0] * B[2][1] - B[1][1] * B[2][0];
+    det = B[0][0] * c00 + B[0][1] * c01 + B[0][2] * c02;
+    inv[0][0] = c00 / det;
+    inv[1][0] = c01 / det;
+    inv[2][0] = c02 / det;
+    inv[0][1] = (B[0][2] * B[2][1] - B[0][1] * B[2][2]) / det;
+    inv[1][1] = (B[0][0] * B[2][2] - B[0][2] * B[2][0]) / det;
+    inv[2][1] = (B[0][1] * B[2][0] - B[0][0] * B[2][1]) / det;
+    inv[0][2] = (B[0][1] * B[1][2] - B[0][2] * B[1][1]) / det;
+    inv[1][2] = (B[0][2] * B[1][0] - B[0][0] * B[1][2]) / det;
+    inv[2][2] = (B[0][0] * B[1][1] - B[0][1] * B[1][0]) / det;
+  }
+  if (!(det != 0.0) || !std::isfinite(det)) return false;
+  double fact = 1.0;
+  for (int m = 2; m <= dim; ++m) fact *= m;
+  g.vol = std::fabs(det) / fact;
+  // lambda_m(x) = (B^{-1}(x - x0))_{m-1} for m >= 1, lambda_0 = 1 - sum
+  for (int r = 0; r < dim; ++r) {
+    double s = 0.0;
+    for (int m = 0; m < dim; ++m) {
+      g.G[m + 1][r] = inv[m][r];
+      s += inv[m][r];
+    }
+    g.G[0][r] = -s;
+  }
+  return true;
+}
+
+template <typename T>
+int upload(const std::vector<T>& h, T** d, int64_t* bytes) {
+  size_t nb = std::max<size_t>(h.size(), 1) * sizeof(T);
+  hipError_t e = hipMalloc((void**)d, nb);
+  if (e != hipSuccess) return egfem::fail(EGFEM_ERR_OOM, "hipMalloc of tensor stream failed");
+  *bytes += (int64_t)nb;
+  if (!h.empty()) {
+    e = hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return egfem::fail(EGFEM_ERR_HIP, "hipMemcpy of tensor stream failed");
+  }
+  return EGFEM_OK;
+}
+
+}  // namespace
+
+extern "C" int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords, int64_t n_cells,
+                                  const int32_t* cells, int form, double drop_rel,
+                                  egfem_tensor_t* out) {
+  using namespace egfem;
+  if (!out) return fail(EGFEM_ERR_ARG, "out is null");
+  *out = nullptr;
+  if (dim < 1 || dim > 3) return fail(EGFEM_ERR_ARG, "dim must be 1, 2 or 3");
+  if (form != EGFEM_FORM_STIFF && form != EGFEM_FORM_MASS) return fail(EGFEM_ERR_ARG, "unknown form");
+  if (!coords || !cells) return fail(EGFEM_ERR_ARG, "coords/cells null");
+  if (n_nodes <= 0 || n_cells <= 0) return fail(EGFEM_ERR_SHAPE, "empty mesh");
+  if (n_nodes >= (int64_t(1) << 31) || n_cells >= (int64_t(1) << 31))
+    return fail(EGFEM_ERR_SHAPE, "mesh too large for int32 indices");
+  if (!(drop_rel >= 0.0)) return fail(EGFEM_ERR_ARG, "drop_rel must be >= 0");
+  const int nl = dim + 1;
+  const int64_t N = n_nodes;
+
+  // --- element geometry --------------------------------------------------
+  std::vector<Geom> geo((size_t)n_cells);
+  for (int64_t e = 0; e < n_cells; ++e) {
+    const int32_t* c = cells + e * nl;
+    for (int a = 0; a < nl; ++a)
+      if (c[a] < 0 || c[a] >= N) return fail(EGFEM_ERR_MESH, "cell index out of range");
+    for (int a = 0; a < nl; ++a)
+      for (int b = a + 1; b < nl; ++b)
+        if (c[a] == c[b]) return fail(EGFEM_ERR_MESH, "repeated vertex in a cell");
+    if (!cell_geometry(dim, coords, c, geo[e])) return fail(EGFEM_ERR_MESH, "degenerate cell");
+  }
+
+  // --- node -> cell incidence -------------------------------------------
+  std::vector<int64_t> nptr(N + 1, 0);
+  for (int64_t e = 0; e < n_cells; ++e)
+    for (int a = 0; a < nl; ++a) nptr[cells[e * nl + a] + 1]++;
+  for (int64_t i = 0; i < N; ++i) {
+    if (nptr[i + 1] == 0) return fail(EGFEM_ERR_MESH, "node not referenced by any cell");
+    nptr[i + 1] += nptr[i];
+  }
+  std::vector<int32_t> ncell(nptr[N]);
+  {
+    std::vector<int64_t> fillp(nptr.begin(), nptr.end() - 1);
+    for (int64_t e = 0; e < n_cells; ++e)
+      for (int a = 0; a < nl; ++a) ncell[fillp[cells[e * nl + a]]++] = (int32_t)e;   // ascending e
+  }
+
+  // local integrals of the mass tensor: d! alpha! / (d+3)! by multiplicity pattern
+  double fact_d = 1.0, fact_d3 = 1.0;
+  for (int m = 2; m <= dim; ++m) fact_d *= m;
+  for (int m = 2; m <= dim + 3; ++m) fact_d3 *= m;
+  const double m3_aaa = fact_d * 6.0 / fact_d3;
+  const double m3_aab = fact_d * 2.0 / fact_d3;
+  const double m3_abc = fact_d * 1.0 / fact_d3;
+  const double m2_diag = 2.0 / ((dim + 1.0) * (dim + 2.0));
+  const double m2_off = 1.0 / ((dim + 1.0) * (dim + 2.0));
+
+  // --- row pass: pattern, matrices and both fiber streams -----------------
+  std::vector<int32_t> rowptr(N + 1, 0), col;
+  std::vector<int32_t> kptrA(1, 0), kA, jptrB(1, 0), jB;
+  std::vector<double> vA, vB, kval, mval;
+  int64_t structural = 0;
+  int max_row_slots = 0;
+  std::vector<int32_t> cols;
+  std::vector<double> acc;
+  std::vector<unsigned char> present;
+  std::vector<double> kacc, macc;
+  const bool sym = (form == EGFEM_FORM_MASS);
+  col.reserve((size_t)N * (dim == 3 ? 15 : 7));
+
+  for (int64_t i = 0; i < N; ++i) {
+    cols.clear();
+    for (int64_t q = nptr[i]; q < nptr[i + 1]; ++q) {
+      const int32_t* c = cells + (int64_t)ncell[q] * nl;
+      for (int a = 0; a < nl; ++a) cols.push_back(c[a]);
+    }
+    std::sort(cols.begin(), cols.end());
+    cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+    const int nc = (int)cols.size();
+    max_row_slots = std::max(max_row_slots, nc);
+    acc.assign((size_t)nc * nc, 0.0);
+    present.assign((size_t)nc * nc, 0);
+    kacc.assign(nc, 0.0);
+    macc.assign(nc, 0.0);
+    auto lidx = [&](int32_t node) {
+      return (int)(std::lower_bound(cols.begin(), cols.end(), node) - cols.begin());
+    };
+    for (int64_t q = nptr[i]; q < nptr[i + 1]; ++q) {
+      const int64_t e = ncell[q];
+      const int32_t* c = cells + e * nl;
+      const Geom& g = geo[e];
+      int a = 0;
+      while (c[a] != (int32_t)i) ++a;
+      int loc[4];
+      for (int b = 0; b < nl; ++b) loc[b] = lidx(c[b]);
+      for (int b = 0; b < nl; ++b) {
+        double gg = 0.0;
+        for (int r = 0; r < dim; ++r) gg += g.G[a][r] * g.G[b][r];
+        const double kab = g.vol * gg;
+        kacc[loc[b]] += kab;
+        macc[loc[b]] += g.vol * (a == b ? m2_diag : m2_off);
+        for (int cc = 0; cc < nl; ++cc) {
+          double val;
+          if (!sym) {
+            val = kab / (double)(dim + 1);
+          } else {
+            const int same = (a == b) + (a == cc) + (b == cc);
+            val = g.vol * (same == 3 ? m3_aaa : (same == 1 ? m3_aab : m3_abc));
+          }
+          const size_t idx = (size_t)loc[b] * nc + loc[cc];
+          acc[idx] += val;
+          present[idx] = 1;
+        }
+      }
+    }
+    double rowmax = 0.0;
+    for (size_t t = 0; t < acc.size(); ++t)
+      if (present[t]) {
+        ++structural;
+        rowmax = std::max(rowmax, std::fabs(acc[t]));
+      }
+    const double thr = drop_rel * rowmax;
+    auto kept = [&](size_t t) { return present[t] && acc[t] != 0.0 && std::fabs(acc[t]) > thr; };
+    for (int jb = 0; jb < nc; ++jb) {
+      col.push_back(cols[jb]);
+      kval.push_back(kacc[jb]);
+      mval.push_back(macc[jb]);
+      for (int kc = 0; kc < nc; ++kc) {
+        const size_t t = (size_t)jb * nc + kc;
+        if (kept(t)) {
+          kA.push_back(cols[kc]);
+          vA.push_back(acc[t]);
+        }
+      }
+      kptrA.push_back((int32_t)kA.size());
+      if (!sym) {
+        // B fiber of slot (i, cols[jb]) as k: j runs over the row's columns
+        for (int jj = 0; jj < nc; ++jj) {
+          const size_t t = (size_t)jj * nc + jb;
+          if (kept(t)) {
+            jB.push_back(cols[jj]);
+            vB.push_back(acc[t]);
+          }
+        }
+        jptrB.push_back((int32_t)jB.size());
+      }
+    }
+    if (col.size() >= (size_t)INT32_MAX || kA.size() >= (size_t)INT32_MAX)
+      return fail(EGFEM_ERR_SHAPE, "more than 2^31 slots or tensor entries");
+    rowptr[i + 1] = (int32_t)col.size();
+  }
+  const int64_t slots = (int64_t)col.size();
+
+  // --- transpose permutation and diagonal ---------------------------------
+  std::vector<int32_t> tperm(slots), diag(N);
+  for (int64_t i = 0; i < N; ++i) {
+    for (int32_t s = rowptr[i]; s < rowptr[i + 1]; ++s) {
+      const int32_t j = col[s];
+      const int32_t* b = col.data() + rowptr[j];
+      const int32_t* e = col.data() + rowptr[j + 1];
+      const int32_t* f = std::lower_bound(b, e, (int32_t)i);
+      if (f == e || *f != (int32_t)i) return fail(EGFEM_ERR_MESH, "non-symmetric adjacency");
+      tperm[s] = (int32_t)(f - col.data());
+      if (j == (int32_t)i) diag[i] = s;
+    }
+  }
+
+  // --- row blocks --------------------------------------------------------
+  const std::vector<int32_t>& kpB = sym ? kptrA : jptrB;
+  std::vector<int32_t> blk(1, 0);
+  {
+    int64_t r0 = 0;
+    while (r0 < N) {
+      int64_t r1 = r0;
+      while (r1 < N) {
+        const int64_t rows = r1 + 1 - r0;
+        const int64_t sl = rowptr[r1 + 1] - rowptr[r0];
+        const int64_t na = kptrA[rowptr[r1 + 1]] - kptrA[rowptr[r0]];
+        const int64_t nb = kpB[rowptr[r1 + 1]] - kpB[rowptr[r0]];
+        if (rows > kCapRows || sl > kCapSlots || na > kCapNnz || nb > kCapNnz) break;
+        ++r1;
+      }
+      if (r1 == r0) return fail(EGFEM_ERR_SHAPE, "a node row exceeds the row-block capacity "
+                                                 "(1024 tensor entries / 512 slots)");
+      blk.push_back((int32_t)r1);
+      r0 = r1;
+    }
+  }
+
+  // --- upload -------------------------------------------------------------
+  egfem_tensor_s* T = new egfem_tensor_s();
+  T->dim = dim;
+  T->form = form;
+  T->symmetric = sym ? 1 : 0;
+  T->n = N;
+  T->n_cells = n_cells;
+  T->nnz = (int64_t)vA.size();
+  T->nnz_b = T->nnz;
+  T->structural = structural;
+  T->slots = slots;
+  T->max_row_slots = max_row_slots;
+  int lanes = 4;
+  while (lanes < max_row_slots && lanes < 64) lanes *= 2;
+  T->lanes_per_row = lanes;
+  T->row_blocks = (int64_t)blk.size() - 1;
+  T->h_rowptr = rowptr;
+  hipGetDevice(&T->device);
+  int64_t bytes = 0;
+  int rc = EGFEM_OK;
+  if (rc == EGFEM_OK) rc = upload(rowptr, &T->rowptr, &bytes);
+  if (rc == EGFEM_OK) rc = upload(col, &T->col, &bytes);
+  if (rc == EGFEM_OK) rc = upload(diag, &T->diag, &bytes);
+  if (rc == EGFEM_OK) rc = upload(tperm, &T->tperm, &bytes);
+  if (rc == EGFEM_OK) rc = upload(kptrA, &T->kptrA, &bytes);
+  if (rc == EGFEM_OK) rc = upload(kA, &T->kA, &bytes);
+  if (rc == EGFEM_OK) rc = upload(vA, &T->vA, &bytes);
+  if (rc == EGFEM_OK && !sym) rc = upload(jptrB, &T->jptrB, &bytes);
+  if (rc == EGFEM_OK && !sym) rc = upload(jB, &T->jB, &bytes);
+  if (rc == EGFEM_OK && !sym) rc = upload(vB, &T->vB, &bytes);
+  if (rc == EGFEM_OK) rc = upload(kval, &T->kval, &bytes);
+  if (rc == EGFEM_OK) rc = upload(mval, &T->mval, &bytes);
+  if (rc == EGFEM_OK) rc = upload(blk, &T->blk_row, &bytes);
+  if (sym) {
+    T->jptrB = T->kptrA;
+    T->jB = T->kA;
+    T->vB = T->vA;
+  }
+  T->device_bytes = bytes;
+  if (rc != EGFEM_OK) {
+    egfem_tensor_destroy(T);
+    return rc;
+  }
+  *out = T;
+  return EGFEM_OK;
+}

@@ -1,0 +1,146 @@
+// Internal declarations shared by the libegfem translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/egfem.h"
+
+namespace egfem {
+
+// Row-block capacities of the LDS-staged tensor kernels.  A block is a run of
+// consecutive node rows whose A-stream entries, B-stream entries and
+// adjacency slots all fit these bounds (one workgroup per block).
+constexpr int kBlockThreads = 256;
+constexpr int kCapNnz = 1024;     // tensor entries per block (A and B separately)
+constexpr int kCapSlots = 512;    // adjacency slots per block
+constexpr int kCapRows = 256;     // rows per block (one thread per row in the row stage)
+
+// Persistent Krylov kernel shape.
+constexpr int kKrylovThreads = 512;
+constexpr int kMaxKrylovBlocks = 1024;
+constexpr int kRedSlots = 8;      // reduction slots in flight (>= 2 barriers apart)
+
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+
+#define EGFEM_HIP_CHECK(expr)                                                        \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return ::egfem::fail(EGFEM_ERR_HIP, std::string(#expr " failed: ") +          \
+                                              hipGetErrorString(e_));                \
+  } while (0)
+
+// Solver workspace owned by a handle (allocated on first use).
+struct Workspace {
+  bool ready = false;
+  double* F = nullptr;          // residual
+  double* delta = nullptr;      // Newton correction
+  double* utry = nullptr;       // damped trial iterate
+  double* jval = nullptr;       // Jacobian values [slots]
+  double* jvalT = nullptr;      // transposed values [slots] (adjoint solves)
+  double* dinv = nullptr;       // 1 / diag
+  double* rhs = nullptr;
+  // BiCGStab vectors
+  double *r = nullptr, *rhat = nullptr, *p = nullptr, *v = nullptr, *s = nullptr,
+         *t = nullptr, *phat = nullptr, *shat = nullptr;
+  double* partial = nullptr;    // per-row-block partial sums [row_blocks]
+  double* red = nullptr;        // persistent-kernel reduction slots [kRedSlots * kMaxKrylovBlocks]
+  unsigned* ctrl = nullptr;     // barrier counter / generation / flags (device)
+  double* qslot = nullptr;      // per-slot scratch [slots] (mode-3 contraction)
+  int32_t* krow = nullptr;      // Krylov row partition [kMaxKrylovBlocks + 1]
+  int krow_blocks = 0;          // grid size the partition was made for
+  double* kout = nullptr;       // Krylov result [4] (device)
+  double* host_partial = nullptr;  // pinned host mirror of partial sums
+  double* host_kout = nullptr;     // pinned host mirror of the Krylov result
+};
+
+}  // namespace egfem
+
+// The handle.
+struct egfem_tensor_s {
+  int dim = 0;
+  int form = 0;
+  int symmetric = 0;
+  int64_t n = 0;
+  int64_t n_cells = 0;
+  int64_t nnz = 0;
+  int64_t nnz_b = 0;
+  int64_t structural = 0;
+  int64_t slots = 0;
+  int max_row_slots = 0;
+  int lanes_per_row = 8;        // SpMV sub-wave width (power of two >= max row length)
+  int device = 0;
+  // device arrays
+  int32_t* rowptr = nullptr;    // [n+1]
+  int32_t* col = nullptr;       // [slots]
+  int32_t* diag = nullptr;      // [n]   slot of (i,i)
+  int32_t* tperm = nullptr;     // [slots] slot of (j,i) for slot (i,j)
+  int32_t* kptrA = nullptr;     // [slots+1]
+  int32_t* kA = nullptr;        // [nnz]
+  double* vA = nullptr;         // [nnz]
+  int32_t* jptrB = nullptr;     // [slots+1]  (aliases kptrA when symmetric)
+  int32_t* jB = nullptr;        // [nnz]
+  double* vB = nullptr;         // [nnz]
+  double* kval = nullptr;       // [slots]
+  double* mval = nullptr;       // [slots]
+  int32_t* blk_row = nullptr;   // [row_blocks+1]
+  int64_t row_blocks = 0;
+  std::vector<int32_t> h_rowptr;  // host copy (row partitions)
+  int64_t device_bytes = 0;
+  egfem::Workspace ws;
+};
+
+namespace egfem {
+
+// Kernel launchers (egfem_kernels.hip).  All return hipError_t of the launch.
+struct ProblemView {
+  const double* a0;       // or null
+  double a0c;
+  const double* load;     // or null (treated as 0)
+  const uint8_t* dir;     // or null
+  int addK;
+};
+
+hipError_t launch_action_raw(const egfem_tensor_s* T, const double* u, const double* a, double* r,
+                             hipStream_t st);
+hipError_t launch_action_problem(const egfem_tensor_s* T, const ProblemView& pv, const double* u,
+                                 const double* delta, double alpha, double* uout, double* F,
+                                 double* partial, hipStream_t st);
+hipError_t launch_jacobian(const egfem_tensor_s* T, const double* u, const double* a,
+                           const double* a0, double a0c, int use_problem_a, const double* dadu,
+                           int dadu_2u, int addK, const uint8_t* dir, double* jval, double* dinv,
+                           hipStream_t st);
+hipError_t launch_slot_mode2(const egfem_tensor_s* T, const double* u, double* q, hipStream_t st);
+hipError_t launch_csr_matvec(const egfem_tensor_s* T, const double* vals, const double* x, double* y,
+                             hipStream_t st);
+hipError_t launch_csr_matvec_perm(const egfem_tensor_s* T, const double* vals, const double* w,
+                                  double* y, hipStream_t st);
+hipError_t launch_permute_slots(const egfem_tensor_s* T, const double* in, double* out,
+                                hipStream_t st);
+hipError_t launch_fill(double* x, double v, int64_t n, hipStream_t st);
+hipError_t launch_fill_u32(unsigned* x, unsigned v, int64_t n, hipStream_t st);
+hipError_t launch_mask_zero(double* x, const uint8_t* dir, int64_t n, hipStream_t st);
+hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t st);
+
+// Krylov (egfem_krylov.hip)
+struct KrylovResult {
+  int status = 0;
+  int iters = 0;
+  double relres = 0.0;
+  double bnorm = 0.0;
+  int blocks = 0;
+};
+// Solves (rhs_scale * rhs) = A x with A = J (perm == null) or J^T (perm = tperm).
+int krylov_bicgstab(egfem_tensor_s* T, const double* jval, const double* dinv, const double* rhs,
+                    double rhs_scale, double* x, bool x_zero, double rtol, int max_iter,
+                    int blocks, KrylovResult* res, hipStream_t st, const int32_t* perm);
+
+// Workspace
+int ensure_workspace(egfem_tensor_s* T);
+
+}  // namespace egfem

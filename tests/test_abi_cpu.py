@@ -1,0 +1,99 @@
+"""CPU checks of the C ABI: the library loads, exports every declared entry
+point, and its host-side argument / mesh validation rejects bad input before
+any device work.  No compute calls (no GPU here)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2005_06193_amd as eg
+from paper_2005_06193_amd import binding as B
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
+                      "egfem.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(egfem_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    lib = eg.load_library()
+    syms = declared_symbols()
+    assert len(syms) >= 15
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(syms) == set(B.EXPORTS), set(syms) ^ set(B.EXPORTS)
+
+
+def test_version_and_defaults():
+    assert eg.version().startswith("egfem")
+    o = B._Opts()
+    eg.load_library().egfem_newton_opts_default(C.byref(o))
+    assert o.tol == 1e-10 and o.max_newton == 50 and o.max_backtracks == 10
+    assert o.forcing == 0 and o.krylov_rtol == 1e-12
+
+
+def _build(coords, cells, dim=None, form=0, drop=1e-13):
+    lib = eg.load_library()
+    coords = np.ascontiguousarray(coords, np.float64)
+    cells = np.ascontiguousarray(cells, np.int32)
+    out = C.c_void_p()
+    rc = lib.egfem_build_tensor(dim or coords.shape[1], coords.shape[0], coords.ctypes.data,
+                                cells.shape[0], cells.ctypes.data, form, drop, C.byref(out))
+    return rc, lib.egfem_last_error().decode()
+
+
+def test_build_argument_errors():
+    c = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
+    t = np.array([[0, 1, 2]])
+    assert _build(c, t, dim=4)[0] == B.EGFEM_ERR_ARG
+    assert _build(c, t, form=7)[0] == B.EGFEM_ERR_ARG
+    assert _build(c, t, drop=-1.0)[0] == B.EGFEM_ERR_ARG
+    rc, msg = _build(c, np.array([[0, 1, 5]]))
+    assert rc == B.EGFEM_ERR_MESH and "range" in msg
+    rc, msg = _build(c, np.array([[0, 1, 1]]))
+    assert rc == B.EGFEM_ERR_MESH
+    rc, msg = _build(np.array([[0.0, 0.0], [1.0, 0.0], [2.0, 0.0]]), t)
+    assert rc == B.EGFEM_ERR_MESH and "degenerate" in msg
+    rc, msg = _build(np.vstack([c, [[5.0, 5.0]]]), t)
+    assert rc == B.EGFEM_ERR_MESH and "referenced" in msg
+    lib = eg.load_library()
+    assert lib.egfem_build_tensor(2, 3, c.ctypes.data, 1, t.ctypes.data, 0, 0.0, None) == \
+        B.EGFEM_ERR_ARG
+
+
+def test_build_row_capacity_limit():
+    """A node of valence 600 exceeds one row block (512 slots) -> ERR_SHAPE."""
+    k = 600
+    ang = 2 * np.pi * np.arange(k) / k
+    coords = np.vstack([[0.0, 0.0], np.stack([np.cos(ang), np.sin(ang)], 1)])
+    cells = np.array([[0, 1 + i, 1 + (i + 1) % k] for i in range(k)])
+    rc, msg = _build(coords, cells)
+    assert rc == B.EGFEM_ERR_SHAPE and "capacity" in msg
+
+
+def test_null_handles_rejected():
+    lib = eg.load_library()
+    z = None
+    assert lib.egfem_residual(z, z, z, z, z) == B.EGFEM_ERR_ARG
+    assert lib.egfem_jacobian(z, z, z, z, 0, z, z, z, z) == B.EGFEM_ERR_ARG
+    assert lib.egfem_mode3(z, z, z, z, z) == B.EGFEM_ERR_ARG
+    assert lib.egfem_matvec(z, 0, z, 0, z, z, z) == B.EGFEM_ERR_ARG
+    assert lib.egfem_newton(z, z, z, z, z, z) == B.EGFEM_ERR_ARG
+    assert lib.egfem_solve(z, z, 0, z, z, 1e-10, 10, None, None, z) == B.EGFEM_ERR_ARG
+    assert lib.egfem_tensor_info(z, None) == B.EGFEM_ERR_ARG
+    assert lib.egfem_newton_batched(0, None, None, None, None, None, None) == B.EGFEM_ERR_ARG
+    lib.egfem_tensor_destroy(z)
+
+
+def test_binding_fails_loudly_without_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    with pytest.raises(eg.EgfemError):
+        eg.Tensor.build(np.zeros((3, 2)), np.array([[0, 1, 2]]))

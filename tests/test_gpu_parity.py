@@ -1,0 +1,338 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tolerances (FP64): per-call outputs (tensor entries, actions, Jacobian values,
+matrix-vector products) differ only by summation order, so they are compared
+normwise at 1e-12 relative (observed ~1e-15).  Converged Newton solutions are
+compared at 1e-10 relative with both sides iterated to their rounding floor,
+plus a certificate: the oracle's residual evaluated at the GPU solution.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+import torch
+
+import workloads as W
+from oracle import egfem_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def eg():
+    import paper_2005_06193_amd as mod
+    return mod
+
+
+def dt(x, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(x), dtype=dtype, device=DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def gpu_problem(T, wl):
+    """Device problem with the load d = M f computed on the GPU."""
+    f = dt(wl.f)
+    load = T.matvec(f, "M")
+    dirm = dt(wl.mesh.dirichlet, torch.uint8)
+    a0 = dt(wl.a0) if wl.a0 is not None else None
+    return eg().Problem(T.n, load, dirm, a0, wl.a0_const, wl.add_stiffness)
+
+
+def csr_of(T, jval):
+    rp, cl = T.pattern()
+    return sp.csr_matrix((host(jval), cl, rp), shape=(T.n, T.n))
+
+
+def relerr(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def irregular_mesh(n, seed=3):
+    """Structured 2D mesh with jittered interior nodes (non-uniform elements)."""
+    m = W.mesh_2d(n)
+    rng = np.random.default_rng(seed)
+    c = m.coords.copy()
+    inner = m.dirichlet == 0
+    c[inner] += rng.uniform(-0.25, 0.25, size=(inner.sum(), 2)) / n
+    return W.Mesh(2, n, c, m.cells, m.dirichlet)
+
+
+MESHES = {
+    "1d_n16": lambda: W.mesh_1d(16),
+    "1d_n257": lambda: W.mesh_1d(257),
+    "2d_n8": lambda: W.mesh_2d(8),
+    "2d_n37": lambda: W.mesh_2d(37),
+    "2d_jitter_n21": lambda: irregular_mesh(21),
+    "3d_n3": lambda: W.mesh_3d(3),
+    "3d_n7": lambda: W.mesh_3d(7),
+}
+
+
+# ---------------------------------------------------------------------------
+# offline build
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mesh", list(MESHES))
+@pytest.mark.parametrize("form", [0, 1])
+def test_build_matches_oracle_tensor(mesh, form):
+    m = MESHES[mesh]()
+    T = eg().Tensor.from_mesh(m, form)
+    To = O.assemble_tensor(m.coords, m.cells, form)
+    i, j, k, v = T.export()
+    assert T.info.nnz == To.nnz
+    assert T.info.structural_nnz == To.structural_nnz
+    key_g = (i.astype(np.int64) * m.n_nodes + j) * m.n_nodes + k
+    key_o = (To.i * m.n_nodes + To.j) * m.n_nodes + To.k
+    og = np.argsort(key_g)
+    oo = np.argsort(key_o)
+    assert np.array_equal(key_g[og], key_o[oo])
+    assert np.abs(v[og] - To.v[oo]).max() <= 1e-14 * np.abs(To.v).max()
+    # stiffness and mass matrices in the pattern
+    x = np.random.default_rng(1).uniform(-1, 1, m.n_nodes)
+    K = O.assemble_stiffness(m.coords, m.cells)
+    M = O.assemble_mass(m.coords, m.cells)
+    assert relerr(host(T.matvec(dt(x), "K")), K @ x) < 1e-13
+    assert relerr(host(T.matvec(dt(x), "M")), M @ x) < 1e-13
+
+
+def test_build_counts_full_size():
+    """Stored / structural entries and slots at the full workload sizes."""
+    for n in (256, 512):
+        m = W.mesh_2d(n)
+        T = eg().Tensor.from_mesh(m, 0)
+        assert T.info.nnz == 23 * n * n + 14 * n + 1
+        assert T.info.structural_nnz == 31 * n * n + 14 * n + 1
+        assert T.info.slots == 7 * n * n + 6 * n + 1
+        T.close()
+    m = W.mesh_2d(512)
+    T = eg().Tensor.from_mesh(m, 1)
+    assert T.info.nnz == 31 * 512 ** 2 + 14 * 512 + 1
+    T.close()
+    n = 64
+    m = W.mesh_3d(n)
+    T = eg().Tensor.from_mesh(m, 0)
+    assert T.info.nnz == 63 * n ** 3 + 69 * n ** 2 + 21 * n + 1
+    assert T.info.structural_nnz == 115 * n ** 3 + 93 * n ** 2 + 21 * n + 1
+    assert T.info.slots == 4018753
+    T.close()
+
+
+# ---------------------------------------------------------------------------
+# tensor actions
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mesh", list(MESHES))
+@pytest.mark.parametrize("form", [0, 1])
+def test_raw_action_and_mode3(mesh, form):
+    m = MESHES[mesh]()
+    T = eg().Tensor.from_mesh(m, form)
+    To = O.assemble_tensor(m.coords, m.cells, form)
+    rng = np.random.default_rng(7)
+    u = rng.uniform(-1, 1, m.n_nodes)
+    a = rng.uniform(0.5, 2, m.n_nodes)
+    w = rng.uniform(-1, 1, m.n_nodes)
+    r = host(T.residual(dt(u), dt(a)))
+    assert relerr(r, O.contract_uv(To, u, a)) < 1e-12
+    q = host(T.mode3(dt(w), dt(u)))
+    assert relerr(q, O.contract_mode3(To, w, u)) < 1e-12
+
+
+@pytest.mark.parametrize("mesh", list(MESHES))
+@pytest.mark.parametrize("form", [0, 1])
+def test_jacobian_emission(mesh, form):
+    m = MESHES[mesh]()
+    T = eg().Tensor.from_mesh(m, form)
+    To = O.assemble_tensor(m.coords, m.cells, form)
+    rng = np.random.default_rng(8)
+    u = rng.uniform(-1, 1, m.n_nodes)
+    a = rng.uniform(0.5, 2, m.n_nodes)
+    g = rng.uniform(-2, 2, m.n_nodes)
+    dirm = m.dirichlet.astype(bool)
+    Jg = csr_of(T, T.jacobian(dt(u), dt(a), dt(g), add_stiffness=(form == 1),
+                              dirichlet=dt(m.dirichlet, torch.uint8)))
+    J = O.contract_first(To, a) + O.contract_mode2(To, u) @ sp.diags(g)
+    if form == 1:
+        J = J + O.assemble_stiffness(m.coords, m.cells)
+    free = sp.diags((~dirm).astype(float))
+    J = (free @ J @ free + sp.diags(dirm.astype(float))).tocsr()
+    assert abs(Jg - J).max() <= 1e-12 * abs(J).max()
+    # without the second term and without boundary handling
+    Jg2 = csr_of(T, T.jacobian(dt(u), dt(a)))
+    assert abs(Jg2 - O.contract_first(To, a)).max() <= 1e-12 * abs(J).max()
+    # transposed product through the slot permutation
+    x = rng.uniform(-1, 1, m.n_nodes)
+    jv = T.jacobian(dt(u), dt(a), dt(g))
+    Jf = O.contract_first(To, a) + O.contract_mode2(To, u) @ sp.diags(g)
+    assert relerr(host(T.matvec(dt(x), "J", jval=jv, transpose=True)), Jf.T @ x) < 1e-12
+    assert relerr(host(T.matvec(dt(x), "J", jval=jv)), Jf @ x) < 1e-12
+
+
+WORKLOADS_SMALL = {
+    "1d": lambda: W.nonlinear_diffusion_1d(256),
+    "2d_n40": lambda: W.nonlinear_diffusion_2d(40),
+    "2d_semilinear_n33": lambda: W.semilinear_2d(33),
+    "3d_kappa_n6": lambda: W.diffusion_3d(6),
+}
+
+
+@pytest.mark.parametrize("name", list(WORKLOADS_SMALL))
+def test_problem_residual_and_jacobian(name):
+    wl = WORKLOADS_SMALL[name]()
+    T = eg().Tensor.from_mesh(wl.mesh, wl.form)
+    p = gpu_problem(T, wl)
+    po = O.build_problem(wl)
+    assert relerr(host(p.load), po.d) < 1e-13
+    u = np.random.default_rng(9).uniform(-1, 1, T.n)
+    u[po.dirichlet] = 0
+    F, nrm = T.problem_residual(p, dt(u), with_norm=True)
+    Fo = O.residual(po, u)
+    assert relerr(host(F), Fo) < 1e-12
+    assert abs(nrm - np.linalg.norm(Fo)) <= 1e-12 * np.linalg.norm(Fo)
+    dinv = torch.empty(T.n, dtype=torch.float64, device=DEV)
+    Jg = csr_of(T, T.problem_jacobian(p, dt(u), dinv=dinv))
+    Jo = O.jacobian(po, u)
+    assert abs(Jg - Jo).max() <= 1e-12 * abs(Jo).max()
+    assert relerr(host(dinv), 1.0 / Jo.diagonal()) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# linear solve
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("transpose", [False, True])
+def test_bicgstab_solve(transpose):
+    wl = W.nonlinear_diffusion_2d(48)
+    T = eg().Tensor.from_mesh(wl.mesh, wl.form)
+    p = gpu_problem(T, wl)
+    po = O.build_problem(wl)
+    u = np.random.default_rng(10).uniform(0, 1, T.n)
+    u[po.dirichlet] = 0
+    jv = T.problem_jacobian(p, dt(u))
+    Jo = O.jacobian(po, u)
+    rhs = np.random.default_rng(11).uniform(-1, 1, T.n)
+    x, rc, its, rr = T.solve(jv, dt(rhs), transpose=transpose, rtol=1e-13)
+    assert rc == 0, (rc, its, rr)
+    A = (Jo.T if transpose else Jo).tocsc()
+    xo = spla.spsolve(A, rhs)
+    # ||x - x*|| <= cond * rtol; cond(J) ~ 1e3 here
+    assert relerr(host(x), xo) < 1e-9
+    assert relerr(A @ host(x), rhs) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Newton
+# ---------------------------------------------------------------------------
+def _tight():
+    return eg().NewtonOptions(tol=1e-14, max_newton=30, krylov_rtol=1e-14)
+
+
+@pytest.mark.parametrize("name", ["1d", "2d_n40", "2d_semilinear_n33", "3d_kappa_n6"])
+def test_newton_matches_oracle(name):
+    wl = WORKLOADS_SMALL[name]()
+    T = eg().Tensor.from_mesh(wl.mesh, wl.form)
+    p = gpu_problem(T, wl)
+    po = O.build_problem(wl)
+    u = torch.zeros(T.n, dtype=torch.float64, device=DEV)
+    st = T.newton(p, u, _tight(), warn=False)
+    assert st.status in (0, 4), st.status_name
+    uo, sto = O.newton(po, tol=1e-14, max_iter=30)
+    ug = host(u)
+    assert relerr(ug, uo) <= 1e-10
+    # certificate: the oracle's residual at the GPU solution
+    Fo0 = np.linalg.norm(po.d[~po.dirichlet])
+    assert np.linalg.norm(O.residual(po, ug)) <= 1e-11 * Fo0
+
+
+def test_newton_full_size_2d_256():
+    """The 2D nonlinear-diffusion workload at full size (66,049 nodes)."""
+    wl = W.nonlinear_diffusion_2d(256)
+    T = eg().Tensor.from_mesh(wl.mesh, wl.form)
+    p = gpu_problem(T, wl)
+    po = O.build_problem(wl)
+    u = torch.zeros(T.n, dtype=torch.float64, device=DEV)
+    st = T.newton(p, u, _tight(), warn=False)
+    assert st.status in (0, 4), st.status_name
+    uo, _ = O.newton(po, tol=1e-14, max_iter=30)
+    ug = host(u)
+    assert relerr(ug, uo) <= 1e-10
+    assert np.linalg.norm(O.residual(po, ug)) <= 1e-10 * np.linalg.norm(po.d[~po.dirichlet])
+    # the performance configuration (Eisenstat-Walker forcing, tol 1e-10)
+    u2 = torch.zeros(T.n, dtype=torch.float64, device=DEV)
+    st2 = T.newton(p, u2, eg().NewtonOptions(tol=1e-10, forcing=1), warn=False)
+    assert st2.status == 0
+    assert st2.res <= 1e-10 * st2.res0
+    assert np.linalg.norm(O.residual(po, host(u2))) <= 1.01e-10 * np.linalg.norm(po.d[~po.dirichlet])
+
+
+def test_newton_deterministic():
+    wl = W.nonlinear_diffusion_2d(64)
+    T = eg().Tensor.from_mesh(wl.mesh, wl.form)
+    p = gpu_problem(T, wl)
+    outs = []
+    for _ in range(2):
+        u = torch.zeros(T.n, dtype=torch.float64, device=DEV)
+        T.newton(p, u, eg().NewtonOptions(tol=1e-10, forcing=1))
+        outs.append(host(u))
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_newton_edge_cases():
+    E = eg()
+    # one interior node: 4u + 2u^3 = d_1
+    wl = W.Workload("t", W.mesh_1d(2), np.full(3, 7.0), 0, None, 1.0, False, 1e-14, 0)
+    T = E.Tensor.from_mesh(wl.mesh, 0)
+    p = gpu_problem(T, wl)
+    u = torch.zeros(3, dtype=torch.float64, device=DEV)
+    st = T.newton(p, u, _tight(), warn=False)
+    d1 = host(p.load)[1]
+    ug = host(u)
+    assert abs(4 * ug[1] + 2 * ug[1] ** 3 - d1) <= 1e-13 * abs(d1)
+    assert ug[0] == 0.0 and ug[2] == 0.0
+    # zero load: u = 0 at once
+    wl0 = W.Workload("t", W.mesh_2d(5), np.zeros(36), 0, None, 1.0, False, 1e-12, 0)
+    T0 = E.Tensor.from_mesh(wl0.mesh, 0)
+    u0 = torch.zeros(36, dtype=torch.float64, device=DEV)
+    st0 = T0.newton(gpu_problem(T0, wl0), u0)
+    assert st0.status == 0 and st0.newton_iters == 0 and not host(u0).any()
+    # warm start at the solution: the iterate does not move
+    u1 = u.clone()
+    st1 = T.newton(p, u1, E.NewtonOptions(tol=1e-12), warn=False)
+    assert st1.status in (0, 4)
+    assert np.abs(host(u1) - ug).max() <= 1e-14 * np.abs(ug).max()
+    # NaN in the initial guess -> nonfinite status, no exception
+    un = torch.full((3,), float("nan"), dtype=torch.float64, device=DEV)
+    stn = T.newton(p, un, warn=False)
+    assert stn.status_name == "nonfinite"
+    # iteration cap
+    wl2 = W.nonlinear_diffusion_2d(24)
+    T2 = E.Tensor.from_mesh(wl2.mesh, 0)
+    u2 = torch.zeros(T2.n, dtype=torch.float64, device=DEV)
+    st2 = T2.newton(gpu_problem(T2, wl2), u2, E.NewtonOptions(max_newton=1), warn=False)
+    assert st2.status_name == "not_converged" and st2.newton_iters == 1
+
+
+# ---------------------------------------------------------------------------
+# full-size spot checks (rows the oracle assembles one by one)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("which", ["2d_semilinear_512", "3d_64"])
+def test_full_size_sampled_rows(which):
+    wl = W.semilinear_2d(512) if which == "2d_semilinear_512" else W.diffusion_3d(64)
+    m = wl.mesh
+    T = eg().Tensor.from_mesh(m, wl.form)
+    rng = np.random.default_rng(12)
+    rows = np.unique(np.concatenate([rng.integers(0, m.n_nodes, 300), [0, m.n_nodes - 1,
+                                                                       m.n_nodes // 2]]))
+    u = rng.uniform(-1, 1, m.n_nodes)
+    a = rng.uniform(0.5, 2, m.n_nodes)
+    g = rng.uniform(-2, 2, m.n_nodes)
+    Tr = O.tensor_rows(m.coords, m.cells, wl.form, rows)
+    r = host(T.residual(dt(u), dt(a)))
+    ro = O.contract_uv(Tr, u, a)
+    assert relerr(r[rows], ro[rows]) < 1e-12
+    Jg = csr_of(T, T.jacobian(dt(u), dt(a), dt(g)))
+    Jo = (O.contract_first(Tr, a) + O.contract_mode2(Tr, u) @ sp.diags(g)).tocsr()
+    d = (Jg[rows] - Jo[rows])
+    assert abs(d).max() <= 1e-12 * abs(Jo[rows]).max()

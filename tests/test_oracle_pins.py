@@ -450,3 +450,22 @@ def test_adjoint_against_finite_differences(dim, n):
             jm = O.tracking_objective(solve(f, kappa - h * vec)[1], u_d)
         fd = (jp - jm) / (2 * h)
         assert abs(fd - grad @ vec) <= 1e-6 * max(abs(fd), 1e-8), (which, fd, grad @ vec)
+
+
+def test_elementwise_residual_equals_tensor_residual():
+    """int a_h grad u_h . grad phi_i with a_h in P1 is exactly T:(u (x) a)."""
+    for dim, n, form in [(1, 9, O.FORM_STIFF), (2, 7, O.FORM_STIFF), (3, 3, O.FORM_STIFF),
+                         (2, 7, O.FORM_MASS)]:
+        p = _small_problem(dim, n, form)
+        u = np.random.default_rng(4).uniform(-1, 1, p.n)
+        u[p.dirichlet] = 0
+        F1 = O.residual(p, u)
+        F2 = O.residual_elementwise(p, u)
+        assert np.abs(F1 - F2).max() <= 1e-13 * np.abs(F1).max()
+        rows = np.array([0, p.n // 3, p.n // 2, p.n - 1])
+        F3 = O.residual_elementwise(p, u, rows)
+        assert np.abs(F3[rows] - F1[rows]).max() <= 1e-13 * np.abs(F1).max()
+        Tr = O.tensor_rows(p.coords, p.cells, form, rows)
+        D = p.T.dense()
+        Dr = Tr.dense()
+        assert np.abs(D[rows] - Dr[rows]).max() <= 1e-15 * np.abs(D).max()
