@@ -191,6 +191,9 @@ typedef struct {
   double eta_max;            /* EW cap (default 0.1) */
   int max_backtracks;        /* damping halvings (default 10) */
   int krylov_blocks;         /* persistent Krylov grid size, 0 = automatic */
+  int krylov_threads;        /* persistent Krylov workgroup size: 256, 512 or 1024 (0 = 1024) */
+  int timing;                /* nonzero: time every kernel launch with HIP events on the
+                                stream (fills the t_* / n_* fields of the statistics) */
 } egfem_newton_opts;
 
 #define EGFEM_HIST 64
@@ -204,6 +207,13 @@ typedef struct {
   double res;                /* final ||F||_2 */
   double res_hist[EGFEM_HIST];    /* ||F|| after step k (k < EGFEM_HIST) */
   int krylov_hist[EGFEM_HIST];    /* Krylov iterations of step k */
+  /* with opts.timing: summed launch durations (ms) and launch counts */
+  double t_action_ms;        /* fused residual / trial-iterate tensor action */
+  double t_jacobian_ms;      /* Jacobian emission */
+  double t_krylov_ms;        /* persistent BiCGStab */
+  int n_action;
+  int n_jacobian;
+  int n_krylov;
 } egfem_newton_stats;
 
 /* Fill opts with the defaults above. */

@@ -60,13 +60,17 @@ class _Problem(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_newton", C.c_int), ("max_krylov", C.c_int),
                 ("krylov_rtol", C.c_double), ("forcing", C.c_int), ("eta_max", C.c_double),
-                ("max_backtracks", C.c_int), ("krylov_blocks", C.c_int)]
+                ("max_backtracks", C.c_int), ("krylov_blocks", C.c_int),
+                ("krylov_threads", C.c_int), ("timing", C.c_int)]
 
 
 class _Stats(C.Structure):
     _fields_ = [("status", C.c_int), ("newton_iters", C.c_int), ("krylov_iters", C.c_int),
                 ("backtracks", C.c_int), ("res0", C.c_double), ("res", C.c_double),
-                ("res_hist", C.c_double * HIST), ("krylov_hist", C.c_int * HIST)]
+                ("res_hist", C.c_double * HIST), ("krylov_hist", C.c_int * HIST),
+                ("t_action_ms", C.c_double), ("t_jacobian_ms", C.c_double),
+                ("t_krylov_ms", C.c_double), ("n_action", C.c_int), ("n_jacobian", C.c_int),
+                ("n_krylov", C.c_int)]
 
 
 _lib = None
@@ -173,10 +177,13 @@ class NewtonOptions:
     eta_max: float = 0.1
     max_backtracks: int = 10
     krylov_blocks: int = 0
+    krylov_threads: int = 0
+    timing: int = 0
 
     def c(self) -> _Opts:
         return _Opts(self.tol, self.max_newton, self.max_krylov, self.krylov_rtol, self.forcing,
-                     self.eta_max, self.max_backtracks, self.krylov_blocks)
+                     self.eta_max, self.max_backtracks, self.krylov_blocks, self.krylov_threads,
+                     self.timing)
 
 
 @dataclass
@@ -189,6 +196,12 @@ class NewtonStats:
     res: float
     res_hist: List[float]
     krylov_hist: List[int]
+    t_action_ms: float = 0.0
+    t_jacobian_ms: float = 0.0
+    t_krylov_ms: float = 0.0
+    n_action: int = 0
+    n_jacobian: int = 0
+    n_krylov: int = 0
 
     @property
     def status_name(self) -> str:
@@ -198,7 +211,8 @@ class NewtonStats:
     def from_c(cls, s: _Stats) -> "NewtonStats":
         k = min(s.newton_iters, HIST)
         return cls(s.status, s.newton_iters, s.krylov_iters, s.backtracks, s.res0, s.res,
-                   list(s.res_hist[:k]), list(s.krylov_hist[:k]))
+                   list(s.res_hist[:k]), list(s.krylov_hist[:k]), s.t_action_ms, s.t_jacobian_ms,
+                   s.t_krylov_ms, s.n_action, s.n_jacobian, s.n_krylov)
 
 
 class Problem:

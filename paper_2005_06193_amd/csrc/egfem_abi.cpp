@@ -31,16 +31,16 @@ int ensure_workspace(egfem_tensor_s* T) {
   if (W.ready) return EGFEM_OK;
   const size_t N = (size_t)T->n, S = (size_t)T->slots;
   int rc = EGFEM_OK;
-  double** nvecs[] = {&W.F, &W.delta, &W.utry, &W.dinv, &W.rhs, &W.r, &W.rhat,
-                      &W.p, &W.v, &W.s, &W.t, &W.phat, &W.shat};
+  double** nvecs[] = {&W.F, &W.delta, &W.utry, &W.dinv, &W.rhs, &W.r, &W.rhat, &W.p,
+                      &W.v, &W.s, &W.t, &W.z, &W.phat, &W.rh, &W.vh};
   for (double** v : nvecs)
     if (rc == EGFEM_OK) rc = dalloc(v, N);
   if (rc == EGFEM_OK) rc = dalloc(&W.jval, S);
   if (rc == EGFEM_OK) rc = dalloc(&W.jvalT, S);
   if (rc == EGFEM_OK) rc = dalloc(&W.qslot, S);
   if (rc == EGFEM_OK) rc = dalloc(&W.partial, (size_t)T->row_blocks);
-  if (rc == EGFEM_OK) rc = dalloc(&W.red, (size_t)kRedSlots * 4 * kMaxKrylovBlocks);
-  if (rc == EGFEM_OK) rc = dalloc(&W.ctrl, 4);
+  if (rc == EGFEM_OK) rc = dalloc(&W.red, (size_t)kRedSlots * 8 * kMaxKrylovBlocks);
+  if (rc == EGFEM_OK) rc = dalloc(&W.ctrl, kCtrlWordsMax);
   if (rc == EGFEM_OK) rc = dalloc(&W.krow, (size_t)kMaxKrylovBlocks + 1);
   if (rc == EGFEM_OK) rc = dalloc(&W.kout, 4);
   if (rc == EGFEM_OK &&
@@ -49,16 +49,17 @@ int ensure_workspace(egfem_tensor_s* T) {
   if (rc == EGFEM_OK && hipHostMalloc((void**)&W.host_kout, 4 * sizeof(double), 0) != hipSuccess)
     rc = fail(EGFEM_ERR_OOM, "hipHostMalloc failed");
   if (rc != EGFEM_OK) return rc;
-  T->device_bytes += (int64_t)((13 * N + 3 * S + T->row_blocks + (size_t)kRedSlots * 4 * kMaxKrylovBlocks + 4) *
-                                   sizeof(double) + (kMaxKrylovBlocks + 1) * 4 + 16);
+  T->device_bytes += (int64_t)((15 * N + 3 * S + T->row_blocks + (size_t)kRedSlots * 8 * kMaxKrylovBlocks + 4) *
+                                   sizeof(double) + (kMaxKrylovBlocks + 1) * 4 + kCtrlWordsMax * 4);
   W.krow_blocks = 0;
   W.ready = true;
   return EGFEM_OK;
 }
 
 static void free_workspace(Workspace& W) {
-  double* vecs[] = {W.F, W.delta, W.utry, W.jval, W.jvalT, W.dinv, W.rhs, W.r, W.rhat, W.p, W.v,
-                    W.s, W.t, W.phat, W.shat, W.partial, W.red, W.qslot, W.kout};
+  double* vecs[] = {W.F,  W.delta, W.utry, W.jval, W.jvalT, W.dinv, W.rhs,     W.r,
+                    W.rhat, W.p,  W.v,     W.s,    W.t,    W.z,    W.phat,  W.rh,
+                    W.vh, W.partial, W.red, W.qslot, W.kout};
   for (double* v : vecs)
     if (v) hipFree(v);
   if (W.ctrl) hipFree(W.ctrl);
@@ -86,6 +87,39 @@ static int read_norm(egfem_tensor_s* T, hipStream_t st, double* norm) {
   *norm = std::sqrt(s);
   return EGFEM_OK;
 }
+
+// Launch-duration accounting with a pair of HIP events on the caller's stream.
+struct LaunchTimer {
+  bool on = false;
+  hipStream_t st = nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
+  int init(bool enable, hipStream_t s) {
+    on = enable;
+    st = s;
+    if (!on) return EGFEM_OK;
+    EGFEM_HIP_CHECK(hipEventCreate(&a));
+    EGFEM_HIP_CHECK(hipEventCreate(&b));
+    return EGFEM_OK;
+  }
+  ~LaunchTimer() {
+    if (a) hipEventDestroy(a);
+    if (b) hipEventDestroy(b);
+  }
+  int start() {
+    if (on) EGFEM_HIP_CHECK(hipEventRecord(a, st));
+    return EGFEM_OK;
+  }
+  int stop(double* acc, int* cnt) {
+    if (!on) return EGFEM_OK;
+    EGFEM_HIP_CHECK(hipEventRecord(b, st));
+    EGFEM_HIP_CHECK(hipEventSynchronize(b));
+    float ms = 0.0f;
+    EGFEM_HIP_CHECK(hipEventElapsedTime(&ms, a, b));
+    *acc += ms;
+    ++*cnt;
+    return EGFEM_OK;
+  }
+};
 
 static ProblemView view(const egfem_problem* p) {
   ProblemView v;
@@ -236,11 +270,15 @@ void egfem_newton_opts_default(egfem_newton_opts* o) {
   o->eta_max = 0.1;
   o->max_backtracks = 10;
   o->krylov_blocks = 0;
+  o->krylov_threads = 0;
+  o->timing = 0;
 }
 
 static int check_opts(const egfem_newton_opts& o) {
   if (!(o.tol >= 0.0) || o.max_newton < 0 || o.max_krylov < 1 || !(o.krylov_rtol > 0.0) ||
       !(o.eta_max > 0.0 && o.eta_max < 1.0) || o.max_backtracks < 0 || o.krylov_blocks < 0 ||
+      (o.krylov_threads != 0 && o.krylov_threads != 256 && o.krylov_threads != 512 &&
+       o.krylov_threads != 1024) ||
       (o.forcing != 0 && o.forcing != 1))
     return fail(EGFEM_ERR_ARG, "invalid Newton options");
   return EGFEM_OK;
@@ -280,10 +318,19 @@ int egfem_newton(egfem_tensor_t T, const egfem_problem* p, double* u, const egfe
   egfem_newton_stats stats;
   std::memset(&stats, 0, sizeof(stats));
 
+  LaunchTimer tm;
+  if ((rc = tm.init(opts.timing != 0, st)) != EGFEM_OK) return rc;
+#define EGFEM_TRY(x)                    \
+  do {                                  \
+    if ((rc = (x)) != EGFEM_OK) return rc; \
+  } while (0)
+
   EGFEM_HIP_CHECK(launch_mask_zero(u, p->dirichlet, T->n, st));
+  EGFEM_TRY(tm.start());
   EGFEM_HIP_CHECK(launch_action_problem(T, pv, u, nullptr, 0.0, nullptr, W.F, W.partial, st));
+  EGFEM_TRY(tm.stop(&stats.t_action_ms, &stats.n_action));
   double nF0 = 0.0;
-  if ((rc = read_norm(T, st, &nF0)) != EGFEM_OK) return rc;
+  EGFEM_TRY(read_norm(T, st, &nF0));
   stats.res0 = nF0;
   stats.res = nF0;
   int status = EGFEM_NOT_CONVERGED;
@@ -295,15 +342,21 @@ int egfem_newton(egfem_tensor_t T, const egfem_problem* p, double* u, const egfe
     if (nF <= opts.tol * nF0) { status = EGFEM_OK; break; }
     if (k >= opts.max_newton) break;
     // Jacobian emission DF(u) and Jacobi diagonal
+    EGFEM_TRY(tm.start());
     EGFEM_HIP_CHECK(launch_jacobian(T, u, nullptr, p->a0, p->a0_const, 1, nullptr, 1,
                                     p->add_stiffness, p->dirichlet, W.jval, W.dinv, st));
+    EGFEM_TRY(tm.stop(&stats.t_jacobian_ms, &stats.n_jacobian));
     const double rtol = opts.forcing ? ew_forcing(k, nF, nF_prev, eta, opts.eta_max, opts.tol * nF0)
                                      : opts.krylov_rtol;
     eta = rtol;
     KrylovResult kr;
     rc = krylov_bicgstab(T, W.jval, W.dinv, W.F, -1.0, W.delta, true, rtol, opts.max_krylov,
-                         opts.krylov_blocks, &kr, st, nullptr);
+                         opts.krylov_blocks, &kr, st, nullptr, tm.on, opts.krylov_threads);
     if (rc != EGFEM_OK) return rc;
+    if (tm.on) {
+      stats.t_krylov_ms += kr.kernel_ms;
+      ++stats.n_krylov;
+    }
     stats.krylov_iters += kr.iters;
     if (k < EGFEM_HIST) stats.krylov_hist[k] = kr.iters;
     if (kr.status == EGFEM_NONFINITE) { status = EGFEM_NONFINITE; break; }
@@ -311,8 +364,10 @@ int egfem_newton(egfem_tensor_t T, const egfem_problem* p, double* u, const egfe
     double alpha = 1.0, nFt = 0.0;
     bool accepted = false;
     for (int bt = 0; bt <= opts.max_backtracks; ++bt) {
+      EGFEM_TRY(tm.start());
       EGFEM_HIP_CHECK(launch_action_problem(T, pv, u, W.delta, alpha, W.utry, W.F, W.partial, st));
-      if ((rc = read_norm(T, st, &nFt)) != EGFEM_OK) return rc;
+      EGFEM_TRY(tm.stop(&stats.t_action_ms, &stats.n_action));
+      EGFEM_TRY(read_norm(T, st, &nFt));
       if (std::isfinite(nFt) && nFt <= (1.0 - 1e-4 * alpha) * nF) { accepted = true; break; }
       alpha *= 0.5;
       ++stats.backtracks;
@@ -329,6 +384,7 @@ int egfem_newton(egfem_tensor_t T, const egfem_problem* p, double* u, const egfe
     if (k < EGFEM_HIST) stats.res_hist[k] = nF;
     ++k;
   }
+#undef EGFEM_TRY
   if (status == EGFEM_NOT_CONVERGED && nF <= opts.tol * nF0) status = EGFEM_OK;
   EGFEM_HIP_CHECK(hipStreamSynchronize(st));
   stats.status = status;

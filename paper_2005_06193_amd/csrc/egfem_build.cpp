@@ -290,6 +290,9 @@ extern "C" int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords
   int lanes = 4;
   while (lanes < max_row_slots && lanes < 64) lanes *= 2;
   T->lanes_per_row = lanes;
+  int klanes = 4;
+  while (2 * klanes < max_row_slots && klanes < 64) klanes *= 2;
+  T->krylov_lanes = klanes;
   T->row_blocks = (int64_t)blk.size() - 1;
   T->h_rowptr = rowptr;
   hipGetDevice(&T->device);

@@ -20,9 +20,10 @@ constexpr int kCapSlots = 512;    // adjacency slots per block
 constexpr int kCapRows = 256;     // rows per block (one thread per row in the row stage)
 
 // Persistent Krylov kernel shape.
-constexpr int kKrylovThreads = 512;
+constexpr int kKrylovThreads = 1024;
 constexpr int kMaxKrylovBlocks = 1024;
 constexpr int kRedSlots = 8;      // reduction slots in flight (>= 2 barriers apart)
+constexpr int kCtrlWordsMax = 1024;  // barrier control words (one 128-byte line per counter)
 
 void set_error(const std::string& msg);
 int fail(int code, const std::string& msg);
@@ -47,10 +48,10 @@ struct Workspace {
   double* rhs = nullptr;
   // BiCGStab vectors
   double *r = nullptr, *rhat = nullptr, *p = nullptr, *v = nullptr, *s = nullptr,
-         *t = nullptr, *phat = nullptr, *shat = nullptr;
+         *t = nullptr, *z = nullptr, *phat = nullptr, *rh = nullptr, *vh = nullptr;
   double* partial = nullptr;    // per-row-block partial sums [row_blocks]
-  double* red = nullptr;        // persistent-kernel reduction slots [kRedSlots * kMaxKrylovBlocks]
-  unsigned* ctrl = nullptr;     // barrier counter / generation / flags (device)
+  double* red = nullptr;        // persistent-kernel reduction slots [kRedSlots * 8 * kMaxKrylovBlocks]
+  unsigned* ctrl = nullptr;     // barrier counters / epoch / abort flag [kCtrlWordsMax] (device)
   double* qslot = nullptr;      // per-slot scratch [slots] (mode-3 contraction)
   int32_t* krow = nullptr;      // Krylov row partition [kMaxKrylovBlocks + 1]
   int krow_blocks = 0;          // grid size the partition was made for
@@ -74,6 +75,7 @@ struct egfem_tensor_s {
   int64_t slots = 0;
   int max_row_slots = 0;
   int lanes_per_row = 8;        // SpMV sub-wave width (power of two >= max row length)
+  int krylov_lanes = 4;         // persistent-Krylov SpMV width (power of two >= max row / 2)
   int device = 0;
   // device arrays
   int32_t* rowptr = nullptr;    // [n+1]
@@ -134,11 +136,14 @@ struct KrylovResult {
   double relres = 0.0;
   double bnorm = 0.0;
   int blocks = 0;
+  int threads = 0;
+  double kernel_ms = 0.0;   // launch duration of the persistent kernel (when timed)
 };
 // Solves (rhs_scale * rhs) = A x with A = J (perm == null) or J^T (perm = tperm).
 int krylov_bicgstab(egfem_tensor_s* T, const double* jval, const double* dinv, const double* rhs,
                     double rhs_scale, double* x, bool x_zero, double rtol, int max_iter,
-                    int blocks, KrylovResult* res, hipStream_t st, const int32_t* perm);
+                    int blocks, KrylovResult* res, hipStream_t st, const int32_t* perm,
+                    bool timed = false, int threads = 0);
 
 // Workspace
 int ensure_workspace(egfem_tensor_s* T);
