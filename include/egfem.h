@@ -239,6 +239,28 @@ int egfem_solve(egfem_tensor_t T, const double* jval, int transpose, const doubl
                 double* x, double rtol, int max_iter, int* iters, double* relres, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Adjoint of the converged solve (implicit function theorem; the gradient
+ * pattern for optimal control that motivates the method, Sec. 6).
+ *
+ * For an objective with dJ/du = ubar at the solution u* of F(u; d, a0) = 0:
+ *   DF(u*)^T lambda = ubar on the free nodes (lambda = 0 on Dirichlet nodes),
+ *   dJ/dd   = lambda                       (F depends on the load through -d),
+ *   dJ/da0  = -(T ._2 u*)^T lambda, i.e. -sum_ij lambda_i T_ijk u*_j.
+ * Only u* is needed (no Newton trajectory is stored).  The transposed
+ * Jacobian is applied through the slot transpose permutation; the solve is the
+ * same Jacobi-BiCGStab with opts->krylov_rtol / max_krylov.
+ *   u, ubar:      device [n_nodes] inputs
+ *   lambda:       device [n_nodes] output (also dJ/dd)
+ *   grad_a0:      device [n_nodes] output or NULL
+ *   krylov_iters, relres: host outputs or NULL
+ * Returns the Krylov status (EGFEM_OK / NOT_CONVERGED / BREAKDOWN / NONFINITE)
+ * or a negative error.  Synchronises the stream.
+ * ---------------------------------------------------------------------- */
+int egfem_adjoint(egfem_tensor_t T, const egfem_problem* p, const double* u, const double* ubar,
+                  const egfem_newton_opts* o, double* lambda, double* grad_a0, int* krylov_iters,
+                  double* relres, void* stream);
+
+/* ------------------------------------------------------------------------
  * Batched form: `count` independent problems (each its own handle, sizes may
  * differ) solved by ONE persistent launch; each instance is owned by a team of
  * workgroups sized by its tensor size, with device-side Newton control and

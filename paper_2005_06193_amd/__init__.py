@@ -4,3 +4,4 @@ from .binding import (  # noqa: F401
     EgfemError, FORM_MASS, FORM_STIFF, Info, NewtonOptions, NewtonStats, Problem, Tensor,
     load_library, newton_batched, version, EXPORTS, LIB_PATH,
 )
+from .autograd import EGFEMSolve, solve  # noqa: F401

@@ -100,6 +100,9 @@ EXPORTS = {
     "egfem_newton_batched": (C.c_int, [C.c_int, C.POINTER(C.c_void_p), C.POINTER(_Problem),
                                        C.POINTER(C.c_void_p), C.POINTER(_Opts), C.POINTER(_Stats),
                                        C.c_void_p]),
+    "egfem_adjoint": (C.c_int, [C.c_void_p, C.POINTER(_Problem), C.c_void_p, C.c_void_p,
+                                C.POINTER(_Opts), C.c_void_p, C.c_void_p, C.POINTER(C.c_int),
+                                C.POINTER(C.c_double), C.c_void_p]),
     "egfem_last_error": (C.c_char_p, []),
     "egfem_version": (C.c_char_p, []),
 }
@@ -229,7 +232,8 @@ class Problem:
         self.add_stiffness = bool(add_stiffness)
 
     def c(self) -> _Problem:
-        return _Problem(_dptr(self.a0, n=self.n), self.a0_const, _dptr(self.load, n=self.n),
+        return _Problem(_dptr(self.a0, n=self.n), self.a0_const,
+                        _dptr(self.load, n=self.n) if self.load is not None else None,
                         _dptr(self.dirichlet, torch.uint8, self.n), int(self.add_stiffness))
 
 
@@ -367,6 +371,22 @@ class Tensor:
         if rc not in (EGFEM_OK, EGFEM_STAGNATED) and warn:
             warnings.warn(f"egfem_newton ended with status {stats.status_name}")
         return stats
+
+    def adjoint(self, p: Problem, u, ubar, opts: Optional[NewtonOptions] = None,
+                grad_a0: bool = True):
+        """lambda = DF(u)^-T ubar (free nodes) and dJ/da0 = -(T ._2 u)^T lambda.
+        Returns (lambda, grad_a0 or None, status, krylov_iters, relres)."""
+        lam = torch.empty_like(u)
+        ga = torch.empty_like(u) if grad_a0 else None
+        o = (opts or NewtonOptions()).c()
+        pc = p.c()
+        it = C.c_int(0)
+        rr = C.c_double(0.0)
+        rc = load_library().egfem_adjoint(self.handle, C.byref(pc), _dptr(u, n=self.n),
+                                          _dptr(ubar, n=self.n), C.byref(o), _dptr(lam, n=self.n),
+                                          _dptr(ga, n=self.n), C.byref(it), C.byref(rr), _stream())
+        _check(rc, allow_positive=True)
+        return lam, ga, rc, it.value, rr.value
 
     def solve(self, jval, rhs, x=None, transpose=False, rtol=1e-12, max_iter=20000):
         x = torch.zeros_like(rhs) if x is None else x

@@ -414,4 +414,41 @@ int egfem_solve(egfem_tensor_t T, const double* jval, int transpose, const doubl
   return kr.status;
 }
 
+int egfem_adjoint(egfem_tensor_t T, const egfem_problem* p, const double* u, const double* ubar,
+                  const egfem_newton_opts* o, double* lambda, double* grad_a0, int* krylov_iters,
+                  double* relres, void* stream) {
+  if (!T || !p || !u || !ubar || !lambda) return fail(EGFEM_ERR_ARG, "null argument");
+  if (lambda == u || lambda == ubar || (grad_a0 && (grad_a0 == u || grad_a0 == lambda)))
+    return fail(EGFEM_ERR_ARG, "outputs must not alias inputs");
+  egfem_newton_opts opts;
+  egfem_newton_opts_default(&opts);
+  if (o) opts = *o;
+  int rc = check_opts(opts);
+  if (rc != EGFEM_OK) return rc;
+  rc = ensure_workspace(T);
+  if (rc != EGFEM_OK) return rc;
+  Workspace& W = T->ws;
+  hipStream_t st = (hipStream_t)stream;
+  // DF(u*) and its diagonal (the same for DF^T)
+  EGFEM_HIP_CHECK(launch_jacobian(T, u, nullptr, p->a0, p->a0_const, 1, nullptr, 1, p->add_stiffness,
+                                  p->dirichlet, W.jval, W.dinv, st));
+  // right-hand side: ubar on the free nodes
+  EGFEM_HIP_CHECK(launch_copy(W.rhs, ubar, T->n, st));
+  EGFEM_HIP_CHECK(launch_mask_zero(W.rhs, p->dirichlet, T->n, st));
+  KrylovResult kr;
+  rc = krylov_bicgstab(T, W.jval, W.dinv, W.rhs, 1.0, lambda, true, opts.krylov_rtol, opts.max_krylov,
+                       opts.krylov_blocks, &kr, st, T->tperm, false, opts.krylov_threads);
+  if (rc != EGFEM_OK) return rc;
+  if (grad_a0) {
+    // -sum_ij lambda_i T_ijk u_j : slot-wise (T ._2 u), then the transposed gather
+    EGFEM_HIP_CHECK(launch_slot_mode2(T, u, W.qslot, st));
+    EGFEM_HIP_CHECK(launch_csr_matvec_perm(T, W.qslot, lambda, grad_a0, st));
+    EGFEM_HIP_CHECK(launch_scale(grad_a0, -1.0, T->n, st));
+  }
+  EGFEM_HIP_CHECK(hipStreamSynchronize(st));
+  if (krylov_iters) *krylov_iters = kr.iters;
+  if (relres) *relres = kr.relres;
+  return kr.status;
+}
+
 }  // extern "C"

@@ -128,6 +128,7 @@ hipError_t launch_fill(double* x, double v, int64_t n, hipStream_t st);
 hipError_t launch_fill_u32(unsigned* x, unsigned v, int64_t n, hipStream_t st);
 hipError_t launch_mask_zero(double* x, const uint8_t* dir, int64_t n, hipStream_t st);
 hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t st);
+hipError_t launch_scale(double* x, double s, int64_t n, hipStream_t st);
 
 // Krylov (egfem_krylov.hip)
 struct KrylovResult {

@@ -252,6 +252,11 @@ __global__ void k_copy(double* __restrict__ dst, const double* __restrict__ src,
   if (i < n) dst[i] = src[i];
 }
 
+__global__ void k_scale(double* x, double s, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] *= s;
+}
+
 inline unsigned grid1d(int64_t n, int bs = kBlockThreads) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -348,6 +353,12 @@ hipError_t launch_mask_zero(double* x, const uint8_t* dir, int64_t n, hipStream_
 hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_copy, dim3(grid1d(n)), dim3(kBlockThreads), 0, st, dst, src, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(double* x, double s, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale, dim3(grid1d(n)), dim3(kBlockThreads), 0, st, x, s, n);
   return hipGetLastError();
 }
 

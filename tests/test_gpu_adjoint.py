@@ -1,0 +1,132 @@
+"""Adjoint of the converged EGFEM solve on the GPU: against the oracle's
+adjoint (direct transpose solve), a dot-product test of the transposed
+operator, and central finite differences through the torch.autograd.Function
+at the full 3D workload size."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import egfem_oracle as O
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def eg():
+    import paper_2005_06193_amd as mod
+    return mod
+
+
+def dt(x, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(x), dtype=dtype, device=DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def relerr(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def tight():
+    return eg().NewtonOptions(tol=1e-14, max_newton=40, krylov_rtol=1e-14)
+
+
+@pytest.mark.parametrize("which", ["2d_kappa_n24", "3d_kappa_n6", "2d_semilinear_n20"])
+def test_adjoint_matches_oracle(which):
+    rng = np.random.default_rng(21)
+    if which == "2d_kappa_n24":
+        m = W.mesh_2d(24)
+        wl = W.Workload("t", m, W.gaussian_sum(m.coords, rng), 0, rng.uniform(0.5, 2, m.n_nodes), 0.0,
+                        False, 1e-14, 0)
+    elif which == "3d_kappa_n6":
+        wl = W.diffusion_3d(6)
+    else:
+        wl = W.semilinear_2d(20)
+    T = eg().Tensor.from_mesh(wl.mesh, wl.form)
+    po = O.build_problem(wl)
+    uo, _ = O.newton(po, tol=1e-14, max_iter=40)
+    ubar = rng.uniform(-1, 1, T.n)
+    lam_o, gf_o, ga_o = O.adjoint_gradients(po, uo, ubar)
+    dirm = dt(wl.mesh.dirichlet, torch.uint8)
+    a0 = dt(po.a0) if wl.a0 is not None else None
+    p = eg().Problem(T.n, None, dirm, a0, wl.a0_const, wl.add_stiffness)
+    lam, ga, rc, its, rr = T.adjoint(p, dt(uo), dt(ubar), tight())
+    assert rc == 0, (rc, its, rr)
+    assert relerr(host(lam), lam_o) < 1e-10
+    assert relerr(host(T.matvec(lam, "M")), gf_o) < 1e-10
+    assert relerr(host(ga), ga_o) < 1e-10
+    # dot-product test of the transposed operator: <J v, lam> = <v, ubar_free>
+    jv = T.problem_jacobian(eg().Problem(T.n, None, dirm, a0, wl.a0_const, wl.add_stiffness),
+                            dt(uo))
+    v = rng.uniform(-1, 1, T.n)
+    Jv = host(T.matvec(dt(v), "J", jval=jv))
+    rhs = ubar.copy()
+    rhs[wl.mesh.dirichlet.astype(bool)] = 0
+    assert abs(Jv @ host(lam) - v @ rhs) <= 1e-11 * np.abs(v) @ np.abs(rhs)
+
+
+def test_autograd_gradients_small():
+    """torch.autograd through EGFEMSolve equals the oracle adjoint (f and kappa)."""
+    rng = np.random.default_rng(22)
+    m = W.mesh_2d(16)
+    f_np = W.gaussian_sum(m.coords, rng)
+    k_np = rng.uniform(0.5, 2.0, m.n_nodes)
+    ud_np = rng.uniform(0, 0.1, m.n_nodes)
+    T = eg().Tensor.from_mesh(m, 0)
+    tpl = eg().Problem(T.n, None, dt(m.dirichlet, torch.uint8), None, 0.0, False)
+    f = dt(f_np).requires_grad_(True)
+    k = dt(k_np).requires_grad_(True)
+    u = eg().solve(f, k, T, tpl, tight())
+    J = 0.5 * torch.sum((u - dt(ud_np)) ** 2)
+    J.backward()
+    wl = W.Workload("t", m, f_np, 0, k_np, 0.0, False, 1e-14, 0)
+    po = O.build_problem(wl)
+    uo, _ = O.newton(po, tol=1e-14, max_iter=40)
+    _, gf_o, gk_o = O.adjoint_gradients(po, uo, uo - ud_np)
+    assert relerr(host(u), uo) < 1e-10
+    assert relerr(host(f.grad), gf_o) < 1e-9
+    assert relerr(host(k.grad), gk_o) < 1e-9
+
+
+def test_autograd_finite_differences_3d_64():
+    """The 3D differentiation workload at full size (274,625 nodes): the adjoint
+    gradients w.r.t. f and kappa against central differences (step 1e-6) of
+    J = 0.5 ||u - u_d||^2 along seeded directions; u_d solves the problem with
+    a second seeded source."""
+    E = eg()
+    wl = W.diffusion_3d(64)
+    m = wl.mesh
+    T = E.Tensor.from_mesh(m, 0)
+    tpl = E.Problem(T.n, None, dt(m.dirichlet, torch.uint8), None, 0.0, False)
+    opts = E.NewtonOptions(tol=1e-13, max_newton=40, krylov_rtol=1e-13)
+    kappa0 = dt(wl.a0)
+    with torch.no_grad():
+        u_d = E.solve(dt(wl.extra["f_target"]), kappa0, T, tpl, opts)
+    f = dt(wl.f).requires_grad_(True)
+    k = kappa0.clone().requires_grad_(True)
+    u = E.solve(f, k, T, tpl, opts)
+    J = 0.5 * torch.sum((u - u_d) ** 2)
+    J.backward()
+    gf = f.grad.detach()
+    gk = k.grad.detach()
+    h = 1e-6
+    for name, seed in (("f", 101), ("kappa", 102)):
+        v = dt(W.direction(T.n, seed))
+        with torch.no_grad():
+            if name == "f":
+                up = E.solve(f.detach() + h * v, k.detach(), T, tpl, opts)
+                um = E.solve(f.detach() - h * v, k.detach(), T, tpl, opts)
+                g = float(torch.dot(gf, v))
+            else:
+                up = E.solve(f.detach(), k.detach() + h * v, T, tpl, opts)
+                um = E.solve(f.detach(), k.detach() - h * v, T, tpl, opts)
+                g = float(torch.dot(gk, v))
+            jp = 0.5 * float(torch.sum((up - u_d) ** 2))
+            jm = 0.5 * float(torch.sum((um - u_d) ** 2))
+        fd = (jp - jm) / (2 * h)
+        print(f"{name}: adjoint {g:.10e} fd {fd:.10e} rel {abs(g - fd) / abs(fd):.2e}")
+        assert abs(g - fd) <= 1e-5 * abs(fd), (name, g, fd)
