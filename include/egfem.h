@@ -262,15 +262,43 @@ int egfem_adjoint(egfem_tensor_t T, const egfem_problem* p, const double* u, con
 
 /* ------------------------------------------------------------------------
  * Batched form: `count` independent problems (each its own handle, sizes may
- * differ) solved by ONE persistent launch; each instance is owned by a team of
- * workgroups sized by its tensor size, with device-side Newton control and
- * team-local barriers.  us[m]: device [n_nodes of m], guess in / solution out.
- * stats: host array [count] or NULL.  Same options for all instances;
- * forcing and backtracking as egfem_newton.  Synchronises the stream.
+ * differ) solved by ONE persistent cooperative launch -- the many-query use the
+ * paper's offline/online split is made for (Sec. 5 preamble).  Each instance
+ * is owned by a team of workgroups sized by its tensor size; every team runs
+ * the whole damped Newton loop (residual, Jacobian emission, BiCGStab, line
+ * search, convergence test) on the device with team-local barriers, so there
+ * is no host round trip.  us[m]: device [n_nodes of m], guess in / solution
+ * out.  stats: host array [count] or NULL.  Same options for all instances
+ * (timing is ignored).  Returns the worst instance status.  Synchronises.
  * ---------------------------------------------------------------------- */
 int egfem_newton_batched(int count, const egfem_tensor_t* Ts, const egfem_problem* ps,
                          double* const* us, const egfem_newton_opts* o,
                          egfem_newton_stats* stats, void* stream);
+
+/* Reusable batch plan behind egfem_newton_batched: device descriptors, team
+ * assignment, control words and statistics buffers are built once; every run
+ * is one persistent launch (plus a control-word fill and a statistics copy),
+ * and egfem_batch_graph_run captures that sequence once in a hipGraph and
+ * replays it.  The handles, problems and solution buffers passed at creation
+ * must stay valid for the plan's life; a handle may appear only once in a
+ * batch (its solver workspace is used by its team).
+ *   threads:  workgroup size of the persistent kernel, 512 or 1024 (0 = 512)
+ *   weight_exp: team share of instance m proportional to slots_m^weight_exp
+ *             (0 = 1.5, the cost model iterations ~ n, work ~ n^2 per iteration)
+ * Runs are asynchronous on `stream`; zero_init != 0 starts every instance from
+ * u = 0 (else from the contents of its solution buffer). */
+typedef struct egfem_batch_s* egfem_batch_t;
+int egfem_batch_create(int count, const egfem_tensor_t* Ts, const egfem_problem* ps,
+                       double* const* us, const egfem_newton_opts* o, int threads,
+                       double weight_exp, egfem_batch_t* out);
+int egfem_batch_run(egfem_batch_t B, int zero_init, void* stream);
+int egfem_batch_graph_run(egfem_batch_t B, int zero_init, void* stream);
+/* Synchronises the stream and copies per-instance statistics into stats
+ * (host array [count]); returns the worst status (largest code). */
+int egfem_batch_stats(egfem_batch_t B, egfem_newton_stats* stats, void* stream);
+/* Team size (workgroups) given to each instance: host array [count]. */
+int egfem_batch_teams(egfem_batch_t B, int* team_sizes, int* total_workgroups);
+void egfem_batch_destroy(egfem_batch_t B);
 
 /* Thread-local message of the last error. */
 const char* egfem_last_error(void);

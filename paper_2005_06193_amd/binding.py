@@ -103,6 +103,14 @@ EXPORTS = {
     "egfem_adjoint": (C.c_int, [C.c_void_p, C.POINTER(_Problem), C.c_void_p, C.c_void_p,
                                 C.POINTER(_Opts), C.c_void_p, C.c_void_p, C.POINTER(C.c_int),
                                 C.POINTER(C.c_double), C.c_void_p]),
+    "egfem_batch_create": (C.c_int, [C.c_int, C.POINTER(C.c_void_p), C.POINTER(_Problem),
+                                     C.POINTER(C.c_void_p), C.POINTER(_Opts), C.c_int, C.c_double,
+                                     C.POINTER(C.c_void_p)]),
+    "egfem_batch_run": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
+    "egfem_batch_graph_run": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
+    "egfem_batch_stats": (C.c_int, [C.c_void_p, C.POINTER(_Stats), C.c_void_p]),
+    "egfem_batch_teams": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "egfem_batch_destroy": (None, [C.c_void_p]),
     "egfem_last_error": (C.c_char_p, []),
     "egfem_version": (C.c_char_p, []),
 }
@@ -397,6 +405,55 @@ class Tensor:
                                         int(max_iter), C.byref(it), C.byref(rr), _stream())
         _check(rc, allow_positive=True)
         return x, rc, it.value, rr.value
+
+
+class Batch:
+    """Reusable batch plan: all instances solved by one persistent launch,
+    optionally replayed from a captured hipGraph."""
+
+    def __init__(self, tensors: Sequence[Tensor], problems: Sequence[Problem],
+                 us: Sequence[torch.Tensor], opts: Optional[NewtonOptions] = None,
+                 threads: int = 0, weight_exp: float = 0.0):
+        m = len(tensors)
+        if not (m == len(problems) == len(us)) or m == 0:
+            raise EgfemError(EGFEM_ERR_SHAPE, "tensors/problems/us must have equal nonzero length")
+        self.count = m
+        self._keep = (list(tensors), list(problems), list(us))   # buffers must outlive the plan
+        hs = (C.c_void_p * m)(*[t.handle.value for t in tensors])
+        self._ps = (_Problem * m)(*[p.c() for p in problems])
+        up = (C.c_void_p * m)(*[_dptr(u, n=t.n) for u, t in zip(us, tensors)])
+        o = (opts or NewtonOptions()).c()
+        out = C.c_void_p()
+        _check(load_library().egfem_batch_create(m, hs, self._ps, up, C.byref(o), int(threads),
+                                                 float(weight_exp), C.byref(out)))
+        self._h = out
+
+    def run(self, zero_init: bool = True, graph: bool = False):
+        fn = load_library().egfem_batch_graph_run if graph else load_library().egfem_batch_run
+        _check(fn(self._h, int(zero_init), _stream()))
+
+    def stats(self):
+        st = (_Stats * self.count)()
+        rc = load_library().egfem_batch_stats(self._h, st, _stream())
+        _check(rc, allow_positive=True)
+        return [NewtonStats.from_c(st[i]) for i in range(self.count)], rc
+
+    def teams(self):
+        t = (C.c_int * self.count)()
+        tot = C.c_int(0)
+        _check(load_library().egfem_batch_teams(self._h, t, C.byref(tot)))
+        return list(t), tot.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().egfem_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def newton_batched(tensors: Sequence[Tensor], problems: Sequence[Problem],

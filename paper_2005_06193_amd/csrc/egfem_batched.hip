@@ -1,0 +1,535 @@
+// Batched EGFEM Newton: many independent instances in ONE persistent
+// cooperative launch.  Instance m is owned by a team of consecutive
+// workgroups; each team member owns a contiguous range of the instance's row
+// blocks (hence a contiguous range of rows), so Jacobian rows, residual rows
+// and Krylov rows of a member coincide and only gathered vectors (u, the
+// Newton correction, the preconditioned Krylov vectors) cross workgroups,
+// through agent-coherent accesses.  The whole damped Newton loop -- residual
+// with fused pointwise update, Jacobian emission, Jacobi-BiCGStab, line
+// search, convergence test -- runs on the device with team-local barriers.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "egfem_device.h"
+
+namespace egfem {
+
+dev::TensorView view_of(const egfem_tensor_s* T);
+
+namespace {
+
+constexpr int kStatsWords = 6 + 2 * EGFEM_HIST;   // status, iters, krylov, backtracks, res0, res, hist
+
+struct Inst {
+  dev::TensorView tv;
+  const double* a0;
+  double a0c;
+  const double* load;
+  const uint8_t* dir;
+  int addK;
+  double* u;          // caller buffer: guess in / solution out
+  double* utry;       // second iterate buffer
+  double* F;
+  double* jval;
+  double* dinv;
+  dev::KArgs K;       // matrix = jval, rhs = F (scale -1), x = Newton correction
+  const int32_t* wgblk;   // [team_size + 1] row-block range of every member
+  unsigned* ctrl;
+  double* red;
+  double* stats;      // [kStatsWords]
+  int team_first;
+  int team_size;
+};
+
+struct BatchOpts {
+  double tol;
+  int max_newton;
+  int max_krylov;
+  double krylov_rtol;
+  int forcing;
+  double eta_max;
+  int max_backtracks;
+  int zero_init;
+};
+
+// Eisenstat-Walker choice 2 with the safeguards of the host driver.
+__device__ double ew_forcing(int k, double nF, double nF_prev, double eta_prev, double eta_max,
+                             double tol_abs) {
+  double eta;
+  if (k == 0) {
+    eta = eta_max;
+  } else {
+    eta = 0.9 * (nF / nF_prev) * (nF / nF_prev);
+    const double guard = 0.9 * eta_prev * eta_prev;
+    if (guard > 0.1) eta = fmax(eta, guard);
+    eta = fmin(eta, eta_max);
+  }
+  eta = fmax(eta, 0.5 * tol_abs / nF);
+  return fmin(eta, eta_max);
+}
+
+template <int NT, int L>
+__global__ __launch_bounds__(NT) void k_newton_batched(const Inst* __restrict__ insts,
+                                                       const int32_t* __restrict__ wg2inst, BatchOpts O) {
+  __shared__ dev::RowBlockLds lds;
+  __shared__ double sh[dev::kShWords<NT>];
+  __shared__ int sh_abort;
+  const Inst& I = insts[wg2inst[blockIdx.x]];
+  dev::Team tm{blockIdx.x - (unsigned)I.team_first, (unsigned)I.team_size, I.ctrl, I.red, 0u};
+  const int b0 = I.wgblk[tm.rank], b1 = I.wgblk[tm.rank + 1];
+  const int rb = I.tv.blk_row[b0], re = I.tv.blk_row[b1];
+  const int tid = threadIdx.x;
+  const double* kval = I.addK ? I.tv.kval : nullptr;
+  double red[dev::kMaxRed];
+  int nslot = 8;
+  bool abort = false;
+
+  // initial iterate (Dirichlet entries 0), published to the team
+  for (int i = rb + tid; i < re; i += NT) {
+    double ui = O.zero_init ? 0.0 : I.u[i];
+    if (I.dir && I.dir[i]) ui = 0.0;
+    dev::st_sh(I.u + i, ui);
+  }
+  abort = dev::team_barrier(tm, &sh_abort);
+  double* ucur = I.u;
+  double* unext = I.utry;
+
+  // residual at the initial iterate
+  double sq = 0.0;
+  for (int b = b0; b < b1 && !abort; ++b)
+    dev::rowblock_action<NT, true, true>(I.tv, b, ucur, nullptr, 0.0, I.a0, I.a0c, I.load, I.dir, kval,
+                                         I.F, nullptr, sq, lds);
+  for (int q = 0; q < dev::kMaxRed; ++q) red[q] = 0.0;
+  red[0] = sq;
+  if (!abort) abort = dev::team_reduce<NT>(tm, nslot, red, 1, sh, &sh_abort);
+  nslot = 17 - nslot;
+  const double nF0 = sqrt(red[0]);
+  double nF = nF0, nF_prev = nF0, eta = O.eta_max;
+  int status = EGFEM_NOT_CONVERGED;
+  if (!isfinite(nF0)) status = EGFEM_NONFINITE;
+  else if (nF0 == 0.0) status = EGFEM_OK;
+  int k = 0, kry = 0, backtracks = 0;
+  double* st = I.stats;
+  const bool writer = (tm.rank == 0 && tid == 0);
+
+  while (!abort && status == EGFEM_NOT_CONVERGED) {
+    if (nF <= O.tol * nF0) { status = EGFEM_OK; break; }
+    if (k >= O.max_newton) break;
+    // Jacobian emission for the member's own rows
+    for (int b = b0; b < b1; ++b)
+      dev::rowblock_jacobian<NT, true>(I.tv, b, ucur, nullptr, I.a0, I.a0c, 1, nullptr, 1, kval, I.dir,
+                                       I.jval, I.dinv, lds);
+    const double rtol = O.forcing ? ew_forcing(k, nF, nF_prev, eta, O.eta_max, O.tol * nF0) : O.krylov_rtol;
+    eta = rtol;
+    dev::KArgs KA = I.K;
+    KA.rtol = rtol;
+    KA.max_iter = O.max_krylov;
+    const dev::KOut ko = dev::team_bicgstab<NT, L>(tm, KA, rb, re, sh, &sh_abort);
+    if ((abort = ko.abort)) break;
+    kry += ko.iters;
+    if (writer && k < EGFEM_HIST) st[6 + EGFEM_HIST + k] = (double)ko.iters;
+    if (ko.status == EGFEM_NONFINITE) { status = EGFEM_NONFINITE; break; }
+    if ((abort = dev::team_barrier(tm, &sh_abort))) break;   // correction visible to the team
+    // damped update with the residual of the trial iterate
+    double alpha = 1.0, nFt = 0.0;
+    bool accepted = false;
+    for (int bt = 0; bt <= O.max_backtracks; ++bt) {
+      sq = 0.0;
+      for (int b = b0; b < b1; ++b)
+        dev::rowblock_action<NT, true, true>(I.tv, b, ucur, KA.x, alpha, I.a0, I.a0c, I.load, I.dir, kval,
+                                             I.F, unext, sq, lds);
+      for (int q = 0; q < dev::kMaxRed; ++q) red[q] = 0.0;
+      red[0] = sq;
+      if ((abort = dev::team_reduce<NT>(tm, nslot, red, 1, sh, &sh_abort))) break;
+      nslot = 17 - nslot;
+      nFt = sqrt(red[0]);
+      if (isfinite(nFt) && nFt <= (1.0 - 1e-4 * alpha) * nF) { accepted = true; break; }
+      alpha *= 0.5;
+      ++backtracks;
+    }
+    if (abort) break;
+    if (!accepted) { status = EGFEM_STAGNATED; break; }
+    double* tmp = ucur;
+    ucur = unext;
+    unext = tmp;
+    nF_prev = nF;
+    nF = nFt;
+    if (writer && k < EGFEM_HIST) st[6 + k] = nF;
+    ++k;
+  }
+  if (!abort && status == EGFEM_NOT_CONVERGED && nF <= O.tol * nF0) status = EGFEM_OK;
+  // the solution lives in the caller's buffer
+  if (!abort && ucur != I.u)
+    for (int i = rb + tid; i < re; i += NT) I.u[i] = dev::ld_sh(ucur + i);
+  if (writer) {
+    st[0] = abort ? (double)EGFEM_ERR_HIP : (double)status;
+    st[1] = (double)k;
+    st[2] = (double)kry;
+    st[3] = (double)backtracks;
+    st[4] = nF0;
+    st[5] = nF;
+  }
+}
+
+template <int NT, int L>
+hipError_t launch_NL(const Inst* insts, const int32_t* wg2inst, const BatchOpts& O, unsigned G,
+                     hipStream_t st) {
+  void* args[] = {(void*)&insts, (void*)&wg2inst, (void*)&O};
+  return hipLaunchCooperativeKernel((const void*)k_newton_batched<NT, L>, dim3(G), dim3(NT), args, 0, st);
+}
+
+template <int NT, int L>
+int cap_NL() {
+  int dev = 0, per_cu = 0, cus = 0;
+  hipGetDevice(&dev);
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_newton_batched<NT, L>, NT, 0) !=
+      hipSuccess)
+    return 0;
+  return per_cu * cus;
+}
+
+template <int NT>
+hipError_t launch_T(int L, const Inst* insts, const int32_t* wg2inst, const BatchOpts& O, unsigned G,
+                    hipStream_t st) {
+  switch (L) {
+    case 4: return launch_NL<NT, 4>(insts, wg2inst, O, G, st);
+    case 8: return launch_NL<NT, 8>(insts, wg2inst, O, G, st);
+    case 16: return launch_NL<NT, 16>(insts, wg2inst, O, G, st);
+    case 32: return launch_NL<NT, 32>(insts, wg2inst, O, G, st);
+    default: return launch_NL<NT, 64>(insts, wg2inst, O, G, st);
+  }
+}
+
+template <int NT>
+int cap_T(int L) {
+  switch (L) {
+    case 4: return cap_NL<NT, 4>();
+    case 8: return cap_NL<NT, 8>();
+    case 16: return cap_NL<NT, 16>();
+    case 32: return cap_NL<NT, 32>();
+    default: return cap_NL<NT, 64>();
+  }
+}
+
+}  // namespace
+}  // namespace egfem
+
+struct egfem_batch_s {
+  int count = 0;
+  int NT = 512;
+  int L = 4;
+  int G = 0;
+  std::vector<egfem_tensor_t> Ts;
+  std::vector<int> team;
+  egfem::BatchOpts opts{};
+  egfem::Inst* d_insts = nullptr;
+  int32_t* d_wg2inst = nullptr;
+  int32_t* d_wgblk = nullptr;
+  unsigned* d_ctrl = nullptr;
+  double* d_red = nullptr;
+  double* d_stats = nullptr;
+  double* h_stats = nullptr;
+  size_t ctrl_words = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int graph_zero_init = -1;
+  hipStream_t cap_stream = nullptr;   // capture stream owned by the plan (default priority)
+};
+
+namespace {
+
+void free_batch(egfem_batch_s* B) {
+  if (!B) return;
+  if (B->exec) hipGraphExecDestroy(B->exec);
+  if (B->graph) hipGraphDestroy(B->graph);
+  if (B->cap_stream) hipStreamDestroy(B->cap_stream);
+  if (B->d_insts) hipFree(B->d_insts);
+  if (B->d_wg2inst) hipFree(B->d_wg2inst);
+  if (B->d_wgblk) hipFree(B->d_wgblk);
+  if (B->d_ctrl) hipFree(B->d_ctrl);
+  if (B->d_red) hipFree(B->d_red);
+  if (B->d_stats) hipFree(B->d_stats);
+  if (B->h_stats) hipHostFree(B->h_stats);
+  delete B;
+}
+
+// Contiguous ranges of row blocks balanced by slots.
+void split_blocks(const egfem_tensor_s* T, const std::vector<int32_t>& hblk, int g, std::vector<int32_t>& out) {
+  const int64_t nb = T->row_blocks;
+  const int64_t S = T->slots;
+  out.assign(g + 1, 0);
+  int64_t b = 0;
+  for (int w = 1; w < g; ++w) {
+    const int64_t target = S * w / g;
+    while (b < nb && T->h_rowptr[hblk[b]] < target) ++b;
+    // every member keeps at least one block
+    b = std::max<int64_t>(b, out[w - 1] + 1);
+    b = std::min<int64_t>(b, nb - (g - w));
+    out[w] = (int32_t)b;
+  }
+  out[g] = (int32_t)nb;
+}
+
+}  // namespace
+
+extern "C" {
+
+int egfem_batch_create(int count, const egfem_tensor_t* Ts, const egfem_problem* ps, double* const* us,
+                       const egfem_newton_opts* o, int threads, double weight_exp, egfem_batch_t* out) {
+  using namespace egfem;
+  if (!out) return fail(EGFEM_ERR_ARG, "out is null");
+  *out = nullptr;
+  if (count <= 0 || !Ts || !ps || !us) return fail(EGFEM_ERR_ARG, "null argument or count <= 0");
+  if (threads != 0 && threads != 512 && threads != 1024) return fail(EGFEM_ERR_ARG, "threads must be 512 or 1024");
+  if (weight_exp < 0.0 || weight_exp > 4.0) return fail(EGFEM_ERR_ARG, "weight_exp out of range");
+  egfem_newton_opts opts;
+  egfem_newton_opts_default(&opts);
+  if (o) opts = *o;
+  if (!(opts.tol >= 0.0) || opts.max_newton < 0 || opts.max_krylov < 1 || !(opts.krylov_rtol > 0.0) ||
+      !(opts.eta_max > 0.0 && opts.eta_max < 1.0) || opts.max_backtracks < 0)
+    return fail(EGFEM_ERR_ARG, "invalid Newton options");
+  for (int m = 0; m < count; ++m) {
+    if (!Ts[m] || !us[m]) return fail(EGFEM_ERR_ARG, "null handle or solution buffer");
+    for (int q = 0; q < m; ++q)
+      if (Ts[q] == Ts[m]) return fail(EGFEM_ERR_ARG, "a handle appears twice in the batch");
+  }
+  egfem_batch_s* B = new egfem_batch_s();
+  B->count = count;
+  B->NT = threads ? threads : 512;
+  B->Ts.assign(Ts, Ts + count);
+  int L = 4;
+  for (int m = 0; m < count; ++m) L = std::max(L, Ts[m]->krylov_lanes);
+  B->L = L;
+  const int cap = B->NT == 1024 ? cap_T<1024>(L) : cap_T<512>(L);
+  if (cap < count) {
+    free_batch(B);
+    return fail(EGFEM_ERR_SHAPE, "more instances than co-resident workgroups");
+  }
+  // team sizes: share of the resident workgroups ~ slots^weight_exp, at least 1,
+  // at most one member per row block and 256 members
+  const double ex = weight_exp > 0.0 ? weight_exp : 1.5;
+  std::vector<double> w(count);
+  double wsum = 0.0;
+  for (int m = 0; m < count; ++m) wsum += (w[m] = std::pow((double)Ts[m]->slots, ex));
+  std::vector<int> g(count);
+  int total = 0;
+  for (int m = 0; m < count; ++m) {
+    const int lim = (int)std::min<int64_t>(Ts[m]->row_blocks, 256);
+    g[m] = std::max(1, std::min(lim, (int)std::floor(cap * w[m] / wsum)));
+    total += g[m];
+  }
+  while (total > cap) {   // shrink the largest teams
+    int mx = 0;
+    for (int m = 1; m < count; ++m) if (g[m] > g[mx]) mx = m;
+    --g[mx];
+    --total;
+  }
+  B->team = g;
+  B->G = total;
+
+  // per-instance workspaces and descriptors
+  std::vector<Inst> hi(count);
+  std::vector<int32_t> wg2inst, wgblk;
+  std::vector<int> wgblk_off(count);
+  int first = 0;
+  for (int m = 0; m < count; ++m) {
+    egfem_tensor_s* T = Ts[m];
+    int rc = ensure_workspace(T);
+    if (rc != EGFEM_OK) {
+      free_batch(B);
+      return rc;
+    }
+    std::vector<int32_t> hblk(T->row_blocks + 1);
+    if (hipMemcpy(hblk.data(), T->blk_row, hblk.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) {
+      free_batch(B);
+      return fail(EGFEM_ERR_HIP, "copy of row blocks failed");
+    }
+    std::vector<int32_t> part;
+    split_blocks(T, hblk, g[m], part);
+    wgblk_off[m] = (int)wgblk.size();
+    wgblk.insert(wgblk.end(), part.begin(), part.end());
+    for (int q = 0; q < g[m]; ++q) wg2inst.push_back(m);
+    Workspace& W = T->ws;
+    Inst& I = hi[m];
+    I.tv = view_of(T);
+    I.a0 = ps[m].a0;
+    I.a0c = ps[m].a0_const;
+    I.load = ps[m].load;
+    I.dir = ps[m].dirichlet;
+    I.addK = ps[m].add_stiffness;
+    I.u = us[m];
+    I.utry = W.utry;
+    I.F = W.F;
+    I.jval = W.jval;
+    I.dinv = W.dinv;
+    dev::KArgs& K = I.K;
+    K.n = T->n;
+    K.rowptr = T->rowptr;
+    K.col = T->col;
+    K.val = W.jval;
+    K.perm = nullptr;
+    K.dinv = W.dinv;
+    K.rhs = W.F;
+    K.rhs_scale = -1.0;
+    K.x = W.delta;
+    K.x_zero = 1;
+    K.r = W.r;
+    K.rhat = W.rhat;
+    K.p = W.p;
+    K.v = W.v;
+    K.s = W.s;
+    K.t = W.t;
+    K.z = W.z;
+    K.phat = W.phat;
+    K.rh = W.rh;
+    K.vh = W.vh;
+    K.rtol = opts.krylov_rtol;
+    K.max_iter = opts.max_krylov;
+    I.team_first = first;
+    I.team_size = g[m];
+    first += g[m];
+  }
+  // batch buffers
+  B->ctrl_words = (size_t)count * 512;
+  size_t red_words = 0;
+  std::vector<size_t> red_off(count);
+  for (int m = 0; m < count; ++m) {
+    red_off[m] = red_words;
+    red_words += (size_t)kRedSlots * dev::kMaxRed * g[m];
+  }
+  bool ok = hipMalloc((void**)&B->d_insts, count * sizeof(Inst)) == hipSuccess &&
+            hipMalloc((void**)&B->d_wg2inst, wg2inst.size() * 4) == hipSuccess &&
+            hipMalloc((void**)&B->d_wgblk, wgblk.size() * 4) == hipSuccess &&
+            hipMalloc((void**)&B->d_ctrl, B->ctrl_words * 4) == hipSuccess &&
+            hipMalloc((void**)&B->d_red, red_words * 8) == hipSuccess &&
+            hipMalloc((void**)&B->d_stats, (size_t)count * kStatsWords * 8) == hipSuccess &&
+            hipHostMalloc((void**)&B->h_stats, (size_t)count * kStatsWords * 8, 0) == hipSuccess;
+  if (!ok) {
+    free_batch(B);
+    return fail(EGFEM_ERR_OOM, "batch buffers");
+  }
+  for (int m = 0; m < count; ++m) {
+    hi[m].wgblk = B->d_wgblk + wgblk_off[m];
+    hi[m].ctrl = B->d_ctrl + (size_t)m * 512;
+    hi[m].red = B->d_red + red_off[m];
+    hi[m].stats = B->d_stats + (size_t)m * kStatsWords;
+  }
+  ok = hipMemcpy(B->d_insts, hi.data(), count * sizeof(Inst), hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(B->d_wg2inst, wg2inst.data(), wg2inst.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(B->d_wgblk, wgblk.data(), wgblk.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+  if (!ok) {
+    free_batch(B);
+    return fail(EGFEM_ERR_HIP, "upload of batch descriptors failed");
+  }
+  B->opts.tol = opts.tol;
+  B->opts.max_newton = opts.max_newton;
+  B->opts.max_krylov = opts.max_krylov;
+  B->opts.krylov_rtol = opts.krylov_rtol;
+  B->opts.forcing = opts.forcing;
+  B->opts.eta_max = opts.eta_max;
+  B->opts.max_backtracks = opts.max_backtracks;
+  *out = B;
+  return EGFEM_OK;
+}
+
+// One run: zero the control words (fill kernel, graph-safe), the persistent
+// launch, statistics to pinned host memory.
+static int batch_enqueue(egfem_batch_t B, int zero_init, hipStream_t st) {
+  using namespace egfem;
+  EGFEM_HIP_CHECK(launch_fill_u32(B->d_ctrl, 0u, (int64_t)B->ctrl_words, st));
+  BatchOpts O = B->opts;
+  O.zero_init = zero_init ? 1 : 0;
+  const hipError_t e = B->NT == 1024 ? launch_T<1024>(B->L, B->d_insts, B->d_wg2inst, O, (unsigned)B->G, st)
+                                     : launch_T<512>(B->L, B->d_insts, B->d_wg2inst, O, (unsigned)B->G, st);
+  if (e != hipSuccess) return fail(EGFEM_ERR_HIP, std::string("batched launch failed: ") + hipGetErrorString(e));
+  EGFEM_HIP_CHECK(hipMemcpyAsync(B->h_stats, B->d_stats, (size_t)B->count * kStatsWords * 8,
+                                 hipMemcpyDeviceToHost, st));
+  return EGFEM_OK;
+}
+
+int egfem_batch_run(egfem_batch_t B, int zero_init, void* stream) {
+  if (!B) return egfem::fail(EGFEM_ERR_ARG, "null batch");
+  return batch_enqueue(B, zero_init, (hipStream_t)stream);
+}
+
+int egfem_batch_graph_run(egfem_batch_t B, int zero_init, void* stream) {
+  using namespace egfem;
+  if (!B) return fail(EGFEM_ERR_ARG, "null batch");
+  hipStream_t st = (hipStream_t)stream;
+  if (!B->exec || B->graph_zero_init != (zero_init ? 1 : 0)) {
+    if (B->exec) hipGraphExecDestroy(B->exec);
+    if (B->graph) hipGraphDestroy(B->graph);
+    B->exec = nullptr;
+    B->graph = nullptr;
+    // capture on a plan-owned stream (the caller's may be the legacy null
+    // stream, which cannot be captured); the graph is launched on `stream`
+    if (!B->cap_stream) EGFEM_HIP_CHECK(hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking));
+    EGFEM_HIP_CHECK(hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal));
+    const int rc = batch_enqueue(B, zero_init, B->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(B->cap_stream, &g);
+    if (rc != EGFEM_OK) {
+      if (g) hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(EGFEM_ERR_HIP, std::string("graph capture failed: ") + hipGetErrorString(e));
+    B->graph = g;
+    EGFEM_HIP_CHECK(hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0));
+    B->graph_zero_init = zero_init ? 1 : 0;
+  }
+  EGFEM_HIP_CHECK(hipGraphLaunch(B->exec, st));
+  return EGFEM_OK;
+}
+
+int egfem_batch_stats(egfem_batch_t B, egfem_newton_stats* stats, void* stream) {
+  using namespace egfem;
+  if (!B) return fail(EGFEM_ERR_ARG, "null batch");
+  EGFEM_HIP_CHECK(hipStreamSynchronize((hipStream_t)stream));
+  int worst = EGFEM_OK;
+  for (int m = 0; m < B->count; ++m) {
+    const double* s = B->h_stats + (size_t)m * kStatsWords;
+    const int status = (int)s[0];
+    if (status == EGFEM_ERR_HIP) return fail(EGFEM_ERR_HIP, "batched Newton: a team barrier timed out");
+    worst = std::max(worst, status);
+    if (!stats) continue;
+    egfem_newton_stats& o = stats[m];
+    std::memset(&o, 0, sizeof(o));
+    o.status = status;
+    o.newton_iters = (int)s[1];
+    o.krylov_iters = (int)s[2];
+    o.backtracks = (int)s[3];
+    o.res0 = s[4];
+    o.res = s[5];
+    for (int k = 0; k < EGFEM_HIST && k < o.newton_iters; ++k) {
+      o.res_hist[k] = s[6 + k];
+      o.krylov_hist[k] = (int)s[6 + EGFEM_HIST + k];
+    }
+  }
+  return worst;
+}
+
+int egfem_batch_teams(egfem_batch_t B, int* team_sizes, int* total_workgroups) {
+  if (!B) return egfem::fail(EGFEM_ERR_ARG, "null batch");
+  if (team_sizes)
+    for (int m = 0; m < B->count; ++m) team_sizes[m] = B->team[m];
+  if (total_workgroups) *total_workgroups = B->G;
+  return EGFEM_OK;
+}
+
+void egfem_batch_destroy(egfem_batch_t B) { free_batch(B); }
+
+int egfem_newton_batched(int count, const egfem_tensor_t* Ts, const egfem_problem* ps, double* const* us,
+                         const egfem_newton_opts* o, egfem_newton_stats* stats, void* stream) {
+  egfem_batch_t B = nullptr;
+  int rc = egfem_batch_create(count, Ts, ps, us, o, o ? o->krylov_threads : 0, 0.0, &B);
+  if (rc != EGFEM_OK) return rc;
+  rc = egfem_batch_run(B, 0, stream);
+  if (rc == EGFEM_OK) rc = egfem_batch_stats(B, stats, stream);
+  egfem_batch_destroy(B);
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,508 @@
+// Device building blocks shared by the single-instance kernels and the
+// batched persistent Newton kernel:
+//   * row-block tensor stages (residual action, Jacobian emission),
+//   * team barrier and deterministic team reductions,
+//   * the Jacobi-BiCGStab iteration run by a team of workgroups.
+// A "team" is a set of co-resident workgroups that synchronise among
+// themselves only (one team = the whole grid for a single solve; one team per
+// instance in the batched kernel).
+#pragma once
+
+#include "egfem_internal.h"
+
+namespace egfem {
+namespace dev {
+
+constexpr int kWave = 64;
+constexpr unsigned kSpinCap = 1u << 24;   // bounded waits: a barrier that never completes aborts
+constexpr int kGroups = 8;                // arrival groups (one per XCD under round-robin dispatch)
+// control block (unsigned words, one 128-byte line each): epoch, global
+// arrivals, abort flag, then one arrival counter per group.
+constexpr int kCtrlGen = 0, kCtrlAll = 32, kCtrlAbort = 64, kCtrlGroup = 96;
+constexpr int kCtrlWords = kCtrlGroup + 32 * kGroups;
+static_assert(kCtrlWords <= kCtrlWordsMax, "barrier control block too small");
+constexpr int kMaxRed = 8;                // values per reduction
+
+// Agent-coherent accessors for data exchanged between workgroups.
+__device__ __forceinline__ double ld_sh(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_sh(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <bool SH>
+__device__ __forceinline__ double ld(const double* p) {
+  return SH ? ld_sh(p) : *p;
+}
+
+// ---------------------------------------------------------------------------
+// Tensor view and row-block stages
+// ---------------------------------------------------------------------------
+struct TensorView {
+  int64_t n;
+  int64_t nblk;
+  int sym;
+  const int32_t* blk_row;
+  const int32_t* rowptr;
+  const int32_t* col;
+  const int32_t* kptrA;
+  const int32_t* kA;
+  const double* vA;
+  const int32_t* jptrB;
+  const int32_t* jB;
+  const double* vB;
+  const double* kval;
+};
+
+// LDS scratch of the row-block stages.
+struct RowBlockLds {
+  double tA[kCapNnz];
+  double tB[kCapNnz];
+  double y[kCapSlots];
+  int scol[kCapSlots];
+  int spa[kCapSlots + 1];
+  int spb[kCapSlots + 1];
+};
+
+// Tensor action over row block b with NT threads:
+//   r_i = sum_{s in row i} w_col(s) * (sum_{p in A(s)} v_p a_{k_p} [+ K_s])
+//   RAW:     a given;                                     out = r
+//   PROBLEM: a = a0 + w^2, w = u + alpha delta (delta may be null);
+//            out = F = r - load, Dirichlet rows 0; uout (optional) = w;
+//            sq += F_i^2 over the rows this thread handled.
+// SH: u, delta gathered with agent-coherent loads and uout written with
+// agent-coherent stores (data produced by other workgroups of the same launch).
+template <int NT, bool PROBLEM, bool SH>
+__device__ void rowblock_action(const TensorView& T, int64_t b, const double* u, const double* delta,
+                                double alpha, const double* a, double a0c, const double* load,
+                                const uint8_t* dir, const double* kval, double* out, double* uout,
+                                double& sq, RowBlockLds& L) {
+  const int tid = threadIdx.x;
+  const int r0 = T.blk_row[b], r1 = T.blk_row[b + 1];
+  const int s0 = T.rowptr[r0], s1 = T.rowptr[r1];
+  const int p0 = T.kptrA[s0], p1 = T.kptrA[s1];
+  for (int p = p0 + tid; p < p1; p += NT) {
+    const int k = T.kA[p];
+    double ak;
+    if (PROBLEM) {
+      double wk = ld<SH>(u + k);
+      if (delta) wk = fma(alpha, ld<SH>(delta + k), wk);
+      ak = fma(wk, wk, a ? a[k] : a0c);
+    } else {
+      ak = a[k];
+    }
+    L.tA[p - p0] = T.vA[p] * ak;
+  }
+  __syncthreads();
+  for (int s = s0 + tid; s < s1; s += NT) {
+    const int q0 = T.kptrA[s] - p0, q1 = T.kptrA[s + 1] - p0;
+    double q = 0.0;
+    for (int t = q0; t < q1; ++t) q += L.tA[t];
+    const int j = T.col[s];
+    double wj = ld<SH>(u + j);
+    if (PROBLEM) {
+      if (delta) wj = fma(alpha, ld<SH>(delta + j), wj);
+      if (kval) q += kval[s];
+    }
+    L.y[s - s0] = q * wj;
+  }
+  __syncthreads();
+  for (int i = r0 + tid; i < r1; i += NT) {
+    const int q0 = T.rowptr[i] - s0, q1 = T.rowptr[i + 1] - s0;
+    double acc = 0.0;
+    for (int t = q0; t < q1; ++t) acc += L.y[t];
+    if (PROBLEM) {
+      if (load) acc -= load[i];
+      const bool d = dir && dir[i];
+      if (d) acc = 0.0;
+      if (uout) {
+        double wi = ld<SH>(u + i);
+        if (delta) wi = fma(alpha, ld<SH>(delta + i), wi);
+        wi = d ? 0.0 : wi;
+        if (SH) st_sh(uout + i, wi);
+        else uout[i] = wi;
+      }
+      sq = fma(acc, acc, sq);
+    }
+    out[i] = acc;
+  }
+  __syncthreads();   // LDS is reused by the next block
+}
+
+// Jacobian emission over row block b with NT threads:
+//   J_s = [K_s] + sum_{p in A(s)} v_p a_{k_p} + g_j sum_{p in B(s)} v_p u_{j_p},
+// s = (i, j), a = a0 + u^2 (problem_a) or given, g = dadu or 2u (dadu_2u) or none.
+// Dirichlet rows -> identity rows, Dirichlet columns -> 0; dinv[i] = 1 / J_ii.
+template <int NT, bool SH>
+__device__ void rowblock_jacobian(const TensorView& T, int64_t b, const double* u, const double* a,
+                                  const double* a0, double a0c, int problem_a, const double* dadu,
+                                  int dadu_2u, const double* kval, const uint8_t* dir, double* jval,
+                                  double* dinv, RowBlockLds& L) {
+  const int tid = threadIdx.x;
+  const int r0 = T.blk_row[b], r1 = T.blk_row[b + 1];
+  const int s0 = T.rowptr[r0], s1 = T.rowptr[r1];
+  const int pa0 = T.kptrA[s0], pa1 = T.kptrA[s1];
+  const int pb0 = T.jptrB[s0], pb1 = T.jptrB[s1];
+  const bool second = dadu || dadu_2u;
+  for (int p = pa0 + tid; p < pa1; p += NT) {
+    const int k = T.kA[p];
+    const double uk = ld<SH>(u + k);
+    const double ak = problem_a ? fma(uk, uk, a0 ? a0[k] : a0c) : a[k];
+    const double v = T.vA[p];
+    L.tA[p - pa0] = v * ak;
+    if (T.sym && second) L.tB[p - pa0] = v * uk;
+  }
+  if (!T.sym && second)
+    for (int p = pb0 + tid; p < pb1; p += NT) L.tB[p - pb0] = T.vB[p] * ld<SH>(u + T.jB[p]);
+  for (int s = s0 + tid; s <= s1; s += NT) {
+    L.spa[s - s0] = T.kptrA[s] - pa0;
+    L.spb[s - s0] = T.jptrB[s] - pb0;
+    if (s < s1) {
+      L.scol[s - s0] = T.col[s];
+      L.y[s - s0] = kval ? kval[s] : 0.0;
+    }
+  }
+  __syncthreads();
+  for (int i = r0 + tid; i < r1; i += NT) {
+    const bool drow = dir && dir[i];
+    for (int s = T.rowptr[i] - s0; s < T.rowptr[i + 1] - s0; ++s) {
+      const int j = L.scol[s];
+      double J;
+      if (drow) {
+        J = (j == i) ? 1.0 : 0.0;
+      } else if (dir && dir[j]) {
+        J = 0.0;
+      } else {
+        double qa = 0.0;
+        for (int t = L.spa[s]; t < L.spa[s + 1]; ++t) qa += L.tA[t];
+        J = L.y[s] + qa;
+        if (second) {
+          double qb = 0.0;
+          for (int t = L.spb[s]; t < L.spb[s + 1]; ++t) qb += L.tB[t];
+          const double g = dadu ? dadu[j] : 2.0 * ld<SH>(u + j);
+          J = fma(g, qb, J);
+        }
+      }
+      L.y[s] = J;
+      if (j == i && dinv) dinv[i] = 1.0 / J;
+    }
+  }
+  __syncthreads();
+  for (int s = s0 + tid; s < s1; s += NT) jval[s] = L.y[s - s0];
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Team barrier and reductions
+// ---------------------------------------------------------------------------
+struct Team {
+  unsigned rank;      // this workgroup's index within the team
+  unsigned size;      // workgroups in the team
+  unsigned* ctrl;     // kCtrlWords control words (zero before the launch)
+  double* red;        // reduction slots [kRedSlots][kMaxRed][size]; 0-7 Krylov, 8-9 Newton
+  unsigned epoch;     // barriers passed so far
+};
+
+// Epoch-counting barrier (no counter resets).  Every wave first waits until
+// its own stores are complete (s_waitcnt vmcnt(0)); data exchanged between
+// workgroups is written and read with agent-coherent accesses, so no cache
+// write-back or invalidation is needed.  Arrivals are counted per group, the
+// last of each group arrives at the team counter, the last team arrival
+// publishes the new epoch, everyone else polls it.  Returns true when the team
+// aborted (a wait exceeded kSpinCap).
+__device__ inline bool team_barrier(Team& tm, int* sh_abort) {
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's stores are complete
+  __syncthreads();
+  const unsigned epoch = tm.epoch++;
+  if (threadIdx.x == 0) {
+    unsigned* ctrl = tm.ctrl;
+    const unsigned G = tm.size;
+    const unsigned ng = G < (unsigned)kGroups ? G : (unsigned)kGroups;
+    const unsigned grp = tm.rank % ng;
+    const unsigned gsz = (G - grp + ng - 1) / ng;   // ranks r < G with r % ng == grp
+    int ab = (int)__hip_atomic_load(ctrl + kCtrlAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!ab) {
+      const unsigned prev = __hip_atomic_fetch_add(ctrl + kCtrlGroup + 32 * grp, 1u, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+      bool last = false;
+      if (prev == (epoch + 1) * gsz - 1) {
+        const unsigned prev2 = __hip_atomic_fetch_add(ctrl + kCtrlAll, 1u, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+        last = (prev2 == (epoch + 1) * ng - 1);
+      }
+      if (last) {
+        __hip_atomic_store(ctrl + kCtrlGen, epoch + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        unsigned spins = 0;
+        while (__hip_atomic_load(ctrl + kCtrlGen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= epoch) {
+          __builtin_amdgcn_s_sleep(1);
+          if (++spins >= kSpinCap) {
+            __hip_atomic_store(ctrl + kCtrlAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ab = 1;
+            break;
+          }
+          if ((spins & 1023u) == 0 &&
+              __hip_atomic_load(ctrl + kCtrlAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            ab = 1;
+            break;
+          }
+        }
+      }
+    }
+    *sh_abort = ab;
+  }
+  __syncthreads();
+  return *sh_abort != 0;
+}
+
+// Deterministic block sum of up to kMaxRed values; results broadcast to all threads.
+template <int NT>
+__device__ void block_sum(double (&v)[kMaxRed], int m, double* sh) {
+  constexpr int NW = NT / kWave;
+  for (int q = 0; q < m; ++q) {
+    double x = v[q];
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_down(x, off, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) sh[q * NW + threadIdx.x / kWave] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < (unsigned)m) {
+    double acc = 0.0;
+    for (int w = 0; w < NW; ++w) acc += sh[threadIdx.x * NW + w];
+    sh[kMaxRed * NW + threadIdx.x] = acc;
+  }
+  __syncthreads();
+  for (int q = 0; q < m; ++q) v[q] = sh[kMaxRed * NW + q];
+  __syncthreads();
+}
+
+template <int NT>
+constexpr int kShWords = kMaxRed * (NT / kWave) + kMaxRed;
+
+// Publish this workgroup's block sums into reduction slot `slot`, pass the
+// team barrier, then add the team's partials of every value in a fixed order.
+template <int NT>
+__device__ bool team_reduce(Team& tm, int slot, double (&v)[kMaxRed], int m, double* sh,
+                            int* sh_abort) {
+  const unsigned G = tm.size;
+  block_sum<NT>(v, m, sh);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < m; ++q) st_sh(tm.red + ((size_t)slot * kMaxRed + q) * G + tm.rank, v[q]);
+  if (team_barrier(tm, sh_abort)) return true;
+  double w[kMaxRed];
+  for (int q = 0; q < m; ++q) {
+    const double* src = tm.red + ((size_t)slot * kMaxRed + q) * G;
+    double acc = 0.0;
+    for (unsigned g = threadIdx.x; g < G; g += NT) acc += ld_sh(src + g);
+    w[q] = acc;
+  }
+  block_sum<NT>(w, m, sh);
+  for (int q = 0; q < m; ++q) v[q] = w[q];
+  return false;
+}
+
+// ---------------------------------------------------------------------------
+// Jacobi-BiCGStab run by a team
+// ---------------------------------------------------------------------------
+struct KArgs {
+  int64_t n;
+  const int32_t* rowptr;
+  const int32_t* col;
+  const double* val;
+  const int32_t* perm;      // non-null: use val[perm[s]] (transposed operator)
+  const double* dinv;
+  const double* rhs;        // b = rhs_scale * rhs (own rows)
+  double rhs_scale;
+  double* x;                // written with agent-coherent stores
+  int x_zero;
+  double *r, *rhat, *p, *v, *s, *t, *z;     // row-local
+  double *phat, *rh, *vh;                   // gathered by other workgroups (agent-coherent)
+  double rtol;
+  int max_iter;
+};
+
+struct KOut {
+  int status;
+  int iters;
+  double rnorm;
+  double bnorm;
+  bool abort;
+};
+
+// Rows [rb, re), L lanes per row: f(i, (J x1)_i, (J x2)_i) on lane 0 of each
+// row's group (x2 may be null); x1 / x2 gathered coherently when SH.
+template <int NT, int L, bool SH, typename Fn>
+__device__ __forceinline__ void spmv_rows(const KArgs& A, int rb, int re, const double* __restrict__ x1,
+                                          const double* __restrict__ x2, Fn f) {
+  constexpr int RPP = NT / L;
+  const int sub = threadIdx.x / L;
+  const int lane = threadIdx.x % L;
+  for (int base = rb; base < re; base += RPP) {
+    const int i = base + sub;
+    double acc1 = 0.0, acc2 = 0.0;
+    if (i < re) {
+      const int e = A.rowptr[i + 1];
+      for (int s = A.rowptr[i] + lane; s < e; s += L) {
+        const double a = A.perm ? A.val[A.perm[s]] : A.val[s];
+        const int c = A.col[s];
+        acc1 = fma(a, ld<SH>(x1 + c), acc1);
+        if (x2) acc2 = fma(a, ld<SH>(x2 + c), acc2);
+      }
+    }
+#pragma unroll
+    for (int off = L / 2; off > 0; off >>= 1) {
+      acc1 += __shfl_xor(acc1, off, L);
+      acc2 += __shfl_xor(acc2, off, L);
+    }
+    if (i < re && lane == 0) f(i, acc1, acc2);
+  }
+}
+
+// Preconditioned BiCGStab (van der Vorst) with D = diag(J), the product
+// t = J D^-1 s formed as z - alpha y (z = J D^-1 r fused with v = J D^-1 p,
+// y = J D^-1 v), three team barriers per iteration:
+//   A: v = J phat, z = J rh            -> (rhat, v)
+//   B: y = J vh; s = r - alpha v; t = z - alpha y
+//                                       -> (t,s) (t,t) (rhat,s) (rhat,t) (s,s)
+//   C: omega; x += alpha phat + omega D^-1 s; r = s - omega t;
+//      rho' = (rhat,s) - omega (rhat,t); beta; p; phat = D^-1 p; rh = D^-1 r -> (r,r)
+template <int NT, int L>
+__device__ KOut team_bicgstab(Team& tm, const KArgs& A, int rb, int re, double* sh, int* sh_abort) {
+  const int tid = threadIdx.x;
+  double red[kMaxRed];
+  KOut o{EGFEM_NOT_CONVERGED, 0, 0.0, 0.0, false};
+#define EGFEM_ZERO_RED() for (int q_ = 0; q_ < kMaxRed; ++q_) red[q_] = 0.0
+  EGFEM_ZERO_RED();
+  if (A.x_zero) {
+    for (int i = rb + tid; i < re; i += NT) {
+      const double bi = A.rhs_scale * A.rhs[i];
+      const double di = A.dinv[i] * bi;
+      st_sh(A.x + i, 0.0);
+      A.r[i] = bi;
+      A.rhat[i] = bi;
+      A.p[i] = bi;
+      st_sh(A.phat + i, di);
+      st_sh(A.rh + i, di);
+      red[0] = fma(bi, bi, red[0]);
+      red[1] = fma(bi, bi, red[1]);
+    }
+  } else {
+    spmv_rows<NT, L, false>(A, rb, re, A.x, nullptr, [&](int i, double Jx, double) {
+      const double bi = A.rhs_scale * A.rhs[i];
+      const double ri = bi - Jx;
+      const double di = A.dinv[i] * ri;
+      A.r[i] = ri;
+      A.rhat[i] = ri;
+      A.p[i] = ri;
+      st_sh(A.phat + i, di);
+      st_sh(A.rh + i, di);
+      red[0] = fma(ri, ri, red[0]);
+      red[1] = fma(bi, bi, red[1]);
+    });
+  }
+  o.abort = team_reduce<NT>(tm, 0, red, 2, sh, sh_abort);
+  double rho = red[0];
+  double rnorm = sqrt(red[0]);
+  const double bnorm = sqrt(red[1]);
+  const double r0norm = rnorm;
+  int restarts = 0;
+  int slot = 1;
+  int it = 0;
+  if (!o.abort && bnorm == 0.0) {
+    for (int i = rb + tid; i < re; i += NT) st_sh(A.x + i, 0.0);
+    o.status = EGFEM_OK;
+    rnorm = 0.0;
+  } else {
+    while (!o.abort) {
+      if (!isfinite(rnorm) || !isfinite(rho)) { o.status = EGFEM_NONFINITE; break; }
+      if (rnorm <= A.rtol * bnorm) { o.status = EGFEM_OK; break; }
+      if (it >= A.max_iter) { o.status = EGFEM_NOT_CONVERGED; break; }
+      if (fabs(rho) <= 1e-15 * r0norm * rnorm) {
+        // lost bi-orthogonality: restart once from the current residual
+        if (restarts++ >= 1) { o.status = EGFEM_BREAKDOWN; break; }
+        EGFEM_ZERO_RED();
+        for (int i = rb + tid; i < re; i += NT) {
+          const double ri = A.r[i];
+          A.rhat[i] = ri;
+          A.p[i] = ri;
+          st_sh(A.phat + i, ld_sh(A.rh + i));
+          red[0] = fma(ri, ri, red[0]);
+        }
+        if ((o.abort = team_reduce<NT>(tm, 7, red, 1, sh, sh_abort))) break;
+        rho = red[0];
+        continue;
+      }
+      // A: v = J phat, z = J rh ; (rhat, v)
+      EGFEM_ZERO_RED();
+      spmv_rows<NT, L, true>(A, rb, re, A.phat, A.rh, [&](int i, double vi, double zi) {
+        A.v[i] = vi;
+        A.z[i] = zi;
+        st_sh(A.vh + i, A.dinv[i] * vi);
+        red[0] = fma(A.rhat[i], vi, red[0]);
+      });
+      if ((o.abort = team_reduce<NT>(tm, slot, red, 1, sh, sh_abort))) break;
+      slot = slot % 6 + 1;
+      const double rv = red[0];
+      if (rv == 0.0 || !isfinite(rv)) { o.status = isfinite(rv) ? EGFEM_BREAKDOWN : EGFEM_NONFINITE; break; }
+      const double alpha = rho / rv;
+      // B: y = J vh ; s, t
+      EGFEM_ZERO_RED();
+      spmv_rows<NT, L, true>(A, rb, re, A.vh, nullptr, [&](int i, double yi, double) {
+        const double si = fma(-alpha, A.v[i], A.r[i]);
+        const double ti = fma(-alpha, yi, A.z[i]);
+        const double hi = A.rhat[i];
+        A.s[i] = si;
+        A.t[i] = ti;
+        red[0] = fma(ti, si, red[0]);
+        red[1] = fma(ti, ti, red[1]);
+        red[2] = fma(hi, si, red[2]);
+        red[3] = fma(hi, ti, red[3]);
+        red[4] = fma(si, si, red[4]);
+      });
+      if ((o.abort = team_reduce<NT>(tm, slot, red, 5, sh, sh_abort))) break;
+      slot = slot % 6 + 1;
+      ++it;
+      if (sqrt(red[4]) <= A.rtol * bnorm) {
+        for (int i = rb + tid; i < re; i += NT) st_sh(A.x + i, fma(alpha, ld_sh(A.phat + i), ld_sh(A.x + i)));
+        rnorm = sqrt(red[4]);
+        o.status = EGFEM_OK;
+        break;
+      }
+      if (red[1] == 0.0 || !isfinite(red[1])) {
+        o.status = isfinite(red[1]) ? EGFEM_BREAKDOWN : EGFEM_NONFINITE;
+        break;
+      }
+      const double omega = red[0] / red[1];
+      if (omega == 0.0) { o.status = EGFEM_BREAKDOWN; break; }
+      const double rho_new = fma(-omega, red[3], red[2]);
+      const double beta = (rho_new / rho) * (alpha / omega);
+      rho = rho_new;
+      // C: x, r, p, phat, rh ; (r, r)
+      EGFEM_ZERO_RED();
+      for (int i = rb + tid; i < re; i += NT) {
+        const double di = A.dinv[i];
+        const double si = A.s[i];
+        const double xi = fma(alpha, ld_sh(A.phat + i), fma(omega, di * si, ld_sh(A.x + i)));
+        const double ri = fma(-omega, A.t[i], si);
+        const double pi = fma(beta, fma(-omega, A.v[i], A.p[i]), ri);
+        st_sh(A.x + i, xi);
+        A.r[i] = ri;
+        A.p[i] = pi;
+        st_sh(A.phat + i, di * pi);
+        st_sh(A.rh + i, di * ri);
+        red[0] = fma(ri, ri, red[0]);
+      }
+      if ((o.abort = team_reduce<NT>(tm, slot, red, 1, sh, sh_abort))) break;
+      slot = slot % 6 + 1;
+      rnorm = sqrt(red[0]);
+    }
+  }
+#undef EGFEM_ZERO_RED
+  o.iters = it;
+  o.rnorm = rnorm;
+  o.bnorm = bnorm;
+  return o;
+}
+
+}  // namespace dev
+}  // namespace egfem

@@ -10,7 +10,7 @@
 //   stage 3  row-parallel sums over the row's slots out of LDS.
 // Every sum runs in a fixed order, so results are bitwise reproducible.  The
 // path moves ~0.15 flop per byte and is bound by HBM bandwidth; no MFMA.
-#include "egfem_internal.h"
+#include "egfem_device.h"
 
 namespace egfem {
 namespace {
@@ -41,152 +41,69 @@ __device__ __forceinline__ double block_sum256(double v, double* sh4) {
   return r;
 }
 
-// r_i = sum_{s in row i} (u_col(s) * sum_{p in A(s)} v_p a_{k_p})
-//   RAW:      a given;                        out = r
-//   PROBLEM:  a = a0 + w^2, w = u + alpha*delta (trial iterate when delta != 0);
-//             out = F = r + K w - load, Dirichlet rows 0; partial[b] = sum F_i^2;
-//             uout (optional) = w.
-template <bool PROBLEM>
-__global__ __launch_bounds__(kBlockThreads) void k_action(
-    const int32_t* __restrict__ blk_row, int64_t nblk, const int32_t* __restrict__ rowptr,
-    const int32_t* __restrict__ col, const int32_t* __restrict__ kptr,
-    const int32_t* __restrict__ kidx, const double* __restrict__ val, const double* __restrict__ u,
-    const double* __restrict__ delta, double alpha, const double* __restrict__ a, double a0c,
-    const double* __restrict__ load, const uint8_t* __restrict__ dir,
-    const double* __restrict__ kval, double* __restrict__ out, double* __restrict__ uout,
-    double* __restrict__ partial) {
-  __shared__ double t_lds[kCapNnz];
-  __shared__ double y_lds[kCapSlots];
-  __shared__ double sh4[4];
-  const int64_t b = xcd_block(blockIdx.x, nblk);
-  if (b < 0) return;
-  const int tid = threadIdx.x;
-  const int r0 = blk_row[b], r1 = blk_row[b + 1];
-  const int s0 = rowptr[r0], s1 = rowptr[r1];
-  const int p0 = kptr[s0], p1 = kptr[s1];
+}  // namespace
 
-  for (int p = p0 + tid; p < p1; p += kBlockThreads) {
-    const int k = kidx[p];
-    double ak;
-    if (PROBLEM) {
-      double wk = u[k];
-      if (delta) wk = fma(alpha, delta[k], wk);
-      ak = fma(wk, wk, a ? a[k] : a0c);
-    } else {
-      ak = a[k];
-    }
-    t_lds[p - p0] = val[p] * ak;
-  }
-  __syncthreads();
-  for (int s = s0 + tid; s < s1; s += kBlockThreads) {
-    const int q0 = kptr[s] - p0, q1 = kptr[s + 1] - p0;
-    double q = 0.0;
-    for (int t = q0; t < q1; ++t) q += t_lds[t];
-    const int j = col[s];
-    double wj = u[j];
-    if (PROBLEM) {
-      if (delta) wj = fma(alpha, delta[j], wj);
-      if (kval) q += kval[s];
-    }
-    y_lds[s - s0] = q * wj;
-  }
-  __syncthreads();
+dev::TensorView view_of(const egfem_tensor_s* T) {
+  dev::TensorView v;
+  v.n = T->n;
+  v.nblk = T->row_blocks;
+  v.sym = T->symmetric;
+  v.blk_row = T->blk_row;
+  v.rowptr = T->rowptr;
+  v.col = T->col;
+  v.kptrA = T->kptrA;
+  v.kA = T->kA;
+  v.vA = T->vA;
+  v.jptrB = T->jptrB;
+  v.jB = T->jB;
+  v.vB = T->vB;
+  v.kval = T->kval;
+  return v;
+}
+
+namespace {
+
+// Residual action over one row block per workgroup (see rowblock_action):
+//   RAW:      out = T:(u (x) a)
+//   PROBLEM:  out = F = [K w] + T:(w (x) (a0 + w^2)) - load, w = u + alpha delta,
+//             Dirichlet rows 0; partial[b] = sum F_i^2; uout (optional) = w.
+template <bool PROBLEM>
+__global__ __launch_bounds__(kBlockThreads) void k_action(dev::TensorView T, const double* __restrict__ u,
+                                                          const double* __restrict__ delta, double alpha,
+                                                          const double* __restrict__ a, double a0c,
+                                                          const double* __restrict__ load,
+                                                          const uint8_t* __restrict__ dir,
+                                                          const double* __restrict__ kval,
+                                                          double* __restrict__ out,
+                                                          double* __restrict__ uout,
+                                                          double* __restrict__ partial) {
+  __shared__ dev::RowBlockLds L;
+  __shared__ double sh4[4];
+  const int64_t b = xcd_block(blockIdx.x, T.nblk);
+  if (b < 0) return;
   double sq = 0.0;
-  for (int i = r0 + tid; i < r1; i += kBlockThreads) {
-    const int q0 = rowptr[i] - s0, q1 = rowptr[i + 1] - s0;
-    double acc = 0.0;
-    for (int t = q0; t < q1; ++t) acc += y_lds[t];
-    if (PROBLEM) {
-      if (load) acc -= load[i];
-      const bool d = dir && dir[i];
-      if (d) acc = 0.0;
-      if (uout) {
-        double wi = u[i];
-        if (delta) wi = fma(alpha, delta[i], wi);
-        uout[i] = d ? 0.0 : wi;
-      }
-      sq = fma(acc, acc, sq);
-    }
-    out[i] = acc;
-  }
+  dev::rowblock_action<kBlockThreads, PROBLEM, false>(T, b, u, delta, alpha, a, a0c, load, dir, kval,
+                                                      out, uout, sq, L);
   if (PROBLEM && partial) {
     const double tot = block_sum256(sq, sh4);
-    if (tid == 0) partial[b] = tot;
+    if (threadIdx.x == 0) partial[b] = tot;
   }
 }
 
-// J_s = [K_s] + sum_{p in A(s)} v_p a_{k_p} + g_j * sum_{p in B(s)} v_p u_{j_p},
-// s = (i, j); g_j = dadu[j] or 2 u_j.  Dirichlet rows -> identity rows,
-// Dirichlet columns -> 0.  dinv[i] = 1 / J_ii.
-__global__ __launch_bounds__(kBlockThreads) void k_jacobian(
-    const int32_t* __restrict__ blk_row, int64_t nblk, const int32_t* __restrict__ rowptr,
-    const int32_t* __restrict__ col, const int32_t* __restrict__ kptrA,
-    const int32_t* __restrict__ kA, const double* __restrict__ vA,
-    const int32_t* __restrict__ jptrB, const int32_t* __restrict__ jB,
-    const double* __restrict__ vB, int sym, const double* __restrict__ u,
-    const double* __restrict__ a, const double* __restrict__ a0, double a0c, int problem_a,
-    const double* __restrict__ dadu, int dadu_2u, const double* __restrict__ kval,
-    const uint8_t* __restrict__ dir, double* __restrict__ jval, double* __restrict__ dinv) {
-  __shared__ double tA[kCapNnz];
-  __shared__ double tB[kCapNnz];
-  __shared__ double y[kCapSlots];
-  __shared__ int scol[kCapSlots];
-  __shared__ int spa[kCapSlots + 1];
-  __shared__ int spb[kCapSlots + 1];
-  const int64_t b = xcd_block(blockIdx.x, nblk);
+// Jacobian emission over one row block per workgroup (see rowblock_jacobian).
+__global__ __launch_bounds__(kBlockThreads) void k_jacobian(dev::TensorView T, const double* __restrict__ u,
+                                                            const double* __restrict__ a,
+                                                            const double* __restrict__ a0, double a0c,
+                                                            int problem_a, const double* __restrict__ dadu,
+                                                            int dadu_2u, const double* __restrict__ kval,
+                                                            const uint8_t* __restrict__ dir,
+                                                            double* __restrict__ jval,
+                                                            double* __restrict__ dinv) {
+  __shared__ dev::RowBlockLds L;
+  const int64_t b = xcd_block(blockIdx.x, T.nblk);
   if (b < 0) return;
-  const int tid = threadIdx.x;
-  const int r0 = blk_row[b], r1 = blk_row[b + 1];
-  const int s0 = rowptr[r0], s1 = rowptr[r1];
-  const int pa0 = kptrA[s0], pa1 = kptrA[s1];
-  const int pb0 = jptrB[s0], pb1 = jptrB[s1];
-  const bool second = dadu || dadu_2u;
-
-  for (int p = pa0 + tid; p < pa1; p += kBlockThreads) {
-    const int k = kA[p];
-    const double uk = u[k];
-    const double ak = problem_a ? fma(uk, uk, a0 ? a0[k] : a0c) : a[k];
-    const double v = vA[p];
-    tA[p - pa0] = v * ak;
-    if (sym && second) tB[p - pa0] = v * uk;
-  }
-  if (!sym && second)
-    for (int p = pb0 + tid; p < pb1; p += kBlockThreads) tB[p - pb0] = vB[p] * u[jB[p]];
-  for (int s = s0 + tid; s <= s1; s += kBlockThreads) {
-    spa[s - s0] = kptrA[s] - pa0;
-    spb[s - s0] = jptrB[s] - pb0;
-    if (s < s1) {
-      scol[s - s0] = col[s];
-      y[s - s0] = kval ? kval[s] : 0.0;
-    }
-  }
-  __syncthreads();
-  for (int i = r0 + tid; i < r1; i += kBlockThreads) {
-    const bool drow = dir && dir[i];
-    for (int s = rowptr[i] - s0; s < rowptr[i + 1] - s0; ++s) {
-      const int j = scol[s];
-      double J;
-      if (drow) {
-        J = (j == i) ? 1.0 : 0.0;
-      } else if (dir && dir[j]) {
-        J = 0.0;
-      } else {
-        double qa = 0.0;
-        for (int t = spa[s]; t < spa[s + 1]; ++t) qa += tA[t];
-        J = y[s] + qa;
-        if (second) {
-          double qb = 0.0;
-          for (int t = spb[s]; t < spb[s + 1]; ++t) qb += tB[t];
-          const double g = dadu ? dadu[j] : 2.0 * u[j];
-          J = fma(g, qb, J);
-        }
-      }
-      y[s] = J;
-      if (j == i && dinv) dinv[i] = 1.0 / J;
-    }
-  }
-  __syncthreads();
-  for (int s = s0 + tid; s < s1; s += kBlockThreads) jval[s] = y[s - s0];
+  dev::rowblock_jacobian<kBlockThreads, false>(T, b, u, a, a0, a0c, problem_a, dadu, dadu_2u, kval, dir,
+                                               jval, dinv, L);
 }
 
 // q_s = sum_{p in B(s)} v_p u_{j_p}  ((T ._2 u) in slot layout), thread per slot.
@@ -264,8 +181,7 @@ inline unsigned grid1d(int64_t n, int bs = kBlockThreads) { return (unsigned)((n
 hipError_t launch_action_raw(const egfem_tensor_s* T, const double* u, const double* a, double* r,
                              hipStream_t st) {
   hipLaunchKernelGGL(k_action<false>, dim3(xcd_grid(T->row_blocks)), dim3(kBlockThreads), 0, st,
-                     T->blk_row, T->row_blocks, T->rowptr, T->col, T->kptrA, T->kA, T->vA, u,
-                     nullptr, 0.0, a, 0.0, nullptr, nullptr, nullptr, r, nullptr, nullptr);
+                     view_of(T), u, nullptr, 0.0, a, 0.0, nullptr, nullptr, nullptr, r, nullptr, nullptr);
   return hipGetLastError();
 }
 
@@ -273,9 +189,8 @@ hipError_t launch_action_problem(const egfem_tensor_s* T, const ProblemView& pv,
                                  const double* delta, double alpha, double* uout, double* F,
                                  double* partial, hipStream_t st) {
   hipLaunchKernelGGL(k_action<true>, dim3(xcd_grid(T->row_blocks)), dim3(kBlockThreads), 0, st,
-                     T->blk_row, T->row_blocks, T->rowptr, T->col, T->kptrA, T->kA, T->vA, u, delta,
-                     alpha, pv.a0, pv.a0c, pv.load, pv.dir, pv.addK ? T->kval : nullptr, F, uout,
-                     partial);
+                     view_of(T), u, delta, alpha, pv.a0, pv.a0c, pv.load, pv.dir,
+                     pv.addK ? T->kval : nullptr, F, uout, partial);
   return hipGetLastError();
 }
 
@@ -284,8 +199,7 @@ hipError_t launch_jacobian(const egfem_tensor_s* T, const double* u, const doubl
                            int dadu_2u, int addK, const uint8_t* dir, double* jval, double* dinv,
                            hipStream_t st) {
   hipLaunchKernelGGL(k_jacobian, dim3(xcd_grid(T->row_blocks)), dim3(kBlockThreads), 0, st,
-                     T->blk_row, T->row_blocks, T->rowptr, T->col, T->kptrA, T->kA, T->vA, T->jptrB,
-                     T->jB, T->vB, T->symmetric, u, a, a0, a0c, use_problem_a, dadu, dadu_2u,
+                     view_of(T), u, a, a0, a0c, use_problem_a, dadu, dadu_2u,
                      addK ? T->kval : nullptr, dir, jval, dinv);
   return hipGetLastError();
 }

@@ -1,0 +1,115 @@
+"""Batched persistent Newton: every instance of one launch equals its own
+per-instance solve and the oracle; hipGraph replays equal the eager run; the
+64-instance workload converges."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import egfem_oracle as O
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def eg():
+    import paper_2005_06193_amd as mod
+    return mod
+
+
+def dt(x, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(x), dtype=dtype, device=DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def relerr(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def setup(wls):
+    E = eg()
+    Ts, Ps = [], []
+    for wl in wls:
+        T = E.Tensor.from_mesh(wl.mesh, wl.form)
+        load = T.matvec(dt(wl.f), "M")
+        a0 = dt(wl.a0) if wl.a0 is not None else None
+        Ps.append(E.Problem(T.n, load, dt(wl.mesh.dirichlet, torch.uint8), a0, wl.a0_const,
+                            wl.add_stiffness))
+        Ts.append(T)
+    return Ts, Ps
+
+
+def mixed():
+    return [W.nonlinear_diffusion_2d(n, seed=7 + n) for n in (5, 17, 24, 40)] + \
+        [W.nonlinear_diffusion_1d(64), W.semilinear_2d(20), W.diffusion_3d(5)]
+
+
+@pytest.mark.parametrize("threads", [512, 1024])
+def test_batched_matches_per_instance_and_oracle(threads):
+    E = eg()
+    wls = mixed()
+    Ts, Ps = setup(wls)
+    opts = E.NewtonOptions(tol=1e-14, max_newton=40, krylov_rtol=1e-14, krylov_threads=threads)
+    us = [torch.zeros(T.n, dtype=torch.float64, device=DEV) for T in Ts]
+    stats, rc = E.newton_batched(Ts, Ps, us, opts)
+    assert rc in (0, 4), rc
+    for wl, T, P, u, st in zip(wls, Ts, Ps, us, stats):
+        assert st.status in (0, 4), (wl.name, st.status_name)
+        ref = torch.zeros(T.n, dtype=torch.float64, device=DEV)
+        T.newton(P, ref, opts, warn=False)
+        assert relerr(host(u), host(ref)) < 1e-11, wl.name
+        uo, _ = O.newton(O.build_problem(wl), tol=1e-14, max_iter=40)
+        assert relerr(host(u), uo) < 1e-10, wl.name
+
+
+def test_batched_graph_replays_equal_eager():
+    E = eg()
+    wls = [W.nonlinear_diffusion_2d(n, seed=100 + n) for n in (12, 33, 48, 64)]
+    Ts, Ps = setup(wls)
+    us = [torch.full((T.n,), 0.3, dtype=torch.float64, device=DEV) for T in Ts]
+    B = E.Batch(Ts, Ps, us, E.NewtonOptions(tol=1e-10, forcing=1))
+    B.run(zero_init=True)
+    st0, rc0 = B.stats()
+    assert rc0 == 0
+    eager = [host(u).copy() for u in us]
+    for rep in range(3):
+        for u in us:
+            u.fill_(float(rep + 1))          # the program's own eager work between replays
+        torch.cuda.synchronize()
+        B.run(zero_init=True, graph=True)
+        st, rc = B.stats()
+        assert rc == 0
+        for e, u, s, s0 in zip(eager, us, st, st0):
+            assert np.array_equal(host(u), e), rep
+            assert s.newton_iters == s0.newton_iters and s.krylov_iters == s0.krylov_iters
+    B.close()
+
+
+def test_batched_full_workload_64_instances():
+    """64 instances, n ~ U{32..256}, one launch; all converge to 1e-10 and
+    sampled instances equal their per-instance solves."""
+    E = eg()
+    wls = W.nonlinear_diffusion_batch(64)
+    Ts, Ps = setup(wls)
+    us = [torch.zeros(T.n, dtype=torch.float64, device=DEV) for T in Ts]
+    opts = E.NewtonOptions(tol=1e-10, forcing=1)
+    B = E.Batch(Ts, Ps, us, opts)
+    B.run(zero_init=True, graph=True)
+    stats, rc = B.stats()
+    assert rc == 0
+    for s in stats:
+        assert s.status == 0 and s.res <= 1e-10 * s.res0
+    teams, total = B.teams()
+    assert sum(teams) == total and min(teams) >= 1
+    for m in (0, 17, int(np.argmax([T.n for T in Ts]))):
+        ref = torch.zeros(Ts[m].n, dtype=torch.float64, device=DEV)
+        Ts[m].newton(Ps[m], ref, opts)
+        po = O.build_problem(wls[m])
+        # both satisfy the oracle's residual test at 1e-10
+        for v in (host(us[m]), host(ref)):
+            assert np.linalg.norm(O.residual(po, v)) <= 1.01e-10 * np.linalg.norm(po.d[~po.dirichlet])
+    B.close()
