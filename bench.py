@@ -123,8 +123,10 @@ def time_solves(T, p, steps: int, warmup: int, opts):
 
 def time_action(T, reps: int, cold: bool):
     """Raw tensor action r = T:(u (x) a) launched back to back (warm), or with
-    a 1 GiB overwrite between launches so the stream comes from HBM (cold).
-    Times with torch events on the stream the library launches on."""
+    1 GiB read between launches so that the stream comes from HBM (cold).  The
+    flush reads (a written flush leaves dirty lines whose write-back would be
+    charged to the timed kernel).  Times with torch events on the stream the
+    library launches on."""
     import torch
     n = T.n
     g = torch.Generator(device="cuda").manual_seed(5)
@@ -144,9 +146,10 @@ def time_action(T, reps: int, cold: bool):
         e1.record()
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
+    flush.fill_(1.0)
     tot = 0.0
     for i in range(reps):
-        flush.fill_(float(i))
+        flush.sum()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -173,6 +176,163 @@ def time_jacobian(T, p, reps: int):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def device_problem(wl, T):
+    import torch
+    import paper_2005_06193_amd as eg
+    dev = torch.device("cuda:0")
+    load = T.matvec(torch.tensor(wl.f, dtype=torch.float64, device=dev), "M")
+    dirm = torch.tensor(wl.mesh.dirichlet, dtype=torch.uint8, device=dev)
+    a0 = torch.tensor(wl.a0, dtype=torch.float64, device=dev) if wl.a0 is not None else None
+    return eg.Problem(T.n, load, dirm, a0, wl.a0_const, wl.add_stiffness)
+
+
+def tensor_action_suite():
+    """Raw tensor action and Jacobian emission on the three single-instance
+    workload sizes (the larger two exceed what launch overhead hides)."""
+    import paper_2005_06193_amd as eg
+    import workloads as W
+    out = {}
+    for name, wl in (("2d_256_stiff", W.nonlinear_diffusion_2d(256)),
+                     ("2d_512_mass", W.semilinear_2d(512)),
+                     ("3d_64_stiff", W.diffusion_3d(64))):
+        T = eg.Tensor.from_mesh(wl.mesh, wl.form)
+        p = device_problem(wl, T)
+        tuned = T.autotune(p, krylov=False)
+        info = T.info
+        warm = time_action(T, 100, cold=False)
+        cold = time_action(T, 20, cold=True)
+        jac = time_jacobian(T, p, 50)
+        ba = bytes_action_raw(info)
+        bj = bytes_jacobian(info)
+        out[name] = {"nnz": info.nnz, "slots": info.slots, "action_bytes": ba,
+                     "action_warm_us": warm * 1e3, "action_warm_GBps": ba / (warm * 1e6),
+                     "action_cold_us": cold * 1e3, "action_cold_GBps": ba / (cold * 1e6),
+                     "action_cold_frac": ba / (cold * 1e6) / HBM_PEAK_GBS,
+                     "action_nnz_per_s": info.nnz / (cold * 1e-3),
+                     "jacobian_bytes": bj, "jacobian_warm_us": jac * 1e3,
+                     "jacobian_warm_GBps": bj / (jac * 1e6),
+                     "jacobian_frac": bj / (jac * 1e6) / HBM_PEAK_GBS,
+                     "shape": tuned["shape"]}
+        T.close()
+    return out
+
+
+def stream_ceiling():
+    """Plain device copy and read-reduction (torch kernels) of 256 MiB after a
+    1 GiB read: the measured bandwidth context for the roofline."""
+    import torch
+    n = 1 << 25
+    x = torch.rand(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    flush = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    res = {}
+    for name, fn, nbytes in (("copy", lambda: y.copy_(x), 16 * n), ("sum", lambda: x.sum(), 8 * n)):
+        fn()
+        tot = 0.0
+        for i in range(10):
+            flush.sum()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            tot += e0.elapsed_time(e1)
+        res[f"{name}_cold_GBps"] = nbytes / (tot / 10 * 1e6)
+    return res
+
+
+def batched_suite(reps: int = 3):
+    """64-instance workload: one persistent launch replayed from a hipGraph,
+    against the same 64 instances solved one by one (egfem_newton)."""
+    import torch
+    import paper_2005_06193_amd as eg
+    import workloads as W
+    wls = W.nonlinear_diffusion_batch(64)
+    Ts = [eg.Tensor.from_mesh(wl.mesh, wl.form) for wl in wls]
+    Ps = [device_problem(wl, T) for wl, T in zip(wls, Ts)]
+    us = [torch.zeros(T.n, dtype=torch.float64, device="cuda") for T in Ts]
+    opts = eg.NewtonOptions(tol=1e-10, forcing=1)
+    res = {"instances": len(Ts), "nodes": sum(T.n for T in Ts),
+           "tensor_nnz": sum(T.info.nnz for T in Ts)}
+    best = None
+    for threads in (512, 1024):
+        for wexp in (1.0, 1.5, 2.0):
+            B = eg.Batch(Ts, Ps, us, opts, threads=threads, weight_exp=wexp)
+            B.run(zero_init=True, graph=True)       # capture + warm
+            st, rc = B.stats()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                B.run(zero_init=True, graph=True)
+            st, rc = B.stats()
+            dt_ = (time.perf_counter() - t0) / reps
+            ok = rc == 0 and all(s.status == 0 for s in st)
+            cand = {"threads": threads, "weight_exp": wexp, "ms": dt_ * 1e3, "converged": ok,
+                    "workgroups": B.teams()[1]}
+            if ok and (best is None or cand["ms"] < best["ms"]):
+                best = cand
+            B.close()
+    res["autotuned"] = best
+    res["batched_ms"] = best["ms"] if best else None
+    res["batched_solves_per_s"] = 64 / (best["ms"] * 1e-3) if best else None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for T, P, u in zip(Ts, Ps, us):
+        u.zero_()
+        T.newton(P, u, opts)
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t0
+    res["per_instance_ms"] = seq * 1e3
+    res["per_instance_solves_per_s"] = 64 / seq
+    if best:
+        res["batched_speedup"] = seq * 1e3 / best["ms"]
+    for T in Ts:
+        T.close()
+    return res
+
+
+def adjoint_suite():
+    """3D 64^3 differentiation workload: forward Newton solve (tol 1e-13) and
+    the adjoint (implicit, checkpointed u*) through torch.autograd."""
+    import torch
+    import paper_2005_06193_amd as eg
+    import workloads as W
+    wl = W.diffusion_3d(64)
+    T = eg.Tensor.from_mesh(wl.mesh, wl.form)
+    dev = torch.device("cuda:0")
+    tpl = eg.Problem(T.n, None, torch.tensor(wl.mesh.dirichlet, dtype=torch.uint8, device=dev),
+                     None, 0.0, False)
+    opts = eg.NewtonOptions(tol=wl.tol, krylov_rtol=1e-13)
+    kappa = torch.tensor(wl.a0, dtype=torch.float64, device=dev)
+    with torch.no_grad():
+        u_d = eg.solve(torch.tensor(wl.extra["f_target"], dtype=torch.float64, device=dev), kappa,
+                       T, tpl, opts)
+    f = torch.tensor(wl.f, dtype=torch.float64, device=dev)
+    tf = tb = 0.0
+    reps = 3
+    for r in range(reps + 1):
+        fr = f.clone().requires_grad_(True)
+        kr = kappa.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u = eg.solve(fr, kr, T, tpl, opts)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        J = 0.5 * torch.sum((u - u_d) ** 2)
+        J.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if r > 0:
+            tf += t1 - t0
+            tb += t2 - t1
+    T.close()
+    return {"workload": "diffusion_3d_64^3_kuhn", "nodes": T.info.n_nodes,
+            "forward_ms": 1e3 * tf / reps, "adjoint_ms": 1e3 * tb / reps,
+            "forward_solves_per_s": reps / tf, "adjoint_solves_per_s": reps / tb,
+            "adjoint_over_forward": tb / tf}
 
 
 def cpu_baseline(n: int, budget_s: float = 20.0):
@@ -230,6 +390,8 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-micro", action="store_true", help="skip the tensor-action microbenchmarks")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance batched form")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the 3D adjoint form")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the build targets a single MI355X); "
@@ -243,6 +405,7 @@ def main():
         print("no HIP device", file=sys.stderr)
         sys.exit(1)
     wl, T, p = gpu_setup(args.n)
+    tuned = T.autotune(p)          # offline, like the tensor build
     info = T.info
     opts = eg.NewtonOptions(tol=wl.tol, forcing=1, timing=1)
     elapsed, stats, u = time_solves(T, p, args.steps, args.warmup, opts)
@@ -281,20 +444,11 @@ def main():
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch}
 
-    micro = None
-    if not args.no_micro:
-        warm = time_action(T, 200, cold=False)
-        cold = time_action(T, 30, cold=True)
-        jac = time_jacobian(T, p, 200)
-        ba = bytes_action_raw(info)
-        bj = bytes_jacobian(info)
-        micro = {
-            "residual_action": {"bytes": ba, "warm_us": warm * 1e3, "warm_GBps": ba / (warm * 1e6),
-                                "cold_us": cold * 1e3, "cold_GBps": ba / (cold * 1e6),
-                                "cold_frac": ba / (cold * 1e6) / HBM_PEAK_GBS,
-                                "nnz_per_s_warm": info.nnz / (warm * 1e-3)},
-            "jacobian_emission": {"bytes": bj, "warm_us": jac * 1e3, "warm_GBps": bj / (jac * 1e6)},
-        }
+    micro = None if args.no_micro else tensor_action_suite()
+    if micro is not None:
+        micro["stream_ceiling"] = stream_ceiling()
+    batched = None if args.no_batched else batched_suite()
+    adjoint = None if args.no_adjoint else adjoint_suite()
 
     cpu = None if args.no_cpu else cpu_baseline(args.n)
     out = {
@@ -315,10 +469,13 @@ def main():
                    "newton_tol": wl.tol, "forcing": "eisenstat-walker-2",
                    "krylov": "bicgstab-jacobi"},
         "converged": ok,
+        "autotuned_shape": tuned,
         "newton_iters_per_solve": sum(s.newton_iters for s in stats) / len(stats),
         "roofline": roofline,
         "kernels": kernels,
         "tensor_action": micro,
+        "batched": batched,
+        "adjoint": adjoint,
         "cpu_baseline": cpu,
     }
     if cpu:

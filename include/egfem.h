@@ -239,6 +239,34 @@ int egfem_solve(egfem_tensor_t T, const double* jval, int transpose, const doubl
                 double* x, double rtol, int max_iter, int* iters, double* relres, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Launch shapes and the autotuner.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int action_runs;           /* workgroups of the tensor-action kernel, each over a contiguous
+                                run of row blocks (0 = one workgroup per row block) */
+  int action_pipe;           /* 1: software-pipelined runs (next block's stream loads issued
+                                before the current block's gathers), 0: one block at a time */
+  int krylov_blocks;         /* persistent BiCGStab grid (0 = heuristic) */
+  int krylov_threads;        /* persistent BiCGStab workgroup size 256/512/1024 (0 = 1024) */
+} egfem_launch_shape;
+
+int egfem_get_shape(egfem_tensor_t T, egfem_launch_shape* s);
+/* Set the shape used by later calls on this handle (e.g. restored from a
+ * cache).  Out-of-range values give EGFEM_ERR_ARG. */
+int egfem_set_shape(egfem_tensor_t T, const egfem_launch_shape* s);
+
+/* Autotuner: time the candidate shapes on this handle's own tensor with HIP
+ * events on `stream` and keep the fastest in the handle.
+ *   what: bit 0 -> tensor action (runs x {pipelined, not}); bit 1 -> Krylov grid
+ *         (threads x blocks, per-iteration time of BiCGStab on DF(0) of problem p,
+ *         which must then be non-NULL).
+ *   best (host, nullable) receives the chosen shape; best_us (host [2], nullable)
+ *   the chosen action launch time and Krylov iteration time in microseconds.
+ * Overwrites the handle's solver workspace.  Synchronises the stream. */
+int egfem_autotune(egfem_tensor_t T, const egfem_problem* p, int what, egfem_launch_shape* best,
+                   double* best_us, void* stream);
+
+/* ------------------------------------------------------------------------
  * Adjoint of the converged solve (implicit function theorem; the gradient
  * pattern for optimal control that motivates the method, Sec. 6).
  *

@@ -64,6 +64,11 @@ class _Opts(C.Structure):
                 ("krylov_threads", C.c_int), ("timing", C.c_int)]
 
 
+class _Shape(C.Structure):
+    _fields_ = [("action_runs", C.c_int), ("action_pipe", C.c_int), ("krylov_blocks", C.c_int),
+                ("krylov_threads", C.c_int)]
+
+
 class _Stats(C.Structure):
     _fields_ = [("status", C.c_int), ("newton_iters", C.c_int), ("krylov_iters", C.c_int),
                 ("backtracks", C.c_int), ("res0", C.c_double), ("res", C.c_double),
@@ -111,6 +116,10 @@ EXPORTS = {
     "egfem_batch_stats": (C.c_int, [C.c_void_p, C.POINTER(_Stats), C.c_void_p]),
     "egfem_batch_teams": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "egfem_batch_destroy": (None, [C.c_void_p]),
+    "egfem_get_shape": (C.c_int, [C.c_void_p, C.POINTER(_Shape)]),
+    "egfem_set_shape": (C.c_int, [C.c_void_p, C.POINTER(_Shape)]),
+    "egfem_autotune": (C.c_int, [C.c_void_p, C.POINTER(_Problem), C.c_int, C.POINTER(_Shape),
+                                 C.POINTER(C.c_double), C.c_void_p]),
     "egfem_last_error": (C.c_char_p, []),
     "egfem_version": (C.c_char_p, []),
 }
@@ -395,6 +404,50 @@ class Tensor:
                                           _dptr(ga, n=self.n), C.byref(it), C.byref(rr), _stream())
         _check(rc, allow_positive=True)
         return lam, ga, rc, it.value, rr.value
+
+    # -- launch shapes / autotuner ------------------------------------------
+    def get_shape(self) -> dict:
+        s = _Shape()
+        _check(load_library().egfem_get_shape(self.handle, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in _Shape._fields_}
+
+    def set_shape(self, **kw):
+        cur = self.get_shape()
+        cur.update(kw)
+        s = _Shape(**cur)
+        _check(load_library().egfem_set_shape(self.handle, C.byref(s)))
+
+    def autotune(self, problem: Optional[Problem] = None, action: bool = True,
+                 krylov: bool = True, cache: Optional[str] = None) -> dict:
+        """Pick the tensor-action run shape and the Krylov grid by timing
+        candidates on this tensor; with `cache` (a JSON path) reuse/store the
+        choice keyed by the tensor's sizes."""
+        import json
+        key = f"d{self.info.dim}-f{self.info.form}-n{self.n}-z{self.info.nnz}-s{self.info.slots}"
+        if cache and os.path.exists(cache):
+            with open(cache) as fh:
+                db = json.load(fh)
+            if key in db:
+                self.set_shape(**db[key]["shape"])
+                return db[key]
+        what = (1 if action else 0) | (2 if (krylov and problem is not None) else 0)
+        pc = problem.c() if problem is not None else None
+        s = _Shape()
+        us = (C.c_double * 2)()
+        _check(load_library().egfem_autotune(self.handle, C.byref(pc) if pc is not None else None,
+                                             what, C.byref(s), us, _stream()))
+        res = {"shape": {f: getattr(s, f) for f, _ in _Shape._fields_},
+               "action_us": us[0], "krylov_iter_us": us[1]}
+        if cache:
+            db = {}
+            if os.path.exists(cache):
+                with open(cache) as fh:
+                    db = json.load(fh)
+            db[key] = res
+            os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+            with open(cache, "w") as fh:
+                json.dump(db, fh, indent=1)
+        return res
 
     def solve(self, jval, rhs, x=None, transpose=False, rtol=1e-12, max_iter=20000):
         x = torch.zeros_like(rhs) if x is None else x

@@ -79,11 +79,11 @@ __global__ void k_diag_inv(int64_t n, const int32_t* __restrict__ diag, const do
 // added on the host in block order (deterministic).
 static int read_norm(egfem_tensor_s* T, hipStream_t st, double* norm) {
   Workspace& W = T->ws;
-  EGFEM_HIP_CHECK(hipMemcpyAsync(W.host_partial, W.partial, T->row_blocks * sizeof(double),
-                                 hipMemcpyDeviceToHost, st));
+  const int64_t nrun = action_runs(T);
+  EGFEM_HIP_CHECK(hipMemcpyAsync(W.host_partial, W.partial, nrun * sizeof(double), hipMemcpyDeviceToHost, st));
   EGFEM_HIP_CHECK(hipStreamSynchronize(st));
   double s = 0.0;
-  for (int64_t b = 0; b < T->row_blocks; ++b) s += W.host_partial[b];
+  for (int64_t b = 0; b < nrun; ++b) s += W.host_partial[b];
   *norm = std::sqrt(s);
   return EGFEM_OK;
 }

@@ -98,9 +98,9 @@ __global__ __launch_bounds__(NT) void k_newton_batched(const Inst* __restrict__ 
 
   // residual at the initial iterate
   double sq = 0.0;
-  for (int b = b0; b < b1 && !abort; ++b)
-    dev::rowblock_action<NT, true, true>(I.tv, b, ucur, nullptr, 0.0, I.a0, I.a0c, I.load, I.dir, kval,
-                                         I.F, nullptr, sq, lds);
+  if (!abort)
+    dev::rowblocks_action_pipelined<NT, true, true>(I.tv, b0, b1, ucur, nullptr, 0.0, I.a0, I.a0c, I.load,
+                                                    I.dir, kval, I.F, nullptr, sq, lds);
   for (int q = 0; q < dev::kMaxRed; ++q) red[q] = 0.0;
   red[0] = sq;
   if (!abort) abort = dev::team_reduce<NT>(tm, nslot, red, 1, sh, &sh_abort);
@@ -137,9 +137,8 @@ __global__ __launch_bounds__(NT) void k_newton_batched(const Inst* __restrict__ 
     bool accepted = false;
     for (int bt = 0; bt <= O.max_backtracks; ++bt) {
       sq = 0.0;
-      for (int b = b0; b < b1; ++b)
-        dev::rowblock_action<NT, true, true>(I.tv, b, ucur, KA.x, alpha, I.a0, I.a0c, I.load, I.dir, kval,
-                                             I.F, unext, sq, lds);
+      dev::rowblocks_action_pipelined<NT, true, true>(I.tv, b0, b1, ucur, KA.x, alpha, I.a0, I.a0c, I.load,
+                                                      I.dir, kval, I.F, unext, sq, lds);
       for (int q = 0; q < dev::kMaxRed; ++q) red[q] = 0.0;
       red[0] = sq;
       if ((abort = dev::team_reduce<NT>(tm, nslot, red, 1, sh, &sh_abort))) break;

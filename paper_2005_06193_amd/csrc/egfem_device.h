@@ -54,17 +54,99 @@ struct TensorView {
   const double* kval;
 };
 
-// LDS scratch of the row-block stages.
+// LDS scratch of the row-block stages (one block at a time per workgroup).
 struct RowBlockLds {
-  double tA[kCapNnz];
-  double tB[kCapNnz];
-  double y[kCapSlots];
-  int scol[kCapSlots];
-  int spa[kCapSlots + 1];
-  int spb[kCapSlots + 1];
+  double tA[kCapNnz];        // products of the A stream
+  double tB[kCapNnz];        // products of the B stream (Jacobian only)
+  double y[kCapSlots];       // slot results (action)
+  int spa[kCapSlots + 1];    // fiber bounds, A stream, block-relative
+  int spb[kCapSlots + 1];    // fiber bounds, B stream, block-relative
+  int srow[kCapRows + 1];    // slot bounds of the rows, block-relative
+  int srid[kCapSlots];       // row of every slot, block-relative (Jacobian)
+  unsigned char sdir[kCapRows];
 };
 
-// Tensor action over row block b with NT threads:
+// LDS scratch of the residual action alone (smaller: higher occupancy).
+struct ActionLds {
+  double tA[kCapNnz];
+  double y[kCapSlots];
+  int spa[kCapSlots + 1];
+  int srow[kCapRows + 1];
+};
+
+// Entries / slots one thread handles in a row block.
+template <int NT>
+struct Per {
+  static_assert(NT >= kCapRows, "one thread per row of a block");
+  static constexpr int P = (kCapNnz + NT - 1) / NT;
+  static constexpr int S = (kCapSlots + NT - 1) / NT;
+};
+
+// Stream registers of one row block for the tensor action (stage 1a).
+template <int NT>
+struct ActionRegs {
+  int kk[Per<NT>::P];
+  double vv[Per<NT>::P];
+  int cc[Per<NT>::S];
+  int kp[Per<NT>::S];
+  double kv[Per<NT>::S];
+  int r0, r1, s0, p0, np, ns, nr, rp;
+  double ldi;
+  bool di;
+};
+
+// Stage 1a of the tensor action: every stream load of this thread for block b
+// (its entries, slots and row), issued without waiting.
+template <int NT, bool PROBLEM>
+__device__ __forceinline__ void action_load(const TensorView& T, int64_t b, const double* load,
+                                            const uint8_t* dir, const double* kval, ActionRegs<NT>& R) {
+  constexpr int PP = Per<NT>::P, SS = Per<NT>::S;
+  const int tid = threadIdx.x;
+  R.r0 = T.blk_row[b];
+  R.r1 = T.blk_row[b + 1];
+  R.s0 = T.rowptr[R.r0];
+  const int s1 = T.rowptr[R.r1];
+  R.p0 = T.kptrA[R.s0];
+  const int p1 = T.kptrA[s1];
+  R.np = p1 - R.p0;
+  R.ns = s1 - R.s0;
+  R.nr = R.r1 - R.r0;
+#pragma unroll
+  for (int q = 0; q < PP; ++q) {
+    const int p = tid + q * NT;
+    R.kk[q] = 0;
+    R.vv[q] = 0.0;
+    if (p < R.np) {
+      R.kk[q] = T.kA[R.p0 + p];
+      R.vv[q] = T.vA[R.p0 + p];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < SS; ++q) {
+    const int s = tid + q * NT;
+    R.cc[q] = 0;
+    R.kp[q] = 0;
+    R.kv[q] = 0.0;
+    if (s < R.ns) {
+      R.cc[q] = T.col[R.s0 + s];
+      R.kp[q] = T.kptrA[R.s0 + s];
+      if (PROBLEM && kval) R.kv[q] = kval[R.s0 + s];
+    }
+  }
+  R.rp = 0;
+  R.ldi = 0.0;
+  R.di = false;
+  if (tid < R.nr) {
+    const int i = R.r0 + tid;
+    R.rp = T.rowptr[i];
+    if (PROBLEM) {
+      if (load) R.ldi = load[i];
+      R.di = dir && dir[i];
+    }
+  }
+}
+
+// Stages 1b-3 of the tensor action on the registers of one block:
 //   r_i = sum_{s in row i} w_col(s) * (sum_{p in A(s)} v_p a_{k_p} [+ K_s])
 //   RAW:     a given;                                     out = r
 //   PROBLEM: a = a0 + w^2, w = u + alpha delta (delta may be null);
@@ -72,53 +154,71 @@ struct RowBlockLds {
 //            sq += F_i^2 over the rows this thread handled.
 // SH: u, delta gathered with agent-coherent loads and uout written with
 // agent-coherent stores (data produced by other workgroups of the same launch).
-template <int NT, bool PROBLEM, bool SH>
-__device__ void rowblock_action(const TensorView& T, int64_t b, const double* u, const double* delta,
-                                double alpha, const double* a, double a0c, const double* load,
-                                const uint8_t* dir, const double* kval, double* out, double* uout,
-                                double& sq, RowBlockLds& L) {
+template <int NT, bool PROBLEM, bool SH, typename Lds>
+__device__ __forceinline__ void action_compute(const ActionRegs<NT>& R, const double* u,
+                                               const double* delta, double alpha, const double* a,
+                                               double a0c, double* out, double* uout, double& sq,
+                                               Lds& L) {
+  constexpr int PP = Per<NT>::P, SS = Per<NT>::S;
   const int tid = threadIdx.x;
-  const int r0 = T.blk_row[b], r1 = T.blk_row[b + 1];
-  const int s0 = T.rowptr[r0], s1 = T.rowptr[r1];
-  const int p0 = T.kptrA[s0], p1 = T.kptrA[s1];
-  for (int p = p0 + tid; p < p1; p += NT) {
-    const int k = T.kA[p];
-    double ak;
-    if (PROBLEM) {
-      double wk = ld<SH>(u + k);
-      if (delta) wk = fma(alpha, ld<SH>(delta + k), wk);
-      ak = fma(wk, wk, a ? a[k] : a0c);
-    } else {
-      ak = a[k];
+#pragma unroll
+  for (int q = 0; q < PP; ++q) {
+    const int p = tid + q * NT;
+    if (p < R.np) {
+      const int k = R.kk[q];
+      double ak;
+      if (PROBLEM) {
+        double wk = ld<SH>(u + k);
+        if (delta) wk = fma(alpha, ld<SH>(delta + k), wk);
+        ak = fma(wk, wk, a ? a[k] : a0c);
+      } else {
+        ak = a[k];
+      }
+      L.tA[p] = R.vv[q] * ak;
     }
-    L.tA[p - p0] = T.vA[p] * ak;
+  }
+  double wj[SS];
+#pragma unroll
+  for (int q = 0; q < SS; ++q) {
+    const int s = tid + q * NT;
+    wj[q] = 0.0;
+    if (s < R.ns) {
+      const int j = R.cc[q];
+      wj[q] = ld<SH>(u + j);
+      if (PROBLEM && delta) wj[q] = fma(alpha, ld<SH>(delta + j), wj[q]);
+      L.spa[s] = R.kp[q] - R.p0;
+    }
+  }
+  const bool has_row = tid < R.nr;
+  if (tid == 0) {
+    L.spa[R.ns] = R.np;
+    L.srow[R.nr] = R.ns;
+  }
+  if (has_row) L.srow[tid] = R.rp - R.s0;
+  __syncthreads();
+  // fiber sums (same slots as loaded by this thread)
+#pragma unroll
+  for (int q = 0; q < SS; ++q) {
+    const int s = tid + q * NT;
+    if (s < R.ns) {
+      double acc = 0.0;
+      for (int t = L.spa[s]; t < L.spa[s + 1]; ++t) acc += L.tA[t];
+      L.y[s] = (acc + R.kv[q]) * wj[q];
+    }
   }
   __syncthreads();
-  for (int s = s0 + tid; s < s1; s += NT) {
-    const int q0 = T.kptrA[s] - p0, q1 = T.kptrA[s + 1] - p0;
-    double q = 0.0;
-    for (int t = q0; t < q1; ++t) q += L.tA[t];
-    const int j = T.col[s];
-    double wj = ld<SH>(u + j);
-    if (PROBLEM) {
-      if (delta) wj = fma(alpha, ld<SH>(delta + j), wj);
-      if (kval) q += kval[s];
-    }
-    L.y[s - s0] = q * wj;
-  }
-  __syncthreads();
-  for (int i = r0 + tid; i < r1; i += NT) {
-    const int q0 = T.rowptr[i] - s0, q1 = T.rowptr[i + 1] - s0;
+  // row sums
+  if (has_row) {
+    const int i = R.r0 + tid;
     double acc = 0.0;
-    for (int t = q0; t < q1; ++t) acc += L.y[t];
+    for (int t = L.srow[tid]; t < L.srow[tid + 1]; ++t) acc += L.y[t];
     if (PROBLEM) {
-      if (load) acc -= load[i];
-      const bool d = dir && dir[i];
-      if (d) acc = 0.0;
+      acc -= R.ldi;
+      if (R.di) acc = 0.0;
       if (uout) {
         double wi = ld<SH>(u + i);
         if (delta) wi = fma(alpha, ld<SH>(delta + i), wi);
-        wi = d ? 0.0 : wi;
+        wi = R.di ? 0.0 : wi;
         if (SH) st_sh(uout + i, wi);
         else uout[i] = wi;
       }
@@ -129,67 +229,178 @@ __device__ void rowblock_action(const TensorView& T, int64_t b, const double* u,
   __syncthreads();   // LDS is reused by the next block
 }
 
+// Tensor action over row block b with NT threads (load + compute).
+template <int NT, bool PROBLEM, bool SH, typename Lds>
+__device__ void rowblock_action(const TensorView& T, int64_t b, const double* u, const double* delta,
+                                double alpha, const double* a, double a0c, const double* load,
+                                const uint8_t* dir, const double* kval, double* out, double* uout,
+                                double& sq, Lds& L) {
+  ActionRegs<NT> R;
+  action_load<NT, PROBLEM>(T, b, load, dir, kval, R);
+  action_compute<NT, PROBLEM, SH>(R, u, delta, alpha, a, a0c, out, uout, sq, L);
+}
+
+// Tensor action over the contiguous block range [b0, b1) of one workgroup,
+// one block after the other (no prefetch: fewer registers, higher occupancy).
+template <int NT, bool PROBLEM, bool SH, typename Lds>
+__device__ void rowblocks_action(const TensorView& T, int64_t b0, int64_t b1, const double* u,
+                                 const double* delta, double alpha, const double* a, double a0c,
+                                 const double* load, const uint8_t* dir, const double* kval, double* out,
+                                 double* uout, double& sq, Lds& L) {
+  for (int64_t b = b0; b < b1; ++b)
+    rowblock_action<NT, PROBLEM, SH>(T, b, u, delta, alpha, a, a0c, load, dir, kval, out, uout, sq, L);
+}
+
+// Tensor action over the contiguous block range [b0, b1) of one workgroup,
+// software-pipelined: the stream loads of block b+1 are issued before the
+// gathers and LDS stages of block b, so they overlap that dependent chain.
+template <int NT, bool PROBLEM, bool SH, typename Lds>
+__device__ void rowblocks_action_pipelined(const TensorView& T, int64_t b0, int64_t b1, const double* u,
+                                           const double* delta, double alpha, const double* a,
+                                           double a0c, const double* load, const uint8_t* dir,
+                                           const double* kval, double* out, double* uout, double& sq,
+                                           Lds& L) {
+  if (b0 >= b1) return;
+  // two named register sets (a dynamically indexed pair would live in scratch)
+  ActionRegs<NT> RA, RB;
+  action_load<NT, PROBLEM>(T, b0, load, dir, kval, RA);
+  for (int64_t b = b0; b < b1; b += 2) {
+    if (b + 1 < b1) action_load<NT, PROBLEM>(T, b + 1, load, dir, kval, RB);
+    action_compute<NT, PROBLEM, SH>(RA, u, delta, alpha, a, a0c, out, uout, sq, L);
+    if (b + 1 >= b1) break;
+    if (b + 2 < b1) action_load<NT, PROBLEM>(T, b + 2, load, dir, kval, RA);
+    action_compute<NT, PROBLEM, SH>(RB, u, delta, alpha, a, a0c, out, uout, sq, L);
+  }
+}
+
 // Jacobian emission over row block b with NT threads:
 //   J_s = [K_s] + sum_{p in A(s)} v_p a_{k_p} + g_j sum_{p in B(s)} v_p u_{j_p},
 // s = (i, j), a = a0 + u^2 (problem_a) or given, g = dadu or 2u (dadu_2u) or none.
 // Dirichlet rows -> identity rows, Dirichlet columns -> 0; dinv[i] = 1 / J_ii.
+// Two phases: every thread loads its A/B entries, slots and row, gathers and
+// writes products and bounds to LDS; then every slot sums its two fibers and
+// stores J_s (coalesced).
 template <int NT, bool SH>
 __device__ void rowblock_jacobian(const TensorView& T, int64_t b, const double* u, const double* a,
                                   const double* a0, double a0c, int problem_a, const double* dadu,
                                   int dadu_2u, const double* kval, const uint8_t* dir, double* jval,
                                   double* dinv, RowBlockLds& L) {
+  constexpr int PP = Per<NT>::P, SS = Per<NT>::S;
   const int tid = threadIdx.x;
   const int r0 = T.blk_row[b], r1 = T.blk_row[b + 1];
   const int s0 = T.rowptr[r0], s1 = T.rowptr[r1];
   const int pa0 = T.kptrA[s0], pa1 = T.kptrA[s1];
   const int pb0 = T.jptrB[s0], pb1 = T.jptrB[s1];
+  const int na = pa1 - pa0, nb = pb1 - pb0, ns = s1 - s0, nr = r1 - r0;
   const bool second = dadu || dadu_2u;
-  for (int p = pa0 + tid; p < pa1; p += NT) {
-    const int k = T.kA[p];
-    const double uk = ld<SH>(u + k);
-    const double ak = problem_a ? fma(uk, uk, a0 ? a0[k] : a0c) : a[k];
-    const double v = T.vA[p];
-    L.tA[p - pa0] = v * ak;
-    if (T.sym && second) L.tB[p - pa0] = v * uk;
-  }
-  if (!T.sym && second)
-    for (int p = pb0 + tid; p < pb1; p += NT) L.tB[p - pb0] = T.vB[p] * ld<SH>(u + T.jB[p]);
-  for (int s = s0 + tid; s <= s1; s += NT) {
-    L.spa[s - s0] = T.kptrA[s] - pa0;
-    L.spb[s - s0] = T.jptrB[s] - pb0;
-    if (s < s1) {
-      L.scol[s - s0] = T.col[s];
-      L.y[s - s0] = kval ? kval[s] : 0.0;
+  const bool bstream = second && !T.sym;
+  // stage 1a: stream loads
+  int ka[PP], jb[PP];
+  double va[PP], vb[PP];
+#pragma unroll
+  for (int q = 0; q < PP; ++q) {
+    const int p = tid + q * NT;
+    ka[q] = 0;
+    va[q] = 0.0;
+    jb[q] = 0;
+    vb[q] = 0.0;
+    if (p < na) {
+      ka[q] = T.kA[pa0 + p];
+      va[q] = T.vA[pa0 + p];
+    }
+    if (bstream && p < nb) {
+      jb[q] = T.jB[pb0 + p];
+      vb[q] = T.vB[pb0 + p];
     }
   }
+  int cc[SS], kpa[SS], kpb[SS];
+  double kv[SS];
+#pragma unroll
+  for (int q = 0; q < SS; ++q) {
+    const int s = tid + q * NT;
+    cc[q] = kpa[q] = kpb[q] = 0;
+    kv[q] = 0.0;
+    if (s < ns) {
+      cc[q] = T.col[s0 + s];
+      kpa[q] = T.kptrA[s0 + s];
+      kpb[q] = T.jptrB[s0 + s];
+      if (kval) kv[q] = kval[s0 + s];
+    }
+  }
+  const bool has_row = tid < nr;
+  const int i = r0 + tid;
+  int rpa = 0, rpb = 0;
+  bool drow = false;
+  if (has_row) {
+    rpa = T.rowptr[i];
+    rpb = T.rowptr[i + 1];
+    drow = dir && dir[i];
+  }
+  // stage 1b: gathers, products, bounds
+#pragma unroll
+  for (int q = 0; q < PP; ++q) {
+    const int p = tid + q * NT;
+    if (p < na) {
+      const int k = ka[q];
+      const double uk = ld<SH>(u + k);
+      const double ak = problem_a ? fma(uk, uk, a0 ? a0[k] : a0c) : a[k];
+      L.tA[p] = va[q] * ak;
+      if (T.sym && second) L.tB[p] = va[q] * uk;
+    }
+    if (bstream && p < nb) L.tB[p] = vb[q] * ld<SH>(u + jb[q]);
+  }
+  double gj[SS];
+  bool dcol[SS];
+#pragma unroll
+  for (int q = 0; q < SS; ++q) {
+    const int s = tid + q * NT;
+    gj[q] = 0.0;
+    dcol[q] = false;
+    if (s < ns) {
+      const int j = cc[q];
+      if (second) gj[q] = dadu ? dadu[j] : 2.0 * ld<SH>(u + j);
+      dcol[q] = dir && dir[j];
+      L.spa[s] = kpa[q] - pa0;
+      L.spb[s] = kpb[q] - pb0;
+    }
+  }
+  if (tid == 0) {
+    L.spa[ns] = na;
+    L.spb[ns] = nb;
+  }
+  if (has_row) {
+    L.sdir[tid] = drow ? 1 : 0;
+    for (int s = rpa - s0; s < rpb - s0; ++s) L.srid[s] = tid;
+  }
   __syncthreads();
-  for (int i = r0 + tid; i < r1; i += NT) {
-    const bool drow = dir && dir[i];
-    for (int s = T.rowptr[i] - s0; s < T.rowptr[i + 1] - s0; ++s) {
-      const int j = L.scol[s];
+  // stage 2: slot assembly
+#pragma unroll
+  for (int q = 0; q < SS; ++q) {
+    const int s = tid + q * NT;
+    if (s < ns) {
+      const int ir = L.srid[s];
+      const int row = r0 + ir;
+      const int j = cc[q];
       double J;
-      if (drow) {
-        J = (j == i) ? 1.0 : 0.0;
-      } else if (dir && dir[j]) {
+      if (L.sdir[ir]) {
+        J = (j == row) ? 1.0 : 0.0;
+      } else if (dcol[q]) {
         J = 0.0;
       } else {
         double qa = 0.0;
         for (int t = L.spa[s]; t < L.spa[s + 1]; ++t) qa += L.tA[t];
-        J = L.y[s] + qa;
+        J = kv[q] + qa;
         if (second) {
           double qb = 0.0;
           for (int t = L.spb[s]; t < L.spb[s + 1]; ++t) qb += L.tB[t];
-          const double g = dadu ? dadu[j] : 2.0 * ld<SH>(u + j);
-          J = fma(g, qb, J);
+          J = fma(gj[q], qb, J);
         }
       }
-      L.y[s] = J;
-      if (j == i && dinv) dinv[i] = 1.0 / J;
+      jval[s0 + s] = J;
+      if (j == row && dinv) dinv[row] = 1.0 / J;
     }
   }
-  __syncthreads();
-  for (int s = s0 + tid; s < s1; s += NT) jval[s] = L.y[s - s0];
-  __syncthreads();
+  __syncthreads();   // LDS is reused by the next block
 }
 
 // ---------------------------------------------------------------------------

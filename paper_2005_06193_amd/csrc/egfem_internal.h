@@ -49,7 +49,7 @@ struct Workspace {
   // BiCGStab vectors
   double *r = nullptr, *rhat = nullptr, *p = nullptr, *v = nullptr, *s = nullptr,
          *t = nullptr, *z = nullptr, *phat = nullptr, *rh = nullptr, *vh = nullptr;
-  double* partial = nullptr;    // per-row-block partial sums [row_blocks]
+  double* partial = nullptr;    // per-workgroup partial sums of the action kernel [row_blocks]
   double* red = nullptr;        // persistent-kernel reduction slots [kRedSlots * 8 * kMaxKrylovBlocks]
   unsigned* ctrl = nullptr;     // barrier counters / epoch / abort flag [kCtrlWordsMax] (device)
   double* qslot = nullptr;      // per-slot scratch [slots] (mode-3 contraction)
@@ -76,6 +76,10 @@ struct egfem_tensor_s {
   int max_row_slots = 0;
   int lanes_per_row = 8;        // SpMV sub-wave width (power of two >= max row length)
   int krylov_lanes = 4;         // persistent-Krylov SpMV width (power of two >= max row / 2)
+  int action_runs_target = 0;   // workgroups of the action kernel (block runs; 0 = one per block)
+  int action_pipe = 0;          // 1: software-pipelined block runs
+  int tuned_krylov_blocks = 0;  // Krylov grid chosen by the autotuner (0 = heuristic)
+  int tuned_krylov_threads = 0;
   int device = 0;
   // device arrays
   int32_t* rowptr = nullptr;    // [n+1]
@@ -108,6 +112,7 @@ struct ProblemView {
   int addK;
 };
 
+int64_t action_runs(const egfem_tensor_s* T);
 hipError_t launch_action_raw(const egfem_tensor_s* T, const double* u, const double* a, double* r,
                              hipStream_t st);
 hipError_t launch_action_problem(const egfem_tensor_s* T, const ProblemView& pv, const double* u,

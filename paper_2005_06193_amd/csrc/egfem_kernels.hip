@@ -10,6 +10,8 @@
 //   stage 3  row-parallel sums over the row's slots out of LDS.
 // Every sum runs in a fixed order, so results are bitwise reproducible.  The
 // path moves ~0.15 flop per byte and is bound by HBM bandwidth; no MFMA.
+#include <algorithm>
+
 #include "egfem_device.h"
 
 namespace egfem {
@@ -63,12 +65,14 @@ dev::TensorView view_of(const egfem_tensor_s* T) {
 
 namespace {
 
-// Residual action over one row block per workgroup (see rowblock_action):
+// Residual action (see action_compute), each workgroup over a contiguous run
+// of row blocks, software-pipelined; XCD-aware run order:
 //   RAW:      out = T:(u (x) a)
 //   PROBLEM:  out = F = [K w] + T:(w (x) (a0 + w^2)) - load, w = u + alpha delta,
-//             Dirichlet rows 0; partial[b] = sum F_i^2; uout (optional) = w.
-template <bool PROBLEM>
-__global__ __launch_bounds__(kBlockThreads) void k_action(dev::TensorView T, const double* __restrict__ u,
+//             Dirichlet rows 0; partial[wg] = sum F_i^2; uout (optional) = w.
+template <bool PROBLEM, bool PIPE>
+__global__ __launch_bounds__(kBlockThreads) void k_action(dev::TensorView T, int64_t nrun,
+                                                          const double* __restrict__ u,
                                                           const double* __restrict__ delta, double alpha,
                                                           const double* __restrict__ a, double a0c,
                                                           const double* __restrict__ load,
@@ -77,16 +81,21 @@ __global__ __launch_bounds__(kBlockThreads) void k_action(dev::TensorView T, con
                                                           double* __restrict__ out,
                                                           double* __restrict__ uout,
                                                           double* __restrict__ partial) {
-  __shared__ dev::RowBlockLds L;
+  __shared__ dev::ActionLds L;
   __shared__ double sh4[4];
-  const int64_t b = xcd_block(blockIdx.x, T.nblk);
-  if (b < 0) return;
+  const int64_t w = xcd_block(blockIdx.x, nrun);
+  if (w < 0) return;
+  const int64_t b0 = T.nblk * w / nrun, b1 = T.nblk * (w + 1) / nrun;
   double sq = 0.0;
-  dev::rowblock_action<kBlockThreads, PROBLEM, false>(T, b, u, delta, alpha, a, a0c, load, dir, kval,
-                                                      out, uout, sq, L);
+  if (PIPE)
+    dev::rowblocks_action_pipelined<kBlockThreads, PROBLEM, false>(T, b0, b1, u, delta, alpha, a, a0c, load,
+                                                                   dir, kval, out, uout, sq, L);
+  else
+    dev::rowblocks_action<kBlockThreads, PROBLEM, false>(T, b0, b1, u, delta, alpha, a, a0c, load, dir, kval,
+                                                         out, uout, sq, L);
   if (PROBLEM && partial) {
     const double tot = block_sum256(sq, sh4);
-    if (threadIdx.x == 0) partial[b] = tot;
+    if (threadIdx.x == 0) partial[w] = tot;
   }
 }
 
@@ -178,19 +187,29 @@ inline unsigned grid1d(int64_t n, int bs = kBlockThreads) { return (unsigned)((n
 
 }  // namespace
 
+// Number of block runs (workgroups) of the action kernel: the handle's
+// tuned target (0 = one block per workgroup), at least one block per run.
+int64_t action_runs(const egfem_tensor_s* T) {
+  const int64_t target = T->action_runs_target > 0 ? (int64_t)T->action_runs_target : T->row_blocks;
+  return std::max<int64_t>(1, std::min<int64_t>(T->row_blocks, target));
+}
+
 hipError_t launch_action_raw(const egfem_tensor_s* T, const double* u, const double* a, double* r,
                              hipStream_t st) {
-  hipLaunchKernelGGL(k_action<false>, dim3(xcd_grid(T->row_blocks)), dim3(kBlockThreads), 0, st,
-                     view_of(T), u, nullptr, 0.0, a, 0.0, nullptr, nullptr, nullptr, r, nullptr, nullptr);
+  const int64_t nrun = action_runs(T);
+  auto kern = T->action_pipe ? k_action<false, true> : k_action<false, false>;
+  hipLaunchKernelGGL(kern, dim3(xcd_grid(nrun)), dim3(kBlockThreads), 0, st, view_of(T), nrun, u, nullptr, 0.0,
+                     a, 0.0, nullptr, nullptr, nullptr, r, nullptr, nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_action_problem(const egfem_tensor_s* T, const ProblemView& pv, const double* u,
                                  const double* delta, double alpha, double* uout, double* F,
                                  double* partial, hipStream_t st) {
-  hipLaunchKernelGGL(k_action<true>, dim3(xcd_grid(T->row_blocks)), dim3(kBlockThreads), 0, st,
-                     view_of(T), u, delta, alpha, pv.a0, pv.a0c, pv.load, pv.dir,
-                     pv.addK ? T->kval : nullptr, F, uout, partial);
+  const int64_t nrun = action_runs(T);
+  auto kern = T->action_pipe ? k_action<true, true> : k_action<true, false>;
+  hipLaunchKernelGGL(kern, dim3(xcd_grid(nrun)), dim3(kBlockThreads), 0, st, view_of(T), nrun, u, delta, alpha,
+                     pv.a0, pv.a0c, pv.load, pv.dir, pv.addK ? T->kval : nullptr, F, uout, partial);
   return hipGetLastError();
 }
 

@@ -126,6 +126,8 @@ int krylov_bicgstab(egfem_tensor_s* T, const double* jval, const double* dinv, c
   int rc = ensure_workspace(T);
   if (rc != EGFEM_OK) return rc;
   Workspace& W = T->ws;
+  if (threads == 0) threads = T->tuned_krylov_threads;
+  if (blocks <= 0) blocks = T->tuned_krylov_blocks;
   const int NT = (threads == 256 || threads == 512 || threads == 1024) ? threads : kKrylovThreads;
   const int cap = cap_shape(NT, T->krylov_lanes);
   if (cap <= 0) return fail(EGFEM_ERR_HIP, "Krylov kernel cannot be resident");
