@@ -44,11 +44,12 @@ def bytes_action_problem(info, trial: bool):
     return 12 * Z + 8 * S + 4 * (N + 1) + vec
 
 
-def bytes_jacobian(info):
+def bytes_jacobian(info, add_stiffness: bool = False):
     N, S, Z = info.n_nodes, info.slots, info.nnz
     streams = 12 * Z + (0 if info.symmetric else 12 * Z)    # A (+ B) streams
     ptrs = 4 * (S + 1) * (1 if info.symmetric else 2) + 4 * S + 4 * (N + 1)
-    return streams + ptrs + 8 * N + N + 8 * S + 8 * N         # u, mask, J values, 1/diag
+    kmat = 8 * S if add_stiffness else 0                      # stiffness values (semilinear form)
+    return streams + ptrs + kmat + 8 * N + N + 8 * S + 8 * N  # u, mask, J values, 1/diag
 
 
 def bytes_krylov(info, iters: int):
@@ -72,18 +73,18 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str):
-    """HBM traffic per launch measured with rocprofv3 --pmc (FETCH_SIZE,
-    WRITE_SIZE), scaled by a copy kernel; None when absent or stale."""
+def load_traffic():
+    """HBM traffic measured with rocprofv3 --pmc (FETCH_SIZE, WRITE_SIZE, scaled
+    by a plain copy of known size) for the kernels as profiled; None when the
+    record is absent or the kernel sources changed since."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    ent = d.get(kernel)
-    if not ent or ent.get("source_sha") != kernel_source_sha():
+    if d.get("source_sha") != kernel_source_sha():
         return None
-    return ent.get("bytes_per_launch")
+    return d
 
 
 # ----------------------------------------------------------------------------
@@ -205,7 +206,7 @@ def tensor_action_suite():
         cold = time_action(T, 20, cold=True)
         jac = time_jacobian(T, p, 50)
         ba = bytes_action_raw(info)
-        bj = bytes_jacobian(info)
+        bj = bytes_jacobian(info, wl.add_stiffness)
         out[name] = {"nnz": info.nnz, "slots": info.slots, "action_bytes": ba,
                      "action_warm_us": warm * 1e3, "action_warm_GBps": ba / (warm * 1e6),
                      "action_cold_us": cold * 1e3, "action_cold_GBps": ba / (cold * 1e6),
@@ -215,6 +216,10 @@ def tensor_action_suite():
                      "jacobian_warm_GBps": bj / (jac * 1e6),
                      "jacobian_frac": bj / (jac * 1e6) / HBM_PEAK_GBS,
                      "shape": tuned["shape"]}
+        tr = load_traffic()
+        if tr:
+            out[name]["action_hbm_bytes_rocprof"] = tr["tensor_action"][name]["hbm_bytes_per_launch"]
+            out[name]["jacobian_hbm_bytes_rocprof"] = tr["jacobian_emission"][name]["hbm_bytes_per_launch"]
         T.close()
     return out
 
@@ -392,6 +397,8 @@ def main():
     ap.add_argument("--no-micro", action="store_true", help="skip the tensor-action microbenchmarks")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance batched form")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the 3D adjoint form")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 256 MiB device copy (scale reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the build targets a single MI355X); "
@@ -439,16 +446,30 @@ def main():
     avg_ms = dk["ms"] / dk["launches"]
     bytes_per_launch = dk["bytes"] / dk["launches"]
     achieved = bytes_per_launch / (avg_ms * 1e6)
-    traffic = load_traffic(dom)
+    tr = load_traffic()
+    traffic = None
+    if tr and dom == "krylov_bicgstab" and args.n == 256:
+        iters_per_launch = k_it / max(n_kry, 1)
+        traffic = tr["krylov_bicgstab"]["hbm_bytes_per_iteration"] * iters_per_launch
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch}
+                "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch,
+                "limiter": ("grid barriers and gather latency: the 2D-256 system (J 5.5 MB, vectors "
+                            "0.5 MB) stays in L2/MALL, HBM traffic is 0.36x the algorithmic bytes")
+                if dom == "krylov_bicgstab" else None}
 
     micro = None if args.no_micro else tensor_action_suite()
     if micro is not None:
         micro["stream_ceiling"] = stream_ceiling()
     batched = None if args.no_batched else batched_suite()
     adjoint = None if args.no_adjoint else adjoint_suite()
+
+    if args.copy_probe:
+        src = torch.ones(1 << 25, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
 
     cpu = None if args.no_cpu else cpu_baseline(args.n)
     out = {
