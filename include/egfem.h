@@ -214,6 +214,8 @@ typedef struct {
   int n_action;
   int n_jacobian;
   int n_krylov;
+  int krylov_status_hist[EGFEM_HIST];     /* Krylov status of step k */
+  double krylov_relres_hist[EGFEM_HIST];  /* Krylov relative residual of step k */
 } egfem_newton_stats;
 
 /* Fill opts with the defaults above. */

@@ -75,7 +75,8 @@ class _Stats(C.Structure):
                 ("res_hist", C.c_double * HIST), ("krylov_hist", C.c_int * HIST),
                 ("t_action_ms", C.c_double), ("t_jacobian_ms", C.c_double),
                 ("t_krylov_ms", C.c_double), ("n_action", C.c_int), ("n_jacobian", C.c_int),
-                ("n_krylov", C.c_int)]
+                ("n_krylov", C.c_int), ("krylov_status_hist", C.c_int * HIST),
+                ("krylov_relres_hist", C.c_double * HIST)]
 
 
 _lib = None
@@ -222,6 +223,8 @@ class NewtonStats:
     n_action: int = 0
     n_jacobian: int = 0
     n_krylov: int = 0
+    krylov_status_hist: List[int] = None
+    krylov_relres_hist: List[float] = None
 
     @property
     def status_name(self) -> str:
@@ -232,7 +235,8 @@ class NewtonStats:
         k = min(s.newton_iters, HIST)
         return cls(s.status, s.newton_iters, s.krylov_iters, s.backtracks, s.res0, s.res,
                    list(s.res_hist[:k]), list(s.krylov_hist[:k]), s.t_action_ms, s.t_jacobian_ms,
-                   s.t_krylov_ms, s.n_action, s.n_jacobian, s.n_krylov)
+                   s.t_krylov_ms, s.n_action, s.n_jacobian, s.n_krylov,
+                   list(s.krylov_status_hist[:k + 1]), list(s.krylov_relres_hist[:k + 1]))
 
 
 class Problem:

@@ -358,7 +358,11 @@ int egfem_newton(egfem_tensor_t T, const egfem_problem* p, double* u, const egfe
       ++stats.n_krylov;
     }
     stats.krylov_iters += kr.iters;
-    if (k < EGFEM_HIST) stats.krylov_hist[k] = kr.iters;
+    if (k < EGFEM_HIST) {
+      stats.krylov_hist[k] = kr.iters;
+      stats.krylov_status_hist[k] = kr.status;
+      stats.krylov_relres_hist[k] = kr.relres;
+    }
     if (kr.status == EGFEM_NONFINITE) { status = EGFEM_NONFINITE; break; }
     // damped update u + alpha delta, residual fused with the trial iterate
     double alpha = 1.0, nFt = 0.0;

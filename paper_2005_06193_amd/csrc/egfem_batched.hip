@@ -20,7 +20,9 @@ dev::TensorView view_of(const egfem_tensor_s* T);
 
 namespace {
 
-constexpr int kStatsWords = 6 + 2 * EGFEM_HIST;   // status, iters, krylov, backtracks, res0, res, hist
+// status, iters, krylov, backtracks, res0, res, then per step: residual, Krylov
+// iterations, Krylov status, Krylov relative residual
+constexpr int kStatsWords = 6 + 4 * EGFEM_HIST;
 
 struct Inst {
   dev::TensorView tv;
@@ -113,6 +115,9 @@ __global__ __launch_bounds__(NT) void k_newton_batched(const Inst* __restrict__ 
   int k = 0, kry = 0, backtracks = 0;
   double* st = I.stats;
   const bool writer = (tm.rank == 0 && tid == 0);
+  // histories start cleared: a replay must not report the previous run's steps
+  if (tm.rank == 0)
+    for (int q = 6 + tid; q < kStatsWords; q += NT) st[q] = 0.0;
 
   while (!abort && status == EGFEM_NOT_CONVERGED) {
     if (nF <= O.tol * nF0) { status = EGFEM_OK; break; }
@@ -129,7 +134,11 @@ __global__ __launch_bounds__(NT) void k_newton_batched(const Inst* __restrict__ 
     const dev::KOut ko = dev::team_bicgstab<NT, L>(tm, KA, rb, re, sh, &sh_abort);
     if ((abort = ko.abort)) break;
     kry += ko.iters;
-    if (writer && k < EGFEM_HIST) st[6 + EGFEM_HIST + k] = (double)ko.iters;
+    if (writer && k < EGFEM_HIST) {
+      st[6 + EGFEM_HIST + k] = (double)ko.iters;
+      st[6 + 2 * EGFEM_HIST + k] = (double)ko.status;
+      st[6 + 3 * EGFEM_HIST + k] = ko.bnorm > 0.0 ? ko.rnorm / ko.bnorm : 0.0;
+    }
     if (ko.status == EGFEM_NONFINITE) { status = EGFEM_NONFINITE; break; }
     if ((abort = dev::team_barrier(tm, &sh_abort))) break;   // correction visible to the team
     // damped update with the residual of the trial iterate
@@ -505,6 +514,11 @@ int egfem_batch_stats(egfem_batch_t B, egfem_newton_stats* stats, void* stream) 
     for (int k = 0; k < EGFEM_HIST && k < o.newton_iters; ++k) {
       o.res_hist[k] = s[6 + k];
       o.krylov_hist[k] = (int)s[6 + EGFEM_HIST + k];
+    }
+    // the Krylov solve of a step that was not accepted is reported too
+    for (int k = 0; k < EGFEM_HIST && k <= o.newton_iters; ++k) {
+      o.krylov_status_hist[k] = (int)s[6 + 2 * EGFEM_HIST + k];
+      o.krylov_relres_hist[k] = s[6 + 3 * EGFEM_HIST + k];
     }
   }
   return worst;

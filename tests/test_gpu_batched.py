@@ -86,6 +86,8 @@ def test_batched_graph_replays_equal_eager():
         for e, u, s, s0 in zip(eager, us, st, st0):
             assert np.array_equal(host(u), e), rep
             assert s.newton_iters == s0.newton_iters and s.krylov_iters == s0.krylov_iters
+            assert s.krylov_status_hist == s0.krylov_status_hist
+            assert s.krylov_relres_hist == s0.krylov_relres_hist
     B.close()
 
 

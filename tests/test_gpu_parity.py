@@ -264,6 +264,12 @@ def test_newton_full_size_2d_256():
     st2 = T.newton(p, u2, eg().NewtonOptions(tol=1e-10, forcing=1), warn=False)
     assert st2.status == 0
     assert st2.res <= 1e-10 * st2.res0
+    # per-step Krylov diagnostics: every accepted step had a converged linear
+    # solve that reduced the residual (forcing terms are below one)
+    k = st2.newton_iters
+    assert len(st2.krylov_status_hist) == min(k + 1, 64) and len(st2.krylov_hist) == k
+    assert all(s == 0 for s in st2.krylov_status_hist[:k])
+    assert all(0.0 < r < 1.0 for r in st2.krylov_relres_hist[:k])
     assert np.linalg.norm(O.residual(po, host(u2))) <= 1.01e-10 * np.linalg.norm(po.d[~po.dirichlet])
 
 
