@@ -145,7 +145,7 @@ void egfem_tensor_destroy(egfem_tensor_t T) {
   if (!T) return;
   free_workspace(T->ws);
   void* ptrs[] = {T->rowptr, T->col, T->diag, T->tperm, T->kptrA, T->kA, T->vA,
-                  T->kval,   T->mval, T->blk_row};
+                  T->kval,   T->mval, T->blk_row, T->blk_meta};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (!T->symmetric) {

@@ -75,16 +75,21 @@ bool cell_geometry(int dim, const double* X, const int32_t* c, Geom& g) {
   return true;
 }
 
+// Every array gets kPad zero elements past its end: the row-block stages load
+// at indices clamped to a range's last element, which for an empty range is
+// the element just past it.
+constexpr size_t kPad = 16;
+
 template <typename T>
 int upload(const std::vector<T>& h, T** d, int64_t* bytes) {
-  size_t nb = std::max<size_t>(h.size(), 1) * sizeof(T);
+  const size_t nb = (h.size() + kPad) * sizeof(T);
   hipError_t e = hipMalloc((void**)d, nb);
   if (e != hipSuccess) return egfem::fail(EGFEM_ERR_OOM, "hipMalloc of tensor stream failed");
   *bytes += (int64_t)nb;
-  if (!h.empty()) {
+  e = hipMemset(*d, 0, nb);
+  if (e == hipSuccess && !h.empty())
     e = hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return egfem::fail(EGFEM_ERR_HIP, "hipMemcpy of tensor stream failed");
-  }
+  if (e != hipSuccess) return egfem::fail(EGFEM_ERR_HIP, "upload of tensor stream failed");
   return EGFEM_OK;
 }
 
@@ -275,6 +280,23 @@ extern "C" int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords
     }
   }
 
+  // per-block bounds in one 32-byte record, so that a block's stream loads
+  // wait on a single (scalar) load instead of three dependent ones
+  std::vector<int32_t> meta((blk.size() - 1) * 8);
+  for (size_t b = 0; b + 1 < blk.size(); ++b) {
+    const int32_t r0 = blk[b], r1 = blk[b + 1];
+    const int32_t s0 = rowptr[r0], s1 = rowptr[r1];
+    int32_t* m = meta.data() + 8 * b;
+    m[0] = r0;
+    m[1] = r1;
+    m[2] = s0;
+    m[3] = s1;
+    m[4] = kptrA[s0];
+    m[5] = kptrA[s1];
+    m[6] = kpB[s0];
+    m[7] = kpB[s1];
+  }
+
   // --- upload -------------------------------------------------------------
   egfem_tensor_s* T = new egfem_tensor_s();
   T->dim = dim;
@@ -311,6 +333,7 @@ extern "C" int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords
   if (rc == EGFEM_OK) rc = upload(kval, &T->kval, &bytes);
   if (rc == EGFEM_OK) rc = upload(mval, &T->mval, &bytes);
   if (rc == EGFEM_OK) rc = upload(blk, &T->blk_row, &bytes);
+  if (rc == EGFEM_OK) rc = upload(meta, &T->blk_meta, &bytes);
   if (sym) {
     T->jptrB = T->kptrA;
     T->jB = T->kA;

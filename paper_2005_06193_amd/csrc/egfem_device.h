@@ -43,6 +43,7 @@ struct TensorView {
   int64_t nblk;
   int sym;
   const int32_t* blk_row;
+  const int4* meta;         // two int4 per block: r0 r1 s0 s1 | pa0 pa1 pb0 pb1
   const int32_t* rowptr;
   const int32_t* col;
   const int32_t* kptrA;
@@ -53,6 +54,16 @@ struct TensorView {
   const double* vB;
   const double* kval;
 };
+
+// Bounds of row block b: rows [r0, r1), slots [s0, s1), A entries [pa0, pa1),
+// B entries [pb0, pb1).  b is uniform, so this is one scalar load.
+struct BlockMeta {
+  int r0, r1, s0, s1, pa0, pa1, pb0, pb1;
+};
+__device__ __forceinline__ BlockMeta block_meta(const TensorView& T, int64_t b) {
+  const int4 x = T.meta[2 * b], y = T.meta[2 * b + 1];
+  return BlockMeta{x.x, x.y, x.z, x.w, y.x, y.y, y.z, y.w};
+}
 
 // LDS scratch of the row-block stages (one block at a time per workgroup).
 struct RowBlockLds {
@@ -90,59 +101,54 @@ struct ActionRegs {
   int cc[Per<NT>::S];
   int kp[Per<NT>::S];
   double kv[Per<NT>::S];
-  int r0, r1, s0, p0, np, ns, nr, rp;
+  int r0, s0, p0, np, ns, nr, rp;
   double ldi;
-  bool di;
+  unsigned char dr;
 };
 
+// Loads are issued without per-entry branches: a load under a divergent
+// branch is followed by a wait for its value (the branch merge copies it), so
+// a thread's loads would complete one after the other.  Indices past the end
+// of a range are clamped to its last element (the streams are padded, so even
+// an empty range clamps in bounds) and the extra values are masked at use.
+__device__ __forceinline__ int clamp_hi(int x, int n) { return min(x, max(n - 1, 0)); }
+
 // Stage 1a of the tensor action: every stream load of this thread for block b
-// (its entries, slots and row), issued without waiting.
+// (its entries, slots and row), issued back to back without waiting.
 template <int NT, bool PROBLEM>
 __device__ __forceinline__ void action_load(const TensorView& T, int64_t b, const double* load,
                                             const uint8_t* dir, const double* kval, ActionRegs<NT>& R) {
   constexpr int PP = Per<NT>::P, SS = Per<NT>::S;
   const int tid = threadIdx.x;
-  R.r0 = T.blk_row[b];
-  R.r1 = T.blk_row[b + 1];
-  R.s0 = T.rowptr[R.r0];
-  const int s1 = T.rowptr[R.r1];
-  R.p0 = T.kptrA[R.s0];
-  const int p1 = T.kptrA[s1];
-  R.np = p1 - R.p0;
-  R.ns = s1 - R.s0;
-  R.nr = R.r1 - R.r0;
+  const BlockMeta m = block_meta(T, b);
+  R.r0 = m.r0;
+  R.s0 = m.s0;
+  R.p0 = m.pa0;
+  R.np = m.pa1 - m.pa0;
+  R.ns = m.s1 - m.s0;
+  R.nr = m.r1 - m.r0;
 #pragma unroll
   for (int q = 0; q < PP; ++q) {
-    const int p = tid + q * NT;
-    R.kk[q] = 0;
-    R.vv[q] = 0.0;
-    if (p < R.np) {
-      R.kk[q] = T.kA[R.p0 + p];
-      R.vv[q] = T.vA[R.p0 + p];
-    }
+    const int p = R.p0 + clamp_hi(tid + q * NT, R.np);
+    R.kk[q] = T.kA[p];
+    R.vv[q] = T.vA[p];
   }
+  // null kval / load / dir are replaced by a valid array and masked at use
+  const double* kvp = kval ? kval : T.kval;
 #pragma unroll
   for (int q = 0; q < SS; ++q) {
-    const int s = tid + q * NT;
-    R.cc[q] = 0;
-    R.kp[q] = 0;
-    R.kv[q] = 0.0;
-    if (s < R.ns) {
-      R.cc[q] = T.col[R.s0 + s];
-      R.kp[q] = T.kptrA[R.s0 + s];
-      if (PROBLEM && kval) R.kv[q] = kval[R.s0 + s];
-    }
+    const int s = R.s0 + clamp_hi(tid + q * NT, R.ns);
+    R.cc[q] = T.col[s];
+    R.kp[q] = T.kptrA[s];
+    R.kv[q] = PROBLEM ? kvp[s] : 0.0;
   }
-  R.rp = 0;
+  const int i = R.r0 + clamp_hi(tid, R.nr);
+  R.rp = T.rowptr[i];
   R.ldi = 0.0;
-  R.di = false;
-  if (tid < R.nr) {
-    const int i = R.r0 + tid;
-    R.rp = T.rowptr[i];
-    if (PROBLEM) {
-      if (load) R.ldi = load[i];
-      R.di = dir && dir[i];
-    }
+  R.dr = 0;
+  if (PROBLEM) {
+    R.ldi = (load ? load : T.kval)[i];
+    R.dr = (dir ? dir : reinterpret_cast<const uint8_t*>(T.kval))[i];
   }
 }
 
@@ -154,42 +160,58 @@ __device__ __forceinline__ void action_load(const TensorView& T, int64_t b, cons
 //            sq += F_i^2 over the rows this thread handled.
 // SH: u, delta gathered with agent-coherent loads and uout written with
 // agent-coherent stores (data produced by other workgroups of the same launch).
+// All gathers of the block are issued before the first product is formed.
 template <int NT, bool PROBLEM, bool SH, typename Lds>
 __device__ __forceinline__ void action_compute(const ActionRegs<NT>& R, const double* u,
                                                const double* delta, double alpha, const double* a,
-                                               double a0c, double* out, double* uout, double& sq,
+                                               double a0c, const double* kval, const double* load,
+                                               const uint8_t* dir, double* out, double* uout, double& sq,
                                                Lds& L) {
   constexpr int PP = Per<NT>::P, SS = Per<NT>::S;
   const int tid = threadIdx.x;
+  const bool has_row = tid < R.nr;
+  const int i = R.r0 + clamp_hi(tid, R.nr);
+  // gathers
+  double gk[PP], dk[PP], ak0[PP], wj[SS], dj[SS];
+  double ui = 0.0, di = 0.0;
+#pragma unroll
+  for (int q = 0; q < PP; ++q) gk[q] = PROBLEM ? ld<SH>(u + R.kk[q]) : a[R.kk[q]];
+#pragma unroll
+  for (int q = 0; q < SS; ++q) wj[q] = ld<SH>(u + R.cc[q]);
+  if (PROBLEM && uout) ui = ld<SH>(u + i);
+  if (PROBLEM && delta) {
+#pragma unroll
+    for (int q = 0; q < PP; ++q) dk[q] = ld<SH>(delta + R.kk[q]);
+#pragma unroll
+    for (int q = 0; q < SS; ++q) dj[q] = ld<SH>(delta + R.cc[q]);
+    if (uout) di = ld<SH>(delta + i);
+  }
+  if (PROBLEM && a) {
+#pragma unroll
+    for (int q = 0; q < PP; ++q) ak0[q] = a[R.kk[q]];
+  }
+  // products and bounds
 #pragma unroll
   for (int q = 0; q < PP; ++q) {
     const int p = tid + q * NT;
     if (p < R.np) {
-      const int k = R.kk[q];
       double ak;
       if (PROBLEM) {
-        double wk = ld<SH>(u + k);
-        if (delta) wk = fma(alpha, ld<SH>(delta + k), wk);
-        ak = fma(wk, wk, a ? a[k] : a0c);
+        double wk = gk[q];
+        if (delta) wk = fma(alpha, dk[q], wk);
+        ak = fma(wk, wk, a ? ak0[q] : a0c);
       } else {
-        ak = a[k];
+        ak = gk[q];
       }
       L.tA[p] = R.vv[q] * ak;
     }
   }
-  double wj[SS];
 #pragma unroll
   for (int q = 0; q < SS; ++q) {
     const int s = tid + q * NT;
-    wj[q] = 0.0;
-    if (s < R.ns) {
-      const int j = R.cc[q];
-      wj[q] = ld<SH>(u + j);
-      if (PROBLEM && delta) wj[q] = fma(alpha, ld<SH>(delta + j), wj[q]);
-      L.spa[s] = R.kp[q] - R.p0;
-    }
+    if (PROBLEM && delta) wj[q] = fma(alpha, dj[q], wj[q]);
+    if (s < R.ns) L.spa[s] = R.kp[q] - R.p0;
   }
-  const bool has_row = tid < R.nr;
   if (tid == 0) {
     L.spa[R.ns] = R.np;
     L.srow[R.nr] = R.ns;
@@ -203,22 +225,22 @@ __device__ __forceinline__ void action_compute(const ActionRegs<NT>& R, const do
     if (s < R.ns) {
       double acc = 0.0;
       for (int t = L.spa[s]; t < L.spa[s + 1]; ++t) acc += L.tA[t];
-      L.y[s] = (acc + R.kv[q]) * wj[q];
+      if (PROBLEM && kval) acc += R.kv[q];
+      L.y[s] = acc * wj[q];
     }
   }
   __syncthreads();
   // row sums
   if (has_row) {
-    const int i = R.r0 + tid;
     double acc = 0.0;
     for (int t = L.srow[tid]; t < L.srow[tid + 1]; ++t) acc += L.y[t];
     if (PROBLEM) {
-      acc -= R.ldi;
-      if (R.di) acc = 0.0;
+      const bool drow = dir && R.dr;
+      if (load) acc -= R.ldi;
+      if (drow) acc = 0.0;
       if (uout) {
-        double wi = ld<SH>(u + i);
-        if (delta) wi = fma(alpha, ld<SH>(delta + i), wi);
-        wi = R.di ? 0.0 : wi;
+        double wi = delta ? fma(alpha, di, ui) : ui;
+        wi = drow ? 0.0 : wi;
         if (SH) st_sh(uout + i, wi);
         else uout[i] = wi;
       }
@@ -237,7 +259,7 @@ __device__ void rowblock_action(const TensorView& T, int64_t b, const double* u,
                                 double& sq, Lds& L) {
   ActionRegs<NT> R;
   action_load<NT, PROBLEM>(T, b, load, dir, kval, R);
-  action_compute<NT, PROBLEM, SH>(R, u, delta, alpha, a, a0c, out, uout, sq, L);
+  action_compute<NT, PROBLEM, SH>(R, u, delta, alpha, a, a0c, kval, load, dir, out, uout, sq, L);
 }
 
 // Tensor action over the contiguous block range [b0, b1) of one workgroup,
@@ -266,10 +288,10 @@ __device__ void rowblocks_action_pipelined(const TensorView& T, int64_t b0, int6
   action_load<NT, PROBLEM>(T, b0, load, dir, kval, RA);
   for (int64_t b = b0; b < b1; b += 2) {
     if (b + 1 < b1) action_load<NT, PROBLEM>(T, b + 1, load, dir, kval, RB);
-    action_compute<NT, PROBLEM, SH>(RA, u, delta, alpha, a, a0c, out, uout, sq, L);
+    action_compute<NT, PROBLEM, SH>(RA, u, delta, alpha, a, a0c, kval, load, dir, out, uout, sq, L);
     if (b + 1 >= b1) break;
     if (b + 2 < b1) action_load<NT, PROBLEM>(T, b + 2, load, dir, kval, RA);
-    action_compute<NT, PROBLEM, SH>(RB, u, delta, alpha, a, a0c, out, uout, sq, L);
+    action_compute<NT, PROBLEM, SH>(RB, u, delta, alpha, a, a0c, kval, load, dir, out, uout, sq, L);
   }
 }
 
@@ -287,79 +309,91 @@ __device__ void rowblock_jacobian(const TensorView& T, int64_t b, const double* 
                                   double* dinv, RowBlockLds& L) {
   constexpr int PP = Per<NT>::P, SS = Per<NT>::S;
   const int tid = threadIdx.x;
-  const int r0 = T.blk_row[b], r1 = T.blk_row[b + 1];
-  const int s0 = T.rowptr[r0], s1 = T.rowptr[r1];
-  const int pa0 = T.kptrA[s0], pa1 = T.kptrA[s1];
-  const int pb0 = T.jptrB[s0], pb1 = T.jptrB[s1];
-  const int na = pa1 - pa0, nb = pb1 - pb0, ns = s1 - s0, nr = r1 - r0;
+  const BlockMeta m = block_meta(T, b);
+  const int r0 = m.r0, s0 = m.s0, pa0 = m.pa0, pb0 = m.pb0;
+  const int na = m.pa1 - m.pa0, nb = m.pb1 - m.pb0, ns = m.s1 - m.s0, nr = m.r1 - m.r0;
   const bool second = dadu || dadu_2u;
   const bool bstream = second && !T.sym;
-  // stage 1a: stream loads
+  const bool need_uk = problem_a || (T.sym && second);
+  // stage 1a: stream loads, back to back at clamped indices (see action_load)
   int ka[PP], jb[PP];
   double va[PP], vb[PP];
 #pragma unroll
   for (int q = 0; q < PP; ++q) {
-    const int p = tid + q * NT;
-    ka[q] = 0;
-    va[q] = 0.0;
-    jb[q] = 0;
-    vb[q] = 0.0;
-    if (p < na) {
-      ka[q] = T.kA[pa0 + p];
-      va[q] = T.vA[pa0 + p];
-    }
-    if (bstream && p < nb) {
-      jb[q] = T.jB[pb0 + p];
-      vb[q] = T.vB[pb0 + p];
+    const int p = pa0 + clamp_hi(tid + q * NT, na);
+    ka[q] = T.kA[p];
+    va[q] = T.vA[p];
+  }
+  if (bstream) {
+#pragma unroll
+    for (int q = 0; q < PP; ++q) {
+      const int p = pb0 + clamp_hi(tid + q * NT, nb);
+      jb[q] = T.jB[p];
+      vb[q] = T.vB[p];
     }
   }
   int cc[SS], kpa[SS], kpb[SS];
   double kv[SS];
+  const double* kvp = kval ? kval : T.kval;
 #pragma unroll
   for (int q = 0; q < SS; ++q) {
-    const int s = tid + q * NT;
-    cc[q] = kpa[q] = kpb[q] = 0;
-    kv[q] = 0.0;
-    if (s < ns) {
-      cc[q] = T.col[s0 + s];
-      kpa[q] = T.kptrA[s0 + s];
-      kpb[q] = T.jptrB[s0 + s];
-      if (kval) kv[q] = kval[s0 + s];
-    }
+    const int s = s0 + clamp_hi(tid + q * NT, ns);
+    cc[q] = T.col[s];
+    kpa[q] = T.kptrA[s];
+    kpb[q] = T.jptrB[s];
+    kv[q] = kvp[s];
   }
   const bool has_row = tid < nr;
-  const int i = r0 + tid;
-  int rpa = 0, rpb = 0;
-  bool drow = false;
-  if (has_row) {
-    rpa = T.rowptr[i];
-    rpb = T.rowptr[i + 1];
-    drow = dir && dir[i];
+  const int i = r0 + clamp_hi(tid, nr);
+  const int rpa = T.rowptr[i], rpb = T.rowptr[i + 1];
+  const unsigned char drow_raw = (dir ? dir : reinterpret_cast<const uint8_t*>(T.kval))[i];
+  // stage 1b: gathers (all issued before the products), products, bounds
+  double uk[PP], gk[PP], ub[PP];
+  if (need_uk) {
+#pragma unroll
+    for (int q = 0; q < PP; ++q) uk[q] = ld<SH>(u + ka[q]);
   }
-  // stage 1b: gathers, products, bounds
+  const double* ga = problem_a ? a0 : a;   // a0 may be null (constant a0c)
+  if (ga) {
+#pragma unroll
+    for (int q = 0; q < PP; ++q) gk[q] = ga[ka[q]];
+  }
+  if (bstream) {
+#pragma unroll
+    for (int q = 0; q < PP; ++q) ub[q] = ld<SH>(u + jb[q]);
+  }
+  double gj[SS];
+  unsigned char dcr[SS];
+#pragma unroll
+  for (int q = 0; q < SS; ++q) {
+    gj[q] = 0.0;
+    dcr[q] = 0;
+  }
+  if (dadu) {
+#pragma unroll
+    for (int q = 0; q < SS; ++q) gj[q] = dadu[cc[q]];
+  } else if (second) {
+#pragma unroll
+    for (int q = 0; q < SS; ++q) gj[q] = ld<SH>(u + cc[q]);
+  }
+  if (dir) {
+#pragma unroll
+    for (int q = 0; q < SS; ++q) dcr[q] = dir[cc[q]];
+  }
 #pragma unroll
   for (int q = 0; q < PP; ++q) {
     const int p = tid + q * NT;
     if (p < na) {
-      const int k = ka[q];
-      const double uk = ld<SH>(u + k);
-      const double ak = problem_a ? fma(uk, uk, a0 ? a0[k] : a0c) : a[k];
+      const double ak = problem_a ? fma(uk[q], uk[q], a0 ? gk[q] : a0c) : gk[q];
       L.tA[p] = va[q] * ak;
-      if (T.sym && second) L.tB[p] = va[q] * uk;
+      if (T.sym && second) L.tB[p] = va[q] * uk[q];
     }
-    if (bstream && p < nb) L.tB[p] = vb[q] * ld<SH>(u + jb[q]);
+    if (bstream && p < nb) L.tB[p] = vb[q] * ub[q];
   }
-  double gj[SS];
-  bool dcol[SS];
 #pragma unroll
   for (int q = 0; q < SS; ++q) {
     const int s = tid + q * NT;
-    gj[q] = 0.0;
-    dcol[q] = false;
     if (s < ns) {
-      const int j = cc[q];
-      if (second) gj[q] = dadu ? dadu[j] : 2.0 * ld<SH>(u + j);
-      dcol[q] = dir && dir[j];
       L.spa[s] = kpa[q] - pa0;
       L.spb[s] = kpb[q] - pb0;
     }
@@ -369,7 +403,7 @@ __device__ void rowblock_jacobian(const TensorView& T, int64_t b, const double* 
     L.spb[ns] = nb;
   }
   if (has_row) {
-    L.sdir[tid] = drow ? 1 : 0;
+    L.sdir[tid] = (dir && drow_raw) ? 1 : 0;
     for (int s = rpa - s0; s < rpb - s0; ++s) L.srid[s] = tid;
   }
   __syncthreads();
@@ -384,16 +418,17 @@ __device__ void rowblock_jacobian(const TensorView& T, int64_t b, const double* 
       double J;
       if (L.sdir[ir]) {
         J = (j == row) ? 1.0 : 0.0;
-      } else if (dcol[q]) {
+      } else if (dcr[q]) {
         J = 0.0;
       } else {
         double qa = 0.0;
         for (int t = L.spa[s]; t < L.spa[s + 1]; ++t) qa += L.tA[t];
-        J = kv[q] + qa;
+        J = (kval ? kv[q] : 0.0) + qa;
         if (second) {
           double qb = 0.0;
           for (int t = L.spb[s]; t < L.spb[s + 1]; ++t) qb += L.tB[t];
-          J = fma(gj[q], qb, J);
+          const double g = dadu ? gj[q] : 2.0 * gj[q];
+          J = fma(g, qb, J);
         }
       }
       jval[s0 + s] = J;

@@ -95,6 +95,7 @@ struct egfem_tensor_s {
   double* kval = nullptr;       // [slots]
   double* mval = nullptr;       // [slots]
   int32_t* blk_row = nullptr;   // [row_blocks+1]
+  int32_t* blk_meta = nullptr;  // [row_blocks*8]: rows, slots, A range, B range of each block
   int64_t row_blocks = 0;
   std::vector<int32_t> h_rowptr;  // host copy (row partitions)
   int64_t device_bytes = 0;

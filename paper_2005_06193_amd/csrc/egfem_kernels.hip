@@ -51,6 +51,7 @@ dev::TensorView view_of(const egfem_tensor_s* T) {
   v.nblk = T->row_blocks;
   v.sym = T->symmetric;
   v.blk_row = T->blk_row;
+  v.meta = reinterpret_cast<const int4*>(T->blk_meta);
   v.rowptr = T->rowptr;
   v.col = T->col;
   v.kptrA = T->kptrA;
