@@ -216,6 +216,7 @@ typedef struct {
   int n_krylov;
   int krylov_status_hist[EGFEM_HIST];     /* Krylov status of step k */
   double krylov_relres_hist[EGFEM_HIST];  /* Krylov relative residual of step k */
+  int krylov_kernels;        /* BiCGStab kernels that ran: bit 0 register-resident, bit 1 streaming */
 } egfem_newton_stats;
 
 /* Fill opts with the defaults above. */
@@ -250,6 +251,9 @@ typedef struct {
                                 before the current block's gathers), 0: one block at a time */
   int krylov_blocks;         /* persistent BiCGStab grid (0 = heuristic) */
   int krylov_threads;        /* persistent BiCGStab workgroup size 256/512/1024 (0 = 1024) */
+  int krylov_kernel;         /* 0: register-resident BiCGStab (one thread per row) when every
+                                workgroup's rows fit its threads and rows hold at most 8
+                                entries, else the streaming one; 1: always the streaming one */
 } egfem_launch_shape;
 
 int egfem_get_shape(egfem_tensor_t T, egfem_launch_shape* s);
@@ -260,8 +264,8 @@ int egfem_set_shape(egfem_tensor_t T, const egfem_launch_shape* s);
 /* Autotuner: time the candidate shapes on this handle's own tensor with HIP
  * events on `stream` and keep the fastest in the handle.
  *   what: bit 0 -> tensor action (runs x {pipelined, not}); bit 1 -> Krylov grid
- *         (threads x blocks, per-iteration time of BiCGStab on DF(0) of problem p,
- *         which must then be non-NULL).
+ *         (kernel x threads x blocks, per-iteration time of BiCGStab on DF(0) of
+ *         problem p, which must then be non-NULL).
  *   best (host, nullable) receives the chosen shape; best_us (host [2], nullable)
  *   the chosen action launch time and Krylov iteration time in microseconds.
  * Overwrites the handle's solver workspace.  Synchronises the stream. */

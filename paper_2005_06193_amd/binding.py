@@ -66,7 +66,7 @@ class _Opts(C.Structure):
 
 class _Shape(C.Structure):
     _fields_ = [("action_runs", C.c_int), ("action_pipe", C.c_int), ("krylov_blocks", C.c_int),
-                ("krylov_threads", C.c_int)]
+                ("krylov_threads", C.c_int), ("krylov_kernel", C.c_int)]
 
 
 class _Stats(C.Structure):
@@ -76,7 +76,7 @@ class _Stats(C.Structure):
                 ("t_action_ms", C.c_double), ("t_jacobian_ms", C.c_double),
                 ("t_krylov_ms", C.c_double), ("n_action", C.c_int), ("n_jacobian", C.c_int),
                 ("n_krylov", C.c_int), ("krylov_status_hist", C.c_int * HIST),
-                ("krylov_relres_hist", C.c_double * HIST)]
+                ("krylov_relres_hist", C.c_double * HIST), ("krylov_kernels", C.c_int)]
 
 
 _lib = None
@@ -225,6 +225,7 @@ class NewtonStats:
     n_krylov: int = 0
     krylov_status_hist: List[int] = None
     krylov_relres_hist: List[float] = None
+    krylov_kernels: int = 0
 
     @property
     def status_name(self) -> str:
@@ -236,7 +237,8 @@ class NewtonStats:
         return cls(s.status, s.newton_iters, s.krylov_iters, s.backtracks, s.res0, s.res,
                    list(s.res_hist[:k]), list(s.krylov_hist[:k]), s.t_action_ms, s.t_jacobian_ms,
                    s.t_krylov_ms, s.n_action, s.n_jacobian, s.n_krylov,
-                   list(s.krylov_status_hist[:k + 1]), list(s.krylov_relres_hist[:k + 1]))
+                   list(s.krylov_status_hist[:k + 1]), list(s.krylov_relres_hist[:k + 1]),
+                   s.krylov_kernels)
 
 
 class Problem:

@@ -358,6 +358,7 @@ int egfem_newton(egfem_tensor_t T, const egfem_problem* p, double* u, const egfe
       ++stats.n_krylov;
     }
     stats.krylov_iters += kr.iters;
+    stats.krylov_kernels |= kr.resident ? 1 : 2;
     if (k < EGFEM_HIST) {
       stats.krylov_hist[k] = kr.iters;
       stats.krylov_status_hist[k] = kr.status;

@@ -511,6 +511,7 @@ int egfem_batch_stats(egfem_batch_t B, egfem_newton_stats* stats, void* stream) 
     o.backtracks = (int)s[3];
     o.res0 = s[4];
     o.res = s[5];
+    o.krylov_kernels = o.newton_iters > 0 ? 2 : 0;   // the team BiCGStab streams its rows
     for (int k = 0; k < EGFEM_HIST && k < o.newton_iters; ++k) {
       o.res_hist[k] = s[6 + k];
       o.krylov_hist[k] = (int)s[6 + EGFEM_HIST + k];

@@ -449,101 +449,148 @@ struct Team {
   unsigned epoch;     // barriers passed so far
 };
 
-// Epoch-counting barrier (no counter resets).  Every wave first waits until
-// its own stores are complete (s_waitcnt vmcnt(0)); data exchanged between
-// workgroups is written and read with agent-coherent accesses, so no cache
-// write-back or invalidation is needed.  Arrivals are counted per group, the
-// last of each group arrives at the team counter, the last team arrival
-// publishes the new epoch, everyone else polls it.  Returns true when the team
-// aborted (a wait exceeded kSpinCap).
+// Arrival at and wait for team barrier number `epoch`, by one thread of the
+// workgroup, after the workgroup's stores are complete.  Epoch counting (no
+// counter resets): arrivals are counted per group, the last of each group
+// arrives at the team counter, the last team arrival publishes the new epoch,
+// everyone else polls it.  All accesses are relaxed agent-scope atomics; data
+// exchanged between workgroups is written and read with agent-coherent
+// accesses, so no cache write-back or invalidation is needed.  Returns
+// nonzero when the team aborted (a wait exceeded kSpinCap).
+__device__ inline int barrier_arrive_wait(const Team& tm, unsigned epoch) {
+  unsigned* ctrl = tm.ctrl;
+  const unsigned G = tm.size;
+  const unsigned ng = G < (unsigned)kGroups ? G : (unsigned)kGroups;
+  const unsigned grp = tm.rank % ng;
+  const unsigned gsz = (G - grp + ng - 1) / ng;   // ranks r < G with r % ng == grp
+  int ab = (int)__hip_atomic_load(ctrl + kCtrlAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (ab) return ab;
+  const unsigned prev = __hip_atomic_fetch_add(ctrl + kCtrlGroup + 32 * grp, 1u, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+  bool last = false;
+  if (prev == (epoch + 1) * gsz - 1) {
+    const unsigned prev2 = __hip_atomic_fetch_add(ctrl + kCtrlAll, 1u, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+    last = (prev2 == (epoch + 1) * ng - 1);
+  }
+  if (last) {
+    __hip_atomic_store(ctrl + kCtrlGen, epoch + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return 0;
+  }
+  unsigned spins = 0;
+  while (__hip_atomic_load(ctrl + kCtrlGen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= epoch) {
+    __builtin_amdgcn_s_sleep(1);
+    if (++spins >= kSpinCap) {
+      __hip_atomic_store(ctrl + kCtrlAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return 1;
+    }
+    if ((spins & 1023u) == 0 &&
+        __hip_atomic_load(ctrl + kCtrlAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      return 1;
+  }
+  return 0;
+}
+
+// Team barrier.  Every wave first waits until its own stores are complete
+// (s_waitcnt vmcnt(0)).  Returns true when the team aborted.
 __device__ inline bool team_barrier(Team& tm, int* sh_abort) {
   __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's stores are complete
   __syncthreads();
   const unsigned epoch = tm.epoch++;
-  if (threadIdx.x == 0) {
-    unsigned* ctrl = tm.ctrl;
-    const unsigned G = tm.size;
-    const unsigned ng = G < (unsigned)kGroups ? G : (unsigned)kGroups;
-    const unsigned grp = tm.rank % ng;
-    const unsigned gsz = (G - grp + ng - 1) / ng;   // ranks r < G with r % ng == grp
-    int ab = (int)__hip_atomic_load(ctrl + kCtrlAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (!ab) {
-      const unsigned prev = __hip_atomic_fetch_add(ctrl + kCtrlGroup + 32 * grp, 1u, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-      bool last = false;
-      if (prev == (epoch + 1) * gsz - 1) {
-        const unsigned prev2 = __hip_atomic_fetch_add(ctrl + kCtrlAll, 1u, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
-        last = (prev2 == (epoch + 1) * ng - 1);
-      }
-      if (last) {
-        __hip_atomic_store(ctrl + kCtrlGen, epoch + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      } else {
-        unsigned spins = 0;
-        while (__hip_atomic_load(ctrl + kCtrlGen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= epoch) {
-          __builtin_amdgcn_s_sleep(1);
-          if (++spins >= kSpinCap) {
-            __hip_atomic_store(ctrl + kCtrlAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            ab = 1;
-            break;
-          }
-          if ((spins & 1023u) == 0 &&
-              __hip_atomic_load(ctrl + kCtrlAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-            ab = 1;
-            break;
-          }
-        }
-      }
-    }
-    *sh_abort = ab;
-  }
+  if (threadIdx.x == 0) *sh_abort = barrier_arrive_wait(tm, epoch);
   __syncthreads();
   return *sh_abort != 0;
 }
 
-// Deterministic block sum of up to kMaxRed values; results broadcast to all threads.
-template <int NT>
-__device__ void block_sum(double (&v)[kMaxRed], int m, double* sh) {
-  constexpr int NW = NT / kWave;
-  for (int q = 0; q < m; ++q) {
-    double x = v[q];
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_down(x, off, kWave);
-    if ((threadIdx.x & (kWave - 1)) == 0) sh[q * NW + threadIdx.x / kWave] = x;
-  }
-  __syncthreads();
-  if (threadIdx.x < (unsigned)m) {
-    double acc = 0.0;
-    for (int w = 0; w < NW; ++w) acc += sh[threadIdx.x * NW + w];
-    sh[kMaxRed * NW + threadIdx.x] = acc;
-  }
-  __syncthreads();
-  for (int q = 0; q < m; ++q) v[q] = sh[kMaxRed * NW + q];
-  __syncthreads();
+// Sum of x over the 64 lanes of a wave, returned in every lane, by DPP lane
+// moves (a few cycles per step, unlike an LDS permute): pairs and quads
+// (quad_perm), half rows and rows (mirrors), then rows 0+1 and 2+3
+// (row_bcast:15) and the two halves (row_bcast:31) leave the total in lane 63,
+// which is read back as a scalar.  The order of the additions is fixed.
+// Requires all 64 lanes active.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ double wave_sum(double x) {
+  x += dpp_move<0xB1, 0xf>(x);    // quad_perm [1,0,3,2]
+  x += dpp_move<0x4E, 0xf>(x);    // quad_perm [2,3,0,1]
+  x += dpp_move<0x141, 0xf>(x);   // row_half_mirror
+  x += dpp_move<0x140, 0xf>(x);   // row_mirror
+  x += dpp_move<0x142, 0xa>(x);   // row_bcast:15 into rows 1 and 3
+  x += dpp_move<0x143, 0xc>(x);   // row_bcast:31 into rows 2 and 3
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
 template <int NT>
 constexpr int kShWords = kMaxRed * (NT / kWave) + kMaxRed;
 
-// Publish this workgroup's block sums into reduction slot `slot`, pass the
-// team barrier, then add the team's partials of every value in a fixed order.
+// Team all-reduce of m <= kMaxRed values (every thread contributes v[q],
+// every thread receives the team totals), with one team barrier:
+//   1. every wave sums its lanes (wave_sum) into LDS; the waves' stores are
+//      complete before the workgroup sync;
+//   2. wave 0 adds the wave sums (fixed order), publishes the workgroup's
+//      partials in reduction slot `slot` ([q][rank]), arrives and waits;
+//   3. wave q (q < m; waves take several values when there are fewer waves
+//      than values) reads the G partials of value q at once, adds them in a
+//      fixed order (lane l: ranks l, l+64, ...; then wave_sum) and puts the
+//      total in LDS for every thread.
+// The order of every addition is fixed, so results are reproducible.
 template <int NT>
 __device__ bool team_reduce(Team& tm, int slot, double (&v)[kMaxRed], int m, double* sh,
                             int* sh_abort) {
+  constexpr int NW = NT / kWave;
   const unsigned G = tm.size;
-  block_sum<NT>(v, m, sh);
-  if (threadIdx.x == 0)
-    for (int q = 0; q < m; ++q) st_sh(tm.red + ((size_t)slot * kMaxRed + q) * G + tm.rank, v[q]);
-  if (team_barrier(tm, sh_abort)) return true;
-  double w[kMaxRed];
-  for (int q = 0; q < m; ++q) {
-    const double* src = tm.red + ((size_t)slot * kMaxRed + q) * G;
-    double acc = 0.0;
-    for (unsigned g = threadIdx.x; g < G; g += NT) acc += ld_sh(src + g);
-    w[q] = acc;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+#pragma unroll
+  for (int q = 0; q < kMaxRed; ++q) {
+    if (q < m) {
+      const double x = wave_sum(v[q]);
+      if (lane == 0) sh[q * NW + wave] = x;
+    }
   }
-  block_sum<NT>(w, m, sh);
-  for (int q = 0; q < m; ++q) v[q] = w[q];
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's stores are complete
+  __syncthreads();
+  const unsigned epoch = tm.epoch++;
+  double* part = tm.red + (size_t)slot * kMaxRed * G;
+  if (wave == 0) {
+    if (lane < m) {
+      double acc = 0.0;
+      for (int w = 0; w < NW; ++w) acc += sh[lane * NW + w];
+      st_sh(part + (size_t)lane * G + tm.rank, acc);
+    }
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    if (lane == 0) *sh_abort = barrier_arrive_wait(tm, epoch);
+  }
+  __syncthreads();
+  if (*sh_abort) return true;
+  const int R = (int)((G + kWave - 1) / kWave);
+  for (int q = wave; q < m; q += NW) {
+    const double* src = part + (size_t)q * G;
+    double acc = 0.0;
+    for (int r0 = 0; r0 < R; r0 += 4) {
+      double y[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) y[r] = ld_sh(src + min((unsigned)(lane + kWave * (r0 + r)), G - 1));
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if ((unsigned)(lane + kWave * (r0 + r)) < G) acc += y[r];
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) sh[kMaxRed * NW + q] = acc;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kMaxRed; ++q)
+    if (q < m) v[q] = sh[kMaxRed * NW + q];
+  __syncthreads();   // sh is reused by the next reduction
   return false;
 }
 
@@ -577,6 +624,10 @@ struct KOut {
 
 // Rows [rb, re), L lanes per row: f(i, (J x1)_i, (J x2)_i) on lane 0 of each
 // row's group (x2 may be null); x1 / x2 gathered coherently when SH.
+// L is chosen >= half the longest row, so a lane's first two entries are
+// loaded unconditionally at clamped slots (every row holds its diagonal, so
+// the clamp stays in the row) and masked after: the index, value and gather
+// loads of both entries are in flight together.  Longer rows finish in a loop.
 template <int NT, int L, bool SH, typename Fn>
 __device__ __forceinline__ void spmv_rows(const KArgs& A, int rb, int re, const double* __restrict__ x1,
                                           const double* __restrict__ x2, Fn f) {
@@ -585,10 +636,33 @@ __device__ __forceinline__ void spmv_rows(const KArgs& A, int rb, int re, const 
   const int lane = threadIdx.x % L;
   for (int base = rb; base < re; base += RPP) {
     const int i = base + sub;
-    double acc1 = 0.0, acc2 = 0.0;
-    if (i < re) {
-      const int e = A.rowptr[i + 1];
-      for (int s = A.rowptr[i] + lane; s < e; s += L) {
+    const bool row = i < re;
+    const int ic = min(i, re - 1);
+    const int beg = A.rowptr[ic], end = A.rowptr[ic + 1];
+    const int s0 = beg + lane, s1 = s0 + L;
+    const int q0 = min(s0, end - 1), q1 = min(s1, end - 1);
+    const int c0 = A.col[q0], c1 = A.col[q1];
+    int v0 = q0, v1 = q1;
+    if (A.perm) {
+      v0 = A.perm[q0];
+      v1 = A.perm[q1];
+    }
+    const double a0 = A.val[v0], a1 = A.val[v1];
+    const double y0 = ld<SH>(x1 + c0), y1 = ld<SH>(x1 + c1);
+    double z0 = 0.0, z1 = 0.0;
+    if (x2) {
+      z0 = ld<SH>(x2 + c0);
+      z1 = ld<SH>(x2 + c1);
+    }
+    const bool m0 = row && s0 < end, m1 = row && s1 < end;
+    double acc1 = m0 ? a0 * y0 : 0.0;
+    double acc2 = m0 ? a0 * z0 : 0.0;
+    if (m1) {
+      acc1 = fma(a1, y1, acc1);
+      acc2 = fma(a1, z1, acc2);
+    }
+    if (row) {
+      for (int s = s1 + L; s < end; s += L) {
         const double a = A.perm ? A.val[A.perm[s]] : A.val[s];
         const int c = A.col[s];
         acc1 = fma(a, ld<SH>(x1 + c), acc1);
@@ -600,7 +674,7 @@ __device__ __forceinline__ void spmv_rows(const KArgs& A, int rb, int re, const 
       acc1 += __shfl_xor(acc1, off, L);
       acc2 += __shfl_xor(acc2, off, L);
     }
-    if (i < re && lane == 0) f(i, acc1, acc2);
+    if (row && lane == 0) f(i, acc1, acc2);
   }
 }
 
@@ -747,6 +821,177 @@ __device__ KOut team_bicgstab(Team& tm, const KArgs& A, int rb, int re, double* 
   o.iters = it;
   o.rnorm = rnorm;
   o.bnorm = bnorm;
+  return o;
+}
+
+// Jacobi-BiCGStab with the team's rows resident in registers: one thread per
+// row (the workgroup's rows fit its threads) keeps the row's K matrix entries
+// (rows hold at most K entries), its diagonal inverse and the row's vectors
+// r, rhat, p, v, z, s, t, x for the whole solve.  Memory traffic per iteration
+// is then the gathered vectors D^-1 p, D^-1 r, D^-1 v (agent-coherent), the
+// partial sums, and x once at the end.  Same iteration as team_bicgstab, with
+// (r, r) reduced together with (rhat, v) at the start of the next iteration,
+// so the third synchronisation of an iteration is a plain barrier:
+//   A: v = J phat, z = J rh                     -> (rhat, v), (r, r)   reduce
+//      stop / restart decisions on ||r||
+//   B: y = J vh; s = r - alpha v; t = z - alpha y
+//                               -> (t,s) (t,t) (rhat,s) (rhat,t) (s,s) reduce
+//   C: x, r, p; publish phat = D^-1 p, rh = D^-1 r                    barrier
+// Row product sum_k a_k x[col_k] with the columns held as byte offsets.  The
+// base pointer passes through an empty asm statement, so the compiler cannot
+// hoist the per-entry 64-bit addresses out of the iteration loop (they would
+// occupy two registers per entry and vector for the whole solve); the loads
+// use the scalar base plus the 32-bit offset.
+template <int K>
+__device__ __forceinline__ double row_dot(const unsigned (&off)[K], const double (&a)[K], const double* x) {
+  const char* base = reinterpret_cast<const char*>(x);
+  __asm__ volatile("" : "+s"(base));
+  double g[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) g[k] = ld_sh(reinterpret_cast<const double*>(base + off[k]));
+  double acc = a[0] * g[0];
+#pragma unroll
+  for (int k = 1; k < K; ++k) acc = fma(a[k], g[k], acc);
+  return acc;
+}
+
+template <int NT, int K>
+__device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, double* sh, int* sh_abort) {
+  double red[kMaxRed];
+  KOut o{EGFEM_NOT_CONVERGED, 0, 0.0, 0.0, false};
+#define EGFEM_ZERO_RED() for (int q_ = 0; q_ < kMaxRed; ++q_) red[q_] = 0.0
+  const int i = rb + (int)threadIdx.x;
+  const bool own = i < re;
+  const int row = max(min(i, re - 1), 0);   // in bounds also for an empty row range
+  // ---- the row's matrix entries (clamped in the row, zero past its end) ----
+  int vi[K];
+  unsigned cc[K];   // columns as byte offsets into a vector
+  double aa[K];
+  const int beg = A.rowptr[row], end = A.rowptr[row + 1];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    vi[k] = min(beg + k, end - 1);
+    cc[k] = (unsigned)A.col[vi[k]] * 8u;
+  }
+  if (A.perm) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) vi[k] = A.perm[vi[k]];
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const double w = A.val[vi[k]];
+    aa[k] = (own && beg + k < end) ? w : 0.0;
+  }
+  const double d = A.dinv[row];
+  const double b = A.rhs_scale * A.rhs[row];
+  // ---- r = b - J x ; rhat = p = r ; publish D^-1 r --------------------------
+  double x = 0.0, r = b;
+  if (!A.x_zero) {
+    double g[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) g[k] = A.x[cc[k] / 8u];
+    x = A.x[row];
+    double acc = aa[0] * g[0];
+#pragma unroll
+    for (int k = 1; k < K; ++k) acc = fma(aa[k], g[k], acc);
+    r = b - acc;
+  }
+  double rh = r, p = r, v = 0.0, z = 0.0, sv = 0.0, tv = 0.0;
+  EGFEM_ZERO_RED();
+  if (own) {
+    st_sh(A.phat + row, d * r);
+    st_sh(A.rh + row, d * r);
+    red[1] = b * b;
+  }
+  if ((o.abort = team_reduce<NT>(tm, 0, red, 2, sh, sh_abort))) return o;
+  const double bnorm = sqrt(red[1]);
+  o.bnorm = bnorm;
+  if (bnorm == 0.0) {
+    if (own) A.x[row] = 0.0;
+    o.status = EGFEM_OK;
+    return o;
+  }
+  double rho = 0.0, rnorm = 0.0, r0norm = -1.0;
+  int restarts = 0, slot = 1, it = 0;
+  while (true) {
+    // A: v = J phat, z = J rh ; (rhat, v), (r, r)
+    v = row_dot<K>(cc, aa, A.phat);
+    z = row_dot<K>(cc, aa, A.rh);
+    EGFEM_ZERO_RED();
+    if (own) {
+      st_sh(A.vh + row, d * v);
+      red[0] = rh * v;
+      red[1] = r * r;
+    }
+    if ((o.abort = team_reduce<NT>(tm, slot, red, 2, sh, sh_abort))) break;
+    slot = slot % 6 + 1;
+    const double rv = red[0];
+    rnorm = sqrt(red[1]);
+    if (r0norm < 0.0) {
+      r0norm = rnorm;
+      rho = red[1];
+    }
+    if (!isfinite(rnorm) || !isfinite(rho)) { o.status = EGFEM_NONFINITE; break; }
+    if (rnorm <= A.rtol * bnorm) { o.status = EGFEM_OK; break; }
+    if (it >= A.max_iter) { o.status = EGFEM_NOT_CONVERGED; break; }
+    if (fabs(rho) <= 1e-15 * r0norm * rnorm) {
+      // lost bi-orthogonality: restart once from the current residual
+      if (restarts++ >= 1) { o.status = EGFEM_BREAKDOWN; break; }
+      rh = r;
+      p = r;
+      if (own) st_sh(A.phat + row, d * r);
+      rho = red[1];
+      if ((o.abort = team_barrier(tm, sh_abort))) break;
+      continue;
+    }
+    if (rv == 0.0 || !isfinite(rv)) { o.status = isfinite(rv) ? EGFEM_BREAKDOWN : EGFEM_NONFINITE; break; }
+    const double alpha = rho / rv;
+    // B: y = J vh ; s, t
+    {
+      const double y = row_dot<K>(cc, aa, A.vh);
+      sv = fma(-alpha, v, r);
+      tv = fma(-alpha, y, z);
+      EGFEM_ZERO_RED();
+      if (own) {
+        red[0] = tv * sv;
+        red[1] = tv * tv;
+        red[2] = rh * sv;
+        red[3] = rh * tv;
+        red[4] = sv * sv;
+      }
+    }
+    if ((o.abort = team_reduce<NT>(tm, slot, red, 5, sh, sh_abort))) break;
+    slot = slot % 6 + 1;
+    ++it;
+    if (sqrt(red[4]) <= A.rtol * bnorm) {
+      x = fma(alpha, d * p, x);
+      rnorm = sqrt(red[4]);
+      o.status = EGFEM_OK;
+      break;
+    }
+    if (red[1] == 0.0 || !isfinite(red[1])) {
+      o.status = isfinite(red[1]) ? EGFEM_BREAKDOWN : EGFEM_NONFINITE;
+      break;
+    }
+    const double omega = red[0] / red[1];
+    if (omega == 0.0) { o.status = EGFEM_BREAKDOWN; break; }
+    const double rho_new = fma(-omega, red[3], red[2]);
+    const double beta = (rho_new / rho) * (alpha / omega);
+    rho = rho_new;
+    // C: x, r, p ; publish phat, rh
+    x = fma(alpha, d * p, fma(omega, d * sv, x));
+    r = fma(-omega, tv, sv);
+    p = fma(beta, fma(-omega, v, p), r);
+    if (own) {
+      st_sh(A.phat + row, d * p);
+      st_sh(A.rh + row, d * r);
+    }
+    if ((o.abort = team_barrier(tm, sh_abort))) break;
+  }
+#undef EGFEM_ZERO_RED
+  if (!o.abort && own) A.x[row] = x;
+  o.iters = it;
+  o.rnorm = rnorm;
   return o;
 }
 

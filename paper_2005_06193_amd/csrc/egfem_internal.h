@@ -55,6 +55,7 @@ struct Workspace {
   double* qslot = nullptr;      // per-slot scratch [slots] (mode-3 contraction)
   int32_t* krow = nullptr;      // Krylov row partition [kMaxKrylovBlocks + 1]
   int krow_blocks = 0;          // grid size the partition was made for
+  int krow_maxrows = 0;         // most rows of one workgroup in that partition
   double* kout = nullptr;       // Krylov result [4] (device)
   double* host_partial = nullptr;  // pinned host mirror of partial sums
   double* host_kout = nullptr;     // pinned host mirror of the Krylov result
@@ -80,6 +81,7 @@ struct egfem_tensor_s {
   int action_pipe = 0;          // 1: software-pipelined block runs
   int tuned_krylov_blocks = 0;  // Krylov grid chosen by the autotuner (0 = heuristic)
   int tuned_krylov_threads = 0;
+  int krylov_kernel = 0;        // 0: register-resident where it fits, 1: streaming
   int device = 0;
   // device arrays
   int32_t* rowptr = nullptr;    // [n+1]
@@ -145,6 +147,7 @@ struct KrylovResult {
   int blocks = 0;
   int threads = 0;
   double kernel_ms = 0.0;   // launch duration of the persistent kernel (when timed)
+  bool resident = false;    // the register-resident kernel ran
 };
 // Solves (rhs_scale * rhs) = A x with A = J (perm == null) or J^T (perm = tperm).
 int krylov_bicgstab(egfem_tensor_s* T, const double* jval, const double* dinv, const double* rhs,

@@ -52,6 +52,41 @@ __global__ __launch_bounds__(NT) void k_bicgstab(LaunchArgs P) {
   }
 }
 
+// Register-resident form: one thread per row, rows of at most K entries.
+constexpr int kResidentRow = 8;
+
+template <int NT, int K>
+__global__ __launch_bounds__(NT) void k_bicgstab_reg(LaunchArgs P) {
+  __shared__ double sh[dev::kShWords<NT>];
+  __shared__ int sh_abort;
+  dev::Team tm{blockIdx.x, gridDim.x, P.ctrl, P.red, 0u};
+  const int rb = P.krow[blockIdx.x], re = P.krow[blockIdx.x + 1];
+  const dev::KOut o = dev::team_bicgstab_reg<NT, K>(tm, P.A, rb, re, sh, &sh_abort);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    P.out[0] = o.abort ? (double)EGFEM_ERR_HIP : (double)o.status;
+    P.out[1] = (double)o.iters;
+    P.out[2] = o.bnorm > 0.0 ? o.rnorm / o.bnorm : 0.0;
+    P.out[3] = o.bnorm;
+  }
+}
+
+template <int NT, int K>
+hipError_t launch_reg_NK(const LaunchArgs& A, unsigned G, hipStream_t st) {
+  void* args[] = {(void*)&A};
+  return hipLaunchCooperativeKernel((const void*)k_bicgstab_reg<NT, K>, dim3(G), dim3(NT), args, 0, st);
+}
+
+template <int NT, int K>
+int max_coresident_reg_NK() {
+  int dev = 0, per_cu = 0, cus = 0;
+  hipGetDevice(&dev);
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_bicgstab_reg<NT, K>, NT, 0) !=
+      hipSuccess)
+    return 0;
+  return per_cu * cus;
+}
+
 template <int NT, int L>
 hipError_t launch_NL(const LaunchArgs& A, unsigned G, hipStream_t st) {
   void* args[] = {(void*)&A};
@@ -81,6 +116,11 @@ struct ShapeNT {
       default: return launch_NL<NT, 64>(A, G, st);
     }
   }
+  // register-resident form: rows of at most kResidentRow entries
+  static hipError_t launch_reg(const LaunchArgs& A, unsigned G, hipStream_t st) {
+    return launch_reg_NK<NT, kResidentRow>(A, G, st);
+  }
+  static int cap_reg() { return max_coresident_reg_NK<NT, kResidentRow>(); }
   static int cap(int L) {
     switch (L) {
       case 4: return max_coresident_NL<NT, 4>();
@@ -102,6 +142,18 @@ int cap_shape(int NT, int L) {
   if (NT == 256) return ShapeNT<256>::cap(L);
   if (NT == 512) return ShapeNT<512>::cap(L);
   return ShapeNT<1024>::cap(L);
+}
+
+hipError_t launch_shape_reg(int NT, const LaunchArgs& A, unsigned G, hipStream_t st) {
+  if (NT == 256) return ShapeNT<256>::launch_reg(A, G, st);
+  if (NT == 512) return ShapeNT<512>::launch_reg(A, G, st);
+  return ShapeNT<1024>::launch_reg(A, G, st);
+}
+
+int cap_shape_reg(int NT) {
+  if (NT == 256) return ShapeNT<256>::cap_reg();
+  if (NT == 512) return ShapeNT<512>::cap_reg();
+  return ShapeNT<1024>::cap_reg();
 }
 
 }  // namespace
@@ -143,6 +195,9 @@ int krylov_bicgstab(egfem_tensor_s* T, const double* jval, const double* dinv, c
   if (W.krow_blocks != G) {
     std::vector<int32_t> kr;
     make_partition(T, G, kr);
+    int most = 0;
+    for (int g = 0; g < G; ++g) most = std::max(most, kr[g + 1] - kr[g]);
+    W.krow_maxrows = most;
     EGFEM_HIP_CHECK(hipMemcpyAsync(W.krow, kr.data(), kr.size() * sizeof(int32_t),
                                    hipMemcpyHostToDevice, st));
     EGFEM_HIP_CHECK(hipStreamSynchronize(st));
@@ -183,7 +238,14 @@ int krylov_bicgstab(egfem_tensor_s* T, const double* jval, const double* dinv, c
     EGFEM_HIP_CHECK(hipEventCreate(&ev1));
     EGFEM_HIP_CHECK(hipEventRecord(ev0, st));
   }
-  const hipError_t e = launch_shape(NT, T->krylov_lanes, P, (unsigned)G, st);
+  // register-resident form when every workgroup's rows fit its threads, rows
+  // hold at most kResidentRow entries, and the grid is co-resident for it
+  const int L = T->krylov_lanes;
+  // (columns are held as 32-bit byte offsets: n < 2^28)
+  const bool resident = T->krylov_kernel == 0 && T->max_row_slots <= kResidentRow &&
+                        W.krow_maxrows <= NT && T->n < (int64_t(1) << 28) && G <= cap_shape_reg(NT);
+  const hipError_t e = resident ? launch_shape_reg(NT, P, (unsigned)G, st)
+                                : launch_shape(NT, L, P, (unsigned)G, st);
   if (e != hipSuccess) {
     if (ev0) hipEventDestroy(ev0);
     if (ev1) hipEventDestroy(ev1);
@@ -206,6 +268,7 @@ int krylov_bicgstab(egfem_tensor_s* T, const double* jval, const double* dinv, c
   res->bnorm = o[3];
   res->blocks = G;
   res->threads = NT;
+  res->resident = resident;
   if (res->status == EGFEM_ERR_HIP) return fail(EGFEM_ERR_HIP, "Krylov grid barrier timed out");
   return EGFEM_OK;
 }

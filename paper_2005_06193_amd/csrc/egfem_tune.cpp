@@ -45,6 +45,7 @@ int egfem_get_shape(egfem_tensor_t T, egfem_launch_shape* s) {
   s->action_pipe = T->action_pipe;
   s->krylov_blocks = T->tuned_krylov_blocks;
   s->krylov_threads = T->tuned_krylov_threads;
+  s->krylov_kernel = T->krylov_kernel;
   return EGFEM_OK;
 }
 
@@ -53,12 +54,14 @@ int egfem_set_shape(egfem_tensor_t T, const egfem_launch_shape* s) {
   if (s->action_runs < 0 || (s->action_pipe != 0 && s->action_pipe != 1) || s->krylov_blocks < 0 ||
       s->krylov_blocks > kMaxKrylovBlocks ||
       (s->krylov_threads != 0 && s->krylov_threads != 256 && s->krylov_threads != 512 &&
-       s->krylov_threads != 1024))
+       s->krylov_threads != 1024) ||
+      (s->krylov_kernel != 0 && s->krylov_kernel != 1))
     return fail(EGFEM_ERR_ARG, "invalid launch shape");
   T->action_runs_target = s->action_runs;
   T->action_pipe = s->action_pipe;
   T->tuned_krylov_blocks = s->krylov_blocks;
   T->tuned_krylov_threads = s->krylov_threads;
+  T->krylov_kernel = s->krylov_kernel;
   return EGFEM_OK;
 }
 
@@ -109,23 +112,32 @@ int egfem_autotune(egfem_tensor_t T, const egfem_problem* p, int what, egfem_lau
     EGFEM_HIP_CHECK(launch_fill(W.rhs, 1.0, T->n, st));
     EGFEM_HIP_CHECK(launch_mask_zero(W.rhs, p->dirichlet, T->n, st));
     double best_t = DBL_MAX;
-    int bb = 0, bt = 0;
-    for (int threads : {256, 512, 1024})
-      for (int blocks : {32, 64, 128, 256, 512}) {
-        KrylovResult kr;
-        rc = krylov_bicgstab(T, W.jval, W.dinv, W.rhs, 1.0, W.delta, true, 1e-300, 40, blocks, &kr, st,
-                             nullptr, true, threads);
-        if (rc != EGFEM_OK) return rc;
-        if (kr.iters <= 0) continue;
-        const double us = 1000.0 * kr.kernel_ms / kr.iters;
-        if (us < best_t) {
-          best_t = us;
-          bb = kr.blocks;
-          bt = kr.threads;
+    int bb = 0, bt = 0, bk = 0;
+    const int keep_kernel = T->krylov_kernel;
+    for (int kernel : {0, 1})
+      for (int threads : {256, 512, 1024})
+        for (int blocks : {32, 64, 128, 256, 512, 1024}) {
+          T->krylov_kernel = kernel;
+          KrylovResult kr;
+          rc = krylov_bicgstab(T, W.jval, W.dinv, W.rhs, 1.0, W.delta, true, 1e-300, 40, blocks, &kr, st,
+                               nullptr, true, threads);
+          if (rc != EGFEM_OK) {
+            T->krylov_kernel = keep_kernel;
+            return rc;
+          }
+          // the register-resident kernel only where it applies (else it repeats kernel 1)
+          if (kr.iters <= 0 || (kernel == 0 && !kr.resident)) continue;
+          const double us = 1000.0 * kr.kernel_ms / kr.iters;
+          if (us < best_t) {
+            best_t = us;
+            bb = kr.blocks;
+            bt = kr.threads;
+            bk = kernel;
+          }
         }
-      }
     T->tuned_krylov_blocks = bb;
     T->tuned_krylov_threads = bt;
+    T->krylov_kernel = bk;
     us_krylov = best_t;
   }
   if (best) egfem_get_shape(T, best);

@@ -202,10 +202,14 @@ def test_problem_residual_and_jacobian(name):
 # ---------------------------------------------------------------------------
 # linear solve
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kernel", [0, 1])
 @pytest.mark.parametrize("transpose", [False, True])
-def test_bicgstab_solve(transpose):
+def test_bicgstab_solve(transpose, kernel):
+    """Both BiCGStab kernels: 0 = register-resident (every workgroup's rows
+    fit its threads here), 1 = streaming."""
     wl = W.nonlinear_diffusion_2d(48)
     T = eg().Tensor.from_mesh(wl.mesh, wl.form)
+    T.set_shape(krylov_kernel=kernel)
     p = gpu_problem(T, wl)
     po = O.build_problem(wl)
     u = np.random.default_rng(10).uniform(0, 1, T.n)
@@ -244,6 +248,23 @@ def test_newton_matches_oracle(name):
     # certificate: the oracle's residual at the GPU solution
     Fo0 = np.linalg.norm(po.d[~po.dirichlet])
     assert np.linalg.norm(O.residual(po, ug)) <= 1e-11 * Fo0
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_newton_krylov_kernels(kernel):
+    """The register-resident and the streaming BiCGStab give the oracle's
+    solution, and the statistics name the kernel that ran."""
+    wl = W.nonlinear_diffusion_2d(40, seed=77)
+    T = eg().Tensor.from_mesh(wl.mesh, wl.form)
+    T.set_shape(krylov_kernel=kernel)
+    p = gpu_problem(T, wl)
+    po = O.build_problem(wl)
+    u = torch.zeros(T.n, dtype=torch.float64, device=DEV)
+    st = T.newton(p, u, _tight(), warn=False)
+    assert st.status in (0, 4), st.status_name
+    assert st.krylov_kernels == (1 if kernel == 0 else 2)
+    uo, _ = O.newton(po, tol=1e-14, max_iter=30)
+    assert relerr(host(u), uo) <= 1e-10
 
 
 def test_newton_full_size_2d_256():
