@@ -401,7 +401,7 @@ int egfem_batch_create(int count, const egfem_tensor_t* Ts, const egfem_problem*
     first += g[m];
   }
   // batch buffers
-  B->ctrl_words = (size_t)count * 512;
+  B->ctrl_words = (size_t)count * dev::kCtrlWords;
   size_t red_words = 0;
   std::vector<size_t> red_off(count);
   for (int m = 0; m < count; ++m) {
@@ -421,7 +421,7 @@ int egfem_batch_create(int count, const egfem_tensor_t* Ts, const egfem_problem*
   }
   for (int m = 0; m < count; ++m) {
     hi[m].wgblk = B->d_wgblk + wgblk_off[m];
-    hi[m].ctrl = B->d_ctrl + (size_t)m * 512;
+    hi[m].ctrl = B->d_ctrl + (size_t)m * dev::kCtrlWords;
     hi[m].red = B->d_red + red_off[m];
     hi[m].stats = B->d_stats + (size_t)m * kStatsWords;
   }

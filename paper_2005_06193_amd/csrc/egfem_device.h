@@ -15,7 +15,7 @@ namespace dev {
 
 constexpr int kWave = 64;
 constexpr unsigned kSpinCap = 1u << 24;   // bounded waits: a barrier that never completes aborts
-constexpr int kGroups = 8;                // arrival groups (one per XCD under round-robin dispatch)
+constexpr int kGroups = 32;               // most arrival groups of a team barrier
 // control block (unsigned words, one 128-byte line each): epoch, global
 // arrivals, abort flag, then one arrival counter per group.
 constexpr int kCtrlGen = 0, kCtrlAll = 32, kCtrlAbort = 64, kCtrlGroup = 96;
@@ -451,27 +451,37 @@ struct Team {
 
 // Arrival at and wait for team barrier number `epoch`, by one thread of the
 // workgroup, after the workgroup's stores are complete.  Epoch counting (no
-// counter resets): arrivals are counted per group, the last of each group
-// arrives at the team counter, the last team arrival publishes the new epoch,
-// everyone else polls it.  All accesses are relaxed agent-scope atomics; data
+// counter resets): arrivals are counted per group (teams of 16 or more
+// workgroups; smaller teams count on the team counter directly), the last of
+// each group arrives at the team counter, the last team arrival publishes the
+// new epoch, everyone else polls it.  All accesses are relaxed agent-scope atomics; data
 // exchanged between workgroups is written and read with agent-coherent
 // accesses, so no cache write-back or invalidation is needed.  Returns
 // nonzero when the team aborted (a wait exceeded kSpinCap).
 __device__ inline int barrier_arrive_wait(const Team& tm, unsigned epoch) {
   unsigned* ctrl = tm.ctrl;
   const unsigned G = tm.size;
-  const unsigned ng = G < (unsigned)kGroups ? G : (unsigned)kGroups;
-  const unsigned grp = tm.rank % ng;
-  const unsigned gsz = (G - grp + ng - 1) / ng;   // ranks r < G with r % ng == grp
   int ab = (int)__hip_atomic_load(ctrl + kCtrlAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (ab) return ab;
-  const unsigned prev = __hip_atomic_fetch_add(ctrl + kCtrlGroup + 32 * grp, 1u, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-  bool last = false;
-  if (prev == (epoch + 1) * gsz - 1) {
-    const unsigned prev2 = __hip_atomic_fetch_add(ctrl + kCtrlAll, 1u, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-    last = (prev2 == (epoch + 1) * ng - 1);
+  bool last;
+  if (G < 16) {
+    // small team: one counter
+    const unsigned prev = __hip_atomic_fetch_add(ctrl + kCtrlAll, 1u, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    last = (prev == (epoch + 1) * G - 1);
+  } else {
+    // groups of about 8 workgroups (fewer arrivals serialised on one counter)
+    const unsigned ng = min(G / 8u, (unsigned)kGroups);
+    const unsigned grp = tm.rank % ng;
+    const unsigned gsz = (G - grp + ng - 1) / ng;   // ranks r < G with r % ng == grp
+    const unsigned prev = __hip_atomic_fetch_add(ctrl + kCtrlGroup + 32 * grp, 1u, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    last = false;
+    if (prev == (epoch + 1) * gsz - 1) {
+      const unsigned prev2 = __hip_atomic_fetch_add(ctrl + kCtrlAll, 1u, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+      last = (prev2 == (epoch + 1) * ng - 1);
+    }
   }
   if (last) {
     __hip_atomic_store(ctrl + kCtrlGen, epoch + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

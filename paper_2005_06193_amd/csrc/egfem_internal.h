@@ -23,7 +23,7 @@ constexpr int kCapRows = 256;     // rows per block (one thread per row in the r
 constexpr int kKrylovThreads = 1024;
 constexpr int kMaxKrylovBlocks = 1024;
 constexpr int kRedSlots = 10;     // reduction slots in flight (>= 2 barriers apart)
-constexpr int kCtrlWordsMax = 1024;  // barrier control words (one 128-byte line per counter)
+constexpr int kCtrlWordsMax = 2048;  // barrier control words (one 128-byte line per counter)
 
 void set_error(const std::string& msg);
 int fail(int code, const std::string& msg);
