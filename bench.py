@@ -33,23 +33,31 @@ METRIC = "tensor-action GB/s + Newton solves/s (FP64, rel. 1e-10) vs per-instanc
 # algorithmic bytes of one launch of each kernel (every stored tensor value and
 # index, every pattern array and every vector touched once)
 # ----------------------------------------------------------------------------
+# Stream format of the tensor (bytes each): an A entry = value (8) + the
+# block-relative slot of (i, k) (2); a slot = fiber pointer (4) + column (4);
+# a row = row pointer (4); a row block = one 32-byte bounds record.  Vectors
+# are counted once each (the per-slot gathers re-hit cache).
+def _stream_bytes(info):
+    N, S, Z = info.n_nodes, info.slots, info.nnz
+    return 10 * Z + 8 * S + 4 * (N + 1) + 32 * info.row_blocks
+
+
 def bytes_action_raw(info):
-    N, S, Z = info.n_nodes, info.slots, info.nnz
-    return 12 * Z + 8 * S + 4 * (N + 1) + 24 * N           # vA,kA | kptr,col | rowptr | u,a,r
+    return _stream_bytes(info) + 24 * info.n_nodes                      # u, a, r
 
 
-def bytes_action_problem(info, trial: bool):
-    N, S, Z = info.n_nodes, info.slots, info.nnz
+def bytes_action_problem(info, trial: bool, add_stiffness: bool = False):
+    N, S = info.n_nodes, info.slots
     vec = 8 * N * (3 + (2 if trial else 0)) + N             # u,d,F [+delta,u_try] + mask
-    return 12 * Z + 8 * S + 4 * (N + 1) + vec
+    kmat = 8 * S if add_stiffness else 0                      # stiffness values (semilinear form)
+    return _stream_bytes(info) + kmat + vec
 
 
 def bytes_jacobian(info, add_stiffness: bool = False):
     N, S, Z = info.n_nodes, info.slots, info.nnz
-    streams = 12 * Z + (0 if info.symmetric else 12 * Z)    # A (+ B) streams
-    ptrs = 4 * (S + 1) * (1 if info.symmetric else 2) + 4 * S + 4 * (N + 1)
-    kmat = 8 * S if add_stiffness else 0                      # stiffness values (semilinear form)
-    return streams + ptrs + kmat + 8 * N + N + 8 * S + 8 * N  # u, mask, J values, 1/diag
+    streams = _stream_bytes(info) + (0 if info.symmetric else 10 * Z + 4 * (S + 1))   # A (+ B)
+    kmat = 8 * S if add_stiffness else 0
+    return streams + kmat + 8 * N + N + 8 * S + 8 * N        # u, mask, J values, 1/diag
 
 
 def bytes_krylov(info, iters: int):

@@ -144,14 +144,15 @@ const char* egfem_version(void) { return "egfem-gfx950 0.1"; }
 void egfem_tensor_destroy(egfem_tensor_t T) {
   if (!T) return;
   free_workspace(T->ws);
-  void* ptrs[] = {T->rowptr, T->col, T->diag, T->tperm, T->kptrA, T->kA, T->vA,
-                  T->kval,   T->mval, T->blk_row, T->blk_meta};
+  void* ptrs[] = {T->rowptr, T->col,  T->diag,    T->tperm,    T->kptrA, T->kA, T->vA,
+                  T->kS,     T->kval, T->mval, T->blk_row, T->blk_meta};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (!T->symmetric) {
     if (T->jptrB) hipFree(T->jptrB);
     if (T->jB) hipFree(T->jB);
     if (T->vB) hipFree(T->vB);
+    if (T->jS) hipFree(T->jS);
   }
   delete T;
 }

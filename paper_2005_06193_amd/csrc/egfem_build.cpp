@@ -151,6 +151,7 @@ extern "C" int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords
   // --- row pass: pattern, matrices and both fiber streams -----------------
   std::vector<int32_t> rowptr(N + 1, 0), col;
   std::vector<int32_t> kptrA(1, 0), kA, jptrB(1, 0), jB;
+  std::vector<uint16_t> kRel, jRel;   // position of k (of j) among the row's columns
   std::vector<double> vA, vB, kval, mval;
   int64_t structural = 0;
   int max_row_slots = 0;
@@ -222,6 +223,7 @@ extern "C" int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords
         const size_t t = (size_t)jb * nc + kc;
         if (kept(t)) {
           kA.push_back(cols[kc]);
+          kRel.push_back((uint16_t)kc);
           vA.push_back(acc[t]);
         }
       }
@@ -232,6 +234,7 @@ extern "C" int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords
           const size_t t = (size_t)jj * nc + jb;
           if (kept(t)) {
             jB.push_back(cols[jj]);
+            jRel.push_back((uint16_t)jj);
             vB.push_back(acc[t]);
           }
         }
@@ -277,6 +280,23 @@ extern "C" int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords
                                                  "(1024 tensor entries / 512 slots)");
       blk.push_back((int32_t)r1);
       r0 = r1;
+    }
+  }
+
+  // Every k of row i's A entries (and every j of its B entries) is a column
+  // of row i, so an entry can name it by the block-relative slot of (i, k):
+  // 16 bits (at most kCapSlots slots per block).  The stages then gather
+  // per slot, not per entry.
+  std::vector<uint16_t> kS(kA.size()), jS(jB.size());
+  for (size_t b = 0; b + 1 < blk.size(); ++b) {
+    const int32_t s0 = rowptr[blk[b]];
+    for (int32_t i = blk[b]; i < blk[b + 1]; ++i) {
+      const int32_t base = rowptr[i] - s0;
+      for (int32_t s = rowptr[i]; s < rowptr[i + 1]; ++s) {
+        for (int32_t p = kptrA[s]; p < kptrA[s + 1]; ++p) kS[p] = (uint16_t)(base + kRel[p]);
+        if (!sym)
+          for (int32_t p = jptrB[s]; p < jptrB[s + 1]; ++p) jS[p] = (uint16_t)(base + jRel[p]);
+      }
     }
   }
 
@@ -327,6 +347,8 @@ extern "C" int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords
   if (rc == EGFEM_OK) rc = upload(kptrA, &T->kptrA, &bytes);
   if (rc == EGFEM_OK) rc = upload(kA, &T->kA, &bytes);
   if (rc == EGFEM_OK) rc = upload(vA, &T->vA, &bytes);
+  if (rc == EGFEM_OK) rc = upload(kS, &T->kS, &bytes);
+  if (rc == EGFEM_OK && !sym) rc = upload(jS, &T->jS, &bytes);
   if (rc == EGFEM_OK && !sym) rc = upload(jptrB, &T->jptrB, &bytes);
   if (rc == EGFEM_OK && !sym) rc = upload(jB, &T->jB, &bytes);
   if (rc == EGFEM_OK && !sym) rc = upload(vB, &T->vB, &bytes);
@@ -338,6 +360,7 @@ extern "C" int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords
     T->jptrB = T->kptrA;
     T->jB = T->kA;
     T->vB = T->vA;
+    T->jS = T->kS;
   }
   T->device_bytes = bytes;
   if (rc != EGFEM_OK) {

@@ -52,6 +52,8 @@ struct TensorView {
   const int32_t* jptrB;
   const int32_t* jB;
   const double* vB;
+  const uint16_t* kS;       // block-relative slot of (i, k) of every A entry
+  const uint16_t* jS;       // block-relative slot of (i, j) of every B entry
   const double* kval;
 };
 
@@ -69,6 +71,8 @@ __device__ __forceinline__ BlockMeta block_meta(const TensorView& T, int64_t b) 
 struct RowBlockLds {
   double tA[kCapNnz];        // products of the A stream
   double tB[kCapNnz];        // products of the B stream (Jacobian only)
+  double aS[kCapSlots];      // a at every slot's column
+  double uS[kCapSlots];      // u at every slot's column (Jacobian only)
   double y[kCapSlots];       // slot results (action)
   int spa[kCapSlots + 1];    // fiber bounds, A stream, block-relative
   int spb[kCapSlots + 1];    // fiber bounds, B stream, block-relative
@@ -80,6 +84,7 @@ struct RowBlockLds {
 // LDS scratch of the residual action alone (smaller: higher occupancy).
 struct ActionLds {
   double tA[kCapNnz];
+  double aS[kCapSlots];
   double y[kCapSlots];
   int spa[kCapSlots + 1];
   int srow[kCapRows + 1];
@@ -96,7 +101,7 @@ struct Per {
 // Stream registers of one row block for the tensor action (stage 1a).
 template <int NT>
 struct ActionRegs {
-  int kk[Per<NT>::P];
+  int kk[Per<NT>::P];       // block-relative slot of (i, k)
   double vv[Per<NT>::P];
   int cc[Per<NT>::S];
   int kp[Per<NT>::S];
@@ -130,7 +135,7 @@ __device__ __forceinline__ void action_load(const TensorView& T, int64_t b, cons
 #pragma unroll
   for (int q = 0; q < PP; ++q) {
     const int p = R.p0 + clamp_hi(tid + q * NT, R.np);
-    R.kk[q] = T.kA[p];
+    R.kk[q] = T.kS[p];
     R.vv[q] = T.vA[p];
   }
   // null kval / load / dir are replaced by a valid array and masked at use
@@ -160,7 +165,8 @@ __device__ __forceinline__ void action_load(const TensorView& T, int64_t b, cons
 //            sq += F_i^2 over the rows this thread handled.
 // SH: u, delta gathered with agent-coherent loads and uout written with
 // agent-coherent stores (data produced by other workgroups of the same launch).
-// All gathers of the block are issued before the first product is formed.
+// Gathers are per slot (w and a at the slot's column, a into LDS); an entry
+// reads a_k from the LDS slot of (i, k).
 template <int NT, bool PROBLEM, bool SH, typename Lds>
 __device__ __forceinline__ void action_compute(const ActionRegs<NT>& R, const double* u,
                                                const double* delta, double alpha, const double* a,
@@ -171,52 +177,49 @@ __device__ __forceinline__ void action_compute(const ActionRegs<NT>& R, const do
   const int tid = threadIdx.x;
   const bool has_row = tid < R.nr;
   const int i = R.r0 + clamp_hi(tid, R.nr);
-  // gathers
-  double gk[PP], dk[PP], ak0[PP], wj[SS], dj[SS];
+  // per-slot gathers
+  double wj[SS], dj[SS], aj[SS];
   double ui = 0.0, di = 0.0;
 #pragma unroll
-  for (int q = 0; q < PP; ++q) gk[q] = PROBLEM ? ld<SH>(u + R.kk[q]) : a[R.kk[q]];
-#pragma unroll
   for (int q = 0; q < SS; ++q) wj[q] = ld<SH>(u + R.cc[q]);
+  if (a) {
+#pragma unroll
+    for (int q = 0; q < SS; ++q) aj[q] = a[R.cc[q]];
+  }
   if (PROBLEM && uout) ui = ld<SH>(u + i);
   if (PROBLEM && delta) {
-#pragma unroll
-    for (int q = 0; q < PP; ++q) dk[q] = ld<SH>(delta + R.kk[q]);
 #pragma unroll
     for (int q = 0; q < SS; ++q) dj[q] = ld<SH>(delta + R.cc[q]);
     if (uout) di = ld<SH>(delta + i);
   }
-  if (PROBLEM && a) {
-#pragma unroll
-    for (int q = 0; q < PP; ++q) ak0[q] = a[R.kk[q]];
-  }
-  // products and bounds
-#pragma unroll
-  for (int q = 0; q < PP; ++q) {
-    const int p = tid + q * NT;
-    if (p < R.np) {
-      double ak;
-      if (PROBLEM) {
-        double wk = gk[q];
-        if (delta) wk = fma(alpha, dk[q], wk);
-        ak = fma(wk, wk, a ? ak0[q] : a0c);
-      } else {
-        ak = gk[q];
-      }
-      L.tA[p] = R.vv[q] * ak;
-    }
-  }
+  // slot values (a in LDS) and bounds
 #pragma unroll
   for (int q = 0; q < SS; ++q) {
     const int s = tid + q * NT;
-    if (PROBLEM && delta) wj[q] = fma(alpha, dj[q], wj[q]);
-    if (s < R.ns) L.spa[s] = R.kp[q] - R.p0;
+    double as;
+    if (PROBLEM) {
+      if (delta) wj[q] = fma(alpha, dj[q], wj[q]);
+      as = fma(wj[q], wj[q], a ? aj[q] : a0c);
+    } else {
+      as = aj[q];
+    }
+    if (s < R.ns) {
+      L.aS[s] = as;
+      L.spa[s] = R.kp[q] - R.p0;
+    }
   }
   if (tid == 0) {
     L.spa[R.ns] = R.np;
     L.srow[R.nr] = R.ns;
   }
   if (has_row) L.srow[tid] = R.rp - R.s0;
+  __syncthreads();
+  // products
+#pragma unroll
+  for (int q = 0; q < PP; ++q) {
+    const int p = tid + q * NT;
+    if (p < R.np) L.tA[p] = R.vv[q] * L.aS[R.kk[q]];
+  }
   __syncthreads();
   // fiber sums (same slots as loaded by this thread)
 #pragma unroll
@@ -307,6 +310,7 @@ __device__ void rowblock_jacobian(const TensorView& T, int64_t b, const double* 
                                   const double* a0, double a0c, int problem_a, const double* dadu,
                                   int dadu_2u, const double* kval, const uint8_t* dir, double* jval,
                                   double* dinv, RowBlockLds& L) {
+  static_assert(NT >= kCapRows, "one thread per row of a block");
   constexpr int PP = Per<NT>::P, SS = Per<NT>::S;
   const int tid = threadIdx.x;
   const BlockMeta m = block_meta(T, b);
@@ -314,21 +318,22 @@ __device__ void rowblock_jacobian(const TensorView& T, int64_t b, const double* 
   const int na = m.pa1 - m.pa0, nb = m.pb1 - m.pb0, ns = m.s1 - m.s0, nr = m.r1 - m.r0;
   const bool second = dadu || dadu_2u;
   const bool bstream = second && !T.sym;
-  const bool need_uk = problem_a || (T.sym && second);
-  // stage 1a: stream loads, back to back at clamped indices (see action_load)
+  const bool need_u = problem_a || second;
+  // stage 1a: stream loads, back to back at clamped indices (see action_load);
+  // entries name their k (their j) by the block-relative slot of (i, k)
   int ka[PP], jb[PP];
   double va[PP], vb[PP];
 #pragma unroll
   for (int q = 0; q < PP; ++q) {
     const int p = pa0 + clamp_hi(tid + q * NT, na);
-    ka[q] = T.kA[p];
+    ka[q] = T.kS[p];
     va[q] = T.vA[p];
   }
   if (bstream) {
 #pragma unroll
     for (int q = 0; q < PP; ++q) {
       const int p = pb0 + clamp_hi(tid + q * NT, nb);
-      jb[q] = T.jB[p];
+      jb[q] = T.jS[p];
       vb[q] = T.vB[p];
     }
   }
@@ -347,53 +352,38 @@ __device__ void rowblock_jacobian(const TensorView& T, int64_t b, const double* 
   const int i = r0 + clamp_hi(tid, nr);
   const int rpa = T.rowptr[i], rpb = T.rowptr[i + 1];
   const unsigned char drow_raw = (dir ? dir : reinterpret_cast<const uint8_t*>(T.kval))[i];
-  // stage 1b: gathers (all issued before the products), products, bounds
-  double uk[PP], gk[PP], ub[PP];
-  if (need_uk) {
+  // stage 1b: per-slot gathers (u, a or a0, g, Dirichlet flag at the slot's column)
+  double uj[SS], aj[SS], gj[SS];
+  unsigned char dcr[SS];
 #pragma unroll
-    for (int q = 0; q < PP; ++q) uk[q] = ld<SH>(u + ka[q]);
+  for (int q = 0; q < SS; ++q) {
+    uj[q] = 0.0;
+    gj[q] = 0.0;
+    dcr[q] = 0;
+  }
+  if (need_u) {
+#pragma unroll
+    for (int q = 0; q < SS; ++q) uj[q] = ld<SH>(u + cc[q]);
   }
   const double* ga = problem_a ? a0 : a;   // a0 may be null (constant a0c)
   if (ga) {
 #pragma unroll
-    for (int q = 0; q < PP; ++q) gk[q] = ga[ka[q]];
-  }
-  if (bstream) {
-#pragma unroll
-    for (int q = 0; q < PP; ++q) ub[q] = ld<SH>(u + jb[q]);
-  }
-  double gj[SS];
-  unsigned char dcr[SS];
-#pragma unroll
-  for (int q = 0; q < SS; ++q) {
-    gj[q] = 0.0;
-    dcr[q] = 0;
+    for (int q = 0; q < SS; ++q) aj[q] = ga[cc[q]];
   }
   if (dadu) {
 #pragma unroll
     for (int q = 0; q < SS; ++q) gj[q] = dadu[cc[q]];
-  } else if (second) {
-#pragma unroll
-    for (int q = 0; q < SS; ++q) gj[q] = ld<SH>(u + cc[q]);
   }
   if (dir) {
 #pragma unroll
     for (int q = 0; q < SS; ++q) dcr[q] = dir[cc[q]];
   }
 #pragma unroll
-  for (int q = 0; q < PP; ++q) {
-    const int p = tid + q * NT;
-    if (p < na) {
-      const double ak = problem_a ? fma(uk[q], uk[q], a0 ? gk[q] : a0c) : gk[q];
-      L.tA[p] = va[q] * ak;
-      if (T.sym && second) L.tB[p] = va[q] * uk[q];
-    }
-    if (bstream && p < nb) L.tB[p] = vb[q] * ub[q];
-  }
-#pragma unroll
   for (int q = 0; q < SS; ++q) {
     const int s = tid + q * NT;
     if (s < ns) {
+      L.aS[s] = problem_a ? fma(uj[q], uj[q], a0 ? aj[q] : a0c) : aj[q];
+      L.uS[s] = uj[q];
       L.spa[s] = kpa[q] - pa0;
       L.spb[s] = kpb[q] - pb0;
     }
@@ -405,6 +395,17 @@ __device__ void rowblock_jacobian(const TensorView& T, int64_t b, const double* 
   if (has_row) {
     L.sdir[tid] = (dir && drow_raw) ? 1 : 0;
     for (int s = rpa - s0; s < rpb - s0; ++s) L.srid[s] = tid;
+  }
+  __syncthreads();
+  // stage 1c: products
+#pragma unroll
+  for (int q = 0; q < PP; ++q) {
+    const int p = tid + q * NT;
+    if (p < na) {
+      L.tA[p] = va[q] * L.aS[ka[q]];
+      if (T.sym && second) L.tB[p] = va[q] * L.uS[ka[q]];
+    }
+    if (bstream && p < nb) L.tB[p] = vb[q] * L.uS[jb[q]];
   }
   __syncthreads();
   // stage 2: slot assembly
@@ -427,7 +428,7 @@ __device__ void rowblock_jacobian(const TensorView& T, int64_t b, const double* 
         if (second) {
           double qb = 0.0;
           for (int t = L.spb[s]; t < L.spb[s + 1]; ++t) qb += L.tB[t];
-          const double g = dadu ? gj[q] : 2.0 * gj[q];
+          const double g = dadu ? gj[q] : 2.0 * uj[q];
           J = fma(g, qb, J);
         }
       }

@@ -94,6 +94,8 @@ struct egfem_tensor_s {
   int32_t* jptrB = nullptr;     // [slots+1]  (aliases kptrA when symmetric)
   int32_t* jB = nullptr;        // [nnz]
   double* vB = nullptr;         // [nnz]
+  uint16_t* kS = nullptr;       // [nnz]  block-relative slot of (i, k) of every A entry
+  uint16_t* jS = nullptr;       // [nnz]  block-relative slot of (i, j) of every B entry (aliases kS)
   double* kval = nullptr;       // [slots]
   double* mval = nullptr;       // [slots]
   int32_t* blk_row = nullptr;   // [row_blocks+1]

@@ -60,6 +60,8 @@ dev::TensorView view_of(const egfem_tensor_s* T) {
   v.jptrB = T->jptrB;
   v.jB = T->jB;
   v.vB = T->vB;
+  v.kS = T->kS;
+  v.jS = T->jS;
   v.kval = T->kval;
   return v;
 }

@@ -34,13 +34,21 @@ def test_action_shapes_bitwise_equal(wlname):
     rng = np.random.default_rng(3)
     u = dt(rng.uniform(-1, 1, T.n))
     a = dt(rng.uniform(0.5, 2, T.n))
+    load = T.matvec(dt(wl.f), "M")
+    p = eg().Problem(T.n, load, dt(wl.mesh.dirichlet, torch.uint8), dt(wl.a0) if wl.a0 is not None else None,
+                     wl.a0_const, wl.add_stiffness)
     T.set_shape(action_runs=0, action_pipe=0)
     ref = host(T.residual(u, a))
+    Fref, nref = T.problem_residual(p, u, with_norm=True)
+    Fref = host(Fref)
     nb = T.info.row_blocks
     for runs, pipe in ((0, 0), (max(1, nb // 3), 0), (max(1, nb // 3), 1), (max(1, nb // 7), 1), (1, 1),
                        (nb + 5, 0)):
         T.set_shape(action_runs=runs, action_pipe=pipe)
         assert np.array_equal(host(T.residual(u, a)), ref), (runs, pipe)
+        F, nF = T.problem_residual(p, u, with_norm=True)
+        assert np.array_equal(host(F), Fref), (runs, pipe)
+        assert abs(nF - nref) <= 1e-14 * nref   # partial sums regroup with the run count
     To = O.assemble_tensor(wl.mesh.coords, wl.mesh.cells, wl.form)
     r = O.contract_uv(To, host(u), host(a))
     assert np.linalg.norm(ref - r) <= 1e-12 * np.linalg.norm(r)
