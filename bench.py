@@ -34,12 +34,13 @@ METRIC = "tensor-action GB/s + Newton solves/s (FP64, rel. 1e-10) vs per-instanc
 # index, every pattern array and every vector touched once)
 # ----------------------------------------------------------------------------
 # Stream format of the tensor (bytes each): an A entry = value (8) + the
-# block-relative slot of (i, k) (2); a slot = fiber pointer (4) + column (4);
+# block-relative slot of (i, k) (2); a slot = block-relative fiber start (2) +
+# column (4);
 # a row = row pointer (4); a row block = one 32-byte bounds record.  Vectors
 # are counted once each (the per-slot gathers re-hit cache).
 def _stream_bytes(info):
     N, S, Z = info.n_nodes, info.slots, info.nnz
-    return 10 * Z + 8 * S + 4 * (N + 1) + 32 * info.row_blocks
+    return 10 * Z + 6 * S + 4 * (N + 1) + 32 * info.row_blocks
 
 
 def bytes_action_raw(info):
@@ -55,7 +56,7 @@ def bytes_action_problem(info, trial: bool, add_stiffness: bool = False):
 
 def bytes_jacobian(info, add_stiffness: bool = False):
     N, S, Z = info.n_nodes, info.slots, info.nnz
-    streams = _stream_bytes(info) + (0 if info.symmetric else 10 * Z + 4 * (S + 1))   # A (+ B)
+    streams = _stream_bytes(info) + (0 if info.symmetric else 10 * Z + 2 * S)   # A (+ B)
     kmat = 8 * S if add_stiffness else 0
     return streams + kmat + 8 * N + N + 8 * S + 8 * N        # u, mask, J values, 1/diag
 

@@ -145,7 +145,7 @@ void egfem_tensor_destroy(egfem_tensor_t T) {
   if (!T) return;
   free_workspace(T->ws);
   void* ptrs[] = {T->rowptr, T->col,  T->diag,    T->tperm,    T->kptrA, T->kA, T->vA,
-                  T->kS,     T->kval, T->mval, T->blk_row, T->blk_meta};
+                  T->kS,     T->kpS,  T->kval, T->mval, T->blk_row, T->blk_meta};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (!T->symmetric) {
@@ -153,6 +153,7 @@ void egfem_tensor_destroy(egfem_tensor_t T) {
     if (T->jB) hipFree(T->jB);
     if (T->vB) hipFree(T->vB);
     if (T->jS) hipFree(T->jS);
+    if (T->jpS) hipFree(T->jpS);
   }
   delete T;
 }

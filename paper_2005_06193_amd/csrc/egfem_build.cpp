@@ -288,8 +288,14 @@ extern "C" int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords
   // 16 bits (at most kCapSlots slots per block).  The stages then gather
   // per slot, not per entry.
   std::vector<uint16_t> kS(kA.size()), jS(jB.size());
+  // fiber starts relative to the block's first entry (at most kCapNnz)
+  std::vector<uint16_t> kpS((size_t)slots + 1), jpS(sym ? 0 : (size_t)slots + 1);
   for (size_t b = 0; b + 1 < blk.size(); ++b) {
     const int32_t s0 = rowptr[blk[b]];
+    for (int32_t s = s0; s < rowptr[blk[b + 1]]; ++s) {
+      kpS[s] = (uint16_t)(kptrA[s] - kptrA[s0]);
+      if (!sym) jpS[s] = (uint16_t)(jptrB[s] - jptrB[s0]);
+    }
     for (int32_t i = blk[b]; i < blk[b + 1]; ++i) {
       const int32_t base = rowptr[i] - s0;
       for (int32_t s = rowptr[i]; s < rowptr[i + 1]; ++s) {
@@ -349,6 +355,8 @@ extern "C" int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords
   if (rc == EGFEM_OK) rc = upload(vA, &T->vA, &bytes);
   if (rc == EGFEM_OK) rc = upload(kS, &T->kS, &bytes);
   if (rc == EGFEM_OK && !sym) rc = upload(jS, &T->jS, &bytes);
+  if (rc == EGFEM_OK) rc = upload(kpS, &T->kpS, &bytes);
+  if (rc == EGFEM_OK && !sym) rc = upload(jpS, &T->jpS, &bytes);
   if (rc == EGFEM_OK && !sym) rc = upload(jptrB, &T->jptrB, &bytes);
   if (rc == EGFEM_OK && !sym) rc = upload(jB, &T->jB, &bytes);
   if (rc == EGFEM_OK && !sym) rc = upload(vB, &T->vB, &bytes);
@@ -361,6 +369,7 @@ extern "C" int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords
     T->jB = T->kA;
     T->vB = T->vA;
     T->jS = T->kS;
+    T->jpS = T->kpS;
   }
   T->device_bytes = bytes;
   if (rc != EGFEM_OK) {

@@ -54,6 +54,8 @@ struct TensorView {
   const double* vB;
   const uint16_t* kS;       // block-relative slot of (i, k) of every A entry
   const uint16_t* jS;       // block-relative slot of (i, j) of every B entry
+  const uint16_t* kpS;      // A fiber start relative to the block's first A entry
+  const uint16_t* jpS;      // B fiber start relative to the block's first B entry
   const double* kval;
 };
 
@@ -104,7 +106,7 @@ struct ActionRegs {
   int kk[Per<NT>::P];       // block-relative slot of (i, k)
   double vv[Per<NT>::P];
   int cc[Per<NT>::S];
-  int kp[Per<NT>::S];
+  int kp[Per<NT>::S];       // fiber start relative to the block's first entry
   double kv[Per<NT>::S];
   int r0, s0, p0, np, ns, nr, rp;
   double ldi;
@@ -144,7 +146,7 @@ __device__ __forceinline__ void action_load(const TensorView& T, int64_t b, cons
   for (int q = 0; q < SS; ++q) {
     const int s = R.s0 + clamp_hi(tid + q * NT, R.ns);
     R.cc[q] = T.col[s];
-    R.kp[q] = T.kptrA[s];
+    R.kp[q] = T.kpS[s];
     R.kv[q] = PROBLEM ? kvp[s] : 0.0;
   }
   const int i = R.r0 + clamp_hi(tid, R.nr);
@@ -205,7 +207,7 @@ __device__ __forceinline__ void action_compute(const ActionRegs<NT>& R, const do
     }
     if (s < R.ns) {
       L.aS[s] = as;
-      L.spa[s] = R.kp[q] - R.p0;
+      L.spa[s] = R.kp[q];
     }
   }
   if (tid == 0) {
@@ -344,8 +346,8 @@ __device__ void rowblock_jacobian(const TensorView& T, int64_t b, const double* 
   for (int q = 0; q < SS; ++q) {
     const int s = s0 + clamp_hi(tid + q * NT, ns);
     cc[q] = T.col[s];
-    kpa[q] = T.kptrA[s];
-    kpb[q] = T.jptrB[s];
+    kpa[q] = T.kpS[s];
+    kpb[q] = T.jpS[s];
     kv[q] = kvp[s];
   }
   const bool has_row = tid < nr;
@@ -384,8 +386,8 @@ __device__ void rowblock_jacobian(const TensorView& T, int64_t b, const double* 
     if (s < ns) {
       L.aS[s] = problem_a ? fma(uj[q], uj[q], a0 ? aj[q] : a0c) : aj[q];
       L.uS[s] = uj[q];
-      L.spa[s] = kpa[q] - pa0;
-      L.spb[s] = kpb[q] - pb0;
+      L.spa[s] = kpa[q];
+      L.spb[s] = kpb[q];
     }
   }
   if (tid == 0) {

@@ -96,6 +96,8 @@ struct egfem_tensor_s {
   double* vB = nullptr;         // [nnz]
   uint16_t* kS = nullptr;       // [nnz]  block-relative slot of (i, k) of every A entry
   uint16_t* jS = nullptr;       // [nnz]  block-relative slot of (i, j) of every B entry (aliases kS)
+  uint16_t* kpS = nullptr;      // [slots] A fiber start relative to the block's first A entry
+  uint16_t* jpS = nullptr;      // [slots] B fiber start relative to the block's first B entry (aliases)
   double* kval = nullptr;       // [slots]
   double* mval = nullptr;       // [slots]
   int32_t* blk_row = nullptr;   // [row_blocks+1]

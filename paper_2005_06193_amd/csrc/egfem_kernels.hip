@@ -62,6 +62,8 @@ dev::TensorView view_of(const egfem_tensor_s* T) {
   v.vB = T->vB;
   v.kS = T->kS;
   v.jS = T->jS;
+  v.kpS = T->kpS;
+  v.jpS = T->jpS;
   v.kval = T->kval;
   return v;
 }
