@@ -463,8 +463,10 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch,
-                "limiter": ("grid barriers and gather latency: the 2D-256 system (J 5.5 MB, vectors "
-                            "0.5 MB) stays in L2/MALL, HBM traffic is 0.36x the algorithmic bytes")
+                "limiter": ("three grid synchronisations per BiCGStab iteration; the register-resident "
+                            "kernel keeps J and the row vectors on chip"
+                            + (", measured HBM traffic %.2fx the algorithmic bytes"
+                               % tr["krylov_bicgstab"]["ratio"] if traffic is not None else ""))
                 if dom == "krylov_bicgstab" else None}
 
     micro = None if args.no_micro else tensor_action_suite()
