@@ -72,7 +72,7 @@ __device__ double ew_forcing(int k, double nF, double nF_prev, double eta_prev, 
   return fmin(eta, eta_max);
 }
 
-template <int NT, int L>
+template <int NT, int RS>
 __global__ __launch_bounds__(NT) void k_newton_batched(const Inst* __restrict__ insts,
                                                        const int32_t* __restrict__ wg2inst, BatchOpts O) {
   __shared__ dev::RowBlockLds lds;
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(NT) void k_newton_batched(const Inst* __restrict__ 
     dev::KArgs KA = I.K;
     KA.rtol = rtol;
     KA.max_iter = O.max_krylov;
-    const dev::KOut ko = dev::team_bicgstab<NT, L>(tm, KA, rb, re, sh, &sh_abort);
+    const dev::KOut ko = dev::team_bicgstab<NT, row_L(RS), row_K(RS)>(tm, KA, rb, re, sh, &sh_abort);
     if ((abort = ko.abort)) break;
     kry += ko.iters;
     if (writer && k < EGFEM_HIST) {
@@ -181,19 +181,19 @@ __global__ __launch_bounds__(NT) void k_newton_batched(const Inst* __restrict__ 
   }
 }
 
-template <int NT, int L>
+template <int NT, int RS>
 hipError_t launch_NL(const Inst* insts, const int32_t* wg2inst, const BatchOpts& O, unsigned G,
                      hipStream_t st) {
   void* args[] = {(void*)&insts, (void*)&wg2inst, (void*)&O};
-  return hipLaunchCooperativeKernel((const void*)k_newton_batched<NT, L>, dim3(G), dim3(NT), args, 0, st);
+  return hipLaunchCooperativeKernel((const void*)k_newton_batched<NT, RS>, dim3(G), dim3(NT), args, 0, st);
 }
 
-template <int NT, int L>
+template <int NT, int RS>
 int cap_NL() {
   int dev = 0, per_cu = 0, cus = 0;
   hipGetDevice(&dev);
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_newton_batched<NT, L>, NT, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_newton_batched<NT, RS>, NT, 0) !=
       hipSuccess)
     return 0;
   return per_cu * cus;
@@ -203,22 +203,30 @@ template <int NT>
 hipError_t launch_T(int L, const Inst* insts, const int32_t* wg2inst, const BatchOpts& O, unsigned G,
                     hipStream_t st) {
   switch (L) {
+    case 0: return launch_NL<NT, 0>(insts, wg2inst, O, G, st);
+    case 1: return launch_NL<NT, 1>(insts, wg2inst, O, G, st);
+    case 2: return launch_NL<NT, 2>(insts, wg2inst, O, G, st);
+    case 3: return launch_NL<NT, 3>(insts, wg2inst, O, G, st);
     case 4: return launch_NL<NT, 4>(insts, wg2inst, O, G, st);
-    case 8: return launch_NL<NT, 8>(insts, wg2inst, O, G, st);
-    case 16: return launch_NL<NT, 16>(insts, wg2inst, O, G, st);
-    case 32: return launch_NL<NT, 32>(insts, wg2inst, O, G, st);
-    default: return launch_NL<NT, 64>(insts, wg2inst, O, G, st);
+    case 5: return launch_NL<NT, 5>(insts, wg2inst, O, G, st);
+    case 6: return launch_NL<NT, 6>(insts, wg2inst, O, G, st);
+    case 7: return launch_NL<NT, 7>(insts, wg2inst, O, G, st);
+    default: return launch_NL<NT, 8>(insts, wg2inst, O, G, st);
   }
 }
 
 template <int NT>
 int cap_T(int L) {
   switch (L) {
+    case 0: return cap_NL<NT, 0>();
+    case 1: return cap_NL<NT, 1>();
+    case 2: return cap_NL<NT, 2>();
+    case 3: return cap_NL<NT, 3>();
     case 4: return cap_NL<NT, 4>();
-    case 8: return cap_NL<NT, 8>();
-    case 16: return cap_NL<NT, 16>();
-    case 32: return cap_NL<NT, 32>();
-    default: return cap_NL<NT, 64>();
+    case 5: return cap_NL<NT, 5>();
+    case 6: return cap_NL<NT, 6>();
+    case 7: return cap_NL<NT, 7>();
+    default: return cap_NL<NT, 8>();
   }
 }
 
@@ -308,8 +316,13 @@ int egfem_batch_create(int count, const egfem_tensor_t* Ts, const egfem_problem*
   B->count = count;
   B->NT = threads ? threads : 512;
   B->Ts.assign(Ts, Ts + count);
-  int L = 4;
-  for (int m = 0; m < count; ++m) L = std::max(L, Ts[m]->krylov_lanes);
+  // one row shape for the launch: the longest row over the instances
+  int lanes = 4, max_row = 0;
+  for (int m = 0; m < count; ++m) {
+    lanes = std::max(lanes, Ts[m]->krylov_lanes);
+    max_row = std::max(max_row, Ts[m]->max_row_slots);
+  }
+  const int L = row_shape_for(max_row, lanes);
   B->L = L;
   const int cap = B->NT == 1024 ? cap_T<1024>(L) : cap_T<512>(L);
   if (cap < count) {

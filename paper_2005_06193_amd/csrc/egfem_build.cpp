@@ -341,6 +341,7 @@ extern "C" int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords
   int klanes = 4;
   while (2 * klanes < max_row_slots && klanes < 64) klanes *= 2;
   T->krylov_lanes = klanes;
+  T->krylov_rs = row_shape_for(max_row_slots, klanes);
   T->row_blocks = (int64_t)blk.size() - 1;
   T->h_rowptr = rowptr;
   hipGetDevice(&T->device);

@@ -637,11 +637,14 @@ struct KOut {
 
 // Rows [rb, re), L lanes per row: f(i, (J x1)_i, (J x2)_i) on lane 0 of each
 // row's group (x2 may be null); x1 / x2 gathered coherently when SH.
-// L is chosen >= half the longest row, so a lane's first two entries are
-// loaded unconditionally at clamped slots (every row holds its diagonal, so
-// the clamp stays in the row) and masked after: the index, value and gather
-// loads of both entries are in flight together.  Longer rows finish in a loop.
-template <int NT, int L, bool SH, typename Fn>
+// A lane's first K entries (slots beg + lane + kL, k < K) are loaded
+// unconditionally at clamped slots (every row holds its diagonal, so the clamp
+// stays in the row) and masked after: the index, value and gather loads of all
+// of them are in flight together.  Entries past K*L finish in a loop (none when
+// K*L covers the longest row, as the host's choice of L and K ensures for
+// meshes of moderate degree).  L = 1 runs one thread per row: a quarter of the
+// passes of L = 4 for the same workgroup.
+template <int NT, int L, int K, bool SH, typename Fn>
 __device__ __forceinline__ void spmv_rows(const KArgs& A, int rb, int re, const double* __restrict__ x1,
                                           const double* __restrict__ x2, Fn f) {
   constexpr int RPP = NT / L;
@@ -652,34 +655,39 @@ __device__ __forceinline__ void spmv_rows(const KArgs& A, int rb, int re, const 
     const bool row = i < re;
     const int ic = min(i, re - 1);
     const int beg = A.rowptr[ic], end = A.rowptr[ic + 1];
-    const int s0 = beg + lane, s1 = s0 + L;
-    const int q0 = min(s0, end - 1), q1 = min(s1, end - 1);
-    const int c0 = A.col[q0], c1 = A.col[q1];
-    int v0 = q0, v1 = q1;
+    int c[K], v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      v[k] = min(beg + lane + k * L, end - 1);
+      c[k] = A.col[v[k]];
+    }
     if (A.perm) {
-      v0 = A.perm[q0];
-      v1 = A.perm[q1];
+#pragma unroll
+      for (int k = 0; k < K; ++k) v[k] = A.perm[v[k]];
     }
-    const double a0 = A.val[v0], a1 = A.val[v1];
-    const double y0 = ld<SH>(x1 + c0), y1 = ld<SH>(x1 + c1);
-    double z0 = 0.0, z1 = 0.0;
+    double a[K], y[K], z[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) a[k] = A.val[v[k]];
+#pragma unroll
+    for (int k = 0; k < K; ++k) y[k] = ld<SH>(x1 + c[k]);
     if (x2) {
-      z0 = ld<SH>(x2 + c0);
-      z1 = ld<SH>(x2 + c1);
+#pragma unroll
+      for (int k = 0; k < K; ++k) z[k] = ld<SH>(x2 + c[k]);
     }
-    const bool m0 = row && s0 < end, m1 = row && s1 < end;
-    double acc1 = m0 ? a0 * y0 : 0.0;
-    double acc2 = m0 ? a0 * z0 : 0.0;
-    if (m1) {
-      acc1 = fma(a1, y1, acc1);
-      acc2 = fma(a1, z1, acc2);
+    double acc1 = 0.0, acc2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (row && beg + lane + k * L < end) {
+        acc1 = fma(a[k], y[k], acc1);
+        if (x2) acc2 = fma(a[k], z[k], acc2);
+      }
     }
     if (row) {
-      for (int s = s1 + L; s < end; s += L) {
-        const double a = A.perm ? A.val[A.perm[s]] : A.val[s];
-        const int c = A.col[s];
-        acc1 = fma(a, ld<SH>(x1 + c), acc1);
-        if (x2) acc2 = fma(a, ld<SH>(x2 + c), acc2);
+      for (int s = beg + lane + K * L; s < end; s += L) {
+        const double w = A.perm ? A.val[A.perm[s]] : A.val[s];
+        const int cs = A.col[s];
+        acc1 = fma(w, ld<SH>(x1 + cs), acc1);
+        if (x2) acc2 = fma(w, ld<SH>(x2 + cs), acc2);
       }
     }
 #pragma unroll
@@ -699,7 +707,7 @@ __device__ __forceinline__ void spmv_rows(const KArgs& A, int rb, int re, const 
 //                                       -> (t,s) (t,t) (rhat,s) (rhat,t) (s,s)
 //   C: omega; x += alpha phat + omega D^-1 s; r = s - omega t;
 //      rho' = (rhat,s) - omega (rhat,t); beta; p; phat = D^-1 p; rh = D^-1 r -> (r,r)
-template <int NT, int L>
+template <int NT, int L, int K>
 __device__ KOut team_bicgstab(Team& tm, const KArgs& A, int rb, int re, double* sh, int* sh_abort) {
   const int tid = threadIdx.x;
   double red[kMaxRed];
@@ -720,7 +728,7 @@ __device__ KOut team_bicgstab(Team& tm, const KArgs& A, int rb, int re, double* 
       red[1] = fma(bi, bi, red[1]);
     }
   } else {
-    spmv_rows<NT, L, false>(A, rb, re, A.x, nullptr, [&](int i, double Jx, double) {
+    spmv_rows<NT, L, K, false>(A, rb, re, A.x, nullptr, [&](int i, double Jx, double) {
       const double bi = A.rhs_scale * A.rhs[i];
       const double ri = bi - Jx;
       const double di = A.dinv[i] * ri;
@@ -767,7 +775,7 @@ __device__ KOut team_bicgstab(Team& tm, const KArgs& A, int rb, int re, double* 
       }
       // A: v = J phat, z = J rh ; (rhat, v)
       EGFEM_ZERO_RED();
-      spmv_rows<NT, L, true>(A, rb, re, A.phat, A.rh, [&](int i, double vi, double zi) {
+      spmv_rows<NT, L, K, true>(A, rb, re, A.phat, A.rh, [&](int i, double vi, double zi) {
         A.v[i] = vi;
         A.z[i] = zi;
         st_sh(A.vh + i, A.dinv[i] * vi);
@@ -780,7 +788,7 @@ __device__ KOut team_bicgstab(Team& tm, const KArgs& A, int rb, int re, double* 
       const double alpha = rho / rv;
       // B: y = J vh ; s, t
       EGFEM_ZERO_RED();
-      spmv_rows<NT, L, true>(A, rb, re, A.vh, nullptr, [&](int i, double yi, double) {
+      spmv_rows<NT, L, K, true>(A, rb, re, A.vh, nullptr, [&](int i, double yi, double) {
         const double si = fma(-alpha, A.v[i], A.r[i]);
         const double ti = fma(-alpha, yi, A.z[i]);
         const double hi = A.rhat[i];

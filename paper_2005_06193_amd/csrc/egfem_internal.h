@@ -77,6 +77,7 @@ struct egfem_tensor_s {
   int max_row_slots = 0;
   int lanes_per_row = 8;        // SpMV sub-wave width (power of two >= max row length)
   int krylov_lanes = 4;         // persistent-Krylov SpMV width (power of two >= max row / 2)
+  int krylov_rs = 4;            // streaming-Krylov row shape code (see row_L / row_K)
   int action_runs_target = 0;   // workgroups of the action kernel (block runs; 0 = one per block)
   int action_pipe = 0;          // 1: software-pipelined block runs
   int tuned_krylov_blocks = 0;  // Krylov grid chosen by the autotuner (0 = heuristic)
@@ -109,6 +110,26 @@ struct egfem_tensor_s {
 };
 
 namespace egfem {
+
+// Row shapes of the streaming BiCGStab SpMV, by code: L lanes per row, K
+// entries per lane loaded at once (rows of up to L*K entries need no tail loop).
+constexpr int kRowShapes = 9;
+constexpr int kRowShapeLK[kRowShapes][2] = {{1, 8}, {2, 4}, {4, 2}, {8, 2}, {16, 2},
+                                            {32, 2}, {64, 2}, {1, 16}, {2, 8}};
+constexpr int row_L(int rs) { return kRowShapeLK[rs][0]; }
+constexpr int row_K(int rs) { return kRowShapeLK[rs][1]; }
+// Shape for rows of at most max_row_slots entries (lanes: power of two >= max_row / 2).
+inline int row_shape_for(int max_row_slots, int lanes) {
+  if (max_row_slots <= 8) return 0;     // (1, 8): one thread per row
+  if (max_row_slots <= 16) return 8;    // (2, 8)
+  switch (lanes) {
+    case 4: return 2;
+    case 8: return 3;
+    case 16: return 4;
+    case 32: return 5;
+    default: return 6;
+  }
+}
 
 // Kernel launchers (egfem_kernels.hip).  All return hipError_t of the launch.
 struct ProblemView {

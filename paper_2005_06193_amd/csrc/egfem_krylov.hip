@@ -37,13 +37,13 @@ struct LaunchArgs {
 };
 
 // One team spanning the whole grid.
-template <int NT, int L>
+template <int NT, int RS>
 __global__ __launch_bounds__(NT) void k_bicgstab(LaunchArgs P) {
   __shared__ double sh[dev::kShWords<NT>];
   __shared__ int sh_abort;
   dev::Team tm{blockIdx.x, gridDim.x, P.ctrl, P.red, 0u};
   const int rb = P.krow[blockIdx.x], re = P.krow[blockIdx.x + 1];
-  const dev::KOut o = dev::team_bicgstab<NT, L>(tm, P.A, rb, re, sh, &sh_abort);
+  const dev::KOut o = dev::team_bicgstab<NT, row_L(RS), row_K(RS)>(tm, P.A, rb, re, sh, &sh_abort);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     P.out[0] = o.abort ? (double)EGFEM_ERR_HIP : (double)o.status;
     P.out[1] = (double)o.iters;
@@ -87,33 +87,37 @@ int max_coresident_reg_NK() {
   return per_cu * cus;
 }
 
-template <int NT, int L>
+template <int NT, int RS>
 hipError_t launch_NL(const LaunchArgs& A, unsigned G, hipStream_t st) {
   void* args[] = {(void*)&A};
-  return hipLaunchCooperativeKernel((const void*)k_bicgstab<NT, L>, dim3(G), dim3(NT), args, 0, st);
+  return hipLaunchCooperativeKernel((const void*)k_bicgstab<NT, RS>, dim3(G), dim3(NT), args, 0, st);
 }
 
-template <int NT, int L>
+template <int NT, int RS>
 int max_coresident_NL() {
   int dev = 0, per_cu = 0, cus = 0;
   hipGetDevice(&dev);
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_bicgstab<NT, L>, NT, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_bicgstab<NT, RS>, NT, 0) !=
       hipSuccess)
     return 0;
   return per_cu * cus;
 }
 
-// Dispatch over the compiled (threads, lanes-per-row) shapes.
+// Dispatch over the compiled (threads, row shape) pairs.
 template <int NT>
 struct ShapeNT {
-  static hipError_t launch(int L, const LaunchArgs& A, unsigned G, hipStream_t st) {
-    switch (L) {
+  static hipError_t launch(int rs, const LaunchArgs& A, unsigned G, hipStream_t st) {
+    switch (rs) {
+      case 0: return launch_NL<NT, 0>(A, G, st);
+      case 1: return launch_NL<NT, 1>(A, G, st);
+      case 2: return launch_NL<NT, 2>(A, G, st);
+      case 3: return launch_NL<NT, 3>(A, G, st);
       case 4: return launch_NL<NT, 4>(A, G, st);
-      case 8: return launch_NL<NT, 8>(A, G, st);
-      case 16: return launch_NL<NT, 16>(A, G, st);
-      case 32: return launch_NL<NT, 32>(A, G, st);
-      default: return launch_NL<NT, 64>(A, G, st);
+      case 5: return launch_NL<NT, 5>(A, G, st);
+      case 6: return launch_NL<NT, 6>(A, G, st);
+      case 7: return launch_NL<NT, 7>(A, G, st);
+      default: return launch_NL<NT, 8>(A, G, st);
     }
   }
   // register-resident form: rows of at most kResidentRow entries
@@ -121,13 +125,17 @@ struct ShapeNT {
     return launch_reg_NK<NT, kResidentRow>(A, G, st);
   }
   static int cap_reg() { return max_coresident_reg_NK<NT, kResidentRow>(); }
-  static int cap(int L) {
-    switch (L) {
+  static int cap(int rs) {
+    switch (rs) {
+      case 0: return max_coresident_NL<NT, 0>();
+      case 1: return max_coresident_NL<NT, 1>();
+      case 2: return max_coresident_NL<NT, 2>();
+      case 3: return max_coresident_NL<NT, 3>();
       case 4: return max_coresident_NL<NT, 4>();
-      case 8: return max_coresident_NL<NT, 8>();
-      case 16: return max_coresident_NL<NT, 16>();
-      case 32: return max_coresident_NL<NT, 32>();
-      default: return max_coresident_NL<NT, 64>();
+      case 5: return max_coresident_NL<NT, 5>();
+      case 6: return max_coresident_NL<NT, 6>();
+      case 7: return max_coresident_NL<NT, 7>();
+      default: return max_coresident_NL<NT, 8>();
     }
   }
 };
@@ -181,7 +189,7 @@ int krylov_bicgstab(egfem_tensor_s* T, const double* jval, const double* dinv, c
   if (threads == 0) threads = T->tuned_krylov_threads;
   if (blocks <= 0) blocks = T->tuned_krylov_blocks;
   const int NT = (threads == 256 || threads == 512 || threads == 1024) ? threads : kKrylovThreads;
-  const int cap = cap_shape(NT, T->krylov_lanes);
+  const int cap = cap_shape(NT, T->krylov_rs);
   if (cap <= 0) return fail(EGFEM_ERR_HIP, "Krylov kernel cannot be resident");
   int G = blocks;
   if (G <= 0) {
@@ -245,7 +253,7 @@ int krylov_bicgstab(egfem_tensor_s* T, const double* jval, const double* dinv, c
   const bool resident = T->krylov_kernel == 0 && T->max_row_slots <= kResidentRow &&
                         W.krow_maxrows <= NT && T->n < (int64_t(1) << 28) && G <= cap_shape_reg(NT);
   const hipError_t e = resident ? launch_shape_reg(NT, P, (unsigned)G, st)
-                                : launch_shape(NT, L, P, (unsigned)G, st);
+                                : launch_shape(NT, T->krylov_rs, P, (unsigned)G, st);
   if (e != hipSuccess) {
     if (ev0) hipEventDestroy(ev0);
     if (ev1) hipEventDestroy(ev1);
