@@ -643,10 +643,12 @@ struct KOut {
 // of them are in flight together.  Entries past K*L finish in a loop (none when
 // K*L covers the longest row, as the host's choice of L and K ensures for
 // meshes of moderate degree).  L = 1 runs one thread per row: a quarter of the
-// passes of L = 4 for the same workgroup.
-template <int NT, int L, int K, bool SH, typename Fn>
+// passes of L = 4 for the same workgroup.  pre(i) loads the row values f needs
+// (issued with the row pointers, so they arrive during the product) and f
+// receives them: f(i, (J x1)_i, (J x2)_i, pre(i)).
+template <int NT, int L, int K, bool SH, typename Pre, typename Fn>
 __device__ __forceinline__ void spmv_rows(const KArgs& A, int rb, int re, const double* __restrict__ x1,
-                                          const double* __restrict__ x2, Fn f) {
+                                          const double* __restrict__ x2, Pre pre, Fn f) {
   constexpr int RPP = NT / L;
   const int sub = threadIdx.x / L;
   const int lane = threadIdx.x % L;
@@ -655,6 +657,7 @@ __device__ __forceinline__ void spmv_rows(const KArgs& A, int rb, int re, const 
     const bool row = i < re;
     const int ic = min(i, re - 1);
     const int beg = A.rowptr[ic], end = A.rowptr[ic + 1];
+    const auto pv = pre(ic);
     int c[K], v[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -695,7 +698,7 @@ __device__ __forceinline__ void spmv_rows(const KArgs& A, int rb, int re, const 
       acc1 += __shfl_xor(acc1, off, L);
       acc2 += __shfl_xor(acc2, off, L);
     }
-    if (row && lane == 0) f(i, acc1, acc2);
+    if (row && lane == 0) f(i, acc1, acc2, pv);
   }
 }
 
@@ -728,10 +731,12 @@ __device__ KOut team_bicgstab(Team& tm, const KArgs& A, int rb, int re, double* 
       red[1] = fma(bi, bi, red[1]);
     }
   } else {
-    spmv_rows<NT, L, K, false>(A, rb, re, A.x, nullptr, [&](int i, double Jx, double) {
-      const double bi = A.rhs_scale * A.rhs[i];
+    spmv_rows<NT, L, K, false>(A, rb, re, A.x, nullptr, [&](int i) {
+      return make_double2(A.rhs[i], A.dinv[i]);
+    }, [&](int i, double Jx, double, double2 q) {
+      const double bi = A.rhs_scale * q.x;
       const double ri = bi - Jx;
-      const double di = A.dinv[i] * ri;
+      const double di = q.y * ri;
       A.r[i] = ri;
       A.rhat[i] = ri;
       A.p[i] = ri;
@@ -775,11 +780,13 @@ __device__ KOut team_bicgstab(Team& tm, const KArgs& A, int rb, int re, double* 
       }
       // A: v = J phat, z = J rh ; (rhat, v)
       EGFEM_ZERO_RED();
-      spmv_rows<NT, L, K, true>(A, rb, re, A.phat, A.rh, [&](int i, double vi, double zi) {
+      spmv_rows<NT, L, K, true>(A, rb, re, A.phat, A.rh, [&](int i) {
+        return make_double2(A.rhat[i], A.dinv[i]);
+      }, [&](int i, double vi, double zi, double2 q) {
         A.v[i] = vi;
         A.z[i] = zi;
-        st_sh(A.vh + i, A.dinv[i] * vi);
-        red[0] = fma(A.rhat[i], vi, red[0]);
+        st_sh(A.vh + i, q.y * vi);
+        red[0] = fma(q.x, vi, red[0]);
       });
       if ((o.abort = team_reduce<NT>(tm, slot, red, 1, sh, sh_abort))) break;
       slot = slot % 6 + 1;
@@ -788,10 +795,12 @@ __device__ KOut team_bicgstab(Team& tm, const KArgs& A, int rb, int re, double* 
       const double alpha = rho / rv;
       // B: y = J vh ; s, t
       EGFEM_ZERO_RED();
-      spmv_rows<NT, L, K, true>(A, rb, re, A.vh, nullptr, [&](int i, double yi, double) {
-        const double si = fma(-alpha, A.v[i], A.r[i]);
-        const double ti = fma(-alpha, yi, A.z[i]);
-        const double hi = A.rhat[i];
+      spmv_rows<NT, L, K, true>(A, rb, re, A.vh, nullptr, [&](int i) {
+        return make_double4(A.v[i], A.r[i], A.z[i], A.rhat[i]);
+      }, [&](int i, double yi, double, double4 q) {
+        const double si = fma(-alpha, q.x, q.y);
+        const double ti = fma(-alpha, yi, q.z);
+        const double hi = q.w;
         A.s[i] = si;
         A.t[i] = ti;
         red[0] = fma(ti, si, red[0]);
@@ -820,18 +829,39 @@ __device__ KOut team_bicgstab(Team& tm, const KArgs& A, int rb, int re, double* 
       rho = rho_new;
       // C: x, r, p, phat, rh ; (r, r)
       EGFEM_ZERO_RED();
-      for (int i = rb + tid; i < re; i += NT) {
-        const double di = A.dinv[i];
-        const double si = A.s[i];
-        const double xi = fma(alpha, ld_sh(A.phat + i), fma(omega, di * si, ld_sh(A.x + i)));
-        const double ri = fma(-omega, A.t[i], si);
-        const double pi = fma(beta, fma(-omega, A.v[i], A.p[i]), ri);
-        st_sh(A.x + i, xi);
-        A.r[i] = ri;
-        A.p[i] = pi;
-        st_sh(A.phat + i, di * pi);
-        st_sh(A.rh + i, di * ri);
-        red[0] = fma(ri, ri, red[0]);
+      // two rows per step, every load of both before the first store (the
+      // stores could alias the next row's loads, so the compiler would not
+      // hoist them); the partial sum keeps the row order
+      for (int i = rb + tid; i < re; i += 2 * NT) {
+        const int i2 = i + NT;
+        const bool two = i2 < re;
+        const int j = two ? i2 : i;
+        const double d1 = A.dinv[i], d2 = A.dinv[j];
+        const double s1 = A.s[i], s2 = A.s[j];
+        const double t1 = A.t[i], t2 = A.t[j];
+        const double v1 = A.v[i], v2 = A.v[j];
+        const double p1 = A.p[i], p2 = A.p[j];
+        const double h1 = ld_sh(A.phat + i), h2 = ld_sh(A.phat + j);
+        const double x1 = ld_sh(A.x + i), x2 = ld_sh(A.x + j);
+        const double xn1 = fma(alpha, h1, fma(omega, d1 * s1, x1));
+        const double xn2 = fma(alpha, h2, fma(omega, d2 * s2, x2));
+        const double r1 = fma(-omega, t1, s1), r2 = fma(-omega, t2, s2);
+        const double pn1 = fma(beta, fma(-omega, v1, p1), r1);
+        const double pn2 = fma(beta, fma(-omega, v2, p2), r2);
+        st_sh(A.x + i, xn1);
+        A.r[i] = r1;
+        A.p[i] = pn1;
+        st_sh(A.phat + i, d1 * pn1);
+        st_sh(A.rh + i, d1 * r1);
+        red[0] = fma(r1, r1, red[0]);
+        if (two) {
+          st_sh(A.x + i2, xn2);
+          A.r[i2] = r2;
+          A.p[i2] = pn2;
+          st_sh(A.phat + i2, d2 * pn2);
+          st_sh(A.rh + i2, d2 * r2);
+          red[0] = fma(r2, r2, red[0]);
+        }
       }
       if ((o.abort = team_reduce<NT>(tm, slot, red, 1, sh, sh_abort))) break;
       slot = slot % 6 + 1;
