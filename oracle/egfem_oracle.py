@@ -20,6 +20,8 @@ Finite Element Method", arXiv 2005.06193):
   operator Pi_u of Sec. 3.2 is the identity.
 * Sec. 4 / eq. (EGFEM_root) reduced to u: F(u) = [K u] + T:(u (x) a(u)) - d
   with a(u) = a0 + u*u evaluated pointwise at the nodes (eq. egfem_coeffs).
+* Sec. 4, Picard iteration (Example picard_iteration): u^{n+1} solves
+  ([K] + T . a(u^n)) u^{n+1} = d, then a is updated pointwise.
 * Sec. 4, Newton iteration: u <- u - DF(u)^{-1} F(u).  The Jacobian needs no
   integration: DF = [K] + T . a + (T ._2 u) diag(a'(u)), the contractions of
   the Notation in Sec. 3.3.  The lifted iteration on z = (u, a) with the block
@@ -433,6 +435,50 @@ def newton(p: Problem, u0: Optional[np.ndarray] = None, tol: float = 1e-10,
         st.iterations = it + 1
         st.residual_norms.append(nF)
     st.status = "converged" if nF <= tol * nF0 else "not_converged"
+    return u, st
+
+
+# ----------------------------------------------------------------------------
+# Picard iteration (Sec. 4, Example picard_iteration)
+# ----------------------------------------------------------------------------
+def picard_matrix(p: Problem, u: np.ndarray) -> sp.csr_matrix:
+    """A(u) = [K] + T . a(u): the previous iterate substituted into the
+    nonlinear coefficient, Dirichlet rows -> identity, columns -> 0."""
+    A = contract_first(p.T, nodal_a(p, u))
+    if p.K is not None:
+        A = A + p.K
+    return _apply_dirichlet(p, A)
+
+
+@dataclass
+class PicardStats:
+    iterations: int = 0
+    updates: list = field(default_factory=list)   # ||u^{n+1} - u^n|| / ||u^{n+1}||
+    status: str = "not_converged"
+
+
+def picard(p: Problem, u0: Optional[np.ndarray] = None, tol: float = 1e-12, max_iter: int = 500):
+    """u^{n+1} = A(u^n)^{-1} d with d's Dirichlet rows zero (u_D = 0), the new
+    coefficient a^{n+1} = a0 + (u^{n+1})^2 evaluated pointwise.  Stops when
+    ||u^{n+1} - u^n||_2 <= tol ||u^{n+1}||_2."""
+    u = np.zeros(p.n) if u0 is None else np.array(u0, dtype=np.float64)
+    u[p.dirichlet] = 0.0
+    b = p.d.copy()
+    b[p.dirichlet] = 0.0
+    st = PicardStats()
+    for it in range(max_iter):
+        un = spla.spsolve(picard_matrix(p, u).tocsc(), b)
+        nu = float(np.linalg.norm(un))
+        upd = float(np.linalg.norm(un - u)) / nu if nu > 0 else 0.0
+        u = un
+        st.iterations = it + 1
+        st.updates.append(upd)
+        if not np.isfinite(upd):
+            st.status = "nonfinite"
+            return u, st
+        if upd <= tol:
+            st.status = "converged"
+            return u, st
     return u, st
 
 

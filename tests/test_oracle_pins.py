@@ -469,3 +469,59 @@ def test_elementwise_residual_equals_tensor_residual():
         D = p.T.dense()
         Dr = Tr.dense()
         assert np.abs(D[rows] - Dr[rows]).max() <= 1e-15 * np.abs(D).max()
+
+
+# ----------------------------------------------------------------------------
+# Picard iteration (Sec. 4, Example picard_iteration)
+# ----------------------------------------------------------------------------
+def test_picard_single_node_recurrence():
+    """n = 2, h = 1/2: the one free row of A(u) = [T . a(u)] is 4 + 2u^2, so
+    the Picard iterates follow u <- d_1 / (4 + 2u^2) exactly and converge to
+    the real root of 4u + 2u^3 = d_1."""
+    m = W.mesh_1d(2)
+    for fval in (0.3, 7.0, -12.0):
+        wl = W.Workload("t", m, np.full(3, fval), O.FORM_STIFF, None, 1.0, False, 1e-14, 0)
+        p = O.build_problem(wl)
+        d1 = p.d[1]
+        t = 0.0
+        for n_it in range(1, 6):
+            t = d1 / (4.0 + 2.0 * t * t)
+            u, st = O.picard(p, tol=0.0, max_iter=n_it)
+            assert abs(u[1] - t) <= 1e-14 * max(1.0, abs(t))
+            assert u[0] == 0.0 and u[2] == 0.0
+        u, st = O.picard(p, tol=1e-15, max_iter=500)
+        ex = _cardano(2.0, -d1 / 2.0)
+        assert st.status == "converged"
+        assert abs(u[1] - ex) <= 1e-13 * max(1.0, abs(ex))
+
+
+@pytest.mark.parametrize("dim,n,form", [(1, 12, O.FORM_STIFF), (2, 6, O.FORM_STIFF), (2, 5, O.FORM_MASS),
+                                        (3, 3, O.FORM_STIFF)])
+def test_picard_matrix_reproduces_residual(dim, n, form):
+    """A(u) u - d = F(u) on the free rows (T : (u (x) a) = (T . a) u), with
+    identity rows on the Dirichlet nodes."""
+    p = _small_problem(dim, n, form)
+    u = np.random.default_rng(4).uniform(-1, 1, p.n)
+    u[p.dirichlet] = 0.0
+    A = O.picard_matrix(p, u)
+    r = A @ u - p.d
+    F = O.residual(p, u)
+    assert np.linalg.norm((r - F)[p.free]) <= 1e-13 * np.linalg.norm(p.d)
+    Ad = A.toarray()
+    assert np.allclose(Ad, Ad.T, rtol=0, atol=1e-14 * np.abs(Ad).max())    # symmetric
+    assert np.all(Ad[np.ix_(p.dirichlet, p.dirichlet)] == np.eye(int(p.dirichlet.sum())))
+    assert np.linalg.eigvalsh(Ad[np.ix_(p.free, p.free)]).min() > 0          # positive definite
+
+
+@pytest.mark.parametrize("name", ["1d", "2d", "semilinear", "3d"])
+def test_picard_fixed_point_is_newton_solution(name):
+    wl = {"1d": lambda: W.nonlinear_diffusion_1d(64), "2d": lambda: W.nonlinear_diffusion_2d(20),
+          "semilinear": lambda: W.semilinear_2d(16), "3d": lambda: W.diffusion_3d(4)}[name]()
+    p = O.build_problem(wl)
+    up, st = O.picard(p, tol=1e-13)
+    un, _ = O.newton(p, tol=1e-14)
+    assert st.status == "converged"
+    assert np.linalg.norm(up - un) <= 1e-11 * np.linalg.norm(un)
+    # linear convergence: the update ratios stay below one after the first step
+    r = np.array(st.updates[1:-1]) / np.array(st.updates[:-2])
+    assert np.all(r < 1.0)
