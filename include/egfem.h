@@ -242,6 +242,63 @@ int egfem_solve(egfem_tensor_t T, const double* jval, int transpose, const doubl
                 double* x, double rtol, int max_iter, int* iters, double* relres, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Picard iteration (Sec. 4, Example picard_iteration): the previous iterate
+ * is substituted into the nonlinear coefficient and the linear system
+ *     ([K] + T . a(u^n)) u^{n+1} = d,   a(u^n) = a0 + (u^n)^2 pointwise,
+ * is solved for the new iterate; Dirichlet rows are identity rows with zero
+ * right-hand side.  The matrix is the A-stream emission of egfem_jacobian
+ * without the a' term; it is symmetric positive definite on the free rows,
+ * so the linear solves are Jacobi-preconditioned conjugate gradients
+ * (single-reduction arrangement, one persistent cooperative launch), warm
+ * started from u^n.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  double tol;                /* stop when ||u^{n+1} - u^n||_2 <= tol ||u^{n+1}||_2 (default 1e-12) */
+  int max_picard;            /* iteration cap (default 200) */
+  int max_krylov;            /* CG iteration cap per solve (default 20000) */
+  double krylov_rtol;        /* each solve: ||r|| <= krylov_rtol ||r_0|| with r_0 = d - A(u^n) u^n,
+                                i.e. relative to the nonlinear residual of u^n (default 1e-4) */
+  int krylov_blocks;         /* persistent CG grid size, 0 = launch shape of the handle */
+  int krylov_threads;        /* 256, 512, 1024, or 0 = launch shape of the handle */
+  int timing;                /* nonzero: time the matrix emissions and solves with HIP events */
+} egfem_picard_opts;
+
+typedef struct {
+  int status;                /* EGFEM_OK, EGFEM_NOT_CONVERGED or EGFEM_NONFINITE */
+  int picard_iters;
+  int krylov_iters;          /* total CG iterations */
+  double update;             /* last relative update ||u^{n+1} - u^n|| / ||u^{n+1}|| */
+  double res0;               /* ||F(u_0)||_2 over the free rows */
+  double res;                /* ||F(u)||_2 at the returned iterate */
+  double update_hist[EGFEM_HIST];
+  int krylov_hist[EGFEM_HIST];
+  double t_matrix_ms;        /* with timing: matrix emissions */
+  double t_krylov_ms;        /* with timing: CG launches */
+  int krylov_kernels;        /* CG kernels that ran: bit 0 register-resident, bit 1 streaming */
+} egfem_picard_stats;
+
+/* Fill opts with the defaults above. */
+void egfem_picard_opts_default(egfem_picard_opts* o);
+
+/* egfem_picard: Picard iteration from the guess in u (device [n_nodes];
+ * Dirichlet entries are set to 0) to the fixed point, written back into u.
+ * p as for egfem_newton; its a0 / a0_const / load / add_stiffness define F.
+ * s (host, nullable) receives the statistics.  Returns the status (EGFEM_OK
+ * when the update test passed) or a negative error.  Synchronises the stream. */
+int egfem_picard(egfem_tensor_t T, const egfem_problem* p, double* u, const egfem_picard_opts* o,
+                 egfem_picard_stats* s, void* stream);
+
+/* egfem_solve_cg: Jacobi-preconditioned conjugate gradients for A x = rhs with
+ * A (jval, T's pattern) symmetric positive definite, e.g. the matrix of a
+ * Picard step.  x: device, initial guess on input, solution on output.  Stops
+ * when ||rhs - A x||_2 <= rtol ||rhs||_2 (recursive residual) or after max_iter
+ * iterations; iters / relres (host, nullable) receive the outcome.  Returns
+ * EGFEM_OK, EGFEM_NOT_CONVERGED, EGFEM_BREAKDOWN (a non-positive curvature, so
+ * A is not SPD) or EGFEM_NONFINITE.  Synchronises the stream. */
+int egfem_solve_cg(egfem_tensor_t T, const double* jval, const double* rhs, double* x, double rtol,
+                   int max_iter, int* iters, double* relres, void* stream);
+
+/* ------------------------------------------------------------------------
  * Launch shapes and the autotuner.
  * ---------------------------------------------------------------------- */
 typedef struct {

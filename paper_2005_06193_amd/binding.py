@@ -64,6 +64,19 @@ class _Opts(C.Structure):
                 ("krylov_threads", C.c_int), ("timing", C.c_int)]
 
 
+class _PicardOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_picard", C.c_int), ("max_krylov", C.c_int),
+                ("krylov_rtol", C.c_double), ("krylov_blocks", C.c_int), ("krylov_threads", C.c_int),
+                ("timing", C.c_int)]
+
+
+class _PicardStats(C.Structure):
+    _fields_ = [("status", C.c_int), ("picard_iters", C.c_int), ("krylov_iters", C.c_int),
+                ("update", C.c_double), ("res0", C.c_double), ("res", C.c_double),
+                ("update_hist", C.c_double * HIST), ("krylov_hist", C.c_int * HIST),
+                ("t_matrix_ms", C.c_double), ("t_krylov_ms", C.c_double), ("krylov_kernels", C.c_int)]
+
+
 class _Shape(C.Structure):
     _fields_ = [("action_runs", C.c_int), ("action_pipe", C.c_int), ("krylov_blocks", C.c_int),
                 ("krylov_threads", C.c_int), ("krylov_kernel", C.c_int)]
@@ -121,6 +134,11 @@ EXPORTS = {
     "egfem_set_shape": (C.c_int, [C.c_void_p, C.POINTER(_Shape)]),
     "egfem_autotune": (C.c_int, [C.c_void_p, C.POINTER(_Problem), C.c_int, C.POINTER(_Shape),
                                  C.POINTER(C.c_double), C.c_void_p]),
+    "egfem_picard_opts_default": (None, [C.POINTER(_PicardOpts)]),
+    "egfem_picard": (C.c_int, [C.c_void_p, C.POINTER(_Problem), C.c_void_p, C.POINTER(_PicardOpts),
+                               C.POINTER(_PicardStats), C.c_void_p]),
+    "egfem_solve_cg": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int,
+                                 C.POINTER(C.c_int), C.POINTER(C.c_double), C.c_void_p]),
     "egfem_last_error": (C.c_char_p, []),
     "egfem_version": (C.c_char_p, []),
 }
@@ -205,6 +223,48 @@ class NewtonOptions:
         return _Opts(self.tol, self.max_newton, self.max_krylov, self.krylov_rtol, self.forcing,
                      self.eta_max, self.max_backtracks, self.krylov_blocks, self.krylov_threads,
                      self.timing)
+
+
+@dataclass
+class PicardOptions:
+    """Mirror of egfem_picard_opts (defaults equal egfem_picard_opts_default)."""
+    tol: float = 1e-12
+    max_picard: int = 200
+    max_krylov: int = 20000
+    krylov_rtol: float = 1e-4
+    krylov_blocks: int = 0
+    krylov_threads: int = 0
+    timing: int = 0
+
+    def c(self) -> _PicardOpts:
+        return _PicardOpts(self.tol, self.max_picard, self.max_krylov, self.krylov_rtol, self.krylov_blocks,
+                           self.krylov_threads, self.timing)
+
+
+@dataclass
+class PicardStats:
+    status: int
+    picard_iters: int
+    krylov_iters: int
+    update: float
+    res0: float
+    res: float
+    update_hist: List[float]
+    krylov_hist: List[int]
+    t_matrix_ms: float
+    t_krylov_ms: float
+    krylov_kernels: int
+
+    @property
+    def status_name(self) -> str:
+        return STATUS_NAMES.get(self.status, str(self.status))
+
+    @classmethod
+    def from_c(cls, s: _PicardStats) -> "PicardStats":
+        k = min(s.picard_iters, HIST)
+        return cls(s.status, s.picard_iters, s.krylov_iters, s.update, s.res0, s.res,
+                   list(s.update_hist[:k]), list(s.krylov_hist[:k]), s.t_matrix_ms, s.t_krylov_ms,
+                   s.krylov_kernels)
 
 
 @dataclass
@@ -454,6 +514,33 @@ class Tensor:
             with open(cache, "w") as fh:
                 json.dump(db, fh, indent=1)
         return res
+
+    def picard(self, p: Problem, u: torch.Tensor, opts: Optional[PicardOptions] = None,
+               warn: bool = True) -> PicardStats:
+        """Picard iteration in place on u (Sec. 4, Example picard_iteration);
+        returns the statistics."""
+        o = (opts or PicardOptions()).c()
+        pc = p.c()
+        st = _PicardStats()
+        rc = load_library().egfem_picard(self.handle, C.byref(pc), _dptr(u, n=self.n), C.byref(o),
+                                         C.byref(st), _stream())
+        _check(rc, allow_positive=True)
+        stats = PicardStats.from_c(st)
+        if rc != EGFEM_OK and warn:
+            warnings.warn(f"egfem_picard ended with status {stats.status_name}")
+        return stats
+
+    def solve_cg(self, jval, rhs, x=None, rtol=1e-12, max_iter=20000):
+        """Jacobi-preconditioned conjugate gradients for an SPD matrix in the
+        tensor's pattern; returns (x, status, iterations, relres)."""
+        x = torch.zeros_like(rhs) if x is None else x
+        it = C.c_int(0)
+        rr = C.c_double(0.0)
+        rc = load_library().egfem_solve_cg(self.handle, _dptr(jval, n=self.info.slots), _dptr(rhs, n=self.n),
+                                           _dptr(x, n=self.n), float(rtol), int(max_iter), C.byref(it),
+                                           C.byref(rr), _stream())
+        _check(rc, allow_positive=True)
+        return x, rc, it.value, rr.value
 
     def solve(self, jval, rhs, x=None, transpose=False, rtol=1e-12, max_iter=20000):
         x = torch.zeros_like(rhs) if x is None else x

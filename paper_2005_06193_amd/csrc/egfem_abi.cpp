@@ -421,6 +421,116 @@ int egfem_solve(egfem_tensor_t T, const double* jval, int transpose, const doubl
   return kr.status;
 }
 
+int egfem_solve_cg(egfem_tensor_t T, const double* jval, const double* rhs, double* x, double rtol,
+                   int max_iter, int* iters, double* relres, void* stream) {
+  if (!T || !jval || !rhs || !x) return fail(EGFEM_ERR_ARG, "null argument");
+  if (!(rtol > 0.0) || max_iter < 1) return fail(EGFEM_ERR_ARG, "rtol > 0 and max_iter >= 1 required");
+  if (x == rhs) return fail(EGFEM_ERR_ARG, "x must not alias rhs");
+  int rc = ensure_workspace(T);
+  if (rc != EGFEM_OK) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_diag_inv, dim3((unsigned)((T->n + 255) / 256)), dim3(256), 0, st, T->n, T->diag,
+                     jval, T->ws.dinv);
+  EGFEM_HIP_CHECK(hipGetLastError());
+  KrylovResult kr;
+  rc = krylov_solve(KrylovMethod::kCG, T, jval, T->ws.dinv, rhs, 1.0, x, false, rtol, false, max_iter, 0, &kr,
+                    st, nullptr);
+  if (rc != EGFEM_OK) return rc;
+  if (iters) *iters = kr.iters;
+  if (relres) *relres = kr.relres;
+  return kr.status;
+}
+
+void egfem_picard_opts_default(egfem_picard_opts* o) {
+  if (!o) return;
+  o->tol = 1e-12;
+  o->max_picard = 200;
+  o->max_krylov = 20000;
+  o->krylov_rtol = 1e-4;
+  o->krylov_blocks = 0;
+  o->krylov_threads = 0;
+  o->timing = 0;
+}
+
+int egfem_picard(egfem_tensor_t T, const egfem_problem* p, double* u, const egfem_picard_opts* o,
+                 egfem_picard_stats* s, void* stream) {
+  if (!T || !p || !u) return fail(EGFEM_ERR_ARG, "null argument");
+  egfem_picard_opts opts;
+  egfem_picard_opts_default(&opts);
+  if (o) opts = *o;
+  if (!(opts.tol >= 0.0) || opts.max_picard < 0 || opts.max_krylov < 1 || !(opts.krylov_rtol > 0.0) ||
+      opts.krylov_blocks < 0 ||
+      (opts.krylov_threads != 0 && opts.krylov_threads != 256 && opts.krylov_threads != 512 &&
+       opts.krylov_threads != 1024))
+    return fail(EGFEM_ERR_ARG, "invalid Picard options");
+  int rc = ensure_workspace(T);
+  if (rc != EGFEM_OK) return rc;
+  Workspace& W = T->ws;
+  hipStream_t st = (hipStream_t)stream;
+  const ProblemView pv = view(p);
+  egfem_picard_stats stats;
+  std::memset(&stats, 0, sizeof(stats));
+  LaunchTimer tm;
+  if ((rc = tm.init(opts.timing != 0, st)) != EGFEM_OK) return rc;
+  int n_dummy = 0;
+#define EGFEM_TRY(x)                    \
+  do {                                  \
+    if ((rc = (x)) != EGFEM_OK) return rc; \
+  } while (0)
+  // u_D = 0; right-hand side d with zero Dirichlet rows
+  EGFEM_HIP_CHECK(launch_mask_zero(u, p->dirichlet, T->n, st));
+  if (p->load) EGFEM_HIP_CHECK(launch_copy(W.rhs, p->load, T->n, st));
+  else EGFEM_HIP_CHECK(launch_fill(W.rhs, 0.0, T->n, st));
+  EGFEM_HIP_CHECK(launch_mask_zero(W.rhs, p->dirichlet, T->n, st));
+  EGFEM_HIP_CHECK(launch_action_problem(T, pv, u, nullptr, 0.0, nullptr, W.F, W.partial, st));
+  EGFEM_TRY(read_norm(T, st, &stats.res0));
+  int status = std::isfinite(stats.res0) ? EGFEM_NOT_CONVERGED : EGFEM_NONFINITE;
+  std::vector<double> part(512);
+  int k = 0;
+  while (status == EGFEM_NOT_CONVERGED && k < opts.max_picard) {
+    // A(u^n) = [K] + T . a(u^n) with Dirichlet identity rows, and 1/diag
+    EGFEM_TRY(tm.start());
+    EGFEM_HIP_CHECK(launch_jacobian(T, u, nullptr, p->a0, p->a0_const, 1, nullptr, 0, p->add_stiffness,
+                                    p->dirichlet, W.jval, W.dinv, st));
+    EGFEM_TRY(tm.stop(&stats.t_matrix_ms, &n_dummy));
+    // u^{n+1}: CG warm started from u^n
+    EGFEM_HIP_CHECK(launch_copy(W.delta, u, T->n, st));
+    KrylovResult kr;
+    rc = krylov_solve(KrylovMethod::kCG, T, W.jval, W.dinv, W.rhs, 1.0, W.delta, false, opts.krylov_rtol,
+                      true, opts.max_krylov, opts.krylov_blocks, &kr, st, nullptr, tm.on, opts.krylov_threads);
+    if (rc != EGFEM_OK) return rc;
+    if (tm.on) stats.t_krylov_ms += kr.kernel_ms;
+    stats.krylov_iters += kr.iters;
+    stats.krylov_kernels |= kr.resident ? 1 : 2;
+    if (k < EGFEM_HIST) stats.krylov_hist[k] = kr.iters;
+    // relative update, then u <- u^{n+1}
+    hipError_t e = hipSuccess;
+    const int g = launch_diff_norms(T->n, W.delta, u, W.red, st, &e);
+    EGFEM_HIP_CHECK(e);
+    EGFEM_HIP_CHECK(hipMemcpyAsync(part.data(), W.red, 2 * g * sizeof(double), hipMemcpyDeviceToHost, st));
+    EGFEM_HIP_CHECK(launch_copy(u, W.delta, T->n, st));
+    EGFEM_HIP_CHECK(hipStreamSynchronize(st));
+    double dd = 0.0, xx = 0.0;
+    for (int q = 0; q < g; ++q) {
+      dd += part[2 * q];
+      xx += part[2 * q + 1];
+    }
+    const double upd = xx > 0.0 ? std::sqrt(dd / xx) : 0.0;
+    stats.update = upd;
+    if (k < EGFEM_HIST) stats.update_hist[k] = upd;
+    ++k;
+    if (kr.status == EGFEM_NONFINITE || !std::isfinite(upd)) { status = EGFEM_NONFINITE; break; }
+    if (upd <= opts.tol) status = EGFEM_OK;
+  }
+#undef EGFEM_TRY
+  EGFEM_HIP_CHECK(launch_action_problem(T, pv, u, nullptr, 0.0, nullptr, W.F, W.partial, st));
+  if ((rc = read_norm(T, st, &stats.res)) != EGFEM_OK) return rc;
+  stats.status = status;
+  stats.picard_iters = k;
+  if (s) *s = stats;
+  return status;
+}
+
 int egfem_adjoint(egfem_tensor_t T, const egfem_problem* p, const double* u, const double* ubar,
                   const egfem_newton_opts* o, double* lambda, double* grad_a0, int* krylov_iters,
                   double* relres, void* stream) {

@@ -625,6 +625,7 @@ struct KArgs {
   double *phat, *rh, *vh;                   // gathered by other workgroups (agent-coherent)
   double rtol;
   int max_iter;
+  int rel_r0;               // conjugate gradients: tolerance relative to ||r0|| instead of ||b||
 };
 
 struct KOut {
@@ -1043,6 +1044,184 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
   if (!o.abort && own) A.x[row] = x;
   o.iters = it;
   o.rnorm = rnorm;
+  return o;
+}
+
+// Jacobi-preconditioned conjugate gradients for a symmetric positive definite
+// J (the Picard matrix), in the single-reduction arrangement of Chronopoulos
+// and Gear: with u = D^-1 r and w = J u, the scalars gamma = (r, u) and
+// delta = (w, u) give beta = gamma / gamma_prev and
+// alpha = gamma / (delta - beta gamma / alpha_prev), and s = J p is kept by the
+// recurrence s = w + beta s.  Per iteration: one product (gathering D^-1 r),
+// one reduction of (r, u), (w, u), (r, r), one barrier after publishing D^-1 r.
+// Stops when ||r|| <= rtol ||r0|| (rel_r0) or rtol ||b||.
+// Register-resident form: one thread per row (rows fit the workgroup's
+// threads, at most K entries), matrix row, D^-1 and the row's x, r, p, s in
+// registers for the whole solve.
+template <int NT, int K>
+__device__ KOut team_pcg_reg(Team& tm, const KArgs& A, int rb, int re, double* sh, int* sh_abort) {
+  double red[kMaxRed];
+  KOut o{EGFEM_NOT_CONVERGED, 0, 0.0, 0.0, false};
+#define EGFEM_ZERO_RED() for (int q_ = 0; q_ < kMaxRed; ++q_) red[q_] = 0.0
+  const int i = rb + (int)threadIdx.x;
+  const bool own = i < re;
+  const int row = max(min(i, re - 1), 0);
+  int vi[K];
+  unsigned cc[K];
+  double aa[K];
+  const int beg = A.rowptr[row], end = A.rowptr[row + 1];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    vi[k] = min(beg + k, end - 1);
+    cc[k] = (unsigned)A.col[vi[k]] * 8u;
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const double w = A.val[vi[k]];
+    aa[k] = (own && beg + k < end) ? w : 0.0;
+  }
+  const double d = A.dinv[row];
+  const double b = A.rhs_scale * A.rhs[row];
+  double x = 0.0, r = b;
+  if (!A.x_zero) {
+    double g[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) g[k] = A.x[cc[k] / 8u];
+    x = A.x[row];
+    double acc = aa[0] * g[0];
+#pragma unroll
+    for (int k = 1; k < K; ++k) acc = fma(aa[k], g[k], acc);
+    r = b - acc;
+  }
+  double u = d * r, p = 0.0, s = 0.0;
+  EGFEM_ZERO_RED();
+  if (own) {
+    st_sh(A.phat + row, u);
+    red[0] = b * b;
+  }
+  if ((o.abort = team_reduce<NT>(tm, 0, red, 1, sh, sh_abort))) return o;
+  const double bnorm = sqrt(red[0]);
+  double ref = bnorm, gamma_prev = 0.0, alpha_prev = 0.0, rnorm = 0.0;
+  int slot = 1, it = 0;
+  while (true) {
+    const double w = row_dot<K>(cc, aa, A.phat);
+    EGFEM_ZERO_RED();
+    if (own) {
+      red[0] = r * u;
+      red[1] = w * u;
+      red[2] = r * r;
+    }
+    if ((o.abort = team_reduce<NT>(tm, slot, red, 3, sh, sh_abort))) break;
+    slot = slot % 6 + 1;
+    const double gamma = red[0], delta = red[1];
+    rnorm = sqrt(red[2]);
+    if (it == 0 && A.rel_r0) ref = rnorm;
+    if (!isfinite(rnorm) || !isfinite(gamma) || !isfinite(delta)) { o.status = EGFEM_NONFINITE; break; }
+    if (rnorm <= A.rtol * ref) { o.status = EGFEM_OK; break; }
+    if (it >= A.max_iter) { o.status = EGFEM_NOT_CONVERGED; break; }
+    const double beta = it == 0 ? 0.0 : gamma / gamma_prev;
+    const double den = it == 0 ? delta : delta - beta * gamma / alpha_prev;
+    if (!(den > 0.0) || !(gamma > 0.0)) { o.status = EGFEM_BREAKDOWN; break; }
+    const double alpha = gamma / den;
+    p = fma(beta, p, u);
+    s = fma(beta, s, w);
+    x = fma(alpha, p, x);
+    r = fma(-alpha, s, r);
+    u = d * r;
+    if (own) st_sh(A.phat + row, u);
+    gamma_prev = gamma;
+    alpha_prev = alpha;
+    ++it;
+    if ((o.abort = team_barrier(tm, sh_abort))) break;
+  }
+#undef EGFEM_ZERO_RED
+  if (!o.abort && own) A.x[row] = x;
+  o.iters = it;
+  o.rnorm = rnorm;
+  o.bnorm = ref;
+  return o;
+}
+
+// Streaming form of the same iteration (any number of rows per workgroup):
+// the row vectors r, p, s, x and w live in memory, the product reads J.
+template <int NT, int L, int K>
+__device__ KOut team_pcg(Team& tm, const KArgs& A, int rb, int re, double* sh, int* sh_abort) {
+  const int tid = threadIdx.x;
+  double red[kMaxRed];
+  KOut o{EGFEM_NOT_CONVERGED, 0, 0.0, 0.0, false};
+#define EGFEM_ZERO_RED() for (int q_ = 0; q_ < kMaxRed; ++q_) red[q_] = 0.0
+  EGFEM_ZERO_RED();
+  if (A.x_zero) {
+    for (int i = rb + tid; i < re; i += NT) {
+      const double bi = A.rhs_scale * A.rhs[i];
+      A.x[i] = 0.0;
+      A.r[i] = bi;
+      A.p[i] = 0.0;
+      A.s[i] = 0.0;
+      st_sh(A.phat + i, A.dinv[i] * bi);
+      red[0] = fma(bi, bi, red[0]);
+    }
+  } else {
+    spmv_rows<NT, L, K, false>(A, rb, re, A.x, nullptr, [&](int i) {
+      return make_double2(A.rhs[i], A.dinv[i]);
+    }, [&](int i, double Jx, double, double2 q) {
+      const double bi = A.rhs_scale * q.x;
+      const double ri = bi - Jx;
+      A.r[i] = ri;
+      A.p[i] = 0.0;
+      A.s[i] = 0.0;
+      st_sh(A.phat + i, q.y * ri);
+      red[0] = fma(bi, bi, red[0]);
+    });
+  }
+  if ((o.abort = team_reduce<NT>(tm, 0, red, 1, sh, sh_abort))) return o;
+  const double bnorm = sqrt(red[0]);
+  double ref = bnorm, gamma_prev = 0.0, alpha_prev = 0.0, rnorm = 0.0;
+  int slot = 1, it = 0;
+  while (true) {
+    EGFEM_ZERO_RED();
+    spmv_rows<NT, L, K, true>(A, rb, re, A.phat, nullptr, [&](int i) {
+      return make_double2(A.r[i], A.dinv[i]);
+    }, [&](int i, double wi, double, double2 q) {
+      const double ui = q.y * q.x;
+      A.v[i] = wi;
+      red[0] = fma(q.x, ui, red[0]);
+      red[1] = fma(wi, ui, red[1]);
+      red[2] = fma(q.x, q.x, red[2]);
+    });
+    if ((o.abort = team_reduce<NT>(tm, slot, red, 3, sh, sh_abort))) break;
+    slot = slot % 6 + 1;
+    const double gamma = red[0], delta = red[1];
+    rnorm = sqrt(red[2]);
+    if (it == 0 && A.rel_r0) ref = rnorm;
+    if (!isfinite(rnorm) || !isfinite(gamma) || !isfinite(delta)) { o.status = EGFEM_NONFINITE; break; }
+    if (rnorm <= A.rtol * ref) { o.status = EGFEM_OK; break; }
+    if (it >= A.max_iter) { o.status = EGFEM_NOT_CONVERGED; break; }
+    const double beta = it == 0 ? 0.0 : gamma / gamma_prev;
+    const double den = it == 0 ? delta : delta - beta * gamma / alpha_prev;
+    if (!(den > 0.0) || !(gamma > 0.0)) { o.status = EGFEM_BREAKDOWN; break; }
+    const double alpha = gamma / den;
+    for (int i = rb + tid; i < re; i += NT) {
+      const double di = A.dinv[i], ri = A.r[i], wi = A.v[i];
+      const double pi = fma(beta, A.p[i], di * ri);
+      const double si = fma(beta, A.s[i], wi);
+      const double xi = fma(alpha, pi, A.x[i]);
+      const double rn = fma(-alpha, si, ri);
+      A.p[i] = pi;
+      A.s[i] = si;
+      A.x[i] = xi;
+      A.r[i] = rn;
+      st_sh(A.phat + i, di * rn);
+    }
+    gamma_prev = gamma;
+    alpha_prev = alpha;
+    ++it;
+    if ((o.abort = team_barrier(tm, sh_abort))) break;
+  }
+#undef EGFEM_ZERO_RED
+  o.iters = it;
+  o.rnorm = rnorm;
+  o.bnorm = ref;
   return o;
 }
 

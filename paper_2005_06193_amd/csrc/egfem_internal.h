@@ -151,6 +151,10 @@ hipError_t launch_jacobian(const egfem_tensor_s* T, const double* u, const doubl
                            int dadu_2u, int addK, const uint8_t* dir, double* jval, double* dinv,
                            hipStream_t st);
 hipError_t launch_slot_mode2(const egfem_tensor_s* T, const double* u, double* q, hipStream_t st);
+// Partial sums of (x - u)^2 and x^2 into partial[2 g], partial[2 g + 1] for
+// the returned number of workgroups g (at most 256).
+int launch_diff_norms(int64_t n, const double* x, const double* u, double* partial, hipStream_t st,
+                      hipError_t* err);
 hipError_t launch_csr_matvec(const egfem_tensor_s* T, const double* vals, const double* x, double* y,
                              hipStream_t st);
 hipError_t launch_csr_matvec_perm(const egfem_tensor_s* T, const double* vals, const double* w,
@@ -174,11 +178,22 @@ struct KrylovResult {
   double kernel_ms = 0.0;   // launch duration of the persistent kernel (when timed)
   bool resident = false;    // the register-resident kernel ran
 };
-// Solves (rhs_scale * rhs) = A x with A = J (perm == null) or J^T (perm = tperm).
-int krylov_bicgstab(egfem_tensor_s* T, const double* jval, const double* dinv, const double* rhs,
-                    double rhs_scale, double* x, bool x_zero, double rtol, int max_iter,
-                    int blocks, KrylovResult* res, hipStream_t st, const int32_t* perm,
-                    bool timed = false, int threads = 0);
+enum class KrylovMethod { kBiCGStab, kCG };
+
+// Persistent Jacobi-preconditioned Krylov solve of (rhs_scale * rhs) = A x,
+// A = J (perm == null) or J^T (perm = tperm); conjugate gradients need an SPD
+// J.  Stops when ||r|| <= rtol ||b|| (or rtol ||r0|| with rel_r0).
+int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, const double* dinv,
+                 const double* rhs, double rhs_scale, double* x, bool x_zero, double rtol, bool rel_r0,
+                 int max_iter, int blocks, KrylovResult* res, hipStream_t st, const int32_t* perm,
+                 bool timed = false, int threads = 0);
+inline int krylov_bicgstab(egfem_tensor_s* T, const double* jval, const double* dinv, const double* rhs,
+                           double rhs_scale, double* x, bool x_zero, double rtol, int max_iter, int blocks,
+                           KrylovResult* res, hipStream_t st, const int32_t* perm, bool timed = false,
+                           int threads = 0) {
+  return krylov_solve(KrylovMethod::kBiCGStab, T, jval, dinv, rhs, rhs_scale, x, x_zero, rtol, false, max_iter,
+                      blocks, res, st, perm, timed, threads);
+}
 
 // Workspace
 int ensure_workspace(egfem_tensor_s* T);

@@ -120,6 +120,27 @@ __global__ __launch_bounds__(kBlockThreads) void k_jacobian(dev::TensorView T, c
                                                jval, dinv, L);
 }
 
+// Per-workgroup partial sums of (x_i - u_i)^2 and x_i^2 (grid-stride rows):
+// partial[2 g], partial[2 g + 1].
+__global__ __launch_bounds__(kBlockThreads) void k_diff_norms(int64_t n, const double* __restrict__ x,
+                                                              const double* __restrict__ u,
+                                                              double* __restrict__ partial) {
+  __shared__ double sh4[4];
+  double dd = 0.0, xx = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlockThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlockThreads) {
+    const double xi = x[i], di = xi - u[i];
+    dd = fma(di, di, dd);
+    xx = fma(xi, xi, xx);
+  }
+  const double a = block_sum256(dd, sh4);
+  const double b = block_sum256(xx, sh4);
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = a;
+    partial[2 * blockIdx.x + 1] = b;
+  }
+}
+
 // q_s = sum_{p in B(s)} v_p u_{j_p}  ((T ._2 u) in slot layout), thread per slot.
 __global__ __launch_bounds__(kBlockThreads) void k_slot_mode2(int64_t slots,
                                                               const int32_t* __restrict__ jptrB,
@@ -226,6 +247,14 @@ hipError_t launch_jacobian(const egfem_tensor_s* T, const double* u, const doubl
                      view_of(T), u, a, a0, a0c, use_problem_a, dadu, dadu_2u,
                      addK ? T->kval : nullptr, dir, jval, dinv);
   return hipGetLastError();
+}
+
+int launch_diff_norms(int64_t n, const double* x, const double* u, double* partial, hipStream_t st,
+                      hipError_t* err) {
+  const int G = (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlockThreads - 1) / kBlockThreads, 256));
+  hipLaunchKernelGGL(k_diff_norms, dim3(G), dim3(kBlockThreads), 0, st, n, x, u, partial);
+  *err = hipGetLastError();
+  return G;
 }
 
 hipError_t launch_slot_mode2(const egfem_tensor_s* T, const double* u, double* q, hipStream_t st) {

@@ -36,14 +36,8 @@ struct LaunchArgs {
   double* out;              // [0] status [1] iterations [2] relres [3] ||b||
 };
 
-// One team spanning the whole grid.
-template <int NT, int RS>
-__global__ __launch_bounds__(NT) void k_bicgstab(LaunchArgs P) {
-  __shared__ double sh[dev::kShWords<NT>];
-  __shared__ int sh_abort;
-  dev::Team tm{blockIdx.x, gridDim.x, P.ctrl, P.red, 0u};
-  const int rb = P.krow[blockIdx.x], re = P.krow[blockIdx.x + 1];
-  const dev::KOut o = dev::team_bicgstab<NT, row_L(RS), row_K(RS)>(tm, P.A, rb, re, sh, &sh_abort);
+// One team spanning the whole grid; the kernel writes its outcome to P.out.
+__device__ void write_out(const LaunchArgs& P, const dev::KOut& o) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     P.out[0] = o.abort ? (double)EGFEM_ERR_HIP : (double)o.status;
     P.out[1] = (double)o.iters;
@@ -52,116 +46,79 @@ __global__ __launch_bounds__(NT) void k_bicgstab(LaunchArgs P) {
   }
 }
 
-// Register-resident form: one thread per row, rows of at most K entries.
+#define EGFEM_TEAM_PROLOGUE()                                   \
+  __shared__ double sh[dev::kShWords<NT>];                      \
+  __shared__ int sh_abort;                                      \
+  dev::Team tm{blockIdx.x, gridDim.x, P.ctrl, P.red, 0u};       \
+  const int rb = P.krow[blockIdx.x], re = P.krow[blockIdx.x + 1]
+
+// Streaming BiCGStab (row shape code RS).
+template <int NT, int RS>
+__global__ __launch_bounds__(NT) void k_bicgstab(LaunchArgs P) {
+  EGFEM_TEAM_PROLOGUE();
+  write_out(P, dev::team_bicgstab<NT, row_L(RS), row_K(RS)>(tm, P.A, rb, re, sh, &sh_abort));
+}
+
+// Streaming conjugate gradients (row shape code RS).
+template <int NT, int RS>
+__global__ __launch_bounds__(NT) void k_pcg(LaunchArgs P) {
+  EGFEM_TEAM_PROLOGUE();
+  write_out(P, dev::team_pcg<NT, row_L(RS), row_K(RS)>(tm, P.A, rb, re, sh, &sh_abort));
+}
+
+// Register-resident forms: one thread per row, rows of at most K entries.
 constexpr int kResidentRow = 8;
 
 template <int NT, int K>
 __global__ __launch_bounds__(NT) void k_bicgstab_reg(LaunchArgs P) {
-  __shared__ double sh[dev::kShWords<NT>];
-  __shared__ int sh_abort;
-  dev::Team tm{blockIdx.x, gridDim.x, P.ctrl, P.red, 0u};
-  const int rb = P.krow[blockIdx.x], re = P.krow[blockIdx.x + 1];
-  const dev::KOut o = dev::team_bicgstab_reg<NT, K>(tm, P.A, rb, re, sh, &sh_abort);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    P.out[0] = o.abort ? (double)EGFEM_ERR_HIP : (double)o.status;
-    P.out[1] = (double)o.iters;
-    P.out[2] = o.bnorm > 0.0 ? o.rnorm / o.bnorm : 0.0;
-    P.out[3] = o.bnorm;
-  }
+  EGFEM_TEAM_PROLOGUE();
+  write_out(P, dev::team_bicgstab_reg<NT, K>(tm, P.A, rb, re, sh, &sh_abort));
 }
 
 template <int NT, int K>
-hipError_t launch_reg_NK(const LaunchArgs& A, unsigned G, hipStream_t st) {
-  void* args[] = {(void*)&A};
-  return hipLaunchCooperativeKernel((const void*)k_bicgstab_reg<NT, K>, dim3(G), dim3(NT), args, 0, st);
+__global__ __launch_bounds__(NT) void k_pcg_reg(LaunchArgs P) {
+  EGFEM_TEAM_PROLOGUE();
+  write_out(P, dev::team_pcg_reg<NT, K>(tm, P.A, rb, re, sh, &sh_abort));
 }
+#undef EGFEM_TEAM_PROLOGUE
 
-template <int NT, int K>
-int max_coresident_reg_NK() {
-  int dev = 0, per_cu = 0, cus = 0;
-  hipGetDevice(&dev);
-  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_bicgstab_reg<NT, K>, NT, 0) !=
-      hipSuccess)
-    return 0;
-  return per_cu * cus;
-}
-
+// Kernel for (method, resident, row shape) at workgroup size NT.
 template <int NT, int RS>
-hipError_t launch_NL(const LaunchArgs& A, unsigned G, hipStream_t st) {
-  void* args[] = {(void*)&A};
-  return hipLaunchCooperativeKernel((const void*)k_bicgstab<NT, RS>, dim3(G), dim3(NT), args, 0, st);
+const void* streaming_kernel(KrylovMethod m) {
+  return m == KrylovMethod::kCG ? (const void*)k_pcg<NT, RS> : (const void*)k_bicgstab<NT, RS>;
 }
 
-template <int NT, int RS>
-int max_coresident_NL() {
-  int dev = 0, per_cu = 0, cus = 0;
-  hipGetDevice(&dev);
-  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_bicgstab<NT, RS>, NT, 0) !=
-      hipSuccess)
-    return 0;
-  return per_cu * cus;
-}
-
-// Dispatch over the compiled (threads, row shape) pairs.
 template <int NT>
-struct ShapeNT {
-  static hipError_t launch(int rs, const LaunchArgs& A, unsigned G, hipStream_t st) {
-    switch (rs) {
-      case 0: return launch_NL<NT, 0>(A, G, st);
-      case 1: return launch_NL<NT, 1>(A, G, st);
-      case 2: return launch_NL<NT, 2>(A, G, st);
-      case 3: return launch_NL<NT, 3>(A, G, st);
-      case 4: return launch_NL<NT, 4>(A, G, st);
-      case 5: return launch_NL<NT, 5>(A, G, st);
-      case 6: return launch_NL<NT, 6>(A, G, st);
-      case 7: return launch_NL<NT, 7>(A, G, st);
-      default: return launch_NL<NT, 8>(A, G, st);
-    }
+const void* kernel_NT(KrylovMethod m, bool resident, int rs) {
+  if (resident)
+    return m == KrylovMethod::kCG ? (const void*)k_pcg_reg<NT, kResidentRow>
+                                  : (const void*)k_bicgstab_reg<NT, kResidentRow>;
+  switch (rs) {
+    case 0: return streaming_kernel<NT, 0>(m);
+    case 1: return streaming_kernel<NT, 1>(m);
+    case 2: return streaming_kernel<NT, 2>(m);
+    case 3: return streaming_kernel<NT, 3>(m);
+    case 4: return streaming_kernel<NT, 4>(m);
+    case 5: return streaming_kernel<NT, 5>(m);
+    case 6: return streaming_kernel<NT, 6>(m);
+    case 7: return streaming_kernel<NT, 7>(m);
+    default: return streaming_kernel<NT, 8>(m);
   }
-  // register-resident form: rows of at most kResidentRow entries
-  static hipError_t launch_reg(const LaunchArgs& A, unsigned G, hipStream_t st) {
-    return launch_reg_NK<NT, kResidentRow>(A, G, st);
-  }
-  static int cap_reg() { return max_coresident_reg_NK<NT, kResidentRow>(); }
-  static int cap(int rs) {
-    switch (rs) {
-      case 0: return max_coresident_NL<NT, 0>();
-      case 1: return max_coresident_NL<NT, 1>();
-      case 2: return max_coresident_NL<NT, 2>();
-      case 3: return max_coresident_NL<NT, 3>();
-      case 4: return max_coresident_NL<NT, 4>();
-      case 5: return max_coresident_NL<NT, 5>();
-      case 6: return max_coresident_NL<NT, 6>();
-      case 7: return max_coresident_NL<NT, 7>();
-      default: return max_coresident_NL<NT, 8>();
-    }
-  }
-};
-
-hipError_t launch_shape(int NT, int L, const LaunchArgs& A, unsigned G, hipStream_t st) {
-  if (NT == 256) return ShapeNT<256>::launch(L, A, G, st);
-  if (NT == 512) return ShapeNT<512>::launch(L, A, G, st);
-  return ShapeNT<1024>::launch(L, A, G, st);
 }
 
-int cap_shape(int NT, int L) {
-  if (NT == 256) return ShapeNT<256>::cap(L);
-  if (NT == 512) return ShapeNT<512>::cap(L);
-  return ShapeNT<1024>::cap(L);
+const void* kernel_for(int NT, KrylovMethod m, bool resident, int rs) {
+  if (NT == 256) return kernel_NT<256>(m, resident, rs);
+  if (NT == 512) return kernel_NT<512>(m, resident, rs);
+  return kernel_NT<1024>(m, resident, rs);
 }
 
-hipError_t launch_shape_reg(int NT, const LaunchArgs& A, unsigned G, hipStream_t st) {
-  if (NT == 256) return ShapeNT<256>::launch_reg(A, G, st);
-  if (NT == 512) return ShapeNT<512>::launch_reg(A, G, st);
-  return ShapeNT<1024>::launch_reg(A, G, st);
-}
-
-int cap_shape_reg(int NT) {
-  if (NT == 256) return ShapeNT<256>::cap_reg();
-  if (NT == 512) return ShapeNT<512>::cap_reg();
-  return ShapeNT<1024>::cap_reg();
+// Workgroups of this kernel that can be resident at once on the device.
+int coresident(const void* kern, int NT) {
+  int dev = 0, per_cu = 0, cus = 0;
+  hipGetDevice(&dev);
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, 0) != hipSuccess) return 0;
+  return per_cu * cus;
 }
 
 }  // namespace
@@ -180,16 +137,17 @@ static void make_partition(const egfem_tensor_s* T, int G, std::vector<int32_t>&
   kr[G] = (int32_t)N;
 }
 
-int krylov_bicgstab(egfem_tensor_s* T, const double* jval, const double* dinv, const double* rhs,
-                    double rhs_scale, double* x, bool x_zero, double rtol, int max_iter, int blocks,
-                    KrylovResult* res, hipStream_t st, const int32_t* perm, bool timed, int threads) {
+int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, const double* dinv,
+                 const double* rhs, double rhs_scale, double* x, bool x_zero, double rtol, bool rel_r0,
+                 int max_iter, int blocks, KrylovResult* res, hipStream_t st, const int32_t* perm, bool timed,
+                 int threads) {
   int rc = ensure_workspace(T);
   if (rc != EGFEM_OK) return rc;
   Workspace& W = T->ws;
   if (threads == 0) threads = T->tuned_krylov_threads;
   if (blocks <= 0) blocks = T->tuned_krylov_blocks;
   const int NT = (threads == 256 || threads == 512 || threads == 1024) ? threads : kKrylovThreads;
-  const int cap = cap_shape(NT, T->krylov_rs);
+  const int cap = coresident(kernel_for(NT, method, false, T->krylov_rs), NT);
   if (cap <= 0) return fail(EGFEM_ERR_HIP, "Krylov kernel cannot be resident");
   int G = blocks;
   if (G <= 0) {
@@ -236,6 +194,7 @@ int krylov_bicgstab(egfem_tensor_s* T, const double* jval, const double* dinv, c
   A.vh = W.vh;
   A.rtol = rtol;
   A.max_iter = max_iter;
+  A.rel_r0 = rel_r0 ? 1 : 0;
   P.krow = W.krow;
   P.ctrl = W.ctrl;
   P.red = W.red;
@@ -248,12 +207,13 @@ int krylov_bicgstab(egfem_tensor_s* T, const double* jval, const double* dinv, c
   }
   // register-resident form when every workgroup's rows fit its threads, rows
   // hold at most kResidentRow entries, and the grid is co-resident for it
-  const int L = T->krylov_lanes;
   // (columns are held as 32-bit byte offsets: n < 2^28)
+  const void* kreg = kernel_for(NT, method, true, 0);
   const bool resident = T->krylov_kernel == 0 && T->max_row_slots <= kResidentRow &&
-                        W.krow_maxrows <= NT && T->n < (int64_t(1) << 28) && G <= cap_shape_reg(NT);
-  const hipError_t e = resident ? launch_shape_reg(NT, P, (unsigned)G, st)
-                                : launch_shape(NT, T->krylov_rs, P, (unsigned)G, st);
+                        W.krow_maxrows <= NT && T->n < (int64_t(1) << 28) && G <= coresident(kreg, NT);
+  const void* kern = resident ? kreg : kernel_for(NT, method, false, T->krylov_rs);
+  void* args[] = {(void*)&P};
+  const hipError_t e = hipLaunchCooperativeKernel(kern, dim3((unsigned)G), dim3((unsigned)NT), args, 0, st);
   if (e != hipSuccess) {
     if (ev0) hipEventDestroy(ev0);
     if (ev1) hipEventDestroy(ev1);

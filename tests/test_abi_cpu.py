@@ -36,6 +36,11 @@ def test_version_and_defaults():
     eg.load_library().egfem_newton_opts_default(C.byref(o))
     assert o.tol == 1e-10 and o.max_newton == 50 and o.max_backtracks == 10
     assert o.forcing == 0 and o.krylov_rtol == 1e-12
+    q = B._PicardOpts()
+    eg.load_library().egfem_picard_opts_default(C.byref(q))
+    d = eg.PicardOptions()
+    assert (q.tol, q.max_picard, q.max_krylov, q.krylov_rtol) == (d.tol, d.max_picard, d.max_krylov,
+                                                                   d.krylov_rtol)
 
 
 def _build(coords, cells, dim=None, form=0, drop=1e-13):
@@ -86,6 +91,8 @@ def test_null_handles_rejected():
     assert lib.egfem_matvec(z, 0, z, 0, z, z, z) == B.EGFEM_ERR_ARG
     assert lib.egfem_newton(z, z, z, z, z, z) == B.EGFEM_ERR_ARG
     assert lib.egfem_solve(z, z, 0, z, z, 1e-10, 10, None, None, z) == B.EGFEM_ERR_ARG
+    assert lib.egfem_solve_cg(z, z, z, z, 1e-10, 10, None, None, z) == B.EGFEM_ERR_ARG
+    assert lib.egfem_picard(z, z, z, z, z, z) == B.EGFEM_ERR_ARG
     assert lib.egfem_tensor_info(z, None) == B.EGFEM_ERR_ARG
     assert lib.egfem_newton_batched(0, None, None, None, None, None, None) == B.EGFEM_ERR_ARG
     lib.egfem_tensor_destroy(z)
