@@ -257,7 +257,8 @@ typedef struct {
   int max_picard;            /* iteration cap (default 200) */
   int max_krylov;            /* CG iteration cap per solve (default 20000) */
   double krylov_rtol;        /* each solve: ||r|| <= krylov_rtol ||r_0|| with r_0 = d - A(u^n) u^n,
-                                i.e. relative to the nonlinear residual of u^n (default 1e-4) */
+                                i.e. relative to the nonlinear residual of u^n (default 0.1: inexact
+                                steps; the tolerance tightens with the residual) */
   int krylov_blocks;         /* persistent CG grid size, 0 = launch shape of the handle */
   int krylov_threads;        /* 256, 512, 1024, or 0 = launch shape of the handle */
   int timing;                /* nonzero: time the matrix emissions and solves with HIP events */

@@ -231,7 +231,7 @@ class PicardOptions:
     tol: float = 1e-12
     max_picard: int = 200
     max_krylov: int = 20000
-    krylov_rtol: float = 1e-4
+    krylov_rtol: float = 0.1
     krylov_blocks: int = 0
     krylov_threads: int = 0
     timing: int = 0

@@ -446,7 +446,7 @@ void egfem_picard_opts_default(egfem_picard_opts* o) {
   o->tol = 1e-12;
   o->max_picard = 200;
   o->max_krylov = 20000;
-  o->krylov_rtol = 1e-4;
+  o->krylov_rtol = 0.1;
   o->krylov_blocks = 0;
   o->krylov_threads = 0;
   o->timing = 0;

@@ -21,6 +21,10 @@
 //   C: omega = (t,s)/(t,t); x += alpha phat + omega D^-1 s; r = s - omega t;
 //      rho' = (rhat,s) - omega (rhat,t); beta = rho'/rho * alpha/omega;
 //      p = r + beta (p - omega v); phat = D^-1 p; rhat_r = D^-1 r -> (r,r)   barrier 3
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "egfem_device.h"
 
 namespace egfem {
@@ -112,12 +116,24 @@ const void* kernel_for(int NT, KrylovMethod m, bool resident, int rs) {
   return kernel_NT<1024>(m, resident, rs);
 }
 
-// Workgroups of this kernel that can be resident at once on the device.
+// Workgroups of this kernel that can be resident at once on the current
+// device (queried once per kernel, workgroup size and device).
 int coresident(const void* kern, int NT) {
-  int dev = 0, per_cu = 0, cus = 0;
+  static std::mutex mu;
+  static std::map<std::tuple<const void*, int, int>, int> cache;
+  int dev = 0;
   hipGetDevice(&dev);
+  const auto key = std::make_tuple(kern, NT, dev);
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    const auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+  }
+  int per_cu = 0, cus = 0;
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, 0) != hipSuccess) return 0;
+  std::lock_guard<std::mutex> lk(mu);
+  cache[key] = per_cu * cus;
   return per_cu * cus;
 }
 
