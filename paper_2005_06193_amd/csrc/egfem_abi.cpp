@@ -42,6 +42,7 @@ int ensure_workspace(egfem_tensor_s* T) {
   if (rc == EGFEM_OK) rc = dalloc(&W.red, (size_t)kRedSlots * 8 * kMaxKrylovBlocks);
   if (rc == EGFEM_OK) rc = dalloc(&W.ctrl, kCtrlWordsMax);
   if (rc == EGFEM_OK) rc = dalloc(&W.krow, (size_t)kMaxKrylovBlocks + 1);
+  if (rc == EGFEM_OK) rc = dalloc(&W.knbr, (size_t)kMaxKrylovBlocks * (kMaxNbrLists + 1));
   if (rc == EGFEM_OK) rc = dalloc(&W.kout, 4);
   if (rc == EGFEM_OK &&
       hipHostMalloc((void**)&W.host_partial, std::max<size_t>(T->row_blocks, 1) * sizeof(double), 0) != hipSuccess)
@@ -50,7 +51,8 @@ int ensure_workspace(egfem_tensor_s* T) {
     rc = fail(EGFEM_ERR_OOM, "hipHostMalloc failed");
   if (rc != EGFEM_OK) return rc;
   T->device_bytes += (int64_t)((15 * N + 3 * S + T->row_blocks + (size_t)kRedSlots * 8 * kMaxKrylovBlocks + 4) *
-                                   sizeof(double) + (kMaxKrylovBlocks + 1) * 4 + kCtrlWordsMax * 4);
+                                   sizeof(double) + (kMaxKrylovBlocks + 1) * 4 + kCtrlWordsMax * 4 +
+                               (int64_t)kMaxKrylovBlocks * (kMaxNbrLists + 1) * 4);
   W.krow_blocks = 0;
   W.ready = true;
   return EGFEM_OK;
@@ -64,6 +66,7 @@ static void free_workspace(Workspace& W) {
     if (v) hipFree(v);
   if (W.ctrl) hipFree(W.ctrl);
   if (W.krow) hipFree(W.krow);
+  if (W.knbr) hipFree(W.knbr);
   if (W.host_partial) hipHostFree(W.host_partial);
   if (W.host_kout) hipHostFree(W.host_kout);
   W = Workspace();

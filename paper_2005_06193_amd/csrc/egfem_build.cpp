@@ -344,6 +344,7 @@ extern "C" int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords
   T->krylov_rs = row_shape_for(max_row_slots, klanes);
   T->row_blocks = (int64_t)blk.size() - 1;
   T->h_rowptr = rowptr;
+  T->h_col = col;
   hipGetDevice(&T->device);
   int64_t bytes = 0;
   int rc = EGFEM_OK;

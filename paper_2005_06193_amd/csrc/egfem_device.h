@@ -19,7 +19,9 @@ constexpr int kGroups = 32;               // most arrival groups of a team barri
 // control block (unsigned words, one 128-byte line each): epoch, global
 // arrivals, abort flag, then one arrival counter per group.
 constexpr int kCtrlGen = 0, kCtrlAll = 32, kCtrlAbort = 64, kCtrlGroup = 96;
-constexpr int kCtrlWords = kCtrlGroup + 32 * kGroups;
+constexpr int kCtrlFlags = kCtrlGroup + 32 * kGroups;   // one publication flag per workgroup
+constexpr int kCtrlWords = kCtrlFlags + kMaxKrylovBlocks;
+constexpr int kMaxNbr = kMaxNbrLists;     // most neighbours of a point-to-point synchronisation
 static_assert(kCtrlWords <= kCtrlWordsMax, "barrier control block too small");
 constexpr int kMaxRed = 8;                // values per reduction
 
@@ -450,6 +452,8 @@ struct Team {
   unsigned* ctrl;     // kCtrlWords control words (zero before the launch)
   double* red;        // reduction slots [kRedSlots][kMaxRed][size]; 0-7 Krylov, 8-9 Newton
   unsigned epoch;     // barriers passed so far
+  const int* nbr = nullptr;   // [count, ranks...] of the workgroups whose rows this one gathers
+  unsigned flag_epoch = 0;    // point-to-point publications so far
 };
 
 // Arrival at and wait for team barrier number `epoch`, by one thread of the
@@ -511,6 +515,48 @@ __device__ inline bool team_barrier(Team& tm, int* sh_abort) {
   __syncthreads();
   const unsigned epoch = tm.epoch++;
   if (threadIdx.x == 0) *sh_abort = barrier_arrive_wait(tm, epoch);
+  __syncthreads();
+  return *sh_abort != 0;
+}
+
+// Point-to-point publication for a gather of rows owned by a few other
+// workgroups: every wave's stores are complete, the workgroup's flag
+// announces publication number `flag_epoch`, then the workgroup waits for the
+// same number on the flags of its neighbours (the workgroups owning columns of
+// its rows).  Only the read-after-write order of that gather is enforced; the
+// caller keeps a team-wide synchronisation between any read of the published
+// vector and its next overwrite.  Without a neighbour list (more than kMaxNbr
+// neighbours) this is the team barrier.  Returns true when the team aborted.
+__device__ inline bool team_neighbor_sync(Team& tm, int* sh_abort) {
+  if (!tm.nbr || tm.nbr[0] < 0) return team_barrier(tm, sh_abort);
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's stores are complete
+  __syncthreads();
+  const unsigned target = ++tm.flag_epoch;
+  unsigned* flags = tm.ctrl + kCtrlFlags;
+  if (threadIdx.x < (unsigned)kWave) {
+    const int lane = threadIdx.x;
+    if (lane == 0) __hip_atomic_store(flags + tm.rank, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int ab = 0;
+    if (lane < tm.nbr[0]) {
+      const unsigned* f = flags + tm.nbr[1 + lane];
+      unsigned spins = 0;
+      while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins >= kSpinCap) {
+          __hip_atomic_store(tm.ctrl + kCtrlAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ab = 1;
+          break;
+        }
+        if ((spins & 1023u) == 0 &&
+            __hip_atomic_load(tm.ctrl + kCtrlAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          ab = 1;
+          break;
+        }
+      }
+    }
+    ab = __any(ab) ? 1 : 0;
+    if (lane == 0) *sh_abort = ab;
+  }
   __syncthreads();
   return *sh_abort != 0;
 }
@@ -1038,7 +1084,9 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
       st_sh(A.phat + row, d * p);
       st_sh(A.rh + row, d * r);
     }
-    if ((o.abort = team_barrier(tm, sh_abort))) break;
+    // phase A gathers D^-1 p and D^-1 r of neighbouring rows only; the two
+    // team reductions before the next overwrite keep the reads ahead of it
+    if ((o.abort = team_neighbor_sync(tm, sh_abort))) break;
   }
 #undef EGFEM_ZERO_RED
   if (!o.abort && own) A.x[row] = x;
@@ -1132,7 +1180,9 @@ __device__ KOut team_pcg_reg(Team& tm, const KArgs& A, int rb, int re, double* s
     gamma_prev = gamma;
     alpha_prev = alpha;
     ++it;
-    if ((o.abort = team_barrier(tm, sh_abort))) break;
+    // the next product gathers D^-1 r of neighbouring rows; the reduction
+    // before the next overwrite keeps every read ahead of it
+    if ((o.abort = team_neighbor_sync(tm, sh_abort))) break;
   }
 #undef EGFEM_ZERO_RED
   if (!o.abort && own) A.x[row] = x;
@@ -1216,7 +1266,7 @@ __device__ KOut team_pcg(Team& tm, const KArgs& A, int rb, int re, double* sh, i
     gamma_prev = gamma;
     alpha_prev = alpha;
     ++it;
-    if ((o.abort = team_barrier(tm, sh_abort))) break;
+    if ((o.abort = team_neighbor_sync(tm, sh_abort))) break;
   }
 #undef EGFEM_ZERO_RED
   o.iters = it;

@@ -23,7 +23,8 @@ constexpr int kCapRows = 256;     // rows per block (one thread per row in the r
 constexpr int kKrylovThreads = 1024;
 constexpr int kMaxKrylovBlocks = 1024;
 constexpr int kRedSlots = 10;     // reduction slots in flight (>= 2 barriers apart)
-constexpr int kCtrlWordsMax = 2048;  // barrier control words (one 128-byte line per counter)
+constexpr int kCtrlWordsMax = 4096;  // barrier control words and publication flags
+constexpr int kMaxNbrLists = 8;      // neighbour workgroups kept per workgroup (more: team barrier)
 
 void set_error(const std::string& msg);
 int fail(int code, const std::string& msg);
@@ -56,6 +57,7 @@ struct Workspace {
   int32_t* krow = nullptr;      // Krylov row partition [kMaxKrylovBlocks + 1]
   int krow_blocks = 0;          // grid size the partition was made for
   int krow_maxrows = 0;         // most rows of one workgroup in that partition
+  int32_t* knbr = nullptr;      // per workgroup: neighbour count (-1: too many), ranks
   double* kout = nullptr;       // Krylov result [4] (device)
   double* host_partial = nullptr;  // pinned host mirror of partial sums
   double* host_kout = nullptr;     // pinned host mirror of the Krylov result
@@ -105,6 +107,7 @@ struct egfem_tensor_s {
   int32_t* blk_meta = nullptr;  // [row_blocks*8]: rows, slots, A range, B range of each block
   int64_t row_blocks = 0;
   std::vector<int32_t> h_rowptr;  // host copy (row partitions)
+  std::vector<int32_t> h_col;     // host copy (neighbour lists of a partition)
   int64_t device_bytes = 0;
   egfem::Workspace ws;
 };

@@ -21,6 +21,7 @@
 //   C: omega = (t,s)/(t,t); x += alpha phat + omega D^-1 s; r = s - omega t;
 //      rho' = (rhat,s) - omega (rhat,t); beta = rho'/rho * alpha/omega;
 //      p = r + beta (p - omega v); phat = D^-1 p; rhat_r = D^-1 r -> (r,r)   barrier 3
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -35,6 +36,7 @@ using dev::KArgs;
 struct LaunchArgs {
   KArgs A;
   const int32_t* krow;      // row partition [G+1]
+  const int32_t* nbr;       // [G][kMaxNbr + 1] neighbour lists (count, ranks), or null
   unsigned* ctrl;
   double* red;
   double* out;              // [0] status [1] iterations [2] relres [3] ||b||
@@ -54,6 +56,7 @@ __device__ void write_out(const LaunchArgs& P, const dev::KOut& o) {
   __shared__ double sh[dev::kShWords<NT>];                      \
   __shared__ int sh_abort;                                      \
   dev::Team tm{blockIdx.x, gridDim.x, P.ctrl, P.red, 0u};       \
+  if (P.nbr) tm.nbr = P.nbr + (size_t)blockIdx.x * (dev::kMaxNbr + 1); \
   const int rb = P.krow[blockIdx.x], re = P.krow[blockIdx.x + 1]
 
 // Streaming BiCGStab (row shape code RS).
@@ -180,6 +183,24 @@ int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, con
     int most = 0;
     for (int g = 0; g < G; ++g) most = std::max(most, kr[g + 1] - kr[g]);
     W.krow_maxrows = most;
+    // neighbour lists: the other workgroups owning a column of this one's rows
+    std::vector<int32_t> nb((size_t)G * (kMaxNbrLists + 1), 0);
+    for (int g = 0; g < G; ++g) {
+      int32_t* lst = nb.data() + (size_t)g * (kMaxNbrLists + 1);
+      int cnt = 0;
+      for (int32_t s = T->h_rowptr[kr[g]]; s < T->h_rowptr[kr[g + 1]] && cnt >= 0; ++s) {
+        const int32_t c = T->h_col[s];
+        if (c >= kr[g] && c < kr[g + 1]) continue;
+        const int owner = (int)(std::upper_bound(kr.begin(), kr.end(), c) - kr.begin()) - 1;
+        bool seen = false;
+        for (int q = 0; q < cnt; ++q) seen = seen || lst[1 + q] == owner;
+        if (seen) continue;
+        if (cnt == kMaxNbrLists) cnt = -1;   // too many: the team barrier
+        else lst[1 + cnt++] = owner;
+      }
+      lst[0] = cnt;
+    }
+    EGFEM_HIP_CHECK(hipMemcpyAsync(W.knbr, nb.data(), nb.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
     EGFEM_HIP_CHECK(hipMemcpyAsync(W.krow, kr.data(), kr.size() * sizeof(int32_t),
                                    hipMemcpyHostToDevice, st));
     EGFEM_HIP_CHECK(hipStreamSynchronize(st));
@@ -212,6 +233,7 @@ int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, con
   A.max_iter = max_iter;
   A.rel_r0 = rel_r0 ? 1 : 0;
   P.krow = W.krow;
+  P.nbr = W.knbr;
   P.ctrl = W.ctrl;
   P.red = W.red;
   P.out = W.kout;
