@@ -496,8 +496,8 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch,
-                "limiter": ("three grid synchronisations per BiCGStab iteration; the register-resident "
-                            "kernel keeps J and the row vectors on chip"
+                "limiter": ("synchronisation: two team reductions and one neighbour synchronisation per "
+                            "BiCGStab iteration; the register-resident kernel keeps J and the row vectors on chip"
                             + (", measured HBM traffic %.2fx the algorithmic bytes"
                                % tr["krylov_bicgstab"]["ratio"] if traffic is not None else ""))
                 if dom == "krylov_bicgstab" else None}
