@@ -30,6 +30,10 @@ Finite Element Method", arXiv 2005.06193):
   approach, re-integrating the nonlinear term by quadrature every iteration.
 * Sec. 3.1 Case 1 / Example exact_egfem: W_h = P2 makes the reformulation
   exact (EGFEM(P2) == SGA for the u^2 nonlinearity).
+* Sec. 5.2, Burgers' equation: the convection tensor
+  N_ijk = int phi_k phi_j (d_1 + d_2) phi_i and the semi-implicit time step
+  (M + dt nu K) u^{n+1} = M u^n + dt (1/2 N:(u^n (x) u^n) + d^{n+1}), in the
+  tensor and the group (N^f (u . u)) formulations.
 
 Integrals use numerical quadrature on the reference simplex (collapsed Gauss-
 Legendre product rules generated here), assembled element by element.  Linear
@@ -55,6 +59,7 @@ import scipy.sparse.linalg as spla
 
 FORM_STIFF = 0
 FORM_MASS = 1
+FORM_CONV = 2
 
 
 # ----------------------------------------------------------------------------
@@ -178,14 +183,17 @@ def _merge_coo3(n, I, J, K, V, drop_rel=DROP_REL) -> Tensor3:
 
 
 def _degree_for(form: int, dim: int) -> int:
-    # stiffness integrand eta_k grad.grad is linear; mass integrand is cubic
-    return 1 if form == FORM_STIFF else 3
+    # stiffness integrand eta_k grad.grad is linear; convection integrand
+    # phi_k phi_j (grad phi_i . 1) quadratic; mass integrand cubic
+    return {FORM_STIFF: 1, FORM_MASS: 3, FORM_CONV: 2}[form]
 
 
 def assemble_tensor(coords, cells, form: int, degree: Optional[int] = None,
                     drop_rel: float = DROP_REL) -> Tensor3:
     """T_ijk = sum_e sum_q w_q |det B_e| psi_k(x_q) grad phi_j . grad phi_i   (stiffness)
-    or T_ijk = sum_e sum_q w_q |det B_e| psi_k phi_j phi_i (x_q)              (mass),
+    or T_ijk = sum_e sum_q w_q |det B_e| psi_k phi_j phi_i (x_q)              (mass)
+    or T_ijk = sum_e sum_q w_q |det B_e| phi_k phi_j (x_q) sum_d d_d phi_i    (convection,
+    the tensor N of the Burgers example, Sec. 5.2),
     with psi = phi = P1 nodal basis (eq. egfem_terms, Case 2 with W_h = V_h)."""
     n = coords.shape[0]
     dim = coords.shape[1]
@@ -201,6 +209,10 @@ def assemble_tensor(coords, cells, form: int, degree: Optional[int] = None,
     elif form == FORM_MASS:
         trip = np.einsum("q,qa,qb,qc->abc", wts, lam, lam, lam)
         Te = det[:, None, None, None] * trip[None]
+    elif form == FORM_CONV:
+        gsum = G.sum(axis=2)                                 # sum_d d_d phi_a, [E, d+1]
+        pair = np.einsum("q,qb,qc->bc", wts, lam, lam)       # int over reference of phi_b phi_c
+        Te = det[:, None, None, None] * gsum[:, :, None, None] * pair[None, None]
     else:
         raise ValueError("unknown form")
     nl = dim + 1
@@ -731,6 +743,63 @@ def tracking_objective(u: np.ndarray, u_d: np.ndarray) -> float:
 # ----------------------------------------------------------------------------
 # the stream sizes of the stored tensor, for byte accounting
 # ----------------------------------------------------------------------------
+# ----------------------------------------------------------------------------
+# viscous Burgers' equation, semi-implicit time stepping (Sec. 5.2)
+# ----------------------------------------------------------------------------
+@dataclass
+class BurgersSystem:
+    N: Tensor3                  # convection tensor N_ijk = int phi_k phi_j (d_1 + d_2) phi_i
+    Nf: sp.csr_matrix           # group matrix N^f_ik = int phi_k (d_1 + d_2) phi_i = sum_j N_ijk
+    M: sp.csr_matrix
+    K: sp.csr_matrix
+    S: sp.csr_matrix            # M + dt nu K, Dirichlet rows identity, Dirichlet columns 0
+    free: np.ndarray            # bool [N]
+    dt: float
+    nu: float
+
+
+def burgers_system(coords, cells, dirichlet, dt: float, nu: float) -> BurgersSystem:
+    """The offline part of the semi-implicit scheme: N (tensor formulation), N^f
+    (group formulation with W_h = V_h = P1, where interpolating u^2 gives
+    N^f (u . u) and N^f = N contracted with the constant 1 in j, by the partition
+    of unity), M, K and the constant system matrix M + dt nu K."""
+    N = assemble_tensor(coords, cells, FORM_CONV)
+    Nf = contract_mode2(N, np.ones(N.n))
+    M = assemble_mass(coords, cells)
+    K = assemble_stiffness(coords, cells)
+    free = np.asarray(dirichlet) == 0
+    S = (M + (dt * nu) * K).tocsr()
+    Df = sp.diags(free.astype(np.float64))
+    S = (Df @ S @ Df + sp.diags((~free).astype(np.float64))).tocsr()
+    return BurgersSystem(N, Nf, M, K, S, free, dt, nu)
+
+
+def burgers(sysm: BurgersSystem, u0: np.ndarray, source: Optional[np.ndarray], steps: int,
+            group: bool = False, history: bool = False):
+    """Semi-implicit Euler steps of Sec. 5.2,
+        M (u^{n+1} - u^n) + dt (nu K u^{n+1} - 1/2 C(u^n) - d^{n+1}) = 0,
+    i.e. (M + dt nu K) u^{n+1} = M u^n + dt (1/2 C(u^n) + d^{n+1}), with
+        C(u) = N : (u (x) u)       (tensor formulation, exact for P1 u), or
+        C(u) = N^f (u . u)         (group formulation: u^2 interpolated onto P1),
+    load d^{n+1} = M s^{n+1} for the nodal source values s^{n+1} = source[n]
+    (source None: no source), zero Dirichlet data.  Each linear system is solved
+    directly (one LU factorisation of the constant matrix).  Returns u^steps, or
+    the list [u^0, ..., u^steps] with history=True."""
+    u = np.array(u0, dtype=np.float64, copy=True)
+    u[~sysm.free] = 0.0
+    lu = spla.splu(sysm.S.tocsc())
+    out = [u.copy()] if history else None
+    for n in range(steps):
+        conv = sysm.Nf @ (u * u) if group else contract_uv(sysm.N, u, u)
+        x = u if source is None else u + sysm.dt * source[n]
+        rhs = sysm.M @ x + (0.5 * sysm.dt) * conv
+        rhs[~sysm.free] = 0.0
+        u = lu.solve(rhs)
+        if history:
+            out.append(u.copy())
+    return out if history else u
+
+
 def slot_count(T: Tensor3) -> int:
     """Number of distinct (i, j) pairs carrying at least one stored T_ijk."""
     return int(np.unique(T.i * T.n + T.j).size)

@@ -68,6 +68,11 @@ def _exact_tensor(coords, cells, form):
                 al = [0] * (d + 1)
                 al[c] += 1
                 val = gg * _int_monomial(al, vol, d)
+            elif form == O.FORM_CONV:
+                al = [0] * (d + 1)
+                al[b] += 1
+                al[c] += 1
+                val = sum(grads[a][r] for r in range(d)) * _int_monomial(al, vol, d)
             else:
                 al = [0] * (d + 1)
                 for x in (a, b, c):
@@ -189,7 +194,7 @@ def test_mass_matrix(dim):
 # third-order tensors
 # ----------------------------------------------------------------------------
 @pytest.mark.parametrize("dim", [1, 2, 3])
-@pytest.mark.parametrize("form", [O.FORM_STIFF, O.FORM_MASS])
+@pytest.mark.parametrize("form", [O.FORM_STIFF, O.FORM_MASS, O.FORM_CONV])
 def test_tensor_matches_exact_rational_integrals(dim, form):
     coords, cells = IRREGULAR[dim]
     T = _as_dict(O.assemble_tensor(coords, cells, form, drop_rel=0.0))
@@ -525,3 +530,87 @@ def test_picard_fixed_point_is_newton_solution(name):
     # linear convergence: the update ratios stay below one after the first step
     r = np.array(st.updates[1:-1]) / np.array(st.updates[:-2])
     assert np.all(r < 1.0)
+
+
+# ----------------------------------------------------------------------------
+# Burgers' equation (Sec. 5.2): convection tensor and semi-implicit steps
+# ----------------------------------------------------------------------------
+def test_convection_tensor_identities():
+    for dim, n in [(1, 8), (2, 6), (3, 3)]:
+        m = W.structured_mesh(dim, n)
+        T = O.assemble_tensor(m.coords, m.cells, O.FORM_CONV)
+        D = T.dense()
+        assert np.abs(D - D.transpose(0, 2, 1)).max() < 1e-16             # N_ijk = N_ikj
+        assert np.abs(D.sum(axis=0)).max() < 1e-14                          # sum_i grad phi_i = 0
+        # sum_jk N_ijk = int sum_d d_d phi_i = 0 unless phi_i touches the boundary
+        inner = m.dirichlet == 0
+        assert np.abs(D.sum(axis=(1, 2))[inner]).max() < 1e-14
+        # u . N:(u (x) u) = 1/3 int sum_d d_d (u^3) = 0 for u vanishing on the boundary
+        rng = np.random.default_rng(7)
+        u = rng.uniform(-1.0, 1.0, T.n) * inner
+        c = O.contract_uv(T, u, u)
+        assert abs(u @ c) < 1e-14 * np.abs(u).sum() * np.abs(c).max()
+        assert np.abs(c).max() > 1e-2 * np.abs(D).max()
+
+
+def test_group_matrix_closed_form():
+    """N^f_ik = int phi_k (d_1 + d_2) phi_i = sum_e (sum_d d_d lambda_a) |e| / (d+1)."""
+    for dim in (1, 2, 3):
+        coords, cells = IRREGULAR[dim]
+        sy = O.burgers_system(coords, cells, np.zeros(coords.shape[0], np.uint8), 0.1, 1.0)
+        n = coords.shape[0]
+        ex = np.zeros((n, n))
+        for cell in cells:
+            verts = [[Fraction(float(x)) for x in coords[v]] for v in cell]
+            grads, vol = _exact_element(verts)
+            for a in range(dim + 1):
+                for c in range(dim + 1):
+                    ex[cell[a], cell[c]] += float(sum(grads[a]) * vol / (dim + 1))
+        assert np.abs(sy.Nf.toarray() - ex).max() < 1e-14 * np.abs(ex).max()
+
+
+def test_burgers_linear_limit_eigen_decay():
+    """With a tiny initial amplitude the convection term is negligible and no
+    source acts, so a generalised eigenvector K v = lam M v (free rows) decays
+    by the factor 1 / (1 + dt nu lam) per semi-implicit step."""
+    m = W.mesh_2d(6)
+    dt, nu = 0.05, 0.7
+    sy = O.burgers_system(m.coords, m.cells, m.dirichlet, dt, nu)
+    f = sy.free
+    import scipy.linalg as sla
+    lam, V = sla.eigh(sy.K.toarray()[np.ix_(f, f)], sy.M.toarray()[np.ix_(f, f)])
+    for q in (0, 3, len(lam) - 1):
+        v = np.zeros(m.n_nodes)
+        v[f] = V[:, q]
+        eps = 1e-12
+        hist = O.burgers(sy, eps * v, None, 4, history=True)
+        for k, uk in enumerate(hist):
+            ref = eps * v / (1.0 + dt * nu * lam[q]) ** k
+            assert np.abs(uk - ref).max() <= 1e-8 * np.abs(ref).max()
+
+
+def test_burgers_manufactured_solution():
+    """The semi-implicit EGFEM scheme converges to the paper's manufactured
+    solution (nu = 1, T = 1, dt = 1e-2) at second order in h; a mistake in the
+    convection term (sign, the factor 1/2, the gradient on j) is visible."""
+    import dataclasses
+    errs = {}
+    for n in (16, 32):
+        b = W.burgers_2d(n)
+        sy = O.burgers_system(b.mesh.coords, b.mesh.cells, b.mesh.dirichlet, b.dt, b.nu)
+        for group in (False, True):
+            u = O.burgers(sy, b.u0, b.source, b.steps, group=group)
+            errs[n, group] = np.linalg.norm(u - b.u_final) / np.linalg.norm(b.u_final)
+        if n == 32:
+            def err(N):
+                u = O.burgers(dataclasses.replace(sy, N=N), b.u0, b.source, b.steps)
+                return np.linalg.norm(u - b.u_final) / np.linalg.norm(b.u_final)
+            T = sy.N
+            assert err(dataclasses.replace(T, v=-T.v)) > 10 * errs[32, False]
+            assert err(dataclasses.replace(T, v=2 * T.v)) > 10 * errs[32, False]
+            assert err(dataclasses.replace(T, i=T.j, j=T.i)) > 10 * errs[32, False]
+    for group in (False, True):
+        assert errs[32, group] < 3e-3
+        assert 3.0 < errs[16, group] / errs[32, group] < 5.0
+    # interpolating u^2 onto P1 changes the result at the discretisation-error level only
+    assert abs(errs[32, True] - errs[32, False]) < 0.05 * errs[32, False]

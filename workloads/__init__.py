@@ -23,6 +23,7 @@ workload adds 1000*m.
 from __future__ import annotations
 
 import itertools
+import math
 from dataclasses import dataclass, field
 from typing import List, Optional
 
@@ -152,6 +153,7 @@ def grid_smooth(values: np.ndarray, dim: int, n: int, sweeps: int) -> np.ndarray
 # ----------------------------------------------------------------------------
 FORM_STIFF = 0   # T_ijk = int psi_k grad phi_j . grad phi_i
 FORM_MASS = 1    # T_ijk = int phi_k phi_j phi_i
+FORM_CONV = 2    # T_ijk = int phi_k phi_j (sum_d d/dx_d phi_i)
 
 
 @dataclass
@@ -246,6 +248,75 @@ def diffusion_3d(n: int = 64, seed: int = SEED_BASE + 5) -> Workload:
 def direction(n_nodes: int, seed: int) -> np.ndarray:
     """Seeded U[-1,1] direction for finite-difference checks."""
     return np.random.default_rng(seed).uniform(-1.0, 1.0, size=n_nodes)
+
+
+# ----------------------------------------------------------------------------
+# viscous Burgers' equation with a manufactured solution (the time-dependent
+# benchmark of the paper's results section)
+# ----------------------------------------------------------------------------
+def burgers_exact(x1: np.ndarray, x2: np.ndarray, t: float) -> np.ndarray:
+    """u(x, t) = 10 x1 x2 (x1-1)(x2-1) [sin(2 x1 t) e^{-t/2} + cos(x2 t) e^{-t/4}
+    + sin(x1 x2 t) e^{-t}] on the unit square; zero on its boundary."""
+    P = 10.0 * x1 * x2 * (x1 - 1.0) * (x2 - 1.0)
+    S = (np.sin(2.0 * x1 * t) * np.exp(-0.5 * t) + np.cos(x2 * t) * np.exp(-0.25 * t)
+         + np.sin(x1 * x2 * t) * np.exp(-t))
+    return P * S
+
+
+def burgers_source(x1: np.ndarray, x2: np.ndarray, t: float, nu: float) -> np.ndarray:
+    """d = u_t - nu (u_11 + u_22) + u (u_1 + u_2) for u = burgers_exact, by the
+    product rule on u = P S (P the polynomial factor, S the bracket)."""
+    e1, e2, e3 = math.exp(-0.5 * t), math.exp(-0.25 * t), math.exp(-t)
+    s1, c1 = np.sin(2.0 * x1 * t), np.cos(2.0 * x1 * t)
+    s2, c2 = np.sin(x2 * t), np.cos(x2 * t)
+    s3, c3 = np.sin(x1 * x2 * t), np.cos(x1 * x2 * t)
+    S = s1 * e1 + c2 * e2 + s3 * e3
+    S_t = (2.0 * x1 * c1 - 0.5 * s1) * e1 + (-x2 * s2 - 0.25 * c2) * e2 + (x1 * x2 * c3 - s3) * e3
+    S_1 = 2.0 * t * c1 * e1 + x2 * t * c3 * e3
+    S_2 = -t * s2 * e2 + x1 * t * c3 * e3
+    S_11 = -4.0 * t * t * s1 * e1 - x2 * x2 * t * t * s3 * e3
+    S_22 = -t * t * c2 * e2 - x1 * x1 * t * t * s3 * e3
+    P = 10.0 * x1 * x2 * (x1 - 1.0) * (x2 - 1.0)
+    P_1 = 10.0 * x2 * (x2 - 1.0) * (2.0 * x1 - 1.0)
+    P_2 = 10.0 * x1 * (x1 - 1.0) * (2.0 * x2 - 1.0)
+    P_11 = 20.0 * x2 * (x2 - 1.0)
+    P_22 = 20.0 * x1 * (x1 - 1.0)
+    u = P * S
+    u_t = P * S_t
+    u_1 = P_1 * S + P * S_1
+    u_2 = P_2 * S + P * S_2
+    lap = P_11 * S + 2.0 * P_1 * S_1 + P * S_11 + P_22 * S + 2.0 * P_2 * S_2 + P * S_22
+    return u_t - nu * lap + u * (u_1 + u_2)
+
+
+@dataclass
+class BurgersWorkload:
+    name: str
+    mesh: Mesh
+    dt: float
+    nu: float
+    steps: int
+    u0: np.ndarray                  # nodal initial value [N]
+    source: np.ndarray              # nodal source values at t_1..t_steps [steps, N]
+    u_final: np.ndarray             # exact solution at t_steps, nodal [N]
+
+    @property
+    def n_nodes(self) -> int:
+        return self.mesh.n_nodes
+
+
+def burgers_2d(n: int = 256, dt: float = 1e-2, t_end: float = 1.0, nu: float = 1.0) -> BurgersWorkload:
+    """Viscous 2D Burgers' equation u_t - nu Lap u + u u_1 + u u_2 = d on the
+    unit square, zero Dirichlet data, source and initial value of the
+    manufactured solution burgers_exact; nu = 1, T = 1, dt = 1e-2 as in the
+    paper's experiment.  Deterministic (no random numbers)."""
+    mesh = mesh_2d(n)
+    steps = int(round(t_end / dt))
+    x1, x2 = mesh.coords[:, 0], mesh.coords[:, 1]
+    u0 = burgers_exact(x1, x2, 0.0)
+    src = np.stack([burgers_source(x1, x2, (m + 1) * dt, nu) for m in range(steps)])
+    return BurgersWorkload(f"burgers_2d_n{n}_dt{dt:g}", mesh, dt, nu, steps, u0, src,
+                           burgers_exact(x1, x2, steps * dt))
 
 
 WORKLOADS = {
