@@ -10,7 +10,9 @@
  *     (K_a : (u (x) a))_i = sum_jk T_ijk u_j a_k,
  *     T_ijk = int phi_k grad phi_j . grad phi_i      (EGFEM_FORM_STIFF)
  *     T_ijk = int phi_k phi_j phi_i                  (EGFEM_FORM_MASS, the
- *             trilinear mass form of Sec. 5.3, decomposition (a)).
+ *             trilinear mass form of Sec. 5.3, decomposition (a)),
+ *     T_ijk = int phi_k phi_j sum_d d_d phi_i        (EGFEM_FORM_CONV, the
+ *             convection tensor N of Burgers' equation, Sec. 5.2).
  *
  * The discrete problem solved is the u-reduced form of eq. (EGFEM_root):
  *
@@ -68,7 +70,8 @@ enum egfem_status {
 
 enum egfem_form {
   EGFEM_FORM_STIFF = 0,      /* T_ijk = int phi_k grad phi_j . grad phi_i */
-  EGFEM_FORM_MASS = 1        /* T_ijk = int phi_k phi_j phi_i (fully symmetric) */
+  EGFEM_FORM_MASS = 1,       /* T_ijk = int phi_k phi_j phi_i (fully symmetric) */
+  EGFEM_FORM_CONV = 2        /* T_ijk = int phi_k phi_j (sum_d d/dx_d phi_i) (T_ijk = T_ikj) */
 };
 
 /* ------------------------------------------------------------------------
@@ -82,7 +85,7 @@ enum egfem_form {
  *   dim      1, 2 or 3
  *   coords   host [n_nodes * dim], node-major (x0,y0,x1,y1,...)
  *   cells    host [n_cells * (dim+1)], 0-based node ids of each simplex
- *   form     EGFEM_FORM_STIFF or EGFEM_FORM_MASS
+ *   form     EGFEM_FORM_STIFF, EGFEM_FORM_MASS or EGFEM_FORM_CONV
  *   drop_rel after summing element contributions, an entry is dropped when
  *            |T_ijk| <= drop_rel * max_{j',k'} |T_ij'k'| (0: only exact zeros).
  *            1e-13 removes the entries that vanish in exact arithmetic.
@@ -103,7 +106,7 @@ void egfem_tensor_destroy(egfem_tensor_t T);
 typedef struct {
   int dim;
   int form;
-  int symmetric;             /* 1: T fully symmetric (mass), B-stream aliases A */
+  int symmetric;             /* 1: T_ijk = T_ikj (mass, convection), the B-stream aliases A */
   int64_t n_nodes;
   int64_t n_cells;
   int64_t nnz;               /* stored entries of T (A-stream length) */
@@ -298,6 +301,63 @@ int egfem_picard(egfem_tensor_t T, const egfem_problem* p, double* u, const egfe
  * A is not SPD) or EGFEM_NONFINITE.  Synchronises the stream. */
 int egfem_solve_cg(egfem_tensor_t T, const double* jval, const double* rhs, double* x, double rtol,
                    int max_iter, int* iters, double* relres, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Viscous Burgers' equation, semi-implicit time stepping (Sec. 5.2):
+ *     u_t - nu Lap u + u sum_d d_d u = d,   u = 0 on the Dirichlet nodes.
+ * With u sum_d d_d u = 1/2 sum_d d_d (u^2) and integration by parts, each step
+ * takes the nonlinear term at the old time level and solves
+ *     (M + dt nu K) u^{n+1} = M (u^n + dt s^{n+1}) + dt/2 C(u^n),
+ *     C(u) = N:(u (x) u)                        (group = 0, tensor formulation),
+ *     C(u) = N^f (u . u), N^f_ik = sum_j N_ijk  (group = 1, group formulation:
+ *            u^2 interpolated onto P1; N^f is int phi_k sum_d d_d phi_i),
+ * with N the EGFEM_FORM_CONV tensor of the handle, s^{n+1} the nodal source
+ * values at t_{n+1} (load M s^{n+1}), Dirichlet rows identity with zero right-
+ * hand side.  The matrix is constant and symmetric positive definite: it is
+ * emitted once, and every step is one tensor action (or one N^f product fused
+ * into the right-hand side) plus one persistent Jacobi-CG launch warm started
+ * from u^n.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  double dt;                 /* time step (default 1e-2) */
+  double nu;                 /* viscosity (default 1) */
+  int steps;                 /* number of steps (default 100) */
+  int group;                 /* 0: tensor formulation, 1: group formulation (default 0) */
+  double krylov_rtol;        /* each solve: ||r||_2 <= krylov_rtol ||rhs||_2 (default 1e-12) */
+  int max_krylov;            /* CG iteration cap per step (default 20000) */
+  int krylov_blocks;         /* persistent CG grid, 0 = launch shape of the handle */
+  int krylov_threads;        /* 256, 512, 1024, or 0 = launch shape of the handle */
+  int timing;                /* nonzero: time the right-hand sides and solves with HIP events */
+} egfem_burgers_opts;
+
+typedef struct {
+  int status;                /* worst step status: EGFEM_OK, NOT_CONVERGED, BREAKDOWN or NONFINITE */
+  int steps;                 /* steps taken (fewer than asked only after a non-finite step) */
+  int64_t krylov_iters;      /* total CG iterations */
+  int max_step_krylov;       /* most CG iterations of one step */
+  double max_relres;         /* largest final relative CG residual of a step */
+  int krylov_hist[EGFEM_HIST];    /* CG iterations of step n (n < EGFEM_HIST) */
+  double t_rhs_ms;           /* with timing: tensor actions and right-hand sides */
+  double t_krylov_ms;        /* with timing: CG launches */
+  int krylov_kernels;        /* CG kernels that ran: bit 0 register-resident, bit 1 streaming */
+} egfem_burgers_stats;
+
+/* Fill opts with the defaults above. */
+void egfem_burgers_opts_default(egfem_burgers_opts* o);
+
+/* egfem_burgers: advance u (device [n_nodes], u^0 in, u^steps out; Dirichlet
+ * entries are set to 0) by opts->steps semi-implicit steps.  T must be an
+ * EGFEM_FORM_CONV handle (its K and M are the stiffness and mass matrices).
+ *   dirichlet      device uint8 [n_nodes] or NULL (no Dirichlet nodes)
+ *   source         device; the nodal source values of step n (n = 0 .. steps-1,
+ *                  i.e. at t_{n+1}) start at source + n * source_stride; a
+ *                  stride of 0 reuses one vector; NULL = no source
+ *   source_stride  >= 0, in elements
+ * s (host, nullable) receives the statistics.  Returns the status, or a
+ * negative error (wrong form, bad option).  Uses the handle's solver workspace;
+ * synchronises the stream (one scalar readback per step). */
+int egfem_burgers(egfem_tensor_t T, const uint8_t* dirichlet, const double* source, int64_t source_stride,
+                  double* u, const egfem_burgers_opts* o, egfem_burgers_stats* s, void* stream);
 
 /* ------------------------------------------------------------------------
  * Launch shapes and the autotuner.

@@ -211,6 +211,9 @@ def assemble_tensor(coords, cells, form: int, degree: Optional[int] = None,
         Te = det[:, None, None, None] * trip[None]
     elif form == FORM_CONV:
         gsum = G.sum(axis=2)                                 # sum_d d_d phi_a, [E, d+1]
+        # a sum that vanishes in exact arithmetic (middle vertices of Kuhn
+        # tetrahedra) is zero, not rounding noise: the exact-zero drop rule
+        gsum[np.abs(gsum) <= 1e-12 * np.abs(G).sum(axis=2)] = 0.0
         pair = np.einsum("q,qb,qc->bc", wts, lam, lam)       # int over reference of phi_b phi_c
         Te = det[:, None, None, None] * gsum[:, :, None, None] * pair[None, None]
     else:

@@ -34,6 +34,7 @@ STATUS_NAMES = {0: "ok", 1: "not_converged", 2: "breakdown", 3: "nonfinite", 4: 
 
 FORM_STIFF = 0
 FORM_MASS = 1
+FORM_CONV = 2
 HIST = 64
 
 
@@ -75,6 +76,18 @@ class _PicardStats(C.Structure):
                 ("update", C.c_double), ("res0", C.c_double), ("res", C.c_double),
                 ("update_hist", C.c_double * HIST), ("krylov_hist", C.c_int * HIST),
                 ("t_matrix_ms", C.c_double), ("t_krylov_ms", C.c_double), ("krylov_kernels", C.c_int)]
+
+
+class _BurgersOpts(C.Structure):
+    _fields_ = [("dt", C.c_double), ("nu", C.c_double), ("steps", C.c_int), ("group", C.c_int),
+                ("krylov_rtol", C.c_double), ("max_krylov", C.c_int), ("krylov_blocks", C.c_int),
+                ("krylov_threads", C.c_int), ("timing", C.c_int)]
+
+
+class _BurgersStats(C.Structure):
+    _fields_ = [("status", C.c_int), ("steps", C.c_int), ("krylov_iters", C.c_int64),
+                ("max_step_krylov", C.c_int), ("max_relres", C.c_double), ("krylov_hist", C.c_int * HIST),
+                ("t_rhs_ms", C.c_double), ("t_krylov_ms", C.c_double), ("krylov_kernels", C.c_int)]
 
 
 class _Shape(C.Structure):
@@ -137,6 +150,9 @@ EXPORTS = {
     "egfem_picard_opts_default": (None, [C.POINTER(_PicardOpts)]),
     "egfem_picard": (C.c_int, [C.c_void_p, C.POINTER(_Problem), C.c_void_p, C.POINTER(_PicardOpts),
                                C.POINTER(_PicardStats), C.c_void_p]),
+    "egfem_burgers_opts_default": (None, [C.POINTER(_BurgersOpts)]),
+    "egfem_burgers": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                C.POINTER(_BurgersOpts), C.POINTER(_BurgersStats), C.c_void_p]),
     "egfem_solve_cg": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int,
                                  C.POINTER(C.c_int), C.POINTER(C.c_double), C.c_void_p]),
     "egfem_last_error": (C.c_char_p, []),
@@ -265,6 +281,47 @@ class PicardStats:
         return cls(s.status, s.picard_iters, s.krylov_iters, s.update, s.res0, s.res,
                    list(s.update_hist[:k]), list(s.krylov_hist[:k]), s.t_matrix_ms, s.t_krylov_ms,
                    s.krylov_kernels)
+
+
+@dataclass
+class BurgersOptions:
+    """Mirror of egfem_burgers_opts (defaults equal egfem_burgers_opts_default)."""
+    dt: float = 1e-2
+    nu: float = 1.0
+    steps: int = 100
+    group: int = 0
+    krylov_rtol: float = 1e-12
+    max_krylov: int = 20000
+    krylov_blocks: int = 0
+    krylov_threads: int = 0
+    timing: int = 0
+
+    def c(self) -> _BurgersOpts:
+        return _BurgersOpts(self.dt, self.nu, self.steps, self.group, self.krylov_rtol, self.max_krylov,
+                            self.krylov_blocks, self.krylov_threads, self.timing)
+
+
+@dataclass
+class BurgersStats:
+    status: int
+    steps: int
+    krylov_iters: int
+    max_step_krylov: int
+    max_relres: float
+    krylov_hist: List[int]
+    t_rhs_ms: float
+    t_krylov_ms: float
+    krylov_kernels: int
+
+    @property
+    def status_name(self) -> str:
+        return STATUS_NAMES.get(self.status, str(self.status))
+
+    @classmethod
+    def from_c(cls, s: _BurgersStats) -> "BurgersStats":
+        k = min(s.steps, HIST)
+        return cls(s.status, s.steps, s.krylov_iters, s.max_step_krylov, s.max_relres, list(s.krylov_hist[:k]),
+                   s.t_rhs_ms, s.t_krylov_ms, s.krylov_kernels)
 
 
 @dataclass
@@ -528,6 +585,33 @@ class Tensor:
         stats = PicardStats.from_c(st)
         if rc != EGFEM_OK and warn:
             warnings.warn(f"egfem_picard ended with status {stats.status_name}")
+        return stats
+
+    def burgers(self, u: torch.Tensor, dirichlet: Optional[torch.Tensor] = None,
+                source: Optional[torch.Tensor] = None, opts: Optional[BurgersOptions] = None,
+                warn: bool = True) -> BurgersStats:
+        """Semi-implicit Burgers steps in place on u (Sec. 5.2) with this
+        convection tensor.  source: None, one nodal vector [n] used at every
+        step, or [steps, n] (row m = nodal source values at t_{m+1})."""
+        o = opts or BurgersOptions()
+        stride = 0
+        sp_ = None
+        if source is not None:
+            if source.dim() == 1:
+                sp_ = _dptr(source, n=self.n)
+            else:
+                if source.dim() != 2 or source.shape[1] != self.n or source.shape[0] < o.steps:
+                    raise EgfemError(EGFEM_ERR_SHAPE, "source must be [n] or [>= steps, n]")
+                sp_ = _dptr(source)
+                stride = self.n
+        st = _BurgersStats()
+        oc = o.c()
+        rc = load_library().egfem_burgers(self.handle, _dptr(dirichlet, dtype=torch.uint8, n=self.n), sp_,
+                                          stride, _dptr(u, n=self.n), C.byref(oc), C.byref(st), _stream())
+        _check(rc, allow_positive=True)
+        stats = BurgersStats.from_c(st)
+        if rc != EGFEM_OK and warn:
+            warnings.warn(f"egfem_burgers ended with status {stats.status_name}")
         return stats
 
     def solve_cg(self, jval, rhs, x=None, rtol=1e-12, max_iter=20000):

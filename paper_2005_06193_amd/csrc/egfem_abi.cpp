@@ -534,6 +534,82 @@ int egfem_picard(egfem_tensor_t T, const egfem_problem* p, double* u, const egfe
   return status;
 }
 
+void egfem_burgers_opts_default(egfem_burgers_opts* o) {
+  if (!o) return;
+  o->dt = 1e-2;
+  o->nu = 1.0;
+  o->steps = 100;
+  o->group = 0;
+  o->krylov_rtol = 1e-12;
+  o->max_krylov = 20000;
+  o->krylov_blocks = 0;
+  o->krylov_threads = 0;
+  o->timing = 0;
+}
+
+int egfem_burgers(egfem_tensor_t T, const uint8_t* dirichlet, const double* source, int64_t source_stride,
+                  double* u, const egfem_burgers_opts* o, egfem_burgers_stats* s, void* stream) {
+  if (!T || !u) return fail(EGFEM_ERR_ARG, "null argument");
+  if (T->form != EGFEM_FORM_CONV) return fail(EGFEM_ERR_ARG, "Burgers steps need an EGFEM_FORM_CONV tensor");
+  egfem_burgers_opts opts;
+  egfem_burgers_opts_default(&opts);
+  if (o) opts = *o;
+  if (!(opts.dt > 0.0) || !std::isfinite(opts.dt) || !(opts.nu >= 0.0) || !std::isfinite(opts.nu) ||
+      opts.steps < 0 || opts.max_krylov < 1 || !(opts.krylov_rtol > 0.0) || opts.krylov_blocks < 0 ||
+      (opts.group != 0 && opts.group != 1) ||
+      (opts.krylov_threads != 0 && opts.krylov_threads != 256 && opts.krylov_threads != 512 &&
+       opts.krylov_threads != 1024))
+    return fail(EGFEM_ERR_ARG, "invalid Burgers options");
+  if (source && source_stride < 0) return fail(EGFEM_ERR_ARG, "source_stride must be >= 0");
+  int rc = ensure_workspace(T);
+  if (rc != EGFEM_OK) return rc;
+  Workspace& W = T->ws;
+  hipStream_t st = (hipStream_t)stream;
+  egfem_burgers_stats stats;
+  std::memset(&stats, 0, sizeof(stats));
+  LaunchTimer tm;
+  if ((rc = tm.init(opts.timing != 0, st)) != EGFEM_OK) return rc;
+  int n_dummy = 0;
+  // offline part of the run: M + dt nu K (Dirichlet identity rows, zero
+  // columns) and its inverse diagonal; N^f = N contracted with 1 in j
+  EGFEM_HIP_CHECK(launch_mk_combine(T, 1.0, opts.dt * opts.nu, dirichlet, W.jval, W.dinv, st));
+  if (opts.group) {
+    EGFEM_HIP_CHECK(launch_fill(W.utry, 1.0, T->n, st));
+    EGFEM_HIP_CHECK(launch_slot_mode2(T, W.utry, W.qslot, st));
+  }
+  EGFEM_HIP_CHECK(launch_mask_zero(u, dirichlet, T->n, st));
+  int status = EGFEM_OK;
+  int n = 0;
+  for (; n < opts.steps; ++n) {
+    const double* src = source ? source + (int64_t)n * source_stride : nullptr;
+    if ((rc = tm.start()) != EGFEM_OK) return rc;
+    if (!opts.group) EGFEM_HIP_CHECK(launch_action_raw(T, u, u, W.F, st));
+    EGFEM_HIP_CHECK(launch_burgers_rhs(T, opts.group != 0, u, src, opts.dt, opts.group ? W.qslot : W.F,
+                                       dirichlet, W.rhs, st));
+    if ((rc = tm.stop(&stats.t_rhs_ms, &n_dummy)) != EGFEM_OK) return rc;
+    KrylovResult kr;
+    rc = krylov_solve(KrylovMethod::kCG, T, W.jval, W.dinv, W.rhs, 1.0, u, false, opts.krylov_rtol, false,
+                      opts.max_krylov, opts.krylov_blocks, &kr, st, nullptr, tm.on, opts.krylov_threads);
+    if (rc != EGFEM_OK) return rc;
+    if (tm.on) stats.t_krylov_ms += kr.kernel_ms;
+    stats.krylov_iters += kr.iters;
+    stats.max_step_krylov = std::max(stats.max_step_krylov, kr.iters);
+    if (std::isfinite(kr.relres)) stats.max_relres = std::max(stats.max_relres, kr.relres);
+    stats.krylov_kernels |= kr.resident ? 1 : 2;
+    if (n < EGFEM_HIST) stats.krylov_hist[n] = kr.iters;
+    status = std::max(status, kr.status);
+    if (kr.status == EGFEM_NONFINITE) {
+      ++n;
+      break;
+    }
+  }
+  EGFEM_HIP_CHECK(hipStreamSynchronize(st));
+  stats.status = status;
+  stats.steps = n;
+  if (s) *s = stats;
+  return status;
+}
+
 int egfem_adjoint(egfem_tensor_t T, const egfem_problem* p, const double* u, const double* ubar,
                   const egfem_newton_opts* o, double* lambda, double* grad_a0, int* krylov_iters,
                   double* relres, void* stream) {

@@ -6,13 +6,15 @@
 //                         = sum_e K^e_ij / (d+1)       (grad phi constant, int_e phi_k = |e|/(d+1))
 //   mass form       T_ijk = sum_e int_e phi_i phi_j phi_k
 //                         = sum_e d! |e| alpha! / (d+3)!  (exact simplex monomial integral)
+//   convection form T_ijk = sum_e int_e phi_k phi_j sum_d d_d phi_i   (tensor N of Sec. 5.2)
+//                         = sum_e (sum_d d_d lambda_i) M^e_jk      (gradient constant per cell)
 // K_ij = sum_e |e| grad phi_j . grad phi_i,  M_ij = sum_e |e| (1 + delta_ij) / ((d+1)(d+2)).
 //
 // Layout (all indices int32, values float64):
 //   CSR pattern of the P1 adjacency including the diagonal: rowptr, col.
 //   A-stream: for slot s = (i,j) the fiber kptrA[s]..kptrA[s+1] of (k, T_ijk), k ascending.
 //   B-stream: for slot s = (i,k) the fiber jptrB[s]..jptrB[s+1] of (j, T_ijk), j ascending.
-//   For the fully symmetric mass tensor B == A and is not stored twice.
+//   For tensors with T_ijk = T_ikj (mass, convection) B == A and is not stored twice.
 //   tperm[s] = slot of (j,i); diag[i] = slot of (i,i).
 //   Row blocks: runs of rows that fit the LDS capacities of the tensor kernels.
 #include <algorithm>
@@ -102,7 +104,8 @@ extern "C" int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords
   if (!out) return fail(EGFEM_ERR_ARG, "out is null");
   *out = nullptr;
   if (dim < 1 || dim > 3) return fail(EGFEM_ERR_ARG, "dim must be 1, 2 or 3");
-  if (form != EGFEM_FORM_STIFF && form != EGFEM_FORM_MASS) return fail(EGFEM_ERR_ARG, "unknown form");
+  if (form != EGFEM_FORM_STIFF && form != EGFEM_FORM_MASS && form != EGFEM_FORM_CONV)
+    return fail(EGFEM_ERR_ARG, "unknown form");
   if (!coords || !cells) return fail(EGFEM_ERR_ARG, "coords/cells null");
   if (n_nodes <= 0 || n_cells <= 0) return fail(EGFEM_ERR_SHAPE, "empty mesh");
   if (n_nodes >= (int64_t(1) << 31) || n_cells >= (int64_t(1) << 31))
@@ -159,7 +162,8 @@ extern "C" int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords
   std::vector<double> acc;
   std::vector<unsigned char> present;
   std::vector<double> kacc, macc;
-  const bool sym = (form == EGFEM_FORM_MASS);
+  // B == A exactly when T_ijk = T_ikj
+  const bool sym = (form != EGFEM_FORM_STIFF);
   col.reserve((size_t)N * (dim == 3 ? 15 : 7));
 
   for (int64_t i = 0; i < N; ++i) {
@@ -187,6 +191,15 @@ extern "C" int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords
       while (c[a] != (int32_t)i) ++a;
       int loc[4];
       for (int b = 0; b < nl; ++b) loc[b] = lidx(c[b]);
+      // sum_d d_d lambda_a (convection form); a sum that vanishes in exact
+      // arithmetic (e.g. the middle vertices of a Kuhn tetrahedron) is set to
+      // zero instead of keeping its rounding noise
+      double gsum = 0.0, gabs = 0.0;
+      for (int r = 0; r < dim; ++r) {
+        gsum += g.G[a][r];
+        gabs += std::fabs(g.G[a][r]);
+      }
+      if (std::fabs(gsum) <= 1e-12 * gabs) gsum = 0.0;
       for (int b = 0; b < nl; ++b) {
         double gg = 0.0;
         for (int r = 0; r < dim; ++r) gg += g.G[a][r] * g.G[b][r];
@@ -195,11 +208,13 @@ extern "C" int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords
         macc[loc[b]] += g.vol * (a == b ? m2_diag : m2_off);
         for (int cc = 0; cc < nl; ++cc) {
           double val;
-          if (!sym) {
+          if (form == EGFEM_FORM_STIFF) {
             val = kab / (double)(dim + 1);
-          } else {
+          } else if (form == EGFEM_FORM_MASS) {
             const int same = (a == b) + (a == cc) + (b == cc);
             val = g.vol * (same == 3 ? m3_aaa : (same == 1 ? m3_aab : m3_abc));
+          } else {
+            val = gsum * g.vol * (b == cc ? m2_diag : m2_off);
           }
           const size_t idx = (size_t)loc[b] * nc + loc[cc];
           acc[idx] += val;

@@ -164,6 +164,14 @@ hipError_t launch_csr_matvec_perm(const egfem_tensor_s* T, const double* vals, c
                                   double* y, hipStream_t st);
 hipError_t launch_permute_slots(const egfem_tensor_s* T, const double* in, double* out,
                                 hipStream_t st);
+// vals = cm M + ck K in T's pattern with Dirichlet identity rows and zero
+// columns; dinv = 1 / diagonal.
+hipError_t launch_mk_combine(const egfem_tensor_s* T, double cm, double ck, const uint8_t* dir, double* vals,
+                             double* dinv, hipStream_t st);
+// Burgers right-hand side M (u + dt src) + dt/2 C; cvals = N^f in slot layout
+// (group) or the tensor action N:(u (x) u) [n] (tensor formulation).
+hipError_t launch_burgers_rhs(const egfem_tensor_s* T, bool group, const double* u, const double* src, double dt,
+                              const double* cvals, const uint8_t* dir, double* rhs, hipStream_t st);
 hipError_t launch_fill(double* x, double v, int64_t n, hipStream_t st);
 hipError_t launch_fill_u32(unsigned* x, unsigned v, int64_t n, hipStream_t st);
 hipError_t launch_mask_zero(double* x, const uint8_t* dir, int64_t n, hipStream_t st);

@@ -178,6 +178,68 @@ __global__ __launch_bounds__(kBlockThreads) void k_csr_matvec(int64_t n, const i
   if (row < n && lane == 0) y[row] = acc;
 }
 
+// Matrix of a linear time step in T's pattern, thread per row:
+//   vals_s = cm M_s + ck K_s, Dirichlet rows identity, Dirichlet columns 0,
+//   dinv_i = 1 / vals_(i,i).
+__global__ __launch_bounds__(kBlockThreads) void k_mk_combine(int64_t n, const int32_t* __restrict__ rowptr,
+                                                              const int32_t* __restrict__ col,
+                                                              const double* __restrict__ mval,
+                                                              const double* __restrict__ kval, double cm,
+                                                              double ck, const uint8_t* __restrict__ dir,
+                                                              double* __restrict__ vals,
+                                                              double* __restrict__ dinv) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const bool di = dir && dir[i];
+  double d = 1.0;
+  for (int s = rowptr[i]; s < rowptr[i + 1]; ++s) {
+    const int32_t j = col[s];
+    double v = fma(cm, mval[s], ck * kval[s]);
+    if (di) v = (j == i) ? 1.0 : 0.0;
+    else if (dir && dir[j]) v = 0.0;
+    vals[s] = v;
+    if (j == i) d = v;
+  }
+  dinv[i] = 1.0 / d;
+}
+
+// Right-hand side of a semi-implicit Burgers step (Sec. 5.2), L lanes per row:
+//   rhs_i = sum_{s in row i} M_s (u_j + dt src_j) + h C_i,   h = dt / 2,
+//   C_i = sum_s Nf_s u_j^2 (GROUP, Nf in slot layout) or conv_i (tensor action),
+//   0 on Dirichlet rows.
+template <int L, bool GROUP>
+__global__ __launch_bounds__(kBlockThreads) void k_burgers_rhs(int64_t n, const int32_t* __restrict__ rowptr,
+                                                               const int32_t* __restrict__ col,
+                                                               const double* __restrict__ mval,
+                                                               const double* __restrict__ cvals,
+                                                               const double* __restrict__ u,
+                                                               const double* __restrict__ src, double dt,
+                                                               double h, const uint8_t* __restrict__ dir,
+                                                               double* __restrict__ rhs) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t row = gid / L;
+  const int lane = (int)(gid % L);
+  double acc = 0.0, nacc = 0.0;
+  if (row < n) {
+    for (int s = rowptr[row] + lane; s < rowptr[row + 1]; s += L) {
+      const int32_t j = col[s];
+      const double uj = u[j];
+      const double xj = src ? fma(dt, src[j], uj) : uj;
+      acc = fma(mval[s], xj, acc);
+      if (GROUP) nacc = fma(cvals[s], uj * uj, nacc);
+    }
+  }
+#pragma unroll
+  for (int off = L / 2; off > 0; off >>= 1) {
+    acc += __shfl_xor(acc, off, L);
+    if (GROUP) nacc += __shfl_xor(nacc, off, L);
+  }
+  if (row < n && lane == 0) {
+    const double c = GROUP ? nacc : cvals[row];
+    rhs[row] = (dir && dir[row]) ? 0.0 : fma(h, c, acc);
+  }
+}
+
 __global__ void k_permute(int64_t slots, const int32_t* __restrict__ perm,
                           const double* __restrict__ in, double* __restrict__ out) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -290,6 +352,33 @@ hipError_t launch_csr_matvec(const egfem_tensor_s* T, const double* vals, const 
 hipError_t launch_csr_matvec_perm(const egfem_tensor_s* T, const double* vals, const double* w,
                                   double* y, hipStream_t st) {
   return matvec_any(T, vals, T->tperm, w, y, st);
+}
+
+hipError_t launch_mk_combine(const egfem_tensor_s* T, double cm, double ck, const uint8_t* dir, double* vals,
+                             double* dinv, hipStream_t st) {
+  hipLaunchKernelGGL(k_mk_combine, dim3(grid1d(T->n)), dim3(kBlockThreads), 0, st, T->n, T->rowptr, T->col,
+                     T->mval, T->kval, cm, ck, dir, vals, dinv);
+  return hipGetLastError();
+}
+
+template <int L>
+static void burgers_rhs_L(const egfem_tensor_s* T, bool group, const double* u, const double* src, double dt,
+                          const double* cvals, const uint8_t* dir, double* rhs, hipStream_t st) {
+  auto kern = group ? k_burgers_rhs<L, true> : k_burgers_rhs<L, false>;
+  hipLaunchKernelGGL(kern, dim3(grid1d(T->n * L)), dim3(kBlockThreads), 0, st, T->n, T->rowptr, T->col, T->mval,
+                     cvals, u, src, dt, 0.5 * dt, dir, rhs);
+}
+
+hipError_t launch_burgers_rhs(const egfem_tensor_s* T, bool group, const double* u, const double* src, double dt,
+                              const double* cvals, const uint8_t* dir, double* rhs, hipStream_t st) {
+  switch (T->lanes_per_row) {
+    case 4: burgers_rhs_L<4>(T, group, u, src, dt, cvals, dir, rhs, st); break;
+    case 8: burgers_rhs_L<8>(T, group, u, src, dt, cvals, dir, rhs, st); break;
+    case 16: burgers_rhs_L<16>(T, group, u, src, dt, cvals, dir, rhs, st); break;
+    case 32: burgers_rhs_L<32>(T, group, u, src, dt, cvals, dir, rhs, st); break;
+    default: burgers_rhs_L<64>(T, group, u, src, dt, cvals, dir, rhs, st); break;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_permute_slots(const egfem_tensor_s* T, const double* in, double* out,

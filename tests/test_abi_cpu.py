@@ -41,6 +41,12 @@ def test_version_and_defaults():
     d = eg.PicardOptions()
     assert (q.tol, q.max_picard, q.max_krylov, q.krylov_rtol) == (d.tol, d.max_picard, d.max_krylov,
                                                                    d.krylov_rtol)
+    b = B._BurgersOpts()
+    eg.load_library().egfem_burgers_opts_default(C.byref(b))
+    e = eg.BurgersOptions()
+    for name, _ in B._BurgersOpts._fields_:
+        assert getattr(b, name) == getattr(e, name), name
+    assert (b.dt, b.nu, b.steps, b.group) == (1e-2, 1.0, 100, 0)
 
 
 def _build(coords, cells, dim=None, form=0, drop=1e-13):
@@ -93,6 +99,7 @@ def test_null_handles_rejected():
     assert lib.egfem_solve(z, z, 0, z, z, 1e-10, 10, None, None, z) == B.EGFEM_ERR_ARG
     assert lib.egfem_solve_cg(z, z, z, z, 1e-10, 10, None, None, z) == B.EGFEM_ERR_ARG
     assert lib.egfem_picard(z, z, z, z, z, z) == B.EGFEM_ERR_ARG
+    assert lib.egfem_burgers(z, z, z, 0, z, z, z, z) == B.EGFEM_ERR_ARG
     assert lib.egfem_tensor_info(z, None) == B.EGFEM_ERR_ARG
     assert lib.egfem_newton_batched(0, None, None, None, None, None, None) == B.EGFEM_ERR_ARG
     lib.egfem_tensor_destroy(z)

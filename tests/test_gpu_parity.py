@@ -78,7 +78,7 @@ MESHES = {
 # offline build
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("mesh", list(MESHES))
-@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("form", [0, 1, 2])
 def test_build_matches_oracle_tensor(mesh, form):
     m = MESHES[mesh]()
     T = eg().Tensor.from_mesh(m, form)
@@ -126,7 +126,7 @@ def test_build_counts_full_size():
 # tensor actions
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("mesh", list(MESHES))
-@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("form", [0, 1, 2])
 def test_raw_action_and_mode3(mesh, form):
     m = MESHES[mesh]()
     T = eg().Tensor.from_mesh(m, form)
@@ -142,7 +142,7 @@ def test_raw_action_and_mode3(mesh, form):
 
 
 @pytest.mark.parametrize("mesh", list(MESHES))
-@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("form", [0, 1, 2])
 def test_jacobian_emission(mesh, form):
     m = MESHES[mesh]()
     T = eg().Tensor.from_mesh(m, form)
