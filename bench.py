@@ -376,6 +376,47 @@ def picard_suite(T, p, reps: int = 3):
             "cg_kernel": "register-resident" if st.krylov_kernels == 1 else "streaming"}
 
 
+def burgers_suite(n: int = 256, reps: int = 2):
+    """The Burgers experiment of Sec. 5.2 (nu = 1, T = 1, dt = 1e-2: 100
+    semi-implicit steps) on the 2D n x n mesh, tensor and group formulations."""
+    import numpy as np
+    import torch
+    import paper_2005_06193_amd as eg
+    import workloads as W
+    b = W.burgers_2d(n)
+    T = eg.Tensor.from_mesh(b.mesh, W.FORM_CONV)
+    dirm = torch.tensor(b.mesh.dirichlet, dtype=torch.uint8, device="cuda")
+    src = torch.tensor(b.source, dtype=torch.float64, device="cuda")
+    u0 = torch.tensor(b.u0, dtype=torch.float64, device="cuda")
+    out = {"workload": b.name, "nodes": T.n, "tensor_nnz": T.info.nnz, "steps": b.steps, "dt": b.dt,
+           "nu": b.nu, "krylov": "cg-jacobi, rtol 1e-12 per step"}
+    for name, group in (("tensor", 0), ("group", 1)):
+        u = u0.clone()
+        T.burgers(u, dirm, src, eg.BurgersOptions(steps=10, group=group))            # warm
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        times, st = [], None
+        for _ in range(reps):
+            u.copy_(u0)
+            torch.cuda.synchronize()
+            ev[0].record()
+            st = T.burgers(u, dirm, src, eg.BurgersOptions(group=group))
+            ev[1].record()
+            torch.cuda.synchronize()
+            times.append(ev[0].elapsed_time(ev[1]))
+        ut = eg.BurgersOptions(group=group, timing=1)
+        u.copy_(u0)
+        stt = T.burgers(u, dirm, src, ut)
+        ms = min(times)
+        err = float(np.linalg.norm(u.cpu().numpy() - b.u_final) / np.linalg.norm(b.u_final))
+        out[name] = {"ms_per_run": ms, "ms_per_step": ms / b.steps, "status": st.status_name,
+                     "cg_iters_per_step": st.krylov_iters / b.steps, "max_step_cg": st.max_step_krylov,
+                     "rhs_ms_per_step": stt.t_rhs_ms / b.steps, "cg_ms_per_step": stt.t_krylov_ms / b.steps,
+                     "cg_us_per_iter": 1e3 * stt.t_krylov_ms / max(stt.krylov_iters, 1),
+                     "rel_l2_error_vs_exact": err}
+    T.close()
+    return out
+
+
 def cpu_baseline(n: int, budget_s: float = 20.0):
     """The CPU oracle (numpy/scipy, SuperLU direct solves) on the same workload:
     EGFEM Newton solves, plus one SGA (re-assembly) solve for context."""
@@ -401,6 +442,12 @@ def cpu_baseline(n: int, budget_s: float = 20.0):
         t0 = time.perf_counter()
         _, pst = O.picard(prob, tol=1e-12)
         t_pic = time.perf_counter() - t0
+        # Burgers (Sec. 5.2): 10 of the 100 semi-implicit steps, tensor formulation
+        bw = W.burgers_2d(n)
+        bsys = O.burgers_system(bw.mesh.coords, bw.mesh.cells, bw.mesh.dirichlet, bw.dt, bw.nu)
+        t0 = time.perf_counter()
+        O.burgers(bsys, bw.u0, bw.source, 10)
+        t_burg = (time.perf_counter() - t0) / 10
     egfem_s = sum(times) / len(times)
     return {
         "value": 1.0 / egfem_s,
@@ -410,9 +457,11 @@ def cpu_baseline(n: int, budget_s: float = 20.0):
         "sample": f"{len(times)} full EGFEM Newton solve(s) of the same 66,049-node workload "
                   f"(numpy/scipy, SuperLU direct solves, tol 1e-10), mean {egfem_s:.3f} s; "
                   f"one SGA re-assembly Newton solve took {t_sga:.3f} s, one EGFEM Picard solve "
-                  f"(update 1e-12, {pst.iterations} iterations) {t_pic:.3f} s",
+                  f"(update 1e-12, {pst.iterations} iterations) {t_pic:.3f} s, 10 Burgers steps "
+                  f"(tensor formulation, one LU of M + dt nu K) {10 * t_burg:.3f} s",
         "sga_solves_per_s": 1.0 / t_sga,
         "picard_solves_per_s": 1.0 / t_pic,
+        "burgers_ms_per_step": 1e3 * t_burg,
         "cpu": _cpu_model(),
     }
 
@@ -439,6 +488,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance batched form")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the 3D adjoint form")
     ap.add_argument("--no-picard", action="store_true", help="skip the Picard iteration")
+    ap.add_argument("--no-burgers", action="store_true", help="skip the Burgers time stepping")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -508,6 +558,7 @@ def main():
     batched = None if args.no_batched else batched_suite()
     adjoint = None if args.no_adjoint else adjoint_suite()
     picard = None if args.no_picard else picard_suite(T, p)
+    burgers = None if args.no_burgers else burgers_suite(args.n)
 
     if args.copy_probe:
         src = torch.ones(1 << 25, dtype=torch.float64, device="cuda")
@@ -543,6 +594,7 @@ def main():
         "batched": batched,
         "adjoint": adjoint,
         "picard": picard,
+        "burgers": burgers,
         "cpu_baseline": cpu,
     }
     if cpu:

@@ -315,8 +315,8 @@ int egfem_solve_cg(egfem_tensor_t T, const double* jval, const double* rhs, doub
  * values at t_{n+1} (load M s^{n+1}), Dirichlet rows identity with zero right-
  * hand side.  The matrix is constant and symmetric positive definite: it is
  * emitted once, and every step is one tensor action (or one N^f product fused
- * into the right-hand side) plus one persistent Jacobi-CG launch warm started
- * from u^n.
+ * into the right-hand side) plus one persistent Jacobi-CG launch started from
+ * an extrapolation of the previous iterates (opts.guess).
  * ---------------------------------------------------------------------- */
 typedef struct {
   double dt;                 /* time step (default 1e-2) */
@@ -325,6 +325,9 @@ typedef struct {
   int group;                 /* 0: tensor formulation, 1: group formulation (default 0) */
   double krylov_rtol;        /* each solve: ||r||_2 <= krylov_rtol ||rhs||_2 (default 1e-12) */
   int max_krylov;            /* CG iteration cap per step (default 20000) */
+  int guess;                 /* initial CG iterate of step n+1: 0 = u^n, 1 = 2u^n - u^{n-1},
+                                2 = 3u^n - 3u^{n-1} + u^{n-2} (polynomial extrapolation in time,
+                                lower order while fewer iterates exist; default 2) */
   int krylov_blocks;         /* persistent CG grid, 0 = launch shape of the handle */
   int krylov_threads;        /* 256, 512, 1024, or 0 = launch shape of the handle */
   int timing;                /* nonzero: time the right-hand sides and solves with HIP events */

@@ -80,8 +80,8 @@ class _PicardStats(C.Structure):
 
 class _BurgersOpts(C.Structure):
     _fields_ = [("dt", C.c_double), ("nu", C.c_double), ("steps", C.c_int), ("group", C.c_int),
-                ("krylov_rtol", C.c_double), ("max_krylov", C.c_int), ("krylov_blocks", C.c_int),
-                ("krylov_threads", C.c_int), ("timing", C.c_int)]
+                ("krylov_rtol", C.c_double), ("max_krylov", C.c_int), ("guess", C.c_int),
+                ("krylov_blocks", C.c_int), ("krylov_threads", C.c_int), ("timing", C.c_int)]
 
 
 class _BurgersStats(C.Structure):
@@ -292,13 +292,14 @@ class BurgersOptions:
     group: int = 0
     krylov_rtol: float = 1e-12
     max_krylov: int = 20000
+    guess: int = 2
     krylov_blocks: int = 0
     krylov_threads: int = 0
     timing: int = 0
 
     def c(self) -> _BurgersOpts:
         return _BurgersOpts(self.dt, self.nu, self.steps, self.group, self.krylov_rtol, self.max_krylov,
-                            self.krylov_blocks, self.krylov_threads, self.timing)
+                            self.guess, self.krylov_blocks, self.krylov_threads, self.timing)
 
 
 @dataclass

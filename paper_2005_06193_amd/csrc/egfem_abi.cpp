@@ -542,6 +542,7 @@ void egfem_burgers_opts_default(egfem_burgers_opts* o) {
   o->group = 0;
   o->krylov_rtol = 1e-12;
   o->max_krylov = 20000;
+  o->guess = 2;
   o->krylov_blocks = 0;
   o->krylov_threads = 0;
   o->timing = 0;
@@ -556,7 +557,7 @@ int egfem_burgers(egfem_tensor_t T, const uint8_t* dirichlet, const double* sour
   if (o) opts = *o;
   if (!(opts.dt > 0.0) || !std::isfinite(opts.dt) || !(opts.nu >= 0.0) || !std::isfinite(opts.nu) ||
       opts.steps < 0 || opts.max_krylov < 1 || !(opts.krylov_rtol > 0.0) || opts.krylov_blocks < 0 ||
-      (opts.group != 0 && opts.group != 1) ||
+      (opts.group != 0 && opts.group != 1) || opts.guess < 0 || opts.guess > 2 ||
       (opts.krylov_threads != 0 && opts.krylov_threads != 256 && opts.krylov_threads != 512 &&
        opts.krylov_threads != 1024))
     return fail(EGFEM_ERR_ARG, "invalid Burgers options");
@@ -587,6 +588,9 @@ int egfem_burgers(egfem_tensor_t T, const uint8_t* dirichlet, const double* sour
     EGFEM_HIP_CHECK(launch_burgers_rhs(T, opts.group != 0, u, src, opts.dt, opts.group ? W.qslot : W.F,
                                        dirichlet, W.rhs, st));
     if ((rc = tm.stop(&stats.t_rhs_ms, &n_dummy)) != EGFEM_OK) return rc;
+    // initial iterate: extrapolation over the iterates kept so far (W.delta
+    // holds u^{n-1}, W.utry u^{n-2})
+    EGFEM_HIP_CHECK(launch_extrapolate(T->n, std::min(opts.guess, n), u, W.delta, W.utry, st));
     KrylovResult kr;
     rc = krylov_solve(KrylovMethod::kCG, T, W.jval, W.dinv, W.rhs, 1.0, u, false, opts.krylov_rtol, false,
                       opts.max_krylov, opts.krylov_blocks, &kr, st, nullptr, tm.on, opts.krylov_threads);

@@ -168,6 +168,8 @@ hipError_t launch_permute_slots(const egfem_tensor_s* T, const double* in, doubl
 // columns; dinv = 1 / diagonal.
 hipError_t launch_mk_combine(const egfem_tensor_s* T, double cm, double ck, const uint8_t* dir, double* vals,
                              double* dinv, hipStream_t st);
+// u <- extrapolation of order 0..2 from u, h1, h2; then h2 <- h1, h1 <- old u.
+hipError_t launch_extrapolate(int64_t n, int order, double* u, double* h1, double* h2, hipStream_t st);
 // Burgers right-hand side M (u + dt src) + dt/2 C; cvals = N^f in slot layout
 // (group) or the tensor action N:(u (x) u) [n] (tensor formulation).
 hipError_t launch_burgers_rhs(const egfem_tensor_s* T, bool group, const double* u, const double* src, double dt,

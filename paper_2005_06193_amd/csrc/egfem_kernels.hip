@@ -240,6 +240,22 @@ __global__ __launch_bounds__(kBlockThreads) void k_burgers_rhs(int64_t n, const 
   }
 }
 
+// Initial iterate of the next time step by polynomial extrapolation of the
+// last iterates (order 0, 1 or 2), in place on u; the history shifts:
+// h2 <- h1, h1 <- u (old).
+__global__ void k_extrapolate(int64_t n, int order, double* __restrict__ u, double* __restrict__ h1,
+                              double* __restrict__ h2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double t = u[i];
+  if (order >= 1) {
+    const double p1 = h1[i];
+    u[i] = order == 2 ? fma(3.0, t - p1, h2[i]) : 2.0 * t - p1;
+    h2[i] = p1;
+  }
+  h1[i] = t;
+}
+
 __global__ void k_permute(int64_t slots, const int32_t* __restrict__ perm,
                           const double* __restrict__ in, double* __restrict__ out) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -378,6 +394,12 @@ hipError_t launch_burgers_rhs(const egfem_tensor_s* T, bool group, const double*
     case 32: burgers_rhs_L<32>(T, group, u, src, dt, cvals, dir, rhs, st); break;
     default: burgers_rhs_L<64>(T, group, u, src, dt, cvals, dir, rhs, st); break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_extrapolate(int64_t n, int order, double* u, double* h1, double* h2, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_extrapolate, dim3(grid1d(n)), dim3(kBlockThreads), 0, st, n, order, u, h1, h2);
   return hipGetLastError();
 }
 

@@ -143,3 +143,22 @@ def test_burgers_edge_cases():
         T.burgers(dt(u0), dirm, None, eg().BurgersOptions(dt=0.0))
     with pytest.raises(eg().EgfemError):
         T.burgers(dt(u0), dirm, dt(np.tile(src, (2, 1))), eg().BurgersOptions(steps=3))
+
+
+def test_burgers_initial_guess_orders():
+    """Extrapolated initial iterates change the CG work, not the answer."""
+    b = W.burgers_2d(32)
+    T = eg().Tensor.from_mesh(b.mesh, W.FORM_CONV)
+    dirm = dt(b.mesh.dirichlet, torch.uint8)
+    src = dt(b.source)
+    uo = _oracle(b.mesh, b.u0, b.source, b.dt, b.nu, 30, False)
+    iters = []
+    for guess in (0, 1, 2):
+        u = dt(b.u0)
+        st = T.burgers(u, dirm, src, eg().BurgersOptions(steps=30, guess=guess, krylov_rtol=1e-13))
+        assert st.status == 0
+        assert relerr(host(u), uo) < 1e-11
+        iters.append(st.krylov_iters)
+    assert iters[2] < iters[1] < iters[0], iters
+    with pytest.raises(eg().EgfemError):
+        T.burgers(dt(b.u0), dirm, src, eg().BurgersOptions(steps=3, guess=3))
