@@ -74,6 +74,13 @@ enum egfem_form {
   EGFEM_FORM_CONV = 2        /* T_ijk = int phi_k phi_j (sum_d d/dx_d phi_i) (T_ijk = T_ikj) */
 };
 
+enum egfem_wspace {
+  EGFEM_W_P1 = 0,            /* W_h = V_h = P1 (Case 2 of Sec. 3.1, the group FEM choice) */
+  EGFEM_W_P2 = 1             /* W_h = P2 on the same mesh with Pi_u the P2 interpolation of the
+                                P1 iterate (Case 1 of Sec. 3.1): for a = a0 + u^2 the coefficient
+                                is then exact and EGFEM coincides with the standard Galerkin method */
+};
+
 /* ------------------------------------------------------------------------
  * Offline phase (Sec. 3.3 eq. egfem_terms; the paper excludes it from the
  * online times, Sec. 5 preamble).
@@ -99,6 +106,25 @@ int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords,
                        int64_t n_cells, const int32_t* cells, int form,
                        double drop_rel, egfem_tensor_t* out);
 
+/* egfem_build_tensor_w: the same with the coefficient space chosen by wspace.
+ * With EGFEM_W_P2 the tensor is T_ijk = int eta_k grad phi_j . grad phi_i
+ * (stiffness) or int eta_k phi_j phi_i (mass) with eta the P2 nodal basis
+ * (vertex lambda(2 lambda - 1), edge midpoint 4 lambda_x lambda_y); k runs
+ * over the n_w = n_nodes + n_edges P2 dofs: the vertices, then the edges in
+ * ascending (smaller vertex id, larger vertex id) order (Sec. 3.1, Case 1;
+ * Sec. 3.2 for Pi_u).  On such a handle:
+ *  - every a / dadu argument of egfem_residual and egfem_jacobian is a vector
+ *    over the P2 dofs (length n_w), and the second Jacobian term becomes
+ *    sum_k (sum_j' T_ij'k u_j') dadu_k (Pi_u)_kj;
+ *  - the problem-level calls (problem residual / Jacobian, Newton, Picard)
+ *    use a = Pi_u a0 + (Pi_u u)^2 at the P2 dofs, a' = 2 Pi_u u;
+ *  - egfem_mode3, egfem_adjoint, the batched form and egfem_burgers return
+ *    EGFEM_ERR_ARG; the convection form is not available (EGFEM_ERR_ARG).
+ * Row blocks additionally hold at most 1024 (row, P2 dof) couplings. */
+int egfem_build_tensor_w(int dim, int64_t n_nodes, const double* coords,
+                         int64_t n_cells, const int32_t* cells, int form, int wspace,
+                         double drop_rel, egfem_tensor_t* out);
+
 void egfem_tensor_destroy(egfem_tensor_t T);
 
 /* Sizes and read-only device views of the pattern (for callers that build
@@ -119,6 +145,8 @@ typedef struct {
   const int32_t* col;        /* device [slots], ascending within a row */
   const double* kval;        /* device [slots] stiffness matrix values */
   const double* mval;        /* device [slots] mass matrix values */
+  int wspace;                /* EGFEM_W_P1 or EGFEM_W_P2 */
+  int64_t n_w;               /* dofs of W_h (n_nodes for P1) */
 } egfem_info;
 
 int egfem_tensor_info(egfem_tensor_t T, egfem_info* info);

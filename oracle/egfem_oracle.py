@@ -673,6 +673,16 @@ def assemble_tensor_p2(coords, cells, W: P2Space, form: int):
     return I, J, K, Te.reshape(-1)
 
 
+def tensor_p2(coords, cells, form: int, drop_rel: float = DROP_REL):
+    """The P2 tensor with duplicates summed and the exact-zero drop rule applied
+    (as for the P1 tensors); the returned Tensor3 has n = n_w, rows and j below
+    the vertex count, k over all P2 dofs (vertices, then edges in ascending
+    (min, max) vertex order).  Returns (tensor, space)."""
+    W = p2_space(coords, cells)
+    I, J, K, V = assemble_tensor_p2(coords, cells, W, form)
+    return _merge_coo3(W.n_w, I, J, K, V, drop_rel), W
+
+
 @dataclass
 class ProblemP2:
     base: Problem

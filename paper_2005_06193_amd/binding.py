@@ -35,6 +35,8 @@ STATUS_NAMES = {0: "ok", 1: "not_converged", 2: "breakdown", 3: "nonfinite", 4: 
 FORM_STIFF = 0
 FORM_MASS = 1
 FORM_CONV = 2
+W_P1 = 0
+W_P2 = 1
 HIST = 64
 
 
@@ -50,7 +52,7 @@ class _Info(C.Structure):
                 ("nnz_b", C.c_int64), ("structural_nnz", C.c_int64), ("slots", C.c_int64),
                 ("row_blocks", C.c_int64), ("device_bytes", C.c_int64),
                 ("rowptr", C.c_void_p), ("col", C.c_void_p), ("kval", C.c_void_p),
-                ("mval", C.c_void_p)]
+                ("mval", C.c_void_p), ("wspace", C.c_int), ("n_w", C.c_int64)]
 
 
 class _Problem(C.Structure):
@@ -110,6 +112,8 @@ _lib = None
 EXPORTS = {
     "egfem_build_tensor": (C.c_int, [C.c_int, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
                                      C.c_int, C.c_double, C.POINTER(C.c_void_p)]),
+    "egfem_build_tensor_w": (C.c_int, [C.c_int, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
+                                       C.c_int, C.c_int, C.c_double, C.POINTER(C.c_void_p)]),
     "egfem_tensor_destroy": (None, [C.c_void_p]),
     "egfem_tensor_info": (C.c_int, [C.c_void_p, C.POINTER(_Info)]),
     "egfem_tensor_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -220,6 +224,8 @@ class Info:
     slots: int
     row_blocks: int
     device_bytes: int
+    wspace: int = 0
+    n_w: int = 0
 
 
 @dataclass
@@ -386,12 +392,13 @@ class Tensor:
         inf = _Info()
         _check(load_library().egfem_tensor_info(self._h, C.byref(inf)))
         self.info = Info(inf.dim, inf.form, inf.symmetric, inf.n_nodes, inf.n_cells, inf.nnz,
-                         inf.nnz_b, inf.structural_nnz, inf.slots, inf.row_blocks, inf.device_bytes)
+                         inf.nnz_b, inf.structural_nnz, inf.slots, inf.row_blocks, inf.device_bytes,
+                         inf.wspace, inf.n_w)
 
     # -- construction ----------------------------------------------------
     @classmethod
     def build(cls, coords: np.ndarray, cells: np.ndarray, form: int = FORM_STIFF,
-              drop_rel: float = 1e-13) -> "Tensor":
+              drop_rel: float = 1e-13, wspace: int = W_P1) -> "Tensor":
         _require_device()
         lib = load_library()
         coords = np.ascontiguousarray(coords, dtype=np.float64)
@@ -399,14 +406,14 @@ class Tensor:
         if coords.ndim != 2 or cells.ndim != 2 or cells.shape[1] != coords.shape[1] + 1:
             raise EgfemError(EGFEM_ERR_SHAPE, "coords [N, d] and cells [E, d+1] expected")
         out = C.c_void_p()
-        _check(lib.egfem_build_tensor(coords.shape[1], coords.shape[0], coords.ctypes.data,
-                                      cells.shape[0], cells.ctypes.data, int(form),
-                                      float(drop_rel), C.byref(out)))
+        _check(lib.egfem_build_tensor_w(coords.shape[1], coords.shape[0], coords.ctypes.data,
+                                        cells.shape[0], cells.ctypes.data, int(form), int(wspace),
+                                        float(drop_rel), C.byref(out)))
         return cls(out.value)
 
     @classmethod
-    def from_mesh(cls, mesh, form: int = FORM_STIFF, drop_rel: float = 1e-13) -> "Tensor":
-        return cls.build(mesh.coords, mesh.cells, form, drop_rel)
+    def from_mesh(cls, mesh, form: int = FORM_STIFF, drop_rel: float = 1e-13, wspace: int = W_P1) -> "Tensor":
+        return cls.build(mesh.coords, mesh.cells, form, drop_rel, wspace)
 
     def close(self):
         if self._h is not None and self._h.value:
@@ -450,17 +457,17 @@ class Tensor:
 
     # -- online actions -----------------------------------------------------
     def residual(self, u: torch.Tensor, a: torch.Tensor, out: Optional[torch.Tensor] = None):
-        """r_i = sum_jk T_ijk u_j a_k."""
+        """r_i = sum_jk T_ijk u_j a_k (a over the dofs of W_h)."""
         out = torch.empty_like(u) if out is None else out
-        _check(load_library().egfem_residual(self.handle, _dptr(u, n=self.n), _dptr(a, n=self.n),
+        _check(load_library().egfem_residual(self.handle, _dptr(u, n=self.n), _dptr(a, n=self.info.n_w),
                                              _dptr(out, n=self.n), _stream()))
         return out
 
     def jacobian(self, u, a, dadu=None, add_stiffness=False, dirichlet=None, out=None,
                  dinv=None):
         out = torch.empty(self.info.slots, dtype=torch.float64, device="cuda") if out is None else out
-        _check(load_library().egfem_jacobian(self.handle, _dptr(u, n=self.n), _dptr(a, n=self.n),
-                                             _dptr(dadu, n=self.n), int(add_stiffness),
+        _check(load_library().egfem_jacobian(self.handle, _dptr(u, n=self.n), _dptr(a, n=self.info.n_w),
+                                             _dptr(dadu, n=self.info.n_w), int(add_stiffness),
                                              _dptr(dirichlet, torch.uint8, self.n),
                                              _dptr(out, n=self.info.slots), _dptr(dinv, n=self.n),
                                              _stream()))

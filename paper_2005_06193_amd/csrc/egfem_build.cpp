@@ -10,6 +10,12 @@
 //                         = sum_e (sum_d d_d lambda_i) M^e_jk      (gradient constant per cell)
 // K_ij = sum_e |e| grad phi_j . grad phi_i,  M_ij = sum_e |e| (1 + delta_ij) / ((d+1)(d+2)).
 //
+// W_h = P2 (Case 1 of Sec. 3.1; egfem_build_tensor_w): k runs over the P2 dofs
+// (vertices 0..N-1, then the edges in ascending (min, max) vertex order) with
+// eta_k the P2 nodal basis: vertex lambda(2 lambda - 1), edge 4 lambda_x lambda_y;
+// every P2 dof coupled to row i is a vertex or an edge of a cell of i, so both
+// of its endpoints are columns of row i.
+//
 // Layout (all indices int32, values float64):
 //   CSR pattern of the P1 adjacency including the diagonal: rowptr, col.
 //   A-stream: for slot s = (i,j) the fiber kptrA[s]..kptrA[s+1] of (k, T_ijk), k ascending.
@@ -95,17 +101,56 @@ int upload(const std::vector<T>& h, T** d, int64_t* bytes) {
   return EGFEM_OK;
 }
 
-}  // namespace
 
-extern "C" int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords, int64_t n_cells,
-                                  const int32_t* cells, int form, double drop_rel,
-                                  egfem_tensor_t* out) {
+// d! prod alpha_m! / (d + |alpha|)!: int_e prod lambda_m^alpha_m / |e|
+double mono(int dim, const int* alpha) {
+  int tot = 0;
+  double num = 1.0;
+  for (int m = 0; m <= dim; ++m) {
+    tot += alpha[m];
+    for (int f = 2; f <= alpha[m]; ++f) num *= f;
+  }
+  for (int f = 2; f <= dim; ++f) num *= f;
+  double den = 1.0;
+  for (int f = 2; f <= dim + tot; ++f) den *= f;
+  return num / den;
+}
+
+// int_e eta_c / |e| and int_e lambda_a lambda_b eta_c / |e| for the local P2
+// dof c (c < nl: vertex c; else the local edge ledge[c - nl]).
+double p2_int(int dim, int a, int b, int c, const int (*ledge)[2], bool with_ab) {
+  const int nl = dim + 1;
+  int base[4] = {0, 0, 0, 0};
+  if (with_ab) {
+    base[a]++;
+    base[b]++;
+  }
+  if (c < nl) {
+    int x1[4], x2[4];
+    for (int m = 0; m < 4; ++m) x1[m] = x2[m] = base[m];
+    x1[c] += 2;
+    x2[c] += 1;
+    return 2.0 * mono(dim, x1) - mono(dim, x2);
+  }
+  int x[4];
+  for (int m = 0; m < 4; ++m) x[m] = base[m];
+  x[ledge[c - nl][0]]++;
+  x[ledge[c - nl][1]]++;
+  return 4.0 * mono(dim, x);
+}
+
+int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, const int32_t* cells, int form,
+               int wspace, double drop_rel, egfem_tensor_t* out) {
   using namespace egfem;
   if (!out) return fail(EGFEM_ERR_ARG, "out is null");
   *out = nullptr;
   if (dim < 1 || dim > 3) return fail(EGFEM_ERR_ARG, "dim must be 1, 2 or 3");
   if (form != EGFEM_FORM_STIFF && form != EGFEM_FORM_MASS && form != EGFEM_FORM_CONV)
     return fail(EGFEM_ERR_ARG, "unknown form");
+  if (wspace != EGFEM_W_P1 && wspace != EGFEM_W_P2) return fail(EGFEM_ERR_ARG, "unknown W space");
+  if (wspace == EGFEM_W_P2 && form == EGFEM_FORM_CONV)
+    return fail(EGFEM_ERR_ARG, "the convection form is built with W_h = P1 only");
+  const bool w2 = (wspace == EGFEM_W_P2);
   if (!coords || !cells) return fail(EGFEM_ERR_ARG, "coords/cells null");
   if (n_nodes <= 0 || n_cells <= 0) return fail(EGFEM_ERR_SHAPE, "empty mesh");
   if (n_nodes >= (int64_t(1) << 31) || n_cells >= (int64_t(1) << 31))
@@ -162,8 +207,43 @@ extern "C" int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords
   std::vector<double> acc;
   std::vector<unsigned char> present;
   std::vector<double> kacc, macc;
-  // B == A exactly when T_ijk = T_ikj
-  const bool sym = (form != EGFEM_FORM_STIFF);
+  // B == A exactly when T_ijk = T_ikj (never with W_h = P2: k and j live in
+  // different spaces)
+  const bool sym = (form != EGFEM_FORM_STIFF) && !w2;
+  // W_h = P2: global edges (ascending (min, max)), per-row W-slot records
+  const int ne_loc = nl * (nl - 1) / 2;
+  int ledge[6][2];
+  {
+    int t = 0;
+    for (int x = 0; x < nl; ++x)
+      for (int y = x + 1; y < nl; ++y) {
+        ledge[t][0] = x;
+        ledge[t][1] = y;
+        ++t;
+      }
+  }
+  std::vector<int64_t> ekeys;   // min * N + max of every edge
+  if (w2) {
+    ekeys.reserve((size_t)n_cells * ne_loc);
+    for (int64_t e = 0; e < n_cells; ++e) {
+      const int32_t* c = cells + e * nl;
+      for (int t = 0; t < ne_loc; ++t) {
+        const int64_t x = c[ledge[t][0]], y = c[ledge[t][1]];
+        ekeys.push_back(std::min(x, y) * N + std::max(x, y));
+      }
+    }
+    std::sort(ekeys.begin(), ekeys.end());
+    ekeys.erase(std::unique(ekeys.begin(), ekeys.end()), ekeys.end());
+    if (N + (int64_t)ekeys.size() >= (int64_t(1) << 31)) return fail(EGFEM_ERR_SHAPE, "too many P2 dofs");
+  }
+  auto edge_id = [&](int64_t x, int64_t y) {
+    const int64_t key = std::min(x, y) * N + std::max(x, y);
+    return (int64_t)(std::lower_bound(ekeys.begin(), ekeys.end(), key) - ekeys.begin());
+  };
+  std::vector<int32_t> wrowptr(w2 ? N + 1 : 0, 0), wcol;
+  std::vector<uint16_t> wpl, wql;   // row-local slot positions of a W-slot's endpoints
+  std::vector<int64_t> redges;
+  int max_row_wslots = 0;
   col.reserve((size_t)N * (dim == 3 ? 15 : 7));
 
   for (int64_t i = 0; i < N; ++i) {
@@ -176,13 +256,108 @@ extern "C" int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords
     cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
     const int nc = (int)cols.size();
     max_row_slots = std::max(max_row_slots, nc);
+    auto lidx = [&](int32_t node) {
+      return (int)(std::lower_bound(cols.begin(), cols.end(), node) - cols.begin());
+    };
+    if (w2) {
+      // W-slots of row i: its vertex dofs (the row's columns, same order),
+      // then the edge dofs of its cells in ascending id
+      redges.clear();
+      for (int64_t q = nptr[i]; q < nptr[i + 1]; ++q) {
+        const int32_t* c = cells + (int64_t)ncell[q] * nl;
+        for (int t = 0; t < ne_loc; ++t) redges.push_back(edge_id(c[ledge[t][0]], c[ledge[t][1]]));
+      }
+      std::sort(redges.begin(), redges.end());
+      redges.erase(std::unique(redges.begin(), redges.end()), redges.end());
+      const int nw = nc + (int)redges.size();
+      max_row_wslots = std::max(max_row_wslots, nw);
+      acc.assign((size_t)nc * nw, 0.0);
+      present.assign((size_t)nc * nw, 0);
+      kacc.assign(nc, 0.0);
+      macc.assign(nc, 0.0);
+      for (int64_t q = nptr[i]; q < nptr[i + 1]; ++q) {
+        const int64_t e = ncell[q];
+        const int32_t* c = cells + e * nl;
+        const Geom& g = geo[e];
+        int a = 0;
+        while (c[a] != (int32_t)i) ++a;
+        int loc[4], wl[10];
+        for (int b = 0; b < nl; ++b) loc[b] = wl[b] = lidx(c[b]);
+        for (int t = 0; t < ne_loc; ++t) {
+          const int64_t eid = edge_id(c[ledge[t][0]], c[ledge[t][1]]);
+          wl[nl + t] = nc + (int)(std::lower_bound(redges.begin(), redges.end(), eid) - redges.begin());
+        }
+        for (int b = 0; b < nl; ++b) {
+          double gg = 0.0;
+          for (int r = 0; r < dim; ++r) gg += g.G[a][r] * g.G[b][r];
+          const double kab = g.vol * gg;
+          kacc[loc[b]] += kab;
+          macc[loc[b]] += g.vol * (a == b ? m2_diag : m2_off);
+          for (int cd = 0; cd < nl + ne_loc; ++cd) {
+            const double val = (form == EGFEM_FORM_STIFF) ? kab * p2_int(dim, a, b, cd, ledge, false)
+                                                          : g.vol * p2_int(dim, a, b, cd, ledge, true);
+            const size_t idx = (size_t)loc[b] * nw + wl[cd];
+            acc[idx] += val;
+            present[idx] = 1;
+          }
+        }
+      }
+      double rowmax = 0.0;
+      for (size_t t = 0; t < acc.size(); ++t)
+        if (present[t]) {
+          ++structural;
+          rowmax = std::max(rowmax, std::fabs(acc[t]));
+        }
+      const double thr = drop_rel * rowmax;
+      auto kept = [&](size_t t) { return present[t] && acc[t] != 0.0 && std::fabs(acc[t]) > thr; };
+      auto wdof = [&](int kc) {
+        return kc < nc ? (int32_t)cols[kc] : (int32_t)(N + redges[kc - nc]);
+      };
+      for (int jb = 0; jb < nc; ++jb) {
+        col.push_back(cols[jb]);
+        kval.push_back(kacc[jb]);
+        mval.push_back(macc[jb]);
+        for (int kc = 0; kc < nw; ++kc) {
+          const size_t t = (size_t)jb * nw + kc;
+          if (kept(t)) {
+            kA.push_back(wdof(kc));
+            kRel.push_back((uint16_t)kc);
+            vA.push_back(acc[t]);
+          }
+        }
+        kptrA.push_back((int32_t)kA.size());
+      }
+      for (int kc = 0; kc < nw; ++kc) {
+        wcol.push_back(wdof(kc));
+        if (kc < nc) {
+          wpl.push_back((uint16_t)kc);
+          wql.push_back((uint16_t)kc);
+        } else {
+          const int64_t key = ekeys[redges[kc - nc]];
+          wpl.push_back((uint16_t)lidx((int32_t)(key / N)));
+          wql.push_back((uint16_t)lidx((int32_t)(key % N)));
+        }
+        for (int jb = 0; jb < nc; ++jb) {
+          const size_t t = (size_t)jb * nw + kc;
+          if (kept(t)) {
+            jB.push_back(cols[jb]);
+            jRel.push_back((uint16_t)jb);
+            vB.push_back(acc[t]);
+          }
+        }
+        jptrB.push_back((int32_t)jB.size());
+      }
+      if (col.size() >= (size_t)INT32_MAX || kA.size() >= (size_t)INT32_MAX || jB.size() >= (size_t)INT32_MAX ||
+          wcol.size() >= (size_t)INT32_MAX)
+        return fail(EGFEM_ERR_SHAPE, "more than 2^31 slots or tensor entries");
+      wrowptr[i + 1] = (int32_t)wcol.size();
+      rowptr[i + 1] = (int32_t)col.size();
+      continue;
+    }
     acc.assign((size_t)nc * nc, 0.0);
     present.assign((size_t)nc * nc, 0);
     kacc.assign(nc, 0.0);
     macc.assign(nc, 0.0);
-    auto lidx = [&](int32_t node) {
-      return (int)(std::lower_bound(cols.begin(), cols.end(), node) - cols.begin());
-    };
     for (int64_t q = nptr[i]; q < nptr[i + 1]; ++q) {
       const int64_t e = ncell[q];
       const int32_t* c = cells + e * nl;
@@ -287,12 +462,14 @@ extern "C" int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords
         const int64_t rows = r1 + 1 - r0;
         const int64_t sl = rowptr[r1 + 1] - rowptr[r0];
         const int64_t na = kptrA[rowptr[r1 + 1]] - kptrA[rowptr[r0]];
-        const int64_t nb = kpB[rowptr[r1 + 1]] - kpB[rowptr[r0]];
-        if (rows > kCapRows || sl > kCapSlots || na > kCapNnz || nb > kCapNnz) break;
+        const int64_t nb = w2 ? jptrB[wrowptr[r1 + 1]] - jptrB[wrowptr[r0]]
+                              : kpB[rowptr[r1 + 1]] - kpB[rowptr[r0]];
+        const int64_t nw = w2 ? wrowptr[r1 + 1] - wrowptr[r0] : 0;
+        if (rows > kCapRows || sl > kCapSlots || na > kCapNnz || nb > kCapNnz || nw > kCapWSlots) break;
         ++r1;
       }
       if (r1 == r0) return fail(EGFEM_ERR_SHAPE, "a node row exceeds the row-block capacity "
-                                                 "(1024 tensor entries / 512 slots)");
+                                                 "(1024 tensor entries / 512 slots / 1024 W-slots)");
       blk.push_back((int32_t)r1);
       r0 = r1;
     }
@@ -305,7 +482,35 @@ extern "C" int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords
   std::vector<uint16_t> kS(kA.size()), jS(jB.size());
   // fiber starts relative to the block's first entry (at most kCapNnz)
   std::vector<uint16_t> kpS((size_t)slots + 1), jpS(sym ? 0 : (size_t)slots + 1);
-  for (size_t b = 0; b + 1 < blk.size(); ++b) {
+  // W_h = P2: an A entry names its k by the block-relative W-slot of (i, k);
+  // the B stream is aligned to W-slots and its entries name j by the
+  // block-relative slot of (i, j); every W-slot records the block-relative
+  // slots of its two endpoints (p | q << 16; p == q for a vertex dof)
+  const int64_t wslots = w2 ? (int64_t)wcol.size() : 0;
+  std::vector<uint32_t> wpq;
+  std::vector<int32_t> wmeta;
+  if (w2) {
+    jpS.assign((size_t)wslots + 1, 0);
+    wpq.assign((size_t)wslots, 0);
+    wmeta.assign((blk.size() - 1) * 2, 0);
+    for (size_t b = 0; b + 1 < blk.size(); ++b) {
+      const int32_t s0 = rowptr[blk[b]], w0 = wrowptr[blk[b]];
+      wmeta[2 * b] = w0;
+      wmeta[2 * b + 1] = wrowptr[blk[b + 1]];
+      for (int32_t s = s0; s < rowptr[blk[b + 1]]; ++s) kpS[s] = (uint16_t)(kptrA[s] - kptrA[s0]);
+      for (int32_t w = w0; w < wrowptr[blk[b + 1]]; ++w) jpS[w] = (uint16_t)(jptrB[w] - jptrB[w0]);
+      for (int32_t i = blk[b]; i < blk[b + 1]; ++i) {
+        const int32_t vb = rowptr[i] - s0, wb = wrowptr[i] - w0;
+        for (int32_t s = rowptr[i]; s < rowptr[i + 1]; ++s)
+          for (int32_t p = kptrA[s]; p < kptrA[s + 1]; ++p) kS[p] = (uint16_t)(wb + kRel[p]);
+        for (int32_t w = wrowptr[i]; w < wrowptr[i + 1]; ++w) {
+          for (int32_t p = jptrB[w]; p < jptrB[w + 1]; ++p) jS[p] = (uint16_t)(vb + jRel[p]);
+          wpq[w] = (uint32_t)(vb + wpl[w]) | ((uint32_t)(vb + wql[w]) << 16);
+        }
+      }
+    }
+  }
+  for (size_t b = 0; !w2 && b + 1 < blk.size(); ++b) {
     const int32_t s0 = rowptr[blk[b]];
     for (int32_t s = s0; s < rowptr[blk[b + 1]]; ++s) {
       kpS[s] = (uint16_t)(kptrA[s] - kptrA[s0]);
@@ -334,8 +539,8 @@ extern "C" int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords
     m[3] = s1;
     m[4] = kptrA[s0];
     m[5] = kptrA[s1];
-    m[6] = kpB[s0];
-    m[7] = kpB[s1];
+    m[6] = w2 ? jptrB[wrowptr[r0]] : kpB[s0];
+    m[7] = w2 ? jptrB[wrowptr[r1]] : kpB[s1];
   }
 
   // --- upload -------------------------------------------------------------
@@ -358,6 +563,10 @@ extern "C" int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords
   T->krylov_lanes = klanes;
   T->krylov_rs = row_shape_for(max_row_slots, klanes);
   T->row_blocks = (int64_t)blk.size() - 1;
+  T->w2 = w2 ? 1 : 0;
+  T->n_w = w2 ? N + (int64_t)ekeys.size() : N;
+  T->wslots = wslots;
+  T->max_row_wslots = w2 ? max_row_wslots : max_row_slots;
   T->h_rowptr = rowptr;
   T->h_col = col;
   hipGetDevice(&T->device);
@@ -381,6 +590,12 @@ extern "C" int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords
   if (rc == EGFEM_OK) rc = upload(mval, &T->mval, &bytes);
   if (rc == EGFEM_OK) rc = upload(blk, &T->blk_row, &bytes);
   if (rc == EGFEM_OK) rc = upload(meta, &T->blk_meta, &bytes);
+  if (w2) {
+    if (rc == EGFEM_OK) rc = upload(wrowptr, &T->wrowptr, &bytes);
+    if (rc == EGFEM_OK) rc = upload(wcol, &T->wcol, &bytes);
+    if (rc == EGFEM_OK) rc = upload(wpq, &T->wpq, &bytes);
+    if (rc == EGFEM_OK) rc = upload(wmeta, &T->wmeta, &bytes);
+  }
   if (sym) {
     T->jptrB = T->kptrA;
     T->jB = T->kA;
@@ -395,4 +610,17 @@ extern "C" int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords
   }
   *out = T;
   return EGFEM_OK;
+}
+
+}  // namespace
+
+extern "C" int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords, int64_t n_cells,
+                                  const int32_t* cells, int form, double drop_rel, egfem_tensor_t* out) {
+  return build_impl(dim, n_nodes, coords, n_cells, cells, form, EGFEM_W_P1, drop_rel, out);
+}
+
+extern "C" int egfem_build_tensor_w(int dim, int64_t n_nodes, const double* coords, int64_t n_cells,
+                                    const int32_t* cells, int form, int wspace, double drop_rel,
+                                    egfem_tensor_t* out) {
+  return build_impl(dim, n_nodes, coords, n_cells, cells, form, wspace, drop_rel, out);
 }

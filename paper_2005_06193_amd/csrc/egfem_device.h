@@ -59,6 +59,12 @@ struct TensorView {
   const uint16_t* kpS;      // A fiber start relative to the block's first A entry
   const uint16_t* jpS;      // B fiber start relative to the block's first B entry
   const double* kval;
+  // W_h = P2 (Case 1): A entries name k by the block-relative W-slot; the B
+  // stream is aligned to W-slots (jpS per W-slot) and names j by the slot
+  const int2* wmeta;        // W-slot range of every block
+  const int32_t* wrowptr;   // W-slot range of every row
+  const int32_t* wcol;      // P2 dof of every W-slot
+  const uint32_t* wpq;      // block-relative slots of a W-slot's endpoints, p | q << 16
 };
 
 // Bounds of row block b: rows [r0, r1), slots [s0, s1), A entries [pa0, pa1),
@@ -441,6 +447,352 @@ __device__ void rowblock_jacobian(const TensorView& T, int64_t b, const double* 
     }
   }
   __syncthreads();   // LDS is reused by the next block
+}
+
+// ---------------------------------------------------------------------------
+// W_h = P2 row-block stages (Case 1 of Sec. 3.1)
+// ---------------------------------------------------------------------------
+// The coefficient lives on the P2 dofs.  Every P2 dof k coupled to row i is a
+// vertex or an edge of a cell of i, so both of its endpoints are columns of
+// row i: the interpolation Pi_u of Sec. 3.2 (vertex value, or the mean of the
+// two endpoint values) is formed from the per-slot gathers, and
+// a_k = (Pi a0)_k + ((Pi w)_k)^2 is computed once per W-slot in LDS.
+constexpr int kPerW(int nt) { return (kCapWSlots + nt - 1) / nt; }
+
+struct ActionLdsW {
+  double tA[kCapNnz];
+  double aS[kCapWSlots];     // a at every W-slot
+  double wS[kCapSlots];      // w at every slot's column
+  double zS[kCapSlots];      // a0 at every slot's column
+  double y[kCapSlots];
+  int spa[kCapSlots + 1];
+  int srow[kCapRows + 1];
+};
+
+__device__ __forceinline__ int w_lo(uint32_t pq) { return (int)(pq & 0xffffu); }
+__device__ __forceinline__ int w_hi(uint32_t pq) { return (int)(pq >> 16); }
+
+// Tensor action of row block b (one block per workgroup):
+//   RAW:     r_i = sum_{s=(i,j)} w_j sum_{p in A(s)} v_p a_{k_p}, a given on the P2 dofs;
+//   PROBLEM: a = Pi a0 + (Pi w)^2 with w = u + alpha delta, a0 nodal (or a0c);
+//            F = r [+ K w] - load, Dirichlet rows 0, uout = w, sq += F_i^2.
+template <int NT, bool PROBLEM>
+__device__ void rowblock_action_w2(const TensorView& T, int64_t b, const double* u, const double* delta,
+                                   double alpha, const double* a, double a0c, const double* load,
+                                   const uint8_t* dir, const double* kval, double* out, double* uout,
+                                   double& sq, ActionLdsW& L) {
+  constexpr int PP = Per<NT>::P, SS = Per<NT>::S, WW = kPerW(NT);
+  const int tid = threadIdx.x;
+  const BlockMeta m = block_meta(T, b);
+  const int2 wm = T.wmeta[b];
+  const int np = m.pa1 - m.pa0, ns = m.s1 - m.s0, nr = m.r1 - m.r0, nw = wm.y - wm.x;
+  // stream loads at clamped indices
+  int kk[PP];
+  double vv[PP];
+#pragma unroll
+  for (int q = 0; q < PP; ++q) {
+    const int p = m.pa0 + clamp_hi(tid + q * NT, np);
+    kk[q] = T.kS[p];
+    vv[q] = T.vA[p];
+  }
+  const double* kvp = kval ? kval : T.kval;
+  int cc[SS], kp[SS];
+  double kv[SS];
+#pragma unroll
+  for (int q = 0; q < SS; ++q) {
+    const int s = m.s0 + clamp_hi(tid + q * NT, ns);
+    cc[q] = T.col[s];
+    kp[q] = T.kpS[s];
+    kv[q] = kvp[s];
+  }
+  uint32_t wq[WW];
+  int wc[WW];
+#pragma unroll
+  for (int q = 0; q < WW; ++q) {
+    const int w = wm.x + clamp_hi(tid + q * NT, nw);
+    if (PROBLEM) wq[q] = T.wpq[w];
+    else wc[q] = T.wcol[w];
+  }
+  const bool has_row = tid < nr;
+  const int i = m.r0 + clamp_hi(tid, nr);
+  const int rp = T.rowptr[i];
+  const double ldi = (PROBLEM && load) ? load[i] : 0.0;
+  const unsigned char dr = (PROBLEM && dir) ? dir[i] : 0;
+  // per-slot gathers
+  double wj[SS];
+#pragma unroll
+  for (int q = 0; q < SS; ++q) {
+    wj[q] = u[cc[q]];
+    if (PROBLEM && delta) wj[q] = fma(alpha, delta[cc[q]], wj[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < SS; ++q) {
+    const int s = tid + q * NT;
+    if (s < ns) {
+      L.wS[s] = wj[q];
+      if (PROBLEM) L.zS[s] = a ? a[cc[q]] : a0c;
+      L.spa[s] = kp[q];
+    }
+  }
+  if (!PROBLEM) {
+#pragma unroll
+    for (int q = 0; q < WW; ++q) {
+      const int t = tid + q * NT;
+      if (t < nw) L.aS[t] = a[wc[q]];
+    }
+  }
+  if (tid == 0) {
+    L.spa[ns] = np;
+    L.srow[nr] = ns;
+  }
+  if (has_row) L.srow[tid] = rp - m.s0;
+  __syncthreads();
+  if (PROBLEM) {
+#pragma unroll
+    for (int q = 0; q < WW; ++q) {
+      const int t = tid + q * NT;
+      if (t < nw) {
+        const int p0 = w_lo(wq[q]), p1 = w_hi(wq[q]);
+        const double pw = 0.5 * (L.wS[p0] + L.wS[p1]);
+        L.aS[t] = fma(pw, pw, 0.5 * (L.zS[p0] + L.zS[p1]));
+      }
+    }
+    __syncthreads();
+  }
+  // products
+#pragma unroll
+  for (int q = 0; q < PP; ++q) {
+    const int p = tid + q * NT;
+    if (p < np) L.tA[p] = vv[q] * L.aS[kk[q]];
+  }
+  __syncthreads();
+  // fiber sums times w_j
+#pragma unroll
+  for (int q = 0; q < SS; ++q) {
+    const int s = tid + q * NT;
+    if (s < ns) {
+      double acc = 0.0;
+      for (int t = L.spa[s]; t < L.spa[s + 1]; ++t) acc += L.tA[t];
+      if (PROBLEM && kval) acc += kv[q];
+      L.y[s] = acc * wj[q];
+    }
+  }
+  __syncthreads();
+  // row sums
+  if (has_row) {
+    double acc = 0.0;
+    for (int t = L.srow[tid]; t < L.srow[tid + 1]; ++t) acc += L.y[t];
+    if (PROBLEM) {
+      const bool drow = dir && dr;
+      if (load) acc -= ldi;
+      if (drow) acc = 0.0;
+      if (uout) {
+        double wi = delta ? fma(alpha, delta[i], u[i]) : u[i];
+        uout[i] = drow ? 0.0 : wi;
+      }
+      sq = fma(acc, acc, sq);
+    }
+    out[i] = acc;
+  }
+  __syncthreads();
+}
+
+struct RowBlockLdsW {
+  double tA[kCapNnz];
+  double tB[kCapNnz];
+  double aS[kCapWSlots];     // a at every W-slot
+  double cW[kCapWSlots];     // g at every W-slot, then g times its B fiber sum
+  double uS[kCapSlots];
+  double zS[kCapSlots];      // a0 at every slot's column
+  double bacc[kCapSlots];    // second term gathered back to the slots
+  uint32_t wpq[kCapWSlots];
+  int spa[kCapSlots + 1];
+  int spbw[kCapWSlots + 1];  // B fiber bounds of every W-slot
+  int srow[kCapRows + 1];
+  int swrow[kCapRows + 1];   // W-slot bounds of every row
+  int srid[kCapSlots];
+  unsigned char sdir[kCapRows];
+};
+
+// Jacobian emission of row block b for W_h = P2:
+//   J_s = [K_s] + sum_{p in A(s)} v_p a_{k_p} + sum_k q_ik g_k (Pi_u)_kj,
+//   q_ik = sum_{p in B(i,k)} v_p u_{j_p},  s = (i, j),
+// a = Pi a0 + (Pi u)^2 (problem_a) or given on the P2 dofs; g = dadu (given on
+// the P2 dofs), 2 Pi u (dadu_2u) or none.  (Pi_u)_kj is 1 for the vertex dof
+// k = j and 1/2 for an edge dof k with endpoint j.  Every row adds its
+// W-slots' terms to its own slots in ascending W-slot order (deterministic).
+// Dirichlet rows -> identity rows, Dirichlet columns -> 0; dinv[i] = 1 / J_ii.
+template <int NT>
+__device__ void rowblock_jacobian_w2(const TensorView& T, int64_t b, const double* u, const double* a,
+                                     const double* a0, double a0c, int problem_a, const double* dadu,
+                                     int dadu_2u, const double* kval, const uint8_t* dir, double* jval,
+                                     double* dinv, RowBlockLdsW& L) {
+  constexpr int PP = Per<NT>::P, SS = Per<NT>::S, WW = kPerW(NT);
+  const int tid = threadIdx.x;
+  const BlockMeta m = block_meta(T, b);
+  const int2 wm = T.wmeta[b];
+  const int r0 = m.r0, s0 = m.s0;
+  const int na = m.pa1 - m.pa0, nb = m.pb1 - m.pb0, ns = m.s1 - m.s0, nr = m.r1 - m.r0, nw = wm.y - wm.x;
+  const bool second = dadu || dadu_2u;
+  const bool need_u = problem_a || second;
+  int ka[PP], jb[PP];
+  double va[PP], vb[PP];
+#pragma unroll
+  for (int q = 0; q < PP; ++q) {
+    const int p = m.pa0 + clamp_hi(tid + q * NT, na);
+    ka[q] = T.kS[p];
+    va[q] = T.vA[p];
+  }
+  if (second) {
+#pragma unroll
+    for (int q = 0; q < PP; ++q) {
+      const int p = m.pb0 + clamp_hi(tid + q * NT, nb);
+      jb[q] = T.jS[p];
+      vb[q] = T.vB[p];
+    }
+  }
+  int cc[SS], kpa[SS];
+  double kv[SS];
+  const double* kvp = kval ? kval : T.kval;
+#pragma unroll
+  for (int q = 0; q < SS; ++q) {
+    const int s = s0 + clamp_hi(tid + q * NT, ns);
+    cc[q] = T.col[s];
+    kpa[q] = T.kpS[s];
+    kv[q] = kvp[s];
+  }
+  uint32_t wq[WW];
+  int wc[WW], wbp[WW];
+#pragma unroll
+  for (int q = 0; q < WW; ++q) {
+    const int w = wm.x + clamp_hi(tid + q * NT, nw);
+    wq[q] = T.wpq[w];
+    wc[q] = T.wcol[w];
+    wbp[q] = T.jpS[w];
+  }
+  const bool has_row = tid < nr;
+  const int i = r0 + clamp_hi(tid, nr);
+  const int rpa = T.rowptr[i], rpb = T.rowptr[i + 1];
+  const int wra = T.wrowptr[i], wrb = T.wrowptr[i + 1];
+  const unsigned char drow_raw = dir ? dir[i] : 0;
+  // per-slot gathers
+  double uj[SS];
+  unsigned char dcr[SS];
+#pragma unroll
+  for (int q = 0; q < SS; ++q) {
+    uj[q] = need_u ? u[cc[q]] : 0.0;
+    dcr[q] = dir ? dir[cc[q]] : 0;
+  }
+#pragma unroll
+  for (int q = 0; q < SS; ++q) {
+    const int s = tid + q * NT;
+    if (s < ns) {
+      L.uS[s] = uj[q];
+      L.zS[s] = (problem_a && a0) ? a0[cc[q]] : a0c;
+      L.spa[s] = kpa[q];
+      L.bacc[s] = 0.0;
+    }
+  }
+  // per-W-slot values that need no slot data
+#pragma unroll
+  for (int q = 0; q < WW; ++q) {
+    const int t = tid + q * NT;
+    if (t < nw) {
+      L.wpq[t] = wq[q];
+      L.spbw[t] = wbp[q];
+      if (!problem_a) L.aS[t] = a[wc[q]];
+      if (dadu) L.cW[t] = dadu[wc[q]];
+    }
+  }
+  if (tid == 0) {
+    L.spa[ns] = na;
+    L.spbw[nw] = nb;
+  }
+  if (has_row) {
+    L.sdir[tid] = (dir && drow_raw) ? 1 : 0;
+    L.srow[tid] = rpa - s0;
+    L.swrow[tid] = wra - wm.x;
+    for (int s = rpa - s0; s < rpb - s0; ++s) L.srid[s] = tid;
+    if (tid == nr - 1) {
+      L.srow[nr] = rpb - s0;
+      L.swrow[nr] = wrb - wm.x;
+    }
+  }
+  __syncthreads();
+  // W-slot values from the slot gathers: a = Pi a0 + (Pi u)^2, g = 2 Pi u
+  if (problem_a || dadu_2u) {
+#pragma unroll
+    for (int q = 0; q < WW; ++q) {
+      const int t = tid + q * NT;
+      if (t < nw) {
+        const int p0 = w_lo(wq[q]), p1 = w_hi(wq[q]);
+        const double pu = 0.5 * (L.uS[p0] + L.uS[p1]);
+        if (problem_a) L.aS[t] = fma(pu, pu, 0.5 * (L.zS[p0] + L.zS[p1]));
+        if (dadu_2u && !dadu) L.cW[t] = 2.0 * pu;
+      }
+    }
+    __syncthreads();
+  }
+  // products
+#pragma unroll
+  for (int q = 0; q < PP; ++q) {
+    const int p = tid + q * NT;
+    if (p < na) L.tA[p] = va[q] * L.aS[ka[q]];
+    if (second && p < nb) L.tB[p] = vb[q] * L.uS[jb[q]];
+  }
+  __syncthreads();
+  if (second) {
+    // c_t = g_t * sum over the B fiber of W-slot t
+#pragma unroll
+    for (int q = 0; q < WW; ++q) {
+      const int t = tid + q * NT;
+      if (t < nw) {
+        double qb = 0.0;
+        for (int x = L.spbw[t]; x < L.spbw[t + 1]; ++x) qb += L.tB[x];
+        L.cW[t] *= qb;
+      }
+    }
+    __syncthreads();
+    // back to the row's slots through Pi_u, one thread per row, fixed order
+    if (has_row) {
+      for (int t = L.swrow[tid]; t < L.swrow[tid + 1]; ++t) {
+        const uint32_t pq = L.wpq[t];
+        const int p0 = w_lo(pq), p1 = w_hi(pq);
+        const double c = L.cW[t];
+        if (p0 == p1) {
+          L.bacc[p0] += c;
+        } else {
+          L.bacc[p0] += 0.5 * c;
+          L.bacc[p1] += 0.5 * c;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // slot assembly
+#pragma unroll
+  for (int q = 0; q < SS; ++q) {
+    const int s = tid + q * NT;
+    if (s < ns) {
+      const int ir = L.srid[s];
+      const int row = r0 + ir;
+      const int j = cc[q];
+      double J;
+      if (L.sdir[ir]) {
+        J = (j == row) ? 1.0 : 0.0;
+      } else if (dcr[q]) {
+        J = 0.0;
+      } else {
+        double qa = 0.0;
+        for (int t = L.spa[s]; t < L.spa[s + 1]; ++t) qa += L.tA[t];
+        J = (kval ? kv[q] : 0.0) + qa;
+        if (second) J += L.bacc[s];
+      }
+      jval[s0 + s] = J;
+      if (j == row && dinv) dinv[row] = 1.0 / J;
+    }
+  }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------

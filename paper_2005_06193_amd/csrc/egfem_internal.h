@@ -18,6 +18,7 @@ constexpr int kBlockThreads = 256;
 constexpr int kCapNnz = 1024;     // tensor entries per block (A and B separately)
 constexpr int kCapSlots = 512;    // adjacency slots per block
 constexpr int kCapRows = 256;     // rows per block (one thread per row in the row stage)
+constexpr int kCapWSlots = 1024;  // W-slots per block (W_h = P2: P2 dofs coupled to the block's rows)
 
 // Persistent Krylov kernel shape.
 constexpr int kKrylovThreads = 1024;
@@ -86,6 +87,11 @@ struct egfem_tensor_s {
   int tuned_krylov_threads = 0;
   int krylov_kernel = 0;        // 0: register-resident where it fits, 1: streaming
   int device = 0;
+  // W_h = P2 (Case 1): k runs over the P2 dofs (vertices, then edges)
+  int w2 = 0;
+  int64_t n_w = 0;              // dofs of W_h (n for P1)
+  int64_t wslots = 0;           // W-slots: (row, P2 dof) couplings
+  int max_row_wslots = 0;
   // device arrays
   int32_t* rowptr = nullptr;    // [n+1]
   int32_t* col = nullptr;       // [slots]
@@ -105,6 +111,10 @@ struct egfem_tensor_s {
   double* mval = nullptr;       // [slots]
   int32_t* blk_row = nullptr;   // [row_blocks+1]
   int32_t* blk_meta = nullptr;  // [row_blocks*8]: rows, slots, A range, B range of each block
+  int32_t* wrowptr = nullptr;   // W_h = P2: [n+1] W-slot range of every row
+  int32_t* wcol = nullptr;      //   [wslots] P2 dof of every W-slot
+  uint32_t* wpq = nullptr;      //   [wslots] block-relative slots of its endpoints, p | q << 16
+  int32_t* wmeta = nullptr;     //   [row_blocks*2] W-slot range of every block
   int64_t row_blocks = 0;
   std::vector<int32_t> h_rowptr;  // host copy (row partitions)
   std::vector<int32_t> h_col;     // host copy (neighbour lists of a partition)

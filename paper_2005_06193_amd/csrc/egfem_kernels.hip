@@ -65,6 +65,10 @@ dev::TensorView view_of(const egfem_tensor_s* T) {
   v.kpS = T->kpS;
   v.jpS = T->jpS;
   v.kval = T->kval;
+  v.wmeta = reinterpret_cast<const int2*>(T->wmeta);
+  v.wrowptr = T->wrowptr;
+  v.wcol = T->wcol;
+  v.wpq = T->wpq;
   return v;
 }
 
@@ -118,6 +122,45 @@ __global__ __launch_bounds__(kBlockThreads) void k_jacobian(dev::TensorView T, c
   if (b < 0) return;
   dev::rowblock_jacobian<kBlockThreads, false>(T, b, u, a, a0, a0c, problem_a, dadu, dadu_2u, kval, dir,
                                                jval, dinv, L);
+}
+
+// W_h = P2 tensor action and Jacobian emission, one row block per workgroup
+// (see rowblock_action_w2 / rowblock_jacobian_w2); partial[b] = sum F_i^2.
+template <bool PROBLEM>
+__global__ __launch_bounds__(kBlockThreads) void k_action_w2(dev::TensorView T, const double* __restrict__ u,
+                                                             const double* __restrict__ delta, double alpha,
+                                                             const double* __restrict__ a, double a0c,
+                                                             const double* __restrict__ load,
+                                                             const uint8_t* __restrict__ dir,
+                                                             const double* __restrict__ kval,
+                                                             double* __restrict__ out, double* __restrict__ uout,
+                                                             double* __restrict__ partial) {
+  __shared__ dev::ActionLdsW L;
+  __shared__ double sh4[4];
+  const int64_t b = xcd_block(blockIdx.x, T.nblk);
+  if (b < 0) return;
+  double sq = 0.0;
+  dev::rowblock_action_w2<kBlockThreads, PROBLEM>(T, b, u, delta, alpha, a, a0c, load, dir, kval, out, uout, sq,
+                                                  L);
+  if (PROBLEM && partial) {
+    const double tot = block_sum256(sq, sh4);
+    if (threadIdx.x == 0) partial[b] = tot;
+  }
+}
+
+__global__ __launch_bounds__(kBlockThreads) void k_jacobian_w2(dev::TensorView T, const double* __restrict__ u,
+                                                               const double* __restrict__ a,
+                                                               const double* __restrict__ a0, double a0c,
+                                                               int problem_a, const double* __restrict__ dadu,
+                                                               int dadu_2u, const double* __restrict__ kval,
+                                                               const uint8_t* __restrict__ dir,
+                                                               double* __restrict__ jval,
+                                                               double* __restrict__ dinv) {
+  __shared__ dev::RowBlockLdsW L;
+  const int64_t b = xcd_block(blockIdx.x, T.nblk);
+  if (b < 0) return;
+  dev::rowblock_jacobian_w2<kBlockThreads>(T, b, u, a, a0, a0c, problem_a, dadu, dadu_2u, kval, dir, jval, dinv,
+                                           L);
 }
 
 // Per-workgroup partial sums of (x_i - u_i)^2 and x_i^2 (grid-stride rows):
@@ -294,12 +337,18 @@ inline unsigned grid1d(int64_t n, int bs = kBlockThreads) { return (unsigned)((n
 // Number of block runs (workgroups) of the action kernel: the handle's
 // tuned target (0 = one block per workgroup), at least one block per run.
 int64_t action_runs(const egfem_tensor_s* T) {
+  if (T->w2) return std::max<int64_t>(1, T->row_blocks);
   const int64_t target = T->action_runs_target > 0 ? (int64_t)T->action_runs_target : T->row_blocks;
   return std::max<int64_t>(1, std::min<int64_t>(T->row_blocks, target));
 }
 
 hipError_t launch_action_raw(const egfem_tensor_s* T, const double* u, const double* a, double* r,
                              hipStream_t st) {
+  if (T->w2) {
+    hipLaunchKernelGGL(k_action_w2<false>, dim3(xcd_grid(T->row_blocks)), dim3(kBlockThreads), 0, st, view_of(T),
+                       u, nullptr, 0.0, a, 0.0, nullptr, nullptr, nullptr, r, nullptr, nullptr);
+    return hipGetLastError();
+  }
   const int64_t nrun = action_runs(T);
   auto kern = T->action_pipe ? k_action<false, true> : k_action<false, false>;
   hipLaunchKernelGGL(kern, dim3(xcd_grid(nrun)), dim3(kBlockThreads), 0, st, view_of(T), nrun, u, nullptr, 0.0,
@@ -310,6 +359,12 @@ hipError_t launch_action_raw(const egfem_tensor_s* T, const double* u, const dou
 hipError_t launch_action_problem(const egfem_tensor_s* T, const ProblemView& pv, const double* u,
                                  const double* delta, double alpha, double* uout, double* F,
                                  double* partial, hipStream_t st) {
+  if (T->w2) {
+    hipLaunchKernelGGL(k_action_w2<true>, dim3(xcd_grid(T->row_blocks)), dim3(kBlockThreads), 0, st, view_of(T),
+                       u, delta, alpha, pv.a0, pv.a0c, pv.load, pv.dir, pv.addK ? T->kval : nullptr, F, uout,
+                       partial);
+    return hipGetLastError();
+  }
   const int64_t nrun = action_runs(T);
   auto kern = T->action_pipe ? k_action<true, true> : k_action<true, false>;
   hipLaunchKernelGGL(kern, dim3(xcd_grid(nrun)), dim3(kBlockThreads), 0, st, view_of(T), nrun, u, delta, alpha,
@@ -321,6 +376,11 @@ hipError_t launch_jacobian(const egfem_tensor_s* T, const double* u, const doubl
                            const double* a0, double a0c, int use_problem_a, const double* dadu,
                            int dadu_2u, int addK, const uint8_t* dir, double* jval, double* dinv,
                            hipStream_t st) {
+  if (T->w2) {
+    hipLaunchKernelGGL(k_jacobian_w2, dim3(xcd_grid(T->row_blocks)), dim3(kBlockThreads), 0, st, view_of(T), u, a,
+                       a0, a0c, use_problem_a, dadu, dadu_2u, addK ? T->kval : nullptr, dir, jval, dinv);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_jacobian, dim3(xcd_grid(T->row_blocks)), dim3(kBlockThreads), 0, st,
                      view_of(T), u, a, a0, a0c, use_problem_a, dadu, dadu_2u,
                      addK ? T->kval : nullptr, dir, jval, dinv);
