@@ -376,6 +376,44 @@ def picard_suite(T, p, reps: int = 3):
             "cg_kernel": "register-resident" if st.krylov_kernels == 1 else "streaming"}
 
 
+def p2_suite(n: int, shape: dict, reps: int = 3):
+    """The headline workload with the coefficient on W_h = P2 (Case 1 of
+    Sec. 3.1: exact for a = 1 + u^2, so the solve is the standard Galerkin
+    one): Newton solves to 1e-10 (EW forcing) with the P1 handle's Krylov grid."""
+    import torch
+    import paper_2005_06193_amd as eg
+    import workloads as W
+    wl = W.nonlinear_diffusion_2d(n)
+    T = eg.Tensor.from_mesh(wl.mesh, wl.form, wspace=eg.W_P2)
+    T.set_shape(krylov_blocks=shape["krylov_blocks"], krylov_threads=shape["krylov_threads"],
+                krylov_kernel=shape["krylov_kernel"])
+    dirm = torch.tensor(wl.mesh.dirichlet, dtype=torch.uint8, device="cuda")
+    load = T.matvec(torch.tensor(wl.f, dtype=torch.float64, device="cuda"), "M")
+    p = eg.Problem(T.n, load, dirm)
+    u = torch.zeros(T.n, dtype=torch.float64, device="cuda")
+    opts = eg.NewtonOptions(tol=wl.tol, forcing=1)
+    T.newton(p, u, opts)                                       # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for _ in range(reps):
+        u.zero_()
+        stats.append(T.newton(p, u, opts))
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    u.zero_()
+    st = T.newton(p, u, eg.NewtonOptions(tol=wl.tol, forcing=1, timing=1))
+    info = T.info
+    T.close()
+    return {"workload": f"nonlinear_diffusion_2d_{n}x{n}_p1_coefficient_p2", "n_w": info.n_w,
+            "tensor_nnz": info.nnz, "converged": all(x.status == 0 for x in stats),
+            "ms_per_solve": el * 1e3, "solves_per_s": 1.0 / el,
+            "newton_iters": st.newton_iters, "krylov_iters": st.krylov_iters,
+            "action_us_per_launch": 1e3 * st.t_action_ms / max(st.n_action, 1),
+            "jacobian_us_per_launch": 1e3 * st.t_jacobian_ms / max(st.n_jacobian, 1),
+            "action_entries_per_s": info.nnz / (st.t_action_ms / max(st.n_action, 1) * 1e-3)}
+
+
 def burgers_suite(n: int = 256, reps: int = 2):
     """The Burgers experiment of Sec. 5.2 (nu = 1, T = 1, dt = 1e-2: 100
     semi-implicit steps) on the 2D n x n mesh, tensor and group formulations."""
@@ -489,6 +527,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the 3D adjoint form")
     ap.add_argument("--no-picard", action="store_true", help="skip the Picard iteration")
     ap.add_argument("--no-burgers", action="store_true", help="skip the Burgers time stepping")
+    ap.add_argument("--no-p2", action="store_true", help="skip the W_h = P2 coefficient solves")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -559,6 +598,7 @@ def main():
     adjoint = None if args.no_adjoint else adjoint_suite()
     picard = None if args.no_picard else picard_suite(T, p)
     burgers = None if args.no_burgers else burgers_suite(args.n)
+    p2 = None if args.no_p2 else p2_suite(args.n, tuned["shape"])
 
     if args.copy_probe:
         src = torch.ones(1 << 25, dtype=torch.float64, device="cuda")
@@ -595,6 +635,7 @@ def main():
         "adjoint": adjoint,
         "picard": picard,
         "burgers": burgers,
+        "p2_coefficient": p2,
         "cpu_baseline": cpu,
     }
     if cpu:

@@ -554,7 +554,8 @@ class Tensor:
         candidates on this tensor; with `cache` (a JSON path) reuse/store the
         choice keyed by the tensor's sizes."""
         import json
-        key = f"d{self.info.dim}-f{self.info.form}-n{self.n}-z{self.info.nnz}-s{self.info.slots}"
+        key = (f"d{self.info.dim}-f{self.info.form}-w{self.info.wspace}-n{self.n}-z{self.info.nnz}"
+               f"-s{self.info.slots}")
         if cache and os.path.exists(cache):
             with open(cache) as fh:
                 db = json.load(fh)
