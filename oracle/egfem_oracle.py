@@ -30,6 +30,9 @@ Finite Element Method", arXiv 2005.06193):
   approach, re-integrating the nonlinear term by quadrature every iteration.
 * Sec. 3.1 Case 1 / Example exact_egfem: W_h = P2 makes the reformulation
   exact (EGFEM(P2) == SGA for the u^2 nonlinearity).
+* Sec. 3.1 Case 3: W_h = I_k, the coefficient carried at the points of a
+  quadrature rule (Pi_u evaluates the P1 iterate there); with a rule exact for
+  the integrand this is again the standard Galerkin approach.
 * Sec. 5.2, Burgers' equation: the convection tensor
   N_ijk = int phi_k phi_j (d_1 + d_2) phi_i and the semi-implicit time step
   (M + dt nu K) u^{n+1} = M u^n + dt (1/2 N:(u^n (x) u^n) + d^{n+1}), in the
@@ -727,6 +730,86 @@ def jacobian_p2(q: ProblemP2, u: np.ndarray) -> sp.csr_matrix:
 def newton_p2(q: ProblemP2, tol=1e-13, max_iter=50):
     return newton(q.base, None, tol, max_iter, residual_fn=lambda v: residual_p2(q, v),
                   jacobian_fn=lambda v: jacobian_p2(q, v))
+
+
+# ----------------------------------------------------------------------------
+# EGFEM with W_h = I_k, the quadrature-point space (Case 3 of Sec. 3.1)
+# ----------------------------------------------------------------------------
+def iq_rule(dim: int):
+    """The fixed quadrature rule whose points carry the coefficient: barycentric
+    points [Q, dim+1] and weights [Q] relative to |e|.
+      1D: 2-point Gauss-Legendre, x = 1/2 -+ 1/(2 sqrt 3), weights 1/2 (degree 3);
+      2D: the 3 interior points with barycentrics (2/3, 1/6, 1/6) and permutations,
+          weights 1/3 (degree 2);
+      3D: the 4 points with barycentrics (a, b, b, b) and permutations,
+          a = (5 + 3 sqrt 5) / 20, b = (5 - sqrt 5) / 20, weights 1/4 (degree 2)."""
+    if dim == 1:
+        x = 0.5 - 0.5 / math.sqrt(3.0), 0.5 + 0.5 / math.sqrt(3.0)
+        lam = np.array([[1.0 - x[0], x[0]], [1.0 - x[1], x[1]]])
+        return lam, np.array([0.5, 0.5])
+    if dim == 2:
+        lam = np.full((3, 3), 1.0 / 6.0)
+        np.fill_diagonal(lam, 2.0 / 3.0)
+        return lam, np.full(3, 1.0 / 3.0)
+    a = (5.0 + 3.0 * math.sqrt(5.0)) / 20.0
+    b = (5.0 - math.sqrt(5.0)) / 20.0
+    lam = np.full((4, 4), b)
+    np.fill_diagonal(lam, a)
+    return lam, np.full(4, 0.25)
+
+
+@dataclass
+class IQSpace:
+    n_u: int
+    n_w: int                   # cells * points: dof k = e * Q + q
+    lam: np.ndarray            # [Q, d+1] barycentrics of the points
+    wts: np.ndarray            # [Q] weights relative to |e|
+    Pi: sp.csr_matrix          # (Pi_u)_kj = phi_j(x_k): evaluation of the P1 function at the points
+
+
+def iq_space(coords, cells) -> IQSpace:
+    n = coords.shape[0]
+    dim = coords.shape[1]
+    lam, wts = iq_rule(dim)
+    E, Q, nl = cells.shape[0], lam.shape[0], dim + 1
+    rows = np.repeat(np.arange(E * Q), nl)
+    cols = np.repeat(cells, Q, axis=0).ravel()
+    vals = np.tile(lam.ravel(), E)
+    Pi = sp.coo_matrix((vals, (rows, cols)), shape=(E * Q, n)).tocsr()
+    return IQSpace(n, E * Q, lam, wts, Pi)
+
+
+def tensor_iq(coords, cells, form: int, drop_rel: float = DROP_REL):
+    """T_ijk = w_q |e| grad phi_j . grad phi_i (x_q)   (stiffness) or
+    T_ijk = w_q |e| phi_j(x_q) phi_i(x_q)               (mass), k = (e, q):
+    the trilinear forms with eta_k the quadrature functional at x_q.  Returns
+    (tensor with n = n_w, space)."""
+    W = iq_space(coords, cells)
+    dim = coords.shape[1]
+    det, G = element_geometry(coords, cells)
+    vol = det / math.factorial(dim)
+    nl, Q = dim + 1, W.lam.shape[0]
+    if form == FORM_STIFF:
+        GG = np.einsum("ead,ebd->eab", G, G)
+        Te = vol[:, None, None, None] * GG[:, :, :, None] * W.wts[None, None, None, :]
+    elif form == FORM_MASS:
+        LL = np.einsum("q,qa,qb->abq", W.wts, W.lam, W.lam)
+        Te = vol[:, None, None, None] * LL[None]
+    else:
+        raise ValueError("unknown form")
+    ai, bi, qi = np.meshgrid(np.arange(nl), np.arange(nl), np.arange(Q), indexing="ij")
+    E = cells.shape[0]
+    I = cells[:, ai.ravel()].ravel().astype(np.int64)
+    J = cells[:, bi.ravel()].ravel().astype(np.int64)
+    K = (np.arange(E)[:, None] * Q + qi.ravel()[None, :]).ravel().astype(np.int64)
+    return _merge_coo3(W.n_w, I, J, K, Te.reshape(-1), drop_rel), W
+
+
+def build_problem_iq(p: Problem) -> ProblemP2:
+    """The problem with the coefficient on I_k: residual_p2 / jacobian_p2 /
+    newton_p2 apply unchanged (they use only Pi and the tensor)."""
+    T, W = tensor_iq(p.coords, p.cells, p.form)
+    return ProblemP2(p, W, T.i, T.j, T.k, T.v)
 
 
 # ----------------------------------------------------------------------------

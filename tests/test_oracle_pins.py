@@ -614,3 +614,45 @@ def test_burgers_manufactured_solution():
         assert 3.0 < errs[16, group] / errs[32, group] < 5.0
     # interpolating u^2 onto P1 changes the result at the discretisation-error level only
     assert abs(errs[32, True] - errs[32, False]) < 0.05 * errs[32, False]
+
+
+# ----------------------------------------------------------------------------
+# W_h = I_k, the quadrature-point coefficient space (Case 3 of Sec. 3.1)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("dim,degree", [(1, 3), (2, 2), (3, 2)])
+def test_iq_rule_exact_for_its_degree(dim, degree):
+    lam, wts = O.iq_rule(dim)
+    assert abs(wts.sum() - 1.0) < 1e-15 and np.allclose(lam.sum(axis=1), 1.0, atol=1e-15)
+    for alpha in itertools.product(range(degree + 1), repeat=dim + 1):
+        if sum(alpha) > degree:
+            continue
+        num = np.sum(wts * np.prod(lam ** np.array(alpha), axis=1))      # relative to |e|
+        ex = float(_int_monomial(alpha, Fraction(1), dim))
+        assert abs(num - ex) < 1e-15, (alpha, num, ex)
+    # and not exact one degree higher (a plausible mistake in the points shows here)
+    hi = [a for a in itertools.product(range(degree + 2), repeat=dim + 1) if sum(a) == degree + 1]
+    errs = [abs(np.sum(wts * np.prod(lam ** np.array(a), axis=1)) - float(_int_monomial(a, Fraction(1), dim)))
+            for a in hi]
+    assert max(errs) > 1e-6
+
+
+def test_egfem_iq_equals_sga_and_p2():
+    """With a rule exact for (a0 + u_h^2) grad u_h . grad phi_i the quadrature
+    space reproduces the standard Galerkin approach, like W_h = P2."""
+    for dim, n in [(1, 16), (2, 6), (3, 3)]:
+        p = _small_problem(dim, n, O.FORM_STIFF)
+        q = O.build_problem_iq(p)
+        rng = np.random.default_rng(9)
+        u = rng.uniform(-1, 1, p.n)
+        u[p.dirichlet] = 0
+        Fs = O.sga_residual(p, u)
+        assert np.abs(O.residual_p2(q, u) - Fs).max() <= 1e-13 * np.abs(Fs).max()
+        Js = O.sga_jacobian(p, u)
+        assert abs(O.jacobian_p2(q, u) - Js).max() <= 1e-13 * abs(Js).max()
+        u1, _ = O.newton_p2(q, tol=1e-14)
+        u2, _ = O.newton_p2(O.build_problem_p2(p), tol=1e-14)
+        assert np.linalg.norm(u1 - u2) <= 1e-13 * np.linalg.norm(u2)
+        # the quadrature functionals sum to the element volumes
+        T, Wsp = O.tensor_iq(p.coords, p.cells, O.FORM_STIFF)
+        assert Wsp.n_w == p.cells.shape[0] * Wsp.lam.shape[0]
+        assert np.allclose(np.asarray(Wsp.Pi.sum(axis=1)).ravel(), 1.0)
