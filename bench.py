@@ -376,15 +376,21 @@ def picard_suite(T, p, reps: int = 3):
             "cg_kernel": "register-resident" if st.krylov_kernels == 1 else "streaming"}
 
 
-def p2_suite(n: int, shape: dict, reps: int = 3):
+def wspace_suite(n: int, shape: dict) -> dict:
+    import paper_2005_06193_amd as eg
+    return {"p2": p2_suite(n, shape, eg.W_P2), "iq": p2_suite(n, shape, eg.W_IQ)}
+
+
+def p2_suite(n: int, shape: dict, wspace: int, reps: int = 3):
     """The headline workload with the coefficient on W_h = P2 (Case 1 of
-    Sec. 3.1: exact for a = 1 + u^2, so the solve is the standard Galerkin
-    one): Newton solves to 1e-10 (EW forcing) with the P1 handle's Krylov grid."""
+    Sec. 3.1) or on the quadrature points I_k (Case 3); both are exact for
+    a = 1 + u^2, so the solve is the standard Galerkin one.  Newton solves to
+    1e-10 (EW forcing) with the P1 handle's Krylov grid."""
     import torch
     import paper_2005_06193_amd as eg
     import workloads as W
     wl = W.nonlinear_diffusion_2d(n)
-    T = eg.Tensor.from_mesh(wl.mesh, wl.form, wspace=eg.W_P2)
+    T = eg.Tensor.from_mesh(wl.mesh, wl.form, wspace=wspace)
     T.set_shape(krylov_blocks=shape["krylov_blocks"], krylov_threads=shape["krylov_threads"],
                 krylov_kernel=shape["krylov_kernel"])
     dirm = torch.tensor(wl.mesh.dirichlet, dtype=torch.uint8, device="cuda")
@@ -405,7 +411,8 @@ def p2_suite(n: int, shape: dict, reps: int = 3):
     st = T.newton(p, u, eg.NewtonOptions(tol=wl.tol, forcing=1, timing=1))
     info = T.info
     T.close()
-    return {"workload": f"nonlinear_diffusion_2d_{n}x{n}_p1_coefficient_p2", "n_w": info.n_w,
+    name = {eg.W_P2: "p2", eg.W_IQ: "quadrature_points"}[wspace]
+    return {"workload": f"nonlinear_diffusion_2d_{n}x{n}_p1_coefficient_{name}", "n_w": info.n_w,
             "tensor_nnz": info.nnz, "converged": all(x.status == 0 for x in stats),
             "ms_per_solve": el * 1e3, "solves_per_s": 1.0 / el,
             "newton_iters": st.newton_iters, "krylov_iters": st.krylov_iters,
@@ -527,7 +534,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the 3D adjoint form")
     ap.add_argument("--no-picard", action="store_true", help="skip the Picard iteration")
     ap.add_argument("--no-burgers", action="store_true", help="skip the Burgers time stepping")
-    ap.add_argument("--no-p2", action="store_true", help="skip the W_h = P2 coefficient solves")
+    ap.add_argument("--no-p2", action="store_true", help="skip the W_h = P2 / I_k coefficient solves")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -598,7 +605,7 @@ def main():
     adjoint = None if args.no_adjoint else adjoint_suite()
     picard = None if args.no_picard else picard_suite(T, p)
     burgers = None if args.no_burgers else burgers_suite(args.n)
-    p2 = None if args.no_p2 else p2_suite(args.n, tuned["shape"])
+    p2 = None if args.no_p2 else wspace_suite(args.n, tuned["shape"])
 
     if args.copy_probe:
         src = torch.ones(1 << 25, dtype=torch.float64, device="cuda")
@@ -635,7 +642,7 @@ def main():
         "adjoint": adjoint,
         "picard": picard,
         "burgers": burgers,
-        "p2_coefficient": p2,
+        "coefficient_spaces": p2,
         "cpu_baseline": cpu,
     }
     if cpu:

@@ -76,9 +76,14 @@ enum egfem_form {
 
 enum egfem_wspace {
   EGFEM_W_P1 = 0,            /* W_h = V_h = P1 (Case 2 of Sec. 3.1, the group FEM choice) */
-  EGFEM_W_P2 = 1             /* W_h = P2 on the same mesh with Pi_u the P2 interpolation of the
+  EGFEM_W_P2 = 1,            /* W_h = P2 on the same mesh with Pi_u the P2 interpolation of the
                                 P1 iterate (Case 1 of Sec. 3.1): for a = a0 + u^2 the coefficient
                                 is then exact and EGFEM coincides with the standard Galerkin method */
+  EGFEM_W_IQ = 2             /* W_h = I_k (Case 3 of Sec. 3.1): the coefficient lives at the points
+                                of a fixed quadrature rule in every cell (1D: 2-point Gauss; 2D: the
+                                3 points with barycentrics (2/3,1/6,1/6); 3D: the 4 points (a,b,b,b),
+                                a = (5+3 sqrt 5)/20, b = (5-sqrt 5)/20; equal weights), Pi_u evaluates
+                                the P1 iterate there; the stiffness form is then again exact */
 };
 
 /* ------------------------------------------------------------------------
@@ -112,15 +117,18 @@ int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords,
  * (vertex lambda(2 lambda - 1), edge midpoint 4 lambda_x lambda_y); k runs
  * over the n_w = n_nodes + n_edges P2 dofs: the vertices, then the edges in
  * ascending (smaller vertex id, larger vertex id) order (Sec. 3.1, Case 1;
- * Sec. 3.2 for Pi_u).  On such a handle:
+ * Sec. 3.2 for Pi_u).  With EGFEM_W_IQ, k = e * Q + q runs over the Q points
+ * of every cell e (n_w = n_cells * Q) and T_ijk = w_q |e| grad phi_j . grad
+ * phi_i (stiffness) or w_q |e| phi_j(x_q) phi_i(x_q) (mass), (Pi_u u)_k =
+ * u_h(x_q) (Sec. 3.1, Case 3).  On such a handle:
  *  - every a / dadu argument of egfem_residual and egfem_jacobian is a vector
- *    over the P2 dofs (length n_w), and the second Jacobian term becomes
+ *    over the dofs of W_h (length n_w), and the second Jacobian term becomes
  *    sum_k (sum_j' T_ij'k u_j') dadu_k (Pi_u)_kj;
  *  - the problem-level calls (problem residual / Jacobian, Newton, Picard)
- *    use a = Pi_u a0 + (Pi_u u)^2 at the P2 dofs, a' = 2 Pi_u u;
+ *    use a = Pi_u a0 + (Pi_u u)^2 at the dofs of W_h, a' = 2 Pi_u u;
  *  - egfem_mode3, egfem_adjoint, the batched form and egfem_burgers return
  *    EGFEM_ERR_ARG; the convection form is not available (EGFEM_ERR_ARG).
- * Row blocks additionally hold at most 1024 (row, P2 dof) couplings. */
+ * Row blocks additionally hold at most 1024 (row, W_h dof) couplings. */
 int egfem_build_tensor_w(int dim, int64_t n_nodes, const double* coords,
                          int64_t n_cells, const int32_t* cells, int form, int wspace,
                          double drop_rel, egfem_tensor_t* out);
@@ -145,7 +153,7 @@ typedef struct {
   const int32_t* col;        /* device [slots], ascending within a row */
   const double* kval;        /* device [slots] stiffness matrix values */
   const double* mval;        /* device [slots] mass matrix values */
-  int wspace;                /* EGFEM_W_P1 or EGFEM_W_P2 */
+  int wspace;                /* EGFEM_W_P1, EGFEM_W_P2 or EGFEM_W_IQ */
   int64_t n_w;               /* dofs of W_h (n_nodes for P1) */
 } egfem_info;
 

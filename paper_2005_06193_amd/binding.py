@@ -37,6 +37,7 @@ FORM_MASS = 1
 FORM_CONV = 2
 W_P1 = 0
 W_P2 = 1
+W_IQ = 2
 HIST = 64
 
 

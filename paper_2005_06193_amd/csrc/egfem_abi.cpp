@@ -149,7 +149,7 @@ void egfem_tensor_destroy(egfem_tensor_t T) {
   free_workspace(T->ws);
   void* ptrs[] = {T->rowptr, T->col,  T->diag,    T->tperm,    T->kptrA, T->kA,   T->vA,   T->kS,
                   T->kpS,    T->kval, T->mval,    T->blk_row,  T->blk_meta, T->wrowptr, T->wcol, T->wpq,
-                  T->wmeta};
+                  T->wmeta,  T->wpq2, T->wqi,       T->qlam};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (!T->symmetric) {
@@ -179,7 +179,7 @@ int egfem_tensor_info(egfem_tensor_t T, egfem_info* info) {
   info->col = T->col;
   info->kval = T->kval;
   info->mval = T->mval;
-  info->wspace = T->w2 ? EGFEM_W_P2 : EGFEM_W_P1;
+  info->wspace = T->w2;   // EGFEM_W_P1 / EGFEM_W_P2 / EGFEM_W_IQ
   info->n_w = T->n_w;
   return EGFEM_OK;
 }
@@ -225,7 +225,7 @@ int egfem_jacobian(egfem_tensor_t T, const double* u, const double* a, const dou
 
 int egfem_mode3(egfem_tensor_t T, const double* w, const double* u, double* out, void* stream) {
   if (!T || !w || !u || !out) return fail(EGFEM_ERR_ARG, "null argument");
-  if (T->w2) return fail(EGFEM_ERR_ARG, "mode-3 contraction is not available for W_h = P2 handles");
+  if (T->w2) return fail(EGFEM_ERR_ARG, "mode-3 contraction is not available for handles with W_h != P1");
   if (out == w || out == u) return fail(EGFEM_ERR_ARG, "out must not alias w or u");
   int rc = ensure_workspace(T);
   if (rc != EGFEM_OK) return rc;
@@ -622,7 +622,7 @@ int egfem_adjoint(egfem_tensor_t T, const egfem_problem* p, const double* u, con
                   const egfem_newton_opts* o, double* lambda, double* grad_a0, int* krylov_iters,
                   double* relres, void* stream) {
   if (!T || !p || !u || !ubar || !lambda) return fail(EGFEM_ERR_ARG, "null argument");
-  if (T->w2) return fail(EGFEM_ERR_ARG, "the adjoint is not available for W_h = P2 handles");
+  if (T->w2) return fail(EGFEM_ERR_ARG, "the adjoint is not available for handles with W_h != P1");
   if (lambda == u || lambda == ubar || (grad_a0 && (grad_a0 == u || grad_a0 == lambda)))
     return fail(EGFEM_ERR_ARG, "outputs must not alias inputs");
   egfem_newton_opts opts;

@@ -309,7 +309,7 @@ int egfem_batch_create(int count, const egfem_tensor_t* Ts, const egfem_problem*
     return fail(EGFEM_ERR_ARG, "invalid Newton options");
   for (int m = 0; m < count; ++m) {
     if (!Ts[m] || !us[m]) return fail(EGFEM_ERR_ARG, "null handle or solution buffer");
-    if (Ts[m]->w2) return fail(EGFEM_ERR_ARG, "the batched form is not available for W_h = P2 handles");
+    if (Ts[m]->w2) return fail(EGFEM_ERR_ARG, "the batched form is not available for handles with W_h != P1");
     for (int q = 0; q < m; ++q)
       if (Ts[q] == Ts[m]) return fail(EGFEM_ERR_ARG, "a handle appears twice in the batch");
   }

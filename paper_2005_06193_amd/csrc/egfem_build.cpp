@@ -10,6 +10,12 @@
 //                         = sum_e (sum_d d_d lambda_i) M^e_jk      (gradient constant per cell)
 // K_ij = sum_e |e| grad phi_j . grad phi_i,  M_ij = sum_e |e| (1 + delta_ij) / ((d+1)(d+2)).
 //
+// W_h = I_k (Case 3 of Sec. 3.1): k = e * Q + q runs over the points of a fixed
+// quadrature rule in every cell, eta_k is the functional f -> w_q |e| f(x_q):
+//   stiffness T_ijk = w_q |e| grad phi_j . grad phi_i,  mass T_ijk = w_q |e| phi_j(x_q) phi_i(x_q);
+// the rule is 2-point Gauss in 1D and the degree-2 interior rules with 3 (2D)
+// and 4 (3D) points.
+//
 // W_h = P2 (Case 1 of Sec. 3.1; egfem_build_tensor_w): k runs over the P2 dofs
 // (vertices 0..N-1, then the edges in ascending (min, max) vertex order) with
 // eta_k the P2 nodal basis: vertex lambda(2 lambda - 1), edge 4 lambda_x lambda_y;
@@ -147,10 +153,39 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
   if (dim < 1 || dim > 3) return fail(EGFEM_ERR_ARG, "dim must be 1, 2 or 3");
   if (form != EGFEM_FORM_STIFF && form != EGFEM_FORM_MASS && form != EGFEM_FORM_CONV)
     return fail(EGFEM_ERR_ARG, "unknown form");
-  if (wspace != EGFEM_W_P1 && wspace != EGFEM_W_P2) return fail(EGFEM_ERR_ARG, "unknown W space");
-  if (wspace == EGFEM_W_P2 && form == EGFEM_FORM_CONV)
+  if (wspace != EGFEM_W_P1 && wspace != EGFEM_W_P2 && wspace != EGFEM_W_IQ)
+    return fail(EGFEM_ERR_ARG, "unknown W space");
+  if (wspace != EGFEM_W_P1 && form == EGFEM_FORM_CONV)
     return fail(EGFEM_ERR_ARG, "the convection form is built with W_h = P1 only");
-  const bool w2 = (wspace == EGFEM_W_P2);
+  const bool w2 = (wspace != EGFEM_W_P1);     // a coefficient space with W-slots
+  const bool wq = (wspace == EGFEM_W_IQ);
+  // quadrature rule of W_h = I_k: barycentrics (padded to 4) and weights / |e|
+  int nq = 0;
+  double qlam[4][4] = {{0}}, qw[4] = {0};
+  if (wq) {
+    if (dim == 1) {
+      nq = 2;
+      const double x0 = 0.5 - 0.5 / std::sqrt(3.0), x1 = 0.5 + 0.5 / std::sqrt(3.0);
+      qlam[0][0] = 1.0 - x0;
+      qlam[0][1] = x0;
+      qlam[1][0] = 1.0 - x1;
+      qlam[1][1] = x1;
+      qw[0] = qw[1] = 0.5;
+    } else if (dim == 2) {
+      nq = 3;
+      for (int q = 0; q < 3; ++q) {
+        for (int m = 0; m < 3; ++m) qlam[q][m] = (q == m) ? 2.0 / 3.0 : 1.0 / 6.0;
+        qw[q] = 1.0 / 3.0;
+      }
+    } else {
+      nq = 4;
+      const double qa = (5.0 + 3.0 * std::sqrt(5.0)) / 20.0, qb = (5.0 - std::sqrt(5.0)) / 20.0;
+      for (int q = 0; q < 4; ++q) {
+        for (int m = 0; m < 4; ++m) qlam[q][m] = (q == m) ? qa : qb;
+        qw[q] = 0.25;
+      }
+    }
+  }
   if (!coords || !cells) return fail(EGFEM_ERR_ARG, "coords/cells null");
   if (n_nodes <= 0 || n_cells <= 0) return fail(EGFEM_ERR_SHAPE, "empty mesh");
   if (n_nodes >= (int64_t(1) << 31) || n_cells >= (int64_t(1) << 31))
@@ -222,8 +257,9 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
         ++t;
       }
   }
+  if (wq && n_cells * nq >= (int64_t(1) << 31)) return fail(EGFEM_ERR_SHAPE, "too many quadrature points");
   std::vector<int64_t> ekeys;   // min * N + max of every edge
-  if (w2) {
+  if (w2 && !wq) {
     ekeys.reserve((size_t)n_cells * ne_loc);
     for (int64_t e = 0; e < n_cells; ++e) {
       const int32_t* c = cells + e * nl;
@@ -242,6 +278,8 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
   };
   std::vector<int32_t> wrowptr(w2 ? N + 1 : 0, 0), wcol;
   std::vector<uint16_t> wpl, wql;   // row-local slot positions of a W-slot's endpoints
+  std::vector<uint16_t> wpl2, wql2; // I_k: slots of the third and fourth vertex
+  std::vector<uint8_t> wqi;         // I_k: point index of a W-slot
   std::vector<int64_t> redges;
   int max_row_wslots = 0;
   col.reserve((size_t)N * (dim == 3 ? 15 : 7));
@@ -259,6 +297,88 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
     auto lidx = [&](int32_t node) {
       return (int)(std::lower_bound(cols.begin(), cols.end(), node) - cols.begin());
     };
+    if (wq) {
+      // W-slots of row i: the points of its cells (ascending cell, then point)
+      const int ncl = (int)(nptr[i + 1] - nptr[i]);
+      const int nw = ncl * nq;
+      max_row_wslots = std::max(max_row_wslots, nw);
+      acc.assign((size_t)nc * nw, 0.0);
+      present.assign((size_t)nc * nw, 0);
+      kacc.assign(nc, 0.0);
+      macc.assign(nc, 0.0);
+      for (int ce = 0; ce < ncl; ++ce) {
+        const int64_t e = ncell[nptr[i] + ce];
+        const int32_t* c = cells + e * nl;
+        const Geom& g = geo[e];
+        int a = 0;
+        while (c[a] != (int32_t)i) ++a;
+        int loc[4];
+        for (int b = 0; b < nl; ++b) loc[b] = lidx(c[b]);
+        for (int b = 0; b < nl; ++b) {
+          double gg = 0.0;
+          for (int r = 0; r < dim; ++r) gg += g.G[a][r] * g.G[b][r];
+          const double kab = g.vol * gg;
+          kacc[loc[b]] += kab;
+          macc[loc[b]] += g.vol * (a == b ? m2_diag : m2_off);
+          for (int q = 0; q < nq; ++q) {
+            const double val = (form == EGFEM_FORM_STIFF) ? qw[q] * kab
+                                                          : qw[q] * g.vol * qlam[q][a] * qlam[q][b];
+            const size_t idx = (size_t)loc[b] * nw + (size_t)ce * nq + q;
+            acc[idx] += val;
+            present[idx] = 1;
+          }
+        }
+      }
+      double rowmax = 0.0;
+      for (size_t t = 0; t < acc.size(); ++t)
+        if (present[t]) {
+          ++structural;
+          rowmax = std::max(rowmax, std::fabs(acc[t]));
+        }
+      const double thr = drop_rel * rowmax;
+      auto kept = [&](size_t t) { return present[t] && acc[t] != 0.0 && std::fabs(acc[t]) > thr; };
+      auto wdof = [&](int kc) { return (int32_t)((int64_t)ncell[nptr[i] + kc / nq] * nq + kc % nq); };
+      for (int jb = 0; jb < nc; ++jb) {
+        col.push_back(cols[jb]);
+        kval.push_back(kacc[jb]);
+        mval.push_back(macc[jb]);
+        for (int kc = 0; kc < nw; ++kc) {
+          const size_t t = (size_t)jb * nw + kc;
+          if (kept(t)) {
+            kA.push_back(wdof(kc));
+            kRel.push_back((uint16_t)kc);
+            vA.push_back(acc[t]);
+          }
+        }
+        kptrA.push_back((int32_t)kA.size());
+      }
+      for (int kc = 0; kc < nw; ++kc) {
+        const int32_t* c = cells + (int64_t)ncell[nptr[i] + kc / nq] * nl;
+        int sl[4];
+        for (int m = 0; m < 4; ++m) sl[m] = lidx(c[m < nl ? m : 0]);
+        wcol.push_back(wdof(kc));
+        wpl.push_back((uint16_t)sl[0]);
+        wql.push_back((uint16_t)sl[1]);
+        wpl2.push_back((uint16_t)sl[2]);
+        wql2.push_back((uint16_t)sl[3]);
+        wqi.push_back((uint8_t)(kc % nq));
+        for (int jb = 0; jb < nc; ++jb) {
+          const size_t t = (size_t)jb * nw + kc;
+          if (kept(t)) {
+            jB.push_back(cols[jb]);
+            jRel.push_back((uint16_t)jb);
+            vB.push_back(acc[t]);
+          }
+        }
+        jptrB.push_back((int32_t)jB.size());
+      }
+      if (col.size() >= (size_t)INT32_MAX || kA.size() >= (size_t)INT32_MAX || jB.size() >= (size_t)INT32_MAX ||
+          wcol.size() >= (size_t)INT32_MAX)
+        return fail(EGFEM_ERR_SHAPE, "more than 2^31 slots or tensor entries");
+      wrowptr[i + 1] = (int32_t)wcol.size();
+      rowptr[i + 1] = (int32_t)col.size();
+      continue;
+    }
     if (w2) {
       // W-slots of row i: its vertex dofs (the row's columns, same order),
       // then the edge dofs of its cells in ascending id
@@ -487,11 +607,12 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
   // block-relative slot of (i, j); every W-slot records the block-relative
   // slots of its two endpoints (p | q << 16; p == q for a vertex dof)
   const int64_t wslots = w2 ? (int64_t)wcol.size() : 0;
-  std::vector<uint32_t> wpq;
+  std::vector<uint32_t> wpq, wpq2;
   std::vector<int32_t> wmeta;
   if (w2) {
     jpS.assign((size_t)wslots + 1, 0);
     wpq.assign((size_t)wslots, 0);
+    if (wq) wpq2.assign((size_t)wslots, 0);
     wmeta.assign((blk.size() - 1) * 2, 0);
     for (size_t b = 0; b + 1 < blk.size(); ++b) {
       const int32_t s0 = rowptr[blk[b]], w0 = wrowptr[blk[b]];
@@ -506,6 +627,7 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
         for (int32_t w = wrowptr[i]; w < wrowptr[i + 1]; ++w) {
           for (int32_t p = jptrB[w]; p < jptrB[w + 1]; ++p) jS[p] = (uint16_t)(vb + jRel[p]);
           wpq[w] = (uint32_t)(vb + wpl[w]) | ((uint32_t)(vb + wql[w]) << 16);
+          if (wq) wpq2[w] = (uint32_t)(vb + wpl2[w]) | ((uint32_t)(vb + wql2[w]) << 16);
         }
       }
     }
@@ -563,8 +685,9 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
   T->krylov_lanes = klanes;
   T->krylov_rs = row_shape_for(max_row_slots, klanes);
   T->row_blocks = (int64_t)blk.size() - 1;
-  T->w2 = w2 ? 1 : 0;
-  T->n_w = w2 ? N + (int64_t)ekeys.size() : N;
+  T->w2 = w2 ? (wq ? 2 : 1) : 0;
+  T->n_w = wq ? n_cells * nq : (w2 ? N + (int64_t)ekeys.size() : N);
+  T->nq = nq;
   T->wslots = wslots;
   T->max_row_wslots = w2 ? max_row_wslots : max_row_slots;
   T->h_rowptr = rowptr;
@@ -595,6 +718,14 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
     if (rc == EGFEM_OK) rc = upload(wcol, &T->wcol, &bytes);
     if (rc == EGFEM_OK) rc = upload(wpq, &T->wpq, &bytes);
     if (rc == EGFEM_OK) rc = upload(wmeta, &T->wmeta, &bytes);
+  }
+  if (wq) {
+    std::vector<double> ql(16, 0.0);
+    for (int q = 0; q < nq; ++q)
+      for (int m = 0; m < 4; ++m) ql[4 * q + m] = qlam[q][m];
+    if (rc == EGFEM_OK) rc = upload(wpq2, &T->wpq2, &bytes);
+    if (rc == EGFEM_OK) rc = upload(wqi, &T->wqi, &bytes);
+    if (rc == EGFEM_OK) rc = upload(ql, &T->qlam, &bytes);
   }
   if (sym) {
     T->jptrB = T->kptrA;

@@ -65,6 +65,11 @@ struct TensorView {
   const int32_t* wrowptr;   // W-slot range of every row
   const int32_t* wcol;      // P2 dof of every W-slot
   const uint32_t* wpq;      // block-relative slots of a W-slot's endpoints, p | q << 16
+  // W_h = I_k (Case 3): a W-slot is a quadrature point of a cell of the row;
+  // wpq / wpq2 hold the slots of the cell's vertices, qlam their barycentrics
+  const uint32_t* wpq2;     // slots of the third and fourth vertex
+  const uint8_t* wqi;       // point index of every W-slot
+  const double* qlam;       // [4][4] barycentrics of the points
 };
 
 // Bounds of row block b: rows [r0, r1), slots [s0, s1), A entries [pa0, pa1),
@@ -450,7 +455,8 @@ __device__ void rowblock_jacobian(const TensorView& T, int64_t b, const double* 
 }
 
 // ---------------------------------------------------------------------------
-// W_h = P2 row-block stages (Case 1 of Sec. 3.1)
+// Row-block stages for a coefficient space W_h != V_h: WK = 1 P2 (Case 1 of
+// Sec. 3.1), WK = 2 the quadrature-point space I_k (Case 3)
 // ---------------------------------------------------------------------------
 // The coefficient lives on the P2 dofs.  Every P2 dof k coupled to row i is a
 // vertex or an edge of a cell of i, so both of its endpoints are columns of
@@ -476,7 +482,7 @@ __device__ __forceinline__ int w_hi(uint32_t pq) { return (int)(pq >> 16); }
 //   RAW:     r_i = sum_{s=(i,j)} w_j sum_{p in A(s)} v_p a_{k_p}, a given on the P2 dofs;
 //   PROBLEM: a = Pi a0 + (Pi w)^2 with w = u + alpha delta, a0 nodal (or a0c);
 //            F = r [+ K w] - load, Dirichlet rows 0, uout = w, sq += F_i^2.
-template <int NT, bool PROBLEM>
+template <int NT, bool PROBLEM, int WK>
 __device__ void rowblock_action_w2(const TensorView& T, int64_t b, const double* u, const double* delta,
                                    double alpha, const double* a, double a0c, const double* load,
                                    const uint8_t* dir, const double* kval, double* out, double* uout,
@@ -505,13 +511,20 @@ __device__ void rowblock_action_w2(const TensorView& T, int64_t b, const double*
     kp[q] = T.kpS[s];
     kv[q] = kvp[s];
   }
-  uint32_t wq[WW];
-  int wc[WW];
+  uint32_t wq[WW], wq2[WW];
+  int wc[WW], wqq[WW];
 #pragma unroll
   for (int q = 0; q < WW; ++q) {
     const int w = wm.x + clamp_hi(tid + q * NT, nw);
-    if (PROBLEM) wq[q] = T.wpq[w];
-    else wc[q] = T.wcol[w];
+    if (PROBLEM) {
+      wq[q] = T.wpq[w];
+      if (WK == 2) {
+        wq2[q] = T.wpq2[w];
+        wqq[q] = T.wqi[w];
+      }
+    } else {
+      wc[q] = T.wcol[w];
+    }
   }
   const bool has_row = tid < nr;
   const int i = m.r0 + clamp_hi(tid, nr);
@@ -553,8 +566,17 @@ __device__ void rowblock_action_w2(const TensorView& T, int64_t b, const double*
       const int t = tid + q * NT;
       if (t < nw) {
         const int p0 = w_lo(wq[q]), p1 = w_hi(wq[q]);
-        const double pw = 0.5 * (L.wS[p0] + L.wS[p1]);
-        L.aS[t] = fma(pw, pw, 0.5 * (L.zS[p0] + L.zS[p1]));
+        double pw, pz;
+        if (WK == 1) {
+          pw = 0.5 * (L.wS[p0] + L.wS[p1]);
+          pz = 0.5 * (L.zS[p0] + L.zS[p1]);
+        } else {
+          const int p2 = w_lo(wq2[q]), p3 = w_hi(wq2[q]);
+          const double* lam = T.qlam + 4 * wqq[q];
+          pw = fma(lam[3], L.wS[p3], fma(lam[2], L.wS[p2], fma(lam[1], L.wS[p1], lam[0] * L.wS[p0])));
+          pz = fma(lam[3], L.zS[p3], fma(lam[2], L.zS[p2], fma(lam[1], L.zS[p1], lam[0] * L.zS[p0])));
+        }
+        L.aS[t] = fma(pw, pw, pz);
       }
     }
     __syncthreads();
@@ -622,7 +644,7 @@ struct RowBlockLdsW {
 // k = j and 1/2 for an edge dof k with endpoint j.  Every row adds its
 // W-slots' terms to its own slots in ascending W-slot order (deterministic).
 // Dirichlet rows -> identity rows, Dirichlet columns -> 0; dinv[i] = 1 / J_ii.
-template <int NT>
+template <int NT, int WK>
 __device__ void rowblock_jacobian_w2(const TensorView& T, int64_t b, const double* u, const double* a,
                                      const double* a0, double a0c, int problem_a, const double* dadu,
                                      int dadu_2u, const double* kval, const uint8_t* dir, double* jval,
@@ -661,14 +683,18 @@ __device__ void rowblock_jacobian_w2(const TensorView& T, int64_t b, const doubl
     kpa[q] = T.kpS[s];
     kv[q] = kvp[s];
   }
-  uint32_t wq[WW];
-  int wc[WW], wbp[WW];
+  uint32_t wq[WW], wq2[WW];
+  int wc[WW], wbp[WW], wqq[WW];
 #pragma unroll
   for (int q = 0; q < WW; ++q) {
     const int w = wm.x + clamp_hi(tid + q * NT, nw);
     wq[q] = T.wpq[w];
     wc[q] = T.wcol[w];
     wbp[q] = T.jpS[w];
+    if (WK == 2) {
+      wq2[q] = T.wpq2[w];
+      wqq[q] = T.wqi[w];
+    }
   }
   const bool has_row = tid < nr;
   const int i = r0 + clamp_hi(tid, nr);
@@ -726,8 +752,17 @@ __device__ void rowblock_jacobian_w2(const TensorView& T, int64_t b, const doubl
       const int t = tid + q * NT;
       if (t < nw) {
         const int p0 = w_lo(wq[q]), p1 = w_hi(wq[q]);
-        const double pu = 0.5 * (L.uS[p0] + L.uS[p1]);
-        if (problem_a) L.aS[t] = fma(pu, pu, 0.5 * (L.zS[p0] + L.zS[p1]));
+        double pu, pz;
+        if (WK == 1) {
+          pu = 0.5 * (L.uS[p0] + L.uS[p1]);
+          pz = 0.5 * (L.zS[p0] + L.zS[p1]);
+        } else {
+          const int p2 = w_lo(wq2[q]), p3 = w_hi(wq2[q]);
+          const double* lam = T.qlam + 4 * wqq[q];
+          pu = fma(lam[3], L.uS[p3], fma(lam[2], L.uS[p2], fma(lam[1], L.uS[p1], lam[0] * L.uS[p0])));
+          pz = fma(lam[3], L.zS[p3], fma(lam[2], L.zS[p2], fma(lam[1], L.zS[p1], lam[0] * L.zS[p0])));
+        }
+        if (problem_a) L.aS[t] = fma(pu, pu, pz);
         if (dadu_2u && !dadu) L.cW[t] = 2.0 * pu;
       }
     }
@@ -759,7 +794,15 @@ __device__ void rowblock_jacobian_w2(const TensorView& T, int64_t b, const doubl
         const uint32_t pq = L.wpq[t];
         const int p0 = w_lo(pq), p1 = w_hi(pq);
         const double c = L.cW[t];
-        if (p0 == p1) {
+        if (WK == 2) {
+          // (Pi_u)_kj = lambda_j(x_q) for the cell's vertices
+          const uint32_t pq2 = T.wpq2[wm.x + t];
+          const double* lam = T.qlam + 4 * T.wqi[wm.x + t];
+          L.bacc[p0] += lam[0] * c;
+          L.bacc[p1] += lam[1] * c;
+          L.bacc[w_lo(pq2)] += lam[2] * c;
+          L.bacc[w_hi(pq2)] += lam[3] * c;
+        } else if (p0 == p1) {
           L.bacc[p0] += c;
         } else {
           L.bacc[p0] += 0.5 * c;

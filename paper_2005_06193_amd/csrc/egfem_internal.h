@@ -87,8 +87,10 @@ struct egfem_tensor_s {
   int tuned_krylov_threads = 0;
   int krylov_kernel = 0;        // 0: register-resident where it fits, 1: streaming
   int device = 0;
-  // W_h = P2 (Case 1): k runs over the P2 dofs (vertices, then edges)
+  // W_h = P2 (Case 1, w2 = 1): k runs over the P2 dofs (vertices, then edges);
+  // W_h = I_k (Case 3, w2 = 2): k runs over the quadrature points of the cells
   int w2 = 0;
+  int nq = 0;                   // I_k: points per cell
   int64_t n_w = 0;              // dofs of W_h (n for P1)
   int64_t wslots = 0;           // W-slots: (row, P2 dof) couplings
   int max_row_wslots = 0;
@@ -115,6 +117,9 @@ struct egfem_tensor_s {
   int32_t* wcol = nullptr;      //   [wslots] P2 dof of every W-slot
   uint32_t* wpq = nullptr;      //   [wslots] block-relative slots of its endpoints, p | q << 16
   int32_t* wmeta = nullptr;     //   [row_blocks*2] W-slot range of every block
+  uint32_t* wpq2 = nullptr;     // I_k: [wslots] slots of the third and fourth cell vertex
+  uint8_t* wqi = nullptr;       // I_k: [wslots] point index
+  double* qlam = nullptr;       // I_k: [4*4] barycentrics of the points
   int64_t row_blocks = 0;
   std::vector<int32_t> h_rowptr;  // host copy (row partitions)
   std::vector<int32_t> h_col;     // host copy (neighbour lists of a partition)

@@ -69,6 +69,9 @@ dev::TensorView view_of(const egfem_tensor_s* T) {
   v.wrowptr = T->wrowptr;
   v.wcol = T->wcol;
   v.wpq = T->wpq;
+  v.wpq2 = T->wpq2;
+  v.wqi = T->wqi;
+  v.qlam = T->qlam;
   return v;
 }
 
@@ -126,7 +129,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_jacobian(dev::TensorView T, c
 
 // W_h = P2 tensor action and Jacobian emission, one row block per workgroup
 // (see rowblock_action_w2 / rowblock_jacobian_w2); partial[b] = sum F_i^2.
-template <bool PROBLEM>
+template <bool PROBLEM, int WK>
 __global__ __launch_bounds__(kBlockThreads) void k_action_w2(dev::TensorView T, const double* __restrict__ u,
                                                              const double* __restrict__ delta, double alpha,
                                                              const double* __restrict__ a, double a0c,
@@ -140,14 +143,15 @@ __global__ __launch_bounds__(kBlockThreads) void k_action_w2(dev::TensorView T, 
   const int64_t b = xcd_block(blockIdx.x, T.nblk);
   if (b < 0) return;
   double sq = 0.0;
-  dev::rowblock_action_w2<kBlockThreads, PROBLEM>(T, b, u, delta, alpha, a, a0c, load, dir, kval, out, uout, sq,
-                                                  L);
+  dev::rowblock_action_w2<kBlockThreads, PROBLEM, WK>(T, b, u, delta, alpha, a, a0c, load, dir, kval, out, uout,
+                                                      sq, L);
   if (PROBLEM && partial) {
     const double tot = block_sum256(sq, sh4);
     if (threadIdx.x == 0) partial[b] = tot;
   }
 }
 
+template <int WK>
 __global__ __launch_bounds__(kBlockThreads) void k_jacobian_w2(dev::TensorView T, const double* __restrict__ u,
                                                                const double* __restrict__ a,
                                                                const double* __restrict__ a0, double a0c,
@@ -159,8 +163,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_jacobian_w2(dev::TensorView T
   __shared__ dev::RowBlockLdsW L;
   const int64_t b = xcd_block(blockIdx.x, T.nblk);
   if (b < 0) return;
-  dev::rowblock_jacobian_w2<kBlockThreads>(T, b, u, a, a0, a0c, problem_a, dadu, dadu_2u, kval, dir, jval, dinv,
-                                           L);
+  dev::rowblock_jacobian_w2<kBlockThreads, WK>(T, b, u, a, a0, a0c, problem_a, dadu, dadu_2u, kval, dir, jval,
+                                               dinv, L);
 }
 
 // Per-workgroup partial sums of (x_i - u_i)^2 and x_i^2 (grid-stride rows):
@@ -345,8 +349,9 @@ int64_t action_runs(const egfem_tensor_s* T) {
 hipError_t launch_action_raw(const egfem_tensor_s* T, const double* u, const double* a, double* r,
                              hipStream_t st) {
   if (T->w2) {
-    hipLaunchKernelGGL(k_action_w2<false>, dim3(xcd_grid(T->row_blocks)), dim3(kBlockThreads), 0, st, view_of(T),
-                       u, nullptr, 0.0, a, 0.0, nullptr, nullptr, nullptr, r, nullptr, nullptr);
+    auto kern = T->w2 == 2 ? k_action_w2<false, 2> : k_action_w2<false, 1>;
+    hipLaunchKernelGGL(kern, dim3(xcd_grid(T->row_blocks)), dim3(kBlockThreads), 0, st, view_of(T), u, nullptr,
+                       0.0, a, 0.0, nullptr, nullptr, nullptr, r, nullptr, nullptr);
     return hipGetLastError();
   }
   const int64_t nrun = action_runs(T);
@@ -360,9 +365,9 @@ hipError_t launch_action_problem(const egfem_tensor_s* T, const ProblemView& pv,
                                  const double* delta, double alpha, double* uout, double* F,
                                  double* partial, hipStream_t st) {
   if (T->w2) {
-    hipLaunchKernelGGL(k_action_w2<true>, dim3(xcd_grid(T->row_blocks)), dim3(kBlockThreads), 0, st, view_of(T),
-                       u, delta, alpha, pv.a0, pv.a0c, pv.load, pv.dir, pv.addK ? T->kval : nullptr, F, uout,
-                       partial);
+    auto kern = T->w2 == 2 ? k_action_w2<true, 2> : k_action_w2<true, 1>;
+    hipLaunchKernelGGL(kern, dim3(xcd_grid(T->row_blocks)), dim3(kBlockThreads), 0, st, view_of(T), u, delta,
+                       alpha, pv.a0, pv.a0c, pv.load, pv.dir, pv.addK ? T->kval : nullptr, F, uout, partial);
     return hipGetLastError();
   }
   const int64_t nrun = action_runs(T);
@@ -377,8 +382,9 @@ hipError_t launch_jacobian(const egfem_tensor_s* T, const double* u, const doubl
                            int dadu_2u, int addK, const uint8_t* dir, double* jval, double* dinv,
                            hipStream_t st) {
   if (T->w2) {
-    hipLaunchKernelGGL(k_jacobian_w2, dim3(xcd_grid(T->row_blocks)), dim3(kBlockThreads), 0, st, view_of(T), u, a,
-                       a0, a0c, use_problem_a, dadu, dadu_2u, addK ? T->kval : nullptr, dir, jval, dinv);
+    auto kern = T->w2 == 2 ? k_jacobian_w2<2> : k_jacobian_w2<1>;
+    hipLaunchKernelGGL(kern, dim3(xcd_grid(T->row_blocks)), dim3(kBlockThreads), 0, st, view_of(T), u, a, a0, a0c,
+                       use_problem_a, dadu, dadu_2u, addK ? T->kval : nullptr, dir, jval, dinv);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_jacobian, dim3(xcd_grid(T->row_blocks)), dim3(kBlockThreads), 0, st,

@@ -74,7 +74,7 @@ int egfem_autotune(egfem_tensor_t T, const egfem_problem* p, int what, egfem_lau
   hipStream_t st = (hipStream_t)stream;
   Workspace& W = T->ws;
   double us_action = 0.0, us_krylov = 0.0;
-  // W_h = P2 handles run one row block per workgroup: no action shape to tune
+  // handles with W_h != P1 run one row block per workgroup: no action shape to tune
   if ((what & 1) && !T->w2) {
     EGFEM_HIP_CHECK(launch_fill(W.utry, 0.5, T->n, st));
     EGFEM_HIP_CHECK(launch_fill(W.delta, 1.25, T->n, st));

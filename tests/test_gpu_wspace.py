@@ -1,7 +1,9 @@
-"""W_h = P2 (Case 1 of Sec. 3.1) on the GPU against the oracle: the P2 tensor
-entry by entry, the raw action and Jacobian with coefficients on the P2 dofs,
-the problem residual / Jacobian with a = Pi a0 + (Pi u)^2, and Newton and
-Picard solutions, which also equal the standard Galerkin (SGA) solution."""
+"""Coefficient spaces W_h != V_h on the GPU against the oracle: P2 (Case 1 of
+Sec. 3.1) and the quadrature-point space I_k (Case 3).  The tensor entry by
+entry, the raw action and Jacobian with coefficients on the dofs of W_h, the
+problem residual / Jacobian with a = Pi a0 + (Pi u)^2, and Newton and Picard
+solutions, which for the stiffness form also equal the standard Galerkin (SGA)
+solution."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -23,18 +25,25 @@ MESHES = {
 }
 
 
-def _p2(m, form):
-    print(f"p2 build dim={m.dim} n={m.n} form={form}", flush=True)
-    return eg().Tensor.from_mesh(m, form, wspace=eg().W_P2)
+SPACES = {
+    "p2": (lambda: eg().W_P2, O.tensor_p2, O.build_problem_p2),
+    "iq": (lambda: eg().W_IQ, O.tensor_iq, O.build_problem_iq),
+}
 
 
+def _p2(m, form, space="p2"):
+    print(f"{space} build dim={m.dim} n={m.n} form={form}", flush=True)
+    return eg().Tensor.from_mesh(m, form, wspace=SPACES[space][0]())
+
+
+@pytest.mark.parametrize("space", list(SPACES))
 @pytest.mark.parametrize("form", [0, 1])
 @pytest.mark.parametrize("mesh", list(MESHES))
-def test_p2_build_matches_oracle(mesh, form):
+def test_p2_build_matches_oracle(mesh, form, space):
     m = MESHES[mesh]()
-    T = _p2(m, form)
-    To, Wsp = O.tensor_p2(m.coords, m.cells, form)
-    assert T.info.wspace == 1 and T.info.n_w == Wsp.n_w
+    T = _p2(m, form, space)
+    To, Wsp = SPACES[space][1](m.coords, m.cells, form)
+    assert T.info.wspace == SPACES[space][0]() and T.info.n_w == Wsp.n_w
     assert T.info.nnz == To.nnz and T.info.structural_nnz == To.structural_nnz
     i, j, k, v = T.export()
     nw = Wsp.n_w
@@ -45,12 +54,13 @@ def test_p2_build_matches_oracle(mesh, form):
     assert np.abs(v[og] - To.v[oo]).max() <= 1e-14 * np.abs(To.v).max()
 
 
+@pytest.mark.parametrize("space", list(SPACES))
 @pytest.mark.parametrize("form", [0, 1])
 @pytest.mark.parametrize("mesh", list(MESHES))
-def test_p2_raw_action_and_jacobian(mesh, form):
+def test_p2_raw_action_and_jacobian(mesh, form, space):
     m = MESHES[mesh]()
-    T = _p2(m, form)
-    To, Wsp = O.tensor_p2(m.coords, m.cells, form)
+    T = _p2(m, form, space)
+    To, Wsp = SPACES[space][1](m.coords, m.cells, form)
     n, nw = m.n_nodes, Wsp.n_w
     rng = np.random.default_rng(17)
     u = rng.uniform(-1, 1, n)
@@ -83,12 +93,13 @@ WORKLOADS = {
 }
 
 
+@pytest.mark.parametrize("space", list(SPACES))
 @pytest.mark.parametrize("name", list(WORKLOADS))
-def test_p2_problem_residual_and_jacobian(name):
+def test_p2_problem_residual_and_jacobian(name, space):
     wl = WORKLOADS[name]()
-    T = _p2(wl.mesh, wl.form)
+    T = _p2(wl.mesh, wl.form, space)
     p = gpu_problem(T, wl)
-    q = O.build_problem_p2(O.build_problem(wl))
+    q = SPACES[space][2](O.build_problem(wl))
     u = np.random.default_rng(21).uniform(-1, 1, T.n)
     u[wl.mesh.dirichlet.astype(bool)] = 0.0
     F = T.problem_residual(p, dt(u))
@@ -101,30 +112,34 @@ def test_p2_problem_residual_and_jacobian(name):
     assert relerr(host(dinv), 1.0 / Jo.diagonal()) < 1e-12
 
 
+@pytest.mark.parametrize("space", list(SPACES))
 @pytest.mark.parametrize("name", list(WORKLOADS))
-def test_p2_newton_equals_oracle_and_sga(name):
+def test_p2_newton_equals_oracle_and_sga(name, space):
     wl = WORKLOADS[name]()
-    T = _p2(wl.mesh, wl.form)
+    T = _p2(wl.mesh, wl.form, space)
     p = gpu_problem(T, wl)
     po = O.build_problem(wl)
-    q = O.build_problem_p2(po)
+    q = SPACES[space][2](po)
     u = torch.zeros(T.n, dtype=torch.float64, device=DEV)
     st = T.newton(p, u, eg().NewtonOptions(tol=1e-14, krylov_rtol=1e-14), warn=False)
     assert st.status in (0, 4), st.status_name       # converged or at the rounding floor
     ug = host(u)
     u_p2, _ = O.newton_p2(q, tol=1e-14)
-    u_sga, _ = O.sga_newton(po, tol=1e-14)
     assert relerr(ug, u_p2) <= 1e-10
-    assert relerr(ug, u_sga) <= 1e-10
+    if space == "p2" or wl.form == 0:
+        # exact reformulations: the standard Galerkin solution
+        u_sga, _ = O.sga_newton(po, tol=1e-14)
+        assert relerr(ug, u_sga) <= 1e-10
     # certificate: the oracle's P2 residual at the GPU solution
     assert np.linalg.norm(O.residual_p2(q, ug)) <= 1e-10 * np.linalg.norm(po.d[po.free])
 
 
-def test_p2_picard_reaches_the_same_solution():
+@pytest.mark.parametrize("space", list(SPACES))
+def test_p2_picard_reaches_the_same_solution(space):
     wl = W.nonlinear_diffusion_2d(24)
-    T = _p2(wl.mesh, wl.form)
+    T = _p2(wl.mesh, wl.form, space)
     p = gpu_problem(T, wl)
-    q = O.build_problem_p2(O.build_problem(wl))
+    q = SPACES[space][2](O.build_problem(wl))
     u = torch.zeros(T.n, dtype=torch.float64, device=DEV)
     st = T.picard(p, u, eg().PicardOptions(tol=1e-13, krylov_rtol=1e-6), warn=False)
     assert st.status == 0
@@ -154,9 +169,10 @@ def test_p2_full_size_2d_256_newton():
     assert np.abs(host(F) - Fo).max() <= 1e-12 * scale
 
 
-def test_p2_deterministic_and_rejections():
+@pytest.mark.parametrize("space", list(SPACES))
+def test_p2_deterministic_and_rejections(space):
     wl = W.nonlinear_diffusion_2d(16)
-    T = _p2(wl.mesh, wl.form)
+    T = _p2(wl.mesh, wl.form, space)
     p = gpu_problem(T, wl)
     u1 = torch.zeros(T.n, dtype=torch.float64, device=DEV)
     u2 = torch.zeros(T.n, dtype=torch.float64, device=DEV)
@@ -167,10 +183,10 @@ def test_p2_deterministic_and_rejections():
     with pytest.raises(eg().EgfemError):
         T.mode3(x, x)
     with pytest.raises(eg().EgfemError):
-        eg().Tensor.from_mesh(wl.mesh, W.FORM_CONV, wspace=eg().W_P2)
+        eg().Tensor.from_mesh(wl.mesh, W.FORM_CONV, wspace=SPACES[space][0]())
     with pytest.raises(eg().EgfemError):
         eg().Tensor.from_mesh(wl.mesh, 0, wspace=7)
     with pytest.raises(eg().EgfemError):
         eg().newton_batched([T], [p], [u1])
     with pytest.raises(eg().EgfemError):
-        T.residual(x, x)      # a must live on the P2 dofs
+        T.residual(x, x)      # a must live on the dofs of W_h
