@@ -131,7 +131,7 @@ def time_solves(T, p, steps: int, warmup: int, opts):
     return t1 - t0, stats, u
 
 
-def time_action(T, reps: int, cold: bool):
+def time_action(T, reps: int, cold: bool, elementwise: bool = False):
     """Raw tensor action r = T:(u (x) a) launched back to back (warm), or with
     1 GiB read between launches so that the stream comes from HBM (cold).  The
     flush reads (a written flush leaves dirty lines whose write-back would be
@@ -143,16 +143,17 @@ def time_action(T, reps: int, cold: bool):
     u = torch.rand(n, dtype=torch.float64, device="cuda", generator=g)
     a = torch.rand(n, dtype=torch.float64, device="cuda", generator=g) + 1.0
     r = torch.empty_like(u)
+    act = T.residual_elementwise if elementwise else T.residual
     flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda") if cold else None
     for _ in range(5):
-        T.residual(u, a, r)
+        act(u, a, r)
     torch.cuda.synchronize()
     if not cold:
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(reps):
-            T.residual(u, a, r)
+            act(u, a, r)
         e1.record()
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
@@ -163,7 +164,7 @@ def time_action(T, reps: int, cold: bool):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
-        T.residual(u, a, r)
+        act(u, a, r)
         e1.record()
         torch.cuda.synchronize()
         tot += e0.elapsed_time(e1)
@@ -225,6 +226,18 @@ def tensor_action_suite():
                      "jacobian_warm_GBps": bj / (jac * 1e6),
                      "jacobian_frac": bj / (jac * 1e6) / HBM_PEAK_GBS,
                      "shape": tuned["shape"]}
+        if wl.form == W.FORM_STIFF:
+            # element-factored form of the same tensor: cells (16 B), packed K^e, incidences
+            T.attach_elements(wl.mesh.coords, wl.mesh.cells)
+            ew = time_action(T, 100, cold=False, elementwise=True)
+            ec = time_action(T, 20, cold=True, elementwise=True)
+            nl = wl.mesh.dim + 1
+            kst = ((nl * (nl + 1) // 2) + 1) & ~1
+            be = wl.mesh.n_cells * (16 + 8 * kst) + 4 * (info.n_nodes + 1) + 4 * nl * wl.mesh.n_cells \
+                + 24 * info.n_nodes
+            out[name]["element_factored"] = {"bytes": be, "warm_us": ew * 1e3, "cold_us": ec * 1e3,
+                                             "cold_GBps": be / (ec * 1e6),
+                                             "cold_speedup_vs_stream": cold / ec}
         tr = load_traffic()
         if tr:
             out[name]["action_hbm_bytes_rocprof"] = tr["tensor_action"][name]["hbm_bytes_per_launch"]

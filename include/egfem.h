@@ -177,6 +177,27 @@ int egfem_tensor_pattern(egfem_tensor_t T, int32_t* rowptr, int32_t* col);
 int egfem_residual(egfem_tensor_t T, const double* u, const double* a, double* r,
                    void* stream);
 
+/* ------------------------------------------------------------------------
+ * Element-factored form of the stiffness tensor (storage comparison): with P1
+ * coefficient functions and constant gradients, T^e_ijk = K^e_ij / (d+1) on
+ * every cell, so
+ *     (T:(u (x) a))_i = sum_{e contains i} abar_e (K^e u_e)_i,  abar_e = mean of a on e.
+ * egfem_attach_elements stores, for an EGFEM_FORM_STIFF handle with W_h = P1,
+ * the cells (4 ids each), the packed symmetric K^e and the node -> cell
+ * incidence (cell id, local index) of the same mesh; the stream format is kept.
+ *   coords, cells: host, as for egfem_build_tensor (must be the same mesh).
+ * Returns EGFEM_ERR_ARG for another form or coefficient space, EGFEM_ERR_SHAPE
+ * when the sizes differ from the handle's, EGFEM_ERR_MESH for bad cells.
+ * Synchronous.  Attaching twice replaces the data. */
+int egfem_attach_elements(egfem_tensor_t T, int dim, int64_t n_nodes, const double* coords,
+                          int64_t n_cells, const int32_t* cells);
+
+/* egfem_residual_elementwise: r = T:(u (x) a) through the element-factored
+ * form (equal to egfem_residual up to rounding).  u, a, r: device [n_nodes],
+ * r must not alias u or a.  EGFEM_ERR_ARG when no elements are attached. */
+int egfem_residual_elementwise(egfem_tensor_t T, const double* u, const double* a, double* r,
+                               void* stream);
+
 /* egfem_jacobian: emit J in the CSR pattern of T (Sec. 4, block Jacobian
  * reduced to u; no integration):
  *   J_ij = [K_ij] + sum_k T_ijk a_k + dadu_j * sum_j' T_ij'j u_j'

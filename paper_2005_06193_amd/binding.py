@@ -115,6 +115,8 @@ EXPORTS = {
                                      C.c_int, C.c_double, C.POINTER(C.c_void_p)]),
     "egfem_build_tensor_w": (C.c_int, [C.c_int, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
                                        C.c_int, C.c_int, C.c_double, C.POINTER(C.c_void_p)]),
+    "egfem_attach_elements": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),
+    "egfem_residual_elementwise": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "egfem_tensor_destroy": (None, [C.c_void_p]),
     "egfem_tensor_info": (C.c_int, [C.c_void_p, C.POINTER(_Info)]),
     "egfem_tensor_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -462,6 +464,20 @@ class Tensor:
         out = torch.empty_like(u) if out is None else out
         _check(load_library().egfem_residual(self.handle, _dptr(u, n=self.n), _dptr(a, n=self.info.n_w),
                                              _dptr(out, n=self.n), _stream()))
+        return out
+
+    def attach_elements(self, coords: np.ndarray, cells: np.ndarray):
+        """Store the element-factored form (K^e per cell) of this stiffness tensor."""
+        coords = np.ascontiguousarray(coords, dtype=np.float64)
+        cells = np.ascontiguousarray(cells, dtype=np.int32)
+        _check(load_library().egfem_attach_elements(self.handle, coords.shape[1], coords.shape[0],
+                                                    coords.ctypes.data, cells.shape[0], cells.ctypes.data))
+
+    def residual_elementwise(self, u: torch.Tensor, a: torch.Tensor, out: Optional[torch.Tensor] = None):
+        """r_i = sum_jk T_ijk u_j a_k through the element-factored form."""
+        out = torch.empty_like(u) if out is None else out
+        _check(load_library().egfem_residual_elementwise(self.handle, _dptr(u, n=self.n), _dptr(a, n=self.n),
+                                                         _dptr(out, n=self.n), _stream()))
         return out
 
     def jacobian(self, u, a, dadu=None, add_stiffness=False, dirichlet=None, out=None,

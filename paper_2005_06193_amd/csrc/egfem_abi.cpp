@@ -149,7 +149,8 @@ void egfem_tensor_destroy(egfem_tensor_t T) {
   free_workspace(T->ws);
   void* ptrs[] = {T->rowptr, T->col,  T->diag,    T->tperm,    T->kptrA, T->kA,   T->vA,   T->kS,
                   T->kpS,    T->kval, T->mval,    T->blk_row,  T->blk_meta, T->wrowptr, T->wcol, T->wpq,
-                  T->wmeta,  T->wpq2, T->wqi,       T->qlam};
+                  T->wmeta,  T->wpq2, T->wqi,       T->qlam,   T->e_cell4, T->e_kp,    T->e_nptr,
+                  T->e_inc};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (!T->symmetric) {
@@ -211,6 +212,14 @@ int egfem_residual(egfem_tensor_t T, const double* u, const double* a, double* r
   if (!T || !u || !a || !r) return fail(EGFEM_ERR_ARG, "null argument");
   if (r == u || r == a) return fail(EGFEM_ERR_ARG, "r must not alias u or a");
   EGFEM_HIP_CHECK(launch_action_raw(T, u, a, r, (hipStream_t)stream));
+  return EGFEM_OK;
+}
+
+int egfem_residual_elementwise(egfem_tensor_t T, const double* u, const double* a, double* r, void* stream) {
+  if (!T || !u || !a || !r) return fail(EGFEM_ERR_ARG, "null argument");
+  if (!T->e_kp) return fail(EGFEM_ERR_ARG, "no element data attached (egfem_attach_elements)");
+  if (r == u || r == a) return fail(EGFEM_ERR_ARG, "r must not alias u or a");
+  EGFEM_HIP_CHECK(launch_action_elementwise(T, u, a, r, (hipStream_t)stream));
   return EGFEM_OK;
 }
 

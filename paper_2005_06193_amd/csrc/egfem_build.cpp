@@ -755,3 +755,69 @@ extern "C" int egfem_build_tensor_w(int dim, int64_t n_nodes, const double* coor
                                     egfem_tensor_t* out) {
   return build_impl(dim, n_nodes, coords, n_cells, cells, form, wspace, drop_rel, out);
 }
+
+extern "C" int egfem_attach_elements(egfem_tensor_t T, int dim, int64_t n_nodes, const double* coords,
+                                     int64_t n_cells, const int32_t* cells) {
+  using namespace egfem;
+  if (!T || !coords || !cells) return fail(EGFEM_ERR_ARG, "null argument");
+  if (T->form != EGFEM_FORM_STIFF || T->w2)
+    return fail(EGFEM_ERR_ARG, "the element-factored form exists for the stiffness tensor with W_h = P1");
+  if (dim != T->dim || n_nodes != T->n || n_cells != T->n_cells)
+    return fail(EGFEM_ERR_SHAPE, "mesh sizes differ from the tensor's");
+  if (n_cells >= (int64_t(1) << 29)) return fail(EGFEM_ERR_SHAPE, "too many cells for the incidence encoding");
+  const int nl = dim + 1;
+  const int kstride = ((nl * (nl + 1) / 2) + 1) & ~1;
+  std::vector<int32_t> cell4((size_t)n_cells * 4);
+  std::vector<double> kp((size_t)n_cells * kstride, 0.0);
+  std::vector<int32_t> nptr(n_nodes + 1, 0);
+  for (int64_t e = 0; e < n_cells; ++e) {
+    const int32_t* c = cells + e * nl;
+    for (int a = 0; a < nl; ++a)
+      if (c[a] < 0 || c[a] >= n_nodes) return fail(EGFEM_ERR_MESH, "cell index out of range");
+    Geom g;
+    if (!cell_geometry(dim, coords, c, g)) return fail(EGFEM_ERR_MESH, "degenerate cell");
+    for (int m = 0; m < 4; ++m) cell4[4 * e + m] = c[m < nl ? m : 0];
+    int t = 0;
+    for (int a = 0; a < nl; ++a)
+      for (int b = a; b < nl; ++b) {
+        double gg = 0.0;
+        for (int r = 0; r < dim; ++r) gg += g.G[a][r] * g.G[b][r];
+        kp[(size_t)e * kstride + t++] = g.vol * gg;
+      }
+    for (int a = 0; a < nl; ++a) nptr[c[a] + 1]++;
+  }
+  int maxinc = 0;
+  for (int64_t i = 0; i < n_nodes; ++i) {
+    maxinc = std::max(maxinc, nptr[i + 1]);
+    nptr[i + 1] += nptr[i];
+  }
+  std::vector<int32_t> inc(nptr[n_nodes]);
+  {
+    std::vector<int32_t> fill(nptr.begin(), nptr.end() - 1);
+    for (int64_t e = 0; e < n_cells; ++e)
+      for (int a = 0; a < nl; ++a) inc[fill[cells[e * nl + a]]++] = (int32_t)((e << 2) | a);
+  }
+  // replace previous data
+  for (void* p : {(void*)T->e_cell4, (void*)T->e_kp, (void*)T->e_nptr, (void*)T->e_inc})
+    if (p) hipFree(p);
+  T->e_cell4 = nullptr;
+  T->e_kp = nullptr;
+  T->e_nptr = nullptr;
+  T->e_inc = nullptr;
+  int64_t bytes = 0;
+  int32_t* c4 = nullptr;
+  int rc = upload(cell4, &c4, &bytes);
+  if (rc == EGFEM_OK) rc = upload(kp, &T->e_kp, &bytes);
+  if (rc == EGFEM_OK) rc = upload(nptr, &T->e_nptr, &bytes);
+  if (rc == EGFEM_OK) rc = upload(inc, &T->e_inc, &bytes);
+  T->e_cell4 = reinterpret_cast<int4*>(c4);
+  if (rc != EGFEM_OK) return rc;
+  int lanes = 2;
+  while (lanes < maxinc && lanes < 64) lanes *= 2;
+  T->e_lanes = lanes;
+  T->e_kstride = kstride;
+  T->e_cells = n_cells;
+  T->device_bytes += bytes;
+  return EGFEM_OK;
+}
+

@@ -117,6 +117,14 @@ struct egfem_tensor_s {
   int32_t* wcol = nullptr;      //   [wslots] P2 dof of every W-slot
   uint32_t* wpq = nullptr;      //   [wslots] block-relative slots of its endpoints, p | q << 16
   int32_t* wmeta = nullptr;     //   [row_blocks*2] W-slot range of every block
+  // element-factored form of the stiffness tensor (optional)
+  int64_t e_cells = 0;
+  int e_kstride = 0;            // doubles per packed K^e (triangle of (d+1)^2, rounded to even)
+  int e_lanes = 0;              // lanes per row of the element action (power of two >= max incidence)
+  int4* e_cell4 = nullptr;      // [cells] vertex ids, padded with the first
+  double* e_kp = nullptr;       // [cells * kstride] packed K^e (row-major upper triangle)
+  int32_t* e_nptr = nullptr;    // [n+1] incidence range of every node
+  int32_t* e_inc = nullptr;     // [incidences] cell << 2 | local index
   uint32_t* wpq2 = nullptr;     // I_k: [wslots] slots of the third and fourth cell vertex
   uint8_t* wqi = nullptr;       // I_k: [wslots] point index
   double* qlam = nullptr;       // I_k: [4*4] barycentrics of the points
@@ -161,6 +169,8 @@ struct ProblemView {
 int64_t action_runs(const egfem_tensor_s* T);
 hipError_t launch_action_raw(const egfem_tensor_s* T, const double* u, const double* a, double* r,
                              hipStream_t st);
+hipError_t launch_action_elementwise(const egfem_tensor_s* T, const double* u, const double* a, double* r,
+                                     hipStream_t st);
 hipError_t launch_action_problem(const egfem_tensor_s* T, const ProblemView& pv, const double* u,
                                  const double* delta, double alpha, double* uout, double* F,
                                  double* partial, hipStream_t st);

@@ -167,6 +167,46 @@ __global__ __launch_bounds__(kBlockThreads) void k_jacobian_w2(dev::TensorView T
                                                dinv, L);
 }
 
+// Element-factored stiffness action, L lanes per row, one incident cell per
+// lane: r_i = sum_{e contains i} abar_e sum_b K^e_{a b} u_{c_b}, a = local index of i,
+// abar_e = (sum_m a_{c_m}) / (d+1); K^e packed as the row-major upper triangle.
+template <int D, int L>
+__global__ __launch_bounds__(kBlockThreads) void k_action_elem(int64_t n, const int32_t* __restrict__ nptr,
+                                                               const int32_t* __restrict__ inc,
+                                                               const int4* __restrict__ cell4,
+                                                               const double* __restrict__ kp, int kstride,
+                                                               const double* __restrict__ u,
+                                                               const double* __restrict__ a,
+                                                               double* __restrict__ r) {
+  constexpr int NL = D + 1;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t row = gid / L;
+  const int lane = (int)(gid % L);
+  double acc = 0.0;
+  if (row < n) {
+    for (int p = nptr[row] + lane; p < nptr[row + 1]; p += L) {
+      const int code = inc[p];
+      const int64_t e = code >> 2;
+      const int la = code & 3;
+      const int4 c = cell4[e];
+      const int cv[4] = {c.x, c.y, c.z, c.w};
+      double asum = 0.0, s = 0.0;
+      const double* K = kp + e * kstride;
+#pragma unroll
+      for (int b = 0; b < NL; ++b) {
+        asum += a[cv[b]];
+        const int lo = la < b ? la : b, hi = la < b ? b : la;
+        const int t = lo * NL - (lo * (lo - 1)) / 2 + (hi - lo);
+        s = fma(K[t], u[cv[b]], s);
+      }
+      acc = fma(asum * (1.0 / NL), s, acc);
+    }
+  }
+#pragma unroll
+  for (int off = L / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, L);
+  if (row < n && lane == 0) r[row] = acc;
+}
+
 // Per-workgroup partial sums of (x_i - u_i)^2 and x_i^2 (grid-stride rows):
 // partial[2 g], partial[2 g + 1].
 __global__ __launch_bounds__(kBlockThreads) void k_diff_norms(int64_t n, const double* __restrict__ x,
@@ -358,6 +398,34 @@ hipError_t launch_action_raw(const egfem_tensor_s* T, const double* u, const dou
   auto kern = T->action_pipe ? k_action<false, true> : k_action<false, false>;
   hipLaunchKernelGGL(kern, dim3(xcd_grid(nrun)), dim3(kBlockThreads), 0, st, view_of(T), nrun, u, nullptr, 0.0,
                      a, 0.0, nullptr, nullptr, nullptr, r, nullptr, nullptr);
+  return hipGetLastError();
+}
+
+template <int D, int L>
+static void elem_launch(const egfem_tensor_s* T, const double* u, const double* a, double* r, hipStream_t st) {
+  hipLaunchKernelGGL((k_action_elem<D, L>), dim3(grid1d(T->n * L)), dim3(kBlockThreads), 0, st, T->n, T->e_nptr,
+                     T->e_inc, T->e_cell4, T->e_kp, T->e_kstride, u, a, r);
+}
+
+template <int D>
+static void elem_launch_l(const egfem_tensor_s* T, const double* u, const double* a, double* r, hipStream_t st) {
+  switch (T->e_lanes) {
+    case 2: elem_launch<D, 2>(T, u, a, r, st); break;
+    case 4: elem_launch<D, 4>(T, u, a, r, st); break;
+    case 8: elem_launch<D, 8>(T, u, a, r, st); break;
+    case 16: elem_launch<D, 16>(T, u, a, r, st); break;
+    case 32: elem_launch<D, 32>(T, u, a, r, st); break;
+    default: elem_launch<D, 64>(T, u, a, r, st); break;
+  }
+}
+
+hipError_t launch_action_elementwise(const egfem_tensor_s* T, const double* u, const double* a, double* r,
+                                     hipStream_t st) {
+  switch (T->dim) {
+    case 1: elem_launch_l<1>(T, u, a, r, st); break;
+    case 2: elem_launch_l<2>(T, u, a, r, st); break;
+    default: elem_launch_l<3>(T, u, a, r, st); break;
+  }
   return hipGetLastError();
 }
 

@@ -109,6 +109,8 @@ def test_null_handles_rejected():
     assert lib.egfem_solve_cg(z, z, z, z, 1e-10, 10, None, None, z) == B.EGFEM_ERR_ARG
     assert lib.egfem_picard(z, z, z, z, z, z) == B.EGFEM_ERR_ARG
     assert lib.egfem_burgers(z, z, z, 0, z, z, z, z) == B.EGFEM_ERR_ARG
+    assert lib.egfem_attach_elements(z, 2, 3, z, 1, z) == B.EGFEM_ERR_ARG
+    assert lib.egfem_residual_elementwise(z, z, z, z, z) == B.EGFEM_ERR_ARG
     assert lib.egfem_tensor_info(z, None) == B.EGFEM_ERR_ARG
     assert lib.egfem_newton_batched(0, None, None, None, None, None, None) == B.EGFEM_ERR_ARG
     lib.egfem_tensor_destroy(z)
