@@ -226,6 +226,21 @@ def tensor_action_suite():
                      "jacobian_warm_GBps": bj / (jac * 1e6),
                      "jacobian_frac": bj / (jac * 1e6) / HBM_PEAK_GBS,
                      "shape": tuned["shape"]}
+        if info.nnz_half:
+            # symmetric half stream (T_ijk = T_ikj) against the full stream, both timed
+            keep = T.get_shape()
+            res = {}
+            for half in (0, 1):
+                T.set_shape(action_half=half)
+                res[half] = (time_action(T, 100, cold=False), time_action(T, 20, cold=True))
+            T.set_shape(**keep)
+            bh = ba - 10 * (info.nnz - info.nnz_half)
+            out[name]["half_stream"] = {"nnz_half": info.nnz_half, "bytes": bh,
+                                        "full_warm_us": res[0][0] * 1e3, "full_cold_us": res[0][1] * 1e3,
+                                        "half_warm_us": res[1][0] * 1e3, "half_cold_us": res[1][1] * 1e3,
+                                        "half_cold_GBps": bh / (res[1][1] * 1e6),
+                                        "cold_speedup": res[0][1] / res[1][1],
+                                        "chosen": keep["action_half"]}
         if wl.form == W.FORM_STIFF:
             # element-factored form of the same tensor: cells (16 B), packed K^e, incidences
             T.attach_elements(wl.mesh.coords, wl.mesh.cells)

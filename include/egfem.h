@@ -155,6 +155,7 @@ typedef struct {
   const double* mval;        /* device [slots] mass matrix values */
   int wspace;                /* EGFEM_W_P1, EGFEM_W_P2 or EGFEM_W_IQ */
   int64_t n_w;               /* dofs of W_h (n_nodes for P1) */
+  int64_t nnz_half;          /* entries of the symmetric half stream (0: none) */
 } egfem_info;
 
 int egfem_tensor_info(egfem_tensor_t T, egfem_info* info);
@@ -432,6 +433,11 @@ typedef struct {
   int krylov_kernel;         /* 0: register-resident BiCGStab (one thread per row) when every
                                 workgroup's rows fit its threads and rows hold at most 8
                                 entries, else the streaming one; 1: always the streaming one */
+  int action_half;           /* 1: residual actions read the symmetric half stream (tensors with
+                                T_ijk = T_ikj: mass, convection; each fiber keeps k at or after j,
+                                the diagonal halved, and sums h a_k and h u_k), one row block per
+                                workgroup; 0: the full stream (default; egfem_autotune picks the
+                                half stream where it is faster) */
 } egfem_launch_shape;
 
 int egfem_get_shape(egfem_tensor_t T, egfem_launch_shape* s);

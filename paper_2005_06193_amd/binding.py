@@ -53,7 +53,7 @@ class _Info(C.Structure):
                 ("nnz_b", C.c_int64), ("structural_nnz", C.c_int64), ("slots", C.c_int64),
                 ("row_blocks", C.c_int64), ("device_bytes", C.c_int64),
                 ("rowptr", C.c_void_p), ("col", C.c_void_p), ("kval", C.c_void_p),
-                ("mval", C.c_void_p), ("wspace", C.c_int), ("n_w", C.c_int64)]
+                ("mval", C.c_void_p), ("wspace", C.c_int), ("n_w", C.c_int64), ("nnz_half", C.c_int64)]
 
 
 class _Problem(C.Structure):
@@ -95,7 +95,7 @@ class _BurgersStats(C.Structure):
 
 class _Shape(C.Structure):
     _fields_ = [("action_runs", C.c_int), ("action_pipe", C.c_int), ("krylov_blocks", C.c_int),
-                ("krylov_threads", C.c_int), ("krylov_kernel", C.c_int)]
+                ("krylov_threads", C.c_int), ("krylov_kernel", C.c_int), ("action_half", C.c_int)]
 
 
 class _Stats(C.Structure):
@@ -229,6 +229,7 @@ class Info:
     device_bytes: int
     wspace: int = 0
     n_w: int = 0
+    nnz_half: int = 0
 
 
 @dataclass
@@ -396,7 +397,7 @@ class Tensor:
         _check(load_library().egfem_tensor_info(self._h, C.byref(inf)))
         self.info = Info(inf.dim, inf.form, inf.symmetric, inf.n_nodes, inf.n_cells, inf.nnz,
                          inf.nnz_b, inf.structural_nnz, inf.slots, inf.row_blocks, inf.device_bytes,
-                         inf.wspace, inf.n_w)
+                         inf.wspace, inf.n_w, inf.nnz_half)
 
     # -- construction ----------------------------------------------------
     @classmethod

@@ -150,7 +150,7 @@ void egfem_tensor_destroy(egfem_tensor_t T) {
   void* ptrs[] = {T->rowptr, T->col,  T->diag,    T->tperm,    T->kptrA, T->kA,   T->vA,   T->kS,
                   T->kpS,    T->kval, T->mval,    T->blk_row,  T->blk_meta, T->wrowptr, T->wcol, T->wpq,
                   T->wmeta,  T->wpq2, T->wqi,       T->qlam,   T->e_cell4, T->e_kp,    T->e_nptr,
-                  T->e_inc};
+                  T->e_inc,  T->kSH,  T->vH,        T->kpSH,   T->hmeta};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (!T->symmetric) {
@@ -182,6 +182,7 @@ int egfem_tensor_info(egfem_tensor_t T, egfem_info* info) {
   info->mval = T->mval;
   info->wspace = T->w2;   // EGFEM_W_P1 / EGFEM_W_P2 / EGFEM_W_IQ
   info->n_w = T->n_w;
+  info->nnz_half = T->nnz_h;
   return EGFEM_OK;
 }
 

@@ -279,6 +279,11 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
   std::vector<int32_t> wrowptr(w2 ? N + 1 : 0, 0), wcol;
   std::vector<uint16_t> wpl, wql;   // row-local slot positions of a W-slot's endpoints
   std::vector<uint16_t> wpl2, wql2; // I_k: slots of the third and fourth vertex
+  // symmetric half stream (T_ijk = T_ikj, W_h = P1): per slot (i, j) the
+  // entries with k at or after j, the diagonal one halved
+  std::vector<int32_t> kptrH(1, 0);
+  std::vector<uint16_t> hRel;
+  std::vector<double> vH;
   std::vector<uint8_t> wqi;         // I_k: point index of a W-slot
   std::vector<int64_t> redges;
   int max_row_wslots = 0;
@@ -538,6 +543,17 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
         }
       }
       kptrA.push_back((int32_t)kA.size());
+      if (sym) {
+        // half fiber (T_ijk = T_ikj): k at or after j in the row, diagonal halved
+        for (int kc = jb; kc < nc; ++kc) {
+          const size_t t = (size_t)jb * nc + kc;
+          if (kept(t)) {
+            hRel.push_back((uint16_t)kc);
+            vH.push_back(kc == jb ? 0.5 * acc[t] : acc[t]);
+          }
+        }
+        kptrH.push_back((int32_t)vH.size());
+      }
       if (!sym) {
         // B fiber of slot (i, cols[jb]) as k: j runs over the row's columns
         for (int jj = 0; jj < nc; ++jj) {
@@ -648,6 +664,26 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
     }
   }
 
+  // half stream: block-relative k slots and fiber starts, per-block range
+  std::vector<uint16_t> kSH, kpSH;
+  std::vector<int32_t> hmeta;
+  if (sym) {
+    kSH.resize(vH.size());
+    kpSH.resize((size_t)slots + 1);
+    hmeta.resize((blk.size() - 1) * 2);
+    for (size_t b = 0; b + 1 < blk.size(); ++b) {
+      const int32_t s0 = rowptr[blk[b]], s1 = rowptr[blk[b + 1]];
+      hmeta[2 * b] = kptrH[s0];
+      hmeta[2 * b + 1] = kptrH[s1];
+      for (int32_t s = s0; s < s1; ++s) kpSH[s] = (uint16_t)(kptrH[s] - kptrH[s0]);
+      for (int32_t i = blk[b]; i < blk[b + 1]; ++i) {
+        const int32_t base = rowptr[i] - s0;
+        for (int32_t s = rowptr[i]; s < rowptr[i + 1]; ++s)
+          for (int32_t p = kptrH[s]; p < kptrH[s + 1]; ++p) kSH[p] = (uint16_t)(base + hRel[p]);
+      }
+    }
+  }
+
   // per-block bounds in one 32-byte record, so that a block's stream loads
   // wait on a single (scalar) load instead of three dependent ones
   std::vector<int32_t> meta((blk.size() - 1) * 8);
@@ -718,6 +754,14 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
     if (rc == EGFEM_OK) rc = upload(wcol, &T->wcol, &bytes);
     if (rc == EGFEM_OK) rc = upload(wpq, &T->wpq, &bytes);
     if (rc == EGFEM_OK) rc = upload(wmeta, &T->wmeta, &bytes);
+  }
+  if (sym) {
+    if (rc == EGFEM_OK) rc = upload(kSH, &T->kSH, &bytes);
+    if (rc == EGFEM_OK) rc = upload(vH, &T->vH, &bytes);
+    if (rc == EGFEM_OK) rc = upload(kpSH, &T->kpSH, &bytes);
+    if (rc == EGFEM_OK) rc = upload(hmeta, &T->hmeta, &bytes);
+    T->nnz_h = (int64_t)vH.size();
+    T->action_half = 0;   // the autotuner switches to it where it is faster
   }
   if (wq) {
     std::vector<double> ql(16, 0.0);

@@ -70,6 +70,11 @@ struct TensorView {
   const uint32_t* wpq2;     // slots of the third and fourth vertex
   const uint8_t* wqi;       // point index of every W-slot
   const double* qlam;       // [4][4] barycentrics of the points
+  // symmetric half stream (T_ijk = T_ikj): k at or after j, diagonal halved
+  const uint16_t* kSH;
+  const double* vH;
+  const uint16_t* kpSH;
+  const int2* hmeta;
 };
 
 // Bounds of row block b: rows [r0, r1), slots [s0, s1), A entries [pa0, pa1),
@@ -452,6 +457,118 @@ __device__ void rowblock_jacobian(const TensorView& T, int64_t b, const double* 
     }
   }
   __syncthreads();   // LDS is reused by the next block
+}
+
+// ---------------------------------------------------------------------------
+// Tensor action from the symmetric half stream (T_ijk = T_ikj)
+// ---------------------------------------------------------------------------
+// With h_ijk = T_ijk for k after j and T_ijj / 2 on the diagonal,
+//   r_i = sum_j sum_k T_ijk w_j a_k = sum_j [ w_j sum_{k>=j} h_ijk a_k + a_j sum_{k>=j} h_ijk w_k ],
+// so each slot sums two products of its half fiber.
+struct ActionLdsH {
+  double tA[kCapNnz];
+  double tU[kCapNnz];
+  double aS[kCapSlots];
+  double wS[kCapSlots];
+  double y[kCapSlots];
+  int spa[kCapSlots + 1];
+  int srow[kCapRows + 1];
+};
+
+template <int NT, bool PROBLEM>
+__device__ void rowblock_action_half(const TensorView& T, int64_t b, const double* u, const double* delta,
+                                     double alpha, const double* a, double a0c, const double* load,
+                                     const uint8_t* dir, const double* kval, double* out, double* uout,
+                                     double& sq, ActionLdsH& L) {
+  constexpr int PP = Per<NT>::P, SS = Per<NT>::S;
+  const int tid = threadIdx.x;
+  const BlockMeta m = block_meta(T, b);
+  const int2 hm = T.hmeta[b];
+  const int np = hm.y - hm.x, ns = m.s1 - m.s0, nr = m.r1 - m.r0;
+  int kk[PP];
+  double vv[PP];
+#pragma unroll
+  for (int q = 0; q < PP; ++q) {
+    const int p = hm.x + clamp_hi(tid + q * NT, np);
+    kk[q] = T.kSH[p];
+    vv[q] = T.vH[p];
+  }
+  const double* kvp = kval ? kval : T.kval;
+  int cc[SS], kp[SS];
+  double kv[SS];
+#pragma unroll
+  for (int q = 0; q < SS; ++q) {
+    const int s = m.s0 + clamp_hi(tid + q * NT, ns);
+    cc[q] = T.col[s];
+    kp[q] = T.kpSH[s];
+    kv[q] = kvp[s];
+  }
+  const bool has_row = tid < nr;
+  const int i = m.r0 + clamp_hi(tid, nr);
+  const int rp = T.rowptr[i];
+  const double ldi = (PROBLEM && load) ? load[i] : 0.0;
+  const unsigned char dr = (PROBLEM && dir) ? dir[i] : 0;
+  double wj[SS], aj[SS];
+#pragma unroll
+  for (int q = 0; q < SS; ++q) {
+    wj[q] = u[cc[q]];
+    if (PROBLEM && delta) wj[q] = fma(alpha, delta[cc[q]], wj[q]);
+    aj[q] = PROBLEM ? fma(wj[q], wj[q], a ? a[cc[q]] : a0c) : a[cc[q]];
+  }
+#pragma unroll
+  for (int q = 0; q < SS; ++q) {
+    const int s = tid + q * NT;
+    if (s < ns) {
+      L.wS[s] = wj[q];
+      L.aS[s] = aj[q];
+      L.spa[s] = kp[q];
+    }
+  }
+  if (tid == 0) {
+    L.spa[ns] = np;
+    L.srow[nr] = ns;
+  }
+  if (has_row) L.srow[tid] = rp - m.s0;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PP; ++q) {
+    const int p = tid + q * NT;
+    if (p < np) {
+      L.tA[p] = vv[q] * L.aS[kk[q]];
+      L.tU[p] = vv[q] * L.wS[kk[q]];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < SS; ++q) {
+    const int s = tid + q * NT;
+    if (s < ns) {
+      double sa = 0.0, su = 0.0;
+      for (int t = L.spa[s]; t < L.spa[s + 1]; ++t) {
+        sa += L.tA[t];
+        su += L.tU[t];
+      }
+      if (PROBLEM && kval) sa += kv[q];
+      L.y[s] = fma(aj[q], su, sa * wj[q]);
+    }
+  }
+  __syncthreads();
+  if (has_row) {
+    double acc = 0.0;
+    for (int t = L.srow[tid]; t < L.srow[tid + 1]; ++t) acc += L.y[t];
+    if (PROBLEM) {
+      const bool drow = dir && dr;
+      if (load) acc -= ldi;
+      if (drow) acc = 0.0;
+      if (uout) {
+        const double wi = delta ? fma(alpha, delta[i], u[i]) : u[i];
+        uout[i] = drow ? 0.0 : wi;
+      }
+      sq = fma(acc, acc, sq);
+    }
+    out[i] = acc;
+  }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------

@@ -117,6 +117,13 @@ struct egfem_tensor_s {
   int32_t* wcol = nullptr;      //   [wslots] P2 dof of every W-slot
   uint32_t* wpq = nullptr;      //   [wslots] block-relative slots of its endpoints, p | q << 16
   int32_t* wmeta = nullptr;     //   [row_blocks*2] W-slot range of every block
+  // symmetric half stream (T_ijk = T_ikj): residual actions may use it
+  int64_t nnz_h = 0;
+  int action_half = 0;          // 1: residual actions read the half stream
+  uint16_t* kSH = nullptr;      // [nnz_h] block-relative slot of (i, k), k at or after j
+  double* vH = nullptr;         // [nnz_h] values, diagonal entries halved
+  uint16_t* kpSH = nullptr;     // [slots] half fiber start relative to the block's first half entry
+  int32_t* hmeta = nullptr;     // [row_blocks*2] half-stream range of every block
   // element-factored form of the stiffness tensor (optional)
   int64_t e_cells = 0;
   int e_kstride = 0;            // doubles per packed K^e (triangle of (d+1)^2, rounded to even)

@@ -72,6 +72,10 @@ dev::TensorView view_of(const egfem_tensor_s* T) {
   v.wpq2 = T->wpq2;
   v.wqi = T->wqi;
   v.qlam = T->qlam;
+  v.kSH = T->kSH;
+  v.vH = T->vH;
+  v.kpSH = T->kpSH;
+  v.hmeta = reinterpret_cast<const int2*>(T->hmeta);
   return v;
 }
 
@@ -145,6 +149,30 @@ __global__ __launch_bounds__(kBlockThreads) void k_action_w2(dev::TensorView T, 
   double sq = 0.0;
   dev::rowblock_action_w2<kBlockThreads, PROBLEM, WK>(T, b, u, delta, alpha, a, a0c, load, dir, kval, out, uout,
                                                       sq, L);
+  if (PROBLEM && partial) {
+    const double tot = block_sum256(sq, sh4);
+    if (threadIdx.x == 0) partial[b] = tot;
+  }
+}
+
+// Tensor action from the symmetric half stream, one row block per workgroup.
+template <bool PROBLEM>
+__global__ __launch_bounds__(kBlockThreads) void k_action_half(dev::TensorView T, const double* __restrict__ u,
+                                                               const double* __restrict__ delta, double alpha,
+                                                               const double* __restrict__ a, double a0c,
+                                                               const double* __restrict__ load,
+                                                               const uint8_t* __restrict__ dir,
+                                                               const double* __restrict__ kval,
+                                                               double* __restrict__ out,
+                                                               double* __restrict__ uout,
+                                                               double* __restrict__ partial) {
+  __shared__ dev::ActionLdsH L;
+  __shared__ double sh4[4];
+  const int64_t b = xcd_block(blockIdx.x, T.nblk);
+  if (b < 0) return;
+  double sq = 0.0;
+  dev::rowblock_action_half<kBlockThreads, PROBLEM>(T, b, u, delta, alpha, a, a0c, load, dir, kval, out, uout, sq,
+                                                    L);
   if (PROBLEM && partial) {
     const double tot = block_sum256(sq, sh4);
     if (threadIdx.x == 0) partial[b] = tot;
@@ -380,8 +408,10 @@ inline unsigned grid1d(int64_t n, int bs = kBlockThreads) { return (unsigned)((n
 
 // Number of block runs (workgroups) of the action kernel: the handle's
 // tuned target (0 = one block per workgroup), at least one block per run.
+static bool use_half(const egfem_tensor_s* T) { return T->action_half && T->vH; }
+
 int64_t action_runs(const egfem_tensor_s* T) {
-  if (T->w2) return std::max<int64_t>(1, T->row_blocks);
+  if (T->w2 || use_half(T)) return std::max<int64_t>(1, T->row_blocks);
   const int64_t target = T->action_runs_target > 0 ? (int64_t)T->action_runs_target : T->row_blocks;
   return std::max<int64_t>(1, std::min<int64_t>(T->row_blocks, target));
 }
@@ -392,6 +422,11 @@ hipError_t launch_action_raw(const egfem_tensor_s* T, const double* u, const dou
     auto kern = T->w2 == 2 ? k_action_w2<false, 2> : k_action_w2<false, 1>;
     hipLaunchKernelGGL(kern, dim3(xcd_grid(T->row_blocks)), dim3(kBlockThreads), 0, st, view_of(T), u, nullptr,
                        0.0, a, 0.0, nullptr, nullptr, nullptr, r, nullptr, nullptr);
+    return hipGetLastError();
+  }
+  if (use_half(T)) {
+    hipLaunchKernelGGL(k_action_half<false>, dim3(xcd_grid(T->row_blocks)), dim3(kBlockThreads), 0, st,
+                       view_of(T), u, nullptr, 0.0, a, 0.0, nullptr, nullptr, nullptr, r, nullptr, nullptr);
     return hipGetLastError();
   }
   const int64_t nrun = action_runs(T);
@@ -436,6 +471,12 @@ hipError_t launch_action_problem(const egfem_tensor_s* T, const ProblemView& pv,
     auto kern = T->w2 == 2 ? k_action_w2<true, 2> : k_action_w2<true, 1>;
     hipLaunchKernelGGL(kern, dim3(xcd_grid(T->row_blocks)), dim3(kBlockThreads), 0, st, view_of(T), u, delta,
                        alpha, pv.a0, pv.a0c, pv.load, pv.dir, pv.addK ? T->kval : nullptr, F, uout, partial);
+    return hipGetLastError();
+  }
+  if (use_half(T)) {
+    hipLaunchKernelGGL(k_action_half<true>, dim3(xcd_grid(T->row_blocks)), dim3(kBlockThreads), 0, st,
+                       view_of(T), u, delta, alpha, pv.a0, pv.a0c, pv.load, pv.dir, pv.addK ? T->kval : nullptr,
+                       F, uout, partial);
     return hipGetLastError();
   }
   const int64_t nrun = action_runs(T);

@@ -46,6 +46,7 @@ int egfem_get_shape(egfem_tensor_t T, egfem_launch_shape* s) {
   s->krylov_blocks = T->tuned_krylov_blocks;
   s->krylov_threads = T->tuned_krylov_threads;
   s->krylov_kernel = T->krylov_kernel;
+  s->action_half = T->action_half;
   return EGFEM_OK;
 }
 
@@ -55,13 +56,15 @@ int egfem_set_shape(egfem_tensor_t T, const egfem_launch_shape* s) {
       s->krylov_blocks > kMaxKrylovBlocks ||
       (s->krylov_threads != 0 && s->krylov_threads != 256 && s->krylov_threads != 512 &&
        s->krylov_threads != 1024) ||
-      (s->krylov_kernel != 0 && s->krylov_kernel != 1))
+      (s->krylov_kernel != 0 && s->krylov_kernel != 1) || (s->action_half != 0 && s->action_half != 1))
     return fail(EGFEM_ERR_ARG, "invalid launch shape");
+  if (s->action_half && !T->vH) return fail(EGFEM_ERR_ARG, "this tensor has no symmetric half stream");
   T->action_runs_target = s->action_runs;
   T->action_pipe = s->action_pipe;
   T->tuned_krylov_blocks = s->krylov_blocks;
   T->tuned_krylov_threads = s->krylov_threads;
   T->krylov_kernel = s->krylov_kernel;
+  T->action_half = s->action_half;
   return EGFEM_OK;
 }
 
@@ -81,7 +84,8 @@ int egfem_autotune(egfem_tensor_t T, const egfem_problem* p, int what, egfem_lau
     std::vector<int> runs = {0};
     for (int r : {8192, 4096, 2048, 1024, 512})
       if (r < T->row_blocks) runs.push_back(r);
-    const int keep_runs = T->action_runs_target, keep_pipe = T->action_pipe;
+    const int keep_runs = T->action_runs_target, keep_pipe = T->action_pipe, keep_half = T->action_half;
+    T->action_half = 0;
     double best_t = DBL_MAX;
     int br = keep_runs, bp = keep_pipe;
     for (int pipe = 0; pipe <= 1; ++pipe)
@@ -93,6 +97,7 @@ int egfem_autotune(egfem_tensor_t T, const egfem_problem* p, int what, egfem_lau
         if ((rc = time_action(T, st, 20, &us)) != EGFEM_OK) {
           T->action_runs_target = keep_runs;
           T->action_pipe = keep_pipe;
+          T->action_half = keep_half;
           return rc;
         }
         if (us < best_t) {
@@ -103,6 +108,15 @@ int egfem_autotune(egfem_tensor_t T, const egfem_problem* p, int what, egfem_lau
       }
     T->action_runs_target = br;
     T->action_pipe = bp;
+    T->action_half = 0;
+    if (T->vH) {
+      // the symmetric half stream (one row block per workgroup) against the best full-stream shape
+      T->action_half = 1;
+      double us = 0.0;
+      if ((rc = time_action(T, st, 20, &us)) != EGFEM_OK) return rc;
+      if (us < best_t) best_t = us;
+      else T->action_half = 0;
+    }
     us_action = best_t;
   }
   if (what & 2) {

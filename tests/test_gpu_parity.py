@@ -363,3 +363,37 @@ def test_full_size_sampled_rows(which):
     Jo = (O.contract_first(Tr, a) + O.contract_mode2(Tr, u) @ sp.diags(g)).tocsr()
     d = (Jg[rows] - Jo[rows])
     assert abs(d).max() <= 1e-12 * abs(Jo[rows]).max()
+
+
+@pytest.mark.parametrize("form", [1, 2])
+@pytest.mark.parametrize("mesh", ["1d_n257", "2d_n37", "2d_jitter_n21", "3d_n7"])
+def test_symmetric_half_stream(mesh, form):
+    """Tensors with T_ijk = T_ikj: the half-stream action equals the full
+    stream's and the oracle's, raw and in the problem residual."""
+    m = MESHES[mesh]()
+    T = eg().Tensor.from_mesh(m, form)
+    assert T.info.nnz_half > 0 and T.get_shape()["action_half"] == 0
+    T.set_shape(action_half=1)
+    To = O.assemble_tensor(m.coords, m.cells, form)
+    rng = np.random.default_rng(41)
+    u = rng.uniform(-1, 1, m.n_nodes)
+    a = rng.uniform(0.5, 2, m.n_nodes)
+    rh = host(T.residual(dt(u), dt(a)))
+    T.set_shape(action_half=0)
+    rf = host(T.residual(dt(u), dt(a)))
+    assert relerr(rh, O.contract_uv(To, u, a)) < 1e-12
+    assert np.abs(rh - rf).max() <= 1e-13 * np.abs(rf).max()
+    # problem residual (semilinear form: K u + T:(u (x) u^2) - d) with both streams
+    wl = W.Workload("t", m, rng.uniform(-5, 5, m.n_nodes), form, None, 0.0, True, 1e-10, 1)
+    p = gpu_problem(T, wl)
+    Ff = host(T.problem_residual(p, dt(u)))
+    T.set_shape(action_half=1)
+    Fh = host(T.problem_residual(p, dt(u)))
+    po = O.build_problem(wl)
+    assert relerr(Fh, O.residual(po, u)) < 1e-12
+    assert np.abs(Fh - Ff).max() <= 1e-13 * np.abs(Ff).max()
+    # a stiffness tensor has no half stream
+    S = eg().Tensor.from_mesh(m, 0)
+    assert S.get_shape()["action_half"] == 0
+    with pytest.raises(eg().EgfemError):
+        S.set_shape(action_half=1)
