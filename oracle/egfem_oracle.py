@@ -33,6 +33,8 @@ Finite Element Method", arXiv 2005.06193):
 * Sec. 3.1 Case 3: W_h = I_k, the coefficient carried at the points of a
   quadrature rule (Pi_u evaluates the P1 iterate there); with a rule exact for
   the integrand this is again the standard Galerkin approach.
+* Sec. 3.2 gradient interpolation with W_h = P0 (the p-Laplace and minimal
+  surface examples of Sec. 5): a(grad u) per cell, T_ijk = K^{e_k}_ij, Picard.
 * Sec. 5.2, Burgers' equation: the convection tensor
   N_ijk = int phi_k phi_j (d_1 + d_2) phi_i and the semi-implicit time step
   (M + dt nu K) u^{n+1} = M u^n + dt (1/2 N:(u^n (x) u^n) + d^{n+1}), in the
@@ -810,6 +812,105 @@ def build_problem_iq(p: Problem) -> ProblemP2:
     newton_p2 apply unchanged (they use only Pi and the tensor)."""
     T, W = tensor_iq(p.coords, p.cells, p.form)
     return ProblemP2(p, W, T.i, T.j, T.k, T.v)
+
+
+# ----------------------------------------------------------------------------
+# EGFEM with W_h = P0 and the gradient interpolation (Sec. 3.2; the p-Laplace and
+# minimal surface examples of Sec. 5): a(grad u) = (c0 + c1 |grad u|^2)^q
+# ----------------------------------------------------------------------------
+@dataclass
+class GradProblem:
+    n: int
+    coords: np.ndarray
+    cells: np.ndarray
+    T: Tensor3                 # T_ijk = int eta_k grad phi_j . grad phi_i = K^{e_k}_ij (k = cell)
+    d: np.ndarray              # load M f
+    dirichlet: np.ndarray      # bool
+    c0: float
+    c1: float
+    q: float
+
+    @property
+    def free(self) -> np.ndarray:
+        return ~self.dirichlet
+
+
+def tensor_p0(coords, cells, drop_rel: float = DROP_REL) -> Tensor3:
+    """eta_k the indicator of cell k, so T_ijk = |e_k| grad phi_j . grad phi_i on e_k;
+    the returned Tensor3 has n = max(nodes, cells) (k indexes cells)."""
+    det, G = element_geometry(coords, cells)
+    dim = coords.shape[1]
+    vol = det / math.factorial(dim)
+    Ke = vol[:, None, None] * np.einsum("ead,ebd->eab", G, G)
+    nl = dim + 1
+    E = cells.shape[0]
+    ai, bi = np.meshgrid(np.arange(nl), np.arange(nl), indexing="ij")
+    I = cells[:, ai.ravel()].ravel().astype(np.int64)
+    J = cells[:, bi.ravel()].ravel().astype(np.int64)
+    K = np.repeat(np.arange(E, dtype=np.int64), nl * nl)
+    return _merge_coo3(max(coords.shape[0], E), I, J, K, Ke.reshape(-1), drop_rel)
+
+
+def build_grad_problem(workload) -> GradProblem:
+    m = workload.mesh
+    M = assemble_mass(m.coords, m.cells)
+    return GradProblem(m.n_nodes, m.coords, m.cells, tensor_p0(m.coords, m.cells), M @ workload.f,
+                       m.dirichlet.astype(bool), workload.c0, workload.c1, workload.q)
+
+
+def grad_interp(p: GradProblem, u: np.ndarray) -> np.ndarray:
+    """Pi_grad u: the (constant) gradient of u_h on every cell, [cells, dim]."""
+    _, G = element_geometry(p.coords, p.cells)
+    return np.einsum("ea,ead->ed", u[p.cells], G)
+
+
+def grad_coef(p: GradProblem, u: np.ndarray) -> np.ndarray:
+    """a_e = (c0 + c1 |grad u_h|_e|^2)^q, the nonlinearity at the P0 dofs (+inf
+    where the base is 0 and q < 0)."""
+    z = grad_interp(p, u)
+    with np.errstate(divide="ignore"):
+        return (p.c0 + p.c1 * np.sum(z * z, axis=1)) ** p.q
+
+
+def grad_matrix(p: GradProblem, a: np.ndarray) -> sp.csr_matrix:
+    """(T . a)_ij = sum_e a_e K^e_ij with Dirichlet identity rows and zero columns.
+    Only entries with a free row and a free column are formed: a cell whose
+    vertices all lie on the boundary has u_h = 0, grad u_h = 0 and, for q < 0 and
+    c0 = 0, an unbounded coefficient, but it couples Dirichlet nodes only."""
+    T = p.T
+    keep = p.free[T.i] & p.free[T.j]
+    A = sp.coo_matrix((T.v[keep] * a[T.k[keep]], (T.i[keep], T.j[keep])), shape=(p.n, p.n)).tocsr()
+    return (A + sp.diags(p.dirichlet.astype(np.float64))).tocsr()
+
+
+def residual_grad(p: GradProblem, u: np.ndarray) -> np.ndarray:
+    """F = T:(u (x) a(grad u)) - d on the free rows (Dirichlet rows 0)."""
+    a = grad_coef(p, u)
+    T = p.T
+    keep = p.free[T.i]
+    F = np.bincount(T.i[keep], weights=T.v[keep] * u[T.j[keep]] * a[T.k[keep]], minlength=p.n) - p.d
+    F[p.dirichlet] = 0.0
+    return F
+
+
+def picard_grad(p: GradProblem, u0: Optional[np.ndarray] = None, tol: float = 1e-12, max_iter: int = 500,
+                start_linear: bool = True):
+    """Picard iteration of the examples: (T . a^n) u^{n+1} = d, a^{n+1} = a(Pi_grad u^{n+1});
+    with start_linear the first matrix uses a = 1 (a Laplace solve), which also
+    serves p < 2 where a(0) is unbounded.  Exact solves; stops on the relative
+    update.  Returns (u, iterations)."""
+    u = np.zeros(p.n) if u0 is None else np.array(u0, dtype=np.float64)
+    u[p.dirichlet] = 0.0
+    rhs = p.d.copy()
+    rhs[p.dirichlet] = 0.0
+    for it in range(max_iter):
+        a = np.ones(p.cells.shape[0]) if (it == 0 and start_linear) else grad_coef(p, u)
+        un = spla.spsolve(grad_matrix(p, a).tocsc(), rhs)
+        upd = np.linalg.norm(un - u) / max(np.linalg.norm(un), 1e-300)
+        u = un
+        if upd <= tol:
+            return u, it + 1
+    return u, max_iter
 
 
 # ----------------------------------------------------------------------------

@@ -656,3 +656,63 @@ def test_egfem_iq_equals_sga_and_p2():
         T, Wsp = O.tensor_iq(p.coords, p.cells, O.FORM_STIFF)
         assert Wsp.n_w == p.cells.shape[0] * Wsp.lam.shape[0]
         assert np.allclose(np.asarray(Wsp.Pi.sum(axis=1)).ravel(), 1.0)
+
+
+# ----------------------------------------------------------------------------
+# W_h = P0 with the gradient interpolation (p-Laplace, minimal surface)
+# ----------------------------------------------------------------------------
+def test_p0_tensor_is_element_stiffness():
+    """T_ijk = K^{e_k}_ij: contracting with a = 1 gives the stiffness matrix, and
+    the per-cell slices are the exact rational element stiffness matrices."""
+    for dim in (1, 2, 3):
+        coords, cells = IRREGULAR[dim]
+        T = O.tensor_p0(coords, cells, drop_rel=0.0)
+        K = O.assemble_stiffness(coords, cells).toarray()
+        n = coords.shape[0]
+        A = np.zeros((n, n))
+        np.add.at(A, (T.i, T.j), T.v)
+        assert np.abs(A - K).max() < 1e-14 * np.abs(K).max()
+        for e, cell in enumerate(cells):
+            verts = [[Fraction(float(x)) for x in coords[v]] for v in cell]
+            grads, vol = _exact_element(verts)
+            sel = T.k == e
+            for i, j, v in zip(T.i[sel], T.j[sel], T.v[sel]):
+                a, b = list(cell).index(i), list(cell).index(j)
+                ex = float(vol * sum(grads[a][r] * grads[b][r] for r in range(dim)))
+                assert abs(v - ex) <= 1e-14 * abs(ex) + 1e-17
+
+
+def test_plaplace_1d_exact_fluxes():
+    """1D p-Laplace, source 1, zero boundary values: the discrete equations fix the
+    element fluxes a(u'_e) u'_e = 1/2 - x_mid(e) exactly (a telescoping sum with the
+    loads int phi_i = h), whatever the nonlinearity."""
+    m = W.mesh_1d(40)
+    for pp in (1.5, 1.8):
+        wl = W.GradientWorkload("t", m, np.ones(m.n_nodes), pp, 0.0, 1.0, (pp - 2.0) / 2.0, None)
+        P = O.build_grad_problem(wl)
+        u, it = O.picard_grad(P, tol=1e-14)
+        z = O.grad_interp(P, u)[:, 0]
+        flux = O.grad_coef(P, u) * z
+        xm = m.coords[m.cells].mean(axis=1)[:, 0]
+        assert np.abs(flux - (0.5 - xm)).max() < 1e-12
+    # q = 0 is the linear problem: one solve with the stiffness matrix
+    wl = W.GradientWorkload("t", m, np.ones(m.n_nodes), 2.0, 1.0, 1.0, 0.0, None)
+    P = O.build_grad_problem(wl)
+    u, it = O.picard_grad(P, tol=1e-14)
+    assert it <= 2
+    x = m.coords[:, 0]
+    assert np.abs(u - 0.5 * x * (1 - x)).max() < 1e-14        # P1 is nodally exact in 1D
+
+
+def test_plaplace_disk_converges_to_exact_solution():
+    """p = 3/2 on the unit disk (the paper's example): the EGFEM(P0) fixed point
+    approaches the radial exact solution at second order."""
+    errs = []
+    for n in (8, 16, 32):
+        wl = W.plaplace_disk(n)
+        P = O.build_grad_problem(wl)
+        u, it = O.picard_grad(P, tol=1e-12)
+        assert np.linalg.norm(O.residual_grad(P, u)) <= 1e-11 * np.linalg.norm(P.d[P.free])
+        errs.append(np.linalg.norm(u - wl.exact) / np.linalg.norm(wl.exact))
+    assert errs[2] < 2e-3
+    assert 3.0 < errs[0] / errs[1] < 5.0 and 3.0 < errs[1] / errs[2] < 5.0

@@ -319,6 +319,51 @@ def burgers_2d(n: int = 256, dt: float = 1e-2, t_end: float = 1.0, nu: float = 1
                            burgers_exact(x1, x2, steps * dt))
 
 
+# ----------------------------------------------------------------------------
+# p-Laplace equation on the unit disk (the gradient-nonlinearity benchmark of
+# the paper's results section)
+# ----------------------------------------------------------------------------
+def mesh_disk(n: int) -> Mesh:
+    """Unit disk: the 2D mesh of [-1,1]^2 with n x n squares (same numbering and
+    diagonals as mesh_2d) mapped by (x, y) -> (x sqrt(1 - y^2/2), y sqrt(1 - x^2/2)),
+    which takes the square's boundary onto the circle; Dirichlet = boundary."""
+    m = mesh_2d(n)
+    x = 2.0 * m.coords[:, 0] - 1.0
+    y = 2.0 * m.coords[:, 1] - 1.0
+    c = np.stack([x * np.sqrt(1.0 - 0.5 * y * y), y * np.sqrt(1.0 - 0.5 * x * x)], axis=1)
+    return Mesh(2, n, c, m.cells, m.dirichlet)
+
+
+def plaplace_exact(coords: np.ndarray, p: float) -> np.ndarray:
+    """Radial solution of -div(|grad u|^{p-2} grad u) = 1 on the unit disk, u = 0
+    on the circle: u = 2^{-1/(p-1)} (p-1)/p (1 - |x|^{p/(p-1)})."""
+    r = np.sqrt(np.sum(coords * coords, axis=1))
+    return 2.0 ** (-1.0 / (p - 1.0)) * (p - 1.0) / p * (1.0 - r ** (p / (p - 1.0)))
+
+
+@dataclass
+class GradientWorkload:
+    name: str
+    mesh: Mesh
+    f: np.ndarray                   # nodal source values; load M f
+    p: float                        # coefficient (c0 + c1 |grad u|^2)^q with
+    c0: float                       #   p-Laplace: c0 = eps^2, c1 = 1, q = (p - 2) / 2
+    c1: float
+    q: float
+    exact: Optional[np.ndarray]     # nodal exact solution or None
+
+    @property
+    def n_nodes(self) -> int:
+        return self.mesh.n_nodes
+
+
+def plaplace_disk(n: int = 256, p: float = 1.5, eps: float = 0.0) -> GradientWorkload:
+    """p-Laplace on the unit disk with source 1 (p = 3/2 as in the paper)."""
+    m = mesh_disk(n)
+    return GradientWorkload(f"plaplace_disk_n{n}_p{p:g}", m, np.ones(m.n_nodes), p, eps * eps, 1.0,
+                            (p - 2.0) / 2.0, plaplace_exact(m.coords, p))
+
+
 WORKLOADS = {
     "1d": nonlinear_diffusion_1d,
     "2d": nonlinear_diffusion_2d,
