@@ -79,11 +79,15 @@ enum egfem_wspace {
   EGFEM_W_P2 = 1,            /* W_h = P2 on the same mesh with Pi_u the P2 interpolation of the
                                 P1 iterate (Case 1 of Sec. 3.1): for a = a0 + u^2 the coefficient
                                 is then exact and EGFEM coincides with the standard Galerkin method */
-  EGFEM_W_IQ = 2             /* W_h = I_k (Case 3 of Sec. 3.1): the coefficient lives at the points
+  EGFEM_W_IQ = 2,            /* W_h = I_k (Case 3 of Sec. 3.1): the coefficient lives at the points
                                 of a fixed quadrature rule in every cell (1D: 2-point Gauss; 2D: the
                                 3 points with barycentrics (2/3,1/6,1/6); 3D: the 4 points (a,b,b,b),
                                 a = (5+3 sqrt 5)/20, b = (5-sqrt 5)/20; equal weights), Pi_u evaluates
                                 the P1 iterate there; the stiffness form is then again exact */
+  EGFEM_W_P0 = 3             /* W_h = P0 (one dof per cell) for nonlinearities of the gradient
+                                (Sec. 3.2, the p-Laplace and minimal surface examples of Sec. 5):
+                                T_ijk = K^{e_k}_ij (stiffness) or M^{e_k}_ij (mass); the
+                                coefficient comes from egfem_picard_grad or is passed per cell */
 };
 
 /* ------------------------------------------------------------------------
@@ -127,7 +131,10 @@ int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords,
  *  - the problem-level calls (problem residual / Jacobian, Newton, Picard)
  *    use a = Pi_u a0 + (Pi_u u)^2 at the dofs of W_h, a' = 2 Pi_u u;
  *  - egfem_mode3, egfem_adjoint, the batched form and egfem_burgers return
- *    EGFEM_ERR_ARG; the convection form is not available (EGFEM_ERR_ARG).
+ *    EGFEM_ERR_ARG; the convection form is not available (EGFEM_ERR_ARG);
+ *  - with EGFEM_W_P0 (k = cell, T_ijk = K^{e_k}_ij or M^{e_k}_ij) the problem-
+ *    level calls return EGFEM_ERR_ARG (the coefficient is a function of the
+ *    gradient: egfem_picard_grad), and egfem_jacobian takes no dadu.
  * Row blocks additionally hold at most 1024 (row, W_h dof) couplings. */
 int egfem_build_tensor_w(int dim, int64_t n_nodes, const double* coords,
                          int64_t n_cells, const int32_t* cells, int form, int wspace,
@@ -153,7 +160,7 @@ typedef struct {
   const int32_t* col;        /* device [slots], ascending within a row */
   const double* kval;        /* device [slots] stiffness matrix values */
   const double* mval;        /* device [slots] mass matrix values */
-  int wspace;                /* EGFEM_W_P1, EGFEM_W_P2 or EGFEM_W_IQ */
+  int wspace;                /* EGFEM_W_P1, EGFEM_W_P2, EGFEM_W_IQ or EGFEM_W_P0 */
   int64_t n_w;               /* dofs of W_h (n_nodes for P1) */
   int64_t nnz_half;          /* entries of the symmetric half stream (0: none) */
 } egfem_info;
@@ -419,6 +426,34 @@ void egfem_burgers_opts_default(egfem_burgers_opts* o);
  * synchronises the stream (one scalar readback per step). */
 int egfem_burgers(egfem_tensor_t T, const uint8_t* dirichlet, const double* source, int64_t source_stride,
                   double* u, const egfem_burgers_opts* o, egfem_burgers_stats* s, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Gradient nonlinearities with W_h = P0 (Sec. 3.2 gradient interpolation; the
+ * p-Laplace and minimal surface examples of Sec. 5), solved like the paper by
+ * Picard iteration:
+ *     (T . a^n) u^{n+1} = d,   a^n_e = (c0 + c1 |grad u_h^n|_e|^2)^q  per cell e,
+ * T the EGFEM_W_P0 tensor (T . a = sum_e a_e K^e), Dirichlet rows identity with
+ * zero right-hand side.  p-Laplace: c0 = eps^2, c1 = 1, q = (p-2)/2; minimal
+ * surface: c0 = c1 = 1, q = -1/2.  Each step: one cell kernel for a^n, the
+ * emission of T . a^n (the A stream with the coefficient gathered per W-slot)
+ * and one persistent Jacobi-CG launch warm started from u^n.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  double c0, c1, q;          /* a(z) = (c0 + c1 |z|^2)^q; c0, c1 >= 0 */
+  int start_linear;          /* nonzero: the first step uses a = 1 (a Laplace solve), which also
+                                starts p < 2 from u = 0 where a(0) is unbounded */
+} egfem_grad_coef;
+
+/* egfem_picard_grad: Picard iteration from u (device [n_nodes]; Dirichlet
+ * entries set to 0) with the options of egfem_picard (tol on the relative
+ * update, inexact CG relative to each step's initial residual).  p: load and
+ * Dirichlet mask (a0 must be NULL, add_stiffness 0).  s->res receives ||F||
+ * over the free rows at the returned iterate, F = T:(u (x) a(grad u)) - d (a
+ * cell whose vertices are all Dirichlet nodes only couples Dirichlet nodes; its
+ * coefficient may be unbounded without effect).  Returns the status or
+ * EGFEM_ERR_ARG (not a W_h = P0 handle, bad parameters).  Synchronises. */
+int egfem_picard_grad(egfem_tensor_t T, const egfem_problem* p, const egfem_grad_coef* g, double* u,
+                      const egfem_picard_opts* o, egfem_picard_stats* s, void* stream);
 
 /* ------------------------------------------------------------------------
  * Launch shapes and the autotuner.

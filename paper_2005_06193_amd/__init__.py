@@ -1,7 +1,7 @@
 """MI355X (gfx950) EGFEM Newton hot path: HIP kernels behind a C ABI
 (include/egfem.h) with a thin ctypes binding.  See binding.py."""
 from .binding import (  # noqa: F401
-    Batch, BurgersOptions, BurgersStats, EgfemError, FORM_CONV, FORM_MASS, FORM_STIFF, Info, W_IQ, W_P1, W_P2, NewtonOptions, NewtonStats, PicardOptions, PicardStats,
+    Batch, BurgersOptions, BurgersStats, EgfemError, FORM_CONV, FORM_MASS, FORM_STIFF, Info, W_IQ, W_P0, W_P1, W_P2, NewtonOptions, NewtonStats, PicardOptions, PicardStats,
     Problem, Tensor,
     load_library, newton_batched, version, EXPORTS, LIB_PATH,
 )

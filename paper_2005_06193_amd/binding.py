@@ -38,6 +38,7 @@ FORM_CONV = 2
 W_P1 = 0
 W_P2 = 1
 W_IQ = 2
+W_P0 = 3
 HIST = 64
 
 
@@ -91,6 +92,10 @@ class _BurgersStats(C.Structure):
     _fields_ = [("status", C.c_int), ("steps", C.c_int), ("krylov_iters", C.c_int64),
                 ("max_step_krylov", C.c_int), ("max_relres", C.c_double), ("krylov_hist", C.c_int * HIST),
                 ("t_rhs_ms", C.c_double), ("t_krylov_ms", C.c_double), ("krylov_kernels", C.c_int)]
+
+
+class _GradCoef(C.Structure):
+    _fields_ = [("c0", C.c_double), ("c1", C.c_double), ("q", C.c_double), ("start_linear", C.c_int)]
 
 
 class _Shape(C.Structure):
@@ -160,6 +165,8 @@ EXPORTS = {
     "egfem_burgers_opts_default": (None, [C.POINTER(_BurgersOpts)]),
     "egfem_burgers": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
                                 C.POINTER(_BurgersOpts), C.POINTER(_BurgersStats), C.c_void_p]),
+    "egfem_picard_grad": (C.c_int, [C.c_void_p, C.POINTER(_Problem), C.POINTER(_GradCoef), C.c_void_p,
+                                    C.POINTER(_PicardOpts), C.POINTER(_PicardStats), C.c_void_p]),
     "egfem_solve_cg": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int,
                                  C.POINTER(C.c_int), C.POINTER(C.c_double), C.c_void_p]),
     "egfem_last_error": (C.c_char_p, []),
@@ -612,6 +619,23 @@ class Tensor:
         stats = PicardStats.from_c(st)
         if rc != EGFEM_OK and warn:
             warnings.warn(f"egfem_picard ended with status {stats.status_name}")
+        return stats
+
+    def picard_grad(self, p: Problem, u: torch.Tensor, c0: float, c1: float, q: float,
+                    start_linear: bool = True, opts: Optional[PicardOptions] = None,
+                    warn: bool = True) -> PicardStats:
+        """Picard iteration for a(grad u) = (c0 + c1 |grad u|^2)^q on a W_h = P0
+        handle (p-Laplace: c0 = eps^2, c1 = 1, q = (p-2)/2), in place on u."""
+        o = (opts or PicardOptions()).c()
+        pc = p.c()
+        g = _GradCoef(float(c0), float(c1), float(q), int(bool(start_linear)))
+        st = _PicardStats()
+        rc = load_library().egfem_picard_grad(self.handle, C.byref(pc), C.byref(g), _dptr(u, n=self.n),
+                                              C.byref(o), C.byref(st), _stream())
+        _check(rc, allow_positive=True)
+        stats = PicardStats.from_c(st)
+        if rc != EGFEM_OK and warn:
+            warnings.warn(f"egfem_picard_grad ended with status {stats.status_name}")
         return stats
 
     def burgers(self, u: torch.Tensor, dirichlet: Optional[torch.Tensor] = None,

@@ -124,6 +124,11 @@ struct LaunchTimer {
   }
 };
 
+#define EGFEM_TRY_RC(x)                    \
+  do {                                     \
+    if ((rc = (x)) != EGFEM_OK) return rc; \
+  } while (0)
+
 static ProblemView view(const egfem_problem* p) {
   ProblemView v;
   v.a0 = p->a0;
@@ -150,7 +155,7 @@ void egfem_tensor_destroy(egfem_tensor_t T) {
   void* ptrs[] = {T->rowptr, T->col,  T->diag,    T->tperm,    T->kptrA, T->kA,   T->vA,   T->kS,
                   T->kpS,    T->kval, T->mval,    T->blk_row,  T->blk_meta, T->wrowptr, T->wcol, T->wpq,
                   T->wmeta,  T->wpq2, T->wqi,       T->qlam,   T->e_cell4, T->e_kp,    T->e_nptr,
-                  T->e_inc,  T->kSH,  T->vH,        T->kpSH,   T->hmeta};
+                  T->e_inc,  T->kSH,  T->vH,        T->kpSH,   T->hmeta,   T->e_grad,  T->e_acoef};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (!T->symmetric) {
@@ -228,6 +233,7 @@ int egfem_jacobian(egfem_tensor_t T, const double* u, const double* a, const dou
                    int add_stiffness, const uint8_t* dirichlet, double* jval, double* dinv,
                    void* stream) {
   if (!T || !u || !a || !jval) return fail(EGFEM_ERR_ARG, "null argument");
+  if (T->w2 == 3 && dadu) return fail(EGFEM_ERR_ARG, "W_h = P0 handles emit the first Jacobian term only");
   EGFEM_HIP_CHECK(launch_jacobian(T, u, a, nullptr, 0.0, 0, dadu, 0, add_stiffness, dirichlet, jval,
                                   dinv, (hipStream_t)stream));
   return EGFEM_OK;
@@ -262,6 +268,7 @@ int egfem_matvec(egfem_tensor_t T, int which, const double* jval, int transpose,
 int egfem_problem_residual(egfem_tensor_t T, const egfem_problem* p, const double* u, double* F,
                            double* norm, void* stream) {
   if (!T || !p || !u || !F) return fail(EGFEM_ERR_ARG, "null argument");
+  if (T->w2 == 3) return fail(EGFEM_ERR_ARG, "W_h = P0 handles take the gradient coefficient (egfem_picard_grad)");
   if (F == u) return fail(EGFEM_ERR_ARG, "F must not alias u");
   int rc = ensure_workspace(T);
   if (rc != EGFEM_OK) return rc;
@@ -274,6 +281,7 @@ int egfem_problem_residual(egfem_tensor_t T, const egfem_problem* p, const doubl
 int egfem_problem_jacobian(egfem_tensor_t T, const egfem_problem* p, const double* u, double* jval,
                            double* dinv, void* stream) {
   if (!T || !p || !u || !jval) return fail(EGFEM_ERR_ARG, "null argument");
+  if (T->w2 == 3) return fail(EGFEM_ERR_ARG, "W_h = P0 handles take the gradient coefficient (egfem_picard_grad)");
   EGFEM_HIP_CHECK(launch_jacobian(T, u, nullptr, p->a0, p->a0_const, 1, nullptr, 1,
                                   p->add_stiffness, p->dirichlet, jval, dinv, (hipStream_t)stream));
   return EGFEM_OK;
@@ -324,6 +332,7 @@ static double ew_forcing(int k, double nF, double nF_prev, double eta_prev, doub
 int egfem_newton(egfem_tensor_t T, const egfem_problem* p, double* u, const egfem_newton_opts* o,
                  egfem_newton_stats* s, void* stream) {
   if (!T || !p || !u) return fail(EGFEM_ERR_ARG, "null argument");
+  if (T->w2 == 3) return fail(EGFEM_ERR_ARG, "W_h = P0 handles take the gradient coefficient (egfem_picard_grad)");
   egfem_newton_opts opts;
   egfem_newton_opts_default(&opts);
   if (o) opts = *o;
@@ -472,6 +481,7 @@ void egfem_picard_opts_default(egfem_picard_opts* o) {
 int egfem_picard(egfem_tensor_t T, const egfem_problem* p, double* u, const egfem_picard_opts* o,
                  egfem_picard_stats* s, void* stream) {
   if (!T || !p || !u) return fail(EGFEM_ERR_ARG, "null argument");
+  if (T->w2 == 3) return fail(EGFEM_ERR_ARG, "W_h = P0 handles take the gradient coefficient (egfem_picard_grad)");
   egfem_picard_opts opts;
   egfem_picard_opts_default(&opts);
   if (o) opts = *o;
@@ -624,6 +634,96 @@ int egfem_burgers(egfem_tensor_t T, const uint8_t* dirichlet, const double* sour
   EGFEM_HIP_CHECK(hipStreamSynchronize(st));
   stats.status = status;
   stats.steps = n;
+  if (s) *s = stats;
+  return status;
+}
+
+int egfem_picard_grad(egfem_tensor_t T, const egfem_problem* p, const egfem_grad_coef* g, double* u,
+                      const egfem_picard_opts* o, egfem_picard_stats* s, void* stream) {
+  if (!T || !p || !g || !u) return fail(EGFEM_ERR_ARG, "null argument");
+  if (T->w2 != 3) return fail(EGFEM_ERR_ARG, "the gradient coefficient needs a W_h = P0 handle");
+  if (p->a0 || p->add_stiffness) return fail(EGFEM_ERR_ARG, "the gradient problem takes no a0 and no K term");
+  if (!std::isfinite(g->c0) || !std::isfinite(g->c1) || !std::isfinite(g->q) || g->c0 < 0.0 || g->c1 < 0.0)
+    return fail(EGFEM_ERR_ARG, "coefficient parameters must be finite, c0 >= 0, c1 >= 0");
+  egfem_picard_opts opts;
+  egfem_picard_opts_default(&opts);
+  if (o) opts = *o;
+  if (!(opts.tol >= 0.0) || opts.max_picard < 0 || opts.max_krylov < 1 || !(opts.krylov_rtol > 0.0) ||
+      opts.krylov_blocks < 0 ||
+      (opts.krylov_threads != 0 && opts.krylov_threads != 256 && opts.krylov_threads != 512 &&
+       opts.krylov_threads != 1024))
+    return fail(EGFEM_ERR_ARG, "invalid Picard options");
+  int rc = ensure_workspace(T);
+  if (rc != EGFEM_OK) return rc;
+  Workspace& W = T->ws;
+  hipStream_t st = (hipStream_t)stream;
+  egfem_picard_stats stats;
+  std::memset(&stats, 0, sizeof(stats));
+  LaunchTimer tm;
+  if ((rc = tm.init(opts.timing != 0, st)) != EGFEM_OK) return rc;
+  int n_dummy = 0;
+  double* a = T->e_acoef;
+  std::vector<double> part(512);
+  // ||F(u)|| over the free rows, F = T:(u (x) a(grad u)) - d
+  auto residual_norm = [&](double* out) -> int {
+    EGFEM_HIP_CHECK(launch_grad_coef(T, u, g->c0, g->c1, g->q, 0, a, st));
+    EGFEM_HIP_CHECK(launch_action_raw(T, u, a, W.F, st));
+    EGFEM_HIP_CHECK(launch_mask_zero(W.F, p->dirichlet, T->n, st));
+    hipError_t e = hipSuccess;
+    const int ng = launch_diff_norms(T->n, W.F, W.rhs, W.red, st, &e);
+    EGFEM_HIP_CHECK(e);
+    EGFEM_HIP_CHECK(hipMemcpyAsync(part.data(), W.red, 2 * ng * sizeof(double), hipMemcpyDeviceToHost, st));
+    EGFEM_HIP_CHECK(hipStreamSynchronize(st));
+    double dd = 0.0;
+    for (int q = 0; q < ng; ++q) dd += part[2 * q];
+    *out = std::sqrt(dd);
+    return EGFEM_OK;
+  };
+  // u_D = 0; right-hand side d with zero Dirichlet rows
+  EGFEM_HIP_CHECK(launch_mask_zero(u, p->dirichlet, T->n, st));
+  if (p->load) EGFEM_HIP_CHECK(launch_copy(W.rhs, p->load, T->n, st));
+  else EGFEM_HIP_CHECK(launch_fill(W.rhs, 0.0, T->n, st));
+  EGFEM_HIP_CHECK(launch_mask_zero(W.rhs, p->dirichlet, T->n, st));
+  int status = EGFEM_NOT_CONVERGED;
+  int k = 0;
+  while (status == EGFEM_NOT_CONVERGED && k < opts.max_picard) {
+    // a^n = a(Pi_grad u^n) per cell (a = 1 on the first step with start_linear)
+    EGFEM_TRY_RC(tm.start());
+    EGFEM_HIP_CHECK(launch_grad_coef(T, u, g->c0, g->c1, g->q, (k == 0 && g->start_linear) ? 1 : 0, a, st));
+    // (T . a^n) with Dirichlet identity rows and zero columns, and 1/diag
+    EGFEM_HIP_CHECK(launch_jacobian(T, u, a, nullptr, 0.0, 0, nullptr, 0, 0, p->dirichlet, W.jval, W.dinv, st));
+    EGFEM_TRY_RC(tm.stop(&stats.t_matrix_ms, &n_dummy));
+    EGFEM_HIP_CHECK(launch_copy(W.delta, u, T->n, st));
+    KrylovResult kr;
+    rc = krylov_solve(KrylovMethod::kCG, T, W.jval, W.dinv, W.rhs, 1.0, W.delta, false, opts.krylov_rtol, true,
+                      opts.max_krylov, opts.krylov_blocks, &kr, st, nullptr, tm.on, opts.krylov_threads);
+    if (rc != EGFEM_OK) return rc;
+    if (tm.on) stats.t_krylov_ms += kr.kernel_ms;
+    stats.krylov_iters += kr.iters;
+    stats.krylov_kernels |= kr.resident ? 1 : 2;
+    if (k < EGFEM_HIST) stats.krylov_hist[k] = kr.iters;
+    hipError_t e = hipSuccess;
+    const int ng = launch_diff_norms(T->n, W.delta, u, W.red, st, &e);
+    EGFEM_HIP_CHECK(e);
+    EGFEM_HIP_CHECK(hipMemcpyAsync(part.data(), W.red, 2 * ng * sizeof(double), hipMemcpyDeviceToHost, st));
+    EGFEM_HIP_CHECK(launch_copy(u, W.delta, T->n, st));
+    EGFEM_HIP_CHECK(hipStreamSynchronize(st));
+    double dd = 0.0, xx = 0.0;
+    for (int q = 0; q < ng; ++q) {
+      dd += part[2 * q];
+      xx += part[2 * q + 1];
+    }
+    const double upd = xx > 0.0 ? std::sqrt(dd / xx) : 0.0;
+    stats.update = upd;
+    if (k < EGFEM_HIST) stats.update_hist[k] = upd;
+    ++k;
+    if (kr.status == EGFEM_NONFINITE || !std::isfinite(upd)) status = EGFEM_NONFINITE;
+    else if (upd <= opts.tol) status = EGFEM_OK;
+  }
+  if ((rc = residual_norm(&stats.res)) != EGFEM_OK) return rc;
+  stats.res0 = 0.0;
+  stats.status = status;
+  stats.picard_iters = k;
   if (s) *s = stats;
   return status;
 }

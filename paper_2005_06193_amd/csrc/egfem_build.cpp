@@ -153,16 +153,22 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
   if (dim < 1 || dim > 3) return fail(EGFEM_ERR_ARG, "dim must be 1, 2 or 3");
   if (form != EGFEM_FORM_STIFF && form != EGFEM_FORM_MASS && form != EGFEM_FORM_CONV)
     return fail(EGFEM_ERR_ARG, "unknown form");
-  if (wspace != EGFEM_W_P1 && wspace != EGFEM_W_P2 && wspace != EGFEM_W_IQ)
+  if (wspace != EGFEM_W_P1 && wspace != EGFEM_W_P2 && wspace != EGFEM_W_IQ && wspace != EGFEM_W_P0)
     return fail(EGFEM_ERR_ARG, "unknown W space");
   if (wspace != EGFEM_W_P1 && form == EGFEM_FORM_CONV)
     return fail(EGFEM_ERR_ARG, "the convection form is built with W_h = P1 only");
   const bool w2 = (wspace != EGFEM_W_P1);     // a coefficient space with W-slots
   const bool wq = (wspace == EGFEM_W_IQ);
+  const bool w0 = (wspace == EGFEM_W_P0);   // one coefficient per cell
   // quadrature rule of W_h = I_k: barycentrics (padded to 4) and weights / |e|
   int nq = 0;
   double qlam[4][4] = {{0}}, qw[4] = {0};
-  if (wq) {
+  if (w0) {
+    // the indicator of the cell: one "point" with weight 1 (|e| folded into the
+    // values); no barycentric weights are used
+    nq = 1;
+    qw[0] = 1.0;
+  } else if (wq) {
     if (dim == 1) {
       nq = 2;
       const double x0 = 0.5 - 0.5 / std::sqrt(3.0), x1 = 0.5 + 0.5 / std::sqrt(3.0);
@@ -257,7 +263,7 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
         ++t;
       }
   }
-  if (wq && n_cells * nq >= (int64_t(1) << 31)) return fail(EGFEM_ERR_SHAPE, "too many quadrature points");
+  if ((wq || w0) && n_cells * nq >= (int64_t(1) << 31)) return fail(EGFEM_ERR_SHAPE, "too many quadrature points");
   std::vector<int64_t> ekeys;   // min * N + max of every edge
   if (w2 && !wq) {
     ekeys.reserve((size_t)n_cells * ne_loc);
@@ -302,8 +308,9 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
     auto lidx = [&](int32_t node) {
       return (int)(std::lower_bound(cols.begin(), cols.end(), node) - cols.begin());
     };
-    if (wq) {
-      // W-slots of row i: the points of its cells (ascending cell, then point)
+    if (wq || w0) {
+      // W-slots of row i: the points of its cells (ascending cell, then point);
+      // for W_h = P0 the cells themselves
       const int ncl = (int)(nptr[i + 1] - nptr[i]);
       const int nw = ncl * nq;
       max_row_wslots = std::max(max_row_wslots, nw);
@@ -326,8 +333,9 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
           kacc[loc[b]] += kab;
           macc[loc[b]] += g.vol * (a == b ? m2_diag : m2_off);
           for (int q = 0; q < nq; ++q) {
-            const double val = (form == EGFEM_FORM_STIFF) ? qw[q] * kab
-                                                          : qw[q] * g.vol * qlam[q][a] * qlam[q][b];
+            double val;
+            if (w0) val = (form == EGFEM_FORM_STIFF) ? kab : g.vol * (a == b ? m2_diag : m2_off);
+            else val = (form == EGFEM_FORM_STIFF) ? qw[q] * kab : qw[q] * g.vol * qlam[q][a] * qlam[q][b];
             const size_t idx = (size_t)loc[b] * nw + (size_t)ce * nq + q;
             acc[idx] += val;
             present[idx] = 1;
@@ -628,7 +636,7 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
   if (w2) {
     jpS.assign((size_t)wslots + 1, 0);
     wpq.assign((size_t)wslots, 0);
-    if (wq) wpq2.assign((size_t)wslots, 0);
+    if (wq || w0) wpq2.assign((size_t)wslots, 0);
     wmeta.assign((blk.size() - 1) * 2, 0);
     for (size_t b = 0; b + 1 < blk.size(); ++b) {
       const int32_t s0 = rowptr[blk[b]], w0 = wrowptr[blk[b]];
@@ -643,7 +651,7 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
         for (int32_t w = wrowptr[i]; w < wrowptr[i + 1]; ++w) {
           for (int32_t p = jptrB[w]; p < jptrB[w + 1]; ++p) jS[p] = (uint16_t)(vb + jRel[p]);
           wpq[w] = (uint32_t)(vb + wpl[w]) | ((uint32_t)(vb + wql[w]) << 16);
-          if (wq) wpq2[w] = (uint32_t)(vb + wpl2[w]) | ((uint32_t)(vb + wql2[w]) << 16);
+          if (wq || w0) wpq2[w] = (uint32_t)(vb + wpl2[w]) | ((uint32_t)(vb + wql2[w]) << 16);
         }
       }
     }
@@ -721,8 +729,8 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
   T->krylov_lanes = klanes;
   T->krylov_rs = row_shape_for(max_row_slots, klanes);
   T->row_blocks = (int64_t)blk.size() - 1;
-  T->w2 = w2 ? (wq ? 2 : 1) : 0;
-  T->n_w = wq ? n_cells * nq : (w2 ? N + (int64_t)ekeys.size() : N);
+  T->w2 = w0 ? 3 : (w2 ? (wq ? 2 : 1) : 0);
+  T->n_w = (wq || w0) ? n_cells * nq : (w2 ? N + (int64_t)ekeys.size() : N);
   T->nq = nq;
   T->wslots = wslots;
   T->max_row_wslots = w2 ? max_row_wslots : max_row_slots;
@@ -763,7 +771,26 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
     T->nnz_h = (int64_t)vH.size();
     T->action_half = 0;   // the autotuner switches to it where it is faster
   }
-  if (wq) {
+  if (w0) {
+    // the gradient interpolation: vertex ids (padded to 4) and grad lambda_m
+    // (4 x 3 doubles, zero padded) of every cell
+    std::vector<int32_t> c4((size_t)n_cells * 4);
+    std::vector<double> gr((size_t)n_cells * 12, 0.0);
+    for (int64_t e = 0; e < n_cells; ++e) {
+      const int32_t* c = cells + e * nl;
+      for (int m = 0; m < 4; ++m) c4[4 * e + m] = c[m < nl ? m : 0];
+      for (int m = 0; m < nl; ++m)
+        for (int r = 0; r < dim; ++r) gr[12 * e + 3 * m + r] = geo[e].G[m][r];
+    }
+    int32_t* d4 = nullptr;
+    if (rc == EGFEM_OK) rc = upload(c4, &d4, &bytes);
+    T->e_cell4 = reinterpret_cast<int4*>(d4);
+    if (rc == EGFEM_OK) rc = upload(gr, &T->e_grad, &bytes);
+    if (rc == EGFEM_OK) rc = hipMalloc((void**)&T->e_acoef, (size_t)n_cells * sizeof(double)) == hipSuccess
+                                ? EGFEM_OK : fail(EGFEM_ERR_OOM, "hipMalloc of the cell coefficients failed");
+    bytes += n_cells * (int64_t)sizeof(double);
+  }
+  if (wq || w0) {
     std::vector<double> ql(16, 0.0);
     for (int q = 0; q < nq; ++q)
       for (int m = 0; m < 4; ++m) ql[4 * q + m] = qlam[q][m];

@@ -88,7 +88,8 @@ struct egfem_tensor_s {
   int krylov_kernel = 0;        // 0: register-resident where it fits, 1: streaming
   int device = 0;
   // W_h = P2 (Case 1, w2 = 1): k runs over the P2 dofs (vertices, then edges);
-  // W_h = I_k (Case 3, w2 = 2): k runs over the quadrature points of the cells
+  // W_h = I_k (Case 3, w2 = 2): k runs over the quadrature points of the cells;
+  // W_h = P0 (w2 = 3): k runs over the cells (gradient nonlinearities)
   int w2 = 0;
   int nq = 0;                   // I_k: points per cell
   int64_t n_w = 0;              // dofs of W_h (n for P1)
@@ -132,6 +133,8 @@ struct egfem_tensor_s {
   double* e_kp = nullptr;       // [cells * kstride] packed K^e (row-major upper triangle)
   int32_t* e_nptr = nullptr;    // [n+1] incidence range of every node
   int32_t* e_inc = nullptr;     // [incidences] cell << 2 | local index
+  double* e_grad = nullptr;     // W_h = P0: [cells * 12] grad lambda_m of every cell (4 x 3, padded)
+  double* e_acoef = nullptr;    // W_h = P0: [cells] coefficient buffer of egfem_picard_grad
   uint32_t* wpq2 = nullptr;     // I_k: [wslots] slots of the third and fourth cell vertex
   uint8_t* wqi = nullptr;       // I_k: [wslots] point index
   double* qlam = nullptr;       // I_k: [4*4] barycentrics of the points
@@ -176,6 +179,9 @@ struct ProblemView {
 int64_t action_runs(const egfem_tensor_s* T);
 hipError_t launch_action_raw(const egfem_tensor_s* T, const double* u, const double* a, double* r,
                              hipStream_t st);
+// a_e = (c0 + c1 |grad u_h|_e|^2)^q over the cells of a W_h = P0 handle (linear: a_e = 1).
+hipError_t launch_grad_coef(const egfem_tensor_s* T, const double* u, double c0, double c1, double q, int linear,
+                            double* a, hipStream_t st);
 hipError_t launch_action_elementwise(const egfem_tensor_s* T, const double* u, const double* a, double* r,
                                      hipStream_t st);
 hipError_t launch_action_problem(const egfem_tensor_s* T, const ProblemView& pv, const double* u,

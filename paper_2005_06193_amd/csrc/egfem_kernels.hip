@@ -235,6 +235,35 @@ __global__ __launch_bounds__(kBlockThreads) void k_action_elem(int64_t n, const 
   if (row < n && lane == 0) r[row] = acc;
 }
 
+// Coefficient of a gradient nonlinearity per cell (W_h = P0, the gradient
+// interpolation of Sec. 3.2): z = sum_m u_{c_m} grad lambda_m, a_e = (c0 + c1 |z|^2)^q.
+template <int D>
+__global__ __launch_bounds__(kBlockThreads) void k_grad_coef(int64_t ncell, const int4* __restrict__ cell4,
+                                                             const double* __restrict__ grad,
+                                                             const double* __restrict__ u, double c0, double c1,
+                                                             double q, int linear, double* __restrict__ a) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ncell) return;
+  if (linear) {
+    a[e] = 1.0;
+    return;
+  }
+  const int4 c = cell4[e];
+  const int cv[4] = {c.x, c.y, c.z, c.w};
+  const double* G = grad + 12 * e;
+  double z[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int m = 0; m <= D; ++m) {
+    const double um = u[cv[m]];
+#pragma unroll
+    for (int r = 0; r < D; ++r) z[r] = fma(um, G[3 * m + r], z[r]);
+  }
+  double s2 = 0.0;
+#pragma unroll
+  for (int r = 0; r < D; ++r) s2 = fma(z[r], z[r], s2);
+  a[e] = pow(fma(c1, s2, c0), q);
+}
+
 // Per-workgroup partial sums of (x_i - u_i)^2 and x_i^2 (grid-stride rows):
 // partial[2 g], partial[2 g + 1].
 __global__ __launch_bounds__(kBlockThreads) void k_diff_norms(int64_t n, const double* __restrict__ x,
@@ -419,7 +448,7 @@ int64_t action_runs(const egfem_tensor_s* T) {
 hipError_t launch_action_raw(const egfem_tensor_s* T, const double* u, const double* a, double* r,
                              hipStream_t st) {
   if (T->w2) {
-    auto kern = T->w2 == 2 ? k_action_w2<false, 2> : k_action_w2<false, 1>;
+    auto kern = T->w2 == 1 ? k_action_w2<false, 1> : k_action_w2<false, 2>;
     hipLaunchKernelGGL(kern, dim3(xcd_grid(T->row_blocks)), dim3(kBlockThreads), 0, st, view_of(T), u, nullptr,
                        0.0, a, 0.0, nullptr, nullptr, nullptr, r, nullptr, nullptr);
     return hipGetLastError();
@@ -454,6 +483,15 @@ static void elem_launch_l(const egfem_tensor_s* T, const double* u, const double
   }
 }
 
+hipError_t launch_grad_coef(const egfem_tensor_s* T, const double* u, double c0, double c1, double q, int linear,
+                            double* a, hipStream_t st) {
+  const int64_t E = T->n_cells;
+  auto kern = T->dim == 1 ? k_grad_coef<1> : (T->dim == 2 ? k_grad_coef<2> : k_grad_coef<3>);
+  hipLaunchKernelGGL(kern, dim3(grid1d(E)), dim3(kBlockThreads), 0, st, E, T->e_cell4, T->e_grad, u, c0, c1, q,
+                     linear, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_action_elementwise(const egfem_tensor_s* T, const double* u, const double* a, double* r,
                                      hipStream_t st) {
   switch (T->dim) {
@@ -468,7 +506,7 @@ hipError_t launch_action_problem(const egfem_tensor_s* T, const ProblemView& pv,
                                  const double* delta, double alpha, double* uout, double* F,
                                  double* partial, hipStream_t st) {
   if (T->w2) {
-    auto kern = T->w2 == 2 ? k_action_w2<true, 2> : k_action_w2<true, 1>;
+    auto kern = T->w2 == 1 ? k_action_w2<true, 1> : k_action_w2<true, 2>;
     hipLaunchKernelGGL(kern, dim3(xcd_grid(T->row_blocks)), dim3(kBlockThreads), 0, st, view_of(T), u, delta,
                        alpha, pv.a0, pv.a0c, pv.load, pv.dir, pv.addK ? T->kval : nullptr, F, uout, partial);
     return hipGetLastError();
@@ -491,7 +529,7 @@ hipError_t launch_jacobian(const egfem_tensor_s* T, const double* u, const doubl
                            int dadu_2u, int addK, const uint8_t* dir, double* jval, double* dinv,
                            hipStream_t st) {
   if (T->w2) {
-    auto kern = T->w2 == 2 ? k_jacobian_w2<2> : k_jacobian_w2<1>;
+    auto kern = T->w2 == 1 ? k_jacobian_w2<1> : k_jacobian_w2<2>;
     hipLaunchKernelGGL(kern, dim3(xcd_grid(T->row_blocks)), dim3(kBlockThreads), 0, st, view_of(T), u, a, a0, a0c,
                        use_problem_a, dadu, dadu_2u, addK ? T->kval : nullptr, dir, jval, dinv);
     return hipGetLastError();
