@@ -449,6 +449,43 @@ def p2_suite(n: int, shape: dict, wspace: int, reps: int = 3):
             "action_entries_per_s": info.nnz / (st.t_action_ms / max(st.n_action, 1) * 1e-3)}
 
 
+def gradient_suite(n: int = 256, reps: int = 2):
+    """The p-Laplace example (p = 3/2, unit disk, source 1) with W_h = P0 and the
+    gradient interpolation, solved by Picard iteration to a relative update 1e-12."""
+    import numpy as np
+    import torch
+    import paper_2005_06193_amd as eg
+    import workloads as W
+    wl = W.plaplace_disk(n)
+    T = eg.Tensor.from_mesh(wl.mesh, W.FORM_STIFF, wspace=eg.W_P0)
+    p = eg.Problem(T.n, T.matvec(torch.tensor(wl.f, dtype=torch.float64, device="cuda"), "M"),
+                   torch.tensor(wl.mesh.dirichlet, dtype=torch.uint8, device="cuda"))
+    u = torch.zeros(T.n, dtype=torch.float64, device="cuda")
+    T.picard_grad(p, u, wl.c0, wl.c1, wl.q)                      # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        u.zero_()
+        st = T.picard_grad(p, u, wl.c0, wl.c1, wl.q)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    u.zero_()
+    stt = T.picard_grad(p, u, wl.c0, wl.c1, wl.q, opts=eg.PicardOptions(timing=1))
+    err = float(np.linalg.norm(u.cpu().numpy() - wl.exact) / np.linalg.norm(wl.exact))
+    out = {"workload": wl.name, "nodes": T.n, "cells": T.info.n_w, "tensor_nnz": T.info.nnz,
+           "ms_per_solve": el * 1e3, "solves_per_s": 1.0 / el, "status": st.status_name,
+           "picard_iters": st.picard_iters, "cg_iters_per_solve": st.krylov_iters,
+           "matrix_ms_per_solve": stt.t_matrix_ms, "cg_ms_per_solve": stt.t_krylov_ms,
+           "rel_l2_error_vs_exact": err}
+    T.close()
+    return out
+
+
+def stage(name: str):
+    """One progress line per benchmark stage on stderr (the JSON line is stdout)."""
+    print(f"[bench] {name}", file=sys.stderr, flush=True)
+
+
 def burgers_suite(n: int = 256, reps: int = 2):
     """The Burgers experiment of Sec. 5.2 (nu = 1, T = 1, dt = 1e-2: 100
     semi-implicit steps) on the 2D n x n mesh, tensor and group formulations."""
@@ -490,7 +527,7 @@ def burgers_suite(n: int = 256, reps: int = 2):
     return out
 
 
-def cpu_baseline(n: int, budget_s: float = 20.0):
+def cpu_baseline(n: int, budget_s: float = 20.0, gradient: bool = False):
     """The CPU oracle (numpy/scipy, SuperLU direct solves) on the same workload:
     EGFEM Newton solves, plus one SGA (re-assembly) solve for context."""
     import numpy as np
@@ -515,6 +552,14 @@ def cpu_baseline(n: int, budget_s: float = 20.0):
         t0 = time.perf_counter()
         _, pst = O.picard(prob, tol=1e-12)
         t_pic = time.perf_counter() - t0
+        # p-Laplace (W_h = P0): 5 Picard iterations
+        t_grad = None
+        if gradient:
+            gw = W.plaplace_disk(n)
+            gp = O.build_grad_problem(gw)
+            t0 = time.perf_counter()
+            O.picard_grad(gp, tol=0.0, max_iter=5)
+            t_grad = (time.perf_counter() - t0) / 5
         # Burgers (Sec. 5.2): 10 of the 100 semi-implicit steps, tensor formulation
         bw = W.burgers_2d(n)
         bsys = O.burgers_system(bw.mesh.coords, bw.mesh.cells, bw.mesh.dirichlet, bw.dt, bw.nu)
@@ -531,10 +576,13 @@ def cpu_baseline(n: int, budget_s: float = 20.0):
                   f"(numpy/scipy, SuperLU direct solves, tol 1e-10), mean {egfem_s:.3f} s; "
                   f"one SGA re-assembly Newton solve took {t_sga:.3f} s, one EGFEM Picard solve "
                   f"(update 1e-12, {pst.iterations} iterations) {t_pic:.3f} s, 10 Burgers steps "
-                  f"(tensor formulation, one LU of M + dt nu K) {10 * t_burg:.3f} s",
+                  f"(tensor formulation, one LU of M + dt nu K) {10 * t_burg:.3f} s"
+                  + (f", 5 p-Laplace Picard iterations (W_h = P0, disk) {5 * t_grad:.3f} s"
+                     if t_grad is not None else ""),
         "sga_solves_per_s": 1.0 / t_sga,
         "picard_solves_per_s": 1.0 / t_pic,
         "burgers_ms_per_step": 1e3 * t_burg,
+        "plaplace_ms_per_picard_iter": 1e3 * t_grad if t_grad is not None else None,
         "cpu": _cpu_model(),
     }
 
@@ -563,6 +611,8 @@ def main():
     ap.add_argument("--no-picard", action="store_true", help="skip the Picard iteration")
     ap.add_argument("--no-burgers", action="store_true", help="skip the Burgers time stepping")
     ap.add_argument("--no-p2", action="store_true", help="skip the W_h = P2 / I_k coefficient solves")
+    ap.add_argument("--gradient", action="store_true",
+                    help="also time the p-Laplace (W_h = P0) solves and their oracle sample (off by default)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -626,13 +676,21 @@ def main():
                                % tr["krylov_bicgstab"]["ratio"] if traffic is not None else ""))
                 if dom == "krylov_bicgstab" else None}
 
+    stage("tensor actions")
     micro = None if args.no_micro else tensor_action_suite()
     if micro is not None:
         micro["stream_ceiling"] = stream_ceiling()
+    stage("batched")
     batched = None if args.no_batched else batched_suite()
+    stage("adjoint")
     adjoint = None if args.no_adjoint else adjoint_suite()
+    stage("picard")
     picard = None if args.no_picard else picard_suite(T, p)
+    stage("burgers")
     burgers = None if args.no_burgers else burgers_suite(args.n)
+    stage("gradient")
+    gradient = gradient_suite(args.n) if args.gradient else None
+    stage("coefficient spaces")
     p2 = None if args.no_p2 else wspace_suite(args.n, tuned["shape"])
 
     if args.copy_probe:
@@ -642,7 +700,8 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
 
-    cpu = None if args.no_cpu else cpu_baseline(args.n)
+    stage("cpu baseline")
+    cpu = None if args.no_cpu else cpu_baseline(args.n, gradient=args.gradient)
     out = {
         "metric": METRIC,
         "value": solves_per_s,
@@ -670,6 +729,7 @@ def main():
         "adjoint": adjoint,
         "picard": picard,
         "burgers": burgers,
+        "gradient_p0": gradient,
         "coefficient_spaces": p2,
         "cpu_baseline": cpu,
     }

@@ -159,11 +159,11 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
     return fail(EGFEM_ERR_ARG, "the convection form is built with W_h = P1 only");
   const bool w2 = (wspace != EGFEM_W_P1);     // a coefficient space with W-slots
   const bool wq = (wspace == EGFEM_W_IQ);
-  const bool w0 = (wspace == EGFEM_W_P0);   // one coefficient per cell
+  const bool wcell = (wspace == EGFEM_W_P0);   // one coefficient per cell
   // quadrature rule of W_h = I_k: barycentrics (padded to 4) and weights / |e|
   int nq = 0;
   double qlam[4][4] = {{0}}, qw[4] = {0};
-  if (w0) {
+  if (wcell) {
     // the indicator of the cell: one "point" with weight 1 (|e| folded into the
     // values); no barycentric weights are used
     nq = 1;
@@ -263,7 +263,7 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
         ++t;
       }
   }
-  if ((wq || w0) && n_cells * nq >= (int64_t(1) << 31)) return fail(EGFEM_ERR_SHAPE, "too many quadrature points");
+  if ((wq || wcell) && n_cells * nq >= (int64_t(1) << 31)) return fail(EGFEM_ERR_SHAPE, "too many quadrature points");
   std::vector<int64_t> ekeys;   // min * N + max of every edge
   if (w2 && !wq) {
     ekeys.reserve((size_t)n_cells * ne_loc);
@@ -308,7 +308,7 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
     auto lidx = [&](int32_t node) {
       return (int)(std::lower_bound(cols.begin(), cols.end(), node) - cols.begin());
     };
-    if (wq || w0) {
+    if (wq || wcell) {
       // W-slots of row i: the points of its cells (ascending cell, then point);
       // for W_h = P0 the cells themselves
       const int ncl = (int)(nptr[i + 1] - nptr[i]);
@@ -334,7 +334,7 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
           macc[loc[b]] += g.vol * (a == b ? m2_diag : m2_off);
           for (int q = 0; q < nq; ++q) {
             double val;
-            if (w0) val = (form == EGFEM_FORM_STIFF) ? kab : g.vol * (a == b ? m2_diag : m2_off);
+            if (wcell) val = (form == EGFEM_FORM_STIFF) ? kab : g.vol * (a == b ? m2_diag : m2_off);
             else val = (form == EGFEM_FORM_STIFF) ? qw[q] * kab : qw[q] * g.vol * qlam[q][a] * qlam[q][b];
             const size_t idx = (size_t)loc[b] * nw + (size_t)ce * nq + q;
             acc[idx] += val;
@@ -636,7 +636,7 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
   if (w2) {
     jpS.assign((size_t)wslots + 1, 0);
     wpq.assign((size_t)wslots, 0);
-    if (wq || w0) wpq2.assign((size_t)wslots, 0);
+    if (wq || wcell) wpq2.assign((size_t)wslots, 0);
     wmeta.assign((blk.size() - 1) * 2, 0);
     for (size_t b = 0; b + 1 < blk.size(); ++b) {
       const int32_t s0 = rowptr[blk[b]], w0 = wrowptr[blk[b]];
@@ -651,7 +651,7 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
         for (int32_t w = wrowptr[i]; w < wrowptr[i + 1]; ++w) {
           for (int32_t p = jptrB[w]; p < jptrB[w + 1]; ++p) jS[p] = (uint16_t)(vb + jRel[p]);
           wpq[w] = (uint32_t)(vb + wpl[w]) | ((uint32_t)(vb + wql[w]) << 16);
-          if (wq || w0) wpq2[w] = (uint32_t)(vb + wpl2[w]) | ((uint32_t)(vb + wql2[w]) << 16);
+          if (wq || wcell) wpq2[w] = (uint32_t)(vb + wpl2[w]) | ((uint32_t)(vb + wql2[w]) << 16);
         }
       }
     }
@@ -729,8 +729,8 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
   T->krylov_lanes = klanes;
   T->krylov_rs = row_shape_for(max_row_slots, klanes);
   T->row_blocks = (int64_t)blk.size() - 1;
-  T->w2 = w0 ? 3 : (w2 ? (wq ? 2 : 1) : 0);
-  T->n_w = (wq || w0) ? n_cells * nq : (w2 ? N + (int64_t)ekeys.size() : N);
+  T->w2 = wcell ? 3 : (w2 ? (wq ? 2 : 1) : 0);
+  T->n_w = (wq || wcell) ? n_cells * nq : (w2 ? N + (int64_t)ekeys.size() : N);
   T->nq = nq;
   T->wslots = wslots;
   T->max_row_wslots = w2 ? max_row_wslots : max_row_slots;
@@ -771,7 +771,7 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
     T->nnz_h = (int64_t)vH.size();
     T->action_half = 0;   // the autotuner switches to it where it is faster
   }
-  if (w0) {
+  if (wcell) {
     // the gradient interpolation: vertex ids (padded to 4) and grad lambda_m
     // (4 x 3 doubles, zero padded) of every cell
     std::vector<int32_t> c4((size_t)n_cells * 4);
@@ -790,7 +790,7 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
                                 ? EGFEM_OK : fail(EGFEM_ERR_OOM, "hipMalloc of the cell coefficients failed");
     bytes += n_cells * (int64_t)sizeof(double);
   }
-  if (wq || w0) {
+  if (wq || wcell) {
     std::vector<double> ql(16, 0.0);
     for (int q = 0; q < nq; ++q)
       for (int m = 0; m < 4; ++m) ql[4 * q + m] = qlam[q][m];
