@@ -611,8 +611,7 @@ def main():
     ap.add_argument("--no-picard", action="store_true", help="skip the Picard iteration")
     ap.add_argument("--no-burgers", action="store_true", help="skip the Burgers time stepping")
     ap.add_argument("--no-p2", action="store_true", help="skip the W_h = P2 / I_k coefficient solves")
-    ap.add_argument("--gradient", action="store_true",
-                    help="also time the p-Laplace (W_h = P0) solves and their oracle sample (off by default)")
+    ap.add_argument("--no-gradient", action="store_true", help="skip the p-Laplace (W_h = P0) solves")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -689,7 +688,7 @@ def main():
     stage("burgers")
     burgers = None if args.no_burgers else burgers_suite(args.n)
     stage("gradient")
-    gradient = gradient_suite(args.n) if args.gradient else None
+    gradient = None if args.no_gradient else gradient_suite(args.n)
     stage("coefficient spaces")
     p2 = None if args.no_p2 else wspace_suite(args.n, tuned["shape"])
 
@@ -701,7 +700,7 @@ def main():
         torch.cuda.synchronize()
 
     stage("cpu baseline")
-    cpu = None if args.no_cpu else cpu_baseline(args.n, gradient=args.gradient)
+    cpu = None if args.no_cpu else cpu_baseline(args.n, gradient=not args.no_gradient)
     out = {
         "metric": METRIC,
         "value": solves_per_s,
