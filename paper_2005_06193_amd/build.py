@@ -27,6 +27,8 @@ CFLAGS = [
     # no packed FP32 instructions anywhere in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
+    # a shadowed name once turned a flag into a loop index: keep it an error
+    "-Werror=shadow",
     "-I", os.path.join(ROOT, "include"),
 ]
 
