@@ -913,6 +913,42 @@ def picard_grad(p: GradProblem, u0: Optional[np.ndarray] = None, tol: float = 1e
     return u, max_iter
 
 
+def jacobian_grad(p: GradProblem, u: np.ndarray) -> sp.csr_matrix:
+    """DF(u) for F = T:(u (x) a(grad u)) - d with a_e = (c0 + c1 |z_e|^2)^q, z_e = grad u_h|_e:
+    the product rule gives, per cell, a_e K^e plus the derivative of a_e,
+    d a_e / d u_j = a'_e z_e . grad lambda_j with a'_e = 2 q c1 (c0 + c1 |z_e|^2)^(q-1),
+    times (K^e u_e)_i = |e| grad lambda_i . z_e.  Free rows and columns only;
+    Dirichlet rows identity."""
+    det, G = element_geometry(p.coords, p.cells)
+    dim = p.coords.shape[1]
+    vol = det / math.factorial(dim)
+    z = np.einsum("ea,ead->ed", u[p.cells], G)
+    base = p.c0 + p.c1 * np.sum(z * z, axis=1)
+    keep = p.free[p.cells].any(axis=1)          # cells with a free vertex
+    with np.errstate(divide="ignore", invalid="ignore"):
+        a = np.where(keep, base, 1.0) ** p.q
+        ap = 2.0 * p.q * p.c1 * np.where(keep, base, 1.0) ** (p.q - 1.0)
+    GG = np.einsum("ead,ebd->eab", G, G)
+    gz = np.einsum("ead,ed->ea", G, z)
+    Je = vol[:, None, None] * (a[:, None, None] * GG + ap[:, None, None] * gz[:, :, None] * gz[:, None, :])
+    nl = dim + 1
+    rows = np.repeat(p.cells, nl, axis=1).ravel()
+    cols = np.tile(p.cells, (1, nl)).ravel()
+    vals = Je.reshape(-1)
+    m = p.free[rows] & p.free[cols]
+    J = sp.coo_matrix((vals[m], (rows[m], cols[m])), shape=(p.n, p.n)).tocsr()
+    return (J + sp.diags(p.dirichlet.astype(np.float64))).tocsr()
+
+
+def newton_grad(p: GradProblem, tol: float = 1e-10, max_iter: int = 50):
+    """Damped Newton (the rule of `newton`) for the gradient nonlinearity,
+    started from the Laplace solution (the first Picard step with a = 1).
+    Returns (u, NewtonStats)."""
+    u0, _ = picard_grad(p, tol=0.0, max_iter=1)
+    return newton(p, u0, tol, max_iter, residual_fn=lambda v: residual_grad(p, v),
+                  jacobian_fn=lambda v: jacobian_grad(p, v))
+
+
 # ----------------------------------------------------------------------------
 # adjoint of the converged solve (implicit function theorem)
 # ----------------------------------------------------------------------------

@@ -716,3 +716,23 @@ def test_plaplace_disk_converges_to_exact_solution():
         errs.append(np.linalg.norm(u - wl.exact) / np.linalg.norm(wl.exact))
     assert errs[2] < 2e-3
     assert 3.0 < errs[0] / errs[1] < 5.0 and 3.0 < errs[1] / errs[2] < 5.0
+
+
+def test_gradient_newton_jacobian_and_fixed_point():
+    """The analytic Jacobian of the gradient nonlinearity passes the Taylor test
+    (remainder O(eps^2)), and damped Newton reaches the Picard fixed point."""
+    cases = [W.GradientWorkload("ms", W.mesh_2d(16), np.ones(17 * 17), 0.0, 1.0, 1.0, -0.5, None),
+             W.plaplace_disk(16)]
+    for wl in cases:
+        P = O.build_grad_problem(wl)
+        u, _ = O.picard_grad(P, tol=1e-12)
+        v = np.random.default_rng(3).uniform(-1, 1, P.n)
+        v[P.dirichlet] = 0.0
+        J = O.jacobian_grad(P, u)
+        F0 = O.residual_grad(P, u)
+        rem = [np.linalg.norm(O.residual_grad(P, u + e * v) - F0 - e * (J @ v)) for e in (1e-3, 1e-4, 1e-5)]
+        assert rem[1] < rem[0] / 30 and rem[2] < rem[1] / 60, rem
+        assert abs(J - J.T).max() <= 1e-13 * abs(J).max()            # symmetric
+        un, st = O.newton_grad(P, tol=1e-13)
+        assert st.status == "converged" and st.iterations <= 10
+        assert np.linalg.norm(un - u) <= 1e-10 * np.linalg.norm(u)
