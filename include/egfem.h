@@ -455,6 +455,19 @@ typedef struct {
 int egfem_picard_grad(egfem_tensor_t T, const egfem_problem* p, const egfem_grad_coef* g, double* u,
                       const egfem_picard_opts* o, egfem_picard_stats* s, void* stream);
 
+/* egfem_newton_grad: damped Newton for the same problem (the rules of
+ * egfem_newton: full steps halved while ||F|| does not fall by the factor
+ * 1 - 1e-4 alpha, Eisenstat-Walker or fixed inner tolerance).  The Jacobian
+ *     DF = T . a(grad u) + sum_e (K^e u_e) (x) (d a_e / d u),
+ *     d a_e / d u_j = 2 q c1 (c0 + c1 |z_e|^2)^(q-1) z_e . grad lambda_j,
+ * is symmetric; it is emitted by the W-slot stage with per-cell weights and
+ * solved by Jacobi-CG (BiCGStab if CG meets a non-positive curvature).  With
+ * g->start_linear, u is first replaced by the Laplace solution (a = 1, CG to
+ * 1e-12), the start from which s->res0 is measured.  Returns the status
+ * (EGFEM_STAGNATED as for egfem_newton) or EGFEM_ERR_ARG.  Synchronises. */
+int egfem_newton_grad(egfem_tensor_t T, const egfem_problem* p, const egfem_grad_coef* g, double* u,
+                      const egfem_newton_opts* o, egfem_newton_stats* s, void* stream);
+
 /* ------------------------------------------------------------------------
  * Launch shapes and the autotuner.
  * ---------------------------------------------------------------------- */

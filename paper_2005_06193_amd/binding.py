@@ -167,6 +167,8 @@ EXPORTS = {
                                 C.POINTER(_BurgersOpts), C.POINTER(_BurgersStats), C.c_void_p]),
     "egfem_picard_grad": (C.c_int, [C.c_void_p, C.POINTER(_Problem), C.POINTER(_GradCoef), C.c_void_p,
                                     C.POINTER(_PicardOpts), C.POINTER(_PicardStats), C.c_void_p]),
+    "egfem_newton_grad": (C.c_int, [C.c_void_p, C.POINTER(_Problem), C.POINTER(_GradCoef), C.c_void_p,
+                                    C.POINTER(_Opts), C.POINTER(_Stats), C.c_void_p]),
     "egfem_solve_cg": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int,
                                  C.POINTER(C.c_int), C.POINTER(C.c_double), C.c_void_p]),
     "egfem_last_error": (C.c_char_p, []),
@@ -636,6 +638,22 @@ class Tensor:
         stats = PicardStats.from_c(st)
         if rc != EGFEM_OK and warn:
             warnings.warn(f"egfem_picard_grad ended with status {stats.status_name}")
+        return stats
+
+    def newton_grad(self, p: Problem, u: torch.Tensor, c0: float, c1: float, q: float,
+                    start_linear: bool = True, opts: Optional[NewtonOptions] = None,
+                    warn: bool = True) -> NewtonStats:
+        """Damped Newton for a(grad u) = (c0 + c1 |grad u|^2)^q on a W_h = P0 handle."""
+        o = (opts or NewtonOptions()).c()
+        pc = p.c()
+        g = _GradCoef(float(c0), float(c1), float(q), int(bool(start_linear)))
+        st = _Stats()
+        rc = load_library().egfem_newton_grad(self.handle, C.byref(pc), C.byref(g), _dptr(u, n=self.n),
+                                              C.byref(o), C.byref(st), _stream())
+        _check(rc, allow_positive=True)
+        stats = NewtonStats.from_c(st)
+        if rc != EGFEM_OK and warn:
+            warnings.warn(f"egfem_newton_grad ended with status {stats.status_name}")
         return stats
 
     def burgers(self, u: torch.Tensor, dirichlet: Optional[torch.Tensor] = None,

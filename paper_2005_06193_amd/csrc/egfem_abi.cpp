@@ -155,7 +155,8 @@ void egfem_tensor_destroy(egfem_tensor_t T) {
   void* ptrs[] = {T->rowptr, T->col,  T->diag,    T->tperm,    T->kptrA, T->kA,   T->vA,   T->kS,
                   T->kpS,    T->kval, T->mval,    T->blk_row,  T->blk_meta, T->wrowptr, T->wcol, T->wpq,
                   T->wmeta,  T->wpq2, T->wqi,       T->qlam,   T->e_cell4, T->e_kp,    T->e_nptr,
-                  T->e_inc,  T->kSH,  T->vH,        T->kpSH,   T->hmeta,   T->e_grad,  T->e_acoef};
+                  T->e_inc,  T->kSH,  T->vH,        T->kpSH,   T->hmeta,   T->e_grad,  T->e_acoef,
+                  T->e_wv};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (!T->symmetric) {
@@ -666,7 +667,7 @@ int egfem_picard_grad(egfem_tensor_t T, const egfem_problem* p, const egfem_grad
   std::vector<double> part(512);
   // ||F(u)|| over the free rows, F = T:(u (x) a(grad u)) - d
   auto residual_norm = [&](double* out) -> int {
-    EGFEM_HIP_CHECK(launch_grad_coef(T, u, g->c0, g->c1, g->q, 0, a, st));
+    EGFEM_HIP_CHECK(launch_grad_coef(T, u, g->c0, g->c1, g->q, 0, a, nullptr, st));
     EGFEM_HIP_CHECK(launch_action_raw(T, u, a, W.F, st));
     EGFEM_HIP_CHECK(launch_mask_zero(W.F, p->dirichlet, T->n, st));
     hipError_t e = hipSuccess;
@@ -689,7 +690,8 @@ int egfem_picard_grad(egfem_tensor_t T, const egfem_problem* p, const egfem_grad
   while (status == EGFEM_NOT_CONVERGED && k < opts.max_picard) {
     // a^n = a(Pi_grad u^n) per cell (a = 1 on the first step with start_linear)
     EGFEM_TRY_RC(tm.start());
-    EGFEM_HIP_CHECK(launch_grad_coef(T, u, g->c0, g->c1, g->q, (k == 0 && g->start_linear) ? 1 : 0, a, st));
+    EGFEM_HIP_CHECK(
+        launch_grad_coef(T, u, g->c0, g->c1, g->q, (k == 0 && g->start_linear) ? 1 : 0, a, nullptr, st));
     // (T . a^n) with Dirichlet identity rows and zero columns, and 1/diag
     EGFEM_HIP_CHECK(launch_jacobian(T, u, a, nullptr, 0.0, 0, nullptr, 0, 0, p->dirichlet, W.jval, W.dinv, st));
     EGFEM_TRY_RC(tm.stop(&stats.t_matrix_ms, &n_dummy));
@@ -724,6 +726,128 @@ int egfem_picard_grad(egfem_tensor_t T, const egfem_problem* p, const egfem_grad
   stats.res0 = 0.0;
   stats.status = status;
   stats.picard_iters = k;
+  if (s) *s = stats;
+  return status;
+}
+
+int egfem_newton_grad(egfem_tensor_t T, const egfem_problem* p, const egfem_grad_coef* g, double* u,
+                      const egfem_newton_opts* o, egfem_newton_stats* s, void* stream) {
+  if (!T || !p || !g || !u) return fail(EGFEM_ERR_ARG, "null argument");
+  if (T->w2 != 3) return fail(EGFEM_ERR_ARG, "the gradient coefficient needs a W_h = P0 handle");
+  if (p->a0 || p->add_stiffness) return fail(EGFEM_ERR_ARG, "the gradient problem takes no a0 and no K term");
+  if (!std::isfinite(g->c0) || !std::isfinite(g->c1) || !std::isfinite(g->q) || g->c0 < 0.0 || g->c1 < 0.0)
+    return fail(EGFEM_ERR_ARG, "coefficient parameters must be finite, c0 >= 0, c1 >= 0");
+  egfem_newton_opts opts;
+  egfem_newton_opts_default(&opts);
+  if (o) opts = *o;
+  int rc = check_opts(opts);
+  if (rc != EGFEM_OK) return rc;
+  rc = ensure_workspace(T);
+  if (rc != EGFEM_OK) return rc;
+  Workspace& W = T->ws;
+  hipStream_t st = (hipStream_t)stream;
+  egfem_newton_stats stats;
+  std::memset(&stats, 0, sizeof(stats));
+  LaunchTimer tm;
+  if ((rc = tm.init(opts.timing != 0, st)) != EGFEM_OK) return rc;
+  double* a = T->e_acoef;
+  double* wv = T->e_wv;
+  std::vector<double> part(256);
+  // F(x) = mask(T:(x (x) a(grad x)) - d) into W.F, ||F|| to the host
+  auto residual = [&](const double* x, double* nrm) -> int {
+    EGFEM_TRY_RC(tm.start());
+    EGFEM_HIP_CHECK(launch_grad_coef(T, x, g->c0, g->c1, g->q, 0, a, nullptr, st));
+    EGFEM_HIP_CHECK(launch_action_raw(T, x, a, W.F, st));
+    hipError_t e = hipSuccess;
+    const int ng = launch_sub_mask_norm(T->n, W.F, W.rhs, p->dirichlet, W.red, st, &e);
+    EGFEM_HIP_CHECK(e);
+    EGFEM_HIP_CHECK(hipMemcpyAsync(part.data(), W.red, ng * sizeof(double), hipMemcpyDeviceToHost, st));
+    EGFEM_HIP_CHECK(hipStreamSynchronize(st));
+    EGFEM_TRY_RC(tm.stop(&stats.t_action_ms, &stats.n_action));
+    double ss = 0.0;
+    for (int q = 0; q < ng; ++q) ss += part[q];
+    *nrm = std::sqrt(ss);
+    return EGFEM_OK;
+  };
+  // CG on the symmetric Jacobian, BiCGStab if CG meets a non-positive curvature
+  auto solve = [&](const double* rhs, double scale, double* x, bool x_zero, double rtol, KrylovResult* kr) -> int {
+    int r2 = krylov_solve(KrylovMethod::kCG, T, W.jval, W.dinv, rhs, scale, x, x_zero, rtol, false,
+                          opts.max_krylov, opts.krylov_blocks, kr, st, nullptr, tm.on, opts.krylov_threads);
+    if (r2 != EGFEM_OK || kr->status != EGFEM_BREAKDOWN) return r2;
+    return krylov_bicgstab(T, W.jval, W.dinv, rhs, scale, x, x_zero, rtol, opts.max_krylov, opts.krylov_blocks,
+                           kr, st, nullptr, tm.on, opts.krylov_threads);
+  };
+  EGFEM_HIP_CHECK(launch_mask_zero(u, p->dirichlet, T->n, st));
+  if (p->load) EGFEM_HIP_CHECK(launch_copy(W.rhs, p->load, T->n, st));
+  else EGFEM_HIP_CHECK(launch_fill(W.rhs, 0.0, T->n, st));
+  EGFEM_HIP_CHECK(launch_mask_zero(W.rhs, p->dirichlet, T->n, st));
+  if (g->start_linear) {
+    // u0: the Laplace solution (a = 1), solved to 1e-12 relative to d
+    EGFEM_HIP_CHECK(launch_grad_coef(T, u, g->c0, g->c1, g->q, 1, a, nullptr, st));
+    EGFEM_HIP_CHECK(launch_jacobian(T, u, a, nullptr, 0.0, 0, nullptr, 0, 0, p->dirichlet, W.jval, W.dinv, st));
+    KrylovResult kr;
+    if ((rc = solve(W.rhs, 1.0, u, true, 1e-12, &kr)) != EGFEM_OK) return rc;
+    stats.krylov_iters += kr.iters;
+    stats.krylov_kernels |= kr.resident ? 1 : 2;
+  }
+  double nF0 = 0.0;
+  if ((rc = residual(u, &nF0)) != EGFEM_OK) return rc;
+  stats.res0 = nF0;
+  int status = EGFEM_NOT_CONVERGED;
+  if (!std::isfinite(nF0)) status = EGFEM_NONFINITE;
+  else if (nF0 == 0.0) status = EGFEM_OK;
+  double nF = nF0, nF_prev = nF0, eta = opts.eta_max;
+  int k = 0;
+  while (status == EGFEM_NOT_CONVERGED) {
+    if (nF <= opts.tol * nF0) { status = EGFEM_OK; break; }
+    if (k >= opts.max_newton) break;
+    // DF(u) = T . a(u) + the derivative of a(u) applied to (K^e u)_i, and 1/diag
+    EGFEM_TRY_RC(tm.start());
+    EGFEM_HIP_CHECK(launch_grad_coef(T, u, g->c0, g->c1, g->q, 0, a, wv, st));
+    EGFEM_HIP_CHECK(launch_jacobian_grad(T, a, u, wv, p->dirichlet, W.jval, W.dinv, st));
+    EGFEM_TRY_RC(tm.stop(&stats.t_jacobian_ms, &stats.n_jacobian));
+    const double rtol = opts.forcing ? ew_forcing(k, nF, nF_prev, eta, opts.eta_max, opts.tol * nF0)
+                                     : opts.krylov_rtol;
+    eta = rtol;
+    KrylovResult kr;
+    if ((rc = solve(W.F, -1.0, W.delta, true, rtol, &kr)) != EGFEM_OK) return rc;
+    if (tm.on) {
+      stats.t_krylov_ms += kr.kernel_ms;
+      ++stats.n_krylov;
+    }
+    stats.krylov_iters += kr.iters;
+    stats.krylov_kernels |= kr.resident ? 1 : 2;
+    if (k < EGFEM_HIST) {
+      stats.krylov_hist[k] = kr.iters;
+      stats.krylov_status_hist[k] = kr.status;
+      stats.krylov_relres_hist[k] = kr.relres;
+    }
+    if (kr.status == EGFEM_NONFINITE) { status = EGFEM_NONFINITE; break; }
+    double alpha = 1.0, nFt = 0.0;
+    bool accepted = false;
+    for (int bt = 0; bt <= opts.max_backtracks; ++bt) {
+      EGFEM_HIP_CHECK(launch_axpy(W.utry, u, alpha, W.delta, T->n, st));
+      if ((rc = residual(W.utry, &nFt)) != EGFEM_OK) return rc;
+      if (std::isfinite(nFt) && nFt <= (1.0 - 1e-4 * alpha) * nF) { accepted = true; break; }
+      alpha *= 0.5;
+      ++stats.backtracks;
+    }
+    if (!accepted) {
+      status = EGFEM_STAGNATED;
+      if ((rc = residual(u, &nFt)) != EGFEM_OK) return rc;   // F at the last accepted iterate
+      break;
+    }
+    EGFEM_HIP_CHECK(launch_copy(u, W.utry, T->n, st));
+    nF_prev = nF;
+    nF = nFt;
+    if (k < EGFEM_HIST) stats.res_hist[k] = nF;
+    ++k;
+  }
+  if (status == EGFEM_NOT_CONVERGED && nF <= opts.tol * nF0) status = EGFEM_OK;
+  EGFEM_HIP_CHECK(hipStreamSynchronize(st));
+  stats.status = status;
+  stats.newton_iters = k;
+  stats.res = nF;
   if (s) *s = stats;
   return status;
 }

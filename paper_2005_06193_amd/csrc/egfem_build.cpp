@@ -788,7 +788,9 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
     if (rc == EGFEM_OK) rc = upload(gr, &T->e_grad, &bytes);
     if (rc == EGFEM_OK) rc = hipMalloc((void**)&T->e_acoef, (size_t)n_cells * sizeof(double)) == hipSuccess
                                 ? EGFEM_OK : fail(EGFEM_ERR_OOM, "hipMalloc of the cell coefficients failed");
-    bytes += n_cells * (int64_t)sizeof(double);
+    if (rc == EGFEM_OK) rc = hipMalloc((void**)&T->e_wv, (size_t)n_cells * 4 * sizeof(double)) == hipSuccess
+                                ? EGFEM_OK : fail(EGFEM_ERR_OOM, "hipMalloc of the cell weights failed");
+    bytes += n_cells * 5 * (int64_t)sizeof(double);
   }
   if (wq || wcell) {
     std::vector<double> ql(16, 0.0);

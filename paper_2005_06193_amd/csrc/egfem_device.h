@@ -808,7 +808,7 @@ __device__ void rowblock_jacobian_w2(const TensorView& T, int64_t b, const doubl
     wq[q] = T.wpq[w];
     wc[q] = T.wcol[w];
     wbp[q] = T.jpS[w];
-    if (WK == 2) {
+    if (WK >= 2) {
       wq2[q] = T.wpq2[w];
       wqq[q] = T.wqi[w];
     }
@@ -844,7 +844,8 @@ __device__ void rowblock_jacobian_w2(const TensorView& T, int64_t b, const doubl
       L.wpq[t] = wq[q];
       L.spbw[t] = wbp[q];
       if (!problem_a) L.aS[t] = a[wc[q]];
-      if (dadu) L.cW[t] = dadu[wc[q]];
+      // WK = 3 (cells): dadu holds 4 weights per cell, applied in the scatter
+      if (dadu) L.cW[t] = (WK == 3) ? 1.0 : dadu[wc[q]];
     }
   }
   if (tid == 0) {
@@ -911,10 +912,11 @@ __device__ void rowblock_jacobian_w2(const TensorView& T, int64_t b, const doubl
         const uint32_t pq = L.wpq[t];
         const int p0 = w_lo(pq), p1 = w_hi(pq);
         const double c = L.cW[t];
-        if (WK == 2) {
-          // (Pi_u)_kj = lambda_j(x_q) for the cell's vertices
+        if (WK >= 2) {
+          // I_k: (Pi_u)_kj = lambda_j(x_q) for the cell's vertices; cells (WK = 3):
+          // the weights d a_k / d u_j passed per cell
           const uint32_t pq2 = T.wpq2[wm.x + t];
-          const double* lam = T.qlam + 4 * T.wqi[wm.x + t];
+          const double* lam = (WK == 2) ? T.qlam + 4 * T.wqi[wm.x + t] : dadu + 4 * (int64_t)T.wcol[wm.x + t];
           L.bacc[p0] += lam[0] * c;
           L.bacc[p1] += lam[1] * c;
           L.bacc[w_lo(pq2)] += lam[2] * c;

@@ -134,7 +134,8 @@ struct egfem_tensor_s {
   int32_t* e_nptr = nullptr;    // [n+1] incidence range of every node
   int32_t* e_inc = nullptr;     // [incidences] cell << 2 | local index
   double* e_grad = nullptr;     // W_h = P0: [cells * 12] grad lambda_m of every cell (4 x 3, padded)
-  double* e_acoef = nullptr;    // W_h = P0: [cells] coefficient buffer of egfem_picard_grad
+  double* e_acoef = nullptr;    // W_h = P0: [cells] coefficient buffer of egfem_picard_grad / egfem_newton_grad
+  double* e_wv = nullptr;       // W_h = P0: [cells * 4] derivative weights of the Newton Jacobian
   uint32_t* wpq2 = nullptr;     // I_k: [wslots] slots of the third and fourth cell vertex
   uint8_t* wqi = nullptr;       // I_k: [wslots] point index
   double* qlam = nullptr;       // I_k: [4*4] barycentrics of the points
@@ -181,7 +182,15 @@ hipError_t launch_action_raw(const egfem_tensor_s* T, const double* u, const dou
                              hipStream_t st);
 // a_e = (c0 + c1 |grad u_h|_e|^2)^q over the cells of a W_h = P0 handle (linear: a_e = 1).
 hipError_t launch_grad_coef(const egfem_tensor_s* T, const double* u, double c0, double c1, double q, int linear,
-                            double* a, hipStream_t st);
+                            double* a, double* wv, hipStream_t st);
+// Newton Jacobian of a gradient nonlinearity (W_h = P0): T . a plus the
+// per-cell derivative weights wv [4 per cell] applied to (K^e u)_i.
+hipError_t launch_jacobian_grad(const egfem_tensor_s* T, const double* a, const double* u, const double* wv,
+                                const uint8_t* dir, double* jval, double* dinv, hipStream_t st);
+// F = mask(F - b) with partial sums of F^2 into partial[g] (returns the workgroup count, at most 256).
+int launch_sub_mask_norm(int64_t n, double* F, const double* b, const uint8_t* dir, double* partial, hipStream_t st,
+                         hipError_t* err);
+hipError_t launch_axpy(double* out, const double* x, double alpha, const double* y, int64_t n, hipStream_t st);
 hipError_t launch_action_elementwise(const egfem_tensor_s* T, const double* u, const double* a, double* r,
                                      hipStream_t st);
 hipError_t launch_action_problem(const egfem_tensor_s* T, const ProblemView& pv, const double* u,

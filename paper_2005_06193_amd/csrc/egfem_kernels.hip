@@ -237,15 +237,20 @@ __global__ __launch_bounds__(kBlockThreads) void k_action_elem(int64_t n, const 
 
 // Coefficient of a gradient nonlinearity per cell (W_h = P0, the gradient
 // interpolation of Sec. 3.2): z = sum_m u_{c_m} grad lambda_m, a_e = (c0 + c1 |z|^2)^q.
+// With wv != null also the derivative weights of the Newton Jacobian,
+// wv[4e + m] = d a_e / d u_{c_m} = 2 q c1 (c0 + c1 |z|^2)^(q-1) z . grad lambda_m (0 past d).
 template <int D>
 __global__ __launch_bounds__(kBlockThreads) void k_grad_coef(int64_t ncell, const int4* __restrict__ cell4,
                                                              const double* __restrict__ grad,
                                                              const double* __restrict__ u, double c0, double c1,
-                                                             double q, int linear, double* __restrict__ a) {
+                                                             double q, int linear, double* __restrict__ a,
+                                                             double* __restrict__ wv) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= ncell) return;
   if (linear) {
     a[e] = 1.0;
+    if (wv)
+      for (int m = 0; m < 4; ++m) wv[4 * e + m] = 0.0;
     return;
   }
   const int4 c = cell4[e];
@@ -261,7 +266,43 @@ __global__ __launch_bounds__(kBlockThreads) void k_grad_coef(int64_t ncell, cons
   double s2 = 0.0;
 #pragma unroll
   for (int r = 0; r < D; ++r) s2 = fma(z[r], z[r], s2);
-  a[e] = pow(fma(c1, s2, c0), q);
+  const double base = fma(c1, s2, c0);
+  a[e] = pow(base, q);
+  if (wv) {
+    const double ap = 2.0 * q * c1 * pow(base, q - 1.0);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      double zg = 0.0;
+      if (m <= D) {
+#pragma unroll
+        for (int r = 0; r < D; ++r) zg = fma(z[r], G[3 * m + r], zg);
+      }
+      wv[4 * e + m] = m <= D ? ap * zg : 0.0;
+    }
+  }
+}
+
+// F_i = dir_i ? 0 : F_i - b_i, and per-workgroup partial sums of F_i^2 (grid-stride).
+__global__ __launch_bounds__(kBlockThreads) void k_sub_mask_norm(int64_t n, double* __restrict__ F,
+                                                                 const double* __restrict__ b,
+                                                                 const uint8_t* __restrict__ dir,
+                                                                 double* __restrict__ partial) {
+  __shared__ double sh4[4];
+  double ss = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlockThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlockThreads) {
+    const double f = (dir && dir[i]) ? 0.0 : F[i] - b[i];
+    F[i] = f;
+    ss = fma(f, f, ss);
+  }
+  const double tot = block_sum256(ss, sh4);
+  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+__global__ void k_axpy_to(double* __restrict__ out, const double* __restrict__ x, double alpha,
+                          const double* __restrict__ y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = fma(alpha, y[i], x[i]);
 }
 
 // Per-workgroup partial sums of (x_i - u_i)^2 and x_i^2 (grid-stride rows):
@@ -484,11 +525,32 @@ static void elem_launch_l(const egfem_tensor_s* T, const double* u, const double
 }
 
 hipError_t launch_grad_coef(const egfem_tensor_s* T, const double* u, double c0, double c1, double q, int linear,
-                            double* a, hipStream_t st) {
+                            double* a, double* wv, hipStream_t st) {
   const int64_t E = T->n_cells;
   auto kern = T->dim == 1 ? k_grad_coef<1> : (T->dim == 2 ? k_grad_coef<2> : k_grad_coef<3>);
   hipLaunchKernelGGL(kern, dim3(grid1d(E)), dim3(kBlockThreads), 0, st, E, T->e_cell4, T->e_grad, u, c0, c1, q,
-                     linear, a);
+                     linear, a, wv);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobian_grad(const egfem_tensor_s* T, const double* a, const double* u, const double* wv,
+                                const uint8_t* dir, double* jval, double* dinv, hipStream_t st) {
+  hipLaunchKernelGGL(k_jacobian_w2<3>, dim3(xcd_grid(T->row_blocks)), dim3(kBlockThreads), 0, st, view_of(T), u, a,
+                     nullptr, 0.0, 0, wv, 0, nullptr, dir, jval, dinv);
+  return hipGetLastError();
+}
+
+int launch_sub_mask_norm(int64_t n, double* F, const double* b, const uint8_t* dir, double* partial, hipStream_t st,
+                         hipError_t* err) {
+  const int G = (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlockThreads - 1) / kBlockThreads, 256));
+  hipLaunchKernelGGL(k_sub_mask_norm, dim3(G), dim3(kBlockThreads), 0, st, n, F, b, dir, partial);
+  *err = hipGetLastError();
+  return G;
+}
+
+hipError_t launch_axpy(double* out, const double* x, double alpha, const double* y, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_axpy_to, dim3(grid1d(n)), dim3(kBlockThreads), 0, st, out, x, alpha, y, n);
   return hipGetLastError();
 }
 
@@ -529,7 +591,7 @@ hipError_t launch_jacobian(const egfem_tensor_s* T, const double* u, const doubl
                            int dadu_2u, int addK, const uint8_t* dir, double* jval, double* dinv,
                            hipStream_t st) {
   if (T->w2) {
-    auto kern = T->w2 == 1 ? k_jacobian_w2<1> : k_jacobian_w2<2>;
+    auto kern = T->w2 == 1 ? k_jacobian_w2<1> : (T->w2 == 2 ? k_jacobian_w2<2> : k_jacobian_w2<3>);
     hipLaunchKernelGGL(kern, dim3(xcd_grid(T->row_blocks)), dim3(kBlockThreads), 0, st, view_of(T), u, a, a0, a0c,
                        use_problem_a, dadu, dadu_2u, addK ? T->kval : nullptr, dir, jval, dinv);
     return hipGetLastError();

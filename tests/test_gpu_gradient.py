@@ -127,3 +127,49 @@ def test_picard_grad_rejections_and_determinism():
     S = eg().Tensor.from_mesh(m, 0)
     with pytest.raises(eg().EgfemError):
         S.picard_grad(p, u1, 0.0, 1.0, -0.25)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_newton_grad_matches_oracle(name):
+    """Damped Newton with the analytic Jacobian (per-cell derivative weights in
+    the W-slot emission) reaches the oracle's Newton solution, which is also the
+    Picard fixed point."""
+    mk, fval, c0, c1, q = CASES[name]
+    m = mk()
+    print(f"newton_grad {name}", flush=True)
+    T = _p0(m)
+    f = np.full(m.n_nodes, fval)
+    p = eg().Problem(T.n, _load(T, m, f), dt(m.dirichlet, torch.uint8))
+    u = torch.zeros(T.n, dtype=torch.float64, device=DEV)
+    # tol 1e-12 lies above the rounding floor of ||F|| (~1e-13 ||F_0||), where
+    # further steps only shuffle rounding noise
+    st = T.newton_grad(p, u, c0, c1, q, opts=eg().NewtonOptions(tol=1e-12, krylov_rtol=1e-13), warn=False)
+    assert st.status == 0, st.status_name
+    wl = W.GradientWorkload("t", m, f, 0.0, c0, c1, q, None)
+    P = O.build_grad_problem(wl)
+    uo, sto = O.newton_grad(P, tol=1e-12)
+    assert sto.status == "converged"
+    ug = host(u)
+    assert relerr(ug, uo) <= 1e-10
+    assert np.linalg.norm(O.residual_grad(P, ug)) <= 1e-11 * np.linalg.norm(P.d[P.free])
+    assert st.newton_iters <= sto.iterations + 2
+
+
+def test_newton_grad_full_size_disk_and_forcing():
+    wl = W.plaplace_disk(256)
+    T = _p0(wl.mesh)
+    p = eg().Problem(T.n, _load(T, wl.mesh, wl.f), dt(wl.mesh.dirichlet, torch.uint8))
+    u = torch.zeros(T.n, dtype=torch.float64, device=DEV)
+    st = T.newton_grad(p, u, wl.c0, wl.c1, wl.q, opts=eg().NewtonOptions(tol=1e-10, forcing=1))
+    assert st.status == 0 and st.newton_iters <= 12
+    P = O.build_grad_problem(wl)
+    ug = host(u)
+    assert np.linalg.norm(O.residual_grad(P, ug)) <= 2e-10 * np.linalg.norm(P.d[P.free])
+    assert np.linalg.norm(ug - wl.exact) / np.linalg.norm(wl.exact) < 1e-4
+    # deterministic, and the Picard fixed point
+    u2 = torch.zeros(T.n, dtype=torch.float64, device=DEV)
+    T.newton_grad(p, u2, wl.c0, wl.c1, wl.q, opts=eg().NewtonOptions(tol=1e-10, forcing=1))
+    assert torch.equal(u, u2)
+    up = torch.zeros(T.n, dtype=torch.float64, device=DEV)
+    T.picard_grad(p, up, wl.c0, wl.c1, wl.q)
+    assert relerr(ug, host(up)) < 1e-8
