@@ -655,11 +655,12 @@ def _p2_basis(lam: np.ndarray, local_edges) -> np.ndarray:
 
 
 def assemble_tensor_p2(coords, cells, W: P2Space, form: int):
-    """T_ijk = int eta_k grad phi_j . grad phi_i (or eta_k phi_j phi_i) with eta the
-    P2 basis of W_h; returned as COO arrays with k over W-dofs."""
+    """T_ijk = int eta_k grad phi_j . grad phi_i (or eta_k phi_j phi_i, or
+    eta_k phi_j sum_d d_d phi_i for the convection form) with eta the P2 basis of
+    W_h; returned as COO arrays with k over W-dofs."""
     dim = coords.shape[1]
     det, G = element_geometry(coords, cells)
-    pts, wts = simplex_quadrature(dim, 2 if form == FORM_STIFF else 4)
+    pts, wts = simplex_quadrature(dim, {FORM_STIFF: 2, FORM_MASS: 4, FORM_CONV: 3}[form])
     lam = barycentric(pts)
     eta = _p2_basis(lam, W.local_edges)
     nl = dim + 1
@@ -668,6 +669,11 @@ def assemble_tensor_p2(coords, cells, W: P2Space, form: int):
         GG = np.einsum("ead,ebd->eab", G, G)
         psi = np.einsum("q,qc->c", wts, eta)
         Te = det[:, None, None, None] * GG[:, :, :, None] * psi[None, None, None, :]
+    elif form == FORM_CONV:
+        gsum = G.sum(axis=2)
+        gsum[np.abs(gsum) <= 1e-12 * np.abs(G).sum(axis=2)] = 0.0
+        pair = np.einsum("q,qb,qc->bc", wts, lam, eta)             # int phi_b eta_c on the reference
+        Te = det[:, None, None, None] * gsum[:, :, None, None] * pair[None, None]
     else:
         trip = np.einsum("q,qa,qb,qc->abc", wts, lam, lam, eta)
         Te = det[:, None, None, None] * trip[None]
@@ -1007,23 +1013,40 @@ def burgers_system(coords, cells, dirichlet, dt: float, nu: float) -> BurgersSys
     return BurgersSystem(N, Nf, M, K, S, free, dt, nu)
 
 
+def burgers_group_p2(coords, cells):
+    """EGFEM group matrix with W_h = P2 (Sec. 5.2): N^f_ik = int eta_k sum_d d_d phi_i
+    for the P2 basis eta, i.e. the P2 convection tensor summed over j (partition
+    of unity), with f = (Pi_u u)^2 at the P2 dofs.  Returns (N^f [n, n_w], space)."""
+    T, W = tensor_p2(coords, cells, FORM_CONV)
+    n = coords.shape[0]
+    Nf = sp.coo_matrix((T.v, (T.i, T.k)), shape=(n, W.n_w)).tocsr()
+    return Nf, W
+
+
 def burgers(sysm: BurgersSystem, u0: np.ndarray, source: Optional[np.ndarray], steps: int,
-            group: bool = False, history: bool = False):
+            group: bool = False, history: bool = False, group_p2=None):
     """Semi-implicit Euler steps of Sec. 5.2,
         M (u^{n+1} - u^n) + dt (nu K u^{n+1} - 1/2 C(u^n) - d^{n+1}) = 0,
     i.e. (M + dt nu K) u^{n+1} = M u^n + dt (1/2 C(u^n) + d^{n+1}), with
         C(u) = N : (u (x) u)       (tensor formulation, exact for P1 u), or
         C(u) = N^f (u . u)         (group formulation: u^2 interpolated onto P1),
     load d^{n+1} = M s^{n+1} for the nodal source values s^{n+1} = source[n]
-    (source None: no source), zero Dirichlet data.  Each linear system is solved
-    directly (one LU factorisation of the constant matrix).  Returns u^steps, or
-    the list [u^0, ..., u^steps] with history=True."""
+    (source None: no source), zero Dirichlet data; with group_p2 = (N^f, space)
+    from burgers_group_p2 the group formulation uses W_h = P2 instead.  Each
+    linear system is solved directly (one LU factorisation of the constant
+    matrix).  Returns u^steps, or the list [u^0, ..., u^steps] with history=True."""
     u = np.array(u0, dtype=np.float64, copy=True)
     u[~sysm.free] = 0.0
     lu = spla.splu(sysm.S.tocsc())
     out = [u.copy()] if history else None
     for n in range(steps):
-        conv = sysm.Nf @ (u * u) if group else contract_uv(sysm.N, u, u)
+        if group_p2 is not None:
+            # EGFEM with W_h = P2: f = (Pi_u u)^2 at the P2 dofs
+            Nf2, W2 = group_p2
+            pu = W2.Pi @ u
+            conv = Nf2 @ (pu * pu)
+        else:
+            conv = sysm.Nf @ (u * u) if group else contract_uv(sysm.N, u, u)
         x = u if source is None else u + sysm.dt * source[n]
         rhs = sysm.M @ x + (0.5 * sysm.dt) * conv
         rhs[~sysm.free] = 0.0

@@ -736,3 +736,23 @@ def test_gradient_newton_jacobian_and_fixed_point():
         un, st = O.newton_grad(P, tol=1e-13)
         assert st.status == "converged" and st.iterations <= 10
         assert np.linalg.norm(un - u) <= 1e-10 * np.linalg.norm(u)
+
+
+def test_burgers_egfem_p2_is_exact():
+    """With W_h = P2 the group formulation interpolates u^2 without error
+    ((Pi_u u)^2 is u_h^2 in P2), so N^f_P2 (Pi_u u)^2 = N:(u (x) u) and the
+    EGFEM(P2) steps reproduce the tensor formulation, unlike the P1 group one."""
+    for m in (W.mesh_1d(9), W.mesh_2d(7), W.mesh_3d(3)):
+        T = O.assemble_tensor(m.coords, m.cells, O.FORM_CONV)
+        Nf2, W2 = O.burgers_group_p2(m.coords, m.cells)
+        u = np.random.default_rng(1).uniform(-1, 1, m.n_nodes)
+        pu = W2.Pi @ u
+        c = O.contract_uv(T, u, u)
+        assert np.abs(Nf2 @ (pu * pu) - c).max() <= 1e-14 * np.abs(c).max()
+    b = W.burgers_2d(16)
+    sy = O.burgers_system(b.mesh.coords, b.mesh.cells, b.mesh.dirichlet, b.dt, b.nu)
+    ut = O.burgers(sy, b.u0, b.source, b.steps)
+    u2 = O.burgers(sy, b.u0, b.source, b.steps, group_p2=O.burgers_group_p2(b.mesh.coords, b.mesh.cells))
+    ug = O.burgers(sy, b.u0, b.source, b.steps, group=True)
+    assert np.linalg.norm(u2 - ut) <= 1e-13 * np.linalg.norm(ut)
+    assert np.linalg.norm(ug - ut) > 1e-6 * np.linalg.norm(ut)
