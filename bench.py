@@ -503,19 +503,21 @@ def stage(name: str):
 
 def burgers_suite(n: int = 256, reps: int = 2):
     """The Burgers experiment of Sec. 5.2 (nu = 1, T = 1, dt = 1e-2: 100
-    semi-implicit steps) on the 2D n x n mesh, tensor and group formulations."""
+    semi-implicit steps) on the 2D n x n mesh, tensor and group formulations,
+    and the EGFEM group formulation with W_h = P2."""
     import numpy as np
     import torch
     import paper_2005_06193_amd as eg
     import workloads as W
     b = W.burgers_2d(n)
-    T = eg.Tensor.from_mesh(b.mesh, W.FORM_CONV)
+    T1 = eg.Tensor.from_mesh(b.mesh, W.FORM_CONV)
+    T2 = eg.Tensor.from_mesh(b.mesh, W.FORM_CONV, wspace=eg.W_P2)
     dirm = torch.tensor(b.mesh.dirichlet, dtype=torch.uint8, device="cuda")
     src = torch.tensor(b.source, dtype=torch.float64, device="cuda")
     u0 = torch.tensor(b.u0, dtype=torch.float64, device="cuda")
-    out = {"workload": b.name, "nodes": T.n, "tensor_nnz": T.info.nnz, "steps": b.steps, "dt": b.dt,
-           "nu": b.nu, "krylov": "cg-jacobi, rtol 1e-12 per step"}
-    for name, group in (("tensor", 0), ("group", 1)):
+    out = {"workload": b.name, "nodes": T1.n, "tensor_nnz": T1.info.nnz, "p2_tensor_nnz": T2.info.nnz,
+           "steps": b.steps, "dt": b.dt, "nu": b.nu, "krylov": "cg-jacobi, rtol 1e-12 per step"}
+    for name, T, group in (("tensor", T1, 0), ("group", T1, 1), ("egfem_p2_group", T2, 1)):
         u = u0.clone()
         T.burgers(u, dirm, src, eg.BurgersOptions(steps=10, group=group))            # warm
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
@@ -538,7 +540,8 @@ def burgers_suite(n: int = 256, reps: int = 2):
                      "rhs_ms_per_step": stt.t_rhs_ms / b.steps, "cg_ms_per_step": stt.t_krylov_ms / b.steps,
                      "cg_us_per_iter": 1e3 * stt.t_krylov_ms / max(stt.krylov_iters, 1),
                      "rel_l2_error_vs_exact": err}
-    T.close()
+    T1.close()
+    T2.close()
     return out
 
 

@@ -118,7 +118,8 @@ int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords,
 /* egfem_build_tensor_w: the same with the coefficient space chosen by wspace.
  * With EGFEM_W_P2 the tensor is T_ijk = int eta_k grad phi_j . grad phi_i
  * (stiffness) or int eta_k phi_j phi_i (mass) with eta the P2 nodal basis
- * (vertex lambda(2 lambda - 1), edge midpoint 4 lambda_x lambda_y); k runs
+ * (vertex lambda(2 lambda - 1), edge midpoint 4 lambda_x lambda_y), or
+ * int eta_k phi_j sum_d d_d phi_i (convection, for egfem_burgers); k runs
  * over the n_w = n_nodes + n_edges P2 dofs: the vertices, then the edges in
  * ascending (smaller vertex id, larger vertex id) order (Sec. 3.1, Case 1;
  * Sec. 3.2 for Pi_u).  With EGFEM_W_IQ, k = e * Q + q runs over the Q points
@@ -130,8 +131,9 @@ int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords,
  *    sum_k (sum_j' T_ij'k u_j') dadu_k (Pi_u)_kj;
  *  - the problem-level calls (problem residual / Jacobian, Newton, Picard)
  *    use a = Pi_u a0 + (Pi_u u)^2 at the dofs of W_h, a' = 2 Pi_u u;
- *  - egfem_mode3, egfem_adjoint, the batched form and egfem_burgers return
- *    EGFEM_ERR_ARG; the convection form is not available (EGFEM_ERR_ARG);
+ *  - egfem_mode3, egfem_adjoint and the batched form return EGFEM_ERR_ARG;
+ *    egfem_burgers takes a W_h = P2 convection handle with group = 1 only;
+ *    the convection form with EGFEM_W_IQ or EGFEM_W_P0 is EGFEM_ERR_ARG;
  *  - with EGFEM_W_P0 (k = cell, T_ijk = K^{e_k}_ij or M^{e_k}_ij) the problem-
  *    level calls return EGFEM_ERR_ARG (the coefficient is a function of the
  *    gradient: egfem_picard_grad), and egfem_jacobian takes no dadu.
@@ -376,6 +378,10 @@ int egfem_solve_cg(egfem_tensor_t T, const double* jval, const double* rhs, doub
  *     C(u) = N:(u (x) u)                        (group = 0, tensor formulation),
  *     C(u) = N^f (u . u), N^f_ik = sum_j N_ijk  (group = 1, group formulation:
  *            u^2 interpolated onto P1; N^f is int phi_k sum_d d_d phi_i),
+ *     C(u) = N^f_P2 (Pi_u u)^2                  (group = 1 on a W_h = P2 handle:
+ *            the EGFEM group formulation, N^f_P2 = int eta_k sum_d d_d phi_i,
+ *            (Pi_u u)^2 squared at the P2 dofs; equal to the tensor
+ *            formulation up to rounding, since u^2 of a P1 u lies in P2),
  * with N the EGFEM_FORM_CONV tensor of the handle, s^{n+1} the nodal source
  * values at t_{n+1} (load M s^{n+1}), Dirichlet rows identity with zero right-
  * hand side.  The matrix is constant and symmetric positive definite: it is
@@ -415,7 +421,8 @@ void egfem_burgers_opts_default(egfem_burgers_opts* o);
 
 /* egfem_burgers: advance u (device [n_nodes], u^0 in, u^steps out; Dirichlet
  * entries are set to 0) by opts->steps semi-implicit steps.  T must be an
- * EGFEM_FORM_CONV handle (its K and M are the stiffness and mass matrices).
+ * EGFEM_FORM_CONV handle (its K and M are the stiffness and mass matrices);
+ * a W_h = P2 handle needs opts->group = 1 (EGFEM_ERR_ARG otherwise).
  *   dirichlet      device uint8 [n_nodes] or NULL (no Dirichlet nodes)
  *   source         device; the nodal source values of step n (n = 0 .. steps-1,
  *                  i.e. at t_{n+1}) start at source + n * source_stride; a

@@ -156,7 +156,7 @@ void egfem_tensor_destroy(egfem_tensor_t T) {
                   T->kpS,    T->kval, T->mval,    T->blk_row,  T->blk_meta, T->wrowptr, T->wcol, T->wpq,
                   T->wmeta,  T->wpq2, T->wqi,       T->qlam,   T->e_cell4, T->e_kp,    T->e_nptr,
                   T->e_inc,  T->kSH,  T->vH,        T->kpSH,   T->hmeta,   T->e_grad,  T->e_acoef,
-                  T->e_wv};
+                  T->e_wv,   T->p2_edges};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (!T->symmetric) {
@@ -577,6 +577,10 @@ int egfem_burgers(egfem_tensor_t T, const uint8_t* dirichlet, const double* sour
                   double* u, const egfem_burgers_opts* o, egfem_burgers_stats* s, void* stream) {
   if (!T || !u) return fail(EGFEM_ERR_ARG, "null argument");
   if (T->form != EGFEM_FORM_CONV) return fail(EGFEM_ERR_ARG, "Burgers steps need an EGFEM_FORM_CONV tensor");
+  // W_h = P2: the group formulation with f = (Pi_u u)^2 at the P2 dofs (EGFEM)
+  const bool egfem_p2 = (T->w2 == 1);
+  if (egfem_p2 && !(o && o->group == 1))
+    return fail(EGFEM_ERR_ARG, "a W_h = P2 convection tensor takes the group formulation (group = 1)");
   egfem_burgers_opts opts;
   egfem_burgers_opts_default(&opts);
   if (o) opts = *o;
@@ -587,6 +591,8 @@ int egfem_burgers(egfem_tensor_t T, const uint8_t* dirichlet, const double* sour
        opts.krylov_threads != 1024))
     return fail(EGFEM_ERR_ARG, "invalid Burgers options");
   if (source && source_stride < 0) return fail(EGFEM_ERR_ARG, "source_stride must be >= 0");
+  // (Pi_u u)^2 is staged in the slot-sized scratch vector
+  if (egfem_p2 && T->n_w > T->slots) return fail(EGFEM_ERR_SHAPE, "P2 dofs exceed the slot scratch");
   int rc = ensure_workspace(T);
   if (rc != EGFEM_OK) return rc;
   Workspace& W = T->ws;
@@ -599,7 +605,9 @@ int egfem_burgers(egfem_tensor_t T, const uint8_t* dirichlet, const double* sour
   // offline part of the run: M + dt nu K (Dirichlet identity rows, zero
   // columns) and its inverse diagonal; N^f = N contracted with 1 in j
   EGFEM_HIP_CHECK(launch_mk_combine(T, 1.0, opts.dt * opts.nu, dirichlet, W.jval, W.dinv, st));
-  if (opts.group) {
+  if (egfem_p2) {
+    EGFEM_HIP_CHECK(launch_fill(W.z, 1.0, T->n, st));      // u_j = 1 in the raw action gives N^f
+  } else if (opts.group) {
     EGFEM_HIP_CHECK(launch_fill(W.utry, 1.0, T->n, st));
     EGFEM_HIP_CHECK(launch_slot_mode2(T, W.utry, W.qslot, st));
   }
@@ -609,9 +617,16 @@ int egfem_burgers(egfem_tensor_t T, const uint8_t* dirichlet, const double* sour
   for (; n < opts.steps; ++n) {
     const double* src = source ? source + (int64_t)n * source_stride : nullptr;
     if ((rc = tm.start()) != EGFEM_OK) return rc;
-    if (!opts.group) EGFEM_HIP_CHECK(launch_action_raw(T, u, u, W.F, st));
-    EGFEM_HIP_CHECK(launch_burgers_rhs(T, opts.group != 0, u, src, opts.dt, opts.group ? W.qslot : W.F,
-                                       dirichlet, W.rhs, st));
+    if (egfem_p2) {
+      // N^f_P2 (Pi_u u)^2: f in W.qslot (slots >= P2 dofs), raw action with u = 1
+      EGFEM_HIP_CHECK(launch_p2_square(T, u, W.qslot, st));
+      EGFEM_HIP_CHECK(launch_action_raw(T, W.z, W.qslot, W.F, st));
+    } else if (!opts.group) {
+      EGFEM_HIP_CHECK(launch_action_raw(T, u, u, W.F, st));
+    }
+    const bool slot_group = opts.group && !egfem_p2;
+    EGFEM_HIP_CHECK(launch_burgers_rhs(T, slot_group, u, src, opts.dt, slot_group ? W.qslot : W.F, dirichlet,
+                                       W.rhs, st));
     if ((rc = tm.stop(&stats.t_rhs_ms, &n_dummy)) != EGFEM_OK) return rc;
     // initial iterate: extrapolation over the iterates kept so far (W.delta
     // holds u^{n-1}, W.utry u^{n-2})

@@ -122,15 +122,11 @@ double mono(int dim, const int* alpha) {
   return num / den;
 }
 
-// int_e eta_c / |e| and int_e lambda_a lambda_b eta_c / |e| for the local P2
-// dof c (c < nl: vertex c; else the local edge ledge[c - nl]).
-double p2_int(int dim, int a, int b, int c, const int (*ledge)[2], bool with_ab) {
+// int_e m eta_c / |e| for the local P2 dof c (c < nl: vertex c; else the
+// local edge ledge[c - nl]), where m is the barycentric monomial with
+// exponents base[].
+double p2_int_base(int dim, const int base[4], int c, const int (*ledge)[2]) {
   const int nl = dim + 1;
-  int base[4] = {0, 0, 0, 0};
-  if (with_ab) {
-    base[a]++;
-    base[b]++;
-  }
   if (c < nl) {
     int x1[4], x2[4];
     for (int m = 0; m < 4; ++m) x1[m] = x2[m] = base[m];
@@ -145,6 +141,23 @@ double p2_int(int dim, int a, int b, int c, const int (*ledge)[2], bool with_ab)
   return 4.0 * mono(dim, x);
 }
 
+// int_e eta_c / |e| and int_e lambda_a lambda_b eta_c / |e| (with_ab).
+double p2_int(int dim, int a, int b, int c, const int (*ledge)[2], bool with_ab) {
+  int base[4] = {0, 0, 0, 0};
+  if (with_ab) {
+    base[a]++;
+    base[b]++;
+  }
+  return p2_int_base(dim, base, c, ledge);
+}
+
+// int_e lambda_b eta_c / |e| (convection form).
+double p2_int1(int dim, int b, int c, const int (*ledge)[2]) {
+  int base[4] = {0, 0, 0, 0};
+  base[b]++;
+  return p2_int_base(dim, base, c, ledge);
+}
+
 int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, const int32_t* cells, int form,
                int wspace, double drop_rel, egfem_tensor_t* out) {
   using namespace egfem;
@@ -155,8 +168,8 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
     return fail(EGFEM_ERR_ARG, "unknown form");
   if (wspace != EGFEM_W_P1 && wspace != EGFEM_W_P2 && wspace != EGFEM_W_IQ && wspace != EGFEM_W_P0)
     return fail(EGFEM_ERR_ARG, "unknown W space");
-  if (wspace != EGFEM_W_P1 && form == EGFEM_FORM_CONV)
-    return fail(EGFEM_ERR_ARG, "the convection form is built with W_h = P1 only");
+  if (wspace != EGFEM_W_P1 && wspace != EGFEM_W_P2 && form == EGFEM_FORM_CONV)
+    return fail(EGFEM_ERR_ARG, "the convection form is built with W_h = P1 or P2 only");
   const bool w2 = (wspace != EGFEM_W_P1);     // a coefficient space with W-slots
   const bool wq = (wspace == EGFEM_W_IQ);
   const bool wcell = (wspace == EGFEM_W_P0);   // one coefficient per cell
@@ -420,6 +433,13 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
           const int64_t eid = edge_id(c[ledge[t][0]], c[ledge[t][1]]);
           wl[nl + t] = nc + (int)(std::lower_bound(redges.begin(), redges.end(), eid) - redges.begin());
         }
+        // sum_d d_d lambda_a (convection form), rounding noise of a zero sum removed
+        double gsum = 0.0, gabs = 0.0;
+        for (int r = 0; r < dim; ++r) {
+          gsum += g.G[a][r];
+          gabs += std::fabs(g.G[a][r]);
+        }
+        if (std::fabs(gsum) <= 1e-12 * gabs) gsum = 0.0;
         for (int b = 0; b < nl; ++b) {
           double gg = 0.0;
           for (int r = 0; r < dim; ++r) gg += g.G[a][r] * g.G[b][r];
@@ -427,8 +447,10 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
           kacc[loc[b]] += kab;
           macc[loc[b]] += g.vol * (a == b ? m2_diag : m2_off);
           for (int cd = 0; cd < nl + ne_loc; ++cd) {
-            const double val = (form == EGFEM_FORM_STIFF) ? kab * p2_int(dim, a, b, cd, ledge, false)
-                                                          : g.vol * p2_int(dim, a, b, cd, ledge, true);
+            double val;
+            if (form == EGFEM_FORM_STIFF) val = kab * p2_int(dim, a, b, cd, ledge, false);
+            else if (form == EGFEM_FORM_MASS) val = g.vol * p2_int(dim, a, b, cd, ledge, true);
+            else val = gsum * g.vol * p2_int1(dim, b, cd, ledge);
             const size_t idx = (size_t)loc[b] * nw + wl[cd];
             acc[idx] += val;
             present[idx] = 1;
@@ -770,6 +792,15 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
     if (rc == EGFEM_OK) rc = upload(hmeta, &T->hmeta, &bytes);
     T->nnz_h = (int64_t)vH.size();
     T->action_half = 0;   // the autotuner switches to it where it is faster
+  }
+  if (w2 && !wq && !wcell) {
+    // P2: the endpoints of every edge dof (Pi_u u at the edge midpoints)
+    std::vector<int32_t> ep(ekeys.size() * 2);
+    for (size_t t = 0; t < ekeys.size(); ++t) {
+      ep[2 * t] = (int32_t)(ekeys[t] / N);
+      ep[2 * t + 1] = (int32_t)(ekeys[t] % N);
+    }
+    if (rc == EGFEM_OK) rc = upload(ep, &T->p2_edges, &bytes);
   }
   if (wcell) {
     // the gradient interpolation: vertex ids (padded to 4) and grad lambda_m

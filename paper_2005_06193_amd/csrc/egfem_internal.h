@@ -136,6 +136,7 @@ struct egfem_tensor_s {
   double* e_grad = nullptr;     // W_h = P0: [cells * 12] grad lambda_m of every cell (4 x 3, padded)
   double* e_acoef = nullptr;    // W_h = P0: [cells] coefficient buffer of egfem_picard_grad / egfem_newton_grad
   double* e_wv = nullptr;       // W_h = P0: [cells * 4] derivative weights of the Newton Jacobian
+  int32_t* p2_edges = nullptr;  // W_h = P2: [edges * 2] endpoints of every edge dof
   uint32_t* wpq2 = nullptr;     // I_k: [wslots] slots of the third and fourth cell vertex
   uint8_t* wqi = nullptr;       // I_k: [wslots] point index
   double* qlam = nullptr;       // I_k: [4*4] barycentrics of the points
@@ -191,6 +192,8 @@ hipError_t launch_jacobian_grad(const egfem_tensor_s* T, const double* a, const 
 int launch_sub_mask_norm(int64_t n, double* F, const double* b, const uint8_t* dir, double* partial, hipStream_t st,
                          hipError_t* err);
 hipError_t launch_axpy(double* out, const double* x, double alpha, const double* y, int64_t n, hipStream_t st);
+// f = (Pi_u u)^2 at the P2 dofs: u_k^2 at the vertices, ((u_x + u_y) / 2)^2 at the edges.
+hipError_t launch_p2_square(const egfem_tensor_s* T, const double* u, double* f, hipStream_t st);
 hipError_t launch_action_elementwise(const egfem_tensor_s* T, const double* u, const double* a, double* r,
                                      hipStream_t st);
 hipError_t launch_action_problem(const egfem_tensor_s* T, const ProblemView& pv, const double* u,

@@ -299,6 +299,20 @@ __global__ __launch_bounds__(kBlockThreads) void k_sub_mask_norm(int64_t n, doub
   if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
+__global__ void k_p2_square(int64_t n, int64_t nw, const int32_t* __restrict__ edges, const double* __restrict__ u,
+                            double* __restrict__ f) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nw) return;
+  double v;
+  if (k < n) {
+    v = u[k];
+  } else {
+    const int64_t t = k - n;
+    v = 0.5 * (u[edges[2 * t]] + u[edges[2 * t + 1]]);
+  }
+  f[k] = v * v;
+}
+
 __global__ void k_axpy_to(double* __restrict__ out, const double* __restrict__ x, double alpha,
                           const double* __restrict__ y, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -546,6 +560,12 @@ int launch_sub_mask_norm(int64_t n, double* F, const double* b, const uint8_t* d
   hipLaunchKernelGGL(k_sub_mask_norm, dim3(G), dim3(kBlockThreads), 0, st, n, F, b, dir, partial);
   *err = hipGetLastError();
   return G;
+}
+
+hipError_t launch_p2_square(const egfem_tensor_s* T, const double* u, double* f, hipStream_t st) {
+  hipLaunchKernelGGL(k_p2_square, dim3(grid1d(T->n_w)), dim3(kBlockThreads), 0, st, T->n, T->n_w, T->p2_edges, u,
+                     f);
+  return hipGetLastError();
 }
 
 hipError_t launch_axpy(double* out, const double* x, double alpha, const double* y, int64_t n, hipStream_t st) {

@@ -76,15 +76,16 @@ def test_build_argument_errors():
     lib = eg.load_library()
     assert lib.egfem_build_tensor(2, 3, c.ctypes.data, 1, t.ctypes.data, 0, 0.0, None) == \
         B.EGFEM_ERR_ARG
-    # coefficient space: unknown, and the convection form with W_h = P2
+    # coefficient space: unknown, and the convection form with W_h = I_k or P0
     out = C.c_void_p()
     cc = np.ascontiguousarray(c, np.float64)
     tt = np.ascontiguousarray(t, np.int32)
     assert lib.egfem_build_tensor_w(2, 3, cc.ctypes.data, 1, tt.ctypes.data, 0, 5, 0.0, C.byref(out)) == \
         B.EGFEM_ERR_ARG
-    assert lib.egfem_build_tensor_w(2, 3, cc.ctypes.data, 1, tt.ctypes.data, B.FORM_CONV, B.W_P2, 0.0,
-                                    C.byref(out)) == B.EGFEM_ERR_ARG
-    assert "convection" in lib.egfem_last_error().decode()
+    for wsp in (B.W_IQ, B.W_P0):
+        assert lib.egfem_build_tensor_w(2, 3, cc.ctypes.data, 1, tt.ctypes.data, B.FORM_CONV, wsp, 0.0,
+                                        C.byref(out)) == B.EGFEM_ERR_ARG
+        assert "convection" in lib.egfem_last_error().decode()
 
 
 def test_build_row_capacity_limit():

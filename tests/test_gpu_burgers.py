@@ -162,3 +162,74 @@ def test_burgers_initial_guess_orders():
     assert iters[2] < iters[1] < iters[0], iters
     with pytest.raises(eg().EgfemError):
         T.burgers(dt(b.u0), dirm, src, eg().BurgersOptions(steps=3, guess=3))
+
+
+P2_MESHES = {
+    "1d_n16": lambda: W.mesh_1d(16),
+    "2d_n9": lambda: W.mesh_2d(9),
+    "2d_jitter_n13": lambda: irregular_mesh(13),
+    "3d_n3": lambda: W.mesh_3d(3),
+}
+
+
+@pytest.mark.parametrize("name", list(P2_MESHES))
+def test_burgers_p2_convection_tensor_matches_oracle(name):
+    """The W_h = P2 convection tensor entry by entry."""
+    m = P2_MESHES[name]()
+    print(f"burgers p2 tensor mesh={name}", flush=True)
+    T = eg().Tensor.from_mesh(m, W.FORM_CONV, wspace=eg().W_P2)
+    To, Wsp = O.tensor_p2(m.coords, m.cells, O.FORM_CONV)
+    assert T.info.wspace == eg().W_P2 and T.info.n_w == Wsp.n_w
+    assert T.info.nnz == To.nnz and T.info.structural_nnz == To.structural_nnz
+    i, j, k, v = T.export()
+    nw = Wsp.n_w
+    kg = (i.astype(np.int64) * nw + j) * nw + k
+    ko = (To.i * nw + To.j) * nw + To.k
+    og, oo = np.argsort(kg), np.argsort(ko)
+    assert np.array_equal(kg[og], ko[oo])
+    assert np.abs(v[og] - To.v[oo]).max() <= 1e-14 * np.abs(To.v).max()
+
+
+@pytest.mark.parametrize("name", ["1d_n16", "2d_jitter_n13", "3d_n3"])
+def test_burgers_p2_group_matches_oracle(name):
+    """EGFEM group formulation with W_h = P2: N^f_P2 (Pi u)^2 on the GPU against
+    the oracle's, and against the tensor formulation N:(u (x) u), which it
+    reproduces exactly (u^2 of a P1 u lies in P2)."""
+    m = P2_MESHES[name]()
+    print(f"burgers p2 group mesh={name}", flush=True)
+    steps = 12
+    T = eg().Tensor.from_mesh(m, W.FORM_CONV, wspace=eg().W_P2)
+    u0, src = _smooth_case(m, 44)
+    u = dt(u0)
+    o = eg().BurgersOptions(dt=0.02, nu=0.3, steps=steps, group=1, krylov_rtol=1e-13)
+    st = T.burgers(u, dt(m.dirichlet, torch.uint8), dt(src), o)
+    assert st.status == 0 and st.steps == steps
+    sy = O.burgers_system(m.coords, m.cells, m.dirichlet, 0.02, 0.3)
+    srcs = np.broadcast_to(src, (steps, m.n_nodes))
+    uo = O.burgers(sy, u0, srcs, steps, group_p2=O.burgers_group_p2(m.coords, m.cells))
+    assert relerr(host(u), uo) < 1e-11
+    ut = O.burgers(sy, u0, srcs, steps, group=False)
+    assert relerr(host(u), ut) < 1e-11
+
+
+def test_burgers_p2_full_size_2d_256_and_rejections():
+    """The 2D 256x256 manufactured run with W_h = P2 equals the tensor
+    formulation; a P2 convection tensor rejects the slot (P1) group form."""
+    print("burgers p2 2d_256 full size", flush=True)
+    b = W.burgers_2d(256)
+    dirm = dt(b.mesh.dirichlet, torch.uint8)
+    src = dt(b.source)
+    T = eg().Tensor.from_mesh(b.mesh, W.FORM_CONV, wspace=eg().W_P2)
+    u = dt(b.u0)
+    st = T.burgers(u, dirm, src, eg().BurgersOptions(group=1))
+    assert st.status == 0 and st.steps == 100
+    uo = _oracle(b.mesh, b.u0, b.source, b.dt, b.nu, b.steps, False)
+    assert relerr(host(u), uo) < 1e-9
+    assert np.linalg.norm(host(u) - b.u_final) / np.linalg.norm(b.u_final) < 1e-3
+    with pytest.raises(eg().EgfemError):
+        T.burgers(dt(b.u0), dirm, src, eg().BurgersOptions(group=0))
+    # I_k and P0 spaces have no convection tensor
+    m = W.mesh_2d(6)
+    for wsp in (eg().W_IQ, eg().W_P0):
+        with pytest.raises(eg().EgfemError):
+            eg().Tensor.from_mesh(m, W.FORM_CONV, wspace=wsp)
