@@ -131,7 +131,7 @@ def time_solves(T, p, steps: int, warmup: int, opts):
     return t1 - t0, stats, u
 
 
-def time_action(T, reps: int, cold: bool, elementwise: bool = False):
+def time_action(T, reps: int, cold: bool, variant: str = "stream"):
     """Raw tensor action r = T:(u (x) a) launched back to back (warm), or with
     1 GiB read between launches so that the stream comes from HBM (cold).  The
     flush reads (a written flush leaves dirty lines whose write-back would be
@@ -143,7 +143,7 @@ def time_action(T, reps: int, cold: bool, elementwise: bool = False):
     u = torch.rand(n, dtype=torch.float64, device="cuda", generator=g)
     a = torch.rand(n, dtype=torch.float64, device="cuda", generator=g) + 1.0
     r = torch.empty_like(u)
-    act = T.residual_elementwise if elementwise else T.residual
+    act = {"stream": T.residual, "elementwise": T.residual_elementwise, "unique": T.residual_unique}[variant]
     flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda") if cold else None
     for _ in range(5):
         act(u, a, r)
@@ -244,8 +244,8 @@ def tensor_action_suite():
         if wl.form == W.FORM_STIFF:
             # element-factored form of the same tensor: cells (16 B), packed K^e, incidences
             T.attach_elements(wl.mesh.coords, wl.mesh.cells)
-            ew = time_action(T, 100, cold=False, elementwise=True)
-            ec = time_action(T, 20, cold=True, elementwise=True)
+            ew = time_action(T, 100, cold=False, variant="elementwise")
+            ec = time_action(T, 20, cold=True, variant="elementwise")
             nl = wl.mesh.dim + 1
             kst = ((nl * (nl + 1) // 2) + 1) & ~1
             be = wl.mesh.n_cells * (16 + 8 * kst) + 4 * (info.n_nodes + 1) + 4 * nl * wl.mesh.n_cells \
@@ -253,6 +253,19 @@ def tensor_action_suite():
             out[name]["element_factored"] = {"bytes": be, "warm_us": ew * 1e3, "cold_us": ec * 1e3,
                                              "cold_GBps": be / (ec * 1e6),
                                              "cold_speedup_vs_stream": cold / ec}
+        if wl.form == W.FORM_MASS:
+            # unique storage of the fully symmetric tensor: N + 2E + F values, per
+            # slot its column and edge reference, per row its face references
+            nu = T.attach_unique(wl.mesh.coords, wl.mesh.cells)
+            uw = time_action(T, 100, cold=False, variant="unique")
+            uc = time_action(T, 20, cold=True, variant="unique")
+            nn, ns = info.n_nodes, info.slots
+            faces = nu - nn - (ns - nn)
+            bu = 8 * nu + 8 * ns + 8 * (nn + 1) + 8 * 3 * faces + 24 * nn
+            out[name]["unique_storage"] = {"values": nu, "stream_entries": info.nnz, "bytes": bu,
+                                           "warm_us": uw * 1e3, "cold_us": uc * 1e3,
+                                           "cold_GBps": bu / (uc * 1e6),
+                                           "cold_speedup_vs_stream": cold / uc}
         tr = load_traffic()
         if tr:
             out[name]["action_hbm_bytes_rocprof"] = tr["tensor_action"][name]["hbm_bytes_per_launch"]

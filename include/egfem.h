@@ -208,6 +208,34 @@ int egfem_attach_elements(egfem_tensor_t T, int dim, int64_t n_nodes, const doub
 int egfem_residual_elementwise(egfem_tensor_t T, const double* u, const double* a, double* r,
                                void* stream);
 
+/* ------------------------------------------------------------------------
+ * Unique storage of the fully symmetric mass tensor (storage comparison; the
+ * storage cost of the tensors is the trade-off noted in Sec. 5.5).  The P1 mass
+ * tensor T_ijk = int phi_i phi_j phi_k (Sec. 3.3) is invariant under every
+ * permutation of (i, j, k), so one value per index multiset suffices: T_iii per
+ * node, T_aab and T_abb per edge (a < b) and T_abc per face (three distinct
+ * vertices of a cell), N + 2E + F values instead of the N + 6E + 6F entries of
+ * the stream.  The action gathers them per row:
+ *     r_i = T_iii u_i a_i + sum_{j ~ i} [T_iij (u_i a_j + u_j a_i) + T_ijj u_j a_j]
+ *         + sum_{faces {i,j,k}} T_ijk (u_j a_k + u_k a_j).
+ * egfem_attach_unique stores, for an EGFEM_FORM_MASS handle with W_h = P1, the
+ * values (integrated from the same mesh), per slot of the handle's pattern its
+ * edge, and per row its faces with the row-local slots of their other two
+ * vertices; the stream format is kept.
+ *   coords, cells: host, as for egfem_build_tensor (must be the same mesh).
+ *   n_unique (host, nullable) receives N + 2E + F.
+ * Returns EGFEM_ERR_ARG for another form or coefficient space, EGFEM_ERR_SHAPE
+ * when the mesh does not give the handle's sizes, entry count or pattern (or a
+ * row has more than 512 slots), EGFEM_ERR_MESH for bad cells.  Synchronous.
+ * Attaching twice replaces the data. */
+int egfem_attach_unique(egfem_tensor_t T, int dim, int64_t n_nodes, const double* coords,
+                        int64_t n_cells, const int32_t* cells, int64_t* n_unique);
+
+/* egfem_residual_unique: r = T:(u (x) a) through the unique storage (equal to
+ * egfem_residual up to rounding; deterministic).  u, a, r: device [n_nodes], r
+ * must not alias u or a.  EGFEM_ERR_ARG when no unique storage is attached. */
+int egfem_residual_unique(egfem_tensor_t T, const double* u, const double* a, double* r, void* stream);
+
 /* egfem_jacobian: emit J in the CSR pattern of T (Sec. 4, block Jacobian
  * reduced to u; no integration):
  *   J_ij = [K_ij] + sum_k T_ijk a_k + dadu_j * sum_j' T_ij'j u_j'

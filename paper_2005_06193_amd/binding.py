@@ -122,6 +122,9 @@ EXPORTS = {
                                        C.c_int, C.c_int, C.c_double, C.POINTER(C.c_void_p)]),
     "egfem_attach_elements": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),
     "egfem_residual_elementwise": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "egfem_attach_unique": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
+                                      C.POINTER(C.c_int64)]),
+    "egfem_residual_unique": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "egfem_tensor_destroy": (None, [C.c_void_p]),
     "egfem_tensor_info": (C.c_int, [C.c_void_p, C.POINTER(_Info)]),
     "egfem_tensor_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -488,6 +491,24 @@ class Tensor:
         out = torch.empty_like(u) if out is None else out
         _check(load_library().egfem_residual_elementwise(self.handle, _dptr(u, n=self.n), _dptr(a, n=self.n),
                                                          _dptr(out, n=self.n), _stream()))
+        return out
+
+    def attach_unique(self, coords: np.ndarray, cells: np.ndarray) -> int:
+        """Store the fully symmetric mass tensor once per index multiset;
+        returns the number of stored values (N + 2E + F)."""
+        coords = np.ascontiguousarray(coords, dtype=np.float64)
+        cells = np.ascontiguousarray(cells, dtype=np.int32)
+        nu = C.c_int64(0)
+        _check(load_library().egfem_attach_unique(self.handle, coords.shape[1], coords.shape[0],
+                                                  coords.ctypes.data, cells.shape[0], cells.ctypes.data,
+                                                  C.byref(nu)))
+        return int(nu.value)
+
+    def residual_unique(self, u: torch.Tensor, a: torch.Tensor, out: Optional[torch.Tensor] = None):
+        """r_i = sum_jk T_ijk u_j a_k through the unique storage."""
+        out = torch.empty_like(u) if out is None else out
+        _check(load_library().egfem_residual_unique(self.handle, _dptr(u, n=self.n), _dptr(a, n=self.n),
+                                                    _dptr(out, n=self.n), _stream()))
         return out
 
     def jacobian(self, u, a, dadu=None, add_stiffness=False, dirichlet=None, out=None,

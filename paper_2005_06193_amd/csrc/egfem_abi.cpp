@@ -156,7 +156,7 @@ void egfem_tensor_destroy(egfem_tensor_t T) {
                   T->kpS,    T->kval, T->mval,    T->blk_row,  T->blk_meta, T->wrowptr, T->wcol, T->wpq,
                   T->wmeta,  T->wpq2, T->wqi,       T->qlam,   T->e_cell4, T->e_kp,    T->e_nptr,
                   T->e_inc,  T->kSH,  T->vH,        T->kpSH,   T->hmeta,   T->e_grad,  T->e_acoef,
-                  T->e_wv,   T->p2_edges};
+                  T->e_wv,   T->p2_edges, T->u_val,   T->u_sref,  T->u_fptr,  T->u_fref};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (!T->symmetric) {
@@ -227,6 +227,14 @@ int egfem_residual_elementwise(egfem_tensor_t T, const double* u, const double* 
   if (!T->e_kp) return fail(EGFEM_ERR_ARG, "no element data attached (egfem_attach_elements)");
   if (r == u || r == a) return fail(EGFEM_ERR_ARG, "r must not alias u or a");
   EGFEM_HIP_CHECK(launch_action_elementwise(T, u, a, r, (hipStream_t)stream));
+  return EGFEM_OK;
+}
+
+int egfem_residual_unique(egfem_tensor_t T, const double* u, const double* a, double* r, void* stream) {
+  if (!T || !u || !a || !r) return fail(EGFEM_ERR_ARG, "null argument");
+  if (!T->u_val) return fail(EGFEM_ERR_ARG, "no unique storage attached (egfem_attach_unique)");
+  if (r == u || r == a) return fail(EGFEM_ERR_ARG, "r must not alias u or a");
+  EGFEM_HIP_CHECK(launch_action_unique(T, u, a, r, (hipStream_t)stream));
   return EGFEM_OK;
 }
 

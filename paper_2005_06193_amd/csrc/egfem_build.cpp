@@ -30,6 +30,7 @@
 //   tperm[s] = slot of (j,i); diag[i] = slot of (i,i).
 //   Row blocks: runs of rows that fit the LDS capacities of the tensor kernels.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -925,3 +926,152 @@ extern "C" int egfem_attach_elements(egfem_tensor_t T, int dim, int64_t n_nodes,
   return EGFEM_OK;
 }
 
+
+// Unique storage of the fully symmetric P1 mass tensor T_ijk = int phi_i phi_j phi_k:
+// one value per index multiset, i.e. T_iii per vertex, T_aab and T_abb per edge
+// (a < b) and T_abc per face of the mesh (three distinct vertices of one cell),
+// N + 2E + F values against N + 6E + 6F stored entries of the full stream.
+extern "C" int egfem_attach_unique(egfem_tensor_t T, int dim, int64_t n_nodes, const double* coords,
+                                   int64_t n_cells, const int32_t* cells, int64_t* n_unique) {
+  using namespace egfem;
+  if (!T || !coords || !cells) return fail(EGFEM_ERR_ARG, "null argument");
+  if (T->form != EGFEM_FORM_MASS || T->w2)
+    return fail(EGFEM_ERR_ARG, "the unique storage exists for the fully symmetric mass tensor with W_h = P1");
+  if (dim != T->dim || n_nodes != T->n || n_cells != T->n_cells)
+    return fail(EGFEM_ERR_SHAPE, "mesh sizes differ from the tensor's");
+  const int nl = dim + 1;
+  const int64_t N = n_nodes;
+  for (int64_t e = 0; e < n_cells * nl; ++e)
+    if (cells[e] < 0 || cells[e] >= N) return fail(EGFEM_ERR_MESH, "cell index out of range");
+  // edges (min * N + max) and faces (sorted vertex triples) of the cells
+  std::vector<int64_t> ekeys;
+  std::vector<std::array<int32_t, 3>> faces;
+  ekeys.reserve((size_t)n_cells * nl * dim / 2);
+  for (int64_t e = 0; e < n_cells; ++e) {
+    const int32_t* c = cells + e * nl;
+    for (int a = 0; a < nl; ++a)
+      for (int b = a + 1; b < nl; ++b) {
+        ekeys.push_back(std::min<int64_t>(c[a], c[b]) * N + std::max<int64_t>(c[a], c[b]));
+        for (int m = b + 1; m < nl; ++m) {
+          std::array<int32_t, 3> f = {c[a], c[b], c[m]};
+          std::sort(f.begin(), f.end());
+          faces.push_back(f);
+        }
+      }
+  }
+  std::sort(ekeys.begin(), ekeys.end());
+  ekeys.erase(std::unique(ekeys.begin(), ekeys.end()), ekeys.end());
+  std::sort(faces.begin(), faces.end());
+  faces.erase(std::unique(faces.begin(), faces.end()), faces.end());
+  const int64_t E = (int64_t)ekeys.size(), F = (int64_t)faces.size();
+  if (E >= (int64_t(1) << 30) || F >= (int64_t(1) << 31))
+    return fail(EGFEM_ERR_SHAPE, "too many edges or faces for the unique storage");
+  // every multiset appears in the full stream once per distinct ordering
+  if (N + 6 * E + 6 * F != T->nnz)
+    return fail(EGFEM_ERR_SHAPE, "the mesh does not match the tensor's entries");
+  auto edge_of = [&](int64_t x, int64_t y) {
+    const int64_t key = std::min(x, y) * N + std::max(x, y);
+    return (int64_t)(std::lower_bound(ekeys.begin(), ekeys.end(), key) - ekeys.begin());
+  };
+  auto face_of = [&](std::array<int32_t, 3> f) {
+    std::sort(f.begin(), f.end());
+    return (int64_t)(std::lower_bound(faces.begin(), faces.end(), f) - faces.begin());
+  };
+  const int64_t foff = N + 2 * E;
+  std::vector<double> val((size_t)(foff + F), 0.0);
+  for (int64_t e = 0; e < n_cells; ++e) {
+    const int32_t* c = cells + e * nl;
+    Geom g;
+    if (!cell_geometry(dim, coords, c, g)) return fail(EGFEM_ERR_MESH, "degenerate cell");
+    for (int a = 0; a < nl; ++a) {
+      int x[4] = {0, 0, 0, 0};
+      x[a] = 3;
+      val[c[a]] += g.vol * mono(dim, x);
+      for (int b = a + 1; b < nl; ++b) {
+        const int lo = c[a] < c[b] ? a : b, hi = c[a] < c[b] ? b : a;
+        const int64_t eid = edge_of(c[a], c[b]);
+        int y[4] = {0, 0, 0, 0};
+        y[lo] = 2;
+        y[hi] = 1;
+        val[N + 2 * eid] += g.vol * mono(dim, y);      // T_{lo lo hi}
+        int z[4] = {0, 0, 0, 0};
+        z[lo] = 1;
+        z[hi] = 2;
+        val[N + 2 * eid + 1] += g.vol * mono(dim, z);  // T_{lo hi hi}
+        for (int m = b + 1; m < nl; ++m) {
+          int w[4] = {0, 0, 0, 0};
+          w[a] = w[b] = w[m] = 1;
+          val[foff + face_of({c[a], c[b], c[m]})] += g.vol * mono(dim, w);
+        }
+      }
+    }
+  }
+  // slot references: the edge of every off-diagonal slot, with its orientation
+  const std::vector<int32_t>& rp = T->h_rowptr;
+  const std::vector<int32_t>& cl = T->h_col;
+  std::vector<int32_t> sref((size_t)T->slots, -1);
+  for (int64_t i = 0; i < N; ++i)
+    for (int32_t p = rp[i]; p < rp[i + 1]; ++p)
+      if (cl[p] != i) {
+        const int64_t eid = edge_of(i, cl[p]);
+        if (eid >= E || ekeys[eid] != std::min<int64_t>(i, cl[p]) * N + std::max<int64_t>(i, cl[p]))
+          return fail(EGFEM_ERR_SHAPE, "the mesh does not match the tensor's pattern");
+        sref[p] = (int32_t)(2 * eid + (i > cl[p] ? 1 : 0));
+      }
+  // face references of every row, in face order
+  std::vector<int32_t> fptr(N + 1, 0);
+  for (const auto& f : faces)
+    for (int v = 0; v < 3; ++v) fptr[f[v] + 1]++;
+  int max_faces = 0;
+  for (int64_t i = 0; i < N; ++i) {
+    max_faces = std::max(max_faces, fptr[i + 1]);
+    fptr[i + 1] += fptr[i];
+  }
+  std::vector<int32_t> fref((size_t)2 * fptr[N]);
+  {
+    std::vector<int32_t> fill(fptr.begin(), fptr.end() - 1);
+    auto local = [&](int64_t i, int32_t j) {
+      const auto b = cl.begin() + rp[i], en = cl.begin() + rp[i + 1];
+      const auto it = std::lower_bound(b, en, j);
+      return (it != en && *it == j) ? (int)(it - b) : -1;
+    };
+    for (int64_t t = 0; t < F; ++t)
+      for (int v = 0; v < 3; ++v) {
+        const int32_t i = faces[t][v], j = faces[t][(v + 1) % 3], k = faces[t][(v + 2) % 3];
+        const int sj = local(i, j), sk = local(i, k);
+        if (sj < 0 || sk < 0) return fail(EGFEM_ERR_SHAPE, "the mesh does not match the tensor's pattern");
+        const int32_t q = fill[i]++;
+        fref[2 * (size_t)q] = (int32_t)t;
+        fref[2 * (size_t)q + 1] = sj | (sk << 16);
+      }
+  }
+  if (T->max_row_slots > 512) return fail(EGFEM_ERR_SHAPE, "rows of more than 512 slots");
+  // replace previous data
+  for (void* p : {(void*)T->u_val, (void*)T->u_sref, (void*)T->u_fptr, (void*)T->u_fref})
+    if (p) hipFree(p);
+  T->u_val = nullptr;
+  T->u_sref = nullptr;
+  T->u_fptr = nullptr;
+  T->u_fref = nullptr;
+  int64_t bytes = 0;
+  int32_t* fr = nullptr;
+  int rc = upload(val, &T->u_val, &bytes);
+  if (rc == EGFEM_OK) rc = upload(sref, &T->u_sref, &bytes);
+  if (rc == EGFEM_OK) rc = upload(fptr, &T->u_fptr, &bytes);
+  if (rc == EGFEM_OK) rc = upload(fref, &fr, &bytes);
+  T->u_fref = reinterpret_cast<int2*>(fr);
+  if (rc != EGFEM_OK) return rc;
+  const int need = std::max(T->max_row_slots, max_faces);
+  const int stride = std::max(T->max_row_slots, 1);
+  int lanes = 2;
+  while (2 * lanes < need && lanes < 64) lanes *= 2;
+  // the rows of a workgroup stage u and a of their slots in at most 32 KB of LDS
+  while ((size_t)(kBlockThreads / lanes) * stride * 16 > 32768 && lanes < 64) lanes *= 2;
+  T->u_lanes = lanes;
+  T->u_stride = stride;
+  T->u_count = foff + F;
+  T->u_foff = foff;
+  T->device_bytes += bytes;
+  if (n_unique) *n_unique = T->u_count;
+  return EGFEM_OK;
+}

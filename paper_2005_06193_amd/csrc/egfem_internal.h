@@ -137,6 +137,16 @@ struct egfem_tensor_s {
   double* e_acoef = nullptr;    // W_h = P0: [cells] coefficient buffer of egfem_picard_grad / egfem_newton_grad
   double* e_wv = nullptr;       // W_h = P0: [cells * 4] derivative weights of the Newton Jacobian
   int32_t* p2_edges = nullptr;  // W_h = P2: [edges * 2] endpoints of every edge dof
+  // unique storage of the fully symmetric mass tensor (optional): every index
+  // multiset {i,j,k} once, as T_iii, then per edge (a < b) T_aab, T_abb, then per face T_abc
+  int64_t u_count = 0;          // N + 2E + F stored values
+  int64_t u_foff = 0;           // N + 2E: first face value
+  int u_lanes = 0;              // lanes per row of the unique-storage action
+  int u_stride = 0;             // LDS entries per row (most slots of a row)
+  double* u_val = nullptr;      // [u_count]
+  int32_t* u_sref = nullptr;    // [slots] 2 e + (i > j) for slot (i, j), j != i
+  int32_t* u_fptr = nullptr;    // [n+1] face-reference range of every row
+  int2* u_fref = nullptr;       // [3F] (face id, row-local slots of the other two vertices s_j | s_k << 16)
   uint32_t* wpq2 = nullptr;     // I_k: [wslots] slots of the third and fourth cell vertex
   uint8_t* wqi = nullptr;       // I_k: [wslots] point index
   double* qlam = nullptr;       // I_k: [4*4] barycentrics of the points
@@ -196,6 +206,8 @@ hipError_t launch_axpy(double* out, const double* x, double alpha, const double*
 hipError_t launch_p2_square(const egfem_tensor_s* T, const double* u, double* f, hipStream_t st);
 hipError_t launch_action_elementwise(const egfem_tensor_s* T, const double* u, const double* a, double* r,
                                      hipStream_t st);
+hipError_t launch_action_unique(const egfem_tensor_s* T, const double* u, const double* a, double* r,
+                                hipStream_t st);
 hipError_t launch_action_problem(const egfem_tensor_s* T, const ProblemView& pv, const double* u,
                                  const double* delta, double alpha, double* uout, double* F,
                                  double* partial, hipStream_t st);

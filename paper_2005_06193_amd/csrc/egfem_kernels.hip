@@ -235,6 +235,64 @@ __global__ __launch_bounds__(kBlockThreads) void k_action_elem(int64_t n, const 
   if (row < n && lane == 0) r[row] = acc;
 }
 
+// Raw action through the unique storage of the fully symmetric mass tensor
+// (each index multiset stored once):
+//   r_i = T_iii u_i a_i + sum_{j ~ i} [T_iij (u_i a_j + u_j a_i) + T_ijj u_j a_j]
+//       + sum_{faces {i,j,k}} T_ijk (u_j a_k + u_k a_j).
+// L lanes per row.  The slot pass gathers u_j, a_j of the row's columns,
+// adds the vertex and edge terms and stages the gathered values in LDS at
+// their row-local slot; the face pass reads them back by slot.  Fixed lane
+// order and a fixed butterfly: the sum is deterministic.
+template <int L>
+__global__ __launch_bounds__(kBlockThreads) void k_action_unique(int64_t n, int64_t foff, int stride,
+                                                                 const int32_t* __restrict__ rowptr,
+                                                                 const int32_t* __restrict__ col,
+                                                                 const int32_t* __restrict__ sref,
+                                                                 const int32_t* __restrict__ fptr,
+                                                                 const int2* __restrict__ fref,
+                                                                 const double* __restrict__ val,
+                                                                 const double* __restrict__ u,
+                                                                 const double* __restrict__ a,
+                                                                 double* __restrict__ r) {
+  extern __shared__ double lds_u[];   // [rows of the workgroup][2][stride]: u, then a
+  constexpr int RPB = kBlockThreads / L;
+  const int sub = (int)threadIdx.x / L, lane = (int)threadIdx.x % L;
+  const int64_t row = (int64_t)blockIdx.x * RPB + sub;
+  double* su = lds_u + (size_t)sub * 2 * stride;
+  double* sa = su + stride;
+  double acc = 0.0;
+  if (row < n) {
+    const int beg = rowptr[row], cnt = rowptr[row + 1] - beg;
+    const double ui = u[row], ai = a[row];
+    for (int s = lane; s < cnt; s += L) {
+      const int j = col[beg + s];
+      const double uj = u[j], aj = a[j];
+      su[s] = uj;
+      sa[s] = aj;
+      if (j == row) {
+        acc = fma(val[row], ui * ai, acc);
+      } else {
+        const int code = sref[beg + s];
+        const int o = code & 1;
+        const double* ev = val + n + (code - o);
+        acc = fma(ev[o], fma(ui, aj, uj * ai), acc);
+        acc = fma(ev[1 - o], uj * aj, acc);
+      }
+    }
+  }
+  __syncthreads();
+  if (row < n) {
+    for (int f = fptr[row] + lane; f < fptr[row + 1]; f += L) {
+      const int2 fr = fref[f];
+      const int sj = fr.y & 0xffff, sk = (int)((unsigned)fr.y >> 16);
+      acc = fma(val[foff + fr.x], fma(su[sj], sa[sk], su[sk] * sa[sj]), acc);
+    }
+  }
+#pragma unroll
+  for (int off = L / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, L);
+  if (row < n && lane == 0) r[row] = acc;
+}
+
 // Coefficient of a gradient nonlinearity per cell (W_h = P0, the gradient
 // interpolation of Sec. 3.2): z = sum_m u_{c_m} grad lambda_m, a_e = (c0 + c1 |z|^2)^q.
 // With wv != null also the derivative weights of the Newton Jacobian,
@@ -536,6 +594,29 @@ static void elem_launch_l(const egfem_tensor_s* T, const double* u, const double
     case 32: elem_launch<D, 32>(T, u, a, r, st); break;
     default: elem_launch<D, 64>(T, u, a, r, st); break;
   }
+}
+
+template <int L>
+static void unique_launch(const egfem_tensor_s* T, const double* u, const double* a, double* r, hipStream_t st) {
+  constexpr int RPB = kBlockThreads / L;
+  const int64_t blocks = (T->n + RPB - 1) / RPB;
+  const size_t lds = (size_t)RPB * 2 * T->u_stride * sizeof(double);
+  hipLaunchKernelGGL((k_action_unique<L>), dim3(blocks), dim3(kBlockThreads), lds, st, T->n, T->u_foff,
+                     T->u_stride, T->rowptr, T->col, T->u_sref, T->u_fptr, T->u_fref, T->u_val, u, a, r);
+}
+
+hipError_t launch_action_unique(const egfem_tensor_s* T, const double* u, const double* a, double* r,
+                                hipStream_t st) {
+  if (T->n <= 0) return hipSuccess;
+  switch (T->u_lanes) {
+    case 2: unique_launch<2>(T, u, a, r, st); break;
+    case 4: unique_launch<4>(T, u, a, r, st); break;
+    case 8: unique_launch<8>(T, u, a, r, st); break;
+    case 16: unique_launch<16>(T, u, a, r, st); break;
+    case 32: unique_launch<32>(T, u, a, r, st); break;
+    default: unique_launch<64>(T, u, a, r, st); break;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_grad_coef(const egfem_tensor_s* T, const double* u, double c0, double c1, double q, int linear,

@@ -112,6 +112,8 @@ def test_null_handles_rejected():
     assert lib.egfem_burgers(z, z, z, 0, z, z, z, z) == B.EGFEM_ERR_ARG
     assert lib.egfem_attach_elements(z, 2, 3, z, 1, z) == B.EGFEM_ERR_ARG
     assert lib.egfem_residual_elementwise(z, z, z, z, z) == B.EGFEM_ERR_ARG
+    assert lib.egfem_attach_unique(z, 2, 3, z, 1, z, None) == B.EGFEM_ERR_ARG
+    assert lib.egfem_residual_unique(z, z, z, z, z) == B.EGFEM_ERR_ARG
     assert lib.egfem_tensor_info(z, None) == B.EGFEM_ERR_ARG
     assert lib.egfem_newton_batched(0, None, None, None, None, None, None) == B.EGFEM_ERR_ARG
     lib.egfem_tensor_destroy(z)

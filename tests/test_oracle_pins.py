@@ -230,6 +230,31 @@ def test_mass_tensor_identities():
         assert np.abs(D.sum(axis=2) - M).max() < 1e-15
 
 
+def test_mass_tensor_unique_multisets():
+    """The fully symmetric mass tensor holds one value per index multiset: N of
+    the form iii, two per edge (iij, ijj), one per face (ijk), each stored in
+    the full tensor once per distinct ordering (1, 3 or 6 entries); on the 2D
+    n x n mesh N + 2E + F = 9 n^2 + 6 n + 1."""
+    for dim, n in [(1, 7), (2, 4), (2, 7), (3, 2)]:
+        m = W.structured_mesh(dim, n)
+        T = O.assemble_tensor(m.coords, m.cells, O.FORM_MASS)
+        groups = {}
+        for i, j, k, v in zip(T.i, T.j, T.k, T.v):
+            groups.setdefault(tuple(sorted((int(i), int(j), int(k)))), []).append(v)
+        edges, faces = set(), set()
+        for c in m.cells:
+            c = sorted(int(x) for x in c)
+            edges.update(itertools.combinations(c, 2))
+            faces.update(itertools.combinations(c, 3))
+        assert len(groups) == m.n_nodes + 2 * len(edges) + len(faces)
+        for key, vals in groups.items():
+            assert len(vals) == len(set(itertools.permutations(key)))
+            assert max(vals) - min(vals) <= 1e-15 * max(vals)   # orderings summed in other orders
+        assert T.nnz == m.n_nodes + 6 * len(edges) + 6 * len(faces)
+        if dim == 2:
+            assert len(groups) == 9 * n * n + 6 * n + 1
+
+
 def test_tensor_nnz_closed_forms():
     for n in (2, 3, 5, 8, 12):
         m = W.mesh_2d(n)
