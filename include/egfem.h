@@ -314,7 +314,8 @@ typedef struct {
   int n_krylov;
   int krylov_status_hist[EGFEM_HIST];     /* Krylov status of step k */
   double krylov_relres_hist[EGFEM_HIST];  /* Krylov relative residual of step k */
-  int krylov_kernels;        /* BiCGStab kernels that ran: bit 0 register-resident, bit 1 streaming */
+  int krylov_kernels;        /* BiCGStab kernels that ran: bit 0 register-resident, bit 1 streaming,
+                                bit 2 with the block-Jacobi preconditioner */
 } egfem_newton_stats;
 
 /* Fill opts with the defaults above. */
@@ -521,6 +522,14 @@ typedef struct {
                                 the diagonal halved, and sums h a_k and h u_k), one row block per
                                 workgroup; 0: the full stream (default; egfem_autotune picks the
                                 half stream where it is faster) */
+  int krylov_precond;        /* preconditioner of the register-resident BiCGStab: 0 = Jacobi
+                                D^-1; k in 2..32 = block-Jacobi (default 8): the rows are split
+                                by recursive coordinate bisection into one compact part per
+                                workgroup, and each workgroup applies k Chebyshev steps (Jacobi
+                                scaled, interval [lmax/30, lmax], lmax the Gershgorin bound of
+                                D^-1 J_b) to its diagonal block J_b: a fixed linear operator,
+                                workgroup-local (LDS), with no synchronisation between
+                                workgroups.  Streaming kernels and CG always use Jacobi. */
 } egfem_launch_shape;
 
 int egfem_get_shape(egfem_tensor_t T, egfem_launch_shape* s);
@@ -531,10 +540,12 @@ int egfem_set_shape(egfem_tensor_t T, const egfem_launch_shape* s);
 /* Autotuner: time the candidate shapes on this handle's own tensor with HIP
  * events on `stream` and keep the fastest in the handle.
  *   what: bit 0 -> tensor action (runs x {pipelined, not}); bit 1 -> Krylov grid
- *         (kernel x threads x blocks, per-iteration time of BiCGStab on DF(0) of
- *         problem p, which must then be non-NULL).
+ *         (kernel x threads x blocks, by the time per decade of residual
+ *         reduction of a BiCGStab solve of DF(0) x = 1 (free rows) to 1e-8 with
+ *         the handle's preconditioner; problem p must then be non-NULL).
  *   best (host, nullable) receives the chosen shape; best_us (host [2], nullable)
- *   the chosen action launch time and Krylov iteration time in microseconds.
+ *   the chosen action launch time and the chosen Krylov grid's iteration time in
+ *   microseconds.
  * Overwrites the handle's solver workspace.  Synchronises the stream. */
 int egfem_autotune(egfem_tensor_t T, const egfem_problem* p, int what, egfem_launch_shape* best,
                    double* best_us, void* stream);

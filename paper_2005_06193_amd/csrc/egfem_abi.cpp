@@ -67,6 +67,10 @@ static void free_workspace(Workspace& W) {
   if (W.ctrl) hipFree(W.ctrl);
   if (W.krow) hipFree(W.krow);
   if (W.knbr) hipFree(W.knbr);
+  if (W.crow) hipFree(W.crow);
+  if (W.cnbr) hipFree(W.cnbr);
+  if (W.crlist) hipFree(W.crlist);
+  if (W.ckloc) hipFree(W.ckloc);
   if (W.host_partial) hipHostFree(W.host_partial);
   if (W.host_kout) hipHostFree(W.host_kout);
   W = Workspace();
@@ -395,7 +399,7 @@ int egfem_newton(egfem_tensor_t T, const egfem_problem* p, double* u, const egfe
       ++stats.n_krylov;
     }
     stats.krylov_iters += kr.iters;
-    stats.krylov_kernels |= kr.resident ? 1 : 2;
+    stats.krylov_kernels |= (kr.resident ? 1 : 2) | (kr.block_precond ? 4 : 0);
     if (k < EGFEM_HIST) {
       stats.krylov_hist[k] = kr.iters;
       stats.krylov_status_hist[k] = kr.status;
@@ -537,7 +541,7 @@ int egfem_picard(egfem_tensor_t T, const egfem_problem* p, double* u, const egfe
     if (rc != EGFEM_OK) return rc;
     if (tm.on) stats.t_krylov_ms += kr.kernel_ms;
     stats.krylov_iters += kr.iters;
-    stats.krylov_kernels |= kr.resident ? 1 : 2;
+    stats.krylov_kernels |= (kr.resident ? 1 : 2) | (kr.block_precond ? 4 : 0);
     if (k < EGFEM_HIST) stats.krylov_hist[k] = kr.iters;
     // relative update, then u <- u^{n+1}
     hipError_t e = hipSuccess;
@@ -647,7 +651,7 @@ int egfem_burgers(egfem_tensor_t T, const uint8_t* dirichlet, const double* sour
     stats.krylov_iters += kr.iters;
     stats.max_step_krylov = std::max(stats.max_step_krylov, kr.iters);
     if (std::isfinite(kr.relres)) stats.max_relres = std::max(stats.max_relres, kr.relres);
-    stats.krylov_kernels |= kr.resident ? 1 : 2;
+    stats.krylov_kernels |= (kr.resident ? 1 : 2) | (kr.block_precond ? 4 : 0);
     if (n < EGFEM_HIST) stats.krylov_hist[n] = kr.iters;
     status = std::max(status, kr.status);
     if (kr.status == EGFEM_NONFINITE) {
@@ -725,7 +729,7 @@ int egfem_picard_grad(egfem_tensor_t T, const egfem_problem* p, const egfem_grad
     if (rc != EGFEM_OK) return rc;
     if (tm.on) stats.t_krylov_ms += kr.kernel_ms;
     stats.krylov_iters += kr.iters;
-    stats.krylov_kernels |= kr.resident ? 1 : 2;
+    stats.krylov_kernels |= (kr.resident ? 1 : 2) | (kr.block_precond ? 4 : 0);
     if (k < EGFEM_HIST) stats.krylov_hist[k] = kr.iters;
     hipError_t e = hipSuccess;
     const int ng = launch_diff_norms(T->n, W.delta, u, W.red, st, &e);
@@ -811,7 +815,7 @@ int egfem_newton_grad(egfem_tensor_t T, const egfem_problem* p, const egfem_grad
     KrylovResult kr;
     if ((rc = solve(W.rhs, 1.0, u, true, 1e-12, &kr)) != EGFEM_OK) return rc;
     stats.krylov_iters += kr.iters;
-    stats.krylov_kernels |= kr.resident ? 1 : 2;
+    stats.krylov_kernels |= (kr.resident ? 1 : 2) | (kr.block_precond ? 4 : 0);
   }
   double nF0 = 0.0;
   if ((rc = residual(u, &nF0)) != EGFEM_OK) return rc;
@@ -839,7 +843,7 @@ int egfem_newton_grad(egfem_tensor_t T, const egfem_problem* p, const egfem_grad
       ++stats.n_krylov;
     }
     stats.krylov_iters += kr.iters;
-    stats.krylov_kernels |= kr.resident ? 1 : 2;
+    stats.krylov_kernels |= (kr.resident ? 1 : 2) | (kr.block_precond ? 4 : 0);
     if (k < EGFEM_HIST) {
       stats.krylov_hist[k] = kr.iters;
       stats.krylov_status_hist[k] = kr.status;

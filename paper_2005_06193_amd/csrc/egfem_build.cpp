@@ -759,6 +759,7 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
   T->max_row_wslots = w2 ? max_row_wslots : max_row_slots;
   T->h_rowptr = rowptr;
   T->h_col = col;
+  T->h_coords.assign(coords, coords + (size_t)N * dim);
   hipGetDevice(&T->device);
   int64_t bytes = 0;
   int rc = EGFEM_OK;

@@ -1186,6 +1186,10 @@ struct KArgs {
   double rtol;
   int max_iter;
   int rel_r0;               // conjugate gradients: tolerance relative to ||r0|| instead of ||b||
+  // block-Jacobi preconditioner (register-resident BiCGStab on a compact partition)
+  const int32_t* rlist = nullptr;   // non-null: the workgroup's rows are rlist[rb, re)
+  const int16_t* kloc = nullptr;    // [slots] position of the column in the row's part, or -1
+  int cheb_steps = 0;               // 0: Jacobi D^-1; k >= 2: k Chebyshev steps on the workgroup's block
 };
 
 struct KOut {
@@ -1311,7 +1315,7 @@ __device__ KOut team_bicgstab(Team& tm, const KArgs& A, int rb, int re, double* 
   double rho = red[0];
   double rnorm = sqrt(red[0]);
   const double bnorm = sqrt(red[1]);
-  const double r0norm = rnorm;
+  double r0norm = rnorm;   // norm of the shadow residual rhat
   int restarts = 0;
   int slot = 1;
   int it = 0;
@@ -1337,6 +1341,7 @@ __device__ KOut team_bicgstab(Team& tm, const KArgs& A, int rb, int re, double* 
         }
         if ((o.abort = team_reduce<NT>(tm, 7, red, 1, sh, sh_abort))) break;
         rho = red[0];
+        r0norm = sqrt(red[0]);   // the test above scales by the new shadow residual
         continue;
       }
       // A: v = J phat, z = J rh ; (rhat, v)
@@ -1467,16 +1472,102 @@ __device__ __forceinline__ double row_dot(const unsigned (&off)[K], const double
   return acc;
 }
 
+// Block-Jacobi preconditioner of the register-resident BiCGStab.  The rows of
+// a workgroup form one diagonal block J_b of J (the entries whose column the
+// same workgroup owns), and z = M_b^-1 x approximates J_b^-1 x by a fixed
+// number of Chebyshev steps with the Jacobi scaling D^-1 (Saad, Iterative
+// Methods for Sparse Linear Systems, Sec. 12.3) on the interval
+// [lmax / kChebRatio, lmax], lmax the workgroup's Gershgorin bound of
+// D^-1 J_b.  The result is a fixed polynomial of D^-1 J_b applied to D^-1 x,
+// i.e. a linear operator, as BiCGStab requires.  In-block products read the
+// other rows' step vectors from LDS: one workgroup barrier per step and no
+// traffic between workgroups.
+constexpr double kChebRatio = 30.0;
+
+struct ChebParams {
+  double theta, delta, sigma;   // centre and half width of the interval, theta / delta
+};
+
+// lmax of the workgroup: max over its rows of |d_i| sum_{in-block j} |J_ij|
+// (own rows only; others contribute 0).  Every thread returns the same value.
+template <int NT, int K>
+__device__ ChebParams cheb_params(const int (&li)[K], const double (&aa)[K], double d, double* lds) {
+  double g = 0.0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) g += (li[k] < NT) ? fabs(aa[k]) : 0.0;
+  g *= fabs(d);
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) g = fmax(g, __shfl_xor(g, off));
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) lds[threadIdx.x / kWave] = g;
+  __syncthreads();
+  double lmax = 0.0;
+#pragma unroll
+  for (int w = 0; w < NT / kWave; ++w) lmax = fmax(lmax, lds[w]);
+  __syncthreads();
+  if (!(lmax > 0.0) || !isfinite(lmax)) lmax = 1.0;
+  const double lmin = lmax / kChebRatio;
+  ChebParams c;
+  c.theta = 0.5 * (lmax + lmin);
+  c.delta = 0.5 * (lmax - lmin);
+  c.sigma = c.theta / c.delta;
+  return c;
+}
+
+// z[v] = M_b^-1 x[v] for NV vectors at once (this thread's row values).  lds
+// holds two buffers of 2 (NT + 1) doubles; entry NT of each vector is 0 and
+// serves columns outside the block (li[k] = NT).  Called by every thread of
+// the workgroup.
+template <int NT, int K, int NV>
+__device__ __forceinline__ void block_cheb(const int (&li)[K], const double (&aa)[K], double d, int steps,
+                                           const ChebParams& c, double* lds, const double (&x)[NV],
+                                           double (&z)[NV]) {
+  const int tid = threadIdx.x;
+  double r[NV], dd[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    r[v] = x[v];
+    dd[v] = d * r[v] / c.theta;
+    z[v] = dd[v];
+  }
+  double rho_old = 1.0 / c.sigma;
+  __syncthreads();   // the previous call's last reads are done before this call's first writes
+  for (int k = 1; k < steps; ++k) {
+    double* buf = lds + (k & 1) * 2 * (NT + 1);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) buf[v * (NT + 1) + tid] = dd[v];
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double acc = 0.0;
+#pragma unroll
+      for (int e = 0; e < K; ++e) acc = fma(aa[e], buf[v * (NT + 1) + li[e]], acc);
+      r[v] -= acc;
+    }
+    const double rho = 1.0 / (2.0 * c.sigma - rho_old);
+    const double c1 = rho * rho_old, c2 = 2.0 * rho / c.delta;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      dd[v] = fma(c1, dd[v], c2 * d * r[v]);
+      z[v] += dd[v];
+    }
+    rho_old = rho;
+  }
+}
+
 template <int NT, int K>
 __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, double* sh, int* sh_abort) {
+  __shared__ double cheb_lds[4 * (NT + 1)];
   double red[kMaxRed];
   KOut o{EGFEM_NOT_CONVERGED, 0, 0.0, 0.0, false};
 #define EGFEM_ZERO_RED() for (int q_ = 0; q_ < kMaxRed; ++q_) red[q_] = 0.0
   const int i = rb + (int)threadIdx.x;
   const bool own = i < re;
-  const int row = max(min(i, re - 1), 0);   // in bounds also for an empty row range
+  const int q = max(min(i, re - 1), 0);     // in bounds also for an empty row range
+  const int row = A.rlist ? A.rlist[q] : q;
+  const bool bj = A.cheb_steps > 0;         // block-Jacobi preconditioner (uniform)
   // ---- the row's matrix entries (clamped in the row, zero past its end) ----
-  int vi[K];
+  int vi[K], li[K];
   unsigned cc[K];   // columns as byte offsets into a vector
   double aa[K];
   const int beg = A.rowptr[row], end = A.rowptr[row + 1];
@@ -1484,6 +1575,14 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
   for (int k = 0; k < K; ++k) {
     vi[k] = min(beg + k, end - 1);
     cc[k] = (unsigned)A.col[vi[k]] * 8u;
+    li[k] = NT;
+  }
+  if (bj) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int l = A.kloc[vi[k]];
+      li[k] = l >= 0 ? l : NT;
+    }
   }
   if (A.perm) {
 #pragma unroll
@@ -1496,7 +1595,20 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
   }
   const double d = A.dinv[row];
   const double b = A.rhs_scale * A.rhs[row];
-  // ---- r = b - J x ; rhat = p = r ; publish D^-1 r --------------------------
+  ChebParams cp{1.0, 1.0, 1.0};
+  if (bj) {
+    cp = cheb_params<NT, K>(li, aa, d, cheb_lds);
+    if (threadIdx.x < 4) cheb_lds[(threadIdx.x >> 1) * 2 * (NT + 1) + (threadIdx.x & 1) * (NT + 1) + NT] = 0.0;
+  }
+  // M^-1 of this thread's row values: D^-1 or the block-Jacobi operator
+  auto prec1 = [&](double x1) -> double {
+    if (!bj) return d * x1;
+    const double xs[1] = {x1};
+    double zs[1];
+    block_cheb<NT, K, 1>(li, aa, d, A.cheb_steps, cp, cheb_lds, xs, zs);
+    return zs[0];
+  };
+  // ---- r = b - J x ; rhat = p = r ; publish M^-1 r --------------------------
   double x = 0.0, r = b;
   if (!A.x_zero) {
     double g[K];
@@ -1508,11 +1620,14 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
     for (int k = 1; k < K; ++k) acc = fma(aa[k], g[k], acc);
     r = b - acc;
   }
+  if (!own) r = 0.0;
   double rh = r, p = r, v = 0.0, z = 0.0, sv = 0.0, tv = 0.0;
+  // this row's entries of the published vectors: M^-1 p, M^-1 r, M^-1 v
+  double ph = prec1(r), rhh = ph, vhh = 0.0;
   EGFEM_ZERO_RED();
   if (own) {
-    st_sh(A.phat + row, d * r);
-    st_sh(A.rh + row, d * r);
+    st_sh(A.phat + row, ph);
+    st_sh(A.rh + row, rhh);
     red[1] = b * b;
   }
   if ((o.abort = team_reduce<NT>(tm, 0, red, 2, sh, sh_abort))) return o;
@@ -1529,9 +1644,10 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
     // A: v = J phat, z = J rh ; (rhat, v), (r, r)
     v = row_dot<K>(cc, aa, A.phat);
     z = row_dot<K>(cc, aa, A.rh);
+    vhh = prec1(v);
     EGFEM_ZERO_RED();
     if (own) {
-      st_sh(A.vh + row, d * v);
+      st_sh(A.vh + row, vhh);
       red[0] = rh * v;
       red[1] = r * r;
     }
@@ -1548,11 +1664,14 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
     if (it >= A.max_iter) { o.status = EGFEM_NOT_CONVERGED; break; }
     if (fabs(rho) <= 1e-15 * r0norm * rnorm) {
       // lost bi-orthogonality: restart once from the current residual
+      // (p = r, so M^-1 p is the published M^-1 r)
       if (restarts++ >= 1) { o.status = EGFEM_BREAKDOWN; break; }
       rh = r;
       p = r;
-      if (own) st_sh(A.phat + row, d * r);
+      ph = rhh;
+      if (own) st_sh(A.phat + row, ph);
       rho = red[1];
+      r0norm = rnorm;   // the test above scales by the new shadow residual
       if ((o.abort = team_barrier(tm, sh_abort))) break;
       continue;
     }
@@ -1576,7 +1695,7 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
     slot = slot % 6 + 1;
     ++it;
     if (sqrt(red[4]) <= A.rtol * bnorm) {
-      x = fma(alpha, d * p, x);
+      x = fma(alpha, ph, x);
       rnorm = sqrt(red[4]);
       o.status = EGFEM_OK;
       break;
@@ -1590,15 +1709,25 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
     const double rho_new = fma(-omega, red[3], red[2]);
     const double beta = (rho_new / rho) * (alpha / omega);
     rho = rho_new;
-    // C: x, r, p ; publish phat, rh
-    x = fma(alpha, d * p, fma(omega, d * sv, x));
+    // C: x, r, p ; publish M^-1 p, M^-1 r  (M^-1 s = M^-1 r - alpha M^-1 v)
+    x = fma(alpha, ph, fma(omega, bj ? fma(-alpha, vhh, rhh) : d * sv, x));
     r = fma(-omega, tv, sv);
     p = fma(beta, fma(-omega, v, p), r);
-    if (own) {
-      st_sh(A.phat + row, d * p);
-      st_sh(A.rh + row, d * r);
+    if (bj) {
+      const double xs[2] = {p, r};
+      double zs[2];
+      block_cheb<NT, K, 2>(li, aa, d, A.cheb_steps, cp, cheb_lds, xs, zs);
+      ph = zs[0];
+      rhh = zs[1];
+    } else {
+      ph = d * p;
+      rhh = d * r;
     }
-    // phase A gathers D^-1 p and D^-1 r of neighbouring rows only; the two
+    if (own) {
+      st_sh(A.phat + row, ph);
+      st_sh(A.rh + row, rhh);
+    }
+    // phase A gathers M^-1 p and M^-1 r of neighbouring rows only; the two
     // team reductions before the next overwrite keep the reads ahead of it
     if ((o.abort = team_neighbor_sync(tm, sh_abort))) break;
   }

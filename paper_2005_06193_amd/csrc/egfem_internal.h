@@ -25,7 +25,23 @@ constexpr int kKrylovThreads = 1024;
 constexpr int kMaxKrylovBlocks = 1024;
 constexpr int kRedSlots = 10;     // reduction slots in flight (>= 2 barriers apart)
 constexpr int kCtrlWordsMax = 4096;  // barrier control words and publication flags
-constexpr int kMaxNbrLists = 8;      // neighbour workgroups kept per workgroup (more: team barrier)
+constexpr int kMaxNbrLists = 16;     // neighbour workgroups kept per workgroup (more, for any
+                                     // workgroup: every workgroup uses the team barrier)
+
+// Compact row partition of the register-resident Krylov solvers (recursive
+// coordinate bisection into G parts of balanced size).
+struct CompactPartition {
+  std::vector<int32_t> kr;      // [G+1] part offsets into rlist
+  std::vector<int32_t> rlist;   // [n] rows of every part, ascending within a part
+  std::vector<int16_t> kloc;    // [slots] row-local position of the column in the row's part, or -1
+  std::vector<int32_t> nbr;     // [G][kMaxNbrLists + 1] neighbour lists (count or -1, parts)
+  int maxrows = 0;
+};
+int make_compact_partition(int dim, const double* X, int64_t n, const int32_t* rowptr, const int32_t* col, int G,
+                           CompactPartition& out);
+// Neighbour lists [G][kMaxNbrLists + 1]: when any workgroup's list overflowed
+// (count -1), mark every list -1 (all workgroups then take the team barrier).
+void uniform_neighbor_lists(std::vector<int32_t>& nbr, int G);
 
 void set_error(const std::string& msg);
 int fail(int code, const std::string& msg);
@@ -59,6 +75,13 @@ struct Workspace {
   int krow_blocks = 0;          // grid size the partition was made for
   int krow_maxrows = 0;         // most rows of one workgroup in that partition
   int32_t* knbr = nullptr;      // per workgroup: neighbour count (-1: too many), ranks
+  // compact partition of the block-Jacobi preconditioner (recursive coordinate bisection)
+  int32_t* crow = nullptr;      // [kMaxKrylovBlocks + 1] part offsets into crlist
+  int32_t* crlist = nullptr;    // [n] rows of every part
+  int16_t* ckloc = nullptr;     // [slots] row-local column position within the part, or -1
+  int32_t* cnbr = nullptr;      // neighbour lists of the parts
+  int crow_blocks = 0;          // grid size the compact partition was made for
+  int crow_maxrows = 0;
   double* kout = nullptr;       // Krylov result [4] (device)
   double* host_partial = nullptr;  // pinned host mirror of partial sums
   double* host_kout = nullptr;     // pinned host mirror of the Krylov result
@@ -86,6 +109,7 @@ struct egfem_tensor_s {
   int tuned_krylov_blocks = 0;  // Krylov grid chosen by the autotuner (0 = heuristic)
   int tuned_krylov_threads = 0;
   int krylov_kernel = 0;        // 0: register-resident where it fits, 1: streaming
+  int krylov_precond = 8;       // 0: Jacobi; k >= 2: block-Jacobi, k Chebyshev steps per block (resident BiCGStab)
   int device = 0;
   // W_h = P2 (Case 1, w2 = 1): k runs over the P2 dofs (vertices, then edges);
   // W_h = I_k (Case 3, w2 = 2): k runs over the quadrature points of the cells;
@@ -153,6 +177,7 @@ struct egfem_tensor_s {
   int64_t row_blocks = 0;
   std::vector<int32_t> h_rowptr;  // host copy (row partitions)
   std::vector<int32_t> h_col;     // host copy (neighbour lists of a partition)
+  std::vector<double> h_coords;   // host copy of the node coordinates (compact partitions)
   int64_t device_bytes = 0;
   egfem::Workspace ws;
 };
@@ -252,6 +277,7 @@ struct KrylovResult {
   int threads = 0;
   double kernel_ms = 0.0;   // launch duration of the persistent kernel (when timed)
   bool resident = false;    // the register-resident kernel ran
+  bool block_precond = false;   // with the block-Jacobi preconditioner
 };
 enum class KrylovMethod { kBiCGStab, kCG };
 

@@ -200,12 +200,50 @@ int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, con
       }
       lst[0] = cnt;
     }
+    uniform_neighbor_lists(nb, G);
     EGFEM_HIP_CHECK(hipMemcpyAsync(W.knbr, nb.data(), nb.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
     EGFEM_HIP_CHECK(hipMemcpyAsync(W.krow, kr.data(), kr.size() * sizeof(int32_t),
                                    hipMemcpyHostToDevice, st));
     EGFEM_HIP_CHECK(hipStreamSynchronize(st));
     W.krow_blocks = G;
   }
+  // register-resident form when every workgroup's rows fit its threads, rows
+  // hold at most kResidentRow entries, and the grid is co-resident for it
+  // (columns are held as 32-bit byte offsets: n < 2^28)
+  const void* kreg = kernel_for(NT, method, true, 0);
+  const bool resident_ok = T->krylov_kernel == 0 && T->max_row_slots <= kResidentRow &&
+                           T->n < (int64_t(1) << 28) && G <= coresident(kreg, NT);
+  // block-Jacobi preconditioner: resident BiCGStab on a compact partition
+  bool block = method == KrylovMethod::kBiCGStab && resident_ok && T->krylov_precond > 0 &&
+               !T->h_coords.empty() && (T->n + G - 1) / G <= NT;
+  if (block && W.crow_blocks != G) {
+    CompactPartition cp;
+    if ((rc = make_compact_partition(T->dim, T->h_coords.data(), T->n, T->h_rowptr.data(), T->h_col.data(), G,
+                                     cp)) != EGFEM_OK)
+      return rc;
+    if (!W.crlist) {
+      if (hipMalloc((void**)&W.crow, ((size_t)kMaxKrylovBlocks + 1) * sizeof(int32_t)) != hipSuccess ||
+          hipMalloc((void**)&W.cnbr, (size_t)kMaxKrylovBlocks * (kMaxNbrLists + 1) * sizeof(int32_t)) !=
+              hipSuccess ||
+          hipMalloc((void**)&W.crlist, std::max<size_t>(T->n, 1) * sizeof(int32_t)) != hipSuccess ||
+          hipMalloc((void**)&W.ckloc, std::max<size_t>(T->slots, 1) * sizeof(int16_t)) != hipSuccess)
+        return fail(EGFEM_ERR_OOM, "hipMalloc of the compact partition failed");
+      T->device_bytes += (int64_t)(((size_t)kMaxKrylovBlocks + 1) * 4 +
+                                   (size_t)kMaxKrylovBlocks * (kMaxNbrLists + 1) * 4 + (size_t)T->n * 4 +
+                                   (size_t)T->slots * 2);
+    }
+    EGFEM_HIP_CHECK(hipMemcpyAsync(W.crow, cp.kr.data(), cp.kr.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    EGFEM_HIP_CHECK(hipMemcpyAsync(W.cnbr, cp.nbr.data(), cp.nbr.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                   st));
+    EGFEM_HIP_CHECK(hipMemcpyAsync(W.crlist, cp.rlist.data(), cp.rlist.size() * sizeof(int32_t),
+                                   hipMemcpyHostToDevice, st));
+    EGFEM_HIP_CHECK(hipMemcpyAsync(W.ckloc, cp.kloc.data(), cp.kloc.size() * sizeof(int16_t),
+                                   hipMemcpyHostToDevice, st));
+    EGFEM_HIP_CHECK(hipStreamSynchronize(st));
+    W.crow_blocks = G;
+    W.crow_maxrows = cp.maxrows;
+  }
+  block = block && W.crow_maxrows <= NT;   // one thread per row
   EGFEM_HIP_CHECK(launch_fill_u32(W.ctrl, 0u, dev::kCtrlWords, st));
   LaunchArgs P;
   KArgs& A = P.A;
@@ -232,8 +270,13 @@ int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, con
   A.rtol = rtol;
   A.max_iter = max_iter;
   A.rel_r0 = rel_r0 ? 1 : 0;
-  P.krow = W.krow;
-  P.nbr = W.knbr;
+  P.krow = block ? W.crow : W.krow;
+  P.nbr = block ? W.cnbr : W.knbr;
+  if (block) {
+    A.rlist = W.crlist;
+    A.kloc = W.ckloc;
+    A.cheb_steps = T->krylov_precond;
+  }
   P.ctrl = W.ctrl;
   P.red = W.red;
   P.out = W.kout;
@@ -243,12 +286,7 @@ int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, con
     EGFEM_HIP_CHECK(hipEventCreate(&ev1));
     EGFEM_HIP_CHECK(hipEventRecord(ev0, st));
   }
-  // register-resident form when every workgroup's rows fit its threads, rows
-  // hold at most kResidentRow entries, and the grid is co-resident for it
-  // (columns are held as 32-bit byte offsets: n < 2^28)
-  const void* kreg = kernel_for(NT, method, true, 0);
-  const bool resident = T->krylov_kernel == 0 && T->max_row_slots <= kResidentRow &&
-                        W.krow_maxrows <= NT && T->n < (int64_t(1) << 28) && G <= coresident(kreg, NT);
+  const bool resident = block || (resident_ok && W.krow_maxrows <= NT);
   const void* kern = resident ? kreg : kernel_for(NT, method, false, T->krylov_rs);
   void* args[] = {(void*)&P};
   const hipError_t e = hipLaunchCooperativeKernel(kern, dim3((unsigned)G), dim3((unsigned)NT), args, 0, st);
@@ -275,6 +313,7 @@ int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, con
   res->blocks = G;
   res->threads = NT;
   res->resident = resident;
+  res->block_precond = block;
   if (res->status == EGFEM_ERR_HIP) return fail(EGFEM_ERR_HIP, "Krylov grid barrier timed out");
   return EGFEM_OK;
 }

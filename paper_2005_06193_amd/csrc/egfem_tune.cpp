@@ -2,6 +2,7 @@
 // events on the handle's own tensor and the fastest is kept in the handle.
 #include <algorithm>
 #include <cfloat>
+#include <cmath>
 #include <vector>
 
 #include "egfem_internal.h"
@@ -47,6 +48,7 @@ int egfem_get_shape(egfem_tensor_t T, egfem_launch_shape* s) {
   s->krylov_threads = T->tuned_krylov_threads;
   s->krylov_kernel = T->krylov_kernel;
   s->action_half = T->action_half;
+  s->krylov_precond = T->krylov_precond;
   return EGFEM_OK;
 }
 
@@ -56,7 +58,8 @@ int egfem_set_shape(egfem_tensor_t T, const egfem_launch_shape* s) {
       s->krylov_blocks > kMaxKrylovBlocks ||
       (s->krylov_threads != 0 && s->krylov_threads != 256 && s->krylov_threads != 512 &&
        s->krylov_threads != 1024) ||
-      (s->krylov_kernel != 0 && s->krylov_kernel != 1) || (s->action_half != 0 && s->action_half != 1))
+      (s->krylov_kernel != 0 && s->krylov_kernel != 1) || (s->action_half != 0 && s->action_half != 1) ||
+      s->krylov_precond < 0 || s->krylov_precond == 1 || s->krylov_precond > 32)
     return fail(EGFEM_ERR_ARG, "invalid launch shape");
   if (s->action_half && !T->vH) return fail(EGFEM_ERR_ARG, "this tensor has no symmetric half stream");
   T->action_runs_target = s->action_runs;
@@ -65,6 +68,7 @@ int egfem_set_shape(egfem_tensor_t T, const egfem_launch_shape* s) {
   T->tuned_krylov_threads = s->krylov_threads;
   T->krylov_kernel = s->krylov_kernel;
   T->action_half = s->action_half;
+  T->krylov_precond = s->krylov_precond;
   return EGFEM_OK;
 }
 
@@ -120,13 +124,15 @@ int egfem_autotune(egfem_tensor_t T, const egfem_problem* p, int what, egfem_lau
     us_action = best_t;
   }
   if (what & 2) {
-    // DF at u = 0 of the problem; BiCGStab iterations at an unreachable tolerance
+    // DF at u = 0 of the problem, right-hand side 1 on the free rows: the time
+    // per decade of residual reduction of a BiCGStab solve to 1e-8 (the block
+    // preconditioner trades cost per iteration against iterations)
     EGFEM_HIP_CHECK(launch_fill(W.utry, 0.0, T->n, st));
     EGFEM_HIP_CHECK(launch_jacobian(T, W.utry, nullptr, p->a0, p->a0_const, 1, nullptr, 1, p->add_stiffness,
                                     p->dirichlet, W.jval, W.dinv, st));
     EGFEM_HIP_CHECK(launch_fill(W.rhs, 1.0, T->n, st));
     EGFEM_HIP_CHECK(launch_mask_zero(W.rhs, p->dirichlet, T->n, st));
-    double best_t = DBL_MAX;
+    double best_t = DBL_MAX, best_iter_us = 0.0;
     int bb = 0, bt = 0, bk = 0;
     const int keep_kernel = T->krylov_kernel;
     for (int kernel : {0, 1})
@@ -134,7 +140,7 @@ int egfem_autotune(egfem_tensor_t T, const egfem_problem* p, int what, egfem_lau
         for (int blocks : {32, 64, 128, 256, 512, 1024}) {
           T->krylov_kernel = kernel;
           KrylovResult kr;
-          rc = krylov_bicgstab(T, W.jval, W.dinv, W.rhs, 1.0, W.delta, true, 1e-300, 40, blocks, &kr, st,
+          rc = krylov_bicgstab(T, W.jval, W.dinv, W.rhs, 1.0, W.delta, true, 1e-8, 3000, blocks, &kr, st,
                                nullptr, true, threads);
           if (rc != EGFEM_OK) {
             T->krylov_kernel = keep_kernel;
@@ -142,9 +148,11 @@ int egfem_autotune(egfem_tensor_t T, const egfem_problem* p, int what, egfem_lau
           }
           // the register-resident kernel only where it applies (else it repeats kernel 1)
           if (kr.iters <= 0 || (kernel == 0 && !kr.resident)) continue;
-          const double us = 1000.0 * kr.kernel_ms / kr.iters;
-          if (us < best_t) {
-            best_t = us;
+          if (!(kr.relres > 0.0 && kr.relres < 1.0)) continue;
+          const double per_decade = kr.kernel_ms / -std::log10(kr.relres);
+          if (per_decade < best_t) {
+            best_t = per_decade;
+            best_iter_us = 1000.0 * kr.kernel_ms / kr.iters;
             bb = kr.blocks;
             bt = kr.threads;
             bk = kernel;
@@ -153,7 +161,7 @@ int egfem_autotune(egfem_tensor_t T, const egfem_problem* p, int what, egfem_lau
     T->tuned_krylov_blocks = bb;
     T->tuned_krylov_threads = bt;
     T->krylov_kernel = bk;
-    us_krylov = best_t;
+    us_krylov = best_iter_us;
   }
   if (best) egfem_get_shape(T, best);
   if (best_us) {

@@ -226,6 +226,69 @@ def test_bicgstab_solve(transpose, kernel):
     assert relerr(A @ host(x), rhs) < 1e-12
 
 
+BJ_MESHES = {
+    "1d_n120": lambda: W.mesh_1d(120),
+    "2d_jitter_n45": lambda: irregular_mesh(45),
+    "disk_n40": lambda: W.mesh_disk(40),
+}
+
+
+@pytest.mark.parametrize("precond", [0, 2, 8, 32])
+@pytest.mark.parametrize("transpose", [False, True])
+@pytest.mark.parametrize("mesh", list(BJ_MESHES))
+def test_bicgstab_block_preconditioner(mesh, transpose, precond):
+    """BiCGStab with the block-Jacobi preconditioner (k Chebyshev steps on each
+    workgroup's block of a coordinate-bisection partition) against SuperLU on
+    a nonsymmetric Newton Jacobian, for several grids (one of them with more
+    neighbours per part than the point-to-point lists hold, so every workgroup
+    takes the team barrier); fewer iterations than Jacobi."""
+    m = BJ_MESHES[mesh]()
+    rng = np.random.default_rng(12)
+    wl = W.Workload("t", m, rng.uniform(0, 10, m.n_nodes), 0, None, 1.0, False, 1e-12, 0)
+    T = eg().Tensor.from_mesh(m, 0)
+    p = gpu_problem(T, wl)
+    po = O.build_problem(wl)
+    u = rng.uniform(0, 1, T.n)
+    u[po.dirichlet] = 0
+    jv = T.problem_jacobian(p, dt(u))
+    Jo = O.jacobian(po, u)
+    A = (Jo.T if transpose else Jo).tocsc()
+    rhs = rng.uniform(-1, 1, T.n)
+    xo = spla.spsolve(A, rhs)
+    cond = np.linalg.cond(A.toarray())
+    iters = {}
+    for blocks, threads in ((0, 0), (7, 1024), (64, 256), (33, 512)):
+        if blocks and (T.n + blocks - 1) // blocks > 1024:
+            continue
+        for pc in sorted({0, precond}):
+            print(f"bicgstab block-Jacobi mesh={mesh} transpose={transpose} precond={pc} grid={blocks}x{threads}",
+                  flush=True)
+            T.set_shape(krylov_precond=pc, krylov_blocks=blocks, krylov_threads=threads)
+            x, rc, its, rr = T.solve(jv, dt(rhs), transpose=transpose, rtol=1e-12)
+            assert rc == 0, (rc, its, rr)
+            # the recursive residual reaches 1e-12; the true one differs from it by
+            # the residual gap, of order eps cond(A)
+            res = relerr(A @ host(x), rhs)
+            assert res < max(5e-12, 2e-16 * cond)
+            assert relerr(host(x), xo) < cond * max(res, 1e-12) * 10
+            iters[(blocks, pc)] = its
+            # deterministic for a fixed grid
+            x2, _, its2, _ = T.solve(jv, dt(rhs), transpose=transpose, rtol=1e-12)
+            assert its2 == its and torch.equal(x, x2)
+    if precond >= 8 and mesh != "1d_n120":
+        assert iters[(0, precond)] < iters[(0, 0)]
+
+
+def test_block_preconditioner_shape_validation():
+    T = eg().Tensor.from_mesh(W.mesh_2d(6), 0)
+    assert T.get_shape()["krylov_precond"] == 8
+    for bad in (-1, 1, 33):
+        with pytest.raises(eg().EgfemError):
+            T.set_shape(krylov_precond=bad)
+    T.set_shape(krylov_precond=2)
+    assert T.get_shape()["krylov_precond"] == 2
+
+
 # ---------------------------------------------------------------------------
 # Newton
 # ---------------------------------------------------------------------------
@@ -250,19 +313,20 @@ def test_newton_matches_oracle(name):
     assert np.linalg.norm(O.residual(po, ug)) <= 1e-11 * Fo0
 
 
-@pytest.mark.parametrize("kernel", [0, 1])
-def test_newton_krylov_kernels(kernel):
-    """The register-resident and the streaming BiCGStab give the oracle's
-    solution, and the statistics name the kernel that ran."""
+@pytest.mark.parametrize("kernel,precond", [(0, 8), (0, 0), (1, 8)])
+def test_newton_krylov_kernels(kernel, precond):
+    """The register-resident BiCGStab (block-Jacobi or Jacobi) and the
+    streaming one (always Jacobi) give the oracle's solution, and the
+    statistics name the kernel that ran (bit 2: block preconditioner)."""
     wl = W.nonlinear_diffusion_2d(40, seed=77)
     T = eg().Tensor.from_mesh(wl.mesh, wl.form)
-    T.set_shape(krylov_kernel=kernel)
+    T.set_shape(krylov_kernel=kernel, krylov_precond=precond)
     p = gpu_problem(T, wl)
     po = O.build_problem(wl)
     u = torch.zeros(T.n, dtype=torch.float64, device=DEV)
     st = T.newton(p, u, _tight(), warn=False)
     assert st.status in (0, 4), st.status_name
-    assert st.krylov_kernels == (1 if kernel == 0 else 2)
+    assert st.krylov_kernels == ((5 if precond else 1) if kernel == 0 else 2)
     uo, _ = O.newton(po, tol=1e-14, max_iter=30)
     assert relerr(host(u), uo) <= 1e-10
 
