@@ -2,8 +2,8 @@
 """EGFEM Newton hot-path benchmark on one MI355X.
 
 A step is one complete EGFEM Newton solve (pointwise coefficient update fused
-into the tensor actions, residual action, Jacobian emission, Jacobi-BiCGStab,
-damped update) of the 2D nonlinear-diffusion workload
+into the tensor actions, residual action, Jacobian emission, BiCGStab with
+the workgroup-local block-Jacobi preconditioner, damped update) of the 2D nonlinear-diffusion workload
 -div((1+u^2) grad u) = f on the 256x256 right-triangle P1 mesh (66,049 nodes),
 from u = 0 to ||F|| <= 1e-10 ||F(0)||, inputs resident in HBM.  The offline
 tensor build is not timed (the paper's online-time convention).
@@ -333,6 +333,11 @@ def batched_suite(reps: int = 3):
     res["autotuned"] = best
     res["batched_ms"] = best["ms"] if best else None
     res["batched_solves_per_s"] = 64 / (best["ms"] * 1e-3) if best else None
+    # one untimed solve per handle first: its partitions and workspace are
+    # built once per handle, as for a caller that reuses its handles
+    for T, P, u in zip(Ts, Ps, us):
+        u.zero_()
+        T.newton(P, u, opts)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for T, P, u in zip(Ts, Ps, us):
@@ -529,7 +534,7 @@ def burgers_suite(n: int = 256, reps: int = 2):
     src = torch.tensor(b.source, dtype=torch.float64, device="cuda")
     u0 = torch.tensor(b.u0, dtype=torch.float64, device="cuda")
     out = {"workload": b.name, "nodes": T1.n, "tensor_nnz": T1.info.nnz, "p2_tensor_nnz": T2.info.nnz,
-           "steps": b.steps, "dt": b.dt, "nu": b.nu, "krylov": "cg-jacobi, rtol 1e-12 per step"}
+           "steps": b.steps, "dt": b.dt, "nu": b.nu, "krylov": "cg, block-jacobi, rtol 1e-12 per step"}
     for name, T, group in (("tensor", T1, 0), ("group", T1, 1), ("egfem_p2_group", T2, 1)):
         u = u0.clone()
         T.burgers(u, dirm, src, eg.BurgersOptions(steps=10, group=group))            # warm
@@ -701,7 +706,9 @@ def main():
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch,
                 "limiter": ("synchronisation: two team reductions and one neighbour synchronisation per "
-                            "BiCGStab iteration; the register-resident kernel keeps J and the row vectors on chip"
+                            "BiCGStab iteration, plus three workgroup-local block-Jacobi applications "
+                            "(%d Chebyshev steps each, in LDS); the register-resident kernel keeps J and the "
+                            "row vectors on chip" % T.get_shape()["krylov_precond"]
                             + (", measured HBM traffic %.2fx the algorithmic bytes"
                                % tr["krylov_bicgstab"]["ratio"] if traffic is not None else ""))
                 if dom == "krylov_bicgstab" else None}
@@ -748,7 +755,8 @@ def main():
         "config": {"workload": f"nonlinear_diffusion_2d_{args.n}x{args.n}_p1",
                    "nodes": info.n_nodes, "tensor_nnz": info.nnz, "slots": info.slots,
                    "newton_tol": wl.tol, "forcing": "eisenstat-walker-2",
-                   "krylov": "bicgstab-jacobi"},
+                   "krylov": ("bicgstab, block-jacobi (coordinate-bisection blocks, %d chebyshev steps)"
+                              % T.get_shape()["krylov_precond"])},
         "converged": ok,
         "autotuned_shape": tuned,
         "newton_iters_per_solve": sum(s.newton_iters for s in stats) / len(stats),

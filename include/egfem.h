@@ -529,7 +529,9 @@ typedef struct {
                                 scaled, interval [lmax/30, lmax], lmax the Gershgorin bound of
                                 D^-1 J_b) to its diagonal block J_b: a fixed linear operator,
                                 workgroup-local (LDS), with no synchronisation between
-                                workgroups.  Streaming kernels and CG always use Jacobi. */
+                                workgroups.  The register-resident CG uses the same operator
+                                (symmetric positive definite for an SPD matrix: the polynomial
+                                is positive on the spectrum); streaming kernels use Jacobi. */
 } egfem_launch_shape;
 
 int egfem_get_shape(egfem_tensor_t T, egfem_launch_shape* s);

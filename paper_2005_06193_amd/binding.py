@@ -706,8 +706,9 @@ class Tensor:
         return stats
 
     def solve_cg(self, jval, rhs, x=None, rtol=1e-12, max_iter=20000):
-        """Jacobi-preconditioned conjugate gradients for an SPD matrix in the
-        tensor's pattern; returns (x, status, iterations, relres)."""
+        """Preconditioned conjugate gradients (the handle's preconditioner:
+        block-Jacobi or Jacobi) for an SPD matrix in the tensor's pattern;
+        returns (x, status, iterations, relres)."""
         x = torch.zeros_like(rhs) if x is None else x
         it = C.c_int(0)
         rr = C.c_double(0.0)

@@ -1738,26 +1738,30 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
   return o;
 }
 
-// Jacobi-preconditioned conjugate gradients for a symmetric positive definite
-// J (the Picard matrix), in the single-reduction arrangement of Chronopoulos
-// and Gear: with u = D^-1 r and w = J u, the scalars gamma = (r, u) and
+// Preconditioned conjugate gradients for a symmetric positive definite J (the
+// Picard matrix), in the single-reduction arrangement of Chronopoulos and
+// Gear: with u = M^-1 r and w = J u, the scalars gamma = (r, u) and
 // delta = (w, u) give beta = gamma / gamma_prev and
 // alpha = gamma / (delta - beta gamma / alpha_prev), and s = J p is kept by the
-// recurrence s = w + beta s.  Per iteration: one product (gathering D^-1 r),
-// one reduction of (r, u), (w, u), (r, r), one barrier after publishing D^-1 r.
+// recurrence s = w + beta s.  Per iteration: one product (gathering M^-1 r),
+// one reduction of (r, u), (w, u), (r, r), one barrier after publishing M^-1 r.
 // Stops when ||r|| <= rtol ||r0|| (rel_r0) or rtol ||b||.
 // Register-resident form: one thread per row (rows fit the workgroup's
 // threads, at most K entries), matrix row, D^-1 and the row's x, r, p, s in
-// registers for the whole solve.
+// registers for the whole solve; M is D (Jacobi) or, on a compact partition,
+// the block-Jacobi operator of block_cheb.
 template <int NT, int K>
 __device__ KOut team_pcg_reg(Team& tm, const KArgs& A, int rb, int re, double* sh, int* sh_abort) {
+  __shared__ double cheb_lds[4 * (NT + 1)];
   double red[kMaxRed];
   KOut o{EGFEM_NOT_CONVERGED, 0, 0.0, 0.0, false};
 #define EGFEM_ZERO_RED() for (int q_ = 0; q_ < kMaxRed; ++q_) red[q_] = 0.0
   const int i = rb + (int)threadIdx.x;
   const bool own = i < re;
-  const int row = max(min(i, re - 1), 0);
-  int vi[K];
+  const int q = max(min(i, re - 1), 0);
+  const int row = A.rlist ? A.rlist[q] : q;
+  const bool bj = A.cheb_steps > 0;         // block-Jacobi preconditioner (uniform)
+  int vi[K], li[K];
   unsigned cc[K];
   double aa[K];
   const int beg = A.rowptr[row], end = A.rowptr[row + 1];
@@ -1765,6 +1769,14 @@ __device__ KOut team_pcg_reg(Team& tm, const KArgs& A, int rb, int re, double* s
   for (int k = 0; k < K; ++k) {
     vi[k] = min(beg + k, end - 1);
     cc[k] = (unsigned)A.col[vi[k]] * 8u;
+    li[k] = NT;
+  }
+  if (bj) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int l = A.kloc[vi[k]];
+      li[k] = l >= 0 ? l : NT;
+    }
   }
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -1773,6 +1785,20 @@ __device__ KOut team_pcg_reg(Team& tm, const KArgs& A, int rb, int re, double* s
   }
   const double d = A.dinv[row];
   const double b = A.rhs_scale * A.rhs[row];
+  ChebParams cp{1.0, 1.0, 1.0};
+  if (bj) {
+    cp = cheb_params<NT, K>(li, aa, d, cheb_lds);
+    if (threadIdx.x < 4) cheb_lds[(threadIdx.x >> 1) * 2 * (NT + 1) + (threadIdx.x & 1) * (NT + 1) + NT] = 0.0;
+  }
+  // M^-1 of this thread's row value: D^-1 or the block-Jacobi operator (SPD
+  // for an SPD J: the Chebyshev polynomial is positive on (0, lmax])
+  auto prec1 = [&](double x1) -> double {
+    if (!bj) return d * x1;
+    const double xs[1] = {x1};
+    double zs[1];
+    block_cheb<NT, K, 1>(li, aa, d, A.cheb_steps, cp, cheb_lds, xs, zs);
+    return zs[0];
+  };
   double x = 0.0, r = b;
   if (!A.x_zero) {
     double g[K];
@@ -1784,7 +1810,8 @@ __device__ KOut team_pcg_reg(Team& tm, const KArgs& A, int rb, int re, double* s
     for (int k = 1; k < K; ++k) acc = fma(aa[k], g[k], acc);
     r = b - acc;
   }
-  double u = d * r, p = 0.0, s = 0.0;
+  if (!own) r = 0.0;
+  double u = prec1(r), p = 0.0, s = 0.0;
   EGFEM_ZERO_RED();
   if (own) {
     st_sh(A.phat + row, u);
@@ -1818,12 +1845,12 @@ __device__ KOut team_pcg_reg(Team& tm, const KArgs& A, int rb, int re, double* s
     s = fma(beta, s, w);
     x = fma(alpha, p, x);
     r = fma(-alpha, s, r);
-    u = d * r;
+    u = prec1(r);
     if (own) st_sh(A.phat + row, u);
     gamma_prev = gamma;
     alpha_prev = alpha;
     ++it;
-    // the next product gathers D^-1 r of neighbouring rows; the reduction
+    // the next product gathers M^-1 r of neighbouring rows; the reduction
     // before the next overwrite keeps every read ahead of it
     if ((o.abort = team_neighbor_sync(tm, sh_abort))) break;
   }

@@ -213,9 +213,8 @@ int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, con
   const void* kreg = kernel_for(NT, method, true, 0);
   const bool resident_ok = T->krylov_kernel == 0 && T->max_row_slots <= kResidentRow &&
                            T->n < (int64_t(1) << 28) && G <= coresident(kreg, NT);
-  // block-Jacobi preconditioner: resident BiCGStab on a compact partition
-  bool block = method == KrylovMethod::kBiCGStab && resident_ok && T->krylov_precond > 0 &&
-               !T->h_coords.empty() && (T->n + G - 1) / G <= NT;
+  // block-Jacobi preconditioner: the resident kernels on a compact partition
+  bool block = resident_ok && T->krylov_precond > 0 && !T->h_coords.empty() && (T->n + G - 1) / G <= NT;
   if (block && W.crow_blocks != G) {
     CompactPartition cp;
     if ((rc = make_compact_partition(T->dim, T->h_coords.data(), T->n, T->h_rowptr.data(), T->h_col.data(), G,
