@@ -1488,11 +1488,12 @@ struct ChebParams {
   double theta, delta, sigma;   // centre and half width of the interval, theta / delta
 };
 
-// lmax of the workgroup: max over its rows of |d_i| sum_{in-block j} |J_ij|
-// (own rows only; others contribute 0).  Every thread returns the same value.
+// lmax of the workgroup: max over its rows of |d_i| (|J_ii| + sum_{in-block
+// j != i} |J_ij|) (own rows only; others contribute 0).  Every thread
+// returns the same value.
 template <int NT, int K>
-__device__ ChebParams cheb_params(const int (&li)[K], const double (&aa)[K], double d, double* lds) {
-  double g = 0.0;
+__device__ ChebParams cheb_params(const int (&li)[K], const double (&aa)[K], double ad, double d, double* lds) {
+  double g = fabs(ad);
 #pragma unroll
   for (int k = 0; k < K; ++k) g += (li[k] < NT) ? fabs(aa[k]) : 0.0;
   g *= fabs(d);
@@ -1515,13 +1516,17 @@ __device__ ChebParams cheb_params(const int (&li)[K], const double (&aa)[K], dou
 }
 
 // z[v] = M_b^-1 x[v] for NV vectors at once (this thread's row values).  lds
-// holds two buffers of 2 (NT + 1) doubles; entry NT of each vector is 0 and
-// serves columns outside the block (li[k] = NT).  Called by every thread of
-// the workgroup.
+// holds two buffers of 2 (NT + 1) doubles; entry NT of each vector is 0.
+// li[k] is the part-local position of an in-block off-diagonal entry, NT for
+// every other entry (outside the block, the diagonal, past the row's end),
+// so the K loads of a step carry no per-entry branch and are in flight
+// together; ad is the row's diagonal entry.  Threads without a row (has_row
+// false; whole waves at the end of a part) skip the loads.  Called by every
+// thread of the workgroup.
 template <int NT, int K, int NV>
-__device__ __forceinline__ void block_cheb(const int (&li)[K], const double (&aa)[K], double d, int steps,
-                                           const ChebParams& c, double* lds, const double (&x)[NV],
-                                           double (&z)[NV]) {
+__device__ __forceinline__ void block_cheb(const int (&li)[K], const double (&aa)[K], double ad, double d,
+                                           bool has_row, int steps, const ChebParams& c, double* lds,
+                                           const double (&x)[NV], double (&z)[NV]) {
   const int tid = threadIdx.x;
   double r[NV], dd[NV];
 #pragma unroll
@@ -1537,12 +1542,14 @@ __device__ __forceinline__ void block_cheb(const int (&li)[K], const double (&aa
 #pragma unroll
     for (int v = 0; v < NV; ++v) buf[v * (NT + 1) + tid] = dd[v];
     __syncthreads();
+    if (has_row) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      double acc = 0.0;
+      for (int v = 0; v < NV; ++v) {
+        double acc = ad * dd[v];
 #pragma unroll
-      for (int e = 0; e < K; ++e) acc = fma(aa[e], buf[v * (NT + 1) + li[e]], acc);
-      r[v] -= acc;
+        for (int e = 0; e < K; ++e) acc = fma(aa[e], buf[v * (NT + 1) + li[e]], acc);
+        r[v] -= acc;
+      }
     }
     const double rho = 1.0 / (2.0 * c.sigma - rho_old);
     const double c1 = rho * rho_old, c2 = 2.0 * rho / c.delta;
@@ -1577,11 +1584,13 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
     cc[k] = (unsigned)A.col[vi[k]] * 8u;
     li[k] = NT;
   }
+  double ad = 0.0;   // diagonal entry (block-Jacobi)
   if (bj) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int l = A.kloc[vi[k]];
-      li[k] = l >= 0 ? l : NT;
+      const bool offd = own && beg + k < end && (int)(cc[k] / 8u) != row;
+      li[k] = (offd && l >= 0) ? l : NT;
     }
   }
   if (A.perm) {
@@ -1597,7 +1606,10 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
   const double b = A.rhs_scale * A.rhs[row];
   ChebParams cp{1.0, 1.0, 1.0};
   if (bj) {
-    cp = cheb_params<NT, K>(li, aa, d, cheb_lds);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (own && beg + k < end && (int)(cc[k] / 8u) == row) ad = aa[k];
+    cp = cheb_params<NT, K>(li, aa, ad, d, cheb_lds);
     if (threadIdx.x < 4) cheb_lds[(threadIdx.x >> 1) * 2 * (NT + 1) + (threadIdx.x & 1) * (NT + 1) + NT] = 0.0;
   }
   // M^-1 of this thread's row values: D^-1 or the block-Jacobi operator
@@ -1605,7 +1617,7 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
     if (!bj) return d * x1;
     const double xs[1] = {x1};
     double zs[1];
-    block_cheb<NT, K, 1>(li, aa, d, A.cheb_steps, cp, cheb_lds, xs, zs);
+    block_cheb<NT, K, 1>(li, aa, ad, d, own, A.cheb_steps, cp, cheb_lds, xs, zs);
     return zs[0];
   };
   // ---- r = b - J x ; rhat = p = r ; publish M^-1 r --------------------------
@@ -1716,7 +1728,7 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
     if (bj) {
       const double xs[2] = {p, r};
       double zs[2];
-      block_cheb<NT, K, 2>(li, aa, d, A.cheb_steps, cp, cheb_lds, xs, zs);
+      block_cheb<NT, K, 2>(li, aa, ad, d, own, A.cheb_steps, cp, cheb_lds, xs, zs);
       ph = zs[0];
       rhh = zs[1];
     } else {
@@ -1771,11 +1783,13 @@ __device__ KOut team_pcg_reg(Team& tm, const KArgs& A, int rb, int re, double* s
     cc[k] = (unsigned)A.col[vi[k]] * 8u;
     li[k] = NT;
   }
+  double ad = 0.0;   // diagonal entry (block-Jacobi)
   if (bj) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int l = A.kloc[vi[k]];
-      li[k] = l >= 0 ? l : NT;
+      const bool offd = own && beg + k < end && (int)(cc[k] / 8u) != row;
+      li[k] = (offd && l >= 0) ? l : NT;
     }
   }
 #pragma unroll
@@ -1787,7 +1801,10 @@ __device__ KOut team_pcg_reg(Team& tm, const KArgs& A, int rb, int re, double* s
   const double b = A.rhs_scale * A.rhs[row];
   ChebParams cp{1.0, 1.0, 1.0};
   if (bj) {
-    cp = cheb_params<NT, K>(li, aa, d, cheb_lds);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (own && beg + k < end && (int)(cc[k] / 8u) == row) ad = aa[k];
+    cp = cheb_params<NT, K>(li, aa, ad, d, cheb_lds);
     if (threadIdx.x < 4) cheb_lds[(threadIdx.x >> 1) * 2 * (NT + 1) + (threadIdx.x & 1) * (NT + 1) + NT] = 0.0;
   }
   // M^-1 of this thread's row value: D^-1 or the block-Jacobi operator (SPD
@@ -1796,7 +1813,7 @@ __device__ KOut team_pcg_reg(Team& tm, const KArgs& A, int rb, int re, double* s
     if (!bj) return d * x1;
     const double xs[1] = {x1};
     double zs[1];
-    block_cheb<NT, K, 1>(li, aa, d, A.cheb_steps, cp, cheb_lds, xs, zs);
+    block_cheb<NT, K, 1>(li, aa, ad, d, own, A.cheb_steps, cp, cheb_lds, xs, zs);
     return zs[0];
   };
   double x = 0.0, r = b;
