@@ -26,7 +26,8 @@
  *     DF = [K] + T . a + (T ._2 u) diag(a'(u)),   a'(u) = 2u,
  *
  * emitted into the fixed CSR pattern of the P1 node adjacency (diagonal
- * included) and solved with Jacobi-preconditioned BiCGStab.
+ * included) and solved with preconditioned BiCGStab (block-Jacobi on compact
+ * row parts, or Jacobi: the launch shape's krylov_precond).
  *
  * Conventions for every entry point below
  *  - Vectors are float64 and contiguous.  Pointers documented as "device" are
@@ -331,7 +332,7 @@ void egfem_newton_opts_default(egfem_newton_opts* o);
 int egfem_newton(egfem_tensor_t T, const egfem_problem* p, double* u,
                  const egfem_newton_opts* o, egfem_newton_stats* s, void* stream);
 
-/* egfem_solve: Jacobi-preconditioned BiCGStab for A x = rhs, A = J (jval in
+/* egfem_solve: preconditioned BiCGStab (krylov_precond) for A x = rhs, A = J (jval in
  * T's pattern) or J^T (transpose != 0).  x: device, initial guess on input.
  * Stops when ||rhs - A x||_2 <= rtol ||rhs||_2 (recursive residual) or after
  * max_iter iterations.  iters / relres (host, nullable) receive the outcome.
@@ -347,7 +348,7 @@ int egfem_solve(egfem_tensor_t T, const double* jval, int transpose, const doubl
  * is solved for the new iterate; Dirichlet rows are identity rows with zero
  * right-hand side.  The matrix is the A-stream emission of egfem_jacobian
  * without the a' term; it is symmetric positive definite on the free rows,
- * so the linear solves are Jacobi-preconditioned conjugate gradients
+ * so the linear solves are preconditioned conjugate gradients (krylov_precond)
  * (single-reduction arrangement, one persistent cooperative launch), warm
  * started from u^n.
  * ---------------------------------------------------------------------- */
@@ -388,7 +389,7 @@ void egfem_picard_opts_default(egfem_picard_opts* o);
 int egfem_picard(egfem_tensor_t T, const egfem_problem* p, double* u, const egfem_picard_opts* o,
                  egfem_picard_stats* s, void* stream);
 
-/* egfem_solve_cg: Jacobi-preconditioned conjugate gradients for A x = rhs with
+/* egfem_solve_cg: preconditioned conjugate gradients (krylov_precond) for A x = rhs with
  * A (jval, T's pattern) symmetric positive definite, e.g. the matrix of a
  * Picard step.  x: device, initial guess on input, solution on output.  Stops
  * when ||rhs - A x||_2 <= rtol ||rhs||_2 (recursive residual) or after max_iter
@@ -415,7 +416,7 @@ int egfem_solve_cg(egfem_tensor_t T, const double* jval, const double* rhs, doub
  * values at t_{n+1} (load M s^{n+1}), Dirichlet rows identity with zero right-
  * hand side.  The matrix is constant and symmetric positive definite: it is
  * emitted once, and every step is one tensor action (or one N^f product fused
- * into the right-hand side) plus one persistent Jacobi-CG launch started from
+ * into the right-hand side) plus one persistent preconditioned CG launch started from
  * an extrapolation of the previous iterates (opts.guess).
  * ---------------------------------------------------------------------- */
 typedef struct {
@@ -472,7 +473,7 @@ int egfem_burgers(egfem_tensor_t T, const uint8_t* dirichlet, const double* sour
  * zero right-hand side.  p-Laplace: c0 = eps^2, c1 = 1, q = (p-2)/2; minimal
  * surface: c0 = c1 = 1, q = -1/2.  Each step: one cell kernel for a^n, the
  * emission of T . a^n (the A stream with the coefficient gathered per W-slot)
- * and one persistent Jacobi-CG launch warm started from u^n.
+ * and one persistent preconditioned CG launch warm started from u^n.
  * ---------------------------------------------------------------------- */
 typedef struct {
   double c0, c1, q;          /* a(z) = (c0 + c1 |z|^2)^q; c0, c1 >= 0 */
@@ -497,7 +498,7 @@ int egfem_picard_grad(egfem_tensor_t T, const egfem_problem* p, const egfem_grad
  *     DF = T . a(grad u) + sum_e (K^e u_e) (x) (d a_e / d u),
  *     d a_e / d u_j = 2 q c1 (c0 + c1 |z_e|^2)^(q-1) z_e . grad lambda_j,
  * is symmetric; it is emitted by the W-slot stage with per-cell weights and
- * solved by Jacobi-CG (BiCGStab if CG meets a non-positive curvature).  With
+ * solved by preconditioned CG (BiCGStab if CG meets a non-positive curvature).  With
  * g->start_linear, u is first replaced by the Laplace solution (a = 1, CG to
  * 1e-12), the start from which s->res0 is measured.  Returns the status
  * (EGFEM_STAGNATED as for egfem_newton) or EGFEM_ERR_ARG.  Synchronises. */
@@ -562,7 +563,7 @@ int egfem_autotune(egfem_tensor_t T, const egfem_problem* p, int what, egfem_lau
  *   dJ/da0  = -(T ._2 u*)^T lambda, i.e. -sum_ij lambda_i T_ijk u*_j.
  * Only u* is needed (no Newton trajectory is stored).  The transposed
  * Jacobian is applied through the slot transpose permutation; the solve is the
- * same Jacobi-BiCGStab with opts->krylov_rtol / max_krylov.
+ * same preconditioned BiCGStab with opts->krylov_rtol / max_krylov.
  *   u, ubar:      device [n_nodes] inputs
  *   lambda:       device [n_nodes] output (also dJ/dd)
  *   grad_a0:      device [n_nodes] output or NULL

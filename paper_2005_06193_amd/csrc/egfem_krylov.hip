@@ -1,26 +1,31 @@
-// Jacobi-preconditioned BiCGStab as ONE persistent cooperative launch.
+// Preconditioned BiCGStab and CG, each as ONE persistent cooperative launch.
 //
 // The linear solve of each Newton step (Sec. 4; the paper used a direct
-// solve, this path uses the preconditioned BiCGStab of van der Vorst with the
-// Jacobi preconditioner D = diag(J), because J = [K] + T.a + (T._2 u) diag(2u)
-// is non-symmetric).  Every workgroup owns a contiguous, slot-balanced range of
-// rows; all vector work is row-local.  Cross-workgroup traffic is limited to
-// the vectors that matrix-vector products gather (written and read with
-// agent-coherent loads/stores, so the read-only matrix stays cached in L2) and
-// FP64 partial sums.  Three grid barriers per iteration, each completing one
-// reduction: workgroups publish partial sums, and after the barrier every
-// workgroup adds all partials in the same fixed order, so all take identical
-// decisions and the result is bitwise reproducible for a fixed grid.
+// solve, this path uses the preconditioned BiCGStab of van der Vorst, because
+// J = [K] + T.a + (T._2 u) diag(2u) is non-symmetric; the Picard and Burgers
+// matrices are SPD and take CG).  Every workgroup owns a set of rows: a
+// contiguous, slot-balanced range, or, for the register-resident kernels with
+// the block-Jacobi preconditioner, one part of a recursive coordinate
+// bisection (a compact patch of the mesh).  All vector work is row-local.
+// Cross-workgroup traffic is limited to the vectors that matrix-vector
+// products gather (written and read with agent-coherent loads/stores, so the
+// read-only matrix stays cached in L2) and FP64 partial sums.  Reductions
+// complete at grid barriers: workgroups publish partial sums, and after the
+// barrier every workgroup adds all partials in the same fixed order, so all
+// take identical decisions and the result is bitwise reproducible for a
+// fixed grid.
 //
-// The second product t = J D^-1 s is formed as z - alpha y with z = J D^-1 r
-// (fused with v = J D^-1 p in one pass over J) and y = J D^-1 v, which removes
-// the barrier that would publish D^-1 s:
+// With M the preconditioner (D = diag(J), or the workgroup-local block-Jacobi
+// operator, which needs no communication between workgroups), the second
+// product t = J M^-1 s is formed as z - alpha y with z = J M^-1 r (fused with
+// v = J M^-1 p in one pass over J) and y = J M^-1 v, which removes the barrier
+// that would publish M^-1 s:
 //   A: v = J phat, z = J rhat_r      -> (rhat, v)                    barrier 1
 //   B: alpha = rho/(rhat,v); y = J vhat; s = r - alpha v; t = z - alpha y
 //                                    -> (t,s) (t,t) (rhat,s) (rhat,t) (s,s)  barrier 2
-//   C: omega = (t,s)/(t,t); x += alpha phat + omega D^-1 s; r = s - omega t;
+//   C: omega = (t,s)/(t,t); x += alpha phat + omega M^-1 s; r = s - omega t;
 //      rho' = (rhat,s) - omega (rhat,t); beta = rho'/rho * alpha/omega;
-//      p = r + beta (p - omega v); phat = D^-1 p; rhat_r = D^-1 r -> (r,r)   barrier 3
+//      p = r + beta (p - omega v); phat = M^-1 p; rhat_r = M^-1 r -> (r,r)   barrier 3
 #include <algorithm>
 #include <map>
 #include <mutex>
