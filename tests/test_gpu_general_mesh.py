@@ -84,3 +84,30 @@ def test_wheel_batched_with_grid_instances():
         assert s.status in (0, 4), (w.name, s.status_name)
         un, _ = O.newton(O.build_problem(w), tol=1e-14)
         assert relerr(host(u), un) <= 1e-10, w.name
+
+
+def test_wheel_neighbour_list_overflow_takes_team_barrier():
+    """64 workgroups on a wheel with 150 rim nodes (some workgroups get no rows):
+    the hub's workgroup gathers from 33 others, more than a neighbour list
+    holds, so every workgroup
+    synchronises through the team barrier (a mix of the two kinds of wait would
+    never complete).  BiCGStab and CG against SuperLU, deterministic."""
+    wl = wheel(150, seed=5)
+    T = eg().Tensor.build(wl.mesh.coords, wl.mesh.cells, wl.form)
+    p = device(T, wl)
+    po = O.build_problem(wl)
+    ur = np.random.default_rng(6).uniform(-1, 1, T.n)
+    ur[po.dirichlet] = 0.0
+    rhs = np.random.default_rng(7).uniform(-1, 1, T.n)
+    jv = T.problem_jacobian(p, dt(ur))
+    A = O.picard_matrix(po, ur)
+    ja = T.jacobian(dt(ur), dt(po.a0 + ur * ur), None, False, dt(wl.mesh.dirichlet, torch.uint8))
+    for threads in (256, 1024):
+        print(f"wheel 150 overflow grid=64x{threads}", flush=True)
+        T.set_shape(krylov_blocks=64, krylov_threads=threads)
+        x, rc, its, rr = T.solve(jv, dt(rhs), rtol=1e-13)
+        assert rc == 0 and relerr(host(x), spla.spsolve(O.jacobian(po, ur).tocsc(), rhs)) < 1e-9
+        x2, _, its2, _ = T.solve(jv, dt(rhs), rtol=1e-13)
+        assert its2 == its and torch.equal(x, x2)
+        x, rc, its, rr = T.solve_cg(ja, dt(rhs), rtol=1e-13)
+        assert rc == 0 and relerr(host(x), spla.spsolve(A.tocsc(), rhs)) < 1e-10

@@ -239,9 +239,10 @@ BJ_MESHES = {
 def test_bicgstab_block_preconditioner(mesh, transpose, precond):
     """BiCGStab with the block-Jacobi preconditioner (k Chebyshev steps on each
     workgroup's block of a coordinate-bisection partition) against SuperLU on
-    a nonsymmetric Newton Jacobian, for several grids (one of them with more
-    neighbours per part than the point-to-point lists hold, so every workgroup
-    takes the team barrier); fewer iterations than Jacobi."""
+    a nonsymmetric Newton Jacobian, for several grids and workgroup sizes;
+    deterministic; fewer iterations than Jacobi.  (The uniform fallback to the
+    team barrier when a part has too many neighbours runs in the wheel-mesh
+    tests, whose hub row couples to every part.)"""
     m = BJ_MESHES[mesh]()
     rng = np.random.default_rng(12)
     wl = W.Workload("t", m, rng.uniform(0, 10, m.n_nodes), 0, None, 1.0, False, 1e-12, 0)
