@@ -280,6 +280,84 @@ def test_bicgstab_block_preconditioner(mesh, transpose, precond):
         assert iters[(0, precond)] < iters[(0, 0)]
 
 
+COARSE_REMOVED = "coarse correction removed: not faster than block-Jacobi alone (~480 us setup per solve), and its first parity case (1D, 2 parts, 1024-thread workgroups) faulted the GPU with the cause not found"
+
+
+@pytest.mark.skip(reason=COARSE_REMOVED)
+@pytest.mark.parametrize("transpose", [False, True])
+@pytest.mark.parametrize("mesh", list(BJ_MESHES))
+def test_bicgstab_coarse_correction(mesh, transpose):
+    """BiCGStab with the two-level preconditioner (block-Jacobi plus a coarse
+    correction with one unknown per part, A_c = R^T J R inverted in every
+    workgroup's LDS) against SuperLU, on grids of up to 128 parts;
+    deterministic; fewer iterations than the block part alone."""
+    m = BJ_MESHES[mesh]()
+    rng = np.random.default_rng(16)
+    wl = W.Workload("t", m, rng.uniform(0, 10, m.n_nodes), 0, None, 1.0, False, 1e-12, 0)
+    T = eg().Tensor.from_mesh(m, 0)
+    p = gpu_problem(T, wl)
+    po = O.build_problem(wl)
+    u = rng.uniform(0, 1, T.n)
+    u[po.dirichlet] = 0
+    jv = T.problem_jacobian(p, dt(u))
+    A = (O.jacobian(po, u).T if transpose else O.jacobian(po, u)).tocsc()
+    rhs = rng.uniform(-1, 1, T.n)
+    xo = spla.spsolve(A, rhs)
+    cond = np.linalg.cond(A.toarray())
+    iters = {}
+    for blocks, threads in ((0, 0), (7, 1024), (33, 512), (64, 256), (128, 1024)):
+        if blocks and (T.n + blocks - 1) // blocks > threads:
+            continue
+        for coarse in (0, 1):
+            print(f"bicgstab coarse={coarse} mesh={mesh} transpose={transpose} grid={blocks}x{threads}", flush=True)
+            T.set_shape(krylov_precond=8, krylov_coarse=coarse, krylov_blocks=blocks, krylov_threads=threads)
+            x, rc, its, rr = T.solve(jv, dt(rhs), transpose=transpose, rtol=1e-12)
+            assert rc == 0, (rc, its, rr)
+            res = relerr(A @ host(x), rhs)
+            assert res < max(5e-12, 2e-16 * cond)
+            assert relerr(host(x), xo) < cond * max(res, 1e-12) * 10
+            iters[(blocks, coarse)] = its
+            x2, _, its2, _ = T.solve(jv, dt(rhs), transpose=transpose, rtol=1e-12)
+            assert its2 == its and torch.equal(x, x2)
+    # the coarse space pays on the 2D grid; on the small disk (27 parts of ~60
+    # rows) the block part alone already needs few iterations
+    if mesh == "2d_jitter_n45":
+        assert iters[(0, 1)] < iters[(0, 0)]
+
+
+@pytest.mark.skip(reason=COARSE_REMOVED)
+def test_newton_coarse_correction_stats():
+    """Newton with the coarse correction: the oracle's solution, statistics
+    bit 3 set, and 2D-256 at 128 parts fewer BiCGStab iterations than the
+    block part alone."""
+    wl = W.nonlinear_diffusion_2d(40, seed=78)
+    T = eg().Tensor.from_mesh(wl.mesh, wl.form)
+    T.set_shape(krylov_coarse=1)
+    p = gpu_problem(T, wl)
+    u = torch.zeros(T.n, dtype=torch.float64, device=DEV)
+    st = T.newton(p, u, _tight(), warn=False)
+    assert st.status in (0, 4), st.status_name
+    assert st.krylov_kernels == 13
+    uo, _ = O.newton(O.build_problem(wl), tol=1e-14, max_iter=30)
+    assert relerr(host(u), uo) <= 1e-10
+    wl = W.nonlinear_diffusion_2d(256)
+    T = eg().Tensor.from_mesh(wl.mesh, wl.form)
+    p = gpu_problem(T, wl)
+    its = {}
+    sols = {}
+    for coarse in (0, 1):
+        print(f"newton 2d_256 coarse={coarse} grid=128x1024", flush=True)
+        T.set_shape(krylov_coarse=coarse, krylov_blocks=128, krylov_threads=1024)
+        u = torch.zeros(T.n, dtype=torch.float64, device=DEV)
+        st = T.newton(p, u, eg().NewtonOptions(tol=1e-10, forcing=1), warn=False)
+        assert st.status == 0, st.status_name
+        assert st.krylov_kernels == (13 if coarse else 5)
+        its[coarse] = st.krylov_iters
+        sols[coarse] = host(u)
+    assert its[1] < its[0]
+    assert relerr(sols[1], sols[0]) < 1e-8
+
+
 @pytest.mark.parametrize("precond", [0, 8, 32])
 @pytest.mark.parametrize("mesh", list(BJ_MESHES))
 def test_cg_block_preconditioner(mesh, precond):
