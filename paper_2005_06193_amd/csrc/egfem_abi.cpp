@@ -73,6 +73,7 @@ static void free_workspace(Workspace& W) {
   if (W.ckloc) hipFree(W.ckloc);
   if (W.host_partial) hipHostFree(W.host_partial);
   if (W.host_kout) hipHostFree(W.host_kout);
+  for (hipEvent_t e : W.timer_events) hipEventDestroy(e);
   W = Workspace();
 }
 
@@ -95,35 +96,62 @@ static int read_norm(egfem_tensor_s* T, hipStream_t st, double* norm) {
   return EGFEM_OK;
 }
 
-// Launch-duration accounting with a pair of HIP events on the caller's stream.
+// Launch-duration accounting with HIP events on the caller's stream: every
+// start/stop pair records two events; the durations are read once, at
+// finish(), after the last event completes, so timing adds no host
+// synchronisation inside a solve.
 struct LaunchTimer {
+  struct Pending {
+    hipEvent_t a, b;
+    double* acc;
+    int* cnt;
+  };
   bool on = false;
   hipStream_t st = nullptr;
-  hipEvent_t a = nullptr, b = nullptr;
-  int init(bool enable, hipStream_t s) {
+  std::vector<hipEvent_t>* pool = nullptr;   // the handle's events, reused from call to call
+  size_t used = 0;
+  std::vector<Pending> pending;
+  hipEvent_t cur = nullptr;
+  int init(bool enable, hipStream_t s, std::vector<hipEvent_t>* events) {
     on = enable;
     st = s;
-    if (!on) return EGFEM_OK;
-    EGFEM_HIP_CHECK(hipEventCreate(&a));
-    EGFEM_HIP_CHECK(hipEventCreate(&b));
+    pool = events;
     return EGFEM_OK;
   }
-  ~LaunchTimer() {
-    if (a) hipEventDestroy(a);
-    if (b) hipEventDestroy(b);
+  int record(hipEvent_t* e) {
+    if (used == pool->size()) {
+      hipEvent_t ne = nullptr;
+      EGFEM_HIP_CHECK(hipEventCreate(&ne));
+      pool->push_back(ne);
+    }
+    *e = (*pool)[used++];
+    EGFEM_HIP_CHECK(hipEventRecord(*e, st));
+    return EGFEM_OK;
   }
   int start() {
-    if (on) EGFEM_HIP_CHECK(hipEventRecord(a, st));
-    return EGFEM_OK;
+    if (!on) return EGFEM_OK;
+    return record(&cur);
   }
   int stop(double* acc, int* cnt) {
     if (!on) return EGFEM_OK;
-    EGFEM_HIP_CHECK(hipEventRecord(b, st));
-    EGFEM_HIP_CHECK(hipEventSynchronize(b));
-    float ms = 0.0f;
-    EGFEM_HIP_CHECK(hipEventElapsedTime(&ms, a, b));
-    *acc += ms;
-    ++*cnt;
+    hipEvent_t b = nullptr;
+    const int rc = record(&b);
+    if (rc != EGFEM_OK) return rc;
+    pending.push_back({cur, b, acc, cnt});
+    return EGFEM_OK;
+  }
+  // Add the recorded durations to their accumulators.
+  int finish() {
+    if (!on || pending.empty()) return EGFEM_OK;
+    EGFEM_HIP_CHECK(hipEventSynchronize(pending.back().b));
+    for (const Pending& q : pending) {
+      float ms = 0.0f;
+      EGFEM_HIP_CHECK(hipEventElapsedTime(&ms, q.a, q.b));
+      *q.acc += ms;
+      ++*q.cnt;
+    }
+    pending.clear();
+    used = 0;
     return EGFEM_OK;
   }
 };
@@ -360,7 +388,7 @@ int egfem_newton(egfem_tensor_t T, const egfem_problem* p, double* u, const egfe
   std::memset(&stats, 0, sizeof(stats));
 
   LaunchTimer tm;
-  if ((rc = tm.init(opts.timing != 0, st)) != EGFEM_OK) return rc;
+  if ((rc = tm.init(opts.timing != 0, st, &T->ws.timer_events)) != EGFEM_OK) return rc;
 #define EGFEM_TRY(x)                    \
   do {                                  \
     if ((rc = (x)) != EGFEM_OK) return rc; \
@@ -436,6 +464,7 @@ int egfem_newton(egfem_tensor_t T, const egfem_problem* p, double* u, const egfe
   stats.status = status;
   stats.newton_iters = k;
   stats.res = nF;
+  if ((rc = tm.finish()) != EGFEM_OK) return rc;
   if (s) *s = stats;
   return status;
 }
@@ -511,7 +540,7 @@ int egfem_picard(egfem_tensor_t T, const egfem_problem* p, double* u, const egfe
   egfem_picard_stats stats;
   std::memset(&stats, 0, sizeof(stats));
   LaunchTimer tm;
-  if ((rc = tm.init(opts.timing != 0, st)) != EGFEM_OK) return rc;
+  if ((rc = tm.init(opts.timing != 0, st, &T->ws.timer_events)) != EGFEM_OK) return rc;
   int n_dummy = 0;
 #define EGFEM_TRY(x)                    \
   do {                                  \
@@ -567,6 +596,7 @@ int egfem_picard(egfem_tensor_t T, const egfem_problem* p, double* u, const egfe
   if ((rc = read_norm(T, st, &stats.res)) != EGFEM_OK) return rc;
   stats.status = status;
   stats.picard_iters = k;
+  if ((rc = tm.finish()) != EGFEM_OK) return rc;
   if (s) *s = stats;
   return status;
 }
@@ -612,7 +642,7 @@ int egfem_burgers(egfem_tensor_t T, const uint8_t* dirichlet, const double* sour
   egfem_burgers_stats stats;
   std::memset(&stats, 0, sizeof(stats));
   LaunchTimer tm;
-  if ((rc = tm.init(opts.timing != 0, st)) != EGFEM_OK) return rc;
+  if ((rc = tm.init(opts.timing != 0, st, &T->ws.timer_events)) != EGFEM_OK) return rc;
   int n_dummy = 0;
   // offline part of the run: M + dt nu K (Dirichlet identity rows, zero
   // columns) and its inverse diagonal; N^f = N contracted with 1 in j
@@ -662,6 +692,7 @@ int egfem_burgers(egfem_tensor_t T, const uint8_t* dirichlet, const double* sour
   EGFEM_HIP_CHECK(hipStreamSynchronize(st));
   stats.status = status;
   stats.steps = n;
+  if ((rc = tm.finish()) != EGFEM_OK) return rc;
   if (s) *s = stats;
   return status;
 }
@@ -688,7 +719,7 @@ int egfem_picard_grad(egfem_tensor_t T, const egfem_problem* p, const egfem_grad
   egfem_picard_stats stats;
   std::memset(&stats, 0, sizeof(stats));
   LaunchTimer tm;
-  if ((rc = tm.init(opts.timing != 0, st)) != EGFEM_OK) return rc;
+  if ((rc = tm.init(opts.timing != 0, st, &T->ws.timer_events)) != EGFEM_OK) return rc;
   int n_dummy = 0;
   double* a = T->e_acoef;
   std::vector<double> part(512);
@@ -753,6 +784,7 @@ int egfem_picard_grad(egfem_tensor_t T, const egfem_problem* p, const egfem_grad
   stats.res0 = 0.0;
   stats.status = status;
   stats.picard_iters = k;
+  if ((rc = tm.finish()) != EGFEM_OK) return rc;
   if (s) *s = stats;
   return status;
 }
@@ -776,7 +808,7 @@ int egfem_newton_grad(egfem_tensor_t T, const egfem_problem* p, const egfem_grad
   egfem_newton_stats stats;
   std::memset(&stats, 0, sizeof(stats));
   LaunchTimer tm;
-  if ((rc = tm.init(opts.timing != 0, st)) != EGFEM_OK) return rc;
+  if ((rc = tm.init(opts.timing != 0, st, &T->ws.timer_events)) != EGFEM_OK) return rc;
   double* a = T->e_acoef;
   double* wv = T->e_wv;
   std::vector<double> part(256);
@@ -875,6 +907,7 @@ int egfem_newton_grad(egfem_tensor_t T, const egfem_problem* p, const egfem_grad
   stats.status = status;
   stats.newton_iters = k;
   stats.res = nF;
+  if ((rc = tm.finish()) != EGFEM_OK) return rc;
   if (s) *s = stats;
   return status;
 }

@@ -85,6 +85,7 @@ struct Workspace {
   double* kout = nullptr;       // Krylov result [4] (device)
   double* host_partial = nullptr;  // pinned host mirror of partial sums
   double* host_kout = nullptr;     // pinned host mirror of the Krylov result
+  std::vector<hipEvent_t> timer_events;   // events of the drivers' launch timing (reused)
 };
 
 }  // namespace egfem
