@@ -652,7 +652,7 @@ def main():
                     help="also run a plain 256 MiB device copy (scale reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (the build targets a single MI355X); "
+        print(f"bench.py measures one GPU only (one MI355X; sharding is not implemented); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
 
