@@ -54,6 +54,14 @@ int fail(int code, const std::string& msg);
                                               hipGetErrorString(e_));                \
   } while (0)
 
+// A Krylov launch whose outcome has not been read yet.
+struct KrylovPending {
+  bool active = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;   // launch timing (timed solves)
+  int G = 0, NT = 0;
+  bool resident = false, block = false;
+};
+
 // Solver workspace owned by a handle (allocated on first use).
 struct Workspace {
   bool ready = false;
@@ -86,6 +94,7 @@ struct Workspace {
   double* host_partial = nullptr;  // pinned host mirror of partial sums
   double* host_kout = nullptr;     // pinned host mirror of the Krylov result
   std::vector<hipEvent_t> timer_events;   // events of the drivers' launch timing (reused)
+  KrylovPending kpend;                    // the Krylov launch in flight (deferred collection)
 };
 
 }  // namespace egfem
@@ -282,19 +291,23 @@ struct KrylovResult {
 };
 enum class KrylovMethod { kBiCGStab, kCG };
 
-// Persistent Jacobi-preconditioned Krylov solve of (rhs_scale * rhs) = A x,
+// Persistent preconditioned Krylov solve of (rhs_scale * rhs) = A x,
 // A = J (perm == null) or J^T (perm = tperm); conjugate gradients need an SPD
-// J.  Stops when ||r|| <= rtol ||b|| (or rtol ||r0|| with rel_r0).
+// J.  Stops when ||r|| <= rtol ||b|| (or rtol ||r0|| with rel_r0).  With
+// defer, the call returns once the launch and the copy of its outcome are
+// enqueued; krylov_collect synchronises the stream and fills res (one solve
+// in flight per handle).
 int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, const double* dinv,
                  const double* rhs, double rhs_scale, double* x, bool x_zero, double rtol, bool rel_r0,
                  int max_iter, int blocks, KrylovResult* res, hipStream_t st, const int32_t* perm,
-                 bool timed = false, int threads = 0);
+                 bool timed = false, int threads = 0, bool defer = false);
+int krylov_collect(egfem_tensor_s* T, hipStream_t st, KrylovResult* res);
 inline int krylov_bicgstab(egfem_tensor_s* T, const double* jval, const double* dinv, const double* rhs,
                            double rhs_scale, double* x, bool x_zero, double rtol, int max_iter, int blocks,
                            KrylovResult* res, hipStream_t st, const int32_t* perm, bool timed = false,
-                           int threads = 0) {
+                           int threads = 0, bool defer = false) {
   return krylov_solve(KrylovMethod::kBiCGStab, T, jval, dinv, rhs, rhs_scale, x, x_zero, rtol, false, max_iter,
-                      blocks, res, st, perm, timed, threads);
+                      blocks, res, st, perm, timed, threads, defer);
 }
 
 // Workspace

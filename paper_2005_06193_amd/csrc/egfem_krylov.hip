@@ -164,7 +164,7 @@ static void make_partition(const egfem_tensor_s* T, int G, std::vector<int32_t>&
 int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, const double* dinv,
                  const double* rhs, double rhs_scale, double* x, bool x_zero, double rtol, bool rel_r0,
                  int max_iter, int blocks, KrylovResult* res, hipStream_t st, const int32_t* perm, bool timed,
-                 int threads) {
+                 int threads, bool defer) {
   int rc = ensure_workspace(T);
   if (rc != EGFEM_OK) return rc;
   Workspace& W = T->ws;
@@ -284,6 +284,11 @@ int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, con
   P.ctrl = W.ctrl;
   P.red = W.red;
   P.out = W.kout;
+  if (W.kpend.active) {   // an outcome never collected (an earlier call returned early)
+    if (W.kpend.ev0) hipEventDestroy(W.kpend.ev0);
+    if (W.kpend.ev1) hipEventDestroy(W.kpend.ev1);
+    W.kpend = KrylovPending();
+  }
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   if (timed) {
     EGFEM_HIP_CHECK(hipEventCreate(&ev0));
@@ -301,23 +306,41 @@ int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, con
   }
   if (timed) EGFEM_HIP_CHECK(hipEventRecord(ev1, st));
   EGFEM_HIP_CHECK(hipMemcpyAsync(W.host_kout, W.kout, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
-  EGFEM_HIP_CHECK(hipStreamSynchronize(st));
-  if (timed) {
+  KrylovPending& q = W.kpend;
+  q.active = true;
+  q.ev0 = ev0;
+  q.ev1 = ev1;
+  q.G = G;
+  q.NT = NT;
+  q.resident = resident;
+  q.block = block;
+  if (defer) return EGFEM_OK;
+  return krylov_collect(T, st, res);
+}
+
+int krylov_collect(egfem_tensor_s* T, hipStream_t st, KrylovResult* res) {
+  Workspace& W = T->ws;
+  KrylovPending& q = W.kpend;
+  if (!q.active) return fail(EGFEM_ERR_ARG, "no Krylov solve in flight");
+  q.active = false;
+  const hipError_t e = hipStreamSynchronize(st);
+  if (q.ev0) {
     float ms = 0.0f;
-    EGFEM_HIP_CHECK(hipEventElapsedTime(&ms, ev0, ev1));
-    res->kernel_ms = ms;
-    hipEventDestroy(ev0);
-    hipEventDestroy(ev1);
+    if (e == hipSuccess && hipEventElapsedTime(&ms, q.ev0, q.ev1) == hipSuccess) res->kernel_ms = ms;
+    hipEventDestroy(q.ev0);
+    hipEventDestroy(q.ev1);
+    q.ev0 = q.ev1 = nullptr;
   }
+  if (e != hipSuccess) return fail(EGFEM_ERR_HIP, std::string("Krylov solve failed: ") + hipGetErrorString(e));
   const double* o = W.host_kout;
   res->status = (int)o[0];
   res->iters = (int)o[1];
   res->relres = o[2];
   res->bnorm = o[3];
-  res->blocks = G;
-  res->threads = NT;
-  res->resident = resident;
-  res->block_precond = block;
+  res->blocks = q.G;
+  res->threads = q.NT;
+  res->resident = q.resident;
+  res->block_precond = q.block;
   if (res->status == EGFEM_ERR_HIP) return fail(EGFEM_ERR_HIP, "Krylov grid barrier timed out");
   return EGFEM_OK;
 }
