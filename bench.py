@@ -266,6 +266,18 @@ def tensor_action_suite():
                                            "warm_us": uw * 1e3, "cold_us": uc * 1e3,
                                            "cold_GBps": bu / (uc * 1e6),
                                            "cold_speedup_vs_stream": cold / uc}
+            # the same comparison on a 3D mass tensor (Kuhn 32^3)
+            m3 = W.diffusion_3d(32).mesh
+            M3 = eg.Tensor.from_mesh(m3, W.FORM_MASS)
+            nu3 = M3.attach_unique(m3.coords, m3.cells)
+            s3w, s3c = time_action(M3, 100, cold=False), time_action(M3, 20, cold=True)
+            u3w = time_action(M3, 100, cold=False, variant="unique")
+            u3c = time_action(M3, 20, cold=True, variant="unique")
+            out[name]["unique_storage_3d_32_mass"] = {"values": nu3, "stream_entries": M3.info.nnz,
+                                                      "stream_warm_us": s3w * 1e3, "stream_cold_us": s3c * 1e3,
+                                                      "unique_warm_us": u3w * 1e3, "unique_cold_us": u3c * 1e3,
+                                                      "cold_speedup_vs_stream": s3c / u3c}
+            M3.close()
         tr = load_traffic()
         if tr:
             out[name]["action_hbm_bytes_rocprof"] = tr["tensor_action"][name]["hbm_bytes_per_launch"]

@@ -1062,10 +1062,11 @@ extern "C" int egfem_attach_unique(egfem_tensor_t T, int dim, int64_t n_nodes, c
   if (rc == EGFEM_OK) rc = upload(fref, &fr, &bytes);
   T->u_fref = reinterpret_cast<int2*>(fr);
   if (rc != EGFEM_OK) return rc;
-  const int need = std::max(T->max_row_slots, max_faces);
+  // lanes per row from the row's slot count (2D: 4, 3D Kuhn meshes: 8; the
+  // face references are read in several passes)
   const int stride = std::max(T->max_row_slots, 1);
   int lanes = 2;
-  while (2 * lanes < need && lanes < 64) lanes *= 2;
+  while (2 * lanes < stride && lanes < 64) lanes *= 2;
   // the rows of a workgroup stage u and a of their slots in at most 32 KB of LDS
   while ((size_t)(kBlockThreads / lanes) * stride * 16 > 32768 && lanes < 64) lanes *= 2;
   T->u_lanes = lanes;
