@@ -170,6 +170,17 @@ int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, con
   Workspace& W = T->ws;
   if (threads == 0) threads = T->tuned_krylov_threads;
   if (blocks <= 0) blocks = T->tuned_krylov_blocks;
+  if (threads == 0 && blocks <= 0 && T->krylov_kernel == 0 && T->max_row_slots <= kResidentRow &&
+      T->n <= (int64_t)256 * kMaxKrylovBlocks) {
+    // untuned, register-resident: 256-thread workgroups, one row per thread,
+    // as few as that allows (largest block-Jacobi parts); kept only when the
+    // grid is co-resident
+    const int g = (int)((T->n + 255) / 256);
+    if (g <= coresident(kernel_for(256, method, true, 0), 256)) {
+      threads = 256;
+      blocks = g;
+    }
+  }
   const int NT = (threads == 256 || threads == 512 || threads == 1024) ? threads : kKrylovThreads;
   const int cap = coresident(kernel_for(NT, method, false, T->krylov_rs), NT);
   if (cap <= 0) return fail(EGFEM_ERR_HIP, "Krylov kernel cannot be resident");

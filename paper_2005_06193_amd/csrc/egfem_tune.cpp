@@ -137,7 +137,10 @@ int egfem_autotune(egfem_tensor_t T, const egfem_problem* p, int what, egfem_lau
     const int keep_kernel = T->krylov_kernel;
     for (int kernel : {0, 1})
       for (int threads : {256, 512, 1024})
-        for (int blocks : {32, 64, 128, 256, 512, 1024}) {
+        // fixed grids and the smallest grid that keeps one row per thread
+        // (the largest parts of the block-Jacobi preconditioner)
+        for (int blocks : {32, 64, 128, 256, 512, 1024,
+                           (int)std::min<int64_t>((T->n + threads - 1) / threads, kMaxKrylovBlocks)}) {
           T->krylov_kernel = kernel;
           KrylovResult kr;
           rc = krylov_bicgstab(T, W.jval, W.dinv, W.rhs, 1.0, W.delta, true, 1e-8, 3000, blocks, &kr, st,
