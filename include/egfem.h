@@ -289,8 +289,9 @@ typedef struct {
   int forcing;               /* 0: fixed krylov_rtol; 1: Eisenstat-Walker choice 2 */
   double eta_max;            /* EW cap (default 0.1) */
   int max_backtracks;        /* damping halvings (default 10) */
-  int krylov_blocks;         /* persistent Krylov grid size, 0 = automatic */
-  int krylov_threads;        /* persistent Krylov workgroup size: 256, 512 or 1024 (0 = 1024) */
+  int krylov_blocks;         /* persistent Krylov grid size, 0 = the handle's launch shape */
+  int krylov_threads;        /* persistent Krylov workgroup size: 256, 512 or 1024, 0 = the
+                                handle's launch shape */
   int timing;                /* nonzero: time every kernel launch with HIP events on the
                                 stream (fills the t_* / n_* fields of the statistics) */
 } egfem_newton_opts;
@@ -513,8 +514,12 @@ typedef struct {
                                 run of row blocks (0 = one workgroup per row block) */
   int action_pipe;           /* 1: software-pipelined runs (next block's stream loads issued
                                 before the current block's gathers), 0: one block at a time */
-  int krylov_blocks;         /* persistent BiCGStab grid (0 = heuristic) */
-  int krylov_threads;        /* persistent BiCGStab workgroup size 256/512/1024 (0 = 1024) */
+  int krylov_blocks;         /* persistent Krylov grid (0 = default) */
+  int krylov_threads;        /* persistent Krylov workgroup size 256/512/1024 (0 = default).  With
+                                both 0 (an untuned handle): 256-thread workgroups with one row per
+                                thread, ceil(n / 256) of them, where the register-resident kernel
+                                applies and that grid is co-resident; otherwise 1024 threads and
+                                min(ceil(n / 64), compute units) workgroups */
   int krylov_kernel;         /* 0: register-resident BiCGStab (one thread per row) when every
                                 workgroup's rows fit its threads and rows hold at most 8
                                 entries, else the streaming one; 1: always the streaming one */
