@@ -577,19 +577,22 @@ int egfem_picard(egfem_tensor_t T, const egfem_problem* p, double* u, const egfe
     EGFEM_HIP_CHECK(launch_copy(W.delta, u, T->n, st));
     KrylovResult kr;
     rc = krylov_solve(KrylovMethod::kCG, T, W.jval, W.dinv, W.rhs, 1.0, W.delta, false, opts.krylov_rtol,
-                      true, opts.max_krylov, opts.krylov_blocks, &kr, st, nullptr, tm.on, opts.krylov_threads);
+                      true, opts.max_krylov, opts.krylov_blocks, &kr, st, nullptr, tm.on, opts.krylov_threads,
+                      true);
     if (rc != EGFEM_OK) return rc;
-    if (tm.on) stats.t_krylov_ms += kr.kernel_ms;
-    stats.krylov_iters += kr.iters;
-    stats.krylov_kernels |= (kr.resident ? 1 : 2) | (kr.block_precond ? 4 : 0);
-    if (k < EGFEM_HIST) stats.krylov_hist[k] = kr.iters;
-    // relative update, then u <- u^{n+1}
+    // relative update, then u <- u^{n+1}, enqueued behind the solve: one
+    // synchronisation reads the solve's outcome and the update norms
     hipError_t e = hipSuccess;
     const int g = launch_diff_norms(T->n, W.delta, u, W.red, st, &e);
     EGFEM_HIP_CHECK(e);
     EGFEM_HIP_CHECK(hipMemcpyAsync(part.data(), W.red, 2 * g * sizeof(double), hipMemcpyDeviceToHost, st));
     EGFEM_HIP_CHECK(launch_copy(u, W.delta, T->n, st));
     EGFEM_HIP_CHECK(hipStreamSynchronize(st));
+    if ((rc = krylov_collect(T, st, &kr)) != EGFEM_OK) return rc;
+    if (tm.on) stats.t_krylov_ms += kr.kernel_ms;
+    stats.krylov_iters += kr.iters;
+    stats.krylov_kernels |= (kr.resident ? 1 : 2) | (kr.block_precond ? 4 : 0);
+    if (k < EGFEM_HIST) stats.krylov_hist[k] = kr.iters;
     double dd = 0.0, xx = 0.0;
     for (int q = 0; q < g; ++q) {
       dd += part[2 * q];
@@ -767,18 +770,19 @@ int egfem_picard_grad(egfem_tensor_t T, const egfem_problem* p, const egfem_grad
     EGFEM_HIP_CHECK(launch_copy(W.delta, u, T->n, st));
     KrylovResult kr;
     rc = krylov_solve(KrylovMethod::kCG, T, W.jval, W.dinv, W.rhs, 1.0, W.delta, false, opts.krylov_rtol, true,
-                      opts.max_krylov, opts.krylov_blocks, &kr, st, nullptr, tm.on, opts.krylov_threads);
+                      opts.max_krylov, opts.krylov_blocks, &kr, st, nullptr, tm.on, opts.krylov_threads, true);
     if (rc != EGFEM_OK) return rc;
-    if (tm.on) stats.t_krylov_ms += kr.kernel_ms;
-    stats.krylov_iters += kr.iters;
-    stats.krylov_kernels |= (kr.resident ? 1 : 2) | (kr.block_precond ? 4 : 0);
-    if (k < EGFEM_HIST) stats.krylov_hist[k] = kr.iters;
     hipError_t e = hipSuccess;
     const int ng = launch_diff_norms(T->n, W.delta, u, W.red, st, &e);
     EGFEM_HIP_CHECK(e);
     EGFEM_HIP_CHECK(hipMemcpyAsync(part.data(), W.red, 2 * ng * sizeof(double), hipMemcpyDeviceToHost, st));
     EGFEM_HIP_CHECK(launch_copy(u, W.delta, T->n, st));
     EGFEM_HIP_CHECK(hipStreamSynchronize(st));
+    if ((rc = krylov_collect(T, st, &kr)) != EGFEM_OK) return rc;
+    if (tm.on) stats.t_krylov_ms += kr.kernel_ms;
+    stats.krylov_iters += kr.iters;
+    stats.krylov_kernels |= (kr.resident ? 1 : 2) | (kr.block_precond ? 4 : 0);
+    if (k < EGFEM_HIST) stats.krylov_hist[k] = kr.iters;
     double dd = 0.0, xx = 0.0;
     for (int q = 0; q < ng; ++q) {
       dd += part[2 * q];
