@@ -73,6 +73,15 @@ def bytes_krylov(info, iters: int):
     return iters * per_iter + setup
 
 
+def cg_kernel_label(bits: int) -> str:
+    """Krylov kernels named by a driver's statistics bit set (1 register-resident,
+    2 streaming, 4 block-Jacobi preconditioner)."""
+    if not bits & 3:
+        return "none"
+    kind = {1: "register-resident", 2: "streaming", 3: "register-resident and streaming"}[bits & 3]
+    return kind + (", block-jacobi" if bits & 4 else ", jacobi")
+
+
 def kernel_source_sha() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2005_06193_amd", "csrc")
@@ -431,7 +440,7 @@ def picard_suite(T, p, reps: int = 3):
             "picard_iters": st.picard_iters, "cg_iters_per_solve": cg / reps,
             "cg_us_per_iter": 1e3 * tk / max(cg, 1), "matrix_ms_per_solve": sum(x.t_matrix_ms for x in stats) / reps,
             "residual_rel": st.res / st.res0,
-            "cg_kernel": "register-resident" if st.krylov_kernels == 1 else "streaming"}
+            "cg_kernel": cg_kernel_label(st.krylov_kernels)}
 
 
 def wspace_suite(n: int, shape: dict) -> dict:
