@@ -175,3 +175,23 @@ def test_newton_grad_full_size_disk_and_forcing():
     up = torch.zeros(T.n, dtype=torch.float64, device=DEV)
     T.picard_grad(p, up, wl.c0, wl.c1, wl.q)
     assert relerr(ug, host(up)) < 1e-8
+
+
+def test_picard_grad_timing_leaves_the_iteration_unchanged():
+    """With timing on, the gradient-coefficient Picard iteration gives bitwise
+    the untimed iterate and statistics, and reports the CG time."""
+    m = W.mesh_disk(16)
+    T = _p0(m)
+    p = eg().Problem(T.n, _load(T, m, np.ones(m.n_nodes)), dt(m.dirichlet, torch.uint8))
+    runs = []
+    for timing in (0, 1):
+        u = torch.zeros(T.n, dtype=torch.float64, device=DEV)
+        st = T.picard_grad(p, u, 0.0, 1.0, -0.25, opts=eg().PicardOptions(timing=timing), warn=False)
+        assert st.status == 0, st.status_name
+        assert st.picard_iters <= 64 and sum(st.krylov_hist) == st.krylov_iters
+        assert (st.t_krylov_ms > 0.0) == bool(timing)
+        runs.append((u, st))
+    (u0, s0), (u1, s1) = runs
+    assert torch.equal(u0, u1)
+    assert s0.picard_iters == s1.picard_iters and s0.krylov_hist == s1.krylov_hist
+    assert s0.update_hist == s1.update_hist

@@ -132,3 +132,30 @@ def test_picard_edge_cases():
     T.picard(p, u, E.PicardOptions(tol=1e-13), warn=False)
     st = T.picard(p, u, E.PicardOptions(tol=1e-11), warn=False)
     assert st.status == 0 and st.picard_iters == 1
+
+
+@pytest.mark.parametrize("kernel,precond", [(0, 8), (1, 0)])
+def test_picard_timing_leaves_the_iteration_unchanged(kernel, precond):
+    """Each Picard step reads the CG outcome, its timing events and the update
+    norms in one synchronisation: with timing on, the iterate is bitwise the
+    untimed one, the per-step CG counts add up to the total and the CG time is
+    reported."""
+    wl = W.nonlinear_diffusion_2d(40, seed=56)
+    T = eg().Tensor.from_mesh(wl.mesh, wl.form)
+    T.set_shape(krylov_kernel=kernel, krylov_precond=precond)
+    p = gpu_problem(T, wl)
+    runs = []
+    for timing in (0, 1, 0):
+        u = torch.zeros(T.n, dtype=torch.float64, device=DEV)
+        st = T.picard(p, u, eg().PicardOptions(tol=1e-13, timing=timing), warn=False)
+        assert st.status == 0, st.status_name
+        assert st.picard_iters <= 64 and sum(st.krylov_hist) == st.krylov_iters
+        assert (st.t_krylov_ms > 0.0) == bool(timing)
+        runs.append((u, st))
+    (u0, s0), (u1, s1), (u2, s2) = runs
+    assert torch.equal(u0, u1) and torch.equal(u0, u2)
+    assert s0.picard_iters == s1.picard_iters == s2.picard_iters
+    assert s0.krylov_hist == s1.krylov_hist == s2.krylov_hist
+    assert s0.update_hist == s1.update_hist
+    un, _ = O.newton(O.build_problem(wl), tol=1e-14)
+    assert relerr(host(u1), un) <= 1e-10
