@@ -501,8 +501,10 @@ int egfem_picard_grad(egfem_tensor_t T, const egfem_problem* p, const egfem_grad
  * is symmetric; it is emitted by the W-slot stage with per-cell weights and
  * solved by preconditioned CG (BiCGStab if CG meets a non-positive curvature).  With
  * g->start_linear, u is first replaced by the Laplace solution (a = 1, CG to
- * 1e-12), the start from which s->res0 is measured.  Returns the status
- * (EGFEM_STAGNATED as for egfem_newton) or EGFEM_ERR_ARG.  Synchronises. */
+ * 1e-12), the start from which s->res0 is measured; s->krylov_iters then
+ * includes that solve's iterations, which s->krylov_hist (per Newton step)
+ * does not hold.  Returns the status (EGFEM_STAGNATED as for egfem_newton) or
+ * EGFEM_ERR_ARG.  Synchronises. */
 int egfem_newton_grad(egfem_tensor_t T, const egfem_problem* p, const egfem_grad_coef* g, double* u,
                       const egfem_newton_opts* o, egfem_newton_stats* s, void* stream);
 

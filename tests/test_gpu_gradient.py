@@ -195,3 +195,25 @@ def test_picard_grad_timing_leaves_the_iteration_unchanged():
     assert torch.equal(u0, u1)
     assert s0.picard_iters == s1.picard_iters and s0.krylov_hist == s1.krylov_hist
     assert s0.update_hist == s1.update_hist
+
+
+def test_newton_grad_timing_leaves_the_iteration_unchanged():
+    """With timing on, the gradient-coefficient Newton iteration gives bitwise
+    the untimed iterate and statistics, and reports the Krylov time."""
+    m = W.mesh_disk(16)
+    T = _p0(m)
+    p = eg().Problem(T.n, _load(T, m, np.ones(m.n_nodes)), dt(m.dirichlet, torch.uint8))
+    runs = []
+    for timing in (0, 1):
+        u = torch.zeros(T.n, dtype=torch.float64, device=DEV)
+        st = T.newton_grad(p, u, 0.0, 1.0, -0.25, opts=eg().NewtonOptions(tol=1e-10, forcing=1, timing=timing),
+                           warn=False)
+        assert st.status == 0, st.status_name
+        # the total also holds the Laplace start solve, the per-step counts do not
+        assert st.newton_iters <= 64 and sum(st.krylov_hist) < st.krylov_iters
+        assert (st.t_krylov_ms > 0.0) == bool(timing)
+        runs.append((u, st))
+    (u0, s0), (u1, s1) = runs
+    assert torch.equal(u0, u1)
+    assert s0.krylov_hist == s1.krylov_hist and s0.res_hist == s1.res_hist
+    assert s0.krylov_iters == s1.krylov_iters

@@ -622,3 +622,30 @@ def test_newton_full_size_3d_64_certificate():
     # and the GPU's own residual on those rows agrees with the oracle's
     Fg = host(T.problem_residual(p, u))
     assert np.abs(Fg[rows] - F[rows]).max() <= 1e-12 * np.abs(b).max()
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_newton_timing_leaves_the_iteration_unchanged(kernel):
+    """Each Newton step enqueues its trial residual behind the Krylov launch and
+    reads the solve's outcome, timing events and the trial norm in one
+    synchronisation: with timing on, the iterate and the per-step statistics
+    are bitwise the untimed ones, and every stage's time is reported."""
+    wl = W.nonlinear_diffusion_2d(40, seed=57)
+    T = eg().Tensor.from_mesh(wl.mesh, wl.form)
+    T.set_shape(krylov_kernel=kernel)
+    p = gpu_problem(T, wl)
+    runs = []
+    for timing in (0, 1, 0):
+        u = torch.zeros(T.n, dtype=torch.float64, device=DEV)
+        st = T.newton(p, u, eg().NewtonOptions(tol=1e-10, forcing=1, timing=timing))
+        assert st.status == 0, st.status_name
+        assert st.newton_iters <= 64 and sum(st.krylov_hist) == st.krylov_iters
+        assert (st.t_krylov_ms > 0.0) == bool(timing)
+        assert (st.t_action_ms > 0.0 and st.t_jacobian_ms > 0.0) == bool(timing)
+        runs.append((u, st))
+    (u0, s0), (u1, s1), (u2, s2) = runs
+    assert torch.equal(u0, u1) and torch.equal(u0, u2)
+    assert s0.krylov_hist == s1.krylov_hist == s2.krylov_hist
+    assert s0.res_hist == s1.res_hist and s0.backtracks == s1.backtracks
+    un, _ = O.newton(O.build_problem(wl), tol=1e-14)
+    assert relerr(host(u1), un) <= 1e-8
