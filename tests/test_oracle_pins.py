@@ -357,6 +357,56 @@ def test_single_interior_node_1d():
         assert abs(u[1] - ex) <= 1e-14 * max(1.0, abs(ex))
 
 
+def _one_node_problem(fval):
+    m = W.mesh_1d(2)
+    wl = W.Workload("t", m, np.full(3, fval), O.FORM_STIFF, None, 1.0, False, 1e-14, 0)
+    return O.build_problem(wl)
+
+
+def test_newton_damping_one_halving_by_hand():
+    """Damping remark of Sec. 4 on the one free node, F(u) = 4u + 2u^3 - d1.
+    f = -12 gives d1 = -6 (the interior row of M sums to h = 1/2).  From u = 0:
+    F = 6, DF = 4, so the full step is u = -1.5 with F = -6 - 6.75 + 6 = -6.75,
+    |F| > 6: rejected.  The halved step u = -0.75 gives F = -3 - 0.84375 + 6 =
+    2.15625 <= (1 - 0.5e-4) 6: accepted.  The iteration then takes full steps
+    to the root u = -1 (4(-1) + 2(-1)^3 + 6 = 0)."""
+    p = _one_node_problem(-12.0)
+    assert p.d[1] == -6.0
+    u1, st1 = O.newton(p, tol=1e-15, max_iter=1)
+    assert st1.backtracks == 1 and st1.iterations == 1
+    assert u1[1] == -0.75
+    assert st1.residual_norms == [6.0, 2.15625]
+    u, st = O.newton(p, tol=1e-15, max_iter=60)
+    assert st.status == "converged" and st.backtracks == 1
+    assert abs(u[1] + 1.0) <= 1e-15
+    # residual norms fall monotonically after the damped step
+    h = st.residual_norms
+    assert all(b < a for a, b in zip(h[1:], h[2:]) if a > 0)
+
+
+@pytest.mark.parametrize("d_sq,halved", [(31.999, True), (32.0 * (1.0 - 1.5e-4), False)])
+def test_newton_sufficient_decrease_constant(d_sq, halved):
+    """The acceptance test ||F(u + alpha delta)|| <= (1 - 1e-4 alpha) ||F(u)||.
+    From u = 0 the full step is u = d1/4 with F = d1^3/32, so the trial ratio
+    |F(d1/4)| / |F(0)| is d1^2/32.  d1^2 = 31.999 gives 0.99996875: a plain
+    decrease (or a constant below 3.1e-5) would accept it, the rule rejects it
+    and the halved step u = d1/8 is taken.  d1^2 = 32 (1 - 1.5e-4) gives
+    0.99985 <= 0.9999: accepted (a constant of 1.5e-4 or more would reject)."""
+    d1 = -math.sqrt(d_sq)
+    p = _one_node_problem(2.0 * d1)
+    assert abs(p.d[1] - d1) <= 4e-16 * abs(d1)
+    u1, st1 = O.newton(p, tol=1e-15, max_iter=1)
+    assert st1.backtracks == (1 if halved else 0)
+    step = d1 / 8.0 if halved else d1 / 4.0
+    assert abs(u1[1] - step) <= 1e-15 * abs(step)
+    ratio = st1.residual_norms[1] / st1.residual_norms[0]
+    if halved:
+        # the halved step: F(d1/8) = -d1/2 + d1^3/256, ratio 1/2 - d1^2/256
+        assert abs(ratio - (0.5 - d_sq / 256.0)) <= 1e-14
+    else:
+        assert abs(ratio - d_sq / 32.0) <= 1e-14
+
+
 def _thomas(a, b, c, r):
     n = len(b)
     cp = np.zeros(n)
