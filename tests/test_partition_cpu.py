@@ -155,3 +155,60 @@ def test_invalid_part_count_rejected(driver, tmp_path, G):
     coords, rowptr, col = mesh_graph("1d_n300")           # 301 nodes
     rc, P = run_partition(driver, tmp_path, coords, rowptr, col, G)
     assert rc != 0 and P is None
+
+
+# Host model of the indexing of the register-resident Krylov kernels with the
+# block-Jacobi preconditioner (one thread per row of the workgroup's part,
+# rows of at most K = 8 entries, LDS step buffers of 2 vectors x (NT + 1)
+# doubles, entry NT of each an always-zero value).  Checked for every
+# workgroup and every thread, also where a part is far smaller than the
+# workgroup: the clamped row of a thread without a row, the clamped entry
+# index, the part-local position of an in-block column (it must name that
+# column's row in the same part), and every LDS index read or written.
+K_RESIDENT = 8
+MODEL_CASES = [("1d_n300", 2, 256), ("1d_n300", 2, 512), ("1d_n300", 5, 256), ("1d_n300", 300, 256),
+               ("2d_n24", 5, 256), ("2d_n24", 3, 512), ("2d_n24", 64, 256), ("disk_n20", 13, 256)]
+
+
+@pytest.mark.parametrize("name,G,NT", MODEL_CASES, ids=[f"{m}-G{g}-NT{t}" for m, g, t in MODEL_CASES])
+def test_resident_block_jacobi_indexing_model(driver, tmp_path, name, G, NT):
+    coords, rowptr, col = mesh_graph(name)
+    n, S = len(coords), len(col)
+    rc, P = run_partition(driver, tmp_path, coords, rowptr, col, G)
+    assert rc == 0
+    kr, rlist, kloc = P["kr"], P["rlist"], P["kloc"]
+    assert P["maxrows"] <= NT                       # the launcher's condition for the resident form
+    assert np.diff(rowptr).max() <= K_RESIDENT
+    lds_words = 4 * (NT + 1)                         # two buffers x two vectors
+    for g in range(G):
+        rb, re = int(kr[g]), int(kr[g + 1])
+        written = set()
+        for tid in range(NT):
+            i = rb + tid
+            own = i < re
+            q = max(min(i, re - 1), 0)
+            assert 0 <= q < n
+            row = int(rlist[q])
+            beg, end = int(rowptr[row]), int(rowptr[row + 1])
+            for k in range(K_RESIDENT):
+                vi = min(beg + k, end - 1)
+                assert 0 <= vi < S
+                c = int(col[vi])
+                offd = own and beg + k < end and c != row
+                l = int(kloc[vi])
+                li = l if (offd and l >= 0) else NT
+                assert 0 <= li <= NT
+                if li < NT:
+                    assert li < re - rb and int(rlist[rb + li]) == c   # the column's own row in the part
+                for v in range(2):
+                    for buf in range(2):
+                        assert buf * 2 * (NT + 1) + v * (NT + 1) + li < lds_words
+            for v in range(2):
+                for buf in range(2):
+                    idx = buf * 2 * (NT + 1) + v * (NT + 1) + tid
+                    assert idx < lds_words
+                    written.add(idx)
+        # the zero entries (index NT of each vector and buffer) are written by
+        # threads 0..3 and by no row thread
+        zeros = {(t >> 1) * 2 * (NT + 1) + (t & 1) * (NT + 1) + NT for t in range(4)}
+        assert len(zeros) == 4 and not (zeros & written)
