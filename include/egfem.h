@@ -523,8 +523,9 @@ typedef struct {
                                 applies and that grid is co-resident; otherwise 1024 threads and
                                 min(ceil(n / 64), compute units) workgroups */
   int krylov_kernel;         /* 0: register-resident BiCGStab (one thread per row) when every
-                                workgroup's rows fit its threads and rows hold at most 8
-                                entries, else the streaming one; 1: always the streaming one */
+                                workgroup's rows fit its threads, rows hold at most 8 entries
+                                and workgroups have at most 512 threads, else the streaming
+                                one; 1: always the streaming one */
   int action_half;           /* 1: residual actions read the symmetric half stream (tensors with
                                 T_ijk = T_ikj: mass, convection; each fiber keeps k at or after j,
                                 the diagonal halved, and sums h a_k and h u_k), one row block per

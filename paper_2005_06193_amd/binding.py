@@ -7,9 +7,11 @@ every call raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
 import warnings
+import weakref
 from dataclasses import dataclass
 from typing import List, Optional, Sequence
 
@@ -115,6 +117,25 @@ class _Stats(C.Structure):
 
 
 _lib = None
+
+# Live handles and batch plans.  They own device memory, events, streams and
+# graphs; an exit hook destroys them (batch plans first, they reference
+# handles) while the HIP runtime is still up, instead of leaving it to object
+# finalisers during interpreter shutdown.  The hook is registered after torch
+# is imported, so it runs before torch's own exit hooks.
+_live_tensors: "weakref.WeakSet" = weakref.WeakSet()
+_live_batches: "weakref.WeakSet" = weakref.WeakSet()
+
+
+def close_all() -> None:
+    """Destroy every live batch plan, then every live tensor handle."""
+    for b in list(_live_batches):
+        b.close()
+    for t in list(_live_tensors):
+        t.close()
+
+
+atexit.register(close_all)
 
 EXPORTS = {
     "egfem_build_tensor": (C.c_int, [C.c_int, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
@@ -406,6 +427,7 @@ class Tensor:
 
     def __init__(self, handle: int):
         self._h = C.c_void_p(handle)
+        _live_tensors.add(self)
         inf = _Info()
         _check(load_library().egfem_tensor_info(self._h, C.byref(inf)))
         self.info = Info(inf.dim, inf.form, inf.symmetric, inf.n_nodes, inf.n_cells, inf.nnz,
@@ -749,6 +771,7 @@ class Batch:
         _check(load_library().egfem_batch_create(m, hs, self._ps, up, C.byref(o), int(threads),
                                                  float(weight_exp), C.byref(out)))
         self._h = out
+        _live_batches.add(self)
 
     def run(self, zero_init: bool = True, graph: bool = False):
         fn = load_library().egfem_batch_graph_run if graph else load_library().egfem_batch_run

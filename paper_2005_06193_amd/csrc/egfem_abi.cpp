@@ -580,13 +580,13 @@ int egfem_picard(egfem_tensor_t T, const egfem_problem* p, double* u, const egfe
                       true, opts.max_krylov, opts.krylov_blocks, &kr, st, nullptr, tm.on, opts.krylov_threads,
                       true);
     if (rc != EGFEM_OK) return rc;
-    // relative update, then u <- u^{n+1}, enqueued behind the solve: one
-    // synchronisation reads the solve's outcome and the update norms
+    // relative update enqueued behind the solve: one synchronisation reads
+    // the solve's outcome and the update norms; u <- u^{n+1} only after both
+    // are known to be valid (an error or a non-finite step leaves u at u^n)
     hipError_t e = hipSuccess;
     const int g = launch_diff_norms(T->n, W.delta, u, W.red, st, &e);
     EGFEM_HIP_CHECK(e);
     EGFEM_HIP_CHECK(hipMemcpyAsync(part.data(), W.red, 2 * g * sizeof(double), hipMemcpyDeviceToHost, st));
-    EGFEM_HIP_CHECK(launch_copy(u, W.delta, T->n, st));
     EGFEM_HIP_CHECK(hipStreamSynchronize(st));
     if ((rc = krylov_collect(T, st, &kr)) != EGFEM_OK) return rc;
     if (tm.on) stats.t_krylov_ms += kr.kernel_ms;
@@ -603,6 +603,7 @@ int egfem_picard(egfem_tensor_t T, const egfem_problem* p, double* u, const egfe
     if (k < EGFEM_HIST) stats.update_hist[k] = upd;
     ++k;
     if (kr.status == EGFEM_NONFINITE || !std::isfinite(upd)) { status = EGFEM_NONFINITE; break; }
+    EGFEM_HIP_CHECK(launch_copy(u, W.delta, T->n, st));
     if (upd <= opts.tol) status = EGFEM_OK;
   }
 #undef EGFEM_TRY
@@ -776,7 +777,6 @@ int egfem_picard_grad(egfem_tensor_t T, const egfem_problem* p, const egfem_grad
     const int ng = launch_diff_norms(T->n, W.delta, u, W.red, st, &e);
     EGFEM_HIP_CHECK(e);
     EGFEM_HIP_CHECK(hipMemcpyAsync(part.data(), W.red, 2 * ng * sizeof(double), hipMemcpyDeviceToHost, st));
-    EGFEM_HIP_CHECK(launch_copy(u, W.delta, T->n, st));
     EGFEM_HIP_CHECK(hipStreamSynchronize(st));
     if ((rc = krylov_collect(T, st, &kr)) != EGFEM_OK) return rc;
     if (tm.on) stats.t_krylov_ms += kr.kernel_ms;
@@ -792,8 +792,12 @@ int egfem_picard_grad(egfem_tensor_t T, const egfem_problem* p, const egfem_grad
     stats.update = upd;
     if (k < EGFEM_HIST) stats.update_hist[k] = upd;
     ++k;
-    if (kr.status == EGFEM_NONFINITE || !std::isfinite(upd)) status = EGFEM_NONFINITE;
-    else if (upd <= opts.tol) status = EGFEM_OK;
+    if (kr.status == EGFEM_NONFINITE || !std::isfinite(upd)) {   // u stays at the last finite iterate
+      status = EGFEM_NONFINITE;
+      break;
+    }
+    EGFEM_HIP_CHECK(launch_copy(u, W.delta, T->n, st));
+    if (upd <= opts.tol) status = EGFEM_OK;
   }
   if ((rc = residual_norm(&stats.res)) != EGFEM_OK) return rc;
   stats.res0 = 0.0;

@@ -78,8 +78,11 @@ __global__ __launch_bounds__(NT) void k_pcg(LaunchArgs P) {
   write_out(P, dev::team_pcg<NT, row_L(RS), row_K(RS)>(tm, P.A, rb, re, sh, &sh_abort));
 }
 
-// Register-resident forms: one thread per row, rows of at most K entries.
+// Register-resident forms: one thread per row, rows of at most K entries,
+// workgroups of at most kResidentMaxThreads threads (at 1024 threads a wave
+// may hold only 128 VGPRs and the resident BiCGStab would spill registers).
 constexpr int kResidentRow = 8;
+constexpr int kResidentMaxThreads = 512;
 
 template <int NT, int K>
 __global__ __launch_bounds__(NT) void k_bicgstab_reg(LaunchArgs P) {
@@ -102,9 +105,13 @@ const void* streaming_kernel(KrylovMethod m) {
 
 template <int NT>
 const void* kernel_NT(KrylovMethod m, bool resident, int rs) {
-  if (resident)
-    return m == KrylovMethod::kCG ? (const void*)k_pcg_reg<NT, kResidentRow>
-                                  : (const void*)k_bicgstab_reg<NT, kResidentRow>;
+  if constexpr (NT <= kResidentMaxThreads) {
+    if (resident)
+      return m == KrylovMethod::kCG ? (const void*)k_pcg_reg<NT, kResidentRow>
+                                    : (const void*)k_bicgstab_reg<NT, kResidentRow>;
+  } else {
+    if (resident) return nullptr;
+  }
   switch (rs) {
     case 0: return streaming_kernel<NT, 0>(m);
     case 1: return streaming_kernel<NT, 1>(m);
@@ -226,8 +233,8 @@ int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, con
   // register-resident form when every workgroup's rows fit its threads, rows
   // hold at most kResidentRow entries, and the grid is co-resident for it
   // (columns are held as 32-bit byte offsets: n < 2^28)
-  const void* kreg = kernel_for(NT, method, true, 0);
-  const bool resident_ok = T->krylov_kernel == 0 && T->max_row_slots <= kResidentRow &&
+  const void* kreg = kernel_for(NT, method, true, 0);   // null above kResidentMaxThreads
+  const bool resident_ok = kreg && T->krylov_kernel == 0 && T->max_row_slots <= kResidentRow &&
                            T->n < (int64_t(1) << 28) && G <= coresident(kreg, NT);
   // block-Jacobi preconditioner: the resident kernels on a compact partition
   bool block = resident_ok && T->krylov_precond > 0 && !T->h_coords.empty() && (T->n + G - 1) / G <= NT;

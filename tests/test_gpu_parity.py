@@ -258,7 +258,7 @@ def test_bicgstab_block_preconditioner(mesh, transpose, precond):
     xo = spla.spsolve(A, rhs)
     cond = np.linalg.cond(A.toarray())
     iters = {}
-    for blocks, threads in ((0, 0), (7, 1024), (64, 256), (33, 512)):
+    for blocks, threads in ((0, 0), (7, 1024), (64, 256), (33, 512), (2, 512)):
         if blocks and (T.n + blocks - 1) // blocks > 1024:
             continue
         for pc in sorted({0, precond}):
@@ -379,7 +379,7 @@ def test_cg_block_preconditioner(mesh, precond):
     xo = spla.spsolve(A, rhs)
     cond = np.linalg.cond(A.toarray())
     iters = {}
-    for blocks, threads in ((0, 0), (7, 1024), (64, 256), (33, 512)):
+    for blocks, threads in ((0, 0), (7, 1024), (64, 256), (33, 512), (2, 512)):
         if blocks and (T.n + blocks - 1) // blocks > 1024:
             continue
         for pc in sorted({0, precond}):

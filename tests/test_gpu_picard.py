@@ -123,6 +123,17 @@ def test_picard_edge_cases():
     u = torch.full((T.n,), float("nan"), dtype=torch.float64, device=DEV)
     st = T.picard(p, u, warn=False)
     assert st.status == 3
+    # a step whose solve turns non-finite (load 1e120: the first iterate is
+    # ~1e120, so the next matrix times it overflows) ends the iteration with u
+    # at the last finite iterate
+    big = E.Problem(T.n, p.load * 1e120, dirm, None, 1.0, False)
+    u1 = torch.zeros(T.n, dtype=torch.float64, device=DEV)
+    st1 = T.picard(big, u1, E.PicardOptions(max_picard=1), warn=False)
+    assert st1.status == 1 and bool(torch.isfinite(u1).all()) and float(u1.abs().max()) > 1e100
+    u = torch.zeros(T.n, dtype=torch.float64, device=DEV)
+    st = T.picard(big, u, warn=False)
+    assert st.status == 3 and st.picard_iters == 2, (st.status_name, st.picard_iters)
+    assert torch.equal(u, u1)
     # iteration cap
     u = torch.zeros(T.n, dtype=torch.float64, device=DEV)
     st = T.picard(p, u, E.PicardOptions(max_picard=2), warn=False)
