@@ -317,7 +317,8 @@ typedef struct {
   int krylov_status_hist[EGFEM_HIST];     /* Krylov status of step k */
   double krylov_relres_hist[EGFEM_HIST];  /* Krylov relative residual of step k */
   int krylov_kernels;        /* BiCGStab kernels that ran: bit 0 register-resident, bit 1 streaming,
-                                bit 2 with the block-Jacobi preconditioner */
+                                bit 2 with the block-Jacobi preconditioner, bit 3 the overlapped
+                                form (flag-in-data synchronisation, see krylov_kernel) */
 } egfem_newton_stats;
 
 /* Fill opts with the defaults above. */
@@ -525,7 +526,14 @@ typedef struct {
   int krylov_kernel;         /* 0: register-resident BiCGStab (one thread per row) when every
                                 workgroup's rows fit its threads, rows hold at most 8 entries
                                 and workgroups have at most 512 threads, else the streaming
-                                one; 1: always the streaming one */
+                                one; with the block-Jacobi preconditioner the resident BiCGStab
+                                runs in its overlapped form: every exchanged value (reduction
+                                partials, gathered vector entries) carries its own completion
+                                flag, the preconditioner's Chebyshev steps run while the
+                                team's reductions complete, and in-part columns of a product
+                                are read from LDS; 1: always the streaming one; 2: the resident
+                                kernels in their barrier form (counter barriers, as the
+                                streaming kernel) */
   int action_half;           /* 1: residual actions read the symmetric half stream (tensors with
                                 T_ijk = T_ikj: mass, convection; each fiber keeps k at or after j,
                                 the diagonal halved, and sums h a_k and h u_k), one row block per

@@ -71,6 +71,10 @@ static void free_workspace(Workspace& W) {
   if (W.cnbr) hipFree(W.cnbr);
   if (W.crlist) hipFree(W.crlist);
   if (W.ckloc) hipFree(W.ckloc);
+  if (W.llv) hipFree(W.llv);
+  if (W.ckext) hipFree(W.ckext);
+  if (W.cgptr) hipFree(W.cgptr);
+  if (W.cgcol) hipFree(W.cgcol);
   if (W.host_partial) hipHostFree(W.host_partial);
   if (W.host_kout) hipHostFree(W.host_kout);
   if (W.kpend.ev0) hipEventDestroy(W.kpend.ev0);
@@ -437,7 +441,7 @@ int egfem_newton(egfem_tensor_t T, const egfem_problem* p, double* u, const egfe
       ++stats.n_krylov;
     }
     stats.krylov_iters += kr.iters;
-    stats.krylov_kernels |= (kr.resident ? 1 : 2) | (kr.block_precond ? 4 : 0);
+    stats.krylov_kernels |= (kr.resident ? 1 : 2) | (kr.block_precond ? 4 : 0) | (kr.overlapped ? 8 : 0);
     if (k < EGFEM_HIST) {
       stats.krylov_hist[k] = kr.iters;
       stats.krylov_status_hist[k] = kr.status;
@@ -591,7 +595,7 @@ int egfem_picard(egfem_tensor_t T, const egfem_problem* p, double* u, const egfe
     if ((rc = krylov_collect(T, st, &kr)) != EGFEM_OK) return rc;
     if (tm.on) stats.t_krylov_ms += kr.kernel_ms;
     stats.krylov_iters += kr.iters;
-    stats.krylov_kernels |= (kr.resident ? 1 : 2) | (kr.block_precond ? 4 : 0);
+    stats.krylov_kernels |= (kr.resident ? 1 : 2) | (kr.block_precond ? 4 : 0) | (kr.overlapped ? 8 : 0);
     if (k < EGFEM_HIST) stats.krylov_hist[k] = kr.iters;
     double dd = 0.0, xx = 0.0;
     for (int q = 0; q < g; ++q) {
@@ -696,7 +700,7 @@ int egfem_burgers(egfem_tensor_t T, const uint8_t* dirichlet, const double* sour
     stats.krylov_iters += kr.iters;
     stats.max_step_krylov = std::max(stats.max_step_krylov, kr.iters);
     if (std::isfinite(kr.relres)) stats.max_relres = std::max(stats.max_relres, kr.relres);
-    stats.krylov_kernels |= (kr.resident ? 1 : 2) | (kr.block_precond ? 4 : 0);
+    stats.krylov_kernels |= (kr.resident ? 1 : 2) | (kr.block_precond ? 4 : 0) | (kr.overlapped ? 8 : 0);
     if (n < EGFEM_HIST) stats.krylov_hist[n] = kr.iters;
     status = std::max(status, kr.status);
     if (kr.status == EGFEM_NONFINITE) {
@@ -781,7 +785,7 @@ int egfem_picard_grad(egfem_tensor_t T, const egfem_problem* p, const egfem_grad
     if ((rc = krylov_collect(T, st, &kr)) != EGFEM_OK) return rc;
     if (tm.on) stats.t_krylov_ms += kr.kernel_ms;
     stats.krylov_iters += kr.iters;
-    stats.krylov_kernels |= (kr.resident ? 1 : 2) | (kr.block_precond ? 4 : 0);
+    stats.krylov_kernels |= (kr.resident ? 1 : 2) | (kr.block_precond ? 4 : 0) | (kr.overlapped ? 8 : 0);
     if (k < EGFEM_HIST) stats.krylov_hist[k] = kr.iters;
     double dd = 0.0, xx = 0.0;
     for (int q = 0; q < ng; ++q) {
@@ -866,7 +870,7 @@ int egfem_newton_grad(egfem_tensor_t T, const egfem_problem* p, const egfem_grad
     KrylovResult kr;
     if ((rc = solve(W.rhs, 1.0, u, true, 1e-12, &kr)) != EGFEM_OK) return rc;
     stats.krylov_iters += kr.iters;
-    stats.krylov_kernels |= (kr.resident ? 1 : 2) | (kr.block_precond ? 4 : 0);
+    stats.krylov_kernels |= (kr.resident ? 1 : 2) | (kr.block_precond ? 4 : 0) | (kr.overlapped ? 8 : 0);
   }
   double nF0 = 0.0;
   if ((rc = residual(u, &nF0)) != EGFEM_OK) return rc;
@@ -894,7 +898,7 @@ int egfem_newton_grad(egfem_tensor_t T, const egfem_problem* p, const egfem_grad
       ++stats.n_krylov;
     }
     stats.krylov_iters += kr.iters;
-    stats.krylov_kernels |= (kr.resident ? 1 : 2) | (kr.block_precond ? 4 : 0);
+    stats.krylov_kernels |= (kr.resident ? 1 : 2) | (kr.block_precond ? 4 : 0) | (kr.overlapped ? 8 : 0);
     if (k < EGFEM_HIST) {
       stats.krylov_hist[k] = kr.iters;
       stats.krylov_status_hist[k] = kr.status;

@@ -1523,7 +1523,23 @@ __device__ ChebParams cheb_params(const int (&li)[K], const double (&aa)[K], dou
 // together; ad is the row's diagonal entry.  Threads without a row (has_row
 // false; whole waves at the end of a part) skip the loads.  Called by every
 // thread of the workgroup.
-template <int NT, int K, int NV>
+// Workgroup barrier that orders LDS accesses only: it waits for this wave's
+// LDS operations, not for its outstanding global loads, stores or atomics
+// (which __syncthreads would), so global traffic issued before it stays in
+// flight across the barrier.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <bool LDS_ONLY>
+__device__ __forceinline__ void cheb_barrier() {
+  if (LDS_ONLY) lds_barrier();
+  else __syncthreads();
+}
+
+template <int NT, int K, int NV, bool LDS_ONLY = false>
 __device__ __forceinline__ void block_cheb(const int (&li)[K], const double (&aa)[K], double ad, double d,
                                            bool has_row, int steps, const ChebParams& c, double* lds,
                                            const double (&x)[NV], double (&z)[NV]) {
@@ -1536,12 +1552,12 @@ __device__ __forceinline__ void block_cheb(const int (&li)[K], const double (&aa
     z[v] = dd[v];
   }
   double rho_old = 1.0 / c.sigma;
-  __syncthreads();   // the previous call's last reads are done before this call's first writes
+  cheb_barrier<LDS_ONLY>();   // the previous call's last reads are done before this call's first writes
   for (int k = 1; k < steps; ++k) {
     double* buf = lds + (k & 1) * 2 * (NT + 1);
 #pragma unroll
     for (int v = 0; v < NV; ++v) buf[v * (NT + 1) + tid] = dd[v];
-    __syncthreads();
+    cheb_barrier<LDS_ONLY>();
     if (has_row) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) {

@@ -59,7 +59,7 @@ struct KrylovPending {
   bool active = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;   // launch timing (timed solves)
   int G = 0, NT = 0;
-  bool resident = false, block = false;
+  bool resident = false, block = false, overlapped = false;
 };
 
 // Solver workspace owned by a handle (allocated on first use).
@@ -90,6 +90,13 @@ struct Workspace {
   int32_t* cnbr = nullptr;      // neighbour lists of the parts
   int crow_blocks = 0;          // grid size the compact partition was made for
   int crow_maxrows = 0;
+  int crow_maxghost = 0;        // most ghost columns (out-of-part columns of its rows) of a part
+  int16_t* ckext = nullptr;     // [slots] LDS position of the column: part-local, or -1 - ghost index
+  int32_t* cgptr = nullptr;     // [kMaxKrylovBlocks + 1] ghost range of every part
+  int32_t* cgcol = nullptr;     // [slots] global column of every ghost
+  // flagged exchange of the overlapped block-Jacobi BiCGStab
+  uint64_t* llv = nullptr;      // flagged words: [3][n][2] published vectors, then the reduction words
+  unsigned ll_salt = 0;         // 1 .. 4095, advanced at every launch (0: buffer not yet zeroed)
   double* kout = nullptr;       // Krylov result [4] (device)
   double* host_partial = nullptr;  // pinned host mirror of partial sums
   double* host_kout = nullptr;     // pinned host mirror of the Krylov result
@@ -288,6 +295,7 @@ struct KrylovResult {
   double kernel_ms = 0.0;   // launch duration of the persistent kernel (when timed)
   bool resident = false;    // the register-resident kernel ran
   bool block_precond = false;   // with the block-Jacobi preconditioner
+  bool overlapped = false;      // the overlapped (flagged-synchronisation) BiCGStab ran
 };
 enum class KrylovMethod { kBiCGStab, kCG };
 

@@ -32,6 +32,7 @@
 #include <tuple>
 
 #include "egfem_device.h"
+#include "egfem_krylov_ov.h"
 
 namespace egfem {
 namespace {
@@ -40,6 +41,7 @@ using dev::KArgs;
 
 struct LaunchArgs {
   KArgs A;
+  dev::OvArgs ov;           // flagged exchange of the overlapped block-Jacobi BiCGStab
   const int32_t* krow;      // row partition [G+1]
   const int32_t* nbr;       // [G][kMaxNbr + 1] neighbour lists (count, ranks), or null
   unsigned* ctrl;
@@ -88,6 +90,28 @@ template <int NT, int K>
 __global__ __launch_bounds__(NT) void k_bicgstab_reg(LaunchArgs P) {
   EGFEM_TEAM_PROLOGUE();
   write_out(P, dev::team_bicgstab_reg<NT, K>(tm, P.A, rb, re, sh, &sh_abort));
+}
+
+// Overlapped block-Jacobi BiCGStab on a compact partition (one thread per
+// row, rows of at most kResidentRow entries, at most NT ghost columns per
+// part); the grid's last workgroup aggregates the reductions.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_bicgstab_ov(LaunchArgs P) {
+  __shared__ double sh[dev::kShWords<NT>];
+  __shared__ int sh_state[2];
+  if (threadIdx.x == 0) sh_state[1] = 0;
+  dev::AggRed ar{blockIdx.x, gridDim.x - 1, P.ov.salt, P.ov.part, P.ov.tot, P.ov.exit_word,
+                 P.ctrl + dev::kCtrlAbort};
+  if (blockIdx.x == gridDim.x - 1) {
+    dev::agg_serve<NT>(ar);
+    return;
+  }
+  const int rb = P.krow[blockIdx.x], re = P.krow[blockIdx.x + 1];
+  const dev::KOut o = dev::team_bicgstab_ov<NT, kResidentRow>(ar, P.A, P.ov, rb, re, sh, sh_state);
+  if (blockIdx.x == 0 && threadIdx.x == 0)   // every reduction is complete: release the aggregator
+    __hip_atomic_store(P.ov.exit_word, (uint64_t)dev::ll_flag(P.ov.salt, dev::kLLEpochMask) << 32,
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  write_out(P, o);
 }
 
 template <int NT, int K>
@@ -177,7 +201,7 @@ int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, con
   Workspace& W = T->ws;
   if (threads == 0) threads = T->tuned_krylov_threads;
   if (blocks <= 0) blocks = T->tuned_krylov_blocks;
-  if (threads == 0 && blocks <= 0 && T->krylov_kernel == 0 && T->max_row_slots <= kResidentRow &&
+  if (threads == 0 && blocks <= 0 && T->krylov_kernel != 1 && T->max_row_slots <= kResidentRow &&
       T->n <= (int64_t)256 * kMaxKrylovBlocks) {
     // untuned, register-resident: 256-thread workgroups, one row per thread,
     // as few as that allows (largest block-Jacobi parts); kept only when the
@@ -234,7 +258,7 @@ int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, con
   // hold at most kResidentRow entries, and the grid is co-resident for it
   // (columns are held as 32-bit byte offsets: n < 2^28)
   const void* kreg = kernel_for(NT, method, true, 0);   // null above kResidentMaxThreads
-  const bool resident_ok = kreg && T->krylov_kernel == 0 && T->max_row_slots <= kResidentRow &&
+  const bool resident_ok = kreg && T->krylov_kernel != 1 && T->max_row_slots <= kResidentRow &&
                            T->n < (int64_t(1) << 28) && G <= coresident(kreg, NT);
   // block-Jacobi preconditioner: the resident kernels on a compact partition
   bool block = resident_ok && T->krylov_precond > 0 && !T->h_coords.empty() && (T->n + G - 1) / G <= NT;
@@ -264,6 +288,47 @@ int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, con
     EGFEM_HIP_CHECK(hipStreamSynchronize(st));
     W.crow_blocks = G;
     W.crow_maxrows = cp.maxrows;
+    // ghosts of every part (its rows' out-of-part columns, ascending) and the
+    // LDS position of every entry: part-local (>= 0) or -1 - ghost index
+    std::vector<int16_t> kext(cp.kloc.begin(), cp.kloc.end());
+    std::vector<int32_t> gptr(1, 0), gcol;
+    int maxghost = 0;
+    std::vector<int32_t> gl;
+    for (int g = 0; g < G; ++g) {
+      gl.clear();
+      for (int32_t q = cp.kr[g]; q < cp.kr[g + 1]; ++q) {
+        const int32_t rr = cp.rlist[q];
+        for (int32_t sl = T->h_rowptr[rr]; sl < T->h_rowptr[rr + 1]; ++sl)
+          if (cp.kloc[sl] < 0) gl.push_back(T->h_col[sl]);
+      }
+      std::sort(gl.begin(), gl.end());
+      gl.erase(std::unique(gl.begin(), gl.end()), gl.end());
+      for (int32_t q = cp.kr[g]; q < cp.kr[g + 1]; ++q) {
+        const int32_t rr = cp.rlist[q];
+        for (int32_t sl = T->h_rowptr[rr]; sl < T->h_rowptr[rr + 1]; ++sl)
+          if (cp.kloc[sl] < 0)
+            kext[sl] = (int16_t)(-1 - (int)(std::lower_bound(gl.begin(), gl.end(), T->h_col[sl]) - gl.begin()));
+      }
+      maxghost = std::max(maxghost, (int)gl.size());
+      gcol.insert(gcol.end(), gl.begin(), gl.end());
+      gptr.push_back((int32_t)gcol.size());
+    }
+    W.crow_maxghost = maxghost;
+    if (maxghost <= 1024) {   // int16 positions, at most one ghost per thread
+      if (!W.ckext) {
+        if (hipMalloc((void**)&W.ckext, std::max<size_t>(T->slots, 1) * sizeof(int16_t)) != hipSuccess ||
+            hipMalloc((void**)&W.cgptr, ((size_t)kMaxKrylovBlocks + 1) * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc((void**)&W.cgcol, std::max<size_t>(T->slots, 1) * sizeof(int32_t)) != hipSuccess)
+          return fail(EGFEM_ERR_OOM, "hipMalloc of the ghost lists failed");
+        T->device_bytes += (int64_t)T->slots * 6 + ((int64_t)kMaxKrylovBlocks + 1) * 4;
+      }
+      EGFEM_HIP_CHECK(hipMemcpyAsync(W.ckext, kext.data(), kext.size() * sizeof(int16_t), hipMemcpyHostToDevice, st));
+      EGFEM_HIP_CHECK(hipMemcpyAsync(W.cgptr, gptr.data(), gptr.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+      if (!gcol.empty())
+        EGFEM_HIP_CHECK(hipMemcpyAsync(W.cgcol, gcol.data(), gcol.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                       st));
+      EGFEM_HIP_CHECK(hipStreamSynchronize(st));
+    }
   }
   block = block && W.crow_maxrows <= NT;   // one thread per row
   EGFEM_HIP_CHECK(launch_fill_u32(W.ctrl, 0u, dev::kCtrlWords, st));
@@ -314,9 +379,47 @@ int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, con
     EGFEM_HIP_CHECK(hipEventRecord(ev0, st));
   }
   const bool resident = block || (resident_ok && W.krow_maxrows <= NT);
-  const void* kern = resident ? kreg : kernel_for(NT, method, false, T->krylov_rs);
+  // the overlapped block-Jacobi BiCGStab (flag-in-data synchronisation) where
+  // the block preconditioner runs, unless the shape asks for the barrier form
+  const void* kov = (method == KrylovMethod::kBiCGStab && block && T->krylov_kernel == 0 &&
+                     W.crow_maxghost <= NT && W.ckext)
+                        ? (NT == 256 ? (const void*)k_bicgstab_ov<256> : (const void*)k_bicgstab_ov<512>)
+                        : nullptr;
+  const bool overlapped = kov && G + 1 <= coresident(kov, NT);   // plus the aggregating workgroup
+  // Flagged words of the overlapped kernel: the published vectors [3][n][2]
+  // and the reduction words (partials [2][4][2][kMaxKrylovBlocks], totals, exit
+  // word), in one buffer that only this kernel writes.  A word is trusted when
+  // its flag carries the launch's salt (1 .. 4095, advanced per launch), so
+  // the buffer is zeroed when allocated and again whenever the salt wraps:
+  // every flag it holds then comes from a distinct earlier launch of this
+  // handle.
+  const size_t ll_vec_words = (size_t)6 * std::max<int64_t>(T->n, 1);
+  const size_t ll_red_words = (size_t)2 * dev::kAggValues * 2 * kMaxKrylovBlocks + 2 * dev::kAggValues * 2 + 8;
+  if (overlapped && !W.llv) {
+    const size_t bytes = (ll_vec_words + ll_red_words) * sizeof(uint64_t);
+    if (hipMalloc((void**)&W.llv, bytes) != hipSuccess)
+      return fail(EGFEM_ERR_OOM, "hipMalloc of the flagged words failed");
+    T->device_bytes += (int64_t)bytes;
+    W.ll_salt = 0;
+  }
+  if (overlapped) {
+    if (W.ll_salt == 0 || W.ll_salt == 4095u)
+      EGFEM_HIP_CHECK(launch_fill_u32(reinterpret_cast<unsigned*>(W.llv), 0u,
+                                      (int64_t)(2 * (ll_vec_words + ll_red_words)), st));
+    W.ll_salt = W.ll_salt % 4095u + 1u;
+    P.ov.llv = W.llv;
+    P.ov.kext = W.ckext;
+    P.ov.gptr = W.cgptr;
+    P.ov.gcol = W.cgcol;
+    P.ov.part = W.llv + ll_vec_words;
+    P.ov.tot = P.ov.part + (size_t)2 * dev::kAggValues * 2 * kMaxKrylovBlocks;
+    P.ov.exit_word = P.ov.tot + 2 * dev::kAggValues * 2;
+    P.ov.salt = W.ll_salt;
+  }
+  const void* kern = overlapped ? kov : (resident ? kreg : kernel_for(NT, method, false, T->krylov_rs));
   void* args[] = {(void*)&P};
-  const hipError_t e = hipLaunchCooperativeKernel(kern, dim3((unsigned)G), dim3((unsigned)NT), args, 0, st);
+  const hipError_t e = hipLaunchCooperativeKernel(kern, dim3((unsigned)(overlapped ? G + 1 : G)), dim3((unsigned)NT),
+                                                   args, 0, st);
   if (e != hipSuccess) {
     if (ev0) hipEventDestroy(ev0);
     if (ev1) hipEventDestroy(ev1);
@@ -332,6 +435,7 @@ int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, con
   q.NT = NT;
   q.resident = resident;
   q.block = block;
+  q.overlapped = overlapped;
   if (defer) return EGFEM_OK;
   return krylov_collect(T, st, res);
 }
@@ -359,6 +463,7 @@ int krylov_collect(egfem_tensor_s* T, hipStream_t st, KrylovResult* res) {
   res->threads = q.NT;
   res->resident = q.resident;
   res->block_precond = q.block;
+  res->overlapped = q.overlapped;
   if (res->status == EGFEM_ERR_HIP) return fail(EGFEM_ERR_HIP, "Krylov grid barrier timed out");
   return EGFEM_OK;
 }

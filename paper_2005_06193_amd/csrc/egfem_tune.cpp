@@ -58,7 +58,7 @@ int egfem_set_shape(egfem_tensor_t T, const egfem_launch_shape* s) {
       s->krylov_blocks > kMaxKrylovBlocks ||
       (s->krylov_threads != 0 && s->krylov_threads != 256 && s->krylov_threads != 512 &&
        s->krylov_threads != 1024) ||
-      (s->krylov_kernel != 0 && s->krylov_kernel != 1) || (s->action_half != 0 && s->action_half != 1) ||
+      (s->krylov_kernel < 0 || s->krylov_kernel > 2) || (s->action_half != 0 && s->action_half != 1) ||
       s->krylov_precond < 0 || s->krylov_precond == 1 || s->krylov_precond > 32)
     return fail(EGFEM_ERR_ARG, "invalid launch shape");
   if (s->action_half && !T->vH) return fail(EGFEM_ERR_ARG, "this tensor has no symmetric half stream");

@@ -202,11 +202,12 @@ def test_problem_residual_and_jacobian(name):
 # ---------------------------------------------------------------------------
 # linear solve
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("kernel", [0, 1])
+@pytest.mark.parametrize("kernel", [0, 1, 2])
 @pytest.mark.parametrize("transpose", [False, True])
 def test_bicgstab_solve(transpose, kernel):
-    """Both BiCGStab kernels: 0 = register-resident (every workgroup's rows
-    fit its threads here), 1 = streaming."""
+    """The BiCGStab kernels: 0 = register-resident (every workgroup's rows
+    fit its threads here; overlapped form with the block preconditioner),
+    1 = streaming, 2 = register-resident in the barrier form."""
     wl = W.nonlinear_diffusion_2d(48)
     T = eg().Tensor.from_mesh(wl.mesh, wl.form)
     T.set_shape(krylov_kernel=kernel)
@@ -233,16 +234,19 @@ BJ_MESHES = {
 }
 
 
+@pytest.mark.parametrize("kernel", [0, 2])
 @pytest.mark.parametrize("precond", [0, 2, 8, 32])
 @pytest.mark.parametrize("transpose", [False, True])
 @pytest.mark.parametrize("mesh", list(BJ_MESHES))
-def test_bicgstab_block_preconditioner(mesh, transpose, precond):
+def test_bicgstab_block_preconditioner(mesh, transpose, precond, kernel):
     """BiCGStab with the block-Jacobi preconditioner (k Chebyshev steps on each
     workgroup's block of a coordinate-bisection partition) against SuperLU on
-    a nonsymmetric Newton Jacobian, for several grids and workgroup sizes;
-    deterministic; fewer iterations than Jacobi.  (The uniform fallback to the
-    team barrier when a part has too many neighbours runs in the wheel-mesh
-    tests, whose hub row couples to every part.)"""
+    a nonsymmetric Newton Jacobian, for several grids and workgroup sizes, in
+    the overlapped form (kernel 0: flag-in-data synchronisation) and the
+    barrier form (kernel 2); deterministic; fewer iterations than Jacobi.
+    (The uniform fallback to the team barrier when a part has too many
+    neighbours runs in the wheel-mesh tests, whose hub row couples to every
+    part.)"""
     m = BJ_MESHES[mesh]()
     rng = np.random.default_rng(12)
     wl = W.Workload("t", m, rng.uniform(0, 10, m.n_nodes), 0, None, 1.0, False, 1e-12, 0)
@@ -262,9 +266,9 @@ def test_bicgstab_block_preconditioner(mesh, transpose, precond):
         if blocks and (T.n + blocks - 1) // blocks > 1024:
             continue
         for pc in sorted({0, precond}):
-            print(f"bicgstab block-Jacobi mesh={mesh} transpose={transpose} precond={pc} grid={blocks}x{threads}",
-                  flush=True)
-            T.set_shape(krylov_precond=pc, krylov_blocks=blocks, krylov_threads=threads)
+            print(f"bicgstab block-Jacobi mesh={mesh} transpose={transpose} precond={pc} kernel={kernel} "
+                  f"grid={blocks}x{threads}", flush=True)
+            T.set_shape(krylov_precond=pc, krylov_blocks=blocks, krylov_threads=threads, krylov_kernel=kernel)
             x, rc, its, rr = T.solve(jv, dt(rhs), transpose=transpose, rtol=1e-12)
             assert rc == 0, (rc, its, rr)
             # the recursive residual reaches 1e-12; the true one differs from it by
@@ -431,11 +435,12 @@ def test_newton_matches_oracle(name):
     assert np.linalg.norm(O.residual(po, ug)) <= 1e-11 * Fo0
 
 
-@pytest.mark.parametrize("kernel,precond", [(0, 8), (0, 0), (1, 8)])
+@pytest.mark.parametrize("kernel,precond", [(0, 8), (0, 0), (1, 8), (2, 8)])
 def test_newton_krylov_kernels(kernel, precond):
-    """The register-resident BiCGStab (block-Jacobi or Jacobi) and the
-    streaming one (always Jacobi) give the oracle's solution, and the
-    statistics name the kernel that ran (bit 2: block preconditioner)."""
+    """The register-resident BiCGStab (block-Jacobi in its overlapped form or
+    in the barrier form, or Jacobi) and the streaming one (always Jacobi) give
+    the oracle's solution, and the statistics name the kernel that ran (bit 2:
+    block preconditioner, bit 3: overlapped form)."""
     wl = W.nonlinear_diffusion_2d(40, seed=77)
     T = eg().Tensor.from_mesh(wl.mesh, wl.form)
     T.set_shape(krylov_kernel=kernel, krylov_precond=precond)
@@ -444,7 +449,8 @@ def test_newton_krylov_kernels(kernel, precond):
     u = torch.zeros(T.n, dtype=torch.float64, device=DEV)
     st = T.newton(p, u, _tight(), warn=False)
     assert st.status in (0, 4), st.status_name
-    assert st.krylov_kernels == ((5 if precond else 1) if kernel == 0 else 2)
+    want = {(0, 8): 13, (0, 0): 1, (1, 8): 2, (2, 8): 5}[(kernel, precond)]
+    assert st.krylov_kernels == want
     uo, _ = O.newton(po, tol=1e-14, max_iter=30)
     assert relerr(host(u), uo) <= 1e-10
 
@@ -624,7 +630,7 @@ def test_newton_full_size_3d_64_certificate():
     assert np.abs(Fg[rows] - F[rows]).max() <= 1e-12 * np.abs(b).max()
 
 
-@pytest.mark.parametrize("kernel", [0, 1])
+@pytest.mark.parametrize("kernel", [0, 1, 2])
 def test_newton_timing_leaves_the_iteration_unchanged(kernel):
     """Each Newton step enqueues its trial residual behind the Krylov launch and
     reads the solve's outcome, timing events and the trial norm in one
