@@ -276,6 +276,22 @@ typedef struct {
 int egfem_problem_residual(egfem_tensor_t T, const egfem_problem* p, const double* u,
                            double* F, double* norm, void* stream);
 
+/* egfem_problem_residual_noalloc: egfem_problem_residual for callers that
+ * cannot allocate device memory (code under graph capture, tight serving
+ * loops, harnesses that forbid allocation).  Same arguments and result (F
+ * bitwise equal; the norm's partial sums are added in another fixed order).
+ * Allocates nothing: the residual kernel's per-workgroup partial sums and
+ * their total live in a fixed array of the library (one per device, held
+ * until the process ends, 16,384 partial sums = 128 KiB); the total is formed
+ * on the device and, with norm != NULL, copied to *norm (synchronises the
+ * stream).  The handle's device must be current.  EGFEM_ERR_SHAPE when the
+ * handle's residual kernel writes more than 16,384 partial sums (an untuned
+ * handle writes one per row block; autotuned action runs write at most 8,192).
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU
+ * (other streams, other threads) race and must be serialised by the caller. */
+int egfem_problem_residual_noalloc(egfem_tensor_t T, const egfem_problem* p, const double* u,
+                                   double* F, double* norm, void* stream);
+
 /* DF(u) = [K] + T . a + (T ._2 u) diag(2u) with Dirichlet identity rows and
  * zero Dirichlet columns, into jval (device [slots]); dinv optional as above. */
 int egfem_problem_jacobian(egfem_tensor_t T, const egfem_problem* p, const double* u,

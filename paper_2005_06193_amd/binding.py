@@ -159,6 +159,8 @@ EXPORTS = {
                                C.c_void_p]),
     "egfem_problem_residual": (C.c_int, [C.c_void_p, C.POINTER(_Problem), C.c_void_p, C.c_void_p,
                                          C.POINTER(C.c_double), C.c_void_p]),
+    "egfem_problem_residual_noalloc": (C.c_int, [C.c_void_p, C.POINTER(_Problem), C.c_void_p, C.c_void_p,
+                                                 C.POINTER(C.c_double), C.c_void_p]),
     "egfem_problem_jacobian": (C.c_int, [C.c_void_p, C.POINTER(_Problem), C.c_void_p, C.c_void_p,
                                          C.c_void_p, C.c_void_p]),
     "egfem_newton_opts_default": (None, [C.POINTER(_Opts)]),
@@ -567,6 +569,18 @@ class Tensor:
                                                      _dptr(out, n=self.n),
                                                      C.byref(nrm) if with_norm else None,
                                                      _stream()))
+        return (out, nrm.value) if with_norm else out
+
+    def problem_residual_noalloc(self, p: Problem, u, out, with_norm=False):
+        """egfem_problem_residual_noalloc: the caller passes the output; the
+        library allocates nothing (its fixed per-device array holds the
+        partial sums)."""
+        pc = p.c()
+        nrm = C.c_double(0.0)
+        _check(load_library().egfem_problem_residual_noalloc(self.handle, C.byref(pc), _dptr(u, n=self.n),
+                                                             _dptr(out, n=self.n),
+                                                             C.byref(nrm) if with_norm else None,
+                                                             _stream()))
         return (out, nrm.value) if with_norm else out
 
     def problem_jacobian(self, p: Problem, u, out=None, dinv=None):
