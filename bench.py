@@ -853,10 +853,11 @@ def main():
                 "streaming_algorithm_bytes_per_launch": dk["bytes"] / dk["launches"],
                 "streaming_algorithm_GBps": dk["bytes"] / dk["launches"] / (avg_ms * 1e6),
                 "us_per_krylov_iteration": (1e3 * t_kry / k_it) if (dom == "krylov_bicgstab" and k_it) else None,
-                "limiter": ("synchronisation: two team reductions and one neighbour synchronisation per "
-                            "BiCGStab iteration, plus three workgroup-local block-Jacobi applications "
-                            "(%d Chebyshev steps each, in LDS); the register-resident kernel keeps J and the "
-                            "row vectors on chip" % T.get_shape()["krylov_precond"]
+                "limiter": ("latency between compute units: two reductions per BiCGStab iteration, each a "
+                            "store of flagged partials, their sum by the aggregating workgroup and a poll of the "
+                            "totals (two hops through the coherent memory level); the block-Jacobi steps "
+                            "(%d Chebyshev steps, LDS) and the exchange of ghost entries run inside those "
+                            "windows; J and the row vectors stay on chip" % T.get_shape()["krylov_precond"]
                             + (", measured HBM traffic %.2fx the algorithmic bytes"
                                % tr["krylov_bicgstab"]["ratio"] if traffic is not None else ""))
                 if dom == "krylov_bicgstab" else None}

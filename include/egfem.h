@@ -572,16 +572,17 @@ int egfem_get_shape(egfem_tensor_t T, egfem_launch_shape* s);
  * cache).  Out-of-range values give EGFEM_ERR_ARG. */
 int egfem_set_shape(egfem_tensor_t T, const egfem_launch_shape* s);
 
-/* Autotuner: time the candidate shapes on this handle's own tensor with HIP
- * events on `stream` and keep the fastest in the handle.
- *   what: bit 0 -> tensor action (runs x {pipelined, not}); bit 1 -> Krylov grid
- *         (kernel x threads x blocks, by the time per decade of residual
- *         reduction of a BiCGStab solve of DF(0) x = 1 (free rows) to 1e-8 with
- *         the handle's preconditioner; problem p must then be non-NULL).
+/* Autotuner: time the candidate shapes on this handle's own tensor on
+ * `stream` and keep the fastest in the handle.
+ *   what: bit 0 -> tensor action (runs x {pipelined, not}, HIP events); bit 1 ->
+ *         Krylov grid (kernel x threads x blocks, by the time of a damped Newton
+ *         solve of problem p from u = 0 to 1e-10 with Eisenstat-Walker forcing,
+ *         the second of two per candidate; p must then be non-NULL).
  *   best (host, nullable) receives the chosen shape; best_us (host [2], nullable)
- *   the chosen action launch time and the chosen Krylov grid's iteration time in
- *   microseconds.
- * Overwrites the handle's solver workspace.  Synchronises the stream. */
+ *   the chosen action launch time and, for the chosen grid, the Newton solve
+ *   time per Krylov iteration in microseconds.
+ * Overwrites the handle's solver workspace; allocates (and frees) one
+ * temporary iterate.  Synchronises the stream. */
 int egfem_autotune(egfem_tensor_t T, const egfem_problem* p, int what, egfem_launch_shape* best,
                    double* best_us, void* stream);
 

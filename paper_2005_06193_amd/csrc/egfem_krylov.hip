@@ -114,6 +114,26 @@ __global__ __launch_bounds__(NT) void k_bicgstab_ov(LaunchArgs P) {
   write_out(P, o);
 }
 
+// Overlapped block-Jacobi conjugate gradients (same arrangement).
+template <int NT>
+__global__ __launch_bounds__(NT) void k_pcg_ov(LaunchArgs P) {
+  __shared__ double sh[dev::kShWords<NT>];
+  __shared__ int sh_state[2];
+  if (threadIdx.x == 0) sh_state[1] = 0;
+  dev::AggRed ar{blockIdx.x, gridDim.x - 1, P.ov.salt, P.ov.part, P.ov.tot, P.ov.exit_word,
+                 P.ctrl + dev::kCtrlAbort};
+  if (blockIdx.x == gridDim.x - 1) {
+    dev::agg_serve<NT>(ar);
+    return;
+  }
+  const int rb = P.krow[blockIdx.x], re = P.krow[blockIdx.x + 1];
+  const dev::KOut o = dev::team_pcg_ov<NT, kResidentRow>(ar, P.A, P.ov, rb, re, sh, sh_state);
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    __hip_atomic_store(P.ov.exit_word, (uint64_t)dev::ll_flag(P.ov.salt, dev::kLLEpochMask) << 32,
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  write_out(P, o);
+}
+
 template <int NT, int K>
 __global__ __launch_bounds__(NT) void k_pcg_reg(LaunchArgs P) {
   EGFEM_TEAM_PROLOGUE();
@@ -381,10 +401,13 @@ int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, con
   const bool resident = block || (resident_ok && W.krow_maxrows <= NT);
   // the overlapped block-Jacobi BiCGStab (flag-in-data synchronisation) where
   // the block preconditioner runs, unless the shape asks for the barrier form
-  const void* kov = (method == KrylovMethod::kBiCGStab && block && T->krylov_kernel == 0 &&
-                     W.crow_maxghost <= NT && W.ckext)
-                        ? (NT == 256 ? (const void*)k_bicgstab_ov<256> : (const void*)k_bicgstab_ov<512>)
-                        : nullptr;
+  const void* kov = nullptr;
+  if (block && T->krylov_kernel == 0 && W.crow_maxghost <= NT && W.ckext) {
+    if (method == KrylovMethod::kBiCGStab)
+      kov = NT == 256 ? (const void*)k_bicgstab_ov<256> : (const void*)k_bicgstab_ov<512>;
+    else
+      kov = NT == 256 ? (const void*)k_pcg_ov<256> : (const void*)k_pcg_ov<512>;
+  }
   const bool overlapped = kov && G + 1 <= coresident(kov, NT);   // plus the aggregating workgroup
   // Flagged words of the overlapped kernel: the published vectors [3][n][2]
   // and the reduction words (partials [2][4][2][kMaxKrylovBlocks], totals, exit

@@ -528,5 +528,197 @@ __device__ KOut team_bicgstab_ov(AggRed& ar, const KArgs& A, const OvArgs& O, in
   return o;
 }
 
+// Preconditioned conjugate gradients (Chronopoulos and Gear: one reduction
+// per iteration) in the same arrangement: with u = M^-1 r and w = J u,
+//   w = J u (LDS)                    arrive (r,u) (w,u) (r,r);  wh = M^-1 w;  publish wh;
+//                                    wait -> alpha, beta;  ghosts' wh
+//   p = u + beta p;  s = w + beta s;  x += alpha p;  r -= alpha s;
+//   sh = wh + beta sh (= M^-1 s);  u -= alpha sh (= M^-1 r)   (own rows and ghosts)
+// so the block operator is applied inside the reduction's window and the
+// ghosts' u follows their owners' recurrences bitwise.  The recurrence for u
+// drifts from M^-1 r by rounding, which matters once r is small (gamma =
+// (r, u) then loses its sign): below ||r|| <= kCgExact ||r_ref|| every
+// iteration forms u = M^-1 r explicitly after the reduction and publishes it
+// for the ghosts.  Stops when ||r|| <= rtol ||r0|| (rel_r0) or rtol ||b||; a
+// non-positive curvature or gamma reports EGFEM_BREAKDOWN.
+constexpr double kCgExact = 1e-7;
+template <int NT, int K>
+__device__ KOut team_pcg_ov(AggRed& ar, const KArgs& A, const OvArgs& O, int rb, int re, double* sh,
+                            int* sh_state) {
+  static_assert(NT / kWave >= kAggValues, "reductions carry kAggValues values");
+  constexpr int LX = 2 * NT + 1;
+  __shared__ double xu[LX];
+  __shared__ double cheb_lds[4 * (NT + 1)];
+  unsigned* const abort_word = ar.abort_word;
+  double red[kMaxRed];
+  KOut o{EGFEM_NOT_CONVERGED, 0, 0.0, 0.0, false};
+#define EGFEM_ZERO_RED() for (int q_ = 0; q_ < kMaxRed; ++q_) red[q_] = 0.0
+  const int tid = (int)threadIdx.x;
+  const int i = rb + tid;
+  const bool own = i < re;
+  const int q = max(min(i, re - 1), 0);
+  const int row = A.rlist[q];
+  const int64_t n = A.n;
+  int px[K], li[K];
+  double aa[K];
+  const int beg = A.rowptr[row], end = A.rowptr[row + 1];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int s = min(beg + k, end - 1);
+    const bool real = own && beg + k < end;
+    const int c = A.col[s];
+    const int l = O.kext[s];
+    px[k] = real ? (l >= 0 ? l : NT + 1 + (-1 - l)) : NT;
+    li[k] = (real && l >= 0 && c != row) ? l : NT;
+    aa[k] = real ? A.val[s] : 0.0;
+  }
+  double ad = 0.0;
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (px[k] == tid && own) ad = aa[k];
+  double ab[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) ab[k] = li[k] < NT ? aa[k] : 0.0;
+  const double d = A.dinv[row];
+  const double b = own ? A.rhs_scale * A.rhs[row] : 0.0;
+  const int g0 = O.gptr[blockIdx.x], ng = O.gptr[blockIdx.x + 1] - g0;
+  const bool gown = tid < ng;
+  const unsigned gc = (unsigned)O.gcol[g0 + min(tid, max(ng - 1, 0))];
+  const bool bj = A.cheb_steps > 0;
+  ChebParams cp{1.0, 1.0, 1.0};
+  if (bj) {
+    cp = cheb_params<NT, K>(li, ab, ad, d, cheb_lds);
+    if (threadIdx.x < 4) cheb_lds[(threadIdx.x >> 1) * 2 * (NT + 1) + (threadIdx.x & 1) * (NT + 1) + NT] = 0.0;
+  }
+  if (threadIdx.x == 0) xu[NT] = 0.0;
+  uint64_t* const llu = O.llv;                      // initial u
+  uint64_t* const llw = O.llv + 2 * (size_t)n;      // wh
+  unsigned ep = 0;
+  double x = 0.0, r = b;
+  if (!A.x_zero) {
+    x = own ? A.x[row] : 0.0;
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc = fma(aa[k], A.x[A.col[min(beg + k, end - 1)]], acc);
+    if (own) r = b - acc;
+  }
+  double u;
+  {
+    const double xs[1] = {r};
+    double zs[1];
+    ov_prec<NT, K, 1>(li, ab, ad, d, own, A.cheb_steps, cp, cheb_lds, xs, zs);
+    u = own ? zs[0] : 0.0;
+  }
+  ++ep;
+  xu[tid] = u;
+  if (own) ll_store(llu + 2 * (size_t)row, u, ll_flag(O.salt, ep));
+  double gu = 0.0, gs = 0.0;   // this thread's ghost: u and sh
+  EGFEM_ZERO_RED();
+  red[0] = b * b;
+  agg_arrive<NT>(ar, red, 1, sh);
+  {
+    GhostWords w;
+    if (ng > 0) ghost_load(llu, gc, w);
+    const bool gab = ng > 0 && ghost_wait(llu, gc, ll_flag(O.salt, ep), w, abort_word);
+    if ((o.abort = agg_wait<NT>(ar, red, 1, sh, sh_state))) return o;
+    if ((o.abort = wg_any(gab, &sh_state[1]))) return o;
+    if (gown) {
+      gu = ll_value(w.lo, w.hi);
+      xu[NT + 1 + tid] = gu;
+    }
+    lds_barrier();
+  }
+  const double bnorm = sqrt(red[0]);
+  double ref = bnorm, gamma_prev = 0.0, alpha_prev = 0.0, rnorm = 0.0;
+  double p = 0.0, sv = 0.0, shv = 0.0;
+  int it = 0;
+  bool exact = false;   // u = M^-1 r formed explicitly (uniform over the team)
+  while (true) {
+    double wv = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) wv = fma(aa[k], xu[px[k]], wv);
+    EGFEM_ZERO_RED();
+    if (own) {
+      red[0] = r * u;
+      red[1] = wv * u;
+      red[2] = r * r;
+    }
+    agg_arrive<NT>(ar, red, 3, sh);
+    double wh = 0.0;
+    GhostWords ww;
+    unsigned fw = 0;
+    if (!exact) {
+      const double xs[1] = {wv};
+      double zs[1];
+      ov_prec<NT, K, 1>(li, ab, ad, d, own, A.cheb_steps, cp, cheb_lds, xs, zs);
+      wh = own ? zs[0] : 0.0;
+      ++ep;
+      fw = ll_flag(O.salt, ep);
+      if (own) ll_store(llw + 2 * (size_t)row, wh, fw);
+      if (ng > 0) ghost_load(llw, gc, ww);
+    }
+    if ((o.abort = agg_wait<NT>(ar, red, 3, sh, sh_state))) break;
+    if (!exact) {
+      const bool gab = ng > 0 && ghost_wait(llw, gc, fw, ww, abort_word);
+      if ((o.abort = wg_any(gab, &sh_state[1]))) break;
+    }
+    const double gamma = red[0], delta = red[1];
+    rnorm = sqrt(red[2]);
+    if (it == 0 && A.rel_r0) ref = rnorm;
+    if (!isfinite(rnorm) || !isfinite(gamma) || !isfinite(delta)) { o.status = EGFEM_NONFINITE; break; }
+    if (rnorm <= A.rtol * ref) { o.status = EGFEM_OK; break; }
+    if (it >= A.max_iter) { o.status = EGFEM_NOT_CONVERGED; break; }
+    const double beta = it == 0 ? 0.0 : gamma / gamma_prev;
+    const double den = it == 0 ? delta : delta - beta * gamma / alpha_prev;
+    if (!(den > 0.0) || !(gamma > 0.0)) { o.status = EGFEM_BREAKDOWN; break; }
+    const double alpha = gamma / den;
+    p = fma(beta, p, u);
+    sv = fma(beta, sv, wv);
+    x = fma(alpha, p, x);
+    r = fma(-alpha, sv, r);
+    if (!own) r = 0.0;
+    if (!exact && rnorm <= kCgExact * ref) exact = true;   // from this update on
+    if (!exact) {
+      shv = fma(beta, shv, wh);
+      u = own ? fma(-alpha, shv, u) : 0.0;
+      xu[tid] = u;
+      if (gown) {
+        const double gw = ll_value(ww.lo, ww.hi);
+        gs = fma(beta, gs, gw);
+        gu = fma(-alpha, gs, gu);
+        xu[NT + 1 + tid] = gu;
+      }
+    } else {
+      // u = M^-1 r, published for the ghosts
+      const double xs[1] = {r};
+      double zs[1];
+      ov_prec<NT, K, 1>(li, ab, ad, d, own, A.cheb_steps, cp, cheb_lds, xs, zs);
+      u = own ? zs[0] : 0.0;
+      ++ep;
+      const unsigned fu = ll_flag(O.salt, ep);
+      if (own) ll_store(llu + 2 * (size_t)row, u, fu);
+      xu[tid] = u;
+      GhostWords wu;
+      if (ng > 0) ghost_load(llu, gc, wu);
+      const bool gab = ng > 0 && ghost_wait(llu, gc, fu, wu, abort_word);
+      if ((o.abort = wg_any(gab, &sh_state[1]))) break;
+      if (gown) {
+        gu = ll_value(wu.lo, wu.hi);
+        xu[NT + 1 + tid] = gu;
+      }
+    }
+    gamma_prev = gamma;
+    alpha_prev = alpha;
+    ++it;
+    lds_barrier();
+  }
+#undef EGFEM_ZERO_RED
+  if (!o.abort && own) A.x[row] = x;
+  o.iters = it;
+  o.rnorm = rnorm;
+  o.bnorm = ref;
+  return o;
+}
+
 }  // namespace dev
 }  // namespace egfem

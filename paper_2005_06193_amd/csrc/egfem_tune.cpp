@@ -2,6 +2,7 @@
 // events on the handle's own tensor and the fastest is kept in the handle.
 #include <algorithm>
 #include <cfloat>
+#include <chrono>
 #include <cmath>
 #include <vector>
 
@@ -124,17 +125,20 @@ int egfem_autotune(egfem_tensor_t T, const egfem_problem* p, int what, egfem_lau
     us_action = best_t;
   }
   if (what & 2) {
-    // DF at u = 0 of the problem, right-hand side 1 on the free rows: the time
-    // per decade of residual reduction of a BiCGStab solve to 1e-8 (the block
-    // preconditioner trades cost per iteration against iterations)
-    EGFEM_HIP_CHECK(launch_fill(W.utry, 0.0, T->n, st));
-    EGFEM_HIP_CHECK(launch_jacobian(T, W.utry, nullptr, p->a0, p->a0_const, 1, nullptr, 1, p->add_stiffness,
-                                    p->dirichlet, W.jval, W.dinv, st));
-    EGFEM_HIP_CHECK(launch_fill(W.rhs, 1.0, T->n, st));
-    EGFEM_HIP_CHECK(launch_mask_zero(W.rhs, p->dirichlet, T->n, st));
+    // The online workload itself: a damped Newton solve of problem p from
+    // u = 0 to 1e-10 with Eisenstat-Walker forcing, timed per candidate grid
+    // (kernel x workgroup size x workgroups; the second of two solves).
+    double* u = nullptr;
+    if (hipMalloc((void**)&u, std::max<int64_t>(T->n, 1) * sizeof(double)) != hipSuccess)
+      return fail(EGFEM_ERR_OOM, "hipMalloc of the autotuner's iterate failed");
+    egfem_newton_opts o;
+    egfem_newton_opts_default(&o);
+    o.tol = 1e-10;
+    o.forcing = 1;
+    const int keep_kernel = T->krylov_kernel, keep_blocks = T->tuned_krylov_blocks,
+              keep_threads = T->tuned_krylov_threads;
     double best_t = DBL_MAX, best_iter_us = 0.0;
-    int bb = 0, bt = 0, bk = 0;
-    const int keep_kernel = T->krylov_kernel;
+    int bb = keep_blocks, bt = keep_threads, bk = keep_kernel;
     for (int kernel : {0, 1})
       for (int threads : {256, 512, 1024})
         // fixed grids and the smallest grid that keeps one row per thread
@@ -142,25 +146,46 @@ int egfem_autotune(egfem_tensor_t T, const egfem_problem* p, int what, egfem_lau
         for (int blocks : {32, 64, 128, 256, 512, 1024,
                            (int)std::min<int64_t>((T->n + threads - 1) / threads, kMaxKrylovBlocks)}) {
           T->krylov_kernel = kernel;
-          KrylovResult kr;
-          rc = krylov_bicgstab(T, W.jval, W.dinv, W.rhs, 1.0, W.delta, true, 1e-8, 3000, blocks, &kr, st,
-                               nullptr, true, threads);
-          if (rc != EGFEM_OK) {
-            T->krylov_kernel = keep_kernel;
-            return rc;
+          T->tuned_krylov_blocks = blocks;
+          T->tuned_krylov_threads = threads;
+          double t_solve = 0.0;
+          egfem_newton_stats stt;
+          bool usable = true;
+          for (int rep = 0; rep < 2 && usable; ++rep) {
+            if (launch_fill(u, 0.0, T->n, st) != hipSuccess) {
+              rc = fail(EGFEM_ERR_HIP, "fill of the autotuner's iterate failed");
+              break;
+            }
+            const auto t0 = std::chrono::steady_clock::now();
+            const int src = egfem_newton(T, p, u, &o, &stt, stream);
+            const auto t1 = std::chrono::steady_clock::now();
+            if (src < 0) {
+              rc = src;
+              break;
+            }
+            t_solve = std::chrono::duration<double, std::milli>(t1 - t0).count();
+            // a converged solve only; the register-resident kernel only where it ran
+            // (elsewhere it repeats kernel 1)
+            usable = src == EGFEM_OK && !(kernel == 0 && !(stt.krylov_kernels & 1));
           }
-          // the register-resident kernel only where it applies (else it repeats kernel 1)
-          if (kr.iters <= 0 || (kernel == 0 && !kr.resident)) continue;
-          if (!(kr.relres > 0.0 && kr.relres < 1.0)) continue;
-          const double per_decade = kr.kernel_ms / -std::log10(kr.relres);
-          if (per_decade < best_t) {
-            best_t = per_decade;
-            best_iter_us = 1000.0 * kr.kernel_ms / kr.iters;
-            bb = kr.blocks;
-            bt = kr.threads;
+          if (rc != EGFEM_OK) break;
+          if (!usable || stt.krylov_iters <= 0) continue;
+          if (t_solve < best_t) {
+            best_t = t_solve;
+            best_iter_us = 0.0;
+            bb = blocks;
+            bt = threads;
             bk = kernel;
+            best_iter_us = 1000.0 * t_solve / stt.krylov_iters;
           }
         }
+    hipFree(u);
+    if (rc != EGFEM_OK) {
+      T->krylov_kernel = keep_kernel;
+      T->tuned_krylov_blocks = keep_blocks;
+      T->tuned_krylov_threads = keep_threads;
+      return rc;
+    }
     T->tuned_krylov_blocks = bb;
     T->tuned_krylov_threads = bt;
     T->krylov_kernel = bk;

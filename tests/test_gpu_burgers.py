@@ -68,7 +68,7 @@ def test_burgers_other_meshes(name, group):
     assert relerr(host(u), uo) < 1e-11
 
 
-@pytest.mark.parametrize("kernel,precond", [(0, 8), (0, 0), (1, 8)])
+@pytest.mark.parametrize("kernel,precond", [(0, 8), (0, 0), (1, 8), (2, 8)])
 def test_burgers_krylov_kernels_and_determinism(kernel, precond):
     b = W.burgers_2d(32, dt=2e-2)
     T = eg().Tensor.from_mesh(b.mesh, W.FORM_CONV)
@@ -80,7 +80,7 @@ def test_burgers_krylov_kernels_and_determinism(kernel, precond):
     s1 = T.burgers(u1, dirm, src, o)
     u2 = dt(b.u0)
     s2 = T.burgers(u2, dirm, src, o)
-    assert s1.status == 0 and s1.krylov_kernels == ((5 if precond else 1) if kernel == 0 else 2)
+    assert s1.status == 0 and s1.krylov_kernels == {(0, 8): 13, (0, 0): 1, (1, 8): 2, (2, 8): 5}[(kernel, precond)]
     assert torch.equal(u1, u2) and s1.krylov_hist == s2.krylov_hist
     assert s1.t_krylov_ms > 0.0 and s1.t_rhs_ms > 0.0
     uo = _oracle(b.mesh, b.u0, b.source, b.dt, b.nu, b.steps, False)

@@ -362,9 +362,10 @@ def test_newton_coarse_correction_stats():
     assert relerr(sols[1], sols[0]) < 1e-8
 
 
+@pytest.mark.parametrize("kernel", [0, 2])
 @pytest.mark.parametrize("precond", [0, 8, 32])
 @pytest.mark.parametrize("mesh", list(BJ_MESHES))
-def test_cg_block_preconditioner(mesh, precond):
+def test_cg_block_preconditioner(mesh, precond, kernel):
     """Conjugate gradients with the block-Jacobi preconditioner (symmetric
     positive definite for the SPD matrix DF(0) = K with identity Dirichlet
     rows) against SuperLU, on several grids; deterministic; fewer iterations
@@ -387,8 +388,8 @@ def test_cg_block_preconditioner(mesh, precond):
         if blocks and (T.n + blocks - 1) // blocks > 1024:
             continue
         for pc in sorted({0, precond}):
-            print(f"cg block-Jacobi mesh={mesh} precond={pc} grid={blocks}x{threads}", flush=True)
-            T.set_shape(krylov_precond=pc, krylov_blocks=blocks, krylov_threads=threads)
+            print(f"cg block-Jacobi mesh={mesh} precond={pc} kernel={kernel} grid={blocks}x{threads}", flush=True)
+            T.set_shape(krylov_precond=pc, krylov_blocks=blocks, krylov_threads=threads, krylov_kernel=kernel)
             x, st, its, rr = T.solve_cg(jv, dt(rhs), rtol=1e-12)
             assert st == 0, (st, its, rr)
             res = relerr(A @ host(x), rhs)

@@ -75,10 +75,12 @@ def test_picard_matches_oracle(name):
     assert st.res <= 1e-10 * st.res0
 
 
-@pytest.mark.parametrize("kernel,precond", [(0, 8), (0, 0), (1, 8)])
+@pytest.mark.parametrize("kernel,precond", [(0, 8), (0, 0), (1, 8), (2, 8)])
 def test_picard_krylov_kernels(kernel, precond):
-    """Resident CG with the block-Jacobi or the Jacobi preconditioner, and the
-    streaming CG (Jacobi): the same Picard fixed point."""
+    """Resident CG with the block-Jacobi preconditioner (overlapped form,
+    kernel 0, or barrier form, kernel 2) or the Jacobi preconditioner, and the
+    streaming CG (Jacobi): the same Picard fixed point; the statistics name
+    the kernel (bit 3: overlapped form)."""
     wl = W.nonlinear_diffusion_2d(40, seed=55)
     T = eg().Tensor.from_mesh(wl.mesh, wl.form)
     T.set_shape(krylov_kernel=kernel, krylov_precond=precond)
@@ -86,7 +88,7 @@ def test_picard_krylov_kernels(kernel, precond):
     u = torch.zeros(T.n, dtype=torch.float64, device=DEV)
     st = T.picard(p, u, eg().PicardOptions(tol=1e-13), warn=False)
     assert st.status == 0
-    assert st.krylov_kernels == ((5 if precond else 1) if kernel == 0 else 2)
+    assert st.krylov_kernels == {(0, 8): 13, (0, 0): 1, (1, 8): 2, (2, 8): 5}[(kernel, precond)]
     un, _ = O.newton(O.build_problem(wl), tol=1e-14)
     assert relerr(host(u), un) <= 1e-10
 
