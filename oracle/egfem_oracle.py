@@ -38,7 +38,8 @@ Finite Element Method", arXiv 2005.06193):
 * Sec. 5.2, Burgers' equation: the convection tensor
   N_ijk = int phi_k phi_j (d_1 + d_2) phi_i and the semi-implicit time step
   (M + dt nu K) u^{n+1} = M u^n + dt (1/2 N:(u^n (x) u^n) + d^{n+1}), in the
-  tensor and the group (N^f (u . u)) formulations.
+  tensor and the group (N^f (u . u)) formulations, the latter also with
+  W_h = P2 and W_h = I_k (f = (Pi_u u)^2 at the P2 dofs or the points).
 
 Integrals use numerical quadrature on the reference simplex (collapsed Gauss-
 Legendre product rules generated here), assembled element by element.  Linear
@@ -788,8 +789,9 @@ def iq_space(coords, cells) -> IQSpace:
 
 
 def tensor_iq(coords, cells, form: int, drop_rel: float = DROP_REL):
-    """T_ijk = w_q |e| grad phi_j . grad phi_i (x_q)   (stiffness) or
-    T_ijk = w_q |e| phi_j(x_q) phi_i(x_q)               (mass), k = (e, q):
+    """T_ijk = w_q |e| grad phi_j . grad phi_i (x_q)       (stiffness),
+    T_ijk = w_q |e| phi_j(x_q) phi_i(x_q)                   (mass), or
+    T_ijk = w_q |e| phi_j(x_q) sum_d d_d phi_i              (convection, Sec. 5.2), k = (e, q):
     the trilinear forms with eta_k the quadrature functional at x_q.  Returns
     (tensor with n = n_w, space)."""
     W = iq_space(coords, cells)
@@ -803,6 +805,11 @@ def tensor_iq(coords, cells, form: int, drop_rel: float = DROP_REL):
     elif form == FORM_MASS:
         LL = np.einsum("q,qa,qb->abq", W.wts, W.lam, W.lam)
         Te = vol[:, None, None, None] * LL[None]
+    elif form == FORM_CONV:
+        gsum = G.sum(axis=2)                                 # sum_d d_d phi_a, [E, d+1]
+        gsum[np.abs(gsum) <= 1e-12 * np.abs(G).sum(axis=2)] = 0.0
+        LW = np.einsum("q,qb->bq", W.wts, W.lam)             # w_q phi_b(x_q)
+        Te = vol[:, None, None, None] * gsum[:, :, None, None] * LW[None, None]
     else:
         raise ValueError("unknown form")
     ai, bi, qi = np.meshgrid(np.arange(nl), np.arange(nl), np.arange(Q), indexing="ij")
@@ -1023,6 +1030,18 @@ def burgers_group_p2(coords, cells):
     return Nf, W
 
 
+def burgers_group_iq(coords, cells):
+    """EGFEM group matrix with W_h = I_k (the quadrature-point space; Sec. 5.2
+    compares EGFEM(I_3)): N^f_ik = w_q |e| sum_d d_d phi_i for k = (e, q), the I_k
+    convection tensor summed over j (partition of unity), with f = (Pi_u u)^2
+    at the points.  Returns (N^f [n, n_w], space); burgers() takes it as
+    group_p2 (any (N^f, space) pair with the space's Pi)."""
+    T, W = tensor_iq(coords, cells, FORM_CONV)
+    n = coords.shape[0]
+    Nf = sp.coo_matrix((T.v, (T.i, T.k)), shape=(n, W.n_w)).tocsr()
+    return Nf, W
+
+
 def burgers(sysm: BurgersSystem, u0: np.ndarray, source: Optional[np.ndarray], steps: int,
             group: bool = False, history: bool = False, group_p2=None):
     """Semi-implicit Euler steps of Sec. 5.2,
@@ -1032,7 +1051,8 @@ def burgers(sysm: BurgersSystem, u0: np.ndarray, source: Optional[np.ndarray], s
         C(u) = N^f (u . u)         (group formulation: u^2 interpolated onto P1),
     load d^{n+1} = M s^{n+1} for the nodal source values s^{n+1} = source[n]
     (source None: no source), zero Dirichlet data; with group_p2 = (N^f, space)
-    from burgers_group_p2 the group formulation uses W_h = P2 instead.  Each
+    from burgers_group_p2 (or burgers_group_iq) the group formulation uses
+    W_h = P2 (or I_k) instead.  Each
     linear system is solved directly (one LU factorisation of the constant
     matrix).  Returns u^steps, or the list [u^0, ..., u^steps] with history=True."""
     u = np.array(u0, dtype=np.float64, copy=True)
@@ -1041,7 +1061,7 @@ def burgers(sysm: BurgersSystem, u0: np.ndarray, source: Optional[np.ndarray], s
     out = [u.copy()] if history else None
     for n in range(steps):
         if group_p2 is not None:
-            # EGFEM with W_h = P2: f = (Pi_u u)^2 at the P2 dofs
+            # EGFEM with W_h = P2 (or I_k): f = (Pi_u u)^2 at the dofs of W_h
             Nf2, W2 = group_p2
             pu = W2.Pi @ u
             conv = Nf2 @ (pu * pu)

@@ -831,3 +831,60 @@ def test_burgers_egfem_p2_is_exact():
     ug = O.burgers(sy, b.u0, b.source, b.steps, group=True)
     assert np.linalg.norm(u2 - ut) <= 1e-13 * np.linalg.norm(ut)
     assert np.linalg.norm(ug - ut) > 1e-6 * np.linalg.norm(ut)
+
+
+def test_burgers_egfem_iq_one_cell_by_hand():
+    """One 1D cell [0, h] with the 2-point Gauss rule: N^f_{i,q} = w_q h phi_i' =
+    -1/2, +1/2 for i = 0, 1 at both points, and with u = (a, b) the group value
+    sum_q N^f_{1,q} u(x_q)^2 is int_0^h u^2 / h = (a^2 + ab + b^2) / 3."""
+    h = 0.3
+    coords = np.array([[0.0], [h]])
+    cells = np.array([[0, 1]])
+    Nf, Wsp = O.burgers_group_iq(coords, cells)
+    assert Wsp.n_w == 2
+    assert np.allclose(Nf.toarray(), [[-0.5, -0.5], [0.5, 0.5]], rtol=0, atol=1e-15)
+    a, b = 0.7, -1.9
+    pu = Wsp.Pi @ np.array([a, b])
+    c = Nf @ (pu * pu)
+    assert abs(c[1] - (a * a + a * b + b * b) / 3.0) <= 1e-15
+    assert abs(c[0] + c[1]) <= 1e-15
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_burgers_egfem_iq_matches_exact_tensor(dim):
+    """The points' rule integrates the quadratic (P1 u)^2 times the constant
+    gradient sum exactly (degree 3 in 1D, 2 in 2D and 3D), so N^f_I (Pi_u u)^2
+    equals the exact rational convection tensor contracted with u (x) u, and
+    the points of one cell carry weights summing to |e| sum_d d_d phi_i."""
+    coords, cells = IRREGULAR[dim]
+    n = coords.shape[0]
+    Te = _exact_tensor(coords, cells, O.FORM_CONV)
+    u = np.random.default_rng(31).uniform(-1, 1, n)
+    c_exact = np.zeros(n)
+    for (i, j, k), v in Te.items():
+        c_exact[i] += float(v) * u[j] * u[k]
+    Nf, Wsp = O.burgers_group_iq(coords, cells)
+    pu = Wsp.Pi @ u
+    c = Nf @ (pu * pu)
+    assert np.abs(c - c_exact).max() <= 1e-14 * np.abs(c_exact).max()
+    Q = Wsp.lam.shape[0]
+    Nd = Nf.toarray()
+    for e, cell in enumerate(cells):
+        verts = [[Fraction(float(x)) for x in coords[v]] for v in cell]
+        grads, vol = _exact_element(verts)
+        for a, i in enumerate(cell):
+            want = float(vol * sum(grads[a]))
+            got = Nd[i, e * Q:(e + 1) * Q].sum()
+            assert abs(got - want) <= 1e-14 * max(1.0, abs(want)), (e, a)
+
+
+def test_burgers_egfem_iq_steps_equal_tensor_formulation():
+    """Exactness carries to the time steps: EGFEM(I_k) reproduces the tensor
+    formulation, while the P1 group formulation differs."""
+    b = W.burgers_2d(16)
+    sy = O.burgers_system(b.mesh.coords, b.mesh.cells, b.mesh.dirichlet, b.dt, b.nu)
+    ut = O.burgers(sy, b.u0, b.source, b.steps)
+    ui = O.burgers(sy, b.u0, b.source, b.steps, group_p2=O.burgers_group_iq(b.mesh.coords, b.mesh.cells))
+    ug = O.burgers(sy, b.u0, b.source, b.steps, group=True)
+    assert np.linalg.norm(ui - ut) <= 1e-13 * np.linalg.norm(ut)
+    assert np.linalg.norm(ug - ut) > 1e-6 * np.linalg.norm(ut)
