@@ -125,7 +125,8 @@ int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords,
  * ascending (smaller vertex id, larger vertex id) order (Sec. 3.1, Case 1;
  * Sec. 3.2 for Pi_u).  With EGFEM_W_IQ, k = e * Q + q runs over the Q points
  * of every cell e (n_w = n_cells * Q) and T_ijk = w_q |e| grad phi_j . grad
- * phi_i (stiffness) or w_q |e| phi_j(x_q) phi_i(x_q) (mass), (Pi_u u)_k =
+ * phi_i (stiffness), w_q |e| phi_j(x_q) phi_i(x_q) (mass) or w_q |e|
+ * phi_j(x_q) sum_d d_d phi_i (convection, for egfem_burgers), (Pi_u u)_k =
  * u_h(x_q) (Sec. 3.1, Case 3).  On such a handle:
  *  - every a / dadu argument of egfem_residual and egfem_jacobian is a vector
  *    over the dofs of W_h (length n_w), and the second Jacobian term becomes
@@ -133,8 +134,8 @@ int egfem_build_tensor(int dim, int64_t n_nodes, const double* coords,
  *  - the problem-level calls (problem residual / Jacobian, Newton, Picard)
  *    use a = Pi_u a0 + (Pi_u u)^2 at the dofs of W_h, a' = 2 Pi_u u;
  *  - egfem_mode3, egfem_adjoint and the batched form return EGFEM_ERR_ARG;
- *    egfem_burgers takes a W_h = P2 convection handle with group = 1 only;
- *    the convection form with EGFEM_W_IQ or EGFEM_W_P0 is EGFEM_ERR_ARG;
+ *    egfem_burgers takes a W_h = P2 or I_k convection handle with group = 1
+ *    only; the convection form with EGFEM_W_P0 is EGFEM_ERR_ARG;
  *  - with EGFEM_W_P0 (k = cell, T_ijk = K^{e_k}_ij or M^{e_k}_ij) the problem-
  *    level calls return EGFEM_ERR_ARG (the coefficient is a function of the
  *    gradient: egfem_picard_grad), and egfem_jacobian takes no dadu.
@@ -430,6 +431,11 @@ int egfem_solve_cg(egfem_tensor_t T, const double* jval, const double* rhs, doub
  *            the EGFEM group formulation, N^f_P2 = int eta_k sum_d d_d phi_i,
  *            (Pi_u u)^2 squared at the P2 dofs; equal to the tensor
  *            formulation up to rounding, since u^2 of a P1 u lies in P2),
+ *     C(u) = N^f_I (Pi_u u)^2                   (group = 1 on a W_h = I_k handle:
+ *            N^f_I,ik = w_q |e| sum_d d_d phi_i for k = (e, q), u_h squared
+ *            at the points; equal to the tensor formulation up to rounding
+ *            where the rule integrates the quadratic u_h^2 exactly, which
+ *            the rules of EGFEM_W_IQ do),
  * with N the EGFEM_FORM_CONV tensor of the handle, s^{n+1} the nodal source
  * values at t_{n+1} (load M s^{n+1}), Dirichlet rows identity with zero right-
  * hand side.  The matrix is constant and symmetric positive definite: it is
@@ -470,7 +476,7 @@ void egfem_burgers_opts_default(egfem_burgers_opts* o);
 /* egfem_burgers: advance u (device [n_nodes], u^0 in, u^steps out; Dirichlet
  * entries are set to 0) by opts->steps semi-implicit steps.  T must be an
  * EGFEM_FORM_CONV handle (its K and M are the stiffness and mass matrices);
- * a W_h = P2 handle needs opts->group = 1 (EGFEM_ERR_ARG otherwise).
+ * a W_h = P2 or I_k handle needs opts->group = 1 (EGFEM_ERR_ARG otherwise).
  *   dirichlet      device uint8 [n_nodes] or NULL (no Dirichlet nodes)
  *   source         device; the nodal source values of step n (n = 0 .. steps-1,
  *                  i.e. at t_{n+1}) start at source + n * source_stride; a
@@ -644,6 +650,18 @@ int egfem_batch_graph_run(egfem_batch_t B, int zero_init, void* stream);
 /* Synchronises the stream and copies per-instance statistics into stats
  * (host array [count]); returns the worst status (largest code). */
 int egfem_batch_stats(egfem_batch_t B, egfem_newton_stats* stats, void* stream);
+/* Batch autotuner: time one eager run of the plan (the second of two, HIP
+ * events on `stream`, every instance started from u = 0) for each candidate
+ * workgroup size {512, 1024} x team weight exponent {1, 1.5, 2} on these
+ * instances and options, and report the fastest whose instances all converge
+ * (EGFEM_OK, or EGFEM_STAGNATED: stopped at the rounding floor of ||F||).  The
+ * solution buffers are overwritten.  best_threads,
+ * best_weight_exp, best_ms (host, nullable) receive the choice, to be passed to
+ * egfem_batch_create (the Python binding caches it by the instance sizes).
+ * EGFEM_ERR_ARG when no candidate converges.  Synchronises the stream. */
+int egfem_batch_autotune(int count, const egfem_tensor_t* Ts, const egfem_problem* ps,
+                         double* const* us, const egfem_newton_opts* o, int* best_threads,
+                         double* best_weight_exp, double* best_ms, void* stream);
 /* Team size (workgroups) given to each instance: host array [count]. */
 int egfem_batch_teams(egfem_batch_t B, int* team_sizes, int* total_workgroups);
 void egfem_batch_destroy(egfem_batch_t B);

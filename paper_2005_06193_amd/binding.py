@@ -182,6 +182,9 @@ EXPORTS = {
     "egfem_batch_stats": (C.c_int, [C.c_void_p, C.POINTER(_Stats), C.c_void_p]),
     "egfem_batch_teams": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "egfem_batch_destroy": (None, [C.c_void_p]),
+    "egfem_batch_autotune": (C.c_int, [C.c_int, C.POINTER(C.c_void_p), C.POINTER(_Problem),
+                                       C.POINTER(C.c_void_p), C.POINTER(_Opts), C.POINTER(C.c_int),
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p]),
     "egfem_get_shape": (C.c_int, [C.c_void_p, C.POINTER(_Shape)]),
     "egfem_set_shape": (C.c_int, [C.c_void_p, C.POINTER(_Shape)]),
     "egfem_autotune": (C.c_int, [C.c_void_p, C.POINTER(_Problem), C.c_int, C.POINTER(_Shape),
@@ -829,6 +832,43 @@ def newton_batched(tensors: Sequence[Tensor], problems: Sequence[Problem],
     rc = load_library().egfem_newton_batched(m, hs, ps, up, C.byref(o), st, _stream())
     _check(rc, allow_positive=True)
     return [NewtonStats.from_c(st[i]) for i in range(m)], rc
+
+
+def batch_autotune(tensors: Sequence[Tensor], problems: Sequence[Problem], us: Sequence[torch.Tensor],
+                   opts: Optional[NewtonOptions] = None, cache: Optional[str] = None) -> dict:
+    """egfem_batch_autotune: the batch plan's workgroup size and team weight by
+    timing; with `cache` (a JSON path) reuse/store the choice keyed by the
+    instances' sizes.  Returns {"threads", "weight_exp", "ms"}."""
+    import json
+    m = len(tensors)
+    if not (m == len(problems) == len(us)) or m == 0:
+        raise EgfemError(EGFEM_ERR_SHAPE, "tensors/problems/us must have equal nonzero length")
+    key = "batch-" + "-".join(f"{t.n}x{t.info.nnz}" for t in tensors)
+    if cache and os.path.exists(cache):
+        with open(cache) as fh:
+            db = json.load(fh)
+        if key in db:
+            return db[key]
+    hs = (C.c_void_p * m)(*[t.handle.value for t in tensors])
+    ps = (_Problem * m)(*[p.c() for p in problems])
+    up = (C.c_void_p * m)(*[_dptr(u, n=t.n) for u, t in zip(us, tensors)])
+    o = (opts or NewtonOptions()).c()
+    thr = C.c_int(0)
+    wexp = C.c_double(0.0)
+    ms = C.c_double(0.0)
+    _check(load_library().egfem_batch_autotune(m, hs, ps, up, C.byref(o), C.byref(thr), C.byref(wexp),
+                                               C.byref(ms), _stream()))
+    res = {"threads": thr.value, "weight_exp": wexp.value, "ms": ms.value}
+    if cache:
+        db = {}
+        if os.path.exists(cache):
+            with open(cache) as fh:
+                db = json.load(fh)
+        db[key] = res
+        os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+        with open(cache, "w") as fh:
+            json.dump(db, fh, indent=1)
+    return res
 
 
 def version() -> str:

@@ -37,7 +37,10 @@ int ensure_workspace(egfem_tensor_s* T) {
     if (rc == EGFEM_OK) rc = dalloc(v, N);
   if (rc == EGFEM_OK) rc = dalloc(&W.jval, S);
   if (rc == EGFEM_OK) rc = dalloc(&W.jvalT, S);
-  if (rc == EGFEM_OK) rc = dalloc(&W.qslot, S);
+  // the Burgers group steps with W_h = P2 or I_k stage f on the n_w dofs here
+  const size_t QS = (T->w2 == 1 || T->w2 == 2) ? std::max(S, (size_t)T->n_w) : S;
+  if (rc == EGFEM_OK) rc = dalloc(&W.qslot, QS);
+  W.qslot_len = (int64_t)QS;
   if (rc == EGFEM_OK) rc = dalloc(&W.partial, (size_t)T->row_blocks);
   if (rc == EGFEM_OK) rc = dalloc(&W.red, (size_t)kRedSlots * 8 * kMaxKrylovBlocks);
   if (rc == EGFEM_OK) rc = dalloc(&W.ctrl, kCtrlWordsMax);
@@ -50,7 +53,7 @@ int ensure_workspace(egfem_tensor_s* T) {
   if (rc == EGFEM_OK && hipHostMalloc((void**)&W.host_kout, 4 * sizeof(double), 0) != hipSuccess)
     rc = fail(EGFEM_ERR_OOM, "hipHostMalloc failed");
   if (rc != EGFEM_OK) return rc;
-  T->device_bytes += (int64_t)((15 * N + 3 * S + T->row_blocks + (size_t)kRedSlots * 8 * kMaxKrylovBlocks + 4) *
+  T->device_bytes += (int64_t)((15 * N + 2 * S + QS + T->row_blocks + (size_t)kRedSlots * 8 * kMaxKrylovBlocks + 4) *
                                    sizeof(double) + (kMaxKrylovBlocks + 1) * 4 + kCtrlWordsMax * 4 +
                                (int64_t)kMaxKrylovBlocks * (kMaxNbrLists + 1) * 4);
   W.krow_blocks = 0;
@@ -638,10 +641,12 @@ int egfem_burgers(egfem_tensor_t T, const uint8_t* dirichlet, const double* sour
                   double* u, const egfem_burgers_opts* o, egfem_burgers_stats* s, void* stream) {
   if (!T || !u) return fail(EGFEM_ERR_ARG, "null argument");
   if (T->form != EGFEM_FORM_CONV) return fail(EGFEM_ERR_ARG, "Burgers steps need an EGFEM_FORM_CONV tensor");
-  // W_h = P2: the group formulation with f = (Pi_u u)^2 at the P2 dofs (EGFEM)
-  const bool egfem_p2 = (T->w2 == 1);
-  if (egfem_p2 && !(o && o->group == 1))
-    return fail(EGFEM_ERR_ARG, "a W_h = P2 convection tensor takes the group formulation (group = 1)");
+  // W_h = P2 or I_k: the group formulation with f = (Pi_u u)^2 at the dofs of
+  // W_h (the P2 dofs, or the points of the rule)
+  const bool egfem_w = (T->w2 == 1 || T->w2 == 2);
+  if (T->w2 == 3) return fail(EGFEM_ERR_ARG, "no Burgers steps with W_h = P0");
+  if (egfem_w && !(o && o->group == 1))
+    return fail(EGFEM_ERR_ARG, "a W_h = P2 or I_k convection tensor takes the group formulation (group = 1)");
   egfem_burgers_opts opts;
   egfem_burgers_opts_default(&opts);
   if (o) opts = *o;
@@ -652,11 +657,11 @@ int egfem_burgers(egfem_tensor_t T, const uint8_t* dirichlet, const double* sour
        opts.krylov_threads != 1024))
     return fail(EGFEM_ERR_ARG, "invalid Burgers options");
   if (source && source_stride < 0) return fail(EGFEM_ERR_ARG, "source_stride must be >= 0");
-  // (Pi_u u)^2 is staged in the slot-sized scratch vector
-  if (egfem_p2 && T->n_w > T->slots) return fail(EGFEM_ERR_SHAPE, "P2 dofs exceed the slot scratch");
   int rc = ensure_workspace(T);
   if (rc != EGFEM_OK) return rc;
   Workspace& W = T->ws;
+  // (Pi_u u)^2 is staged in the scratch vector sized for the dofs of W_h
+  if (egfem_w && T->n_w > W.qslot_len) return fail(EGFEM_ERR_SHAPE, "dofs of W_h exceed the staging scratch");
   hipStream_t st = (hipStream_t)stream;
   egfem_burgers_stats stats;
   std::memset(&stats, 0, sizeof(stats));
@@ -666,7 +671,7 @@ int egfem_burgers(egfem_tensor_t T, const uint8_t* dirichlet, const double* sour
   // offline part of the run: M + dt nu K (Dirichlet identity rows, zero
   // columns) and its inverse diagonal; N^f = N contracted with 1 in j
   EGFEM_HIP_CHECK(launch_mk_combine(T, 1.0, opts.dt * opts.nu, dirichlet, W.jval, W.dinv, st));
-  if (egfem_p2) {
+  if (egfem_w) {
     EGFEM_HIP_CHECK(launch_fill(W.z, 1.0, T->n, st));      // u_j = 1 in the raw action gives N^f
   } else if (opts.group) {
     EGFEM_HIP_CHECK(launch_fill(W.utry, 1.0, T->n, st));
@@ -678,14 +683,18 @@ int egfem_burgers(egfem_tensor_t T, const uint8_t* dirichlet, const double* sour
   for (; n < opts.steps; ++n) {
     const double* src = source ? source + (int64_t)n * source_stride : nullptr;
     if ((rc = tm.start()) != EGFEM_OK) return rc;
-    if (egfem_p2) {
-      // N^f_P2 (Pi_u u)^2: f in W.qslot (slots >= P2 dofs), raw action with u = 1
-      EGFEM_HIP_CHECK(launch_p2_square(T, u, W.qslot, st));
+    if (egfem_w) {
+      // N^f (Pi_u u)^2: f on the dofs of W_h in W.qslot, raw action with u = 1
+      if (T->w2 == 1) {
+        EGFEM_HIP_CHECK(launch_p2_square(T, u, W.qslot, st));
+      } else {
+        EGFEM_HIP_CHECK(launch_iq_square(T, u, W.qslot, st));
+      }
       EGFEM_HIP_CHECK(launch_action_raw(T, W.z, W.qslot, W.F, st));
     } else if (!opts.group) {
       EGFEM_HIP_CHECK(launch_action_raw(T, u, u, W.F, st));
     }
-    const bool slot_group = opts.group && !egfem_p2;
+    const bool slot_group = opts.group && !egfem_w;
     EGFEM_HIP_CHECK(launch_burgers_rhs(T, slot_group, u, src, opts.dt, slot_group ? W.qslot : W.F, dirichlet,
                                        W.rhs, st));
     if ((rc = tm.stop(&stats.t_rhs_ms, &n_dummy)) != EGFEM_OK) return rc;

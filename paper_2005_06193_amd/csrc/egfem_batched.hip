@@ -8,6 +8,7 @@
 // with fused pointwise update, Jacobian emission, Jacobi-BiCGStab, line
 // search, convergence test -- runs on the device with team-local barriers.
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -548,6 +549,66 @@ int egfem_batch_teams(egfem_batch_t B, int* team_sizes, int* total_workgroups) {
 }
 
 void egfem_batch_destroy(egfem_batch_t B) { free_batch(B); }
+
+int egfem_batch_autotune(int count, const egfem_tensor_t* Ts, const egfem_problem* ps, double* const* us,
+                         const egfem_newton_opts* o, int* best_threads, double* best_weight_exp, double* best_ms,
+                         void* stream) {
+  using namespace egfem;
+  if (count < 1) return fail(EGFEM_ERR_ARG, "count must be >= 1");
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<egfem_newton_stats> stats((size_t)count);
+  double bt = DBL_MAX;
+  int bthr = 0;
+  double bw = 0.0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  EGFEM_HIP_CHECK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return fail(EGFEM_ERR_HIP, "hipEventCreate failed");
+  }
+  int rc = EGFEM_OK;
+  for (int threads : {512, 1024}) {
+    for (double wexp : {1.0, 1.5, 2.0}) {
+      egfem_batch_t B = nullptr;
+      rc = egfem_batch_create(count, Ts, ps, us, o, threads, wexp, &B);
+      if (rc != EGFEM_OK) break;
+      // a first run warms the handles and the plan; the second is timed
+      bool good = true;
+      float ms = 0.0f;
+      for (int rep = 0; rep < 2 && rc == EGFEM_OK; ++rep) {
+        if (rep == 1 && hipEventRecord(e0, st) != hipSuccess) rc = fail(EGFEM_ERR_HIP, "hipEventRecord failed");
+        if (rc == EGFEM_OK) rc = egfem_batch_run(B, 1, st);
+        if (rc == EGFEM_OK && rep == 1 && hipEventRecord(e1, st) != hipSuccess)
+          rc = fail(EGFEM_ERR_HIP, "hipEventRecord failed");
+        if (rc == EGFEM_OK) {
+          const int worst = egfem_batch_stats(B, stats.data(), st);
+          if (worst < 0) rc = worst;
+        }
+      }
+      // every instance converged, or stopped at the rounding floor of ||F||
+      for (int m = 0; rc == EGFEM_OK && m < count; ++m)
+        good = good && (stats[m].status == EGFEM_OK || stats[m].status == EGFEM_STAGNATED);
+      if (rc == EGFEM_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+        rc = fail(EGFEM_ERR_HIP, "hipEventElapsedTime failed");
+      egfem_batch_destroy(B);
+      if (rc != EGFEM_OK) break;
+      if (good && ms < bt) {
+        bt = ms;
+        bthr = threads;
+        bw = wexp;
+      }
+    }
+    if (rc != EGFEM_OK) break;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc != EGFEM_OK) return rc;
+  if (bthr == 0) return fail(EGFEM_ERR_ARG, "no batch shape converged");
+  if (best_threads) *best_threads = bthr;
+  if (best_weight_exp) *best_weight_exp = bw;
+  if (best_ms) *best_ms = bt;
+  return EGFEM_OK;
+}
 
 int egfem_newton_batched(int count, const egfem_tensor_t* Ts, const egfem_problem* ps, double* const* us,
                          const egfem_newton_opts* o, egfem_newton_stats* stats, void* stream) {

@@ -169,8 +169,8 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
     return fail(EGFEM_ERR_ARG, "unknown form");
   if (wspace != EGFEM_W_P1 && wspace != EGFEM_W_P2 && wspace != EGFEM_W_IQ && wspace != EGFEM_W_P0)
     return fail(EGFEM_ERR_ARG, "unknown W space");
-  if (wspace != EGFEM_W_P1 && wspace != EGFEM_W_P2 && form == EGFEM_FORM_CONV)
-    return fail(EGFEM_ERR_ARG, "the convection form is built with W_h = P1 or P2 only");
+  if (wspace == EGFEM_W_P0 && form == EGFEM_FORM_CONV)
+    return fail(EGFEM_ERR_ARG, "the convection form is built with W_h = P1, P2 or I_k only");
   const bool w2 = (wspace != EGFEM_W_P1);     // a coefficient space with W-slots
   const bool wq = (wspace == EGFEM_W_IQ);
   const bool wcell = (wspace == EGFEM_W_P0);   // one coefficient per cell
@@ -340,6 +340,13 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
         while (c[a] != (int32_t)i) ++a;
         int loc[4];
         for (int b = 0; b < nl; ++b) loc[b] = lidx(c[b]);
+        // sum_d d_d lambda_a (convection form), rounding noise of a zero sum removed
+        double gsum = 0.0, gabs = 0.0;
+        for (int r = 0; r < dim; ++r) {
+          gsum += g.G[a][r];
+          gabs += std::fabs(g.G[a][r]);
+        }
+        if (std::fabs(gsum) <= 1e-12 * gabs) gsum = 0.0;
         for (int b = 0; b < nl; ++b) {
           double gg = 0.0;
           for (int r = 0; r < dim; ++r) gg += g.G[a][r] * g.G[b][r];
@@ -349,7 +356,9 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
           for (int q = 0; q < nq; ++q) {
             double val;
             if (wcell) val = (form == EGFEM_FORM_STIFF) ? kab : g.vol * (a == b ? m2_diag : m2_off);
-            else val = (form == EGFEM_FORM_STIFF) ? qw[q] * kab : qw[q] * g.vol * qlam[q][a] * qlam[q][b];
+            else if (form == EGFEM_FORM_STIFF) val = qw[q] * kab;
+            else if (form == EGFEM_FORM_MASS) val = qw[q] * g.vol * qlam[q][a] * qlam[q][b];
+            else val = qw[q] * g.vol * gsum * qlam[q][b];   // w_q |e| phi_b(x_q) sum_d d_d phi_a
             const size_t idx = (size_t)loc[b] * nw + (size_t)ce * nq + q;
             acc[idx] += val;
             present[idx] = 1;
@@ -804,20 +813,25 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
     }
     if (rc == EGFEM_OK) rc = upload(ep, &T->p2_edges, &bytes);
   }
-  if (wcell) {
-    // the gradient interpolation: vertex ids (padded to 4) and grad lambda_m
-    // (4 x 3 doubles, zero padded) of every cell
+  if (wq || wcell) {
+    // vertex ids of every cell (padded to 4 with the first): the points of
+    // W_h = I_k evaluate Pi_u u from them, W_h = P0 its gradient
     std::vector<int32_t> c4((size_t)n_cells * 4);
-    std::vector<double> gr((size_t)n_cells * 12, 0.0);
     for (int64_t e = 0; e < n_cells; ++e) {
       const int32_t* c = cells + e * nl;
       for (int m = 0; m < 4; ++m) c4[4 * e + m] = c[m < nl ? m : 0];
-      for (int m = 0; m < nl; ++m)
-        for (int r = 0; r < dim; ++r) gr[12 * e + 3 * m + r] = geo[e].G[m][r];
     }
     int32_t* d4 = nullptr;
     if (rc == EGFEM_OK) rc = upload(c4, &d4, &bytes);
     T->e_cell4 = reinterpret_cast<int4*>(d4);
+  }
+  if (wcell) {
+    // the gradient interpolation: grad lambda_m (4 x 3 doubles, zero padded)
+    // of every cell
+    std::vector<double> gr((size_t)n_cells * 12, 0.0);
+    for (int64_t e = 0; e < n_cells; ++e)
+      for (int m = 0; m < nl; ++m)
+        for (int r = 0; r < dim; ++r) gr[12 * e + 3 * m + r] = geo[e].G[m][r];
     if (rc == EGFEM_OK) rc = upload(gr, &T->e_grad, &bytes);
     if (rc == EGFEM_OK) rc = hipMalloc((void**)&T->e_acoef, (size_t)n_cells * sizeof(double)) == hipSuccess
                                 ? EGFEM_OK : fail(EGFEM_ERR_OOM, "hipMalloc of the cell coefficients failed");

@@ -78,7 +78,9 @@ struct Workspace {
   double* partial = nullptr;    // per-workgroup partial sums of the action kernel [row_blocks]
   double* red = nullptr;        // persistent-kernel reduction slots [kRedSlots * 8 * kMaxKrylovBlocks]
   unsigned* ctrl = nullptr;     // barrier counters / epoch / abort flag [kCtrlWordsMax] (device)
-  double* qslot = nullptr;      // per-slot scratch [slots] (mode-3 contraction)
+  double* qslot = nullptr;      // per-slot scratch [qslot_len >= slots] (mode-3 contraction,
+                                //   f on the dofs of W_h in the Burgers group steps)
+  int64_t qslot_len = 0;
   int32_t* krow = nullptr;      // Krylov row partition [kMaxKrylovBlocks + 1]
   int krow_blocks = 0;          // grid size the partition was made for
   int krow_maxrows = 0;         // most rows of one workgroup in that partition
@@ -246,6 +248,7 @@ int launch_sub_mask_norm(int64_t n, double* F, const double* b, const uint8_t* d
 hipError_t launch_axpy(double* out, const double* x, double alpha, const double* y, int64_t n, hipStream_t st);
 // f = (Pi_u u)^2 at the P2 dofs: u_k^2 at the vertices, ((u_x + u_y) / 2)^2 at the edges.
 hipError_t launch_p2_square(const egfem_tensor_s* T, const double* u, double* f, hipStream_t st);
+hipError_t launch_iq_square(const egfem_tensor_s* T, const double* u, double* f, hipStream_t st);
 hipError_t launch_action_elementwise(const egfem_tensor_s* T, const double* u, const double* a, double* r,
                                      hipStream_t st);
 hipError_t launch_action_unique(const egfem_tensor_s* T, const double* u, const double* a, double* r,

@@ -371,6 +371,21 @@ __global__ void k_p2_square(int64_t n, int64_t nw, const int32_t* __restrict__ e
   f[k] = v * v;
 }
 
+// W_h = I_k: f_k = (Pi_u u)(x_k)^2 for the point k = e nq + q, Pi_u u the P1
+// iterate evaluated at the point from its cell's vertices (barycentrics padded
+// with zeros, vertex ids with the first).
+__global__ void k_iq_square(int64_t nw, int nq, const int4* __restrict__ cell4, const double* __restrict__ qlam,
+                            const double* __restrict__ u, double* __restrict__ f) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nw) return;
+  const int64_t e = k / nq;
+  const int q = (int)(k - e * nq);
+  const int4 c = cell4[e];
+  const double* lam = qlam + 4 * q;
+  const double v = fma(lam[3], u[c.w], fma(lam[2], u[c.z], fma(lam[1], u[c.y], lam[0] * u[c.x])));
+  f[k] = v * v;
+}
+
 __global__ void k_axpy_to(double* __restrict__ out, const double* __restrict__ x, double alpha,
                           const double* __restrict__ y, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -646,6 +661,12 @@ int launch_sub_mask_norm(int64_t n, double* F, const double* b, const uint8_t* d
 hipError_t launch_p2_square(const egfem_tensor_s* T, const double* u, double* f, hipStream_t st) {
   hipLaunchKernelGGL(k_p2_square, dim3(grid1d(T->n_w)), dim3(kBlockThreads), 0, st, T->n, T->n_w, T->p2_edges, u,
                      f);
+  return hipGetLastError();
+}
+
+hipError_t launch_iq_square(const egfem_tensor_s* T, const double* u, double* f, hipStream_t st) {
+  hipLaunchKernelGGL(k_iq_square, dim3(grid1d(T->n_w)), dim3(kBlockThreads), 0, st, T->n_w, T->nq, T->e_cell4,
+                     T->qlam, u, f);
   return hipGetLastError();
 }
 

@@ -82,10 +82,10 @@ def test_build_argument_errors():
     tt = np.ascontiguousarray(t, np.int32)
     assert lib.egfem_build_tensor_w(2, 3, cc.ctypes.data, 1, tt.ctypes.data, 0, 5, 0.0, C.byref(out)) == \
         B.EGFEM_ERR_ARG
-    for wsp in (B.W_IQ, B.W_P0):
-        assert lib.egfem_build_tensor_w(2, 3, cc.ctypes.data, 1, tt.ctypes.data, B.FORM_CONV, wsp, 0.0,
-                                        C.byref(out)) == B.EGFEM_ERR_ARG
-        assert "convection" in lib.egfem_last_error().decode()
+    # the convection form exists with W_h = P1, P2 and I_k, not P0
+    assert lib.egfem_build_tensor_w(2, 3, cc.ctypes.data, 1, tt.ctypes.data, B.FORM_CONV, B.W_P0, 0.0,
+                                    C.byref(out)) == B.EGFEM_ERR_ARG
+    assert "convection" in lib.egfem_last_error().decode()
 
 
 def test_build_row_capacity_limit():

@@ -149,3 +149,27 @@ def test_batched_large_team_matches_oracle(threads):
         ug = host(u)
         assert relerr(ug, uo) < 1e-10, wl.name
         assert np.abs(ug - uo).max() <= 1e-10 * np.abs(uo).max(), wl.name
+
+
+def test_batch_autotune_plan_solves_to_oracle(tmp_path):
+    """The library's batch autotuner returns a workgroup size and team weight
+    from its candidates; the plan built with them solves every instance to
+    the oracle's solution; the cached choice is returned without retiming."""
+    E = eg()
+    wls = [W.nonlinear_diffusion_2d(n, seed=200 + n) for n in (10, 21, 33)] + [W.nonlinear_diffusion_1d(40)]
+    Ts, Ps = setup(wls)
+    us = [torch.zeros(T.n, dtype=torch.float64, device=DEV) for T in Ts]
+    opts = E.NewtonOptions(tol=1e-14, max_newton=40, krylov_rtol=1e-14)
+    cache = str(tmp_path / "batch.json")
+    res = E.batch_autotune(Ts, Ps, us, opts, cache=cache)
+    assert res["threads"] in (512, 1024) and res["weight_exp"] in (1.0, 1.5, 2.0) and res["ms"] > 0
+    assert E.batch_autotune(Ts, Ps, us, opts, cache=cache) == res
+    B = E.Batch(Ts, Ps, us, opts, threads=res["threads"], weight_exp=res["weight_exp"])
+    B.run(zero_init=True, graph=True)
+    stats, rc = B.stats()
+    B.close()
+    assert rc in (0, 4)
+    for wl, u, st in zip(wls, us, stats):
+        assert st.status in (0, 4), st.status_name
+        uo, _ = O.newton(O.build_problem(wl), tol=1e-14, max_iter=40)
+        assert relerr(host(u), uo) < 1e-10, wl.name

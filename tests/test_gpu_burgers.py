@@ -228,8 +228,67 @@ def test_burgers_p2_full_size_2d_256_and_rejections():
     assert np.linalg.norm(host(u) - b.u_final) / np.linalg.norm(b.u_final) < 1e-3
     with pytest.raises(eg().EgfemError):
         T.burgers(dt(b.u0), dirm, src, eg().BurgersOptions(group=0))
-    # I_k and P0 spaces have no convection tensor
-    m = W.mesh_2d(6)
-    for wsp in (eg().W_IQ, eg().W_P0):
-        with pytest.raises(eg().EgfemError):
-            eg().Tensor.from_mesh(m, W.FORM_CONV, wspace=wsp)
+    # the P0 space has no convection tensor
+    with pytest.raises(eg().EgfemError):
+        eg().Tensor.from_mesh(W.mesh_2d(6), W.FORM_CONV, wspace=eg().W_P0)
+
+
+@pytest.mark.parametrize("name", list(P2_MESHES))
+def test_burgers_iq_convection_tensor_matches_oracle(name):
+    """The W_h = I_k convection tensor (w_q |e| phi_j(x_q) sum_d d_d phi_i)
+    entry by entry."""
+    m = P2_MESHES[name]()
+    print(f"burgers iq tensor mesh={name}", flush=True)
+    T = eg().Tensor.from_mesh(m, W.FORM_CONV, wspace=eg().W_IQ)
+    To, Wsp = O.tensor_iq(m.coords, m.cells, O.FORM_CONV)
+    assert T.info.wspace == eg().W_IQ and T.info.n_w == Wsp.n_w
+    assert T.info.nnz == To.nnz and T.info.structural_nnz == To.structural_nnz
+    i, j, k, v = T.export()
+    nw = Wsp.n_w
+    kg = (i.astype(np.int64) * nw + j) * nw + k
+    ko = (To.i * nw + To.j) * nw + To.k
+    og, oo = np.argsort(kg), np.argsort(ko)
+    assert np.array_equal(kg[og], ko[oo])
+    assert np.abs(v[og] - To.v[oo]).max() <= 1e-14 * np.abs(To.v).max()
+
+
+@pytest.mark.parametrize("name", ["1d_n16", "2d_jitter_n13", "3d_n3"])
+def test_burgers_iq_group_matches_oracle(name):
+    """EGFEM group formulation with W_h = I_k: N^f_I (Pi u)^2, u_h squared at
+    the points, on the GPU against the oracle's, and against the tensor
+    formulation, which it reproduces (the rules integrate u_h^2 exactly)."""
+    m = P2_MESHES[name]()
+    print(f"burgers iq group mesh={name}", flush=True)
+    steps = 12
+    T = eg().Tensor.from_mesh(m, W.FORM_CONV, wspace=eg().W_IQ)
+    u0, src = _smooth_case(m, 45)
+    u = dt(u0)
+    o = eg().BurgersOptions(dt=0.02, nu=0.3, steps=steps, group=1, krylov_rtol=1e-13)
+    st = T.burgers(u, dt(m.dirichlet, torch.uint8), dt(src), o)
+    assert st.status == 0 and st.steps == steps
+    sy = O.burgers_system(m.coords, m.cells, m.dirichlet, 0.02, 0.3)
+    srcs = np.broadcast_to(src, (steps, m.n_nodes))
+    uo = O.burgers(sy, u0, srcs, steps, group_p2=O.burgers_group_iq(m.coords, m.cells))
+    assert relerr(host(u), uo) < 1e-11
+    ut = O.burgers(sy, u0, srcs, steps, group=False)
+    assert relerr(host(u), ut) < 1e-11
+
+
+def test_burgers_iq_full_size_2d_256_and_rejections():
+    """The 2D 256x256 manufactured run with W_h = I_3 (the 3-point rule)
+    equals the tensor formulation; an I_k convection tensor rejects the slot
+    (P1) group form and the tensor formulation."""
+    print("burgers iq 2d_256 full size", flush=True)
+    b = W.burgers_2d(256)
+    dirm = dt(b.mesh.dirichlet, torch.uint8)
+    src = dt(b.source)
+    T = eg().Tensor.from_mesh(b.mesh, W.FORM_CONV, wspace=eg().W_IQ)
+    assert T.info.n_w == 3 * b.mesh.cells.shape[0]
+    u = dt(b.u0)
+    st = T.burgers(u, dirm, src, eg().BurgersOptions(group=1))
+    assert st.status == 0 and st.steps == 100
+    uo = _oracle(b.mesh, b.u0, b.source, b.dt, b.nu, b.steps, False)
+    assert relerr(host(u), uo) < 1e-9
+    assert np.linalg.norm(host(u) - b.u_final) / np.linalg.norm(b.u_final) < 1e-3
+    with pytest.raises(eg().EgfemError):
+        T.burgers(dt(b.u0), dirm, src, eg().BurgersOptions(group=0))

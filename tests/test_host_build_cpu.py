@@ -102,13 +102,13 @@ def test_host_build_matches_oracle_under_sanitizers(driver, tmp_path, mesh, form
 @pytest.mark.parametrize("mesh", sorted(MESHES))
 @pytest.mark.parametrize("wspace", [1, 2, 3])
 def test_host_build_coefficient_spaces_under_sanitizers(driver, tmp_path, mesh, wspace):
-    """W_h = P2, I_k and P0 handles (stiffness and mass forms; P2 also the
-    convection form) build without a sanitizer report; the stored entry count
-    equals the oracle's tensor on that space."""
+    """W_h = P2, I_k and P0 handles (stiffness and mass forms; P2 and I_k also
+    the convection form) build without a sanitizer report; the stored entry
+    count equals the oracle's tensor on that space."""
     coords, cells = MESHES[mesh]()
     coords = np.asarray(coords, np.float64).reshape(len(coords), -1)
     cells = np.asarray(cells)
-    forms = [O.FORM_STIFF, O.FORM_MASS] + ([O.FORM_CONV] if wspace == 1 else [])
+    forms = [O.FORM_STIFF, O.FORM_MASS] + ([O.FORM_CONV] if wspace in (1, 2) else [])
     for form in forms:
         if wspace == 3 and form == O.FORM_MASS:
             continue
