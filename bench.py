@@ -272,11 +272,13 @@ def tensor_action_suite():
         info = T.info
         warm = time_action(T, 100, cold=False)
         cold = time_action(T, 20, cold=True)
+        graph = time_action_graph(T)
         jac = time_jacobian(T, p, 50)
         ba = bytes_action_raw(info)
         bj = bytes_jacobian(info, wl.add_stiffness)
         out[name] = {"nnz": info.nnz, "slots": info.slots, "action_bytes": ba,
                      "action_warm_us": warm * 1e3, "action_warm_GBps": ba / (warm * 1e6),
+                     "action_graph_us": graph * 1e3, "action_graph_GBps": ba / (graph * 1e6),
                      "action_cold_us": cold * 1e3, "action_cold_GBps": ba / (cold * 1e6),
                      "action_cold_frac": ba / (cold * 1e6) / HBM_PEAK_GBS,
                      "action_nnz_per_s": info.nnz / (cold * 1e-3),
@@ -345,15 +347,20 @@ def tensor_action_suite():
 
 
 def stream_ceiling():
-    """Plain device copy and read-reduction (torch kernels) of 256 MiB after a
-    1 GiB read: the measured bandwidth context for the roofline."""
+    """Measured bandwidth context for the roofline, each on 256 MiB after a
+    1 GiB read: the library's streaming-read probe (egfem_stream_read: the
+    tensor action's launch arrangement, reads only), and torch's device copy
+    and read-reduction."""
     import torch
+    import paper_2005_06193_amd as eg
     n = 1 << 25
     x = torch.rand(n, dtype=torch.float64, device="cuda")
     y = torch.empty_like(x)
+    part = torch.empty(eg.load_library().egfem_stream_read_chunks(n), dtype=torch.float64, device="cuda")
     flush = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
     res = {}
-    for name, fn, nbytes in (("copy", lambda: y.copy_(x), 16 * n), ("sum", lambda: x.sum(), 8 * n)):
+    for name, fn, nbytes in (("probe_read", lambda: eg.stream_read(x, part), 8 * n),
+                             ("copy", lambda: y.copy_(x), 16 * n), ("sum", lambda: x.sum(), 8 * n)):
         fn()
         tot = 0.0
         for i in range(10):
@@ -367,6 +374,45 @@ def stream_ceiling():
             tot += e0.elapsed_time(e1)
         res[f"{name}_cold_GBps"] = nbytes / (tot / 10 * 1e6)
     return res
+
+
+def time_action_graph(T, launches: int = 20, replays: int = 10):
+    """Raw tensor action launched `launches` times inside one captured graph,
+    replayed `replays` times: the per-launch time without host launch gaps."""
+    import torch
+    n = T.n
+    g = torch.Generator(device="cuda").manual_seed(5)
+    u = torch.rand(n, dtype=torch.float64, device="cuda", generator=g)
+    a = torch.rand(n, dtype=torch.float64, device="cuda", generator=g) + 1.0
+    r = torch.empty_like(u)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(3):
+            T.residual(u, a, r)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for _ in range(launches):
+            T.residual(u, a, r)
+    graph.replay()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(replays):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / (replays * launches)
+    # the replayed result is the eager one
+    r_eager = torch.empty_like(r)
+    T.residual(u, a, r_eager)
+    torch.cuda.synchronize()
+    assert torch.equal(r, r_eager), "graph replay of the tensor action differs from the eager launch"
+    del graph
+    return ms
 
 
 def batched_suite(reps: int = 3):

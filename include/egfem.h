@@ -666,6 +666,23 @@ int egfem_batch_autotune(int count, const egfem_tensor_t* Ts, const egfem_proble
 int egfem_batch_teams(egfem_batch_t B, int* team_sizes, int* total_workgroups);
 void egfem_batch_destroy(egfem_batch_t B);
 
+/* ------------------------------------------------------------------------
+ * Measurement aid: the streaming-read ceiling.  A plain read of x with the
+ * tensor action's launch arrangement (one contiguous chunk of
+ * egfem_stream_read_chunks granularity per workgroup, every 16-byte load of a
+ * thread issued before the first is used, chunks mapped to the XCDs in
+ * contiguous regions); the bandwidth it reaches on a buffer that is not in
+ * the caches is the measured reference for the tensor action's HBM fraction.
+ *   x        device [n] doubles (16-byte aligned for the vector path)
+ *   partial  device [n_partial] doubles, n_partial >= egfem_stream_read_chunks(n);
+ *            partial[c] receives the sum of chunk c (2048 doubles, the last
+ *            one shorter)
+ * Asynchronous on `stream`.  EGFEM_ERR_ARG for null pointers or n < 0,
+ * EGFEM_ERR_SHAPE when partial is too short.
+ * ---------------------------------------------------------------------- */
+int64_t egfem_stream_read_chunks(int64_t n);
+int egfem_stream_read(const double* x, int64_t n, double* partial, int64_t n_partial, void* stream);
+
 /* Thread-local message of the last error. */
 const char* egfem_last_error(void);
 

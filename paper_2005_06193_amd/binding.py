@@ -201,6 +201,8 @@ EXPORTS = {
                                     C.POINTER(_Opts), C.POINTER(_Stats), C.c_void_p]),
     "egfem_solve_cg": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int,
                                  C.POINTER(C.c_int), C.POINTER(C.c_double), C.c_void_p]),
+    "egfem_stream_read_chunks": (C.c_int64, [C.c_int64]),
+    "egfem_stream_read": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),
     "egfem_last_error": (C.c_char_p, []),
     "egfem_version": (C.c_char_p, []),
 }
@@ -869,6 +871,17 @@ def batch_autotune(tensors: Sequence[Tensor], problems: Sequence[Problem], us: S
         with open(cache, "w") as fh:
             json.dump(db, fh, indent=1)
     return res
+
+
+def stream_read(x: torch.Tensor, partial: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Streaming-read ceiling probe: per-chunk sums of x (float64, contiguous)
+    written into `partial` (allocated when None); see egfem_stream_read."""
+    n = x.numel()
+    nc = int(load_library().egfem_stream_read_chunks(n))
+    if partial is None:
+        partial = torch.empty(max(nc, 1), dtype=torch.float64, device=x.device)
+    _check(load_library().egfem_stream_read(_dptr(x), n, _dptr(partial), partial.numel(), _stream()))
+    return partial
 
 
 def version() -> str:

@@ -138,6 +138,24 @@ struct ActionRegs {
 // an empty range clamps in bounds) and the extra values are masked at use.
 __device__ __forceinline__ int clamp_hi(int x, int n) { return min(x, max(n - 1, 0)); }
 
+// acc + x[lo] + x[lo+1] + ... + x[hi-1], added in that order (the result of
+// the plain loop, bit for bit), with the LDS reads issued four at a time:
+// reads past hi are clamped to hi - 1 and their values not added, so four
+// reads are in flight per wait instead of one.
+__device__ __forceinline__ double lds_range_sum(const double* x, int lo, int hi, double acc) {
+  for (int t = lo; t < hi; t += 4) {
+    const double v0 = x[t];
+    const double v1 = x[min(t + 1, hi - 1)];
+    const double v2 = x[min(t + 2, hi - 1)];
+    const double v3 = x[min(t + 3, hi - 1)];
+    acc += v0;
+    if (t + 1 < hi) acc += v1;
+    if (t + 2 < hi) acc += v2;
+    if (t + 3 < hi) acc += v3;
+  }
+  return acc;
+}
+
 // Stage 1a of the tensor action: every stream load of this thread for block b
 // (its entries, slots and row), issued back to back without waiting.
 template <int NT, bool PROBLEM>
@@ -246,8 +264,7 @@ __device__ __forceinline__ void action_compute(const ActionRegs<NT>& R, const do
   for (int q = 0; q < SS; ++q) {
     const int s = tid + q * NT;
     if (s < R.ns) {
-      double acc = 0.0;
-      for (int t = L.spa[s]; t < L.spa[s + 1]; ++t) acc += L.tA[t];
+      double acc = lds_range_sum(L.tA, L.spa[s], L.spa[s + 1], 0.0);
       if (PROBLEM && kval) acc += R.kv[q];
       L.y[s] = acc * wj[q];
     }
@@ -255,8 +272,7 @@ __device__ __forceinline__ void action_compute(const ActionRegs<NT>& R, const do
   __syncthreads();
   // row sums
   if (has_row) {
-    double acc = 0.0;
-    for (int t = L.srow[tid]; t < L.srow[tid + 1]; ++t) acc += L.y[t];
+    double acc = lds_range_sum(L.y, L.srow[tid], L.srow[tid + 1], 0.0);
     if (PROBLEM) {
       const bool drow = dir && R.dr;
       if (load) acc -= R.ldi;
@@ -442,12 +458,10 @@ __device__ void rowblock_jacobian(const TensorView& T, int64_t b, const double* 
       } else if (dcr[q]) {
         J = 0.0;
       } else {
-        double qa = 0.0;
-        for (int t = L.spa[s]; t < L.spa[s + 1]; ++t) qa += L.tA[t];
+        const double qa = lds_range_sum(L.tA, L.spa[s], L.spa[s + 1], 0.0);
         J = (kval ? kv[q] : 0.0) + qa;
         if (second) {
-          double qb = 0.0;
-          for (int t = L.spb[s]; t < L.spb[s + 1]; ++t) qb += L.tB[t];
+          const double qb = lds_range_sum(L.tB, L.spb[s], L.spb[s + 1], 0.0);
           const double g = dadu ? gj[q] : 2.0 * uj[q];
           J = fma(g, qb, J);
         }

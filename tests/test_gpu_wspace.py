@@ -182,9 +182,8 @@ def test_p2_deterministic_and_rejections(space):
     x = dt(np.ones(T.n))
     with pytest.raises(eg().EgfemError):
         T.mode3(x, x)
-    if space == "iq":     # the convection form takes W_h = P1 or P2 only
-        with pytest.raises(eg().EgfemError):
-            eg().Tensor.from_mesh(wl.mesh, W.FORM_CONV, wspace=SPACES[space][0]())
+    with pytest.raises(eg().EgfemError):      # no convection form with W_h = P0
+        eg().Tensor.from_mesh(wl.mesh, W.FORM_CONV, wspace=eg().W_P0)
     with pytest.raises(eg().EgfemError):
         eg().Tensor.from_mesh(wl.mesh, 0, wspace=7)
     with pytest.raises(eg().EgfemError):
