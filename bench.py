@@ -242,9 +242,10 @@ def newton_config_suite(reps: int = 5) -> dict:
             _, res0 = T.problem_residual(p, torch.zeros(T.n, dtype=torch.float64, device="cuda"),
                                          with_norm=True)
             tol = 1e-12 / res0
-        opts = eg.NewtonOptions(tol=tol, forcing=1, timing=1)
-        elapsed, stats, _ = time_solves(T, p, reps, 1, opts)
-        ok = all(s.status == 0 and s.res <= tol * s.res0 for s in stats)
+        elapsed, stats0, _ = time_solves(T, p, reps, 1, eg.NewtonOptions(tol=tol, forcing=1))
+        # the Krylov split from a second, event-timed pass
+        _, stats, _ = time_solves(T, p, reps, 0, eg.NewtonOptions(tol=tol, forcing=1, timing=1))
+        ok = all(s.status == 0 and s.res <= tol * s.res0 for s in stats0 + stats)
         k_it = sum(s.krylov_iters for s in stats)
         t_kry = sum(s.t_krylov_ms for s in stats)
         out[name] = {"nodes": T.n, "tensor_nnz": T.info.nnz, "tol_rel": tol, "converged": ok,
@@ -849,11 +850,18 @@ def main():
     wl, T, p = gpu_setup(args.n)
     tuned = T.autotune(p)          # offline, like the tensor build
     info = T.info
-    opts = eg.NewtonOptions(tol=wl.tol, forcing=1, timing=1)
-    elapsed, stats, u = time_solves(T, p, args.steps, args.warmup, opts)
-    ok = all(s.status == 0 and s.res <= wl.tol * s.res0 for s in stats)
+    # the timed region: K solves as a user runs them (no per-launch events)
+    opts = eg.NewtonOptions(tol=wl.tol, forcing=1)
+    elapsed, stats_plain, u = time_solves(T, p, args.steps, args.warmup, opts)
     ms_per_step = 1000.0 * elapsed / args.steps
     solves_per_s = args.steps / elapsed
+    # the same K solves again with HIP events around every launch on the
+    # library's stream: the per-kernel split and the dominant kernel's average
+    # launch duration (the events themselves cost ~0.25 ms per solve, so this
+    # second region is reported beside, not as, the throughput)
+    opts_t = eg.NewtonOptions(tol=wl.tol, forcing=1, timing=1)
+    elapsed_t, stats, _ = time_solves(T, p, args.steps, max(args.warmup, 1), opts_t)
+    ok = all(s.status == 0 and s.res <= wl.tol * s.res0 for s in stats_plain + stats)
 
     # per-kernel split over the timed region (events inside the driver)
     t_act = sum(s.t_action_ms for s in stats)
@@ -943,6 +951,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
+        "instrumented_ms_per_step": 1000.0 * elapsed_t / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
