@@ -417,8 +417,10 @@ def time_action_graph(T, launches: int = 20, replays: int = 10):
 
 
 def batched_suite(reps: int = 3):
-    """64-instance workload: one persistent launch replayed from a hipGraph,
-    against the same 64 instances solved one by one (egfem_newton)."""
+    """64-instance workload: one persistent launch replayed from a hipGraph
+    (the plan kind, workgroup size and exponent from the library's batch
+    autotuner), against the same 64 instances solved one by one
+    (egfem_newton)."""
     import torch
     import paper_2005_06193_amd as eg
     import workloads as W
@@ -431,7 +433,7 @@ def batched_suite(reps: int = 3):
            "tensor_nnz": sum(T.info.nnz for T in Ts)}
     # the library's batch autotuner picks the workgroup size and team weight
     tuned = eg.batch_autotune(Ts, Ps, us, opts)
-    B = eg.Batch(Ts, Ps, us, opts, threads=tuned["threads"], weight_exp=tuned["weight_exp"])
+    B = eg.Batch(Ts, Ps, us, opts, threads=tuned["threads"], weight_exp=tuned["weight_exp"], kind=tuned["kind"])
     B.run(zero_init=True, graph=True)       # capture + warm
     st, rc = B.stats()
     torch.cuda.synchronize()
@@ -441,7 +443,8 @@ def batched_suite(reps: int = 3):
     st, rc = B.stats()
     dt_ = (time.perf_counter() - t0) / reps
     ok = rc == 0 and all(s.status == 0 for s in st)
-    best = {"threads": tuned["threads"], "weight_exp": tuned["weight_exp"], "tuner_eager_ms": tuned["ms"],
+    best = {"kind": ["streaming teams", "scheduled resident teams"][tuned["kind"]],
+            "threads": tuned["threads"], "weight_exp": tuned["weight_exp"], "tuner_eager_ms": tuned["ms"],
             "ms": dt_ * 1e3, "converged": ok, "workgroups": B.teams()[1]}
     B.close()
     res["autotuned"] = best

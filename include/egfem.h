@@ -645,6 +645,23 @@ typedef struct egfem_batch_s* egfem_batch_t;
 int egfem_batch_create(int count, const egfem_tensor_t* Ts, const egfem_problem* ps,
                        double* const* us, const egfem_newton_opts* o, int threads,
                        double weight_exp, egfem_batch_t* out);
+/* Scheduled resident teams (the same run / graph / stats / destroy calls):
+ * every team member owns at most `threads` consecutive rows (whole row
+ * blocks), one per thread, so each Newton system is solved by the
+ * register-resident BiCGStab with the block-Jacobi preconditioner of the
+ * handle (krylov_precond Chebyshev steps on the member's rows; 0 = Jacobi).
+ * The teams this needs exceed the co-resident workgroups, so the host packs
+ * the instances into them in space and time: longest estimated duration
+ * (n_nodes^dur_exp) first, each instance on the window of consecutive
+ * workgroups that frees first; every workgroup then runs its (instance,
+ * rank) list in start order within the one launch.  Requires rows of at
+ * most 8 entries and W_h = P1 (EGFEM_ERR_ARG otherwise), and every team to
+ * fit the resident workgroups (EGFEM_ERR_SHAPE otherwise).
+ *   threads:  256 or 512 (0 = 256)
+ *   dur_exp:  duration model exponent (0 = 0.5: Krylov iterations ~ h^-1) */
+int egfem_batch_create_sched(int count, const egfem_tensor_t* Ts, const egfem_problem* ps,
+                             double* const* us, const egfem_newton_opts* o, int threads,
+                             double dur_exp, egfem_batch_t* out);
 int egfem_batch_run(egfem_batch_t B, int zero_init, void* stream);
 int egfem_batch_graph_run(egfem_batch_t B, int zero_init, void* stream);
 /* Synchronises the stream and copies per-instance statistics into stats
@@ -652,17 +669,21 @@ int egfem_batch_graph_run(egfem_batch_t B, int zero_init, void* stream);
 int egfem_batch_stats(egfem_batch_t B, egfem_newton_stats* stats, void* stream);
 /* Batch autotuner: time one eager run of the plan (the second of two, HIP
  * events on `stream`, every instance started from u = 0) for each candidate
- * workgroup size {512, 1024} x team weight exponent {1, 1.5, 2} on these
- * instances and options, and report the fastest whose instances all converge
- * (EGFEM_OK, or EGFEM_STAGNATED: stopped at the rounding floor of ||F||).  The
- * solution buffers are overwritten.  best_threads,
- * best_weight_exp, best_ms (host, nullable) receive the choice, to be passed to
- * egfem_batch_create (the Python binding caches it by the instance sizes).
- * EGFEM_ERR_ARG when no candidate converges.  Synchronises the stream. */
+ * -- streaming teams: workgroup size {512, 1024} x team weight exponent
+ * {1, 1.5, 2}; scheduled resident teams (where they apply): workgroup size
+ * {256, 512} x duration exponent {0.5, 1} -- on these instances and options,
+ * and report the fastest whose instances all converge (EGFEM_OK, or
+ * EGFEM_STAGNATED: stopped at the rounding floor of ||F||).  The solution
+ * buffers are overwritten.  best_kind (0 streaming: egfem_batch_create, 1
+ * scheduled: egfem_batch_create_sched), best_threads, best_exp (the weight or
+ * duration exponent) and best_ms (host, nullable) receive the choice (the
+ * Python binding caches it by the instance sizes).  EGFEM_ERR_ARG when no
+ * candidate converges.  Synchronises the stream. */
 int egfem_batch_autotune(int count, const egfem_tensor_t* Ts, const egfem_problem* ps,
-                         double* const* us, const egfem_newton_opts* o, int* best_threads,
-                         double* best_weight_exp, double* best_ms, void* stream);
-/* Team size (workgroups) given to each instance: host array [count]. */
+                         double* const* us, const egfem_newton_opts* o, int* best_kind,
+                         int* best_threads, double* best_exp, double* best_ms, void* stream);
+/* Team size (workgroups) given to each instance: host array [count]; the
+ * workgroups of the launch. */
 int egfem_batch_teams(egfem_batch_t B, int* team_sizes, int* total_workgroups);
 void egfem_batch_destroy(egfem_batch_t B);
 

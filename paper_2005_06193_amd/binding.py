@@ -177,6 +177,9 @@ EXPORTS = {
     "egfem_batch_create": (C.c_int, [C.c_int, C.POINTER(C.c_void_p), C.POINTER(_Problem),
                                      C.POINTER(C.c_void_p), C.POINTER(_Opts), C.c_int, C.c_double,
                                      C.POINTER(C.c_void_p)]),
+    "egfem_batch_create_sched": (C.c_int, [C.c_int, C.POINTER(C.c_void_p), C.POINTER(_Problem),
+                                           C.POINTER(C.c_void_p), C.POINTER(_Opts), C.c_int, C.c_double,
+                                           C.POINTER(C.c_void_p)]),
     "egfem_batch_run": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
     "egfem_batch_graph_run": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
     "egfem_batch_stats": (C.c_int, [C.c_void_p, C.POINTER(_Stats), C.c_void_p]),
@@ -184,7 +187,8 @@ EXPORTS = {
     "egfem_batch_destroy": (None, [C.c_void_p]),
     "egfem_batch_autotune": (C.c_int, [C.c_int, C.POINTER(C.c_void_p), C.POINTER(_Problem),
                                        C.POINTER(C.c_void_p), C.POINTER(_Opts), C.POINTER(C.c_int),
-                                       C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p]),
+                                       C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                       C.c_void_p]),
     "egfem_get_shape": (C.c_int, [C.c_void_p, C.POINTER(_Shape)]),
     "egfem_set_shape": (C.c_int, [C.c_void_p, C.POINTER(_Shape)]),
     "egfem_autotune": (C.c_int, [C.c_void_p, C.POINTER(_Problem), C.c_int, C.POINTER(_Shape),
@@ -772,11 +776,14 @@ class Tensor:
 
 class Batch:
     """Reusable batch plan: all instances solved by one persistent launch,
-    optionally replayed from a captured hipGraph."""
+    optionally replayed from a captured hipGraph.  kind 0: streaming teams
+    (egfem_batch_create; threads 512/1024, weight_exp the team weight
+    exponent); kind 1: scheduled resident teams (egfem_batch_create_sched;
+    threads 256/512, weight_exp the duration exponent)."""
 
     def __init__(self, tensors: Sequence[Tensor], problems: Sequence[Problem],
                  us: Sequence[torch.Tensor], opts: Optional[NewtonOptions] = None,
-                 threads: int = 0, weight_exp: float = 0.0):
+                 threads: int = 0, weight_exp: float = 0.0, kind: int = 0):
         m = len(tensors)
         if not (m == len(problems) == len(us)) or m == 0:
             raise EgfemError(EGFEM_ERR_SHAPE, "tensors/problems/us must have equal nonzero length")
@@ -787,8 +794,11 @@ class Batch:
         up = (C.c_void_p * m)(*[_dptr(u, n=t.n) for u, t in zip(us, tensors)])
         o = (opts or NewtonOptions()).c()
         out = C.c_void_p()
-        _check(load_library().egfem_batch_create(m, hs, self._ps, up, C.byref(o), int(threads),
-                                                 float(weight_exp), C.byref(out)))
+        if kind not in (0, 1):
+            raise EgfemError(EGFEM_ERR_ARG, "kind must be 0 (streaming teams) or 1 (scheduled teams)")
+        create = load_library().egfem_batch_create_sched if kind == 1 else load_library().egfem_batch_create
+        _check(create(m, hs, self._ps, up, C.byref(o), int(threads), float(weight_exp), C.byref(out)))
+        self.kind = kind
         self._h = out
         _live_batches.add(self)
 
@@ -838,14 +848,15 @@ def newton_batched(tensors: Sequence[Tensor], problems: Sequence[Problem],
 
 def batch_autotune(tensors: Sequence[Tensor], problems: Sequence[Problem], us: Sequence[torch.Tensor],
                    opts: Optional[NewtonOptions] = None, cache: Optional[str] = None) -> dict:
-    """egfem_batch_autotune: the batch plan's workgroup size and team weight by
-    timing; with `cache` (a JSON path) reuse/store the choice keyed by the
-    instances' sizes.  Returns {"threads", "weight_exp", "ms"}."""
+    """egfem_batch_autotune: the batch plan's kind, workgroup size and team
+    weight (or duration) exponent by timing; with `cache` (a JSON path)
+    reuse/store the choice keyed by the instances' sizes.  Returns {"kind",
+    "threads", "weight_exp", "ms"}, the arguments of Batch."""
     import json
     m = len(tensors)
     if not (m == len(problems) == len(us)) or m == 0:
         raise EgfemError(EGFEM_ERR_SHAPE, "tensors/problems/us must have equal nonzero length")
-    key = "batch-" + "-".join(f"{t.n}x{t.info.nnz}" for t in tensors)
+    key = "batch2-" + "-".join(f"{t.n}x{t.info.nnz}" for t in tensors)
     if cache and os.path.exists(cache):
         with open(cache) as fh:
             db = json.load(fh)
@@ -855,12 +866,13 @@ def batch_autotune(tensors: Sequence[Tensor], problems: Sequence[Problem], us: S
     ps = (_Problem * m)(*[p.c() for p in problems])
     up = (C.c_void_p * m)(*[_dptr(u, n=t.n) for u, t in zip(us, tensors)])
     o = (opts or NewtonOptions()).c()
+    kind = C.c_int(0)
     thr = C.c_int(0)
     wexp = C.c_double(0.0)
     ms = C.c_double(0.0)
-    _check(load_library().egfem_batch_autotune(m, hs, ps, up, C.byref(o), C.byref(thr), C.byref(wexp),
-                                               C.byref(ms), _stream()))
-    res = {"threads": thr.value, "weight_exp": wexp.value, "ms": ms.value}
+    _check(load_library().egfem_batch_autotune(m, hs, ps, up, C.byref(o), C.byref(kind), C.byref(thr),
+                                               C.byref(wexp), C.byref(ms), _stream()))
+    res = {"kind": kind.value, "threads": thr.value, "weight_exp": wexp.value, "ms": ms.value}
     if cache:
         db = {}
         if os.path.exists(cache):

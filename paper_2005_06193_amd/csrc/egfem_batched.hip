@@ -5,8 +5,20 @@
 // and Krylov rows of a member coincide and only gathered vectors (u, the
 // Newton correction, the preconditioned Krylov vectors) cross workgroups,
 // through agent-coherent accesses.  The whole damped Newton loop -- residual
-// with fused pointwise update, Jacobian emission, Jacobi-BiCGStab, line
-// search, convergence test -- runs on the device with team-local barriers.
+// with fused pointwise update, Jacobian emission, BiCGStab, line search,
+// convergence test -- runs on the device with team-local barriers.
+//
+// Two plan kinds.  Streaming teams: every instance has its team for the whole
+// launch and its members stream their rows through the Jacobi BiCGStab.
+// Scheduled resident teams: a member owns at most one row per thread, so the
+// Krylov solve is the register-resident block-Jacobi BiCGStab (the member's
+// rows are its block); the teams that this needs exceed the co-resident
+// workgroups, so the host packs the instances into the resident workgroups in
+// space and time (list scheduling on an estimated duration), and every
+// workgroup runs its own list of (instance, rank) in start order.  A team
+// forms when its members reach the instance's first team barrier; since every
+// workgroup takes its instances in the order of their start times, no wait can
+// close a cycle.
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
@@ -39,6 +51,10 @@ struct Inst {
   double* dinv;
   dev::KArgs K;       // matrix = jval, rhs = F (scale -1), x = Newton correction
   const int32_t* wgblk;   // [team_size + 1] row-block range of every member
+  // scheduled resident teams: member q's Krylov rows are K.rlist[kr[q], kr[q+1])
+  // (a part of the compact partition); nbr its neighbour list, or null
+  const int32_t* kr;
+  const int32_t* nbr;
   unsigned* ctrl;
   double* red;
   double* stats;      // [kStatsWords]
@@ -73,15 +89,12 @@ __device__ double ew_forcing(int k, double nF, double nF_prev, double eta_prev, 
   return fmin(eta, eta_max);
 }
 
-template <int NT, int RS>
-__global__ __launch_bounds__(NT) void k_newton_batched(const Inst* __restrict__ insts,
-                                                       const int32_t* __restrict__ wg2inst, BatchOpts O) {
-  __shared__ dev::RowBlockLds lds;
-  __shared__ double sh[dev::kShWords<NT>];
-  __shared__ int sh_abort;
-  const Inst& I = insts[wg2inst[blockIdx.x]];
-  dev::Team tm{blockIdx.x - (unsigned)I.team_first, (unsigned)I.team_size, I.ctrl, I.red, 0u};
-  const int b0 = I.wgblk[tm.rank], b1 = I.wgblk[tm.rank + 1];
+// The damped Newton loop of instance I by team member tm (row blocks [b0, b1)).
+// RES: the Krylov solve is the register-resident block-Jacobi BiCGStab (the
+// member's rows fit its threads); otherwise the streaming Jacobi BiCGStab.
+template <int NT, int RS, bool RES>
+__device__ void newton_team(const Inst& I, dev::Team& tm, int b0, int b1, const BatchOpts& O,
+                            dev::RowBlockLds& lds, double* sh, int& sh_abort) {
   const int rb = I.tv.blk_row[b0], re = I.tv.blk_row[b1];
   const int tid = threadIdx.x;
   const double* kval = I.addK ? I.tv.kval : nullptr;
@@ -132,7 +145,15 @@ __global__ __launch_bounds__(NT) void k_newton_batched(const Inst* __restrict__ 
     dev::KArgs KA = I.K;
     KA.rtol = rtol;
     KA.max_iter = O.max_krylov;
-    const dev::KOut ko = dev::team_bicgstab<NT, row_L(RS), row_K(RS)>(tm, KA, rb, re, sh, &sh_abort);
+    dev::KOut ko;
+    if constexpr (RES) {
+      // the member's Krylov rows are its part of the compact partition: rows
+      // whose Jacobian, D^-1 and residual other members emitted
+      if ((abort = dev::team_barrier(tm, &sh_abort))) break;
+      ko = dev::team_bicgstab_reg<NT, kResidentRow>(tm, KA, I.kr[tm.rank], I.kr[tm.rank + 1], sh, &sh_abort);
+    } else {
+      ko = dev::team_bicgstab<NT, row_L(RS), row_K(RS)>(tm, KA, rb, re, sh, &sh_abort);
+    }
     if ((abort = ko.abort)) break;
     kry += ko.iters;
     if (writer && k < EGFEM_HIST) {
@@ -183,6 +204,35 @@ __global__ __launch_bounds__(NT) void k_newton_batched(const Inst* __restrict__ 
 }
 
 template <int NT, int RS>
+__global__ __launch_bounds__(NT) void k_newton_batched(const Inst* __restrict__ insts,
+                                                       const int32_t* __restrict__ wg2inst, BatchOpts O) {
+  __shared__ dev::RowBlockLds lds;
+  __shared__ double sh[dev::kShWords<NT>];
+  __shared__ int sh_abort;
+  const Inst& I = insts[wg2inst[blockIdx.x]];
+  dev::Team tm{blockIdx.x - (unsigned)I.team_first, (unsigned)I.team_size, I.ctrl, I.red, 0u};
+  newton_team<NT, RS, false>(I, tm, I.wgblk[tm.rank], I.wgblk[tm.rank + 1], O, lds, sh, sh_abort);
+}
+
+// Scheduled resident teams: workgroup w runs the (instance, rank) pairs
+// list[ptr[w], ptr[w + 1]) in order.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_newton_sched(const Inst* __restrict__ insts,
+                                                     const int32_t* __restrict__ ptr,
+                                                     const int2* __restrict__ list, BatchOpts O) {
+  __shared__ dev::RowBlockLds lds;
+  __shared__ double sh[dev::kShWords<NT>];
+  __shared__ int sh_abort;
+  for (int t = ptr[blockIdx.x]; t < ptr[blockIdx.x + 1]; ++t) {
+    const int2 e = list[t];
+    const Inst& I = insts[e.x];
+    dev::Team tm{(unsigned)e.y, (unsigned)I.team_size, I.ctrl, I.red, 0u};
+    if (I.nbr) tm.nbr = I.nbr + (size_t)e.y * (dev::kMaxNbr + 1);
+    newton_team<NT, 0, true>(I, tm, I.wgblk[e.y], I.wgblk[e.y + 1], O, lds, sh, sh_abort);
+  }
+}
+
+template <int NT, int RS>
 hipError_t launch_NL(const Inst* insts, const int32_t* wg2inst, const BatchOpts& O, unsigned G,
                      hipStream_t st) {
   void* args[] = {(void*)&insts, (void*)&wg2inst, (void*)&O};
@@ -196,6 +246,23 @@ int cap_NL() {
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_newton_batched<NT, RS>, NT, 0) !=
       hipSuccess)
+    return 0;
+  return per_cu * cus;
+}
+
+template <int NT>
+hipError_t launch_sched(const Inst* insts, const int32_t* ptr, const int2* list, const BatchOpts& O, unsigned G,
+                        hipStream_t st) {
+  void* args[] = {(void*)&insts, (void*)&ptr, (void*)&list, (void*)&O};
+  return hipLaunchCooperativeKernel((const void*)k_newton_sched<NT>, dim3(G), dim3(NT), args, 0, st);
+}
+
+template <int NT>
+int cap_sched() {
+  int dev = 0, per_cu = 0, cus = 0;
+  hipGetDevice(&dev);
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_newton_sched<NT>, NT, 0) != hipSuccess)
     return 0;
   return per_cu * cus;
 }
@@ -236,6 +303,7 @@ int cap_T(int L) {
 
 struct egfem_batch_s {
   int count = 0;
+  int kind = 0;       // 0 streaming teams, 1 scheduled resident teams
   int NT = 512;
   int L = 4;
   int G = 0;
@@ -254,6 +322,15 @@ struct egfem_batch_s {
   hipGraphExec_t exec = nullptr;
   int graph_zero_init = -1;
   hipStream_t cap_stream = nullptr;   // capture stream owned by the plan (default priority)
+  // scheduled resident teams: per-workgroup (instance, rank) lists, part-local
+  // column positions of every instance's slots
+  int32_t* d_sched_ptr = nullptr;
+  int2* d_sched_list = nullptr;
+  int16_t* d_kloc = nullptr;
+  int32_t* d_kr = nullptr;      // every instance's part offsets
+  int32_t* d_rlist = nullptr;   // every instance's part rows
+  int32_t* d_nbr = nullptr;     // every instance's neighbour lists
+  double makespan = 0.0;   // of the schedule, in the duration model's units
 };
 
 namespace {
@@ -270,7 +347,77 @@ void free_batch(egfem_batch_s* B) {
   if (B->d_red) hipFree(B->d_red);
   if (B->d_stats) hipFree(B->d_stats);
   if (B->h_stats) hipHostFree(B->h_stats);
+  if (B->d_sched_ptr) hipFree(B->d_sched_ptr);
+  if (B->d_sched_list) hipFree(B->d_sched_list);
+  if (B->d_kloc) hipFree(B->d_kloc);
+  if (B->d_kr) hipFree(B->d_kr);
+  if (B->d_rlist) hipFree(B->d_rlist);
+  if (B->d_nbr) hipFree(B->d_nbr);
   delete B;
+}
+
+// Newton options of a batch (defaults where o is null), validated.
+int batch_opts(const egfem_newton_opts* o, egfem_newton_opts* out) {
+  using namespace egfem;
+  egfem_newton_opts_default(out);
+  if (o) *out = *o;
+  if (!(out->tol >= 0.0) || out->max_newton < 0 || out->max_krylov < 1 || !(out->krylov_rtol > 0.0) ||
+      !(out->eta_max > 0.0 && out->eta_max < 1.0) || out->max_backtracks < 0)
+    return fail(EGFEM_ERR_ARG, "invalid Newton options");
+  return EGFEM_OK;
+}
+
+int batch_handles(int count, const egfem_tensor_t* Ts, double* const* us) {
+  using namespace egfem;
+  for (int m = 0; m < count; ++m) {
+    if (!Ts[m] || !us[m]) return fail(EGFEM_ERR_ARG, "null handle or solution buffer");
+    if (Ts[m]->w2) return fail(EGFEM_ERR_ARG, "the batched form is not available for handles with W_h != P1");
+    for (int q = 0; q < m; ++q)
+      if (Ts[q] == Ts[m]) return fail(EGFEM_ERR_ARG, "a handle appears twice in the batch");
+  }
+  return EGFEM_OK;
+}
+
+// Descriptor of instance m (its handle's workspace holds the Newton and
+// Krylov vectors); team and buffer pointers are set by the caller.
+void fill_inst(egfem::Inst& I, egfem_tensor_s* T, const egfem_problem& p, double* u,
+               const egfem_newton_opts& opts) {
+  using namespace egfem;
+  Workspace& W = T->ws;
+  I.tv = view_of(T);
+  I.a0 = p.a0;
+  I.a0c = p.a0_const;
+  I.load = p.load;
+  I.dir = p.dirichlet;
+  I.addK = p.add_stiffness;
+  I.u = u;
+  I.utry = W.utry;
+  I.F = W.F;
+  I.jval = W.jval;
+  I.dinv = W.dinv;
+  dev::KArgs& K = I.K;
+  K.n = T->n;
+  K.rowptr = T->rowptr;
+  K.col = T->col;
+  K.val = W.jval;
+  K.perm = nullptr;
+  K.dinv = W.dinv;
+  K.rhs = W.F;
+  K.rhs_scale = -1.0;
+  K.x = W.delta;
+  K.x_zero = 1;
+  K.r = W.r;
+  K.rhat = W.rhat;
+  K.p = W.p;
+  K.v = W.v;
+  K.s = W.s;
+  K.t = W.t;
+  K.z = W.z;
+  K.phat = W.phat;
+  K.rh = W.rh;
+  K.vh = W.vh;
+  K.rtol = opts.krylov_rtol;
+  K.max_iter = opts.max_krylov;
 }
 
 // Contiguous ranges of row blocks balanced by slots.
@@ -303,17 +450,9 @@ int egfem_batch_create(int count, const egfem_tensor_t* Ts, const egfem_problem*
   if (threads != 0 && threads != 512 && threads != 1024) return fail(EGFEM_ERR_ARG, "threads must be 512 or 1024");
   if (weight_exp < 0.0 || weight_exp > 4.0) return fail(EGFEM_ERR_ARG, "weight_exp out of range");
   egfem_newton_opts opts;
-  egfem_newton_opts_default(&opts);
-  if (o) opts = *o;
-  if (!(opts.tol >= 0.0) || opts.max_newton < 0 || opts.max_krylov < 1 || !(opts.krylov_rtol > 0.0) ||
-      !(opts.eta_max > 0.0 && opts.eta_max < 1.0) || opts.max_backtracks < 0)
-    return fail(EGFEM_ERR_ARG, "invalid Newton options");
-  for (int m = 0; m < count; ++m) {
-    if (!Ts[m] || !us[m]) return fail(EGFEM_ERR_ARG, "null handle or solution buffer");
-    if (Ts[m]->w2) return fail(EGFEM_ERR_ARG, "the batched form is not available for handles with W_h != P1");
-    for (int q = 0; q < m; ++q)
-      if (Ts[q] == Ts[m]) return fail(EGFEM_ERR_ARG, "a handle appears twice in the batch");
-  }
+  int rc0 = batch_opts(o, &opts);
+  if (rc0 == EGFEM_OK) rc0 = batch_handles(count, Ts, us);
+  if (rc0 != EGFEM_OK) return rc0;
   egfem_batch_s* B = new egfem_batch_s();
   B->count = count;
   B->NT = threads ? threads : 512;
@@ -375,42 +514,8 @@ int egfem_batch_create(int count, const egfem_tensor_t* Ts, const egfem_problem*
     wgblk_off[m] = (int)wgblk.size();
     wgblk.insert(wgblk.end(), part.begin(), part.end());
     for (int q = 0; q < g[m]; ++q) wg2inst.push_back(m);
-    Workspace& W = T->ws;
     Inst& I = hi[m];
-    I.tv = view_of(T);
-    I.a0 = ps[m].a0;
-    I.a0c = ps[m].a0_const;
-    I.load = ps[m].load;
-    I.dir = ps[m].dirichlet;
-    I.addK = ps[m].add_stiffness;
-    I.u = us[m];
-    I.utry = W.utry;
-    I.F = W.F;
-    I.jval = W.jval;
-    I.dinv = W.dinv;
-    dev::KArgs& K = I.K;
-    K.n = T->n;
-    K.rowptr = T->rowptr;
-    K.col = T->col;
-    K.val = W.jval;
-    K.perm = nullptr;
-    K.dinv = W.dinv;
-    K.rhs = W.F;
-    K.rhs_scale = -1.0;
-    K.x = W.delta;
-    K.x_zero = 1;
-    K.r = W.r;
-    K.rhat = W.rhat;
-    K.p = W.p;
-    K.v = W.v;
-    K.s = W.s;
-    K.t = W.t;
-    K.z = W.z;
-    K.phat = W.phat;
-    K.rh = W.rh;
-    K.vh = W.vh;
-    K.rtol = opts.krylov_rtol;
-    K.max_iter = opts.max_krylov;
+    fill_inst(I, T, ps[m], us[m], opts);
     I.team_first = first;
     I.team_size = g[m];
     first += g[m];
@@ -458,6 +563,186 @@ int egfem_batch_create(int count, const egfem_tensor_t* Ts, const egfem_problem*
   return EGFEM_OK;
 }
 
+int egfem_batch_create_sched(int count, const egfem_tensor_t* Ts, const egfem_problem* ps, double* const* us,
+                             const egfem_newton_opts* o, int threads, double dur_exp, egfem_batch_t* out) {
+  using namespace egfem;
+  if (!out) return fail(EGFEM_ERR_ARG, "out is null");
+  *out = nullptr;
+  if (count <= 0 || !Ts || !ps || !us) return fail(EGFEM_ERR_ARG, "null argument or count <= 0");
+  if (threads != 0 && threads != 256 && threads != 512) return fail(EGFEM_ERR_ARG, "threads must be 256 or 512");
+  if (!(dur_exp >= 0.0) || dur_exp > 4.0) return fail(EGFEM_ERR_ARG, "dur_exp out of range");
+  egfem_newton_opts opts;
+  int rc = batch_opts(o, &opts);
+  if (rc == EGFEM_OK) rc = batch_handles(count, Ts, us);
+  if (rc != EGFEM_OK) return rc;
+  for (int m = 0; m < count; ++m) {
+    if (Ts[m]->max_row_slots > kResidentRow)
+      return fail(EGFEM_ERR_ARG, "rows of more than 8 entries: the resident teams do not apply");
+    if (Ts[m]->n >= (int64_t(1) << 28)) return fail(EGFEM_ERR_SHAPE, "instance too large for the resident teams");
+  }
+  const int NT = threads ? threads : 256;
+  const int cap = NT == 512 ? cap_sched<512>() : cap_sched<256>();
+  if (cap < 1) return fail(EGFEM_ERR_HIP, "the scheduled batch kernel cannot be resident");
+  egfem_batch_s* B = new egfem_batch_s();
+  B->kind = 1;
+  B->count = count;
+  B->NT = NT;
+  B->Ts.assign(Ts, Ts + count);
+  // members: a compact partition of the rows into parts of at most NT rows
+  // (the Krylov rows, one per thread) and, for the residual and the Jacobian,
+  // consecutive row blocks balanced by slots
+  std::vector<int> g(count);
+  std::vector<int32_t> wgblk, kr, rlist, nbr;
+  std::vector<int> wgblk_off(count), kr_off(count), nbr_off(count);
+  std::vector<int64_t> rlist_off(count);
+  std::vector<int16_t> kloc;
+  std::vector<int64_t> kloc_off(count);
+  for (int m = 0; m < count; ++m) {
+    egfem_tensor_s* T = Ts[m];
+    if ((rc = ensure_workspace(T)) != EGFEM_OK) {
+      free_batch(B);
+      return rc;
+    }
+    if (T->h_coords.empty()) {
+      free_batch(B);
+      return fail(EGFEM_ERR_ARG, "a handle without node coordinates cannot be partitioned");
+    }
+    std::vector<int32_t> hblk(T->row_blocks + 1);
+    if (hipMemcpy(hblk.data(), T->blk_row, hblk.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) {
+      free_batch(B);
+      return fail(EGFEM_ERR_HIP, "copy of row blocks failed");
+    }
+    int gm = (int)((T->n + NT - 1) / NT);
+    CompactPartition cp;
+    for (;;) {
+      if (gm > cap || gm > kMaxKrylovBlocks || gm > T->row_blocks) {
+        free_batch(B);
+        return fail(EGFEM_ERR_SHAPE, "an instance needs more resident workgroups than the GPU holds");
+      }
+      if ((rc = make_compact_partition(T->dim, T->h_coords.data(), T->n, T->h_rowptr.data(), T->h_col.data(), gm,
+                                       cp)) != EGFEM_OK) {
+        free_batch(B);
+        return rc;
+      }
+      if (cp.maxrows <= NT) break;
+      ++gm;
+    }
+    g[m] = gm;
+    std::vector<int32_t> part;
+    split_blocks(T, hblk, gm, part);
+    wgblk_off[m] = (int)wgblk.size();
+    wgblk.insert(wgblk.end(), part.begin(), part.end());
+    kr_off[m] = (int)kr.size();
+    kr.insert(kr.end(), cp.kr.begin(), cp.kr.end());
+    rlist_off[m] = (int64_t)rlist.size();
+    rlist.insert(rlist.end(), cp.rlist.begin(), cp.rlist.end());
+    nbr_off[m] = (int)nbr.size();
+    nbr.insert(nbr.end(), cp.nbr.begin(), cp.nbr.end());
+    kloc_off[m] = (int64_t)kloc.size();
+    kloc.insert(kloc.end(), cp.kloc.begin(), cp.kloc.end());
+  }
+  // list scheduling: instances by estimated duration (n^dur_exp), longest
+  // first, each on the window of g[m] consecutive workgroups that frees first
+  const double ex = dur_exp > 0.0 ? dur_exp : 0.5;
+  std::vector<double> dur(count);
+  for (int m = 0; m < count; ++m) dur[m] = std::pow((double)Ts[m]->n, ex);
+  std::vector<int> order(count);
+  for (int m = 0; m < count; ++m) order[m] = m;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return dur[a] > dur[b]; });
+  std::vector<double> finish(cap, 0.0);
+  std::vector<std::vector<int2>> lists(cap);
+  int used = 0;
+  for (int m : order) {
+    int bp = 0;
+    double bs = DBL_MAX;
+    for (int p0 = 0; p0 + g[m] <= cap; ++p0) {
+      double st0 = 0.0;
+      for (int w = p0; w < p0 + g[m]; ++w) st0 = std::max(st0, finish[w]);
+      if (st0 < bs) {
+        bs = st0;
+        bp = p0;
+      }
+    }
+    for (int w = bp; w < bp + g[m]; ++w) {
+      finish[w] = bs + dur[m];
+      lists[w].push_back(make_int2(m, w - bp));
+    }
+    used = std::max(used, bp + g[m]);
+  }
+  B->makespan = *std::max_element(finish.begin(), finish.end());
+  std::vector<int32_t> sptr(used + 1, 0);
+  std::vector<int2> slist;
+  for (int w = 0; w < used; ++w) {
+    slist.insert(slist.end(), lists[w].begin(), lists[w].end());
+    sptr[w + 1] = (int32_t)slist.size();
+  }
+  B->team = g;
+  B->G = used;
+  // buffers and descriptors
+  B->ctrl_words = (size_t)count * dev::kCtrlWords;
+  size_t red_words = 0;
+  std::vector<size_t> red_off(count);
+  for (int m = 0; m < count; ++m) {
+    red_off[m] = red_words;
+    red_words += (size_t)kRedSlots * dev::kMaxRed * g[m];
+  }
+  bool ok = hipMalloc((void**)&B->d_insts, count * sizeof(Inst)) == hipSuccess &&
+            hipMalloc((void**)&B->d_wgblk, wgblk.size() * 4) == hipSuccess &&
+            hipMalloc((void**)&B->d_ctrl, B->ctrl_words * 4) == hipSuccess &&
+            hipMalloc((void**)&B->d_red, red_words * 8) == hipSuccess &&
+            hipMalloc((void**)&B->d_stats, (size_t)count * kStatsWords * 8) == hipSuccess &&
+            hipHostMalloc((void**)&B->h_stats, (size_t)count * kStatsWords * 8, 0) == hipSuccess &&
+            hipMalloc((void**)&B->d_sched_ptr, sptr.size() * 4) == hipSuccess &&
+            hipMalloc((void**)&B->d_sched_list, std::max<size_t>(slist.size(), 1) * sizeof(int2)) == hipSuccess &&
+            hipMalloc((void**)&B->d_kloc, std::max<size_t>(kloc.size(), 1) * 2) == hipSuccess &&
+            hipMalloc((void**)&B->d_kr, kr.size() * 4) == hipSuccess &&
+            hipMalloc((void**)&B->d_rlist, std::max<size_t>(rlist.size(), 1) * 4) == hipSuccess &&
+            hipMalloc((void**)&B->d_nbr, std::max<size_t>(nbr.size(), 1) * 4) == hipSuccess;
+  if (!ok) {
+    free_batch(B);
+    return fail(EGFEM_ERR_OOM, "batch buffers");
+  }
+  std::vector<Inst> hi(count);
+  for (int m = 0; m < count; ++m) {
+    Inst& I = hi[m];
+    fill_inst(I, Ts[m], ps[m], us[m], opts);
+    I.K.kloc = B->d_kloc + kloc_off[m];
+    I.K.rlist = B->d_rlist + rlist_off[m];
+    I.K.cheb_steps = Ts[m]->krylov_precond;
+    I.kr = B->d_kr + kr_off[m];
+    I.nbr = B->d_nbr + nbr_off[m];
+    I.team_first = 0;
+    I.team_size = g[m];
+    I.wgblk = B->d_wgblk + wgblk_off[m];
+    I.ctrl = B->d_ctrl + (size_t)m * dev::kCtrlWords;
+    I.red = B->d_red + red_off[m];
+    I.stats = B->d_stats + (size_t)m * kStatsWords;
+  }
+  ok = hipMemcpy(B->d_insts, hi.data(), count * sizeof(Inst), hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(B->d_wgblk, wgblk.data(), wgblk.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(B->d_sched_ptr, sptr.data(), sptr.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
+       (slist.empty() ||
+        hipMemcpy(B->d_sched_list, slist.data(), slist.size() * sizeof(int2), hipMemcpyHostToDevice) ==
+            hipSuccess) &&
+       (kloc.empty() || hipMemcpy(B->d_kloc, kloc.data(), kloc.size() * 2, hipMemcpyHostToDevice) == hipSuccess) &&
+       hipMemcpy(B->d_kr, kr.data(), kr.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
+       (rlist.empty() || hipMemcpy(B->d_rlist, rlist.data(), rlist.size() * 4, hipMemcpyHostToDevice) == hipSuccess) &&
+       (nbr.empty() || hipMemcpy(B->d_nbr, nbr.data(), nbr.size() * 4, hipMemcpyHostToDevice) == hipSuccess);
+  if (!ok) {
+    free_batch(B);
+    return fail(EGFEM_ERR_HIP, "upload of batch descriptors failed");
+  }
+  B->opts.tol = opts.tol;
+  B->opts.max_newton = opts.max_newton;
+  B->opts.max_krylov = opts.max_krylov;
+  B->opts.krylov_rtol = opts.krylov_rtol;
+  B->opts.forcing = opts.forcing;
+  B->opts.eta_max = opts.eta_max;
+  B->opts.max_backtracks = opts.max_backtracks;
+  *out = B;
+  return EGFEM_OK;
+}
+
 // One run: zero the control words (fill kernel, graph-safe), the persistent
 // launch, statistics to pinned host memory.
 static int batch_enqueue(egfem_batch_t B, int zero_init, hipStream_t st) {
@@ -465,8 +750,13 @@ static int batch_enqueue(egfem_batch_t B, int zero_init, hipStream_t st) {
   EGFEM_HIP_CHECK(launch_fill_u32(B->d_ctrl, 0u, (int64_t)B->ctrl_words, st));
   BatchOpts O = B->opts;
   O.zero_init = zero_init ? 1 : 0;
-  const hipError_t e = B->NT == 1024 ? launch_T<1024>(B->L, B->d_insts, B->d_wg2inst, O, (unsigned)B->G, st)
-                                     : launch_T<512>(B->L, B->d_insts, B->d_wg2inst, O, (unsigned)B->G, st);
+  hipError_t e;
+  if (B->kind == 1)
+    e = B->NT == 512 ? launch_sched<512>(B->d_insts, B->d_sched_ptr, B->d_sched_list, O, (unsigned)B->G, st)
+                     : launch_sched<256>(B->d_insts, B->d_sched_ptr, B->d_sched_list, O, (unsigned)B->G, st);
+  else
+    e = B->NT == 1024 ? launch_T<1024>(B->L, B->d_insts, B->d_wg2inst, O, (unsigned)B->G, st)
+                      : launch_T<512>(B->L, B->d_insts, B->d_wg2inst, O, (unsigned)B->G, st);
   if (e != hipSuccess) return fail(EGFEM_ERR_HIP, std::string("batched launch failed: ") + hipGetErrorString(e));
   EGFEM_HIP_CHECK(hipMemcpyAsync(B->h_stats, B->d_stats, (size_t)B->count * kStatsWords * 8,
                                  hipMemcpyDeviceToHost, st));
@@ -526,7 +816,10 @@ int egfem_batch_stats(egfem_batch_t B, egfem_newton_stats* stats, void* stream) 
     o.backtracks = (int)s[3];
     o.res0 = s[4];
     o.res = s[5];
-    o.krylov_kernels = o.newton_iters > 0 ? 2 : 0;   // the team BiCGStab streams its rows
+    // the streaming teams' BiCGStab streams its rows; the scheduled teams run
+    // the register-resident form (block-Jacobi unless the handle asks Jacobi)
+    if (o.newton_iters > 0)
+      o.krylov_kernels = B->kind == 1 ? (1 | (B->Ts[m]->krylov_precond > 0 ? 4 : 0)) : 2;
     for (int k = 0; k < EGFEM_HIST && k < o.newton_iters; ++k) {
       o.res_hist[k] = s[6 + k];
       o.krylov_hist[k] = (int)s[6 + EGFEM_HIST + k];
@@ -551,15 +844,28 @@ int egfem_batch_teams(egfem_batch_t B, int* team_sizes, int* total_workgroups) {
 void egfem_batch_destroy(egfem_batch_t B) { free_batch(B); }
 
 int egfem_batch_autotune(int count, const egfem_tensor_t* Ts, const egfem_problem* ps, double* const* us,
-                         const egfem_newton_opts* o, int* best_threads, double* best_weight_exp, double* best_ms,
-                         void* stream) {
+                         const egfem_newton_opts* o, int* best_kind, int* best_threads, double* best_exp,
+                         double* best_ms, void* stream) {
   using namespace egfem;
   if (count < 1) return fail(EGFEM_ERR_ARG, "count must be >= 1");
   hipStream_t st = (hipStream_t)stream;
   std::vector<egfem_newton_stats> stats((size_t)count);
+  // the scheduled resident teams apply to P1 handles with rows of <= 8 entries
+  bool sched_ok = true;
+  for (int m = 0; m < count; ++m)
+    if (!Ts || !Ts[m] || Ts[m]->w2 || Ts[m]->max_row_slots > kResidentRow) sched_ok = false;
+  struct Cand {
+    int kind, threads;
+    double ex;
+  };
+  std::vector<Cand> cands;
+  for (int threads : {512, 1024})
+    for (double wexp : {1.0, 1.5, 2.0}) cands.push_back({0, threads, wexp});
+  if (sched_ok)
+    for (int threads : {256, 512})
+      for (double dexp : {0.5, 1.0}) cands.push_back({1, threads, dexp});
   double bt = DBL_MAX;
-  int bthr = 0;
-  double bw = 0.0;
+  Cand best{-1, 0, 0.0};
   hipEvent_t e0 = nullptr, e1 = nullptr;
   EGFEM_HIP_CHECK(hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -567,45 +873,47 @@ int egfem_batch_autotune(int count, const egfem_tensor_t* Ts, const egfem_proble
     return fail(EGFEM_ERR_HIP, "hipEventCreate failed");
   }
   int rc = EGFEM_OK;
-  for (int threads : {512, 1024}) {
-    for (double wexp : {1.0, 1.5, 2.0}) {
-      egfem_batch_t B = nullptr;
-      rc = egfem_batch_create(count, Ts, ps, us, o, threads, wexp, &B);
-      if (rc != EGFEM_OK) break;
-      // a first run warms the handles and the plan; the second is timed
-      bool good = true;
-      float ms = 0.0f;
-      for (int rep = 0; rep < 2 && rc == EGFEM_OK; ++rep) {
-        if (rep == 1 && hipEventRecord(e0, st) != hipSuccess) rc = fail(EGFEM_ERR_HIP, "hipEventRecord failed");
-        if (rc == EGFEM_OK) rc = egfem_batch_run(B, 1, st);
-        if (rc == EGFEM_OK && rep == 1 && hipEventRecord(e1, st) != hipSuccess)
-          rc = fail(EGFEM_ERR_HIP, "hipEventRecord failed");
-        if (rc == EGFEM_OK) {
-          const int worst = egfem_batch_stats(B, stats.data(), st);
-          if (worst < 0) rc = worst;
-        }
-      }
-      // every instance converged, or stopped at the rounding floor of ||F||
-      for (int m = 0; rc == EGFEM_OK && m < count; ++m)
-        good = good && (stats[m].status == EGFEM_OK || stats[m].status == EGFEM_STAGNATED);
-      if (rc == EGFEM_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
-        rc = fail(EGFEM_ERR_HIP, "hipEventElapsedTime failed");
-      egfem_batch_destroy(B);
-      if (rc != EGFEM_OK) break;
-      if (good && ms < bt) {
-        bt = ms;
-        bthr = threads;
-        bw = wexp;
-      }
+  for (const Cand& c : cands) {
+    egfem_batch_t B = nullptr;
+    rc = c.kind == 1 ? egfem_batch_create_sched(count, Ts, ps, us, o, c.threads, c.ex, &B)
+                     : egfem_batch_create(count, Ts, ps, us, o, c.threads, c.ex, &B);
+    if (rc == EGFEM_ERR_SHAPE) {   // this shape does not fit the resident workgroups
+      rc = EGFEM_OK;
+      continue;
     }
     if (rc != EGFEM_OK) break;
+    // a first run warms the handles and the plan; the second is timed
+    bool good = true;
+    float ms = 0.0f;
+    for (int rep = 0; rep < 2 && rc == EGFEM_OK; ++rep) {
+      if (rep == 1 && hipEventRecord(e0, st) != hipSuccess) rc = fail(EGFEM_ERR_HIP, "hipEventRecord failed");
+      if (rc == EGFEM_OK) rc = egfem_batch_run(B, 1, st);
+      if (rc == EGFEM_OK && rep == 1 && hipEventRecord(e1, st) != hipSuccess)
+        rc = fail(EGFEM_ERR_HIP, "hipEventRecord failed");
+      if (rc == EGFEM_OK) {
+        const int worst = egfem_batch_stats(B, stats.data(), st);
+        if (worst < 0) rc = worst;
+      }
+    }
+    // every instance converged, or stopped at the rounding floor of ||F||
+    for (int m = 0; rc == EGFEM_OK && m < count; ++m)
+      good = good && (stats[m].status == EGFEM_OK || stats[m].status == EGFEM_STAGNATED);
+    if (rc == EGFEM_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      rc = fail(EGFEM_ERR_HIP, "hipEventElapsedTime failed");
+    egfem_batch_destroy(B);
+    if (rc != EGFEM_OK) break;
+    if (good && ms < bt) {
+      bt = ms;
+      best = c;
+    }
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (rc != EGFEM_OK) return rc;
-  if (bthr == 0) return fail(EGFEM_ERR_ARG, "no batch shape converged");
-  if (best_threads) *best_threads = bthr;
-  if (best_weight_exp) *best_weight_exp = bw;
+  if (best.kind < 0) return fail(EGFEM_ERR_ARG, "no batch shape converged");
+  if (best_kind) *best_kind = best.kind;
+  if (best_threads) *best_threads = best.threads;
+  if (best_exp) *best_exp = best.ex;
   if (best_ms) *best_ms = bt;
   return EGFEM_OK;
 }

@@ -201,8 +201,9 @@ __device__ __forceinline__ void action_load(const TensorView& T, int64_t b, cons
 //   PROBLEM: a = a0 + w^2, w = u + alpha delta (delta may be null);
 //            out = F = r - load, Dirichlet rows 0; uout (optional) = w;
 //            sq += F_i^2 over the rows this thread handled.
-// SH: u, delta gathered with agent-coherent loads and uout written with
-// agent-coherent stores (data produced by other workgroups of the same launch).
+// SH: u, delta gathered with agent-coherent loads, out and uout written with
+// agent-coherent stores (data produced or read by other workgroups of the same
+// launch).
 // Gathers are per slot (w and a at the slot's column, a into LDS); an entry
 // reads a_k from the LDS slot of (i, k).
 template <int NT, bool PROBLEM, bool SH, typename Lds>
@@ -285,7 +286,8 @@ __device__ __forceinline__ void action_compute(const ActionRegs<NT>& R, const do
       }
       sq = fma(acc, acc, sq);
     }
-    out[i] = acc;
+    if (SH) st_sh(out + i, acc);   // read by other workgroups of the launch (batched)
+    else out[i] = acc;
   }
   __syncthreads();   // LDS is reused by the next block
 }
@@ -466,8 +468,13 @@ __device__ void rowblock_jacobian(const TensorView& T, int64_t b, const double* 
           J = fma(g, qb, J);
         }
       }
-      jval[s0 + s] = J;
-      if (j == row && dinv) dinv[row] = 1.0 / J;
+      // SH: other workgroups of the launch may read these rows (batched)
+      if (SH) st_sh(jval + s0 + s, J);
+      else jval[s0 + s] = J;
+      if (j == row && dinv) {
+        if (SH) st_sh(dinv + row, 1.0 / J);
+        else dinv[row] = 1.0 / J;
+      }
     }
   }
   __syncthreads();   // LDS is reused by the next block
@@ -1627,13 +1634,15 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
 #pragma unroll
     for (int k = 0; k < K; ++k) vi[k] = A.perm[vi[k]];
   }
+  // row values, D^-1 and the right-hand side with agent-coherent loads: in a
+  // batched launch other workgroups of the team emitted them
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const double w = A.val[vi[k]];
+    const double w = ld_sh(A.val + vi[k]);
     aa[k] = (own && beg + k < end) ? w : 0.0;
   }
-  const double d = A.dinv[row];
-  const double b = A.rhs_scale * A.rhs[row];
+  const double d = ld_sh(A.dinv + row);
+  const double b = A.rhs_scale * ld_sh(A.rhs + row);
   ChebParams cp{1.0, 1.0, 1.0};
   if (bj) {
 #pragma unroll
@@ -1676,7 +1685,9 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
   const double bnorm = sqrt(red[1]);
   o.bnorm = bnorm;
   if (bnorm == 0.0) {
-    if (own) A.x[row] = 0.0;
+    // x is written coherently: inside a batched launch other workgroups of
+    // the team gather it before the launch ends
+    if (own) st_sh(A.x + row, 0.0);
     o.status = EGFEM_OK;
     return o;
   }
@@ -1774,7 +1785,7 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
     if ((o.abort = team_neighbor_sync(tm, sh_abort))) break;
   }
 #undef EGFEM_ZERO_RED
-  if (!o.abort && own) A.x[row] = x;
+  if (!o.abort && own) st_sh(A.x + row, x);
   o.iters = it;
   o.rnorm = rnorm;
   return o;

@@ -83,7 +83,6 @@ __global__ __launch_bounds__(NT) void k_pcg(LaunchArgs P) {
 // Register-resident forms: one thread per row, rows of at most K entries,
 // workgroups of at most kResidentMaxThreads threads (at 1024 threads a wave
 // may hold only 128 VGPRs and the resident BiCGStab would spill registers).
-constexpr int kResidentRow = 8;
 constexpr int kResidentMaxThreads = 512;
 
 template <int NT, int K>
