@@ -543,12 +543,23 @@ typedef struct {
   int krylov_threads;        /* persistent Krylov workgroup size 256/512/1024 (0 = default).  With
                                 both 0 (an untuned handle): 256-thread workgroups with one row per
                                 thread, ceil(n / 256) of them, where the register-resident kernel
-                                applies and that grid is co-resident; otherwise 1024 threads and
-                                min(ceil(n / 64), compute units) workgroups */
+                                applies and that grid is co-resident; else, in the Newton solver
+                                (egfem_newton) of a handle with the block-Jacobi preconditioner,
+                                1024-thread workgroups over the free rows (below) when they fit;
+                                otherwise 1024 threads and min(ceil(n / 64), compute units)
+                                workgroups of the streaming kernel */
   int krylov_kernel;         /* 0: register-resident BiCGStab (one thread per row) when every
                                 workgroup's rows fit its threads, rows hold at most 8 entries
                                 and workgroups have at most 512 threads, else the streaming
-                                one; with the block-Jacobi preconditioner the resident BiCGStab
+                                one.  Free rows: in egfem_newton the Dirichlet rows of the
+                                Newton system are identity rows with zero residual, so with
+                                1024-thread workgroups and the block-Jacobi preconditioner they
+                                are left out (their correction is 0) and the barrier-form
+                                resident BiCGStab runs one free row per thread on a compact
+                                partition of the free rows (2D 512x512: 261,121 free rows on
+                                256 workgroups, where 263,169 rows exceed the 256/512-thread
+                                resident grids); the partition is rebuilt when the Dirichlet
+                                mask's contents change.  With the block-Jacobi preconditioner the resident BiCGStab
                                 runs in its overlapped form: every exchanged value (reduction
                                 partials, gathered vector entries) carries its own completion
                                 flag, the preconditioner's Chebyshev steps run while the

@@ -428,8 +428,10 @@ int egfem_newton(egfem_tensor_t T, const egfem_problem* p, double* u, const egfe
                                      : opts.krylov_rtol;
     eta = rtol;
     KrylovResult kr;
+    // the Dirichlet rows are identity rows with zero residual: large systems
+    // leave them out of the resident solve
     rc = krylov_bicgstab(T, W.jval, W.dinv, W.F, -1.0, W.delta, true, rtol, opts.max_krylov,
-                         opts.krylov_blocks, &kr, st, nullptr, tm.on, opts.krylov_threads, true);
+                         opts.krylov_blocks, &kr, st, nullptr, tm.on, opts.krylov_threads, true, p->dirichlet);
     if (rc != EGFEM_OK) return rc;
     // the full step's trial residual is enqueued behind the solve, so one
     // synchronisation reads the solve's outcome and the trial norm

@@ -32,6 +32,19 @@ __device__ __forceinline__ double ld_sh(const double* p) {
 __device__ __forceinline__ void st_sh(double* p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Agent-coherent store at a 32-bit byte offset from a uniform base: the base
+// stays in scalar registers and the address is formed by the store itself,
+// so no 64-bit per-lane address has to be kept in vector registers.
+__device__ __forceinline__ void st_sh_at(double* base, unsigned off, double v) {
+  char* b = reinterpret_cast<char*>(base);
+  __asm__ volatile("" : "+s"(b));
+  st_sh(reinterpret_cast<double*>(b + off), v);
+}
+__device__ __forceinline__ double ld_sh_at(const double* base, unsigned off) {
+  const char* b = reinterpret_cast<const char*>(base);
+  __asm__ volatile("" : "+s"(b));
+  return ld_sh(reinterpret_cast<const double*>(b + off));
+}
 template <bool SH>
 __device__ __forceinline__ double ld(const double* p) {
   return SH ? ld_sh(p) : *p;
@@ -1122,6 +1135,16 @@ __device__ __forceinline__ double wave_sum(double x) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// A value every lane of the wave holds (a reduction total read from LDS),
+// moved to scalar registers: the compiler cannot prove it uniform by itself,
+// and kept in vector registers it costs one register per lane.
+__device__ __forceinline__ double uniform(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(unsigned)b);
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 template <int NT>
 constexpr int kShWords = kMaxRed * (NT / kWave) + kMaxRed;
 
@@ -1183,7 +1206,7 @@ __device__ bool team_reduce(Team& tm, int slot, double (&v)[kMaxRed], int m, dou
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < kMaxRed; ++q)
-    if (q < m) v[q] = sh[kMaxRed * NW + q];
+    if (q < m) v[q] = uniform(sh[kMaxRed * NW + q]);
   __syncthreads();   // sh is reused by the next reduction
   return false;
 }
@@ -1512,8 +1535,16 @@ struct ChebParams {
 // lmax of the workgroup: max over its rows of |d_i| (|J_ii| + sum_{in-block
 // j != i} |J_ij|) (own rows only; others contribute 0).  Every thread
 // returns the same value.
-template <int NT, int K>
-__device__ ChebParams cheb_params(const int (&li)[K], const double (&aa)[K], double ad, double d, double* lds) {
+// Part-local positions packed two per 32-bit register (positions < 2^16), for
+// kernels short of registers; indexed like the plain int array.
+template <int K>
+struct PackedLi {
+  unsigned w[(K + 1) / 2];
+  __device__ __forceinline__ int operator[](int k) const { return (int)((w[k >> 1] >> (16 * (k & 1))) & 0xffffu); }
+};
+
+template <int NT, int K, typename LI>
+__device__ ChebParams cheb_params(const LI& li, const double (&aa)[K], double ad, double d, double* lds) {
   double g = fabs(ad);
 #pragma unroll
   for (int k = 0; k < K; ++k) g += (li[k] < NT) ? fabs(aa[k]) : 0.0;
@@ -1526,6 +1557,7 @@ __device__ ChebParams cheb_params(const int (&li)[K], const double (&aa)[K], dou
   double lmax = 0.0;
 #pragma unroll
   for (int w = 0; w < NT / kWave; ++w) lmax = fmax(lmax, lds[w]);
+  lmax = uniform(lmax);
   __syncthreads();
   if (!(lmax > 0.0) || !isfinite(lmax)) lmax = 1.0;
   const double lmin = lmax / kChebRatio;
@@ -1560,8 +1592,8 @@ __device__ __forceinline__ void cheb_barrier() {
   else __syncthreads();
 }
 
-template <int NT, int K, int NV, bool LDS_ONLY = false>
-__device__ __forceinline__ void block_cheb(const int (&li)[K], const double (&aa)[K], double ad, double d,
+template <int NT, int K, int NV, bool LDS_ONLY = false, typename LI>
+__device__ __forceinline__ void block_cheb(const LI& li, const double (&aa)[K], double ad, double d,
                                            bool has_row, int steps, const ChebParams& c, double* lds,
                                            const double (&x)[NV], double (&z)[NV]) {
   const int tid = threadIdx.x;
@@ -1609,6 +1641,7 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
   const bool own = i < re;
   const int q = max(min(i, re - 1), 0);     // in bounds also for an empty row range
   const int row = A.rlist ? A.rlist[q] : q;
+  const unsigned roff = (unsigned)row * 8u;  // byte offset of the row in a vector (n < 2^28)
   const bool bj = A.cheb_steps > 0;         // block-Jacobi preconditioner (uniform)
   // ---- the row's matrix entries (clamped in the row, zero past its end) ----
   int vi[K], li[K];
@@ -1621,6 +1654,10 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
     cc[k] = (unsigned)A.col[vi[k]] * 8u;
     li[k] = NT;
   }
+  // the positions stay packed for the solve (two per register)
+  PackedLi<K> lp;
+#pragma unroll
+  for (int k = 0; k < (K + 1) / 2; ++k) lp.w[k] = 0u;
   double ad = 0.0;   // diagonal entry (block-Jacobi)
   if (bj) {
 #pragma unroll
@@ -1649,6 +1686,8 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
     for (int k = 0; k < K; ++k)
       if (own && beg + k < end && (int)(cc[k] / 8u) == row) ad = aa[k];
     cp = cheb_params<NT, K>(li, aa, ad, d, cheb_lds);
+#pragma unroll
+    for (int k = 0; k < K; ++k) lp.w[k >> 1] |= (unsigned)li[k] << (16 * (k & 1));
     if (threadIdx.x < 4) cheb_lds[(threadIdx.x >> 1) * 2 * (NT + 1) + (threadIdx.x & 1) * (NT + 1) + NT] = 0.0;
   }
   // M^-1 of this thread's row values: D^-1 or the block-Jacobi operator
@@ -1656,7 +1695,7 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
     if (!bj) return d * x1;
     const double xs[1] = {x1};
     double zs[1];
-    block_cheb<NT, K, 1>(li, aa, ad, d, own, A.cheb_steps, cp, cheb_lds, xs, zs);
+    block_cheb<NT, K, 1>(lp, aa, ad, d, own, A.cheb_steps, cp, cheb_lds, xs, zs);
     return zs[0];
   };
   // ---- r = b - J x ; rhat = p = r ; publish M^-1 r --------------------------
@@ -1672,22 +1711,29 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
     r = b - acc;
   }
   if (!own) r = 0.0;
-  double rh = r, p = r, v = 0.0, z = 0.0, sv = 0.0, tv = 0.0;
+  // the iterate x is updated once per iteration: it lives in memory (this
+  // thread's row, written coherently: inside a batched launch other workgroups
+  // of the team gather it before the launch ends), not in registers
+  if (own) st_sh_at(A.x, roff, x);
+  // the shadow residual r^ is read three times per iteration and written only
+  // at a restart: it lives in memory (this thread's row), not in registers
+  // (threads without a row alias the part's last row: only owners write)
+  double* const rhat_row = A.rhat + row;
+  if (own) *rhat_row = r;
+  double p = r, v = 0.0, z = 0.0, sv = 0.0, tv = 0.0;
   // this row's entries of the published vectors: M^-1 p, M^-1 r, M^-1 v
   double ph = prec1(r), rhh = ph, vhh = 0.0;
   EGFEM_ZERO_RED();
   if (own) {
-    st_sh(A.phat + row, ph);
-    st_sh(A.rh + row, rhh);
+    st_sh_at(A.phat, roff, ph);
+    st_sh_at(A.rh, roff, rhh);
     red[1] = b * b;
   }
   if ((o.abort = team_reduce<NT>(tm, 0, red, 2, sh, sh_abort))) return o;
   const double bnorm = sqrt(red[1]);
   o.bnorm = bnorm;
   if (bnorm == 0.0) {
-    // x is written coherently: inside a batched launch other workgroups of
-    // the team gather it before the launch ends
-    if (own) st_sh(A.x + row, 0.0);
+    if (own) st_sh_at(A.x, roff, 0.0);
     o.status = EGFEM_OK;
     return o;
   }
@@ -1700,8 +1746,8 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
     vhh = prec1(v);
     EGFEM_ZERO_RED();
     if (own) {
-      st_sh(A.vh + row, vhh);
-      red[0] = rh * v;
+      st_sh_at(A.vh, roff, vhh);
+      red[0] = *rhat_row * v;
       red[1] = r * r;
     }
     if ((o.abort = team_reduce<NT>(tm, slot, red, 2, sh, sh_abort))) break;
@@ -1719,10 +1765,10 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
       // lost bi-orthogonality: restart once from the current residual
       // (p = r, so M^-1 p is the published M^-1 r)
       if (restarts++ >= 1) { o.status = EGFEM_BREAKDOWN; break; }
-      rh = r;
+      if (own) *rhat_row = r;
       p = r;
       ph = rhh;
-      if (own) st_sh(A.phat + row, ph);
+      if (own) st_sh_at(A.phat, roff, ph);
       rho = red[1];
       r0norm = rnorm;   // the test above scales by the new shadow residual
       if ((o.abort = team_barrier(tm, sh_abort))) break;
@@ -1739,8 +1785,9 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
       if (own) {
         red[0] = tv * sv;
         red[1] = tv * tv;
-        red[2] = rh * sv;
-        red[3] = rh * tv;
+        const double rhv = *rhat_row;
+        red[2] = rhv * sv;
+        red[3] = rhv * tv;
         red[4] = sv * sv;
       }
     }
@@ -1748,7 +1795,7 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
     slot = slot % 6 + 1;
     ++it;
     if (sqrt(red[4]) <= A.rtol * bnorm) {
-      x = fma(alpha, ph, x);
+      if (own) st_sh_at(A.x, roff, fma(alpha, ph, ld_sh_at(A.x, roff)));
       rnorm = sqrt(red[4]);
       o.status = EGFEM_OK;
       break;
@@ -1763,13 +1810,13 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
     const double beta = (rho_new / rho) * (alpha / omega);
     rho = rho_new;
     // C: x, r, p ; publish M^-1 p, M^-1 r  (M^-1 s = M^-1 r - alpha M^-1 v)
-    x = fma(alpha, ph, fma(omega, bj ? fma(-alpha, vhh, rhh) : d * sv, x));
+    if (own) st_sh_at(A.x, roff, fma(alpha, ph, fma(omega, bj ? fma(-alpha, vhh, rhh) : d * sv, ld_sh_at(A.x, roff))));
     r = fma(-omega, tv, sv);
     p = fma(beta, fma(-omega, v, p), r);
     if (bj) {
       const double xs[2] = {p, r};
       double zs[2];
-      block_cheb<NT, K, 2>(li, aa, ad, d, own, A.cheb_steps, cp, cheb_lds, xs, zs);
+      block_cheb<NT, K, 2>(lp, aa, ad, d, own, A.cheb_steps, cp, cheb_lds, xs, zs);
       ph = zs[0];
       rhh = zs[1];
     } else {
@@ -1777,15 +1824,15 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
       rhh = d * r;
     }
     if (own) {
-      st_sh(A.phat + row, ph);
-      st_sh(A.rh + row, rhh);
+      st_sh_at(A.phat, roff, ph);
+      st_sh_at(A.rh, roff, rhh);
     }
     // phase A gathers M^-1 p and M^-1 r of neighbouring rows only; the two
     // team reductions before the next overwrite keep the reads ahead of it
     if ((o.abort = team_neighbor_sync(tm, sh_abort))) break;
   }
 #undef EGFEM_ZERO_RED
-  if (!o.abort && own) st_sh(A.x + row, x);
+
   o.iters = it;
   o.rnorm = rnorm;
   return o;

@@ -38,8 +38,10 @@ struct CompactPartition {
   std::vector<int32_t> nbr;     // [G][kMaxNbrLists + 1] neighbour lists (count or -1, parts)
   int maxrows = 0;
 };
+// skip (host, nullable): rows marked nonzero are left out of every part (the
+// Dirichlet rows of a Newton system: identity rows with zero right-hand side).
 int make_compact_partition(int dim, const double* X, int64_t n, const int32_t* rowptr, const int32_t* col, int G,
-                           CompactPartition& out);
+                           CompactPartition& out, const uint8_t* skip = nullptr);
 // Neighbour lists [G][kMaxNbrLists + 1]: when any workgroup's list overflowed
 // (count -1), mark every list -1 (all workgroups then take the team barrier).
 void uniform_neighbor_lists(std::vector<int32_t>& nbr, int G);
@@ -79,6 +81,11 @@ struct Workspace {
   double* partial = nullptr;    // per-workgroup partial sums of the action kernel [row_blocks]
   double* red = nullptr;        // persistent-kernel reduction slots [kRedSlots * 8 * kMaxKrylovBlocks]
   unsigned* ctrl = nullptr;     // barrier counters / epoch / abort flag [kCtrlWordsMax] (device)
+  // free-row partition (rows left out of the resident solve): the mask it was
+  // built for (host copy) and its device pointer
+  std::vector<uint8_t> crow_skip;
+  const uint8_t* crow_skip_dev = nullptr;
+  bool crow_free = false;       // the compact partition in crow/crlist leaves those rows out
   double* qslot = nullptr;      // per-slot scratch [qslot_len >= slots] (mode-3 contraction,
                                 //   f on the dofs of W_h in the Burgers group steps)
   int64_t qslot_len = 0;
@@ -312,14 +319,14 @@ enum class KrylovMethod { kBiCGStab, kCG };
 int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, const double* dinv,
                  const double* rhs, double rhs_scale, double* x, bool x_zero, double rtol, bool rel_r0,
                  int max_iter, int blocks, KrylovResult* res, hipStream_t st, const int32_t* perm,
-                 bool timed = false, int threads = 0, bool defer = false);
+                 bool timed = false, int threads = 0, bool defer = false, const uint8_t* skip_rows = nullptr);
 int krylov_collect(egfem_tensor_s* T, hipStream_t st, KrylovResult* res);
 inline int krylov_bicgstab(egfem_tensor_s* T, const double* jval, const double* dinv, const double* rhs,
                            double rhs_scale, double* x, bool x_zero, double rtol, int max_iter, int blocks,
                            KrylovResult* res, hipStream_t st, const int32_t* perm, bool timed = false,
-                           int threads = 0, bool defer = false) {
+                           int threads = 0, bool defer = false, const uint8_t* skip_rows = nullptr) {
   return krylov_solve(KrylovMethod::kBiCGStab, T, jval, dinv, rhs, rhs_scale, x, x_zero, rtol, false, max_iter,
-                      blocks, res, st, perm, timed, threads, defer);
+                      blocks, res, st, perm, timed, threads, defer, skip_rows);
 }
 
 // Workspace

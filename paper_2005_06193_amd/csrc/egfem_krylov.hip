@@ -81,13 +81,17 @@ __global__ __launch_bounds__(NT) void k_pcg(LaunchArgs P) {
 }
 
 // Register-resident forms: one thread per row, rows of at most K entries,
-// workgroups of at most kResidentMaxThreads threads (at 1024 threads a wave
-// may hold only 128 VGPRs and the resident BiCGStab would spill registers).
+// workgroups of at most kResidentMaxThreads threads; the barrier-form BiCGStab
+// also at 1024 threads (a lane then holds at most 128 VGPRs: it keeps its
+// shadow residual in memory and its reduction totals in scalar registers).
 constexpr int kResidentMaxThreads = 512;
 
 template <int NT, int K>
 __global__ __launch_bounds__(NT) void k_bicgstab_reg(LaunchArgs P) {
   EGFEM_TEAM_PROLOGUE();
+  // at 1024 threads the point-to-point synchronisation's registers do not fit
+  // beside the row's: the team barrier stands in for it
+  if constexpr (NT > kResidentMaxThreads) tm.nbr = nullptr;
   write_out(P, dev::team_bicgstab_reg<NT, K>(tm, P.A, rb, re, sh, &sh_abort));
 }
 
@@ -153,7 +157,9 @@ const void* kernel_NT(KrylovMethod m, bool resident, int rs) {
       return m == KrylovMethod::kCG ? (const void*)k_pcg_reg<NT, kResidentRow>
                                     : (const void*)k_bicgstab_reg<NT, kResidentRow>;
   } else {
-    if (resident) return nullptr;
+    // 1024 threads: the barrier-form BiCGStab only (fits the 128 registers a
+    // lane has at that size, no spill), for the free-row partition
+    if (resident) return m == KrylovMethod::kBiCGStab ? (const void*)k_bicgstab_reg<NT, kResidentRow> : nullptr;
   }
   switch (rs) {
     case 0: return streaming_kernel<NT, 0>(m);
@@ -214,24 +220,52 @@ static void make_partition(const egfem_tensor_s* T, int G, std::vector<int32_t>&
 int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, const double* dinv,
                  const double* rhs, double rhs_scale, double* x, bool x_zero, double rtol, bool rel_r0,
                  int max_iter, int blocks, KrylovResult* res, hipStream_t st, const int32_t* perm, bool timed,
-                 int threads, bool defer) {
+                 int threads, bool defer, const uint8_t* skip_rows) {
   int rc = ensure_workspace(T);
   if (rc != EGFEM_OK) return rc;
   Workspace& W = T->ws;
   if (threads == 0) threads = T->tuned_krylov_threads;
   if (blocks <= 0) blocks = T->tuned_krylov_blocks;
+  // Free-row resident BiCGStab: rows marked in skip_rows (the Newton system's
+  // Dirichlet rows: identity rows, zero right-hand side, zero columns) are left
+  // out of the solve (their x is 0), so that one row per thread of 1024-thread
+  // workgroups covers systems above the 256/512-thread resident capacity.
+  const bool free_ok = skip_rows && method == KrylovMethod::kBiCGStab && !perm && T->krylov_kernel != 1 &&
+                       T->max_row_slots <= kResidentRow && T->krylov_precond > 0 && !T->h_coords.empty() &&
+                       T->n < (int64_t(1) << 28);
+  int64_t n_free = T->n;
+  if (free_ok) {
+    // the mask as it is now (it is compared, not trusted, on every call)
+    std::vector<uint8_t> hm((size_t)T->n);
+    EGFEM_HIP_CHECK(hipMemcpyAsync(hm.data(), skip_rows, hm.size(), hipMemcpyDeviceToHost, st));
+    EGFEM_HIP_CHECK(hipStreamSynchronize(st));
+    if (W.crow_skip != hm || W.crow_skip_dev != skip_rows) {
+      W.crow_skip.swap(hm);
+      W.crow_skip_dev = skip_rows;
+      W.crow_blocks = 0;   // a free-row partition built for another mask is stale
+    }
+    n_free = 0;
+    for (uint8_t b : W.crow_skip) n_free += b ? 0 : 1;
+  }
   if (threads == 0 && blocks <= 0 && T->krylov_kernel != 1 && T->max_row_slots <= kResidentRow &&
       T->n <= (int64_t)256 * kMaxKrylovBlocks) {
     // untuned, register-resident: 256-thread workgroups, one row per thread,
     // as few as that allows (largest block-Jacobi parts); kept only when the
-    // grid is co-resident
+    // grid is co-resident; above that, 1024-thread workgroups on the free rows
     const int g = (int)((T->n + 255) / 256);
+    const int gf = (int)((n_free + 1023) / 1024);
     if (g <= coresident(kernel_for(256, method, true, 0), 256)) {
       threads = 256;
       blocks = g;
+    } else if (free_ok && n_free > 0 && gf <= coresident(kernel_for(1024, method, true, 0), 1024)) {
+      threads = 1024;
+      blocks = gf;
     }
   }
   const int NT = (threads == 256 || threads == 512 || threads == 1024) ? threads : kKrylovThreads;
+  // the free-row partition serves the 1024-thread resident form only
+  const bool free_rows = free_ok && NT == 1024 && n_free > 0;
+  if (free_rows) blocks = std::max(blocks, (int)((n_free + NT - 1) / NT));
   const int cap = coresident(kernel_for(NT, method, false, T->krylov_rs), NT);
   if (cap <= 0) return fail(EGFEM_ERR_HIP, "Krylov kernel cannot be resident");
   int G = blocks;
@@ -243,6 +277,7 @@ int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, con
     G = (int)std::min<int64_t>((T->n + 63) / 64, (int64_t)cus);
   }
   G = std::max(1, std::min({G, cap, kMaxKrylovBlocks, (int)T->n}));
+  if (free_rows) G = std::min<int64_t>(G, n_free);   // every part holds a free row
   if (W.krow_blocks != G) {
     std::vector<int32_t> kr;
     make_partition(T, G, kr);
@@ -278,14 +313,16 @@ int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, con
   // (columns are held as 32-bit byte offsets: n < 2^28)
   const void* kreg = kernel_for(NT, method, true, 0);   // null above kResidentMaxThreads
   const bool resident_ok = kreg && T->krylov_kernel != 1 && T->max_row_slots <= kResidentRow &&
-                           T->n < (int64_t(1) << 28) && G <= coresident(kreg, NT);
+                           T->n < (int64_t(1) << 28) && G <= coresident(kreg, NT) && (NT <= 512 || free_rows);
   // block-Jacobi preconditioner: the resident kernels on a compact partition
-  bool block = resident_ok && T->krylov_precond > 0 && !T->h_coords.empty() && (T->n + G - 1) / G <= NT;
-  if (block && W.crow_blocks != G) {
+  // (of the free rows at 1024 threads)
+  bool block = resident_ok && T->krylov_precond > 0 && !T->h_coords.empty() && (n_free + G - 1) / G <= NT;
+  if (block && (W.crow_blocks != G || W.crow_free != free_rows)) {
     CompactPartition cp;
     if ((rc = make_compact_partition(T->dim, T->h_coords.data(), T->n, T->h_rowptr.data(), T->h_col.data(), G,
-                                     cp)) != EGFEM_OK)
+                                     cp, free_rows ? W.crow_skip.data() : nullptr)) != EGFEM_OK)
       return rc;
+    W.crow_free = free_rows;
     if (!W.crlist) {
       if (hipMalloc((void**)&W.crow, ((size_t)kMaxKrylovBlocks + 1) * sizeof(int32_t)) != hipSuccess ||
           hipMalloc((void**)&W.cnbr, (size_t)kMaxKrylovBlocks * (kMaxNbrLists + 1) * sizeof(int32_t)) !=
@@ -401,7 +438,7 @@ int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, con
   // the overlapped block-Jacobi BiCGStab (flag-in-data synchronisation) where
   // the block preconditioner runs, unless the shape asks for the barrier form
   const void* kov = nullptr;
-  if (block && T->krylov_kernel == 0 && W.crow_maxghost <= NT && W.ckext) {
+  if (block && NT <= 512 && T->krylov_kernel == 0 && W.crow_maxghost <= NT && W.ckext) {
     if (method == KrylovMethod::kBiCGStab)
       kov = NT == 256 ? (const void*)k_bicgstab_ov<256> : (const void*)k_bicgstab_ov<512>;
     else
@@ -437,6 +474,14 @@ int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, con
     P.ov.tot = P.ov.part + (size_t)2 * dev::kAggValues * 2 * kMaxKrylovBlocks;
     P.ov.exit_word = P.ov.tot + 2 * dev::kAggValues * 2;
     P.ov.salt = W.ll_salt;
+  }
+  if (free_rows && block) {
+    // rows left out are never written: x = 0 there, and the published
+    // vectors hold 0 where the solve gathers them with zero matrix entries
+    EGFEM_HIP_CHECK(launch_fill(x, 0.0, T->n, st));
+    EGFEM_HIP_CHECK(launch_fill(W.phat, 0.0, T->n, st));
+    EGFEM_HIP_CHECK(launch_fill(W.rh, 0.0, T->n, st));
+    EGFEM_HIP_CHECK(launch_fill(W.vh, 0.0, T->n, st));
   }
   const void* kern = overlapped ? kov : (resident ? kreg : kernel_for(NT, method, false, T->krylov_rs));
   void* args[] = {(void*)&P};

@@ -57,13 +57,18 @@ void uniform_neighbor_lists(std::vector<int32_t>& nbr, int G) {
 }
 
 int make_compact_partition(int dim, const double* X, int64_t n, const int32_t* rowptr, const int32_t* col, int G,
-                           CompactPartition& out) {
-  if (n <= 0 || G < 1 || G > n || dim < 1 || dim > 3) return fail(EGFEM_ERR_ARG, "invalid partition request");
-  std::vector<int32_t> idx(n);
-  std::iota(idx.begin(), idx.end(), 0);
+                           CompactPartition& out, const uint8_t* skip) {
+  if (n <= 0 || G < 1 || dim < 1 || dim > 3) return fail(EGFEM_ERR_ARG, "invalid partition request");
+  // the rows to partition: all, or those not marked in skip
+  std::vector<int32_t> idx;
+  idx.reserve((size_t)n);
+  for (int64_t i = 0; i < n; ++i)
+    if (!skip || !skip[i]) idx.push_back((int32_t)i);
+  const int64_t nr = (int64_t)idx.size();
+  if (nr == 0 || G > nr) return fail(EGFEM_ERR_ARG, "invalid partition request");
   out.kr.assign(G + 1, 0);
-  rcb(X, dim, idx, 0, (size_t)n, G, 0, out.kr);
-  std::vector<int32_t> owner(n), pos(n);
+  rcb(X, dim, idx, 0, (size_t)nr, G, 0, out.kr);
+  std::vector<int32_t> owner(n, -1), pos(n, 0);
   out.maxrows = 0;
   for (int g = 0; g < G; ++g) {
     // rows of a part in ascending order
@@ -77,10 +82,11 @@ int make_compact_partition(int dim, const double* X, int64_t n, const int32_t* r
   if (out.maxrows > 32767) return fail(EGFEM_ERR_SHAPE, "partition parts too large");
   out.rlist = idx;
   // per slot: the row-local position of its column when the same part owns it, else -1
+  // (rows left out own no part and keep -1)
   out.kloc.assign((size_t)rowptr[n], -1);
   for (int64_t i = 0; i < n; ++i)
     for (int32_t s = rowptr[i]; s < rowptr[i + 1]; ++s)
-      if (owner[col[s]] == owner[i]) out.kloc[s] = (int16_t)pos[col[s]];
+      if (owner[i] >= 0 && owner[col[s]] == owner[i]) out.kloc[s] = (int16_t)pos[col[s]];
   // neighbour lists: the other parts owning a column of this part's rows
   out.nbr.assign((size_t)G * (kMaxNbrLists + 1), 0);
   for (int g = 0; g < G; ++g) {
@@ -90,7 +96,7 @@ int make_compact_partition(int dim, const double* X, int64_t n, const int32_t* r
       const int32_t i = idx[q];
       for (int32_t s = rowptr[i]; s < rowptr[i + 1] && cnt >= 0; ++s) {
         const int o = owner[col[s]];
-        if (o == g) continue;
+        if (o == g || o < 0) continue;   // own part, or a row left out (never published)
         bool seen = false;
         for (int m = 0; m < cnt; ++m) seen = seen || lst[1 + m] == o;
         if (seen) continue;

@@ -598,6 +598,10 @@ def test_newton_full_size_semilinear_512():
     u = torch.zeros(T.n, dtype=torch.float64, device=DEV)
     st = T.newton(p, u, eg().NewtonOptions(tol=1e-12, krylov_rtol=1e-13), warn=False)
     assert st.status in (0, 4), st.status_name
+    # 263,169 rows exceed one row per thread of the 256/512-thread resident
+    # grids; the 261,121 free rows fit 1024-thread workgroups: resident
+    # block-Jacobi BiCGStab on the free-row partition
+    assert st.krylov_kernels == 5, st.krylov_kernels
     po = O.build_problem(wl)
     uo, sto = O.newton(po, tol=1e-12)
     ug = host(u)
@@ -656,3 +660,68 @@ def test_newton_timing_leaves_the_iteration_unchanged(kernel):
     assert s0.res_hist == s1.res_hist and s0.backtracks == s1.backtracks
     un, _ = O.newton(O.build_problem(wl), tol=1e-14)
     assert relerr(host(u1), un) <= 1e-8
+
+
+# ---------------------------------------------------------------------------
+# free-row resident BiCGStab (1024-thread workgroups, Dirichlet rows left out)
+# ---------------------------------------------------------------------------
+FREE_ROW_CASES = {
+    "2d_n96": lambda: W.nonlinear_diffusion_2d(96, seed=61),
+    "2d_semilinear_n64": lambda: W.semilinear_2d(64),
+    "1d_n3000": lambda: W.nonlinear_diffusion_1d(3000),
+}
+
+
+@pytest.mark.parametrize("name", list(FREE_ROW_CASES))
+def test_newton_free_rows_matches_oracle(name):
+    """Newton with 1024-thread Krylov workgroups: the Dirichlet rows (identity
+    rows, zero residual) are left out of the resident block-Jacobi BiCGStab,
+    which runs on a compact partition of the free rows; the solution equals
+    the oracle's element-wise, as with the default grid."""
+    wl = FREE_ROW_CASES[name]()
+    print(f"newton free rows {name}", flush=True)
+    T = eg().Tensor.from_mesh(wl.mesh, wl.form)
+    p = gpu_problem(T, wl)
+    opts = eg().NewtonOptions(tol=1e-13, krylov_rtol=1e-13)
+    uo, _ = O.newton(O.build_problem(wl), tol=1e-14, max_iter=40)
+    for kernel in (0, 2):     # both select the barrier form at 1024 threads
+        T.set_shape(krylov_threads=1024, krylov_blocks=0, krylov_kernel=kernel)
+        u = torch.zeros(T.n, dtype=torch.float64, device=DEV)
+        st = T.newton(p, u, opts, warn=False)
+        assert st.status in (0, 4), st.status_name
+        assert st.krylov_kernels == 5, st.krylov_kernels
+        ug = host(u)
+        assert relerr(ug, uo) < 1e-10
+        assert np.abs(ug - uo).max() <= 1e-10 * np.abs(uo).max()
+        assert np.all(ug[wl.mesh.dirichlet != 0] == 0.0)
+        # deterministic
+        u2 = torch.zeros(T.n, dtype=torch.float64, device=DEV)
+        st2 = T.newton(p, u2, opts, warn=False)
+        assert torch.equal(u, u2) and st2.krylov_iters == st.krylov_iters
+
+
+def test_newton_free_rows_mask_change_rebuilds_partition():
+    """The same handle solved with two different Dirichlet sets (the whole
+    boundary, then only the left and right walls, in one buffer rewritten in
+    place): the free-row partition follows the mask and both solutions equal
+    the oracle's."""
+    E = eg()
+    wl = W.nonlinear_diffusion_2d(64, seed=62)
+    m = wl.mesh
+    T = E.Tensor.from_mesh(m, wl.form)
+    T.set_shape(krylov_threads=1024, krylov_blocks=0)
+    load = T.matvec(dt(wl.f), "M")
+    mask = dt(m.dirichlet, torch.uint8)
+    p = E.Problem(T.n, load, mask, None, wl.a0_const, wl.add_stiffness)
+    x = np.asarray(m.coords)[:, 0]
+    walls = ((x <= 1e-12) | (x >= 1 - 1e-12)).astype(np.uint8)
+    for dmask in (np.asarray(m.dirichlet, np.uint8), walls):
+        mask.copy_(dt(dmask, torch.uint8))
+        u = torch.zeros(T.n, dtype=torch.float64, device=DEV)
+        st = T.newton(p, u, E.NewtonOptions(tol=1e-13, krylov_rtol=1e-13), warn=False)
+        assert st.status in (0, 4) and st.krylov_kernels == 5, (st.status_name, st.krylov_kernels)
+        wlm = W.Workload(wl.name, W.Mesh(m.dim, m.n, m.coords, m.cells, dmask), wl.f, wl.form, wl.a0,
+                         wl.a0_const, wl.add_stiffness, wl.tol, wl.seed)
+        po = O.build_problem(wlm)
+        uo, _ = O.newton(po, tol=1e-14, max_iter=40)
+        assert relerr(host(u), uo) < 1e-10
