@@ -576,12 +576,15 @@ typedef struct {
                                 D^-1; k in 2..32 = block-Jacobi (default 8): the rows are split
                                 by recursive coordinate bisection into one compact part per
                                 workgroup, and each workgroup applies k Chebyshev steps (Jacobi
-                                scaled, interval [lmax/30, lmax], lmax the Gershgorin bound of
+                                scaled, interval [lmax/ratio, lmax], ratio = krylov_cheb_ratio
+                                (default 30), lmax the Gershgorin bound of
                                 D^-1 J_b) to its diagonal block J_b: a fixed linear operator,
                                 workgroup-local (LDS), with no synchronisation between
                                 workgroups.  The register-resident CG uses the same operator
                                 (symmetric positive definite for an SPD matrix: the polynomial
                                 is positive on the spectrum); streaming kernels use Jacobi. */
+  double krylov_cheb_ratio;  /* lmax / lmin of the Chebyshev interval of the block steps, in
+                                [2, 1000]; 0 = 30 (the default) */
 } egfem_launch_shape;
 
 int egfem_get_shape(egfem_tensor_t T, egfem_launch_shape* s);

@@ -103,7 +103,7 @@ class _GradCoef(C.Structure):
 class _Shape(C.Structure):
     _fields_ = [("action_runs", C.c_int), ("action_pipe", C.c_int), ("krylov_blocks", C.c_int),
                 ("krylov_threads", C.c_int), ("krylov_kernel", C.c_int), ("action_half", C.c_int),
-                ("krylov_precond", C.c_int)]
+                ("krylov_precond", C.c_int), ("krylov_cheb_ratio", C.c_double)]
 
 
 class _Stats(C.Structure):

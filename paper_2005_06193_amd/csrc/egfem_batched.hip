@@ -709,6 +709,7 @@ int egfem_batch_create_sched(int count, const egfem_tensor_t* Ts, const egfem_pr
     I.K.kloc = B->d_kloc + kloc_off[m];
     I.K.rlist = B->d_rlist + rlist_off[m];
     I.K.cheb_steps = Ts[m]->krylov_precond;
+    I.K.cheb_ratio = Ts[m]->krylov_cheb_ratio;
     I.kr = B->d_kr + kr_off[m];
     I.nbr = B->d_nbr + nbr_off[m];
     I.team_first = 0;

@@ -1234,6 +1234,7 @@ struct KArgs {
   const int32_t* rlist = nullptr;   // non-null: the workgroup's rows are rlist[rb, re)
   const int16_t* kloc = nullptr;    // [slots] position of the column in the row's part, or -1
   int cheb_steps = 0;               // 0: Jacobi D^-1; k >= 2: k Chebyshev steps on the workgroup's block
+  double cheb_ratio = 30.0;         // the steps' interval [lmax / cheb_ratio, lmax]
 };
 
 struct KOut {
@@ -1521,12 +1522,12 @@ __device__ __forceinline__ double row_dot(const unsigned (&off)[K], const double
 // same workgroup owns), and z = M_b^-1 x approximates J_b^-1 x by a fixed
 // number of Chebyshev steps with the Jacobi scaling D^-1 (Saad, Iterative
 // Methods for Sparse Linear Systems, Sec. 12.3) on the interval
-// [lmax / kChebRatio, lmax], lmax the workgroup's Gershgorin bound of
+// [lmax / ratio, lmax] (ratio 30 unless the handle's shape sets it), lmax the
+// workgroup's Gershgorin bound of
 // D^-1 J_b.  The result is a fixed polynomial of D^-1 J_b applied to D^-1 x,
 // i.e. a linear operator, as BiCGStab requires.  In-block products read the
 // other rows' step vectors from LDS: one workgroup barrier per step and no
 // traffic between workgroups.
-constexpr double kChebRatio = 30.0;
 
 struct ChebParams {
   double theta, delta, sigma;   // centre and half width of the interval, theta / delta
@@ -1544,7 +1545,8 @@ struct PackedLi {
 };
 
 template <int NT, int K, typename LI>
-__device__ ChebParams cheb_params(const LI& li, const double (&aa)[K], double ad, double d, double* lds) {
+__device__ ChebParams cheb_params(const LI& li, const double (&aa)[K], double ad, double d, double* lds,
+                                  double ratio) {
   double g = fabs(ad);
 #pragma unroll
   for (int k = 0; k < K; ++k) g += (li[k] < NT) ? fabs(aa[k]) : 0.0;
@@ -1560,7 +1562,7 @@ __device__ ChebParams cheb_params(const LI& li, const double (&aa)[K], double ad
   lmax = uniform(lmax);
   __syncthreads();
   if (!(lmax > 0.0) || !isfinite(lmax)) lmax = 1.0;
-  const double lmin = lmax / kChebRatio;
+  const double lmin = lmax / ratio;
   ChebParams c;
   c.theta = 0.5 * (lmax + lmin);
   c.delta = 0.5 * (lmax - lmin);
@@ -1685,7 +1687,7 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
 #pragma unroll
     for (int k = 0; k < K; ++k)
       if (own && beg + k < end && (int)(cc[k] / 8u) == row) ad = aa[k];
-    cp = cheb_params<NT, K>(li, aa, ad, d, cheb_lds);
+    cp = cheb_params<NT, K>(li, aa, ad, d, cheb_lds, A.cheb_ratio);
 #pragma unroll
     for (int k = 0; k < K; ++k) lp.w[k >> 1] |= (unsigned)li[k] << (16 * (k & 1));
     if (threadIdx.x < 4) cheb_lds[(threadIdx.x >> 1) * 2 * (NT + 1) + (threadIdx.x & 1) * (NT + 1) + NT] = 0.0;
@@ -1892,7 +1894,7 @@ __device__ KOut team_pcg_reg(Team& tm, const KArgs& A, int rb, int re, double* s
 #pragma unroll
     for (int k = 0; k < K; ++k)
       if (own && beg + k < end && (int)(cc[k] / 8u) == row) ad = aa[k];
-    cp = cheb_params<NT, K>(li, aa, ad, d, cheb_lds);
+    cp = cheb_params<NT, K>(li, aa, ad, d, cheb_lds, A.cheb_ratio);
     if (threadIdx.x < 4) cheb_lds[(threadIdx.x >> 1) * 2 * (NT + 1) + (threadIdx.x & 1) * (NT + 1) + NT] = 0.0;
   }
   // M^-1 of this thread's row value: D^-1 or the block-Jacobi operator (SPD

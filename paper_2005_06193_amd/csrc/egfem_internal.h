@@ -137,6 +137,7 @@ struct egfem_tensor_s {
   int tuned_krylov_threads = 0;
   int krylov_kernel = 0;        // 0: register-resident where it fits, 1: streaming
   int krylov_precond = 8;       // 0: Jacobi; k >= 2: block-Jacobi, k Chebyshev steps per block (resident BiCGStab)
+  double krylov_cheb_ratio = 30.0;   // Chebyshev interval [lmax / ratio, lmax] of the block steps
   int device = 0;
   // W_h = P2 (Case 1, w2 = 1): k runs over the P2 dofs (vertices, then edges);
   // W_h = I_k (Case 3, w2 = 2): k runs over the quadrature points of the cells;

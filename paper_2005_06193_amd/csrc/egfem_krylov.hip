@@ -419,6 +419,7 @@ int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, con
     A.rlist = W.crlist;
     A.kloc = W.ckloc;
     A.cheb_steps = T->krylov_precond;
+    A.cheb_ratio = T->krylov_cheb_ratio;
   }
   P.ctrl = W.ctrl;
   P.red = W.red;

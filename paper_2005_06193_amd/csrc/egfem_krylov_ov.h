@@ -333,7 +333,7 @@ __device__ KOut team_bicgstab_ov(AggRed& ar, const KArgs& A, const OvArgs& O, in
   const bool bj = A.cheb_steps > 0;
   ChebParams cp{1.0, 1.0, 1.0};
   if (bj) {
-    cp = cheb_params<NT, K>(li, ab, ad, d, cheb_lds);
+    cp = cheb_params<NT, K>(li, ab, ad, d, cheb_lds, A.cheb_ratio);
     if (threadIdx.x < 4) cheb_lds[(threadIdx.x >> 1) * 2 * (NT + 1) + (threadIdx.x & 1) * (NT + 1) + NT] = 0.0;
   }
   if (threadIdx.x == 0) {
@@ -587,7 +587,7 @@ __device__ KOut team_pcg_ov(AggRed& ar, const KArgs& A, const OvArgs& O, int rb,
   const bool bj = A.cheb_steps > 0;
   ChebParams cp{1.0, 1.0, 1.0};
   if (bj) {
-    cp = cheb_params<NT, K>(li, ab, ad, d, cheb_lds);
+    cp = cheb_params<NT, K>(li, ab, ad, d, cheb_lds, A.cheb_ratio);
     if (threadIdx.x < 4) cheb_lds[(threadIdx.x >> 1) * 2 * (NT + 1) + (threadIdx.x & 1) * (NT + 1) + NT] = 0.0;
   }
   if (threadIdx.x == 0) xu[NT] = 0.0;

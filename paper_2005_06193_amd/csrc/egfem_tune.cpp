@@ -50,6 +50,7 @@ int egfem_get_shape(egfem_tensor_t T, egfem_launch_shape* s) {
   s->krylov_kernel = T->krylov_kernel;
   s->action_half = T->action_half;
   s->krylov_precond = T->krylov_precond;
+  s->krylov_cheb_ratio = T->krylov_cheb_ratio;
   return EGFEM_OK;
 }
 
@@ -60,7 +61,8 @@ int egfem_set_shape(egfem_tensor_t T, const egfem_launch_shape* s) {
       (s->krylov_threads != 0 && s->krylov_threads != 256 && s->krylov_threads != 512 &&
        s->krylov_threads != 1024) ||
       (s->krylov_kernel < 0 || s->krylov_kernel > 2) || (s->action_half != 0 && s->action_half != 1) ||
-      s->krylov_precond < 0 || s->krylov_precond == 1 || s->krylov_precond > 32)
+      s->krylov_precond < 0 || s->krylov_precond == 1 || s->krylov_precond > 32 ||
+      !(s->krylov_cheb_ratio == 0.0 || (s->krylov_cheb_ratio >= 2.0 && s->krylov_cheb_ratio <= 1000.0)))
     return fail(EGFEM_ERR_ARG, "invalid launch shape");
   if (s->action_half && !T->vH) return fail(EGFEM_ERR_ARG, "this tensor has no symmetric half stream");
   T->action_runs_target = s->action_runs;
@@ -70,6 +72,7 @@ int egfem_set_shape(egfem_tensor_t T, const egfem_launch_shape* s) {
   T->krylov_kernel = s->krylov_kernel;
   T->action_half = s->action_half;
   T->krylov_precond = s->krylov_precond;
+  T->krylov_cheb_ratio = s->krylov_cheb_ratio > 0.0 ? s->krylov_cheb_ratio : 30.0;
   return EGFEM_OK;
 }
 
@@ -179,8 +182,8 @@ int egfem_autotune(egfem_tensor_t T, const egfem_problem* p, int what, egfem_lau
             best_iter_us = 1000.0 * t_solve / stt.krylov_iters;
           }
         }
-    hipFree(u);
     if (rc != EGFEM_OK) {
+      hipFree(u);
       T->krylov_kernel = keep_kernel;
       T->tuned_krylov_blocks = keep_blocks;
       T->tuned_krylov_threads = keep_threads;
@@ -189,6 +192,54 @@ int egfem_autotune(egfem_tensor_t T, const egfem_problem* p, int what, egfem_lau
     T->tuned_krylov_blocks = bb;
     T->tuned_krylov_threads = bt;
     T->krylov_kernel = bk;
+    // the block preconditioner on that grid: Chebyshev steps x interval ratio,
+    // timed the same way (the handle's own setting is among the candidates)
+    const int keep_precond = T->krylov_precond;
+    const double keep_ratio = T->krylov_cheb_ratio;
+    int bpc = keep_precond;
+    double brat = keep_ratio;
+    if (keep_precond > 0) {
+      for (int steps : {6, 8, 10})
+        for (double ratio : {20.0, 30.0, 50.0}) {
+          if (steps == keep_precond && ratio == keep_ratio) continue;   // timed above
+          T->krylov_precond = steps;
+          T->krylov_cheb_ratio = ratio;
+          double t_solve = 0.0;
+          egfem_newton_stats stt;
+          bool usable = true;
+          for (int rep = 0; rep < 2 && usable; ++rep) {
+            if (launch_fill(u, 0.0, T->n, st) != hipSuccess) {
+              rc = fail(EGFEM_ERR_HIP, "fill of the autotuner's iterate failed");
+              break;
+            }
+            const auto t0 = std::chrono::steady_clock::now();
+            const int src = egfem_newton(T, p, u, &o, &stt, stream);
+            const auto t1 = std::chrono::steady_clock::now();
+            if (src < 0) {
+              rc = src;
+              break;
+            }
+            t_solve = std::chrono::duration<double, std::milli>(t1 - t0).count();
+            usable = src == EGFEM_OK && (stt.krylov_kernels & 4);   // the block preconditioner ran
+          }
+          if (rc != EGFEM_OK) break;
+          if (!usable || stt.krylov_iters <= 0) continue;
+          if (t_solve < best_t) {
+            best_t = t_solve;
+            bpc = steps;
+            brat = ratio;
+            best_iter_us = 1000.0 * t_solve / stt.krylov_iters;
+          }
+        }
+    }
+    hipFree(u);
+    T->krylov_precond = bpc;
+    T->krylov_cheb_ratio = brat;
+    if (rc != EGFEM_OK) {
+      T->krylov_precond = keep_precond;
+      T->krylov_cheb_ratio = keep_ratio;
+      return rc;
+    }
     us_krylov = best_iter_us;
   }
   if (best) egfem_get_shape(T, best);

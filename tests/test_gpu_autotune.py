@@ -63,6 +63,8 @@ def test_autotuned_handle_solves():
     res = T.autotune(p)
     s = res["shape"]
     assert s["action_pipe"] in (0, 1) and s["krylov_threads"] in (256, 512, 1024)
+    # the block preconditioner's steps and interval come from the tuner's candidates
+    assert s["krylov_precond"] in (6, 8, 10) and s["krylov_cheb_ratio"] in (20.0, 30.0, 50.0)
     assert res["action_us"] > 0 and res["krylov_iter_us"] > 0
     assert T.get_shape() == s
     u = torch.zeros(T.n, dtype=torch.float64, device=DEV)

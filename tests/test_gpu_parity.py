@@ -410,6 +410,32 @@ def test_block_preconditioner_shape_validation():
             T.set_shape(krylov_precond=bad)
     T.set_shape(krylov_precond=2)
     assert T.get_shape()["krylov_precond"] == 2
+    # the Chebyshev interval ratio: [2, 1000], 0 = the default 30
+    assert T.get_shape()["krylov_cheb_ratio"] == 30.0
+    for bad in (1.5, -1.0, 2000.0, float("nan")):
+        with pytest.raises(eg().EgfemError):
+            T.set_shape(krylov_cheb_ratio=bad)
+    T.set_shape(krylov_cheb_ratio=20.0)
+    assert T.get_shape()["krylov_cheb_ratio"] == 20.0
+    T.set_shape(krylov_cheb_ratio=0.0)
+    assert T.get_shape()["krylov_cheb_ratio"] == 30.0
+
+
+@pytest.mark.parametrize("ratio", [10.0, 20.0, 50.0, 200.0])
+def test_cheb_ratio_solves_to_oracle(ratio):
+    """Every Chebyshev interval ratio gives a fixed linear block preconditioner:
+    the overlapped and barrier-form BiCGStab solve the Newton systems to the
+    oracle's solution."""
+    wl = W.nonlinear_diffusion_2d(40, seed=71)
+    T = eg().Tensor.from_mesh(wl.mesh, wl.form)
+    p = gpu_problem(T, wl)
+    uo, _ = O.newton(O.build_problem(wl), tol=1e-14, max_iter=40)
+    for kernel in (0, 2):
+        T.set_shape(krylov_cheb_ratio=ratio, krylov_kernel=kernel)
+        u = torch.zeros(T.n, dtype=torch.float64, device=DEV)
+        st = T.newton(p, u, eg().NewtonOptions(tol=1e-13, krylov_rtol=1e-13), warn=False)
+        assert st.status in (0, 4) and st.krylov_kernels & 4, (st.status_name, st.krylov_kernels)
+        assert relerr(host(u), uo) < 1e-10
 
 
 # ---------------------------------------------------------------------------
