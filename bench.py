@@ -119,6 +119,18 @@ def load_traffic():
     return d
 
 
+def same_krylov_kernel(rec: dict, kernels_bits: int, shape: dict) -> bool:
+    """Whether the profiled Krylov kernel (overlapped or barrier form, threads
+    per workgroup, preconditioner steps) is the one this run launched: the
+    counters belong to one kernel, and the autotuner's choice can differ
+    between runs."""
+    prof = rec.get("shape", {})
+    overlapped = bool(kernels_bits & 8)
+    return (rec.get("kernel", "").startswith("k_bicgstab_ov") == overlapped
+            and prof.get("krylov_threads") == shape["krylov_threads"]
+            and prof.get("krylov_precond") == shape["krylov_precond"])
+
+
 # ----------------------------------------------------------------------------
 def gpu_setup(n: int):
     import numpy as np
@@ -258,7 +270,7 @@ def newton_config_suite(reps: int = 5) -> dict:
     return out
 
 
-def tensor_action_suite():
+def tensor_action_suite(with_graph: bool = True):
     """Raw tensor action and Jacobian emission on the three single-instance
     workload sizes (the larger two exceed what launch overhead hides)."""
     import paper_2005_06193_amd as eg
@@ -267,13 +279,14 @@ def tensor_action_suite():
     for name, wl in (("2d_256_stiff", W.nonlinear_diffusion_2d(256)),
                      ("2d_512_mass", W.semilinear_2d(512)),
                      ("3d_64_stiff", W.diffusion_3d(64))):
+        stage(f"tensor actions: {name}")
         T = eg.Tensor.from_mesh(wl.mesh, wl.form)
         p = device_problem(wl, T)
         tuned = T.autotune(p, krylov=False)
         info = T.info
         warm = time_action(T, 100, cold=False)
         cold = time_action(T, 20, cold=True)
-        graph = time_action_graph(T)
+        graph = time_action_graph(T) if with_graph else float("nan")
         jac = time_jacobian(T, p, 50)
         ba = bytes_action_raw(info)
         bj = bytes_jacobian(info, wl.add_stiffness)
@@ -826,6 +839,8 @@ def main():
     ap.add_argument("--no-burgers", action="store_true", help="skip the Burgers time stepping")
     ap.add_argument("--no-p2", action="store_true", help="skip the W_h = P2 / I_k coefficient solves")
     ap.add_argument("--no-gradient", action="store_true", help="skip the p-Laplace (W_h = P0) solves")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="tensor-action suite without the graph-replay timing (counter runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (scale reference for HBM counters)")
     ap.add_argument("--no-configs", action="store_true", help="skip the 1D-256 and 2D-512 Newton solves")
@@ -900,7 +915,8 @@ def main():
     achieved = bytes_per_launch / (avg_ms * 1e6)
     tr = load_traffic()
     traffic = None
-    if tr and dom == "krylov_bicgstab" and args.n == 256 and "krylov_bicgstab" in tr:
+    if tr and dom == "krylov_bicgstab" and args.n == 256 and "krylov_bicgstab" in tr \
+            and same_krylov_kernel(tr["krylov_bicgstab"], stats[0].krylov_kernels, T.get_shape()):
         iters_per_launch = k_it / max(n_kry, 1)
         traffic = tr["krylov_bicgstab"]["hbm_bytes_per_iteration"] * iters_per_launch
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
@@ -923,7 +939,7 @@ def main():
     stage("newton configurations")
     configs = None if args.no_configs else newton_config_suite()
     stage("tensor actions")
-    micro = None if args.no_micro else tensor_action_suite()
+    micro = None if args.no_micro else tensor_action_suite(with_graph=not args.no_graph)
     if micro is not None:
         micro["stream_ceiling"] = stream_ceiling()
     stage("batched")
