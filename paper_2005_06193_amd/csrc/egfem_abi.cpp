@@ -969,8 +969,11 @@ int egfem_adjoint(egfem_tensor_t T, const egfem_problem* p, const double* u, con
   EGFEM_HIP_CHECK(launch_copy(W.rhs, ubar, T->n, st));
   EGFEM_HIP_CHECK(launch_mask_zero(W.rhs, p->dirichlet, T->n, st));
   KrylovResult kr;
+  // DF's Dirichlet rows are identity rows and its Dirichlet columns zero, so
+  // DF^T has the same block form and the right-hand side is zero there:
+  // large systems leave those rows out of the resident solve (lambda = 0 there)
   rc = krylov_bicgstab(T, W.jval, W.dinv, W.rhs, 1.0, lambda, true, opts.krylov_rtol, opts.max_krylov,
-                       opts.krylov_blocks, &kr, st, T->tperm, false, opts.krylov_threads);
+                       opts.krylov_blocks, &kr, st, T->tperm, false, opts.krylov_threads, false, p->dirichlet);
   if (rc != EGFEM_OK) return rc;
   if (grad_a0) {
     // -sum_ij lambda_i T_ijk u_j : slot-wise (T ._2 u), then the transposed gather

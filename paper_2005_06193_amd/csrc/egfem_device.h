@@ -8,6 +8,8 @@
 // instance in the batched kernel).
 #pragma once
 
+#include <type_traits>
+
 #include "egfem_internal.h"
 
 namespace egfem {
@@ -1517,6 +1519,38 @@ __device__ __forceinline__ double row_dot(const unsigned (&off)[K], const double
   return acc;
 }
 
+// Rows wider than the K entries a thread holds in registers: entries K ..
+// K + KW - 1 of the row sit in LDS, in the thread's own slice (written and
+// read by that thread only, so no barrier orders them), laid out [entry][thread]
+// so that a wave's accesses fall in distinct banks.  NoWide stands for KW = 0.
+struct NoWide {
+  static constexpr int kw = 0;
+};
+
+template <int NT, int KW>
+struct WideLds {
+  static constexpr int kw = KW;
+  double val[KW * NT];      // value (0 past the row's end and for threads without a row)
+  unsigned off[KW * NT];    // column as a byte offset into a vector
+  uint16_t li[KW * NT];     // part-local position of an in-block off-diagonal entry, NT otherwise
+};
+
+// sum over the LDS-held entries of a_e x[col_e], x gathered coherently
+template <int NT, typename WX>
+__device__ __forceinline__ double wide_dot(const WX& wx, const double* x, double acc) {
+  if constexpr (WX::kw > 0) {
+    const char* base = reinterpret_cast<const char*>(x);
+    __asm__ volatile("" : "+s"(base));
+    const int tid = threadIdx.x;
+    double g[WX::kw];
+#pragma unroll
+    for (int e = 0; e < WX::kw; ++e) g[e] = ld_sh(reinterpret_cast<const double*>(base + wx.off[e * NT + tid]));
+#pragma unroll
+    for (int e = 0; e < WX::kw; ++e) acc = fma(wx.val[e * NT + tid], g[e], acc);
+  }
+  return acc;
+}
+
 // Block-Jacobi preconditioner of the register-resident BiCGStab.  The rows of
 // a workgroup form one diagonal block J_b of J (the entries whose column the
 // same workgroup owns), and z = M_b^-1 x approximates J_b^-1 x by a fixed
@@ -1544,12 +1578,17 @@ struct PackedLi {
   __device__ __forceinline__ int operator[](int k) const { return (int)((w[k >> 1] >> (16 * (k & 1))) & 0xffffu); }
 };
 
-template <int NT, int K, typename LI>
+template <int NT, int K, typename LI, typename WX = NoWide>
 __device__ ChebParams cheb_params(const LI& li, const double (&aa)[K], double ad, double d, double* lds,
-                                  double ratio) {
+                                  double ratio, const WX& wx = WX{}) {
   double g = fabs(ad);
 #pragma unroll
   for (int k = 0; k < K; ++k) g += (li[k] < NT) ? fabs(aa[k]) : 0.0;
+  if constexpr (WX::kw > 0) {
+#pragma unroll
+    for (int e = 0; e < WX::kw; ++e)
+      g += (wx.li[e * NT + threadIdx.x] < NT) ? fabs(wx.val[e * NT + threadIdx.x]) : 0.0;
+  }
   g *= fabs(d);
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) g = fmax(g, __shfl_xor(g, off));
@@ -1594,10 +1633,10 @@ __device__ __forceinline__ void cheb_barrier() {
   else __syncthreads();
 }
 
-template <int NT, int K, int NV, bool LDS_ONLY = false, typename LI>
+template <int NT, int K, int NV, bool LDS_ONLY = false, typename LI, typename WX = NoWide>
 __device__ __forceinline__ void block_cheb(const LI& li, const double (&aa)[K], double ad, double d,
                                            bool has_row, int steps, const ChebParams& c, double* lds,
-                                           const double (&x)[NV], double (&z)[NV]) {
+                                           const double (&x)[NV], double (&z)[NV], const WX& wx = WX{}) {
   const int tid = threadIdx.x;
   double r[NV], dd[NV];
 #pragma unroll
@@ -1619,6 +1658,11 @@ __device__ __forceinline__ void block_cheb(const LI& li, const double (&aa)[K], 
         double acc = ad * dd[v];
 #pragma unroll
         for (int e = 0; e < K; ++e) acc = fma(aa[e], buf[v * (NT + 1) + li[e]], acc);
+        if constexpr (WX::kw > 0) {
+#pragma unroll
+          for (int e = 0; e < WX::kw; ++e)
+            acc = fma(wx.val[e * NT + tid], buf[v * (NT + 1) + wx.li[e * NT + tid]], acc);
+        }
         r[v] -= acc;
       }
     }
@@ -1633,9 +1677,12 @@ __device__ __forceinline__ void block_cheb(const LI& li, const double (&aa)[K], 
   }
 }
 
-template <int NT, int K>
+template <int NT, int K, int KW = 0>
 __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, double* sh, int* sh_abort) {
   __shared__ double cheb_lds[4 * (NT + 1)];
+  // rows of up to K + KW entries: the KW past the first K in LDS
+  using WX = std::conditional_t<(KW > 0), WideLds<NT, KW>, NoWide>;
+  __shared__ WX wide;
   double red[kMaxRed];
   KOut o{EGFEM_NOT_CONVERGED, 0, 0.0, 0.0, false};
 #define EGFEM_ZERO_RED() for (int q_ = 0; q_ < kMaxRed; ++q_) red[q_] = 0.0
@@ -1682,12 +1729,33 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
   }
   const double d = ld_sh(A.dinv + row);
   const double b = A.rhs_scale * ld_sh(A.rhs + row);
+  if constexpr (KW > 0) {
+    // entries K .. K + KW - 1 (clamped in the row, zero past its end) to LDS
+#pragma unroll
+    for (int e = 0; e < KW; ++e) {
+      int sk = min(beg + K + e, end - 1);
+      const int ck = A.col[sk];
+      const bool in = own && beg + K + e < end;
+      int l = NT;
+      if (bj) {
+        const int kl = A.kloc[sk];
+        if (in && ck != row && kl >= 0) l = kl;
+      }
+      if (A.perm) sk = A.perm[sk];
+      const double w = ld_sh(A.val + sk);
+      const double wv = in ? w : 0.0;
+      if (bj && in && ck == row) ad = wv;
+      wide.val[e * NT + threadIdx.x] = wv;
+      wide.off[e * NT + threadIdx.x] = (unsigned)ck * 8u;
+      wide.li[e * NT + threadIdx.x] = (uint16_t)l;
+    }
+  }
   ChebParams cp{1.0, 1.0, 1.0};
   if (bj) {
 #pragma unroll
     for (int k = 0; k < K; ++k)
       if (own && beg + k < end && (int)(cc[k] / 8u) == row) ad = aa[k];
-    cp = cheb_params<NT, K>(li, aa, ad, d, cheb_lds, A.cheb_ratio);
+    cp = cheb_params<NT, K>(li, aa, ad, d, cheb_lds, A.cheb_ratio, wide);
 #pragma unroll
     for (int k = 0; k < K; ++k) lp.w[k >> 1] |= (unsigned)li[k] << (16 * (k & 1));
     if (threadIdx.x < 4) cheb_lds[(threadIdx.x >> 1) * 2 * (NT + 1) + (threadIdx.x & 1) * (NT + 1) + NT] = 0.0;
@@ -1697,7 +1765,7 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
     if (!bj) return d * x1;
     const double xs[1] = {x1};
     double zs[1];
-    block_cheb<NT, K, 1>(lp, aa, ad, d, own, A.cheb_steps, cp, cheb_lds, xs, zs);
+    block_cheb<NT, K, 1>(lp, aa, ad, d, own, A.cheb_steps, cp, cheb_lds, xs, zs, wide);
     return zs[0];
   };
   // ---- r = b - J x ; rhat = p = r ; publish M^-1 r --------------------------
@@ -1710,7 +1778,7 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
     double acc = aa[0] * g[0];
 #pragma unroll
     for (int k = 1; k < K; ++k) acc = fma(aa[k], g[k], acc);
-    r = b - acc;
+    r = b - wide_dot<NT>(wide, A.x, acc);
   }
   if (!own) r = 0.0;
   // the iterate x is updated once per iteration: it lives in memory (this
@@ -1743,8 +1811,8 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
   int restarts = 0, slot = 1, it = 0;
   while (true) {
     // A: v = J phat, z = J rh ; (rhat, v), (r, r)
-    v = row_dot<K>(cc, aa, A.phat);
-    z = row_dot<K>(cc, aa, A.rh);
+    v = wide_dot<NT>(wide, A.phat, row_dot<K>(cc, aa, A.phat));
+    z = wide_dot<NT>(wide, A.rh, row_dot<K>(cc, aa, A.rh));
     vhh = prec1(v);
     EGFEM_ZERO_RED();
     if (own) {
@@ -1780,7 +1848,7 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
     const double alpha = rho / rv;
     // B: y = J vh ; s, t
     {
-      const double y = row_dot<K>(cc, aa, A.vh);
+      const double y = wide_dot<NT>(wide, A.vh, row_dot<K>(cc, aa, A.vh));
       sv = fma(-alpha, v, r);
       tv = fma(-alpha, y, z);
       EGFEM_ZERO_RED();
@@ -1818,7 +1886,7 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
     if (bj) {
       const double xs[2] = {p, r};
       double zs[2];
-      block_cheb<NT, K, 2>(lp, aa, ad, d, own, A.cheb_steps, cp, cheb_lds, xs, zs);
+      block_cheb<NT, K, 2>(lp, aa, ad, d, own, A.cheb_steps, cp, cheb_lds, xs, zs, wide);
       ph = zs[0];
       rhh = zs[1];
     } else {

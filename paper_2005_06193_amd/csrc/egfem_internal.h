@@ -24,6 +24,7 @@ constexpr int kCapWSlots = 1024;  // W-slots per block (W_h = P2: P2 dofs couple
 constexpr int kKrylovThreads = 1024;
 constexpr int kMaxKrylovBlocks = 1024;
 constexpr int kResidentRow = 8;    // most entries of a row in the register-resident Krylov forms
+constexpr int kWideRow = 8;        // entries past those the 1024-thread resident BiCGStab keeps in LDS
 constexpr int kRedSlots = 10;     // reduction slots in flight (>= 2 barriers apart)
 constexpr int kCtrlWordsMax = 4096;  // barrier control words and publication flags
 constexpr int kMaxNbrLists = 16;     // neighbour workgroups kept per workgroup (more, for any

@@ -86,13 +86,15 @@ __global__ __launch_bounds__(NT) void k_pcg(LaunchArgs P) {
 // shadow residual in memory and its reduction totals in scalar registers).
 constexpr int kResidentMaxThreads = 512;
 
-template <int NT, int K>
+// KW > 0: rows of up to K + KW entries, the KW past the first K in LDS (the
+// 1024-thread form for 3D meshes, whose rows hold up to 15 entries).
+template <int NT, int K, int KW = 0>
 __global__ __launch_bounds__(NT) void k_bicgstab_reg(LaunchArgs P) {
   EGFEM_TEAM_PROLOGUE();
   // at 1024 threads the point-to-point synchronisation's registers do not fit
   // beside the row's: the team barrier stands in for it
   if constexpr (NT > kResidentMaxThreads) tm.nbr = nullptr;
-  write_out(P, dev::team_bicgstab_reg<NT, K>(tm, P.A, rb, re, sh, &sh_abort));
+  write_out(P, dev::team_bicgstab_reg<NT, K, KW>(tm, P.A, rb, re, sh, &sh_abort));
 }
 
 // Overlapped block-Jacobi BiCGStab on a compact partition (one thread per
@@ -150,16 +152,24 @@ const void* streaming_kernel(KrylovMethod m) {
   return m == KrylovMethod::kCG ? (const void*)k_pcg<NT, RS> : (const void*)k_bicgstab<NT, RS>;
 }
 
+// Resident kernels exist for rows of at most kResidentRow entries, and at
+// 1024 threads (BiCGStab) also for wide rows of up to kResidentRow + kWideRow;
+// null where there is none.
 template <int NT>
-const void* kernel_NT(KrylovMethod m, bool resident, int rs) {
+const void* kernel_NT(KrylovMethod m, bool resident, int rs, bool wide) {
   if constexpr (NT <= kResidentMaxThreads) {
+    if (resident && wide) return nullptr;
     if (resident)
       return m == KrylovMethod::kCG ? (const void*)k_pcg_reg<NT, kResidentRow>
                                     : (const void*)k_bicgstab_reg<NT, kResidentRow>;
   } else {
     // 1024 threads: the barrier-form BiCGStab only (fits the 128 registers a
     // lane has at that size, no spill), for the free-row partition
-    if (resident) return m == KrylovMethod::kBiCGStab ? (const void*)k_bicgstab_reg<NT, kResidentRow> : nullptr;
+    if (resident) {
+      if (m != KrylovMethod::kBiCGStab) return nullptr;
+      return wide ? (const void*)k_bicgstab_reg<NT, kResidentRow, kWideRow>
+                  : (const void*)k_bicgstab_reg<NT, kResidentRow>;
+    }
   }
   switch (rs) {
     case 0: return streaming_kernel<NT, 0>(m);
@@ -174,10 +184,10 @@ const void* kernel_NT(KrylovMethod m, bool resident, int rs) {
   }
 }
 
-const void* kernel_for(int NT, KrylovMethod m, bool resident, int rs) {
-  if (NT == 256) return kernel_NT<256>(m, resident, rs);
-  if (NT == 512) return kernel_NT<512>(m, resident, rs);
-  return kernel_NT<1024>(m, resident, rs);
+const void* kernel_for(int NT, KrylovMethod m, bool resident, int rs, bool wide = false) {
+  if (NT == 256) return kernel_NT<256>(m, resident, rs, wide);
+  if (NT == 512) return kernel_NT<512>(m, resident, rs, wide);
+  return kernel_NT<1024>(m, resident, rs, wide);
 }
 
 // Workgroups of this kernel that can be resident at once on the current
@@ -227,12 +237,15 @@ int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, con
   if (threads == 0) threads = T->tuned_krylov_threads;
   if (blocks <= 0) blocks = T->tuned_krylov_blocks;
   // Free-row resident BiCGStab: rows marked in skip_rows (the Newton system's
-  // Dirichlet rows: identity rows, zero right-hand side, zero columns) are left
-  // out of the solve (their x is 0), so that one row per thread of 1024-thread
-  // workgroups covers systems above the 256/512-thread resident capacity.
-  const bool free_ok = skip_rows && method == KrylovMethod::kBiCGStab && !perm && T->krylov_kernel != 1 &&
-                       T->max_row_slots <= kResidentRow && T->krylov_precond > 0 && !T->h_coords.empty() &&
-                       T->n < (int64_t(1) << 28);
+  // Dirichlet rows: identity rows, zero right-hand side, zero columns, so
+  // also for the transposed operator) are left out of the solve (their x is
+  // 0), so that one row per thread of 1024-thread workgroups covers systems
+  // above the 256/512-thread resident capacity.  Rows of up to
+  // kResidentRow + kWideRow entries (3D meshes) run this form only.
+  const bool wide = T->max_row_slots > kResidentRow;
+  const bool free_ok = skip_rows && x_zero && method == KrylovMethod::kBiCGStab && T->krylov_kernel != 1 &&
+                       T->max_row_slots <= kResidentRow + kWideRow && T->krylov_precond > 0 &&
+                       !T->h_coords.empty() && T->n < (int64_t(1) << 28);
   int64_t n_free = T->n;
   if (free_ok) {
     // the mask as it is now (it is compared, not trusted, on every call)
@@ -247,17 +260,18 @@ int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, con
     n_free = 0;
     for (uint8_t b : W.crow_skip) n_free += b ? 0 : 1;
   }
-  if (threads == 0 && blocks <= 0 && T->krylov_kernel != 1 && T->max_row_slots <= kResidentRow &&
+  if (threads == 0 && blocks <= 0 && T->krylov_kernel != 1 && T->max_row_slots <= kResidentRow + kWideRow &&
       T->n <= (int64_t)256 * kMaxKrylovBlocks) {
     // untuned, register-resident: 256-thread workgroups, one row per thread,
     // as few as that allows (largest block-Jacobi parts); kept only when the
-    // grid is co-resident; above that, 1024-thread workgroups on the free rows
+    // grid is co-resident; above that, or for wide rows, 1024-thread
+    // workgroups on the free rows
     const int g = (int)((T->n + 255) / 256);
     const int gf = (int)((n_free + 1023) / 1024);
-    if (g <= coresident(kernel_for(256, method, true, 0), 256)) {
+    if (!wide && g <= coresident(kernel_for(256, method, true, 0), 256)) {
       threads = 256;
       blocks = g;
-    } else if (free_ok && n_free > 0 && gf <= coresident(kernel_for(1024, method, true, 0), 1024)) {
+    } else if (free_ok && n_free > 0 && gf <= coresident(kernel_for(1024, method, true, 0, wide), 1024)) {
       threads = 1024;
       blocks = gf;
     }
@@ -311,8 +325,8 @@ int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, con
   // register-resident form when every workgroup's rows fit its threads, rows
   // hold at most kResidentRow entries, and the grid is co-resident for it
   // (columns are held as 32-bit byte offsets: n < 2^28)
-  const void* kreg = kernel_for(NT, method, true, 0);   // null above kResidentMaxThreads
-  const bool resident_ok = kreg && T->krylov_kernel != 1 && T->max_row_slots <= kResidentRow &&
+  const void* kreg = kernel_for(NT, method, true, 0, wide);   // null where there is none
+  const bool resident_ok = kreg && T->krylov_kernel != 1 && T->max_row_slots <= kResidentRow + kWideRow &&
                            T->n < (int64_t(1) << 28) && G <= coresident(kreg, NT) && (NT <= 512 || free_rows);
   // block-Jacobi preconditioner: the resident kernels on a compact partition
   // (of the free rows at 1024 threads)

@@ -695,6 +695,9 @@ FREE_ROW_CASES = {
     "2d_n96": lambda: W.nonlinear_diffusion_2d(96, seed=61),
     "2d_semilinear_n64": lambda: W.semilinear_2d(64),
     "1d_n3000": lambda: W.nonlinear_diffusion_1d(3000),
+    # 3D Kuhn rows hold up to 15 entries: 8 in registers, the rest in LDS
+    "3d_kappa_n12": lambda: W.diffusion_3d(12),
+    "3d_kappa_n17": lambda: W.diffusion_3d(17),
 }
 
 
@@ -724,6 +727,29 @@ def test_newton_free_rows_matches_oracle(name):
         u2 = torch.zeros(T.n, dtype=torch.float64, device=DEV)
         st2 = T.newton(p, u2, opts, warn=False)
         assert torch.equal(u, u2) and st2.krylov_iters == st.krylov_iters
+
+
+@pytest.mark.parametrize("n", [5, 10, 22])
+def test_newton_wide_rows_default_shape(n):
+    """3D meshes (rows of up to 15 entries) with the default launch shape: the
+    solve runs the 1024-thread resident block-Jacobi BiCGStab on the free
+    rows (one part for n = 5 and 10, several for n = 22: 9,261 free rows) and
+    equals the oracle's solution element-wise."""
+    wl = W.diffusion_3d(n)
+    print(f"newton wide rows default shape n={n}", flush=True)
+    T = eg().Tensor.from_mesh(wl.mesh, wl.form)
+    rowptr = np.asarray(T.pattern()[0])
+    assert np.diff(rowptr).max() == 15
+    p = gpu_problem(T, wl)
+    u = torch.zeros(T.n, dtype=torch.float64, device=DEV)
+    st = T.newton(p, u, eg().NewtonOptions(tol=1e-13, krylov_rtol=1e-13), warn=False)
+    assert st.status in (0, 4), st.status_name
+    assert st.krylov_kernels == 5, st.krylov_kernels
+    uo, _ = O.newton(O.build_problem(wl), tol=1e-14, max_iter=40)
+    ug = host(u)
+    assert relerr(ug, uo) < 1e-10
+    assert np.abs(ug - uo).max() <= 1e-10 * np.abs(uo).max()
+    assert np.all(ug[wl.mesh.dirichlet != 0] == 0.0)
 
 
 def test_newton_free_rows_mask_change_rebuilds_partition():
