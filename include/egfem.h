@@ -559,7 +559,14 @@ typedef struct {
                                 partition of the free rows (2D 512x512: 261,121 free rows on
                                 256 workgroups, where 263,169 rows exceed the 256/512-thread
                                 resident grids); the partition is rebuilt when the Dirichlet
-                                mask's contents change.  With the block-Jacobi preconditioner the resident BiCGStab
+                                mask's contents change.  3D meshes (rows of up to 16 entries)
+                                run only this form: 8 entries of a row in registers, the
+                                others in the thread's slice of LDS.  egfem_adjoint leaves the
+                                same rows out (DF^T keeps the identity rows and zero columns).
+                                At 1024 threads the products read LDS: the part's own rows and
+                                its ghosts (at most 1024, one coherent load per thread) are
+                                staged there before each product (kernel 2: every column
+                                gathered from memory).  With the block-Jacobi preconditioner the resident BiCGStab
                                 runs in its overlapped form: every exchanged value (reduction
                                 partials, gathered vector entries) carries its own completion
                                 flag, the preconditioner's Chebyshev steps run while the

@@ -1237,6 +1237,10 @@ struct KArgs {
   const int16_t* kloc = nullptr;    // [slots] position of the column in the row's part, or -1
   int cheb_steps = 0;               // 0: Jacobi D^-1; k >= 2: k Chebyshev steps on the workgroup's block
   double cheb_ratio = 30.0;         // the steps' interval [lmax / cheb_ratio, lmax]
+  // ghosts of every part (the products of the LDS-exchange form; part = workgroup)
+  const int16_t* kext = nullptr;    // [slots] part-local position of the column (>= 0) or -1 - ghost index
+  const int32_t* gptr = nullptr;    // [G + 1] ghost range of every part (at most NT ghosts)
+  const int32_t* gcol = nullptr;    // [ghosts] global column of every ghost
 };
 
 struct KOut {
@@ -1578,6 +1582,20 @@ struct PackedLi {
   __device__ __forceinline__ int operator[](int k) const { return (int)((w[k >> 1] >> (16 * (k & 1))) & 0xffffu); }
 };
 
+// Block positions derived from staging positions (the LDS-exchange form):
+// an in-part entry's staging position is its part-local position, the
+// diagonal's is the thread's own, ghosts and masked entries lie at NT and
+// above; only in-part off-diagonal entries belong to the block operator.
+template <int NT, int K>
+struct StagedLi {
+  const PackedLi<K>& px;
+  int tid;
+  __device__ __forceinline__ int operator[](int k) const {
+    const int p = px[k];
+    return (p < NT && p != tid) ? p : NT;
+  }
+};
+
 template <int NT, int K, typename LI, typename WX = NoWide>
 __device__ ChebParams cheb_params(const LI& li, const double (&aa)[K], double ad, double d, double* lds,
                                   double ratio, const WX& wx = WX{}) {
@@ -1677,7 +1695,14 @@ __device__ __forceinline__ void block_cheb(const LI& li, const double (&aa)[K], 
   }
 }
 
-template <int NT, int K, int KW = 0>
+// LX (one workgroup per part, ghost lists in A): the products gather from
+// LDS.  Before each product the workgroup stages the vector's entries of its
+// own rows (each thread its row's value, which it holds) and of its ghosts
+// (one coherent load per thread) in a staging vector of the Chebyshev buffer,
+// laid out like the Chebyshev vectors: own rows at [0, NT), the zero entry at
+// NT, ghost g at NT + 1 + g.  A row's entries then name LDS positions, and
+// only the ghosts come from the coherent memory level.
+template <int NT, int K, int KW = 0, bool LX = false>
 __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, double* sh, int* sh_abort) {
   __shared__ double cheb_lds[4 * (NT + 1)];
   // rows of up to K + KW entries: the KW past the first K in LDS
@@ -1694,16 +1719,27 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
   const bool bj = A.cheb_steps > 0;         // block-Jacobi preconditioner (uniform)
   // ---- the row's matrix entries (clamped in the row, zero past its end) ----
   int vi[K], li[K];
-  unsigned cc[K];   // columns as byte offsets into a vector
+  unsigned cc[LX ? 1 : K];   // columns as byte offsets into a vector (not LX)
+  int px[K];                 // staging positions (LX)
   double aa[K];
   const int beg = A.rowptr[row], end = A.rowptr[row + 1];
+  bool diag[K];     // the row's diagonal entry
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     vi[k] = min(beg + k, end - 1);
-    cc[k] = (unsigned)A.col[vi[k]] * 8u;
+    const int c = A.col[vi[k]];
+    diag[k] = own && beg + k < end && c == row;
+    if constexpr (LX) {
+      const int l = A.kext[vi[k]];
+      px[k] = (own && beg + k < end) ? (l >= 0 ? l : NT + 1 + (-1 - l)) : NT;
+    } else {
+      cc[k] = (unsigned)c * 8u;
+    }
     li[k] = NT;
   }
-  // the positions stay packed for the solve (two per register)
+  // the positions stay packed for the solve (two per register): the block
+  // positions, or (LX) the staging positions, from which the block positions
+  // follow
   PackedLi<K> lp;
 #pragma unroll
   for (int k = 0; k < (K + 1) / 2; ++k) lp.w[k] = 0u;
@@ -1712,7 +1748,7 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int l = A.kloc[vi[k]];
-      const bool offd = own && beg + k < end && (int)(cc[k] / 8u) != row;
+      const bool offd = own && beg + k < end && !diag[k];
       li[k] = (offd && l >= 0) ? l : NT;
     }
   }
@@ -1741,12 +1777,17 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
         const int kl = A.kloc[sk];
         if (in && ck != row && kl >= 0) l = kl;
       }
+      unsigned wofs = (unsigned)ck * 8u;
+      if constexpr (LX) {
+        const int x = A.kext[sk];
+        wofs = in ? (unsigned)(x >= 0 ? x : NT + 1 + (-1 - x)) : (unsigned)NT;
+      }
       if (A.perm) sk = A.perm[sk];
       const double w = ld_sh(A.val + sk);
       const double wv = in ? w : 0.0;
       if (bj && in && ck == row) ad = wv;
       wide.val[e * NT + threadIdx.x] = wv;
-      wide.off[e * NT + threadIdx.x] = (unsigned)ck * 8u;
+      wide.off[e * NT + threadIdx.x] = wofs;
       wide.li[e * NT + threadIdx.x] = (uint16_t)l;
     }
   }
@@ -1754,31 +1795,72 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
   if (bj) {
 #pragma unroll
     for (int k = 0; k < K; ++k)
-      if (own && beg + k < end && (int)(cc[k] / 8u) == row) ad = aa[k];
+      if (diag[k]) ad = aa[k];
     cp = cheb_params<NT, K>(li, aa, ad, d, cheb_lds, A.cheb_ratio, wide);
+    if constexpr (!LX) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) lp.w[k >> 1] |= (unsigned)li[k] << (16 * (k & 1));
+      for (int k = 0; k < K; ++k) lp.w[k >> 1] |= (unsigned)li[k] << (16 * (k & 1));
+    }
     if (threadIdx.x < 4) cheb_lds[(threadIdx.x >> 1) * 2 * (NT + 1) + (threadIdx.x & 1) * (NT + 1) + NT] = 0.0;
   }
+  if constexpr (LX) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) lp.w[k >> 1] |= (unsigned)px[k] << (16 * (k & 1));
+  }
+  const StagedLi<NT, K> sli{lp, (int)threadIdx.x};
   // M^-1 of this thread's row values: D^-1 or the block-Jacobi operator
   auto prec1 = [&](double x1) -> double {
     if (!bj) return d * x1;
     const double xs[1] = {x1};
     double zs[1];
-    block_cheb<NT, K, 1>(lp, aa, ad, d, own, A.cheb_steps, cp, cheb_lds, xs, zs, wide);
+    if constexpr (LX) block_cheb<NT, K, 1>(sli, aa, ad, d, own, A.cheb_steps, cp, cheb_lds, xs, zs, wide);
+    else block_cheb<NT, K, 1>(lp, aa, ad, d, own, A.cheb_steps, cp, cheb_lds, xs, zs, wide);
     return zs[0];
   };
+  // ---- LDS-exchange products (LX) -----------------------------------------
+  // this part's ghosts: thread t < ng stages ghost t
+  int ng = 0;
+  unsigned gofs = 0u;
+  if constexpr (LX) {
+    const int g0 = A.gptr[blockIdx.x];
+    ng = A.gptr[blockIdx.x + 1] - g0;
+    gofs = (unsigned)A.gcol[g0 + min((int)threadIdx.x, max(ng - 1, 0))] * 8u;
+  }
+  // S[own position] = this thread's row value, S[NT + 1 + t] = ghost t of vec
+  // (the zero entry S[NT] is never written: it is the Chebyshev buffer's)
+  auto stage = [&](double* S, double own_val, const double* vec) {
+    S[threadIdx.x] = own_val;
+    if ((int)threadIdx.x < ng) S[NT + 1 + threadIdx.x] = ld_sh_at(vec, gofs);
+  };
+  auto lds_dot = [&](const double* S) -> double {
+    double acc = aa[0] * S[lp[0]];
+#pragma unroll
+    for (int k = 1; k < K; ++k) acc = fma(aa[k], S[lp[k]], acc);
+    if constexpr (KW > 0) {
+#pragma unroll
+      for (int e = 0; e < KW; ++e) acc = fma(wide.val[e * NT + threadIdx.x], S[wide.off[e * NT + threadIdx.x]], acc);
+    }
+    return acc;
+  };
+  double* const S0 = cheb_lds;                 // staging vectors: the two Chebyshev buffers
+  double* const S1 = cheb_lds + 2 * (NT + 1);
   // ---- r = b - J x ; rhat = p = r ; publish M^-1 r --------------------------
   double x = 0.0, r = b;
   if (!A.x_zero) {
+    // once per solve: the columns from the matrix (LX rows name LDS positions)
     double g[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) g[k] = A.x[cc[k] / 8u];
+    for (int k = 0; k < K; ++k) g[k] = A.x[A.col[min(beg + k, end - 1)]];
     x = A.x[row];
     double acc = aa[0] * g[0];
 #pragma unroll
     for (int k = 1; k < K; ++k) acc = fma(aa[k], g[k], acc);
-    r = b - wide_dot<NT>(wide, A.x, acc);
+    if constexpr (KW > 0) {
+#pragma unroll
+      for (int e = 0; e < KW; ++e)
+        acc = fma(wide.val[e * NT + threadIdx.x], A.x[A.col[min(beg + K + e, end - 1)]], acc);
+    }
+    r = b - acc;
   }
   if (!own) r = 0.0;
   // the iterate x is updated once per iteration: it lives in memory (this
@@ -1790,7 +1872,9 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
   // (threads without a row alias the part's last row: only owners write)
   double* const rhat_row = A.rhat + row;
   if (own) *rhat_row = r;
-  double p = r, v = 0.0, z = 0.0, sv = 0.0, tv = 0.0;
+  // the direction p itself is not kept: its preconditioned form follows
+  // from the recurrence below
+  double v = 0.0, z = 0.0, sv = 0.0, tv = 0.0;
   // this row's entries of the published vectors: M^-1 p, M^-1 r, M^-1 v
   double ph = prec1(r), rhh = ph, vhh = 0.0;
   EGFEM_ZERO_RED();
@@ -1811,8 +1895,17 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
   int restarts = 0, slot = 1, it = 0;
   while (true) {
     // A: v = J phat, z = J rh ; (rhat, v), (r, r)
-    v = wide_dot<NT>(wide, A.phat, row_dot<K>(cc, aa, A.phat));
-    z = wide_dot<NT>(wide, A.rh, row_dot<K>(cc, aa, A.rh));
+    if constexpr (LX) {
+      __syncthreads();   // the last reads of the Chebyshev buffers are done
+      stage(S0, ph, A.phat);
+      stage(S1, rhh, A.rh);
+      __syncthreads();
+      v = lds_dot(S0);
+      z = lds_dot(S1);
+    } else {
+      v = wide_dot<NT>(wide, A.phat, row_dot<K>(cc, aa, A.phat));
+      z = wide_dot<NT>(wide, A.rh, row_dot<K>(cc, aa, A.rh));
+    }
     vhh = prec1(v);
     EGFEM_ZERO_RED();
     if (own) {
@@ -1836,7 +1929,6 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
       // (p = r, so M^-1 p is the published M^-1 r)
       if (restarts++ >= 1) { o.status = EGFEM_BREAKDOWN; break; }
       if (own) *rhat_row = r;
-      p = r;
       ph = rhh;
       if (own) st_sh_at(A.phat, roff, ph);
       rho = red[1];
@@ -1848,7 +1940,15 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
     const double alpha = rho / rv;
     // B: y = J vh ; s, t
     {
-      const double y = wide_dot<NT>(wide, A.vh, row_dot<K>(cc, aa, A.vh));
+      double y;
+      if constexpr (LX) {
+        __syncthreads();
+        stage(S0, vhh, A.vh);
+        __syncthreads();
+        y = lds_dot(S0);
+      } else {
+        y = wide_dot<NT>(wide, A.vh, row_dot<K>(cc, aa, A.vh));
+      }
       sv = fma(-alpha, v, r);
       tv = fma(-alpha, y, z);
       EGFEM_ZERO_RED();
@@ -1879,20 +1979,14 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
     const double rho_new = fma(-omega, red[3], red[2]);
     const double beta = (rho_new / rho) * (alpha / omega);
     rho = rho_new;
-    // C: x, r, p ; publish M^-1 p, M^-1 r  (M^-1 s = M^-1 r - alpha M^-1 v)
+    // C: x, r ; publish M^-1 p, M^-1 r  (M^-1 s = M^-1 r - alpha M^-1 v).
+    // M^-1 is linear, so p = r + beta (p - omega v) gives
+    // M^-1 p = M^-1 r + beta (M^-1 p - omega M^-1 v): one application per
+    // iteration (M^-1 r) besides M^-1 v
     if (own) st_sh_at(A.x, roff, fma(alpha, ph, fma(omega, bj ? fma(-alpha, vhh, rhh) : d * sv, ld_sh_at(A.x, roff))));
     r = fma(-omega, tv, sv);
-    p = fma(beta, fma(-omega, v, p), r);
-    if (bj) {
-      const double xs[2] = {p, r};
-      double zs[2];
-      block_cheb<NT, K, 2>(lp, aa, ad, d, own, A.cheb_steps, cp, cheb_lds, xs, zs, wide);
-      ph = zs[0];
-      rhh = zs[1];
-    } else {
-      ph = d * p;
-      rhh = d * r;
-    }
+    rhh = prec1(r);
+    ph = fma(beta, fma(-omega, vhh, ph), rhh);
     if (own) {
       st_sh_at(A.phat, roff, ph);
       st_sh_at(A.rh, roff, rhh);

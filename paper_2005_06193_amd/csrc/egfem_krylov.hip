@@ -88,13 +88,14 @@ constexpr int kResidentMaxThreads = 512;
 
 // KW > 0: rows of up to K + KW entries, the KW past the first K in LDS (the
 // 1024-thread form for 3D meshes, whose rows hold up to 15 entries).
-template <int NT, int K, int KW = 0>
+// LX: products from LDS (the part's own rows and its ghosts staged per product).
+template <int NT, int K, int KW = 0, bool LX = false>
 __global__ __launch_bounds__(NT) void k_bicgstab_reg(LaunchArgs P) {
   EGFEM_TEAM_PROLOGUE();
   // at 1024 threads the point-to-point synchronisation's registers do not fit
   // beside the row's: the team barrier stands in for it
   if constexpr (NT > kResidentMaxThreads) tm.nbr = nullptr;
-  write_out(P, dev::team_bicgstab_reg<NT, K, KW>(tm, P.A, rb, re, sh, &sh_abort));
+  write_out(P, dev::team_bicgstab_reg<NT, K, KW, LX>(tm, P.A, rb, re, sh, &sh_abort));
 }
 
 // Overlapped block-Jacobi BiCGStab on a compact partition (one thread per
@@ -156,9 +157,9 @@ const void* streaming_kernel(KrylovMethod m) {
 // 1024 threads (BiCGStab) also for wide rows of up to kResidentRow + kWideRow;
 // null where there is none.
 template <int NT>
-const void* kernel_NT(KrylovMethod m, bool resident, int rs, bool wide) {
+const void* kernel_NT(KrylovMethod m, bool resident, int rs, bool wide, bool lx) {
   if constexpr (NT <= kResidentMaxThreads) {
-    if (resident && wide) return nullptr;
+    if (resident && (wide || lx)) return nullptr;
     if (resident)
       return m == KrylovMethod::kCG ? (const void*)k_pcg_reg<NT, kResidentRow>
                                     : (const void*)k_bicgstab_reg<NT, kResidentRow>;
@@ -167,6 +168,9 @@ const void* kernel_NT(KrylovMethod m, bool resident, int rs, bool wide) {
     // lane has at that size, no spill), for the free-row partition
     if (resident) {
       if (m != KrylovMethod::kBiCGStab) return nullptr;
+      if (lx)
+        return wide ? (const void*)k_bicgstab_reg<NT, kResidentRow, kWideRow, true>
+                    : (const void*)k_bicgstab_reg<NT, kResidentRow, 0, true>;
       return wide ? (const void*)k_bicgstab_reg<NT, kResidentRow, kWideRow>
                   : (const void*)k_bicgstab_reg<NT, kResidentRow>;
     }
@@ -184,10 +188,10 @@ const void* kernel_NT(KrylovMethod m, bool resident, int rs, bool wide) {
   }
 }
 
-const void* kernel_for(int NT, KrylovMethod m, bool resident, int rs, bool wide = false) {
-  if (NT == 256) return kernel_NT<256>(m, resident, rs, wide);
-  if (NT == 512) return kernel_NT<512>(m, resident, rs, wide);
-  return kernel_NT<1024>(m, resident, rs, wide);
+const void* kernel_for(int NT, KrylovMethod m, bool resident, int rs, bool wide = false, bool lx = false) {
+  if (NT == 256) return kernel_NT<256>(m, resident, rs, wide, lx);
+  if (NT == 512) return kernel_NT<512>(m, resident, rs, wide, lx);
+  return kernel_NT<1024>(m, resident, rs, wide, lx);
 }
 
 // Workgroups of this kernel that can be resident at once on the current
@@ -401,6 +405,12 @@ int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, con
     }
   }
   block = block && W.crow_maxrows <= NT;   // one thread per row
+  // the 1024-thread form takes its products from LDS where every part's
+  // ghosts fit its threads
+  const void* klx = (block && NT == 1024 && W.ckext && W.crow_maxghost <= NT && T->krylov_kernel != 2)
+                        ? kernel_for(NT, method, true, 0, wide, true) : nullptr;
+  const bool lx = klx && G <= coresident(klx, NT);
+  if (lx) kreg = klx;
   EGFEM_HIP_CHECK(launch_fill_u32(W.ctrl, 0u, dev::kCtrlWords, st));
   LaunchArgs P;
   KArgs& A = P.A;
@@ -434,6 +444,11 @@ int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, con
     A.kloc = W.ckloc;
     A.cheb_steps = T->krylov_precond;
     A.cheb_ratio = T->krylov_cheb_ratio;
+  }
+  if (lx) {
+    A.kext = W.ckext;
+    A.gptr = W.cgptr;
+    A.gcol = W.cgcol;
   }
   P.ctrl = W.ctrl;
   P.red = W.red;
