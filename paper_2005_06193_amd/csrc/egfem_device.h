@@ -47,6 +47,17 @@ __device__ __forceinline__ double ld_sh_at(const double* base, unsigned off) {
   __asm__ volatile("" : "+s"(b));
   return ld_sh(reinterpret_cast<const double*>(b + off));
 }
+// Plain (row-local) load and store at a 32-bit byte offset from a uniform base.
+__device__ __forceinline__ void st_at(double* base, unsigned off, double v) {
+  char* b = reinterpret_cast<char*>(base);
+  __asm__ volatile("" : "+s"(b));
+  *reinterpret_cast<double*>(b + off) = v;
+}
+__device__ __forceinline__ double ld_at(const double* base, unsigned off) {
+  const char* b = reinterpret_cast<const char*>(base);
+  __asm__ volatile("" : "+s"(b));
+  return *reinterpret_cast<const double*>(b + off);
+}
 template <bool SH>
 __device__ __forceinline__ double ld(const double* p) {
   return SH ? ld_sh(p) : *p;
@@ -1531,12 +1542,27 @@ struct NoWide {
   static constexpr int kw = 0;
 };
 
-template <int NT, int KW>
+template <int NT, int KW, bool LX = false>
 struct WideLds {
   static constexpr int kw = KW;
   double val[KW * NT];      // value (0 past the row's end and for threads without a row)
   unsigned off[KW * NT];    // column as a byte offset into a vector
   uint16_t li[KW * NT];     // part-local position of an in-block off-diagonal entry, NT otherwise
+  __device__ __forceinline__ int blk(int i) const { return li[i]; }
+};
+
+// The LDS-exchange form keeps a value and a staging position per entry; the
+// block position follows from the staging position (in-part off-diagonal
+// entries only: the diagonal's position is the thread's own).
+template <int NT, int KW>
+struct WideLds<NT, KW, true> {
+  static constexpr int kw = KW;
+  double val[KW * NT];
+  uint16_t px[KW * NT];     // staging position (own rows [0, NT), zero entry NT, ghosts above)
+  __device__ __forceinline__ int blk(int i) const {
+    const int p = px[i];
+    return (p < NT && p != (int)threadIdx.x) ? p : NT;
+  }
 };
 
 // sum over the LDS-held entries of a_e x[col_e], x gathered coherently
@@ -1567,8 +1593,13 @@ __device__ __forceinline__ double wide_dot(const WX& wx, const double* x, double
 // other rows' step vectors from LDS: one workgroup barrier per step and no
 // traffic between workgroups.
 
+constexpr int kMaxChebSteps = 32;
+
 struct ChebParams {
   double theta, delta, sigma;   // centre and half width of the interval, theta / delta
+  // LDS table of the step coefficients (c1, c2) of steps 1 .. kMaxChebSteps - 1:
+  // they depend on the interval only, so they are formed once per solve
+  const double* coef = nullptr;
 };
 
 // lmax of the workgroup: max over its rows of |d_i| (|J_ii| + sum_{in-block
@@ -1605,7 +1636,7 @@ __device__ ChebParams cheb_params(const LI& li, const double (&aa)[K], double ad
   if constexpr (WX::kw > 0) {
 #pragma unroll
     for (int e = 0; e < WX::kw; ++e)
-      g += (wx.li[e * NT + threadIdx.x] < NT) ? fabs(wx.val[e * NT + threadIdx.x]) : 0.0;
+      g += (wx.blk(e * NT + threadIdx.x) < NT) ? fabs(wx.val[e * NT + threadIdx.x]) : 0.0;
   }
   g *= fabs(d);
 #pragma unroll
@@ -1624,6 +1655,21 @@ __device__ ChebParams cheb_params(const LI& li, const double (&aa)[K], double ad
   c.theta = 0.5 * (lmax + lmin);
   c.delta = 0.5 * (lmax - lmin);
   c.sigma = c.theta / c.delta;
+  // rho_k = 1 / (2 sigma - rho_{k-1}) from rho_0 = 1 / sigma; step k takes
+  // c1 = rho_k rho_{k-1} and c2 = 2 rho_k / delta
+  __shared__ double coef[2 * kMaxChebSteps];
+  if (threadIdx.x == 0) {
+    double rho_old = 1.0 / c.sigma;
+    coef[0] = coef[1] = 0.0;
+    for (int k = 1; k < kMaxChebSteps; ++k) {
+      const double rho = 1.0 / (2.0 * c.sigma - rho_old);
+      coef[2 * k] = rho * rho_old;
+      coef[2 * k + 1] = 2.0 * rho / c.delta;
+      rho_old = rho;
+    }
+  }
+  __syncthreads();
+  c.coef = coef;
   return c;
 }
 
@@ -1663,7 +1709,6 @@ __device__ __forceinline__ void block_cheb(const LI& li, const double (&aa)[K], 
     dd[v] = d * r[v] / c.theta;
     z[v] = dd[v];
   }
-  double rho_old = 1.0 / c.sigma;
   cheb_barrier<LDS_ONLY>();   // the previous call's last reads are done before this call's first writes
   for (int k = 1; k < steps; ++k) {
     double* buf = lds + (k & 1) * 2 * (NT + 1);
@@ -1679,19 +1724,17 @@ __device__ __forceinline__ void block_cheb(const LI& li, const double (&aa)[K], 
         if constexpr (WX::kw > 0) {
 #pragma unroll
           for (int e = 0; e < WX::kw; ++e)
-            acc = fma(wx.val[e * NT + tid], buf[v * (NT + 1) + wx.li[e * NT + tid]], acc);
+            acc = fma(wx.val[e * NT + tid], buf[v * (NT + 1) + wx.blk(e * NT + tid)], acc);
         }
         r[v] -= acc;
       }
     }
-    const double rho = 1.0 / (2.0 * c.sigma - rho_old);
-    const double c1 = rho * rho_old, c2 = 2.0 * rho / c.delta;
+    const double c1 = c.coef[2 * k], c2 = c.coef[2 * k + 1];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       dd[v] = fma(c1, dd[v], c2 * d * r[v]);
       z[v] += dd[v];
     }
-    rho_old = rho;
   }
 }
 
@@ -1706,7 +1749,7 @@ template <int NT, int K, int KW = 0, bool LX = false>
 __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, double* sh, int* sh_abort) {
   __shared__ double cheb_lds[4 * (NT + 1)];
   // rows of up to K + KW entries: the KW past the first K in LDS
-  using WX = std::conditional_t<(KW > 0), WideLds<NT, KW>, NoWide>;
+  using WX = std::conditional_t<(KW > 0), WideLds<NT, KW, LX>, NoWide>;
   __shared__ WX wide;
   double red[kMaxRed];
   KOut o{EGFEM_NOT_CONVERGED, 0, 0.0, 0.0, false};
@@ -1787,8 +1830,12 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
       const double wv = in ? w : 0.0;
       if (bj && in && ck == row) ad = wv;
       wide.val[e * NT + threadIdx.x] = wv;
-      wide.off[e * NT + threadIdx.x] = wofs;
-      wide.li[e * NT + threadIdx.x] = (uint16_t)l;
+      if constexpr (LX) {
+        wide.px[e * NT + threadIdx.x] = (uint16_t)wofs;
+      } else {
+        wide.off[e * NT + threadIdx.x] = wofs;
+        wide.li[e * NT + threadIdx.x] = (uint16_t)l;
+      }
     }
   }
   ChebParams cp{1.0, 1.0, 1.0};
@@ -1836,9 +1883,9 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
     double acc = aa[0] * S[lp[0]];
 #pragma unroll
     for (int k = 1; k < K; ++k) acc = fma(aa[k], S[lp[k]], acc);
-    if constexpr (KW > 0) {
+    if constexpr (KW > 0 && LX) {
 #pragma unroll
-      for (int e = 0; e < KW; ++e) acc = fma(wide.val[e * NT + threadIdx.x], S[wide.off[e * NT + threadIdx.x]], acc);
+      for (int e = 0; e < KW; ++e) acc = fma(wide.val[e * NT + threadIdx.x], S[wide.px[e * NT + threadIdx.x]], acc);
     }
     return acc;
   };
@@ -1870,8 +1917,7 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
   // the shadow residual r^ is read three times per iteration and written only
   // at a restart: it lives in memory (this thread's row), not in registers
   // (threads without a row alias the part's last row: only owners write)
-  double* const rhat_row = A.rhat + row;
-  if (own) *rhat_row = r;
+  if (own) st_at(A.rhat, roff, r);
   // the direction p itself is not kept: its preconditioned form follows
   // from the recurrence below
   double v = 0.0, z = 0.0, sv = 0.0, tv = 0.0;
@@ -1910,7 +1956,7 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
     EGFEM_ZERO_RED();
     if (own) {
       st_sh_at(A.vh, roff, vhh);
-      red[0] = *rhat_row * v;
+      red[0] = ld_at(A.rhat, roff) * v;
       red[1] = r * r;
     }
     if ((o.abort = team_reduce<NT>(tm, slot, red, 2, sh, sh_abort))) break;
@@ -1928,7 +1974,7 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
       // lost bi-orthogonality: restart once from the current residual
       // (p = r, so M^-1 p is the published M^-1 r)
       if (restarts++ >= 1) { o.status = EGFEM_BREAKDOWN; break; }
-      if (own) *rhat_row = r;
+      if (own) st_at(A.rhat, roff, r);
       ph = rhh;
       if (own) st_sh_at(A.phat, roff, ph);
       rho = red[1];
@@ -1955,7 +2001,7 @@ __device__ KOut team_bicgstab_reg(Team& tm, const KArgs& A, int rb, int re, doub
       if (own) {
         red[0] = tv * sv;
         red[1] = tv * tv;
-        const double rhv = *rhat_row;
+        const double rhv = ld_at(A.rhat, roff);
         red[2] = rhv * sv;
         red[3] = rhv * tv;
         red[4] = sv * sv;
