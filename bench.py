@@ -119,16 +119,21 @@ def load_traffic():
     return d
 
 
-def same_krylov_kernel(rec: dict, kernels_bits: int, shape: dict) -> bool:
-    """Whether the profiled Krylov kernel (overlapped or barrier form, threads
-    per workgroup, preconditioner steps) is the one this run launched: the
-    counters belong to one kernel, and the autotuner's choice can differ
-    between runs."""
-    prof = rec.get("shape", {})
+def krylov_traffic_record(tr: dict, kernels_bits: int, shape: dict):
+    """The counter record of the Krylov kernel this run launched (overlapped
+    or barrier form, threads per workgroup: one kernel instantiation), or
+    None: the autotuner's choice can differ between runs.  The Chebyshev step
+    count is a run-time argument that changes only LDS work, not the bytes an
+    iteration moves through HBM."""
+    recs = tr.get("krylov_bicgstab") or []
+    if isinstance(recs, dict):
+        recs = [recs]
     overlapped = bool(kernels_bits & 8)
-    return (rec.get("kernel", "").startswith("k_bicgstab_ov") == overlapped
-            and prof.get("krylov_threads") == shape["krylov_threads"]
-            and prof.get("krylov_precond") == shape["krylov_precond"])
+    for rec in recs:
+        if (rec.get("kernel", "").startswith("k_bicgstab_ov") == overlapped
+                and rec.get("shape", {}).get("krylov_threads") == shape["krylov_threads"]):
+            return rec
+    return None
 
 
 # ----------------------------------------------------------------------------
@@ -844,6 +849,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (scale reference for HBM counters)")
     ap.add_argument("--no-configs", action="store_true", help="skip the 1D-256 and 2D-512 Newton solves")
+    ap.add_argument("--shape", default="",
+                    help="JSON launch shape for the headline handle instead of the autotuner's (counter runs)")
     ap.add_argument("--cpu-worker", type=int, default=0, help=argparse.SUPPRESS)
     ap.add_argument("--cpu-extras", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
@@ -866,7 +873,12 @@ def main():
         print("no HIP device", file=sys.stderr)
         sys.exit(1)
     wl, T, p = gpu_setup(args.n)
-    tuned = T.autotune(p)          # offline, like the tensor build
+    if args.shape:
+        # a fixed launch shape instead of the autotuner's (counter runs per shape)
+        T.set_shape(**json.loads(args.shape))
+        tuned = {"shape": T.get_shape(), "action_us": None, "krylov_iter_us": None}
+    else:
+        tuned = T.autotune(p)      # offline, like the tensor build
     info = T.info
     # the timed region: K solves as a user runs them (no per-launch events)
     opts = eg.NewtonOptions(tol=wl.tol, forcing=1)
@@ -915,10 +927,11 @@ def main():
     achieved = bytes_per_launch / (avg_ms * 1e6)
     tr = load_traffic()
     traffic = None
-    if tr and dom == "krylov_bicgstab" and args.n == 256 and "krylov_bicgstab" in tr \
-            and same_krylov_kernel(tr["krylov_bicgstab"], stats[0].krylov_kernels, T.get_shape()):
+    krec = (krylov_traffic_record(tr, stats[0].krylov_kernels, T.get_shape())
+            if tr and dom == "krylov_bicgstab" and args.n == 256 else None)
+    if krec:
         iters_per_launch = k_it / max(n_kry, 1)
-        traffic = tr["krylov_bicgstab"]["hbm_bytes_per_iteration"] * iters_per_launch
+        traffic = krec["hbm_bytes_per_iteration"] * iters_per_launch
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch,
@@ -933,7 +946,7 @@ def main():
                             "(%d Chebyshev steps, LDS) and the exchange of ghost entries run inside those "
                             "windows; J and the row vectors stay on chip" % T.get_shape()["krylov_precond"]
                             + (", measured HBM traffic %.2fx the algorithmic bytes"
-                               % tr["krylov_bicgstab"]["ratio"] if traffic is not None else ""))
+                               % krec["ratio"] if traffic is not None else ""))
                 if dom == "krylov_bicgstab" else None}
 
     stage("newton configurations")
