@@ -559,9 +559,11 @@ typedef struct {
                                 partition of the free rows (2D 512x512: 261,121 free rows on
                                 256 workgroups, where 263,169 rows exceed the 256/512-thread
                                 resident grids); the partition is rebuilt when the Dirichlet
-                                mask's contents change.  3D meshes (rows of up to 16 entries)
-                                run only this form: 8 entries of a row in registers, the
-                                others in the thread's slice of LDS.  egfem_adjoint leaves the
+                                mask's contents change.  The 1024-thread BiCGStab also runs
+                                resident on every row where each part fits (linear solves,
+                                systems without a mask).  3D meshes (rows of up to 16
+                                entries) run only this form: 8 entries of a row in registers,
+                                the others in the thread's slice of LDS.  egfem_adjoint leaves the
                                 same rows out (DF^T keeps the identity rows and zero columns).
                                 At 1024 threads the products read LDS: the part's own rows and
                                 its ghosts (at most 1024, one coherent load per thread) are

@@ -330,8 +330,9 @@ int krylov_solve(KrylovMethod method, egfem_tensor_s* T, const double* jval, con
   // hold at most kResidentRow entries, and the grid is co-resident for it
   // (columns are held as 32-bit byte offsets: n < 2^28)
   const void* kreg = kernel_for(NT, method, true, 0, wide);   // null where there is none
+  // (1024 threads: BiCGStab only, on the free rows or on every row)
   const bool resident_ok = kreg && T->krylov_kernel != 1 && T->max_row_slots <= kResidentRow + kWideRow &&
-                           T->n < (int64_t(1) << 28) && G <= coresident(kreg, NT) && (NT <= 512 || free_rows);
+                           T->n < (int64_t(1) << 28) && G <= coresident(kreg, NT);
   // block-Jacobi preconditioner: the resident kernels on a compact partition
   // (of the free rows at 1024 threads)
   bool block = resident_ok && T->krylov_precond > 0 && !T->h_coords.empty() && (n_free + G - 1) / G <= NT;
