@@ -1189,12 +1189,14 @@ __device__ bool team_reduce(Team& tm, int slot, double (&v)[kMaxRed], int m, dou
   __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's stores are complete
   __syncthreads();
   const unsigned epoch = tm.epoch++;
-  double* part = tm.red + (size_t)slot * kMaxRed * G;
+  // partials at 32-bit byte offsets from a base in scalar registers (the slot
+  // and the wave's value index are uniform: read-first-lane says so)
+  double* part = tm.red + (size_t)__builtin_amdgcn_readfirstlane(slot) * kMaxRed * G;
   if (wave == 0) {
     if (lane < m) {
       double acc = 0.0;
       for (int w = 0; w < NW; ++w) acc += sh[lane * NW + w];
-      st_sh(part + (size_t)lane * G + tm.rank, acc);
+      st_sh_at(part, ((unsigned)lane * G + tm.rank) * 8u, acc);
     }
     __builtin_amdgcn_s_waitcnt(0x0F70);
     if (lane == 0) *sh_abort = barrier_arrive_wait(tm, epoch);
@@ -1202,13 +1204,13 @@ __device__ bool team_reduce(Team& tm, int slot, double (&v)[kMaxRed], int m, dou
   __syncthreads();
   if (*sh_abort) return true;
   const int R = (int)((G + kWave - 1) / kWave);
-  for (int q = wave; q < m; q += NW) {
+  for (int q = __builtin_amdgcn_readfirstlane(wave); q < m; q += NW) {
     const double* src = part + (size_t)q * G;
     double acc = 0.0;
     for (int r0 = 0; r0 < R; r0 += 4) {
       double y[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) y[r] = ld_sh(src + min((unsigned)(lane + kWave * (r0 + r)), G - 1));
+      for (int r = 0; r < 4; ++r) y[r] = ld_sh_at(src, min((unsigned)(lane + kWave * (r0 + r)), G - 1) * 8u);
 #pragma unroll
       for (int r = 0; r < 4; ++r)
         if ((unsigned)(lane + kWave * (r0 + r)) < G) acc += y[r];
