@@ -37,26 +37,30 @@ __device__ __forceinline__ void st_sh(double* p, double v) {
 // Agent-coherent store at a 32-bit byte offset from a uniform base: the base
 // stays in scalar registers and the address is formed by the store itself,
 // so no 64-bit per-lane address has to be kept in vector registers.
+// (The base is a global-memory pointer: in that address space the access
+// takes the scalar-base plus 32-bit-offset addressing of global instructions.)
+typedef __attribute__((address_space(1))) char gchar;
+typedef __attribute__((address_space(1))) double gdouble;
 __device__ __forceinline__ void st_sh_at(double* base, unsigned off, double v) {
-  char* b = reinterpret_cast<char*>(base);
+  gchar* b = (gchar*)base;
   __asm__ volatile("" : "+s"(b));
-  st_sh(reinterpret_cast<double*>(b + off), v);
+  __hip_atomic_store((gdouble*)(b + off), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ double ld_sh_at(const double* base, unsigned off) {
-  const char* b = reinterpret_cast<const char*>(base);
+  const gchar* b = (const gchar*)base;
   __asm__ volatile("" : "+s"(b));
-  return ld_sh(reinterpret_cast<const double*>(b + off));
+  return __hip_atomic_load((const gdouble*)(b + off), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 // Plain (row-local) load and store at a 32-bit byte offset from a uniform base.
 __device__ __forceinline__ void st_at(double* base, unsigned off, double v) {
-  char* b = reinterpret_cast<char*>(base);
+  gchar* b = (gchar*)base;
   __asm__ volatile("" : "+s"(b));
-  *reinterpret_cast<double*>(b + off) = v;
+  *(gdouble*)(b + off) = v;
 }
 __device__ __forceinline__ double ld_at(const double* base, unsigned off) {
-  const char* b = reinterpret_cast<const char*>(base);
+  const gchar* b = (const gchar*)base;
   __asm__ volatile("" : "+s"(b));
-  return *reinterpret_cast<const double*>(b + off);
+  return *(const gdouble*)(b + off);
 }
 template <bool SH>
 __device__ __forceinline__ double ld(const double* p) {
