@@ -500,7 +500,10 @@ def adjoint_suite():
     dev = torch.device("cuda:0")
     tpl = eg.Problem(T.n, None, torch.tensor(wl.mesh.dirichlet, dtype=torch.uint8, device=dev),
                      None, 0.0, False)
-    opts = eg.NewtonOptions(tol=wl.tol, krylov_rtol=1e-13)
+    # the forward solve takes the headline's Krylov rule (Eisenstat-Walker
+    # forcing; the Newton tolerance 1e-13 bounds the final residual); the
+    # adjoint's linear solve runs to krylov_rtol = 1e-13
+    opts = eg.NewtonOptions(tol=wl.tol, krylov_rtol=1e-13, forcing=1)
     kappa = torch.tensor(wl.a0, dtype=torch.float64, device=dev)
     with torch.no_grad():
         u_d = eg.solve(torch.tensor(wl.extra["f_target"], dtype=torch.float64, device=dev), kappa,
@@ -525,6 +528,7 @@ def adjoint_suite():
             tb += t2 - t1
     T.close()
     return {"workload": "diffusion_3d_64^3_kuhn", "nodes": T.info.n_nodes,
+            "newton_tol": wl.tol, "forward_forcing": "eisenstat-walker-2", "adjoint_krylov_rtol": 1e-13,
             "forward_ms": 1e3 * tf / reps, "adjoint_ms": 1e3 * tb / reps,
             "forward_solves_per_s": reps / tf, "adjoint_solves_per_s": reps / tb,
             "adjoint_over_forward": tb / tf}
