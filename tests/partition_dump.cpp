@@ -58,8 +58,16 @@ int main(int argc, char** argv) {
     std::fprintf(stderr, "inconsistent mesh graph files\n");
     return 2;
   }
+  // optional mask of rows left out (the free-row partition)
+  std::vector<uint8_t> skip;
+  const bool has_skip = read_all(p + ".skip", skip);
+  if (has_skip && (int64_t)skip.size() != n) {
+    std::fprintf(stderr, "inconsistent skip mask\n");
+    return 2;
+  }
   egfem::CompactPartition cp;
-  const int rc = egfem::make_compact_partition(dim, X.data(), n, rowptr.data(), col.data(), G, cp);
+  const int rc = egfem::make_compact_partition(dim, X.data(), n, rowptr.data(), col.data(), G, cp,
+                                               has_skip ? skip.data() : nullptr);
   std::printf("rc %d\n", rc);
   if (rc != EGFEM_OK) return 0;
   const std::vector<int32_t> meta = {cp.maxrows, egfem::kMaxNbrLists};

@@ -56,7 +56,8 @@ def mesh_graph(name):
         coords, cells = wheel_mesh(150)
     else:
         m = {"1d_n300": lambda: W.mesh_1d(300), "2d_n24": lambda: W.mesh_2d(24),
-             "3d_n7": lambda: W.mesh_3d(7), "disk_n20": lambda: W.mesh_disk(20)}[name]()
+             "3d_n7": lambda: W.mesh_3d(7), "3d_n11": lambda: W.mesh_3d(11),
+             "disk_n20": lambda: W.mesh_disk(20)}[name]()
         coords, cells = np.asarray(m.coords, np.float64), np.asarray(m.cells, np.int64)
     coords = coords.reshape(len(coords), -1)
     n, nl = len(coords), cells.shape[1]
@@ -68,10 +69,12 @@ def mesh_graph(name):
     return coords, A.indptr.astype(np.int32), A.indices.astype(np.int32)
 
 
-def run_partition(driver, tmp_path, coords, rowptr, col, G):
+def run_partition(driver, tmp_path, coords, rowptr, col, G, skip=None):
     p = str(tmp_path / f"g{G}")
     n, dim = coords.shape
     np.asarray([dim, n], np.int64).tofile(p + ".hdr")
+    if skip is not None:
+        np.ascontiguousarray(skip, np.uint8).tofile(p + ".skip")
     np.ascontiguousarray(coords, np.float64).tofile(p + ".x")
     rowptr.tofile(p + ".rp")
     col.tofile(p + ".col")
@@ -212,3 +215,77 @@ def test_resident_block_jacobi_indexing_model(driver, tmp_path, name, G, NT):
         # threads 0..3 and by no row thread
         zeros = {(t >> 1) * 2 * (NT + 1) + (t & 1) * (NT + 1) + NT for t in range(4)}
         assert len(zeros) == 4 and not (zeros & written)
+
+
+# Host model of the 1024-thread resident BiCGStab in its LDS-exchange form on
+# rows of up to 16 entries (K = 8 in registers, KW = 8 in the thread's LDS
+# slice), on every row or on the free rows.  The ghost lists are formed as
+# the launcher forms them (the part's out-of-part columns, ascending).  For
+# every workgroup and thread: each entry's staging position (own row
+# position, the zero entry NT, or NT + 1 + ghost) stays inside the staging
+# vector and off the other Chebyshev buffer's zero entries; the block
+# position derived from it equals the one from the part-local positions; the
+# staging writes (own value at the thread's position, ghost t at NT + 1 + t)
+# never touch a zero entry.
+WIDE_K, WIDE_KW, WIDE_NT = 8, 8, 1024
+WIDE_CASES = [("3d_n7", 1, False), ("3d_n7", 3, False), ("3d_n7", 9, False), ("3d_n11", 2, True),
+              ("3d_n11", 7, True), ("3d_n11", 40, True)]
+
+
+def dirichlet_3d(coords):
+    x = np.asarray(coords)
+    return (np.any(x <= 1e-12, axis=1) | np.any(x >= 1 - 1e-12, axis=1)).astype(np.uint8)
+
+
+@pytest.mark.parametrize("name,G,free", WIDE_CASES, ids=[f"{m}-G{g}-{'free' if f else 'all'}" for m, g, f in WIDE_CASES])
+def test_wide_exchange_indexing_model(driver, tmp_path, name, G, free):
+    NT, K, KW = WIDE_NT, WIDE_K, WIDE_KW
+    coords, rowptr, col = mesh_graph(name)
+    n, S = len(coords), len(col)
+    assert 8 < np.diff(rowptr).max() <= K + KW
+    skip = dirichlet_3d(coords) if free else None
+    rc, P = run_partition(driver, tmp_path, coords, rowptr, col, G, skip)
+    assert rc == 0
+    kr, rlist, kloc = P["kr"], P["rlist"], P["kloc"]
+    assert P["maxrows"] <= NT
+    zero = {NT, 3 * NT + 2}                 # zero entries of the two staging vectors (buffers 0 and 1)
+    sentinels = {NT, 2 * NT + 1, 3 * NT + 2, 4 * NT + 3}
+    for g in range(G):
+        rb, re = int(kr[g]), int(kr[g + 1])
+        rows = [int(r) for r in rlist[rb:re]]
+        if free:
+            assert all(skip[r] == 0 for r in rows)
+        ghosts = sorted({int(col[s]) for r in rows for s in range(rowptr[r], rowptr[r + 1]) if kloc[s] < 0})
+        ng = len(ghosts)
+        assert ng <= NT                      # the exchange form's condition
+        gidx = {c: t for t, c in enumerate(ghosts)}
+        for base in (0, 2 * (NT + 1)):       # staging vector S0, S1
+            writes = {base + t for t in range(NT)} | {base + NT + 1 + t for t in range(ng)}
+            assert not (writes & sentinels)
+            assert max(writes) < 4 * (NT + 1)
+        for tid in range(NT):
+            i = rb + tid
+            own = i < re
+            q = max(min(i, re - 1), 0)
+            row = int(rlist[q])
+            beg, end = int(rowptr[row]), int(rowptr[row + 1])
+            for k in range(K + KW):
+                s = min(beg + k, end - 1)
+                assert 0 <= s < S
+                c = int(col[s])
+                real = own and beg + k < end
+                l = int(kloc[s])
+                ext = l if l >= 0 else -1 - gidx[c]
+                px = (ext if ext >= 0 else NT + 1 + (-1 - ext)) if real else NT
+                assert 0 <= px <= 2 * NT
+                for base in (0, 2 * (NT + 1)):
+                    assert base + px < 4 * (NT + 1) and (base + px not in sentinels or base + px in zero)
+                if real and l < 0:
+                    assert ghosts[px - NT - 1] == c
+                if real and 0 <= px < NT:
+                    assert int(rlist[rb + px]) == c
+                # block position: from the staging position vs from the part-local position
+                derived = px if (px < NT and px != tid) else NT
+                offd = real and c != row
+                li = l if (offd and l >= 0) else NT
+                assert derived == li, (g, tid, k, px, l)
