@@ -206,22 +206,24 @@ __device__ __forceinline__ void action_load(const TensorView& T, int64_t b, cons
     R.kk[q] = T.kS[p];
     R.vv[q] = T.vA[p];
   }
-  // null kval / load / dir are replaced by a valid array and masked at use
+  // null kval / load / dir are replaced by a valid array and masked at use;
+  // their loads then all read its first word (one cache line, no stream traffic)
   const double* kvp = kval ? kval : T.kval;
+  const int kmask = kval ? -1 : 0;   // no K: every lane reads one word (masked at use)
 #pragma unroll
   for (int q = 0; q < SS; ++q) {
     const int s = R.s0 + clamp_hi(tid + q * NT, R.ns);
     R.cc[q] = T.col[s];
     R.kp[q] = T.kpS[s];
-    R.kv[q] = PROBLEM ? kvp[s] : 0.0;
+    R.kv[q] = PROBLEM ? kvp[s & kmask] : 0.0;
   }
   const int i = R.r0 + clamp_hi(tid, R.nr);
   R.rp = T.rowptr[i];
   R.ldi = 0.0;
   R.dr = 0;
   if (PROBLEM) {
-    R.ldi = (load ? load : T.kval)[i];
-    R.dr = (dir ? dir : reinterpret_cast<const uint8_t*>(T.kval))[i];
+    R.ldi = (load ? load : T.kval)[load ? i : 0];
+    R.dr = (dir ? dir : reinterpret_cast<const uint8_t*>(T.kval))[dir ? i : 0];
   }
 }
 
@@ -408,18 +410,19 @@ __device__ void rowblock_jacobian(const TensorView& T, int64_t b, const double* 
   int cc[SS], kpa[SS], kpb[SS];
   double kv[SS];
   const double* kvp = kval ? kval : T.kval;
+  const int kmask = kval ? -1 : 0;   // no K: every lane reads one word (masked at use)
 #pragma unroll
   for (int q = 0; q < SS; ++q) {
     const int s = s0 + clamp_hi(tid + q * NT, ns);
     cc[q] = T.col[s];
     kpa[q] = T.kpS[s];
     kpb[q] = T.jpS[s];
-    kv[q] = kvp[s];
+    kv[q] = kvp[s & kmask];
   }
   const bool has_row = tid < nr;
   const int i = r0 + clamp_hi(tid, nr);
   const int rpa = T.rowptr[i], rpb = T.rowptr[i + 1];
-  const unsigned char drow_raw = (dir ? dir : reinterpret_cast<const uint8_t*>(T.kval))[i];
+  const unsigned char drow_raw = (dir ? dir : reinterpret_cast<const uint8_t*>(T.kval))[dir ? i : 0];
   // stage 1b: per-slot gathers (u, a or a0, g, Dirichlet flag at the slot's column)
   double uj[SS], aj[SS], gj[SS];
   unsigned char dcr[SS];
@@ -545,6 +548,7 @@ __device__ void rowblock_action_half(const TensorView& T, int64_t b, const doubl
     vv[q] = T.vH[p];
   }
   const double* kvp = kval ? kval : T.kval;
+  const int kmask = kval ? -1 : 0;   // no K: every lane reads one word (masked at use)
   int cc[SS], kp[SS];
   double kv[SS];
 #pragma unroll
@@ -552,7 +556,7 @@ __device__ void rowblock_action_half(const TensorView& T, int64_t b, const doubl
     const int s = m.s0 + clamp_hi(tid + q * NT, ns);
     cc[q] = T.col[s];
     kp[q] = T.kpSH[s];
-    kv[q] = kvp[s];
+    kv[q] = kvp[s & kmask];
   }
   const bool has_row = tid < nr;
   const int i = m.r0 + clamp_hi(tid, nr);
@@ -670,6 +674,7 @@ __device__ void rowblock_action_w2(const TensorView& T, int64_t b, const double*
     vv[q] = T.vA[p];
   }
   const double* kvp = kval ? kval : T.kval;
+  const int kmask = kval ? -1 : 0;   // no K: every lane reads one word (masked at use)
   int cc[SS], kp[SS];
   double kv[SS];
 #pragma unroll
@@ -677,7 +682,7 @@ __device__ void rowblock_action_w2(const TensorView& T, int64_t b, const double*
     const int s = m.s0 + clamp_hi(tid + q * NT, ns);
     cc[q] = T.col[s];
     kp[q] = T.kpS[s];
-    kv[q] = kvp[s];
+    kv[q] = kvp[s & kmask];
   }
   uint32_t wq[WW], wq2[WW];
   int wc[WW], wqq[WW];
@@ -844,12 +849,13 @@ __device__ void rowblock_jacobian_w2(const TensorView& T, int64_t b, const doubl
   int cc[SS], kpa[SS];
   double kv[SS];
   const double* kvp = kval ? kval : T.kval;
+  const int kmask = kval ? -1 : 0;   // no K: every lane reads one word (masked at use)
 #pragma unroll
   for (int q = 0; q < SS; ++q) {
     const int s = s0 + clamp_hi(tid + q * NT, ns);
     cc[q] = T.col[s];
     kpa[q] = T.kpS[s];
-    kv[q] = kvp[s];
+    kv[q] = kvp[s & kmask];
   }
   uint32_t wq[WW], wq2[WW];
   int wc[WW], wbp[WW], wqq[WW];
