@@ -54,11 +54,12 @@ def bytes_action_problem(info, trial: bool, add_stiffness: bool = False):
     return _stream_bytes(info) + kmat + vec
 
 
-def bytes_jacobian(info, add_stiffness: bool = False):
+def bytes_jacobian(info, add_stiffness: bool = False, a0_field: bool = False):
     N, S, Z = info.n_nodes, info.slots, info.nnz
     streams = _stream_bytes(info) + (0 if info.symmetric else 10 * Z + 2 * S)   # A (+ B)
     kmat = 8 * S if add_stiffness else 0
-    return streams + kmat + 8 * N + N + 8 * S + 8 * N        # u, mask, J values, 1/diag
+    a0 = 8 * N if a0_field else 0                             # a nodal coefficient field (3D: kappa)
+    return streams + kmat + a0 + 8 * N + N + 8 * S + 8 * N    # u, mask, J values, 1/diag
 
 
 def bytes_krylov(info, iters: int):
@@ -294,7 +295,7 @@ def tensor_action_suite(with_graph: bool = True):
         graph = time_action_graph(T) if with_graph else float("nan")
         jac = time_jacobian(T, p, 50)
         ba = bytes_action_raw(info)
-        bj = bytes_jacobian(info, wl.add_stiffness)
+        bj = bytes_jacobian(info, wl.add_stiffness, wl.a0 is not None)
         out[name] = {"nnz": info.nnz, "slots": info.slots, "action_bytes": ba,
                      "action_warm_us": warm * 1e3, "action_warm_GBps": ba / (warm * 1e6),
                      "action_graph_us": graph * 1e3, "action_graph_GBps": ba / (graph * 1e6),
