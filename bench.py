@@ -294,9 +294,14 @@ def tensor_action_suite(with_graph: bool = True):
         cold = time_action(T, 20, cold=True)
         graph = time_action_graph(T) if with_graph else float("nan")
         jac = time_jacobian(T, p, 50)
-        ba = bytes_action_raw(info)
+        ba_full = bytes_action_raw(info)
+        bh = ba_full - 10 * (info.nnz - info.nnz_half) if info.nnz_half else ba_full
+        # the tuned shape may read the symmetric half stream: its bytes then
+        ba = bh if tuned["shape"]["action_half"] else ba_full
         bj = bytes_jacobian(info, wl.add_stiffness, wl.a0 is not None)
         out[name] = {"nnz": info.nnz, "slots": info.slots, "action_bytes": ba,
+                     "action_stream": "half" if tuned["shape"]["action_half"] else "full",
+                     "action_bytes_full_stream": ba_full,
                      "action_warm_us": warm * 1e3, "action_warm_GBps": ba / (warm * 1e6),
                      "action_graph_us": graph * 1e3, "action_graph_GBps": ba / (graph * 1e6),
                      "action_cold_us": cold * 1e3, "action_cold_GBps": ba / (cold * 1e6),
@@ -314,7 +319,6 @@ def tensor_action_suite(with_graph: bool = True):
                 T.set_shape(action_half=half)
                 res[half] = (time_action(T, 100, cold=False), time_action(T, 20, cold=True))
             T.set_shape(**keep)
-            bh = ba - 10 * (info.nnz - info.nnz_half)
             out[name]["half_stream"] = {"nnz_half": info.nnz_half, "bytes": bh,
                                         "full_warm_us": res[0][0] * 1e3, "full_cold_us": res[0][1] * 1e3,
                                         "half_warm_us": res[1][0] * 1e3, "half_cold_us": res[1][1] * 1e3,
