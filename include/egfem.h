@@ -582,7 +582,8 @@ typedef struct {
                                 workgroup; 0: the full stream (default; egfem_autotune picks the
                                 half stream where it is faster) */
   int krylov_precond;        /* preconditioner of the register-resident BiCGStab: 0 = Jacobi
-                                D^-1; k in 2..32 = block-Jacobi (default 8): the rows are split
+                                D^-1; k in 2..32 = block-Jacobi (default 8; 6 where rows hold more
+                                than 8 entries, as on 3D meshes): the rows are split
                                 by recursive coordinate bisection into one compact part per
                                 workgroup, and each workgroup applies k Chebyshev steps (Jacobi
                                 scaled, interval [lmax/ratio, lmax], ratio = krylov_cheb_ratio
