@@ -56,7 +56,8 @@ def bytes_action_problem(info, trial: bool, add_stiffness: bool = False):
 
 def bytes_jacobian(info, add_stiffness: bool = False, a0_field: bool = False):
     N, S, Z = info.n_nodes, info.slots, info.nnz
-    streams = _stream_bytes(info) + (0 if info.symmetric else 10 * Z + 2 * S)   # A (+ B)
+    # A stream (+ the B position of every A entry and the B fiber starts)
+    streams = _stream_bytes(info) + (0 if info.symmetric else 2 * Z + 2 * S)
     kmat = 8 * S if add_stiffness else 0
     a0 = 8 * N if a0_field else 0                             # a nodal coefficient field (3D: kappa)
     return streams + kmat + a0 + 8 * N + N + 8 * S + 8 * N    # u, mask, J values, 1/diag

@@ -205,6 +205,7 @@ void egfem_tensor_destroy(egfem_tensor_t T) {
     if (T->jB) hipFree(T->jB);
     if (T->vB) hipFree(T->vB);
     if (T->jS) hipFree(T->jS);
+    if (T->bS) hipFree(T->bS);
     if (T->jpS) hipFree(T->jpS);
   }
   delete T;

@@ -655,7 +655,7 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
   // of row i, so an entry can name it by the block-relative slot of (i, k):
   // 16 bits (at most kCapSlots slots per block).  The stages then gather
   // per slot, not per entry.
-  std::vector<uint16_t> kS(kA.size()), jS(jB.size());
+  std::vector<uint16_t> kS(kA.size()), jS(w2 ? jB.size() : 0);
   // fiber starts relative to the block's first entry (at most kCapNnz)
   std::vector<uint16_t> kpS((size_t)slots + 1), jpS(sym ? 0 : (size_t)slots + 1);
   // W_h = P2: an A entry names its k by the block-relative W-slot of (i, k);
@@ -688,6 +688,14 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
       }
     }
   }
+  // W_h = P1 without the (j, k) symmetry: the B stream holds the A entries
+  // again, (i, j, k) in the fiber of slot (i, k), j in column order.  The
+  // Jacobian reads, per A entry, the block-relative B position of the same
+  // entry (16 bits) instead of the B values and slots, and places the A
+  // entry's product there; checked here to be a bijection onto the B stream
+  // with bitwise equal values.
+  std::vector<uint16_t> bS((!w2 && !sym) ? kA.size() : 0);
+  std::vector<int32_t> taken;
   for (size_t b = 0; !w2 && b + 1 < blk.size(); ++b) {
     const int32_t s0 = rowptr[blk[b]];
     for (int32_t s = s0; s < rowptr[blk[b + 1]]; ++s) {
@@ -696,11 +704,19 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
     }
     for (int32_t i = blk[b]; i < blk[b + 1]; ++i) {
       const int32_t base = rowptr[i] - s0;
-      for (int32_t s = rowptr[i]; s < rowptr[i + 1]; ++s) {
+      for (int32_t s = rowptr[i]; s < rowptr[i + 1]; ++s)
         for (int32_t p = kptrA[s]; p < kptrA[s + 1]; ++p) kS[p] = (uint16_t)(base + kRel[p]);
-        if (!sym)
-          for (int32_t p = jptrB[s]; p < jptrB[s + 1]; ++p) jS[p] = (uint16_t)(base + jRel[p]);
-      }
+      if (sym) continue;
+      taken.assign((size_t)(rowptr[i + 1] - rowptr[i]), 0);
+      for (int32_t s = rowptr[i]; s < rowptr[i + 1]; ++s)
+        for (int32_t p = kptrA[s]; p < kptrA[s + 1]; ++p) {
+          const int32_t sk = rowptr[i] + kRel[p];
+          const int32_t q = jptrB[sk] + taken[kRel[p]]++;
+          if (q >= jptrB[sk + 1] || jRel[q] != s - rowptr[i] ||
+              std::memcmp(&vB[q], &vA[p], sizeof(double)) != 0)
+            return fail(EGFEM_ERR_SHAPE, "internal: the B stream is not a permutation of the A stream");
+          bS[p] = (uint16_t)(q - jptrB[s0]);
+        }
     }
   }
 
@@ -784,7 +800,8 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
   if (rc == EGFEM_OK) rc = upload(kA, &T->kA, &bytes);
   if (rc == EGFEM_OK) rc = upload(vA, &T->vA, &bytes);
   if (rc == EGFEM_OK) rc = upload(kS, &T->kS, &bytes);
-  if (rc == EGFEM_OK && !sym) rc = upload(jS, &T->jS, &bytes);
+  if (rc == EGFEM_OK && !sym && w2) rc = upload(jS, &T->jS, &bytes);
+  if (rc == EGFEM_OK && !sym && !w2) rc = upload(bS, &T->bS, &bytes);
   if (rc == EGFEM_OK) rc = upload(kpS, &T->kpS, &bytes);
   if (rc == EGFEM_OK && !sym) rc = upload(jpS, &T->jpS, &bytes);
   if (rc == EGFEM_OK && !sym) rc = upload(jptrB, &T->jptrB, &bytes);

@@ -85,7 +85,8 @@ struct TensorView {
   const int32_t* jB;
   const double* vB;
   const uint16_t* kS;       // block-relative slot of (i, k) of every A entry
-  const uint16_t* jS;       // block-relative slot of (i, j) of every B entry
+  const uint16_t* jS;       // block-relative slot of (i, j) of every B entry (W_h != P1)
+  const uint16_t* bS;       // block-relative B position of every A entry (W_h = P1)
   const uint16_t* kpS;      // A fiber start relative to the block's first A entry
   const uint16_t* jpS;      // B fiber start relative to the block's first B entry
   const double* kval;
@@ -128,6 +129,22 @@ struct RowBlockLds {
   int spb[kCapSlots + 1];    // fiber bounds, B stream, block-relative
   int srow[kCapRows + 1];    // slot bounds of the rows, block-relative
   int srid[kCapSlots];       // row of every slot, block-relative (Jacobian)
+  uint16_t pslot[kCapNnz];   // slot of every A entry, block-relative (Jacobian)
+  unsigned char sdir[kCapRows];
+};
+
+// LDS scratch of the Jacobian emission alone (no action stages, 16-bit
+// bounds and indices; at most kCapNnz entries and kCapSlots slots per block):
+// 29 KiB, five 256-thread workgroups per CU where RowBlockLds allows four.
+struct JacobianLds {
+  double tA[kCapNnz];
+  double tB[kCapNnz];
+  double aS[kCapSlots];
+  double uS[kCapSlots];
+  uint16_t spa[kCapSlots + 1];
+  uint16_t spb[kCapSlots + 1];
+  uint16_t srid[kCapSlots];
+  uint16_t pslot[kCapNnz];
   unsigned char sdir[kCapRows];
 };
 
@@ -372,51 +389,50 @@ __device__ void rowblocks_action_pipelined(const TensorView& T, int64_t b0, int6
 //   J_s = [K_s] + sum_{p in A(s)} v_p a_{k_p} + g_j sum_{p in B(s)} v_p u_{j_p},
 // s = (i, j), a = a0 + u^2 (problem_a) or given, g = dadu or 2u (dadu_2u) or none.
 // Dirichlet rows -> identity rows, Dirichlet columns -> 0; dinv[i] = 1 / J_ii.
-// Two phases: every thread loads its A/B entries, slots and row, gathers and
+// Two phases: every thread loads its A entries, slots and row, gathers and
 // writes products and bounds to LDS; then every slot sums its two fibers and
-// stores J_s (coalesced).
-template <int NT, bool SH>
+// stores J_s (coalesced).  The B fiber of slot (i, k) holds the A entries
+// (i, j, k) of the row; each A entry places its second product v u_j (u at
+// the column of the slot that holds it) at its B position, so the B stream
+// is read as one 16-bit position per entry and the sums run in B order.
+template <int NT, bool SH, typename Lds>
 __device__ void rowblock_jacobian(const TensorView& T, int64_t b, const double* u, const double* a,
                                   const double* a0, double a0c, int problem_a, const double* dadu,
                                   int dadu_2u, const double* kval, const uint8_t* dir, double* jval,
-                                  double* dinv, RowBlockLds& L) {
+                                  double* dinv, Lds& L) {
   static_assert(NT >= kCapRows, "one thread per row of a block");
   constexpr int PP = Per<NT>::P, SS = Per<NT>::S;
   const int tid = threadIdx.x;
   const BlockMeta m = block_meta(T, b);
-  const int r0 = m.r0, s0 = m.s0, pa0 = m.pa0, pb0 = m.pb0;
+  const int r0 = m.r0, s0 = m.s0, pa0 = m.pa0;
   const int na = m.pa1 - m.pa0, nb = m.pb1 - m.pb0, ns = m.s1 - m.s0, nr = m.r1 - m.r0;
   const bool second = dadu || dadu_2u;
   const bool bstream = second && !T.sym;
   const bool need_u = problem_a || second;
   // stage 1a: stream loads, back to back at clamped indices (see action_load);
   // entries name their k (their j) by the block-relative slot of (i, k)
-  int ka[PP], jb[PP];
-  double va[PP], vb[PP];
+  int ka[PP], bp[PP];
+  double va[PP];
 #pragma unroll
   for (int q = 0; q < PP; ++q) {
     const int p = pa0 + clamp_hi(tid + q * NT, na);
     ka[q] = T.kS[p];
     va[q] = T.vA[p];
+    if (bstream) bp[q] = T.bS[p];
   }
-  if (bstream) {
-#pragma unroll
-    for (int q = 0; q < PP; ++q) {
-      const int p = pb0 + clamp_hi(tid + q * NT, nb);
-      jb[q] = T.jS[p];
-      vb[q] = T.vB[p];
-    }
-  }
-  int cc[SS], kpa[SS], kpb[SS];
+  int cc[SS], kpa[SS], kpe[SS], kpb[SS];
   double kv[SS];
   const double* kvp = kval ? kval : T.kval;
   const int kmask = kval ? -1 : 0;   // no K: every lane reads one word (masked at use)
 #pragma unroll
   for (int q = 0; q < SS; ++q) {
-    const int s = s0 + clamp_hi(tid + q * NT, ns);
+    const int sl = tid + q * NT;
+    const int s = s0 + clamp_hi(sl, ns);
     cc[q] = T.col[s];
     kpa[q] = T.kpS[s];
-    kpb[q] = T.jpS[s];
+    kpb[q] = T.jpS[s];   // symmetric: aliases kpS
+    // end of the slot's A fiber (kpS has one entry past the last slot)
+    kpe[q] = bstream ? (sl + 1 < ns ? (int)T.kpS[s + 1] : na) : 0;
     kv[q] = kvp[s & kmask];
   }
   const bool has_row = tid < nr;
@@ -457,6 +473,8 @@ __device__ void rowblock_jacobian(const TensorView& T, int64_t b, const double* 
       L.uS[s] = uj[q];
       L.spa[s] = kpa[q];
       L.spb[s] = kpb[q];
+      if (bstream)
+        for (int p = kpa[q]; p < kpe[q]; ++p) L.pslot[p] = (uint16_t)s;
     }
   }
   if (tid == 0) {
@@ -475,8 +493,8 @@ __device__ void rowblock_jacobian(const TensorView& T, int64_t b, const double* 
     if (p < na) {
       L.tA[p] = va[q] * L.aS[ka[q]];
       if (T.sym && second) L.tB[p] = va[q] * L.uS[ka[q]];
+      if (bstream) L.tB[bp[q]] = va[q] * L.uS[L.pslot[p]];
     }
-    if (bstream && p < nb) L.tB[p] = vb[q] * L.uS[jb[q]];
   }
   __syncthreads();
   // stage 2: slot assembly

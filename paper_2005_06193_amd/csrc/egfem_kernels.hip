@@ -62,6 +62,7 @@ dev::TensorView view_of(const egfem_tensor_s* T) {
   v.vB = T->vB;
   v.kS = T->kS;
   v.jS = T->jS;
+  v.bS = T->bS;
   v.kpS = T->kpS;
   v.jpS = T->jpS;
   v.kval = T->kval;
@@ -124,7 +125,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_jacobian(dev::TensorView T, c
                                                             const uint8_t* __restrict__ dir,
                                                             double* __restrict__ jval,
                                                             double* __restrict__ dinv) {
-  __shared__ dev::RowBlockLds L;
+  __shared__ dev::JacobianLds L;
   const int64_t b = xcd_block(blockIdx.x, T.nblk);
   if (b < 0) return;
   dev::rowblock_jacobian<kBlockThreads, false>(T, b, u, a, a0, a0c, problem_a, dadu, dadu_2u, kval, dir,

@@ -71,10 +71,14 @@ static bool write_all(const std::string& path, const T* v, size_t n) {
 }
 
 // Every entry of the block-relative streams names the same slot / fiber as
-// the global streams: fiber starts, the slot of (i, k) (A) and of (i, j) (B).
+// the global streams: fiber starts and the slot of (i, k) (A); without the
+// (j, k) symmetry, the B position of every A entry (i, j, k) lies in the B
+// fiber of slot (i, k), names column j, holds the same value bit for bit,
+// and no B position is named twice.
 static int check_blocks(const egfem_tensor_s* T) {
   const int4* meta = reinterpret_cast<const int4*>(T->blk_meta);
   int bad = 0;
+  std::vector<int> hit;
   for (int64_t b = 0; b < T->row_blocks; ++b) {
     const int4 x = meta[2 * b], y = meta[2 * b + 1];
     const int r0 = x.x, r1 = x.y, s0 = x.z, s1 = x.w, pa0 = y.x, pa1 = y.y, pb0 = y.z, pb1 = y.w;
@@ -82,22 +86,26 @@ static int check_blocks(const egfem_tensor_s* T) {
     if (r1 - r0 > egfem::kCapRows || s1 - s0 > egfem::kCapSlots || pa1 - pa0 > egfem::kCapNnz ||
         pb1 - pb0 > egfem::kCapNnz)
       ++bad;
+    hit.assign((size_t)(pb1 - pb0), 0);
     for (int i = r0; i < r1; ++i)
       for (int s = T->rowptr[i]; s < T->rowptr[i + 1]; ++s) {
         if (T->kptrA[s] != pa0 + T->kpS[s]) ++bad;
+        if (!T->symmetric && T->jptrB[s] != pb0 + T->jpS[s]) ++bad;
         for (int p = T->kptrA[s]; p < T->kptrA[s + 1]; ++p) {
           const int ks = s0 + T->kS[p];
-          if (ks < T->rowptr[i] || ks >= T->rowptr[i + 1] || T->col[ks] != T->kA[p]) ++bad;
-        }
-        if (!T->symmetric) {
-          if (T->jptrB[s] != pb0 + T->jpS[s]) ++bad;
-          for (int p = T->jptrB[s]; p < T->jptrB[s + 1]; ++p) {
-            const int js = s0 + T->jS[p];
-            if (js < T->rowptr[i] || js >= T->rowptr[i + 1] || T->col[js] != T->jB[p]) ++bad;
+          if (ks < T->rowptr[i] || ks >= T->rowptr[i + 1] || T->col[ks] != T->kA[p]) {
+            ++bad;
+            continue;
           }
+          if (T->symmetric) continue;
+          const int q = pb0 + T->bS[p];
+          if (q < T->jptrB[ks] || q >= T->jptrB[ks + 1] || T->jB[q] != T->col[s] ||
+              std::memcmp(&T->vB[q], &T->vA[p], sizeof(double)) != 0 || hit[q - pb0]++)
+            ++bad;
         }
       }
     if (T->kptrA[s1] != pa1) ++bad;
+    if (!T->symmetric && pb1 - pb0 != pa1 - pa0) ++bad;
   }
   return bad;
 }
