@@ -204,7 +204,6 @@ void egfem_tensor_destroy(egfem_tensor_t T) {
     if (T->jptrB) hipFree(T->jptrB);
     if (T->jB) hipFree(T->jB);
     if (T->vB) hipFree(T->vB);
-    if (T->jS) hipFree(T->jS);
     if (T->bS) hipFree(T->bS);
     if (T->jpS) hipFree(T->jpS);
   }

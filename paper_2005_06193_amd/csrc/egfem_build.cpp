@@ -655,12 +655,28 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
   // of row i, so an entry can name it by the block-relative slot of (i, k):
   // 16 bits (at most kCapSlots slots per block).  The stages then gather
   // per slot, not per entry.
-  std::vector<uint16_t> kS(kA.size()), jS(w2 ? jB.size() : 0);
+  std::vector<uint16_t> kS(kA.size());
   // fiber starts relative to the block's first entry (at most kCapNnz)
   std::vector<uint16_t> kpS((size_t)slots + 1), jpS(sym ? 0 : (size_t)slots + 1);
+  // Without the (j, k) symmetry the B stream holds the A entries again: entry
+  // (i, j, k) sits in the B fiber of (i, k) (a slot, or a W-slot for
+  // W_h != P1), j in column order.  The Jacobian reads, per A entry, the
+  // block-relative B position of the same entry (16 bits) instead of the B
+  // values and slots, and places the A entry's product there; checked here to
+  // be a bijection onto the B stream with bitwise equal values.
+  std::vector<uint16_t> bS(sym ? 0 : kA.size());
+  std::vector<int32_t> taken;   // B entries of every fiber of the row handed out so far
+  // A entry p of the row's j-th slot, in the B fiber fb (the row's kr-th):
+  // its B position relative to the block's first B entry pb0
+  auto bpos = [&](int32_t p, int32_t fb, int32_t kr, int32_t j, int32_t pb0) {
+    const int32_t q = jptrB[fb] + taken[(size_t)kr]++;
+    if (q >= jptrB[fb + 1] || jRel[q] != j || std::memcmp(&vB[q], &vA[p], sizeof(double)) != 0) return false;
+    bS[p] = (uint16_t)(q - pb0);
+    return true;
+  };
+  auto bad_b = [&]() { return fail(EGFEM_ERR_SHAPE, "internal: the B stream is not a permutation of the A stream"); };
   // W_h = P2: an A entry names its k by the block-relative W-slot of (i, k);
-  // the B stream is aligned to W-slots and its entries name j by the
-  // block-relative slot of (i, j); every W-slot records the block-relative
+  // the B stream is aligned to W-slots; every W-slot records the block-relative
   // slots of its two endpoints (p | q << 16; p == q for a vertex dof)
   const int64_t wslots = w2 ? (int64_t)wcol.size() : 0;
   std::vector<uint32_t> wpq, wpq2;
@@ -678,24 +694,19 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
       for (int32_t w = w0; w < wrowptr[blk[b + 1]]; ++w) jpS[w] = (uint16_t)(jptrB[w] - jptrB[w0]);
       for (int32_t i = blk[b]; i < blk[b + 1]; ++i) {
         const int32_t vb = rowptr[i] - s0, wb = wrowptr[i] - w0;
+        taken.assign((size_t)(wrowptr[i + 1] - wrowptr[i]), 0);
         for (int32_t s = rowptr[i]; s < rowptr[i + 1]; ++s)
-          for (int32_t p = kptrA[s]; p < kptrA[s + 1]; ++p) kS[p] = (uint16_t)(wb + kRel[p]);
+          for (int32_t p = kptrA[s]; p < kptrA[s + 1]; ++p) {
+            kS[p] = (uint16_t)(wb + kRel[p]);
+            if (!bpos(p, wrowptr[i] + kRel[p], kRel[p], s - rowptr[i], jptrB[w0])) return bad_b();
+          }
         for (int32_t w = wrowptr[i]; w < wrowptr[i + 1]; ++w) {
-          for (int32_t p = jptrB[w]; p < jptrB[w + 1]; ++p) jS[p] = (uint16_t)(vb + jRel[p]);
           wpq[w] = (uint32_t)(vb + wpl[w]) | ((uint32_t)(vb + wql[w]) << 16);
           if (wq || wcell) wpq2[w] = (uint32_t)(vb + wpl2[w]) | ((uint32_t)(vb + wql2[w]) << 16);
         }
       }
     }
   }
-  // W_h = P1 without the (j, k) symmetry: the B stream holds the A entries
-  // again, (i, j, k) in the fiber of slot (i, k), j in column order.  The
-  // Jacobian reads, per A entry, the block-relative B position of the same
-  // entry (16 bits) instead of the B values and slots, and places the A
-  // entry's product there; checked here to be a bijection onto the B stream
-  // with bitwise equal values.
-  std::vector<uint16_t> bS((!w2 && !sym) ? kA.size() : 0);
-  std::vector<int32_t> taken;
   for (size_t b = 0; !w2 && b + 1 < blk.size(); ++b) {
     const int32_t s0 = rowptr[blk[b]];
     for (int32_t s = s0; s < rowptr[blk[b + 1]]; ++s) {
@@ -709,14 +720,8 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
       if (sym) continue;
       taken.assign((size_t)(rowptr[i + 1] - rowptr[i]), 0);
       for (int32_t s = rowptr[i]; s < rowptr[i + 1]; ++s)
-        for (int32_t p = kptrA[s]; p < kptrA[s + 1]; ++p) {
-          const int32_t sk = rowptr[i] + kRel[p];
-          const int32_t q = jptrB[sk] + taken[kRel[p]]++;
-          if (q >= jptrB[sk + 1] || jRel[q] != s - rowptr[i] ||
-              std::memcmp(&vB[q], &vA[p], sizeof(double)) != 0)
-            return fail(EGFEM_ERR_SHAPE, "internal: the B stream is not a permutation of the A stream");
-          bS[p] = (uint16_t)(q - jptrB[s0]);
-        }
+        for (int32_t p = kptrA[s]; p < kptrA[s + 1]; ++p)
+          if (!bpos(p, rowptr[i] + kRel[p], kRel[p], s - rowptr[i], jptrB[s0])) return bad_b();
     }
   }
 
@@ -800,8 +805,7 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
   if (rc == EGFEM_OK) rc = upload(kA, &T->kA, &bytes);
   if (rc == EGFEM_OK) rc = upload(vA, &T->vA, &bytes);
   if (rc == EGFEM_OK) rc = upload(kS, &T->kS, &bytes);
-  if (rc == EGFEM_OK && !sym && w2) rc = upload(jS, &T->jS, &bytes);
-  if (rc == EGFEM_OK && !sym && !w2) rc = upload(bS, &T->bS, &bytes);
+  if (rc == EGFEM_OK && !sym) rc = upload(bS, &T->bS, &bytes);
   if (rc == EGFEM_OK) rc = upload(kpS, &T->kpS, &bytes);
   if (rc == EGFEM_OK && !sym) rc = upload(jpS, &T->jpS, &bytes);
   if (rc == EGFEM_OK && !sym) rc = upload(jptrB, &T->jptrB, &bytes);
@@ -872,7 +876,6 @@ int build_impl(int dim, int64_t n_nodes, const double* coords, int64_t n_cells, 
     T->jptrB = T->kptrA;
     T->jB = T->kA;
     T->vB = T->vA;
-    T->jS = T->kS;
     T->jpS = T->kpS;
   }
   T->device_bytes = bytes;

@@ -85,13 +85,12 @@ struct TensorView {
   const int32_t* jB;
   const double* vB;
   const uint16_t* kS;       // block-relative slot of (i, k) of every A entry
-  const uint16_t* jS;       // block-relative slot of (i, j) of every B entry (W_h != P1)
-  const uint16_t* bS;       // block-relative B position of every A entry (W_h = P1)
+  const uint16_t* bS;       // block-relative B position of every A entry (not symmetric)
   const uint16_t* kpS;      // A fiber start relative to the block's first A entry
   const uint16_t* jpS;      // B fiber start relative to the block's first B entry
   const double* kval;
   // W_h = P2 (Case 1): A entries name k by the block-relative W-slot; the B
-  // stream is aligned to W-slots (jpS per W-slot) and names j by the slot
+  // stream is aligned to W-slots (jpS per W-slot)
   const int2* wmeta;        // W-slot range of every block
   const int32_t* wrowptr;   // W-slot range of every row
   const int32_t* wcol;      // P2 dof of every W-slot
@@ -824,6 +823,7 @@ struct RowBlockLdsW {
   int srow[kCapRows + 1];
   int swrow[kCapRows + 1];   // W-slot bounds of every row
   int srid[kCapSlots];
+  uint16_t pslot[kCapNnz];   // slot of every A entry, block-relative
   unsigned char sdir[kCapRows];
 };
 
@@ -848,31 +848,29 @@ __device__ void rowblock_jacobian_w2(const TensorView& T, int64_t b, const doubl
   const int na = m.pa1 - m.pa0, nb = m.pb1 - m.pb0, ns = m.s1 - m.s0, nr = m.r1 - m.r0, nw = wm.y - wm.x;
   const bool second = dadu || dadu_2u;
   const bool need_u = problem_a || second;
-  int ka[PP], jb[PP];
-  double va[PP], vb[PP];
+  // the B fiber of W-slot (i, w) holds the A entries (i, j, w) of the row:
+  // each A entry places its product v u_j at its B position (see rowblock_jacobian)
+  int ka[PP], bp[PP];
+  double va[PP];
 #pragma unroll
   for (int q = 0; q < PP; ++q) {
     const int p = m.pa0 + clamp_hi(tid + q * NT, na);
     ka[q] = T.kS[p];
     va[q] = T.vA[p];
+    if (second) bp[q] = T.bS[p];
   }
-  if (second) {
-#pragma unroll
-    for (int q = 0; q < PP; ++q) {
-      const int p = m.pb0 + clamp_hi(tid + q * NT, nb);
-      jb[q] = T.jS[p];
-      vb[q] = T.vB[p];
-    }
-  }
-  int cc[SS], kpa[SS];
+  int cc[SS], kpa[SS], kpe[SS];
   double kv[SS];
   const double* kvp = kval ? kval : T.kval;
   const int kmask = kval ? -1 : 0;   // no K: every lane reads one word (masked at use)
 #pragma unroll
   for (int q = 0; q < SS; ++q) {
-    const int s = s0 + clamp_hi(tid + q * NT, ns);
+    const int sl = tid + q * NT;
+    const int s = s0 + clamp_hi(sl, ns);
     cc[q] = T.col[s];
     kpa[q] = T.kpS[s];
+    // end of the slot's A fiber (kpS has one entry past the last slot)
+    kpe[q] = second ? (sl + 1 < ns ? (int)T.kpS[s + 1] : na) : 0;
     kv[q] = kvp[s & kmask];
   }
   uint32_t wq[WW], wq2[WW];
@@ -909,6 +907,8 @@ __device__ void rowblock_jacobian_w2(const TensorView& T, int64_t b, const doubl
       L.zS[s] = (problem_a && a0) ? a0[cc[q]] : a0c;
       L.spa[s] = kpa[q];
       L.bacc[s] = 0.0;
+      if (second)
+        for (int p = kpa[q]; p < kpe[q]; ++p) L.pslot[p] = (uint16_t)s;
     }
   }
   // per-W-slot values that need no slot data
@@ -965,8 +965,10 @@ __device__ void rowblock_jacobian_w2(const TensorView& T, int64_t b, const doubl
 #pragma unroll
   for (int q = 0; q < PP; ++q) {
     const int p = tid + q * NT;
-    if (p < na) L.tA[p] = va[q] * L.aS[ka[q]];
-    if (second && p < nb) L.tB[p] = vb[q] * L.uS[jb[q]];
+    if (p < na) {
+      L.tA[p] = va[q] * L.aS[ka[q]];
+      if (second) L.tB[bp[q]] = va[q] * L.uS[L.pslot[p]];
+    }
   }
   __syncthreads();
   if (second) {

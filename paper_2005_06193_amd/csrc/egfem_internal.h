@@ -160,8 +160,7 @@ struct egfem_tensor_s {
   int32_t* jB = nullptr;        // [nnz]
   double* vB = nullptr;         // [nnz]
   uint16_t* kS = nullptr;       // [nnz]  block-relative slot of (i, k) of every A entry
-  uint16_t* jS = nullptr;       // [nnz]  block-relative slot of (i, j) of every B entry (W_h != P1; aliases kS)
-  uint16_t* bS = nullptr;       // [nnz]  block-relative B position of every A entry (W_h = P1, not symmetric)
+  uint16_t* bS = nullptr;       // [nnz]  block-relative B position of every A entry (not symmetric)
   uint16_t* kpS = nullptr;      // [slots] A fiber start relative to the block's first A entry
   uint16_t* jpS = nullptr;      // [slots] B fiber start relative to the block's first B entry (aliases)
   double* kval = nullptr;       // [slots]

@@ -61,7 +61,6 @@ dev::TensorView view_of(const egfem_tensor_s* T) {
   v.jB = T->jB;
   v.vB = T->vB;
   v.kS = T->kS;
-  v.jS = T->jS;
   v.bS = T->bS;
   v.kpS = T->kpS;
   v.jpS = T->jpS;
