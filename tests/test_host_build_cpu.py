@@ -104,7 +104,8 @@ def test_host_build_matches_oracle_under_sanitizers(driver, tmp_path, mesh, form
 def test_host_build_coefficient_spaces_under_sanitizers(driver, tmp_path, mesh, wspace):
     """W_h = P2, I_k and P0 handles (stiffness and mass forms; P2 and I_k also
     the convection form) build without a sanitizer report; the stored entry
-    count equals the oracle's tensor on that space."""
+    count equals the oracle's tensor on that space, and the B position of
+    every entry names the same entry in the W-slot-aligned B stream."""
     coords, cells = MESHES[mesh]()
     coords = np.asarray(coords, np.float64).reshape(len(coords), -1)
     cells = np.asarray(cells)
@@ -114,6 +115,7 @@ def test_host_build_coefficient_spaces_under_sanitizers(driver, tmp_path, mesh, 
             continue
         _, kv, out = run_build(driver, tmp_path, coords, cells, form, wspace)
         assert kv["rc"] == 0, out
+        assert kv["block_mismatch"] == 0, (form, out)
         if wspace == 1:
             ref = O.tensor_p2(coords, cells, form)
         elif wspace == 2:
