@@ -409,7 +409,8 @@ __device__ void rowblock_jacobian(const TensorView& T, int64_t b, const double* 
   const bool bstream = second && !T.sym;
   const bool need_u = problem_a || second;
   // stage 1a: stream loads, back to back at clamped indices (see action_load);
-  // entries name their k (their j) by the block-relative slot of (i, k)
+  // entries name their k by the block-relative slot of (i, k) and, without the
+  // symmetry, their place in the B stream by a block-relative position
   int ka[PP], bp[PP];
   double va[PP];
 #pragma unroll
